@@ -1,0 +1,190 @@
+/*
+ * sf.h - C ABI of the halfway-domain scene-flow solver for MI355X (gfx950).
+ *
+ * The library computes dense geometry and 3D motion from two synchronized,
+ * pre-calibrated monochrome stereo pairs (left/right camera at time t and
+ * t+1; paper Sec. 3), by minimising the halfway-domain energy of Sec. 4
+ * (Eqs. (8)-(18)) over a coarse warp grid (Sec. 3.3, Eq. (7)) with
+ * data-parallel Gauss-Newton and preconditioned conjugate gradients
+ * (Sec. 5.1, Eqs. (19)-(24)) inside the delta hierarchy of Sec. 5.3.
+ *
+ * Conventions shared by every entry point:
+ *  - Images are float32, row-major, H x W, nominally in [0, 1]; pixel (x, y)
+ *    has integer coordinates at its centre.
+ *  - "device" pointers are HIP device memory owned by the caller (for
+ *    example torch tensors); they must stay valid until the work enqueued on
+ *    the context's stream has completed.  All compute runs on the GPU.
+ *  - Every function returns sf_status; arguments are validated on the host
+ *    before anything is enqueued, so a failed call enqueues nothing.
+ *  - A context is bound to one HIP stream and one device; it is not
+ *    thread-safe (use one context per host thread / stream).
+ *  - No C++ types or exceptions cross this boundary.
+ */
+#ifndef SF_H
+#define SF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SF_OK = 0,
+    SF_ERR_INVALID_ARG = -1, /* null pointer, bad enum, weight < 0, ...     */
+    SF_ERR_SIZE = -2,        /* image too small for the requested levels    */
+    SF_ERR_HIP = -3,         /* a HIP runtime call failed                   */
+    SF_ERR_OOM = -4,         /* device allocation failed                    */
+    SF_ERR_NUMERIC = -5,     /* NaN/Inf energy (reported through the log)   */
+    SF_ERR_STATE = -6        /* call not valid in the context's state       */
+} sf_status;
+
+/* Opaque solver context: owns all device workspace (pyramid, node vectors,
+ * per-pixel linearisation records, reduction scratch, log, HIP graph). */
+typedef struct sf_ctx sf_ctx;
+
+/* Rectified pinhole stereo pair (Sec. 3): focal lengths and principal point
+ * in level-0 pixels, baseline in metres, and the fundamental matrix F
+ * (row-major) with x_L^T F x_R = 0 for corresponding homogeneous pixels,
+ * used by the epipolar term, Eqs. (15)-(17).  For a rectified rig normalise
+ * F = [[0,0,0],[0,0,-1],[0,1,0]], so the residual is r_y - l_y in pixels. */
+typedef struct {
+    float fx, fy, cx, cy, baseline;
+    float F[9];
+} sf_calib;
+
+/* Energy weights (Eqs. (8)-(10), (14), (18); Appendix A) and schedule.
+ *  levels          pyramid levels (coarse-to-fine hierarchy, Sec. 5.3)
+ *  grid_stride     warp-grid step in pixels at every level (Sec. 3.3)
+ *  gn_iters        Gauss-Newton steps per level
+ *  pcg_iters       PCG iterations per Gauss-Newton step (1..64)
+ *  max_backtracks  step-length halvings after tau = 1 (0..7)
+ *  init_mode       0 = zero initialisation of the coarsest level
+ *  exec_mode       0 = replay a captured HIP graph, 1 = enqueue kernels
+ *  w_*, m_*        weights of the energy terms; m_s, m_m, m_d must be > 0
+ *  eps             pseudo-Huber parameter of Eq. (12)
+ *  eps_p           colour-pruning threshold of Sec. 4.1
+ *  st_gamma,st_tau smoothness-weight map w_i = 1 + st_gamma exp(-l / tau_l),
+ *                  tau_l = st_tau 4^level, l = smaller eigenvalue of the
+ *                  3x3-window structure tensor (Sec. 4.3 names only the
+ *                  eigenvalue analysis; this map is the library's reading). */
+typedef struct {
+    int levels, grid_stride, gn_iters, pcg_iters, max_backtracks, init_mode;
+    int exec_mode;
+    float w_reg, w_photo, w_grad, w_epi, w_smooth, w_mag;
+    float w_s, w_m, w_d, m_s, m_m, m_d;
+    float eps, eps_p, st_gamma, st_tau;
+} sf_params;
+
+/* Fills *out with the paper's "Figures 5, 6, 8" parameter column
+ * (Appendix A), w_smooth = w_mag = 1, eps = 0.001, eps_p = 0.2, and the
+ * schedule levels 3, stride 8, 5 GN x 10 PCG, 4 backtracks. */
+sf_status sf_params_default(sf_params *out);
+
+/* Creates a context for width x height frames on the current HIP device,
+ * allocating all workspace up front.  hip_stream is a hipStream_t (NULL for
+ * the null stream).  Errors: SF_ERR_INVALID_ARG (null out/p, bad params),
+ * SF_ERR_SIZE (a level would be smaller than 8 x 8 pixels), SF_ERR_OOM,
+ * SF_ERR_HIP.  On error *out is set to NULL. */
+sf_status sf_create(sf_ctx **out, int width, int height, const sf_params *p,
+                    void *hip_stream);
+
+/* Solves one frame.  Inputs: the four device images of the context's size
+ * (left t, right t, left t+1, right t+1; Sec. 3.1), calibration, and
+ * optional params (NULL = creation-time params; a non-NULL p may change
+ * weights but must keep levels, grid_stride, gn_iters, pcg_iters and
+ * max_backtracks, else SF_ERR_STATE).  Outputs (device, caller-owned):
+ *  depth   H x W: depth Z_t of each halfway-domain pixel at time t in the
+ *          left camera (metres), NaN where the disparity is <= 0;
+ *  flow3d  3 x H x W: X_{t+1} - X_t in the left-camera frame (metres);
+ *  flows   6 x H x W (may be NULL): per-pixel s_x, s_y, m_x, m_y, d_x, d_y
+ *          of the finest level in pixels.
+ * Asynchronous on the context's stream; allocates nothing. */
+sf_status sf_solve(sf_ctx *ctx, const float *I_left_t, const float *I_right_t,
+                   const float *I_left_t1, const float *I_right_t1,
+                   const sf_calib *calib, const sf_params *p, float *depth,
+                   float *flow3d, float *flows);
+
+/* One record per (level, Gauss-Newton step), coarsest level first. */
+typedef struct {
+    int level, gn_iter;
+    double energy;            /* E of Eq. (8) before the step                */
+    double e_photo, e_grad;   /* raw E_photo, E_grad (Eqs. (11), (13))       */
+    double e_smooth, e_epi, e_mag; /* raw regularisers (Eqs. (14),(15),(18)) */
+    double energy_after;      /* E after the accepted step                   */
+    float tau;                /* accepted step length (0 = rejected)         */
+    int pcg_iters;
+    float pcg_res[64];        /* ||r|| after each PCG iteration              */
+    int n_valid;              /* pixels with V(x) W(x) = 1 at this level     */
+} sf_iter_log;
+
+/* Copies the log of the last solve into out (at most cap records) and sets
+ * *n_written.  Synchronises the context's stream.  Returns SF_ERR_NUMERIC
+ * if any logged energy is NaN or Inf (the records are still written). */
+sf_status sf_get_log(sf_ctx *ctx, sf_iter_log *out, int cap, int *n_written);
+
+/* Human-readable name of a status code (static string). */
+const char *sf_status_string(sf_status s);
+
+/* Frees the context and all its device memory; NULL-safe.  Synchronises the
+ * context's stream first. */
+void sf_destroy(sf_ctx *ctx);
+
+/* ---- test support: per-stage access to intermediates --------------------
+ * These entry points exist so that tests can compare each stage with an
+ * independent implementation.  They synchronise the stream.  host_dst /
+ * host_src are host pointers of exactly `bytes` bytes; the expected size
+ * for (what, level) is returned by sf_debug_size. */
+enum {
+    SF_DBG_TEX = 0,     /* 4 x N_l float4: (I, G_x, G_y, 0) per image, with
+                           G the central-difference gradient images       */
+    SF_DBG_CMASK = 1,   /* N_l uint8: V(x) W(x)                              */
+    SF_DBG_WNODE = 2,   /* G_l float: smoothness weights w_i                 */
+    SF_DBG_BASE = 3,    /* 6 x G_l float: prolongated total of the level     */
+    SF_DBG_DELTA = 4,   /* 6 x G_l float: delta unknowns                     */
+    SF_DBG_DX = 5,      /* 6 x G_l float: PCG solution (GN step)             */
+    SF_DBG_R = 6,       /* 6 x G_l float: PCG residual (initially -grad E)   */
+    SF_DBG_Z = 7,       /* 6 x G_l float: preconditioned residual            */
+    SF_DBG_Q = 8,       /* 6 x G_l float: last H p                           */
+    SF_DBG_DIAG = 9,    /* 6 x G_l float: diag(H)                            */
+    SF_DBG_REC = 10,    /* 27 x N_l float: per-pixel gradient (6) and
+                           upper-triangular Gauss-Newton block (21)          */
+    SF_DBG_P = 11,      /* 6 x G_l float: last search direction              */
+    SF_DBG_ENERGY = 12  /* 6 double: photo, grad, smooth, epi, mag, total
+                           at the last linearisation                         */
+};
+size_t sf_debug_size(sf_ctx *ctx, int what, int level);
+sf_status sf_debug_read(sf_ctx *ctx, int what, int level, void *host_dst,
+                        size_t bytes);
+sf_status sf_debug_write(sf_ctx *ctx, int what, int level,
+                         const void *host_src, size_t bytes);
+
+/* Builds the image pyramid from four device images and stores the
+ * calibration, without solving. */
+sf_status sf_debug_set_images(sf_ctx *ctx, const float *I_left_t,
+                              const float *I_right_t, const float *I_left_t1,
+                              const float *I_right_t1, const sf_calib *calib);
+
+/* Runs one stage at `level` on the current state:
+ *  SF_STAGE_LEVEL_INIT   prolongate (zero at the coarsest level), zero the
+ *                        delta, compute masks and smoothness weights
+ *  SF_STAGE_LINEARIZE    per-pixel records, energy, gradient and diag(H)
+ *  SF_STAGE_APPLY        q = H p with p = the current SF_DBG_Z vector
+ *  SF_STAGE_PCG          pcg_iters PCG iterations from x = 0
+ *  SF_STAGE_GN           one full Gauss-Newton step with step control
+ *  SF_STAGE_FINISH       store base + delta as the level's total        */
+enum {
+    SF_STAGE_LEVEL_INIT = 0,
+    SF_STAGE_LINEARIZE = 1,
+    SF_STAGE_APPLY = 2,
+    SF_STAGE_PCG = 3,
+    SF_STAGE_GN = 4,
+    SF_STAGE_FINISH = 5
+};
+sf_status sf_debug_run(sf_ctx *ctx, int stage, int level);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SF_H */

@@ -1,0 +1,572 @@
+// Host side of the C ABI declared in include/sf.h: argument validation,
+// workspace allocation, the coarse-to-fine level loop (Algorithm 1 without
+// the occlusion and illumination map updates; Sec. 5.3), HIP graph capture
+// and replay, logging and test access to intermediates.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "sf_internal.h"
+
+struct sf_ctx {
+    int W = 0, H = 0, device = 0;
+    sf_params prm{};
+    hipStream_t stream = nullptr;      // caller's stream
+    hipStream_t cap_stream = nullptr;  // private stream for graph capture
+    int L = 0;
+    LevelDims lv[SF_MAX_LEVELS]{};
+    TileCfg tile{};
+    long N0 = 0, G0 = 0;
+    int max_blocks = 0;
+    float4 *tex = nullptr;
+    unsigned char *cmask = nullptr;
+    float *wnode = nullptr;
+    float *nodes = nullptr;
+    float *rec = nullptr;
+    float *partials = nullptr;
+    DevConst *dconst = nullptr;
+    DevConst *hconst = nullptr;  // pinned staging copy
+    DevScalars *sc = nullptr;
+    DevLog *dlog = nullptr;
+    int nlog = 0;
+    hipEvent_t const_ev = nullptr;
+    bool const_pending = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool have_images = false;
+    int last_p = NV_P0;
+};
+
+namespace {
+
+#define HIP_TRY(x)                                   \
+    do {                                             \
+        if ((x) != hipSuccess) return SF_ERR_HIP;    \
+    } while (0)
+
+sf_status check_params(const sf_params *p) {
+    if (!p) return SF_ERR_INVALID_ARG;
+    if (p->levels < 1 || p->levels > SF_MAX_LEVELS) return SF_ERR_INVALID_ARG;
+    if (p->grid_stride < 1 || p->grid_stride > 64) return SF_ERR_INVALID_ARG;
+    if (p->gn_iters < 1 || p->gn_iters > 1000) return SF_ERR_INVALID_ARG;
+    if (p->pcg_iters < 1 || p->pcg_iters > SF_MAX_PCG) return SF_ERR_INVALID_ARG;
+    if (p->max_backtracks < 0 || p->max_backtracks > SF_MAX_TRIALS - 1) return SF_ERR_INVALID_ARG;
+    if (p->init_mode != 0) return SF_ERR_INVALID_ARG;
+    if (p->exec_mode != 0 && p->exec_mode != 1) return SF_ERR_INVALID_ARG;
+    const float w[] = {p->w_reg, p->w_photo, p->w_grad, p->w_epi, p->w_smooth,
+                       p->w_mag, p->w_s, p->w_m, p->w_d, p->st_gamma};
+    for (float v : w)
+        if (!(v >= 0.f) || !isfinite(v)) return SF_ERR_INVALID_ARG;
+    const float pos[] = {p->m_s, p->m_m, p->m_d, p->eps, p->eps_p, p->st_tau};
+    for (float v : pos)
+        if (!(v > 0.f) || !isfinite(v)) return SF_ERR_INVALID_ARG;
+    if (!(p->w_reg > 0.f && p->w_mag > 0.f)) return SF_ERR_INVALID_ARG;  // keeps H SPD
+    return SF_OK;
+}
+
+bool same_schedule(const sf_params &a, const sf_params &b) {
+    return a.levels == b.levels && a.grid_stride == b.grid_stride &&
+           a.gn_iters == b.gn_iters && a.pcg_iters == b.pcg_iters &&
+           a.max_backtracks == b.max_backtracks && a.init_mode == b.init_mode;
+}
+
+// Tile shape of the node-tile kernels: about 32 x 32 owned pixels per
+// workgroup, at most 256 nodes.
+TileCfg pick_tile(int s) {
+    TileCfg t;
+    int n = s >= 32 ? 1 : 32 / s;
+    if (n > 16) n = 16;
+    if (n < 2) n = 2;
+    t.tx = n;
+    t.ty = n;
+    t.rb = s >= 8 ? 8 : 2 * s;
+    if (t.rb < 4) t.rb = 4;
+    return t;
+}
+
+void fill_const(const sf_ctx *c, const sf_params &p, const sf_calib &cal, DevConst &k) {
+    memset(&k, 0, sizeof(k));
+    k.w_reg = p.w_reg; k.w_photo = p.w_photo; k.w_grad = p.w_grad;
+    k.w_epi = p.w_epi; k.w_smooth = p.w_smooth; k.w_mag = p.w_mag;
+    const float wf[6] = {p.w_s, p.w_s, p.w_m, p.w_m, p.w_d, p.w_d};
+    const float mf[6] = {p.m_s, p.m_s, p.m_m, p.m_m, p.m_d, p.m_d};
+    for (int q = 0; q < 6; ++q) { k.wf[q] = wf[q]; k.mf[q] = mf[q]; }
+    k.eps = p.eps; k.eps_p = p.eps_p; k.st_gamma = p.st_gamma; k.st_tau = p.st_tau;
+    k.fx = cal.fx; k.fy = cal.fy; k.cx = cal.cx; k.cy = cal.cy; k.baseline = cal.baseline;
+    // level-l pixel p_l maps to level-0 pixel 2^l p_l + (2^l - 1)/2; the
+    // level fundamental matrix A^T F A / 2^l keeps residuals in level pixels
+    for (int l = 0; l < c->L; ++l) {
+        const double s = ldexp(1.0, l), o = (s - 1.0) / 2.0;
+        const double A[9] = {s, 0, o, 0, s, o, 0, 0, 1};
+        double T[9], R[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double acc = 0;
+                for (int m = 0; m < 3; ++m) acc += (double)cal.F[i * 3 + m] * A[m * 3 + j];
+                T[i * 3 + j] = acc;  // F A
+            }
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double acc = 0;
+                for (int m = 0; m < 3; ++m) acc += A[m * 3 + i] * T[m * 3 + j];
+                R[i * 3 + j] = acc / s;  // A^T F A / 2^l
+            }
+        for (int q = 0; q < 9; ++q) k.F[l][q] = (float)R[q];
+    }
+}
+
+sf_status upload_const(sf_ctx *c, const sf_params &p, const sf_calib &cal) {
+    DevConst k;
+    fill_const(c, p, cal, k);
+    if (memcmp(&k, c->hconst, sizeof(k)) == 0 && c->have_images) return SF_OK;
+    if (c->const_pending) {
+        HIP_TRY(hipEventSynchronize(c->const_ev));
+        c->const_pending = false;
+    }
+    memcpy(c->hconst, &k, sizeof(k));
+    HIP_TRY(hipMemcpyAsync(c->dconst, c->hconst, sizeof(k), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipEventRecord(c->const_ev, c->stream));
+    c->const_pending = true;
+    return SF_OK;
+}
+
+LevelArgs level_args(sf_ctx *c, int l) {
+    LevelArgs a;
+    a.d = c->lv[l];
+    a.level = l;
+    a.s = c->prm.grid_stride;
+    a.N0 = (int)c->N0;
+    a.G0 = (int)c->G0;
+    a.tex = c->tex + c->lv[l].tex_off;
+    a.nodes = c->nodes;
+    a.rec = c->rec;
+    a.cmask = c->cmask;
+    a.wnode = c->wnode;
+    a.partials = c->partials;
+    a.max_blocks = c->max_blocks;
+    a.cst = c->dconst;
+    a.sc = c->sc;
+    a.log = c->dlog;
+    return a;
+}
+
+void enqueue_pyramid(sf_ctx *c, hipStream_t st, const float *const img[4]) {
+    launch_tex_level0(st, img, c->tex + c->lv[0].tex_off, c->W, c->H);
+    for (int l = 1; l < c->L; ++l)
+        launch_downsample(st, c->tex + c->lv[l - 1].tex_off, c->lv[l - 1].W, c->lv[l - 1].H,
+                          c->tex + c->lv[l].tex_off, c->lv[l].W, c->lv[l].H);
+}
+
+void enqueue_level_init(sf_ctx *c, hipStream_t st, int l) {
+    const LevelArgs a = level_args(c, l);
+    const bool coarsest = (l == c->L - 1);
+    launch_level_init(st, a, coarsest ? nullptr : &c->lv[l + 1], coarsest);
+}
+
+void enqueue_linearize(sf_ctx *c, hipStream_t st, int l) {
+    const LevelArgs a = level_args(c, l);
+    launch_energy(st, a, 0, 0, 0.f, 0);
+    launch_node_rhs(st, a, c->tile);
+}
+
+void enqueue_pcg(sf_ctx *c, hipStream_t st, int l, int log_index) {
+    const LevelArgs a = level_args(c, l);
+    for (int i = 0; i < c->prm.pcg_iters; ++i) {
+        launch_apply(st, a, c->tile, i, log_index);
+        launch_update(st, a, i, log_index);
+    }
+    c->last_p = ((c->prm.pcg_iters - 1) & 1) ? NV_P1 : NV_P0;
+}
+
+void enqueue_gn(sf_ctx *c, hipStream_t st, int l, int g, int log_index) {
+    enqueue_linearize(c, st, l);
+    enqueue_pcg(c, st, l, log_index);
+    const LevelArgs a = level_args(c, l);
+    const int T = c->prm.max_backtracks + 1;
+    for (int j = 0; j < T; ++j) launch_energy(st, a, 1, j, ldexpf(1.f, -j), j);
+    launch_accept(st, a, T, log_index, g, c->prm.pcg_iters);
+}
+
+void enqueue_levels(sf_ctx *c, hipStream_t st) {
+    int log_index = 0;
+    for (int l = c->L - 1; l >= 0; --l) {
+        enqueue_level_init(c, st, l);
+        for (int g = 0; g < c->prm.gn_iters; ++g) enqueue_gn(c, st, l, g, log_index++);
+        launch_finish_level(st, level_args(c, l));
+    }
+}
+
+sf_status check_calib(const sf_calib *cal) {
+    if (!cal) return SF_ERR_INVALID_ARG;
+    const float v[] = {cal->fx, cal->fy, cal->cx, cal->cy, cal->baseline};
+    for (float x : v)
+        if (!isfinite(x)) return SF_ERR_INVALID_ARG;
+    if (!(cal->fx > 0.f) || !(cal->fy > 0.f) || !(cal->baseline > 0.f)) return SF_ERR_INVALID_ARG;
+    for (int i = 0; i < 9; ++i)
+        if (!isfinite(cal->F[i])) return SF_ERR_INVALID_ARG;
+    return SF_OK;
+}
+
+sf_status prepare_frame(sf_ctx *c, const float *const img[4], const sf_calib *cal,
+                        const sf_params *p) {
+    for (int k = 0; k < 4; ++k)
+        if (!img[k]) return SF_ERR_INVALID_ARG;
+    sf_status s = check_calib(cal);
+    if (s != SF_OK) return s;
+    if (p) {
+        s = check_params(p);
+        if (s != SF_OK) return s;
+        if (!same_schedule(*p, c->prm)) return SF_ERR_STATE;
+        c->prm = *p;
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    s = upload_const(c, c->prm, *cal);
+    if (s != SF_OK) return s;
+    enqueue_pyramid(c, c->stream, img);
+    c->have_images = true;
+    return SF_OK;
+}
+
+sf_status ensure_graph(sf_ctx *c) {
+    if (c->gexec) return SF_OK;
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    enqueue_levels(c, c->cap_stream);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(c->cap_stream, &g) != hipSuccess || !g) return SF_ERR_HIP;
+    hipGraphExec_t e = nullptr;
+    if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return SF_ERR_HIP;
+    }
+    c->graph = g;
+    c->gexec = e;
+    return SF_OK;
+}
+
+void free_all(sf_ctx *c) {
+    // best-effort release: errors here cannot be reported to anyone
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    (void)hipFree(c->tex);
+    (void)hipFree(c->cmask);
+    (void)hipFree(c->wnode);
+    (void)hipFree(c->nodes);
+    (void)hipFree(c->rec);
+    (void)hipFree(c->partials);
+    (void)hipFree(c->dconst);
+    (void)hipFree(c->sc);
+    (void)hipFree(c->dlog);
+    if (c->hconst) (void)hipHostFree(c->hconst);
+    if (c->const_ev) (void)hipEventDestroy(c->const_ev);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+sf_status sf_params_default(sf_params *out) {
+    if (!out) return SF_ERR_INVALID_ARG;
+    memset(out, 0, sizeof(*out));
+    out->levels = 3;
+    out->grid_stride = 8;
+    out->gn_iters = 5;
+    out->pcg_iters = 10;
+    out->max_backtracks = 4;
+    out->init_mode = 0;
+    out->exec_mode = 0;
+    out->w_reg = 0.5f;
+    out->w_photo = 0.5f;
+    out->w_grad = 5.0f;
+    out->w_epi = 0.5f;
+    out->w_smooth = 1.0f;
+    out->w_mag = 1.0f;
+    out->w_s = 0.75f;
+    out->w_m = 0.5f;
+    out->w_d = 0.01f;
+    out->m_s = 0.5f;
+    out->m_m = 10.0f;
+    out->m_d = 100.0f;
+    out->eps = 0.001f;
+    out->eps_p = 0.2f;
+    out->st_gamma = 4.0f;
+    out->st_tau = 1e-3f;
+    return SF_OK;
+}
+
+sf_status sf_create(sf_ctx **out, int width, int height, const sf_params *p,
+                    void *hip_stream) {
+    if (!out) return SF_ERR_INVALID_ARG;
+    *out = nullptr;
+    sf_status s = check_params(p);
+    if (s != SF_OK) return s;
+    if (width < 8 || height < 8) return SF_ERR_SIZE;
+    sf_ctx *c = new (std::nothrow) sf_ctx();
+    if (!c) return SF_ERR_OOM;
+    c->W = width;
+    c->H = height;
+    c->prm = *p;
+    c->stream = (hipStream_t)hip_stream;
+    c->L = p->levels;
+    const int st = p->grid_stride;
+    long tex_off = 0;
+    for (int l = 0; l < c->L; ++l) {
+        LevelDims &d = c->lv[l];
+        d.W = width >> l;
+        d.H = height >> l;
+        if (d.W < 8 || d.H < 8) {
+            delete c;
+            return SF_ERR_SIZE;
+        }
+        d.Gx = (d.W + st - 1) / st;
+        d.Gy = (d.H + st - 1) / st;
+        d.N = d.W * d.H;
+        d.G = d.Gx * d.Gy;
+        d.tex_off = tex_off;
+        tex_off += 4L * d.N;
+    }
+    c->tile = pick_tile(st);
+    c->N0 = c->lv[0].N;
+    c->G0 = c->lv[0].G;
+    int mb = 1;
+    for (int l = 0; l < c->L; ++l) {
+        const LevelDims &d = c->lv[l];
+        mb = mb > energy_blocks(d) ? mb : energy_blocks(d);
+        mb = mb > node_tile_blocks(d, c->tile) ? mb : node_tile_blocks(d, c->tile);
+        const int gb = (d.G + SF_BLOCK - 1) / SF_BLOCK;
+        mb = mb > gb ? mb : gb;
+    }
+    c->max_blocks = mb;
+    if (node_tile_lds_bytes(c->tile, st, 12) > 64 * 1024) {
+        delete c;
+        return SF_ERR_INVALID_ARG;
+    }
+    c->nlog = c->L * p->gn_iters;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return SF_ERR_HIP;
+    }
+    bool ok = true;
+    ok = ok && hipMalloc(&c->tex, sizeof(float4) * tex_off) == hipSuccess;
+    ok = ok && hipMalloc(&c->cmask, c->N0) == hipSuccess;
+    ok = ok && hipMalloc(&c->wnode, sizeof(float) * c->G0) == hipSuccess;
+    ok = ok && hipMalloc(&c->nodes, sizeof(float) * NV_COUNT * 6 * c->G0) == hipSuccess;
+    ok = ok && hipMalloc(&c->rec, sizeof(float) * SF_REC_PLANES * c->N0) == hipSuccess;
+    ok = ok && hipMalloc(&c->partials, sizeof(float) * 8 * (size_t)mb) == hipSuccess;
+    ok = ok && hipMalloc(&c->dconst, sizeof(DevConst)) == hipSuccess;
+    ok = ok && hipMalloc(&c->sc, sizeof(DevScalars)) == hipSuccess;
+    ok = ok && hipMalloc(&c->dlog, sizeof(DevLog) * c->nlog) == hipSuccess;
+    ok = ok && hipHostMalloc(&c->hconst, sizeof(DevConst), hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        free_all(c);
+        delete c;
+        return SF_ERR_OOM;
+    }
+    memset(c->hconst, 0, sizeof(DevConst));
+    ok = ok && hipEventCreateWithFlags(&c->const_ev, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipMemset(c->sc, 0, sizeof(DevScalars)) == hipSuccess;
+    ok = ok && hipMemset(c->dlog, 0, sizeof(DevLog) * c->nlog) == hipSuccess;
+    ok = ok && hipMemset(c->nodes, 0, sizeof(float) * NV_COUNT * 6 * c->G0) == hipSuccess;
+    ok = ok && hipMemset(c->rec, 0, sizeof(float) * SF_REC_PLANES * c->N0) == hipSuccess;
+    ok = ok && hipDeviceSynchronize() == hipSuccess;
+    if (!ok) {
+        free_all(c);
+        delete c;
+        return SF_ERR_HIP;
+    }
+    *out = c;
+    return SF_OK;
+}
+
+sf_status sf_solve(sf_ctx *c, const float *I_left_t, const float *I_right_t,
+                   const float *I_left_t1, const float *I_right_t1,
+                   const sf_calib *calib, const sf_params *p, float *depth,
+                   float *flow3d, float *flows) {
+    if (!c || !depth || !flow3d) return SF_ERR_INVALID_ARG;
+    const float *img[4] = {I_left_t, I_right_t, I_left_t1, I_right_t1};
+    sf_status s = prepare_frame(c, img, calib, p);
+    if (s != SF_OK) return s;
+    if (c->prm.exec_mode == 0) {
+        s = ensure_graph(c);
+        if (s != SF_OK) return s;
+        HIP_TRY(hipGraphLaunch(c->gexec, c->stream));
+    } else {
+        enqueue_levels(c, c->stream);
+    }
+    launch_output(c->stream, level_args(c, 0), depth, flow3d, flows);
+    HIP_TRY(hipGetLastError());
+    return SF_OK;
+}
+
+sf_status sf_get_log(sf_ctx *c, sf_iter_log *out, int cap, int *n_written) {
+    if (!c || !n_written || (cap > 0 && !out) || cap < 0) return SF_ERR_INVALID_ARG;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const int n = cap < c->nlog ? cap : c->nlog;
+    DevLog *tmp = new (std::nothrow) DevLog[c->nlog > 0 ? c->nlog : 1];
+    if (!tmp) return SF_ERR_OOM;
+    if (hipMemcpy(tmp, c->dlog, sizeof(DevLog) * c->nlog, hipMemcpyDeviceToHost) != hipSuccess) {
+        delete[] tmp;
+        return SF_ERR_HIP;
+    }
+    bool bad = false;
+    for (int i = 0; i < n; ++i) {
+        sf_iter_log &o = out[i];
+        const DevLog &d = tmp[i];
+        o.level = d.level;
+        o.gn_iter = d.gn_iter;
+        o.energy = d.energy;
+        o.e_photo = d.e_photo;
+        o.e_grad = d.e_grad;
+        o.e_smooth = d.e_smooth;
+        o.e_epi = d.e_epi;
+        o.e_mag = d.e_mag;
+        o.energy_after = d.energy_after;
+        o.tau = d.tau;
+        o.pcg_iters = d.pcg_iters;
+        for (int k = 0; k < 64; ++k) o.pcg_res[k] = k < SF_MAX_PCG ? d.pcg_res[k] : 0.f;
+        o.n_valid = d.n_valid;
+        if (!isfinite(d.energy) || !isfinite(d.energy_after)) bad = true;
+    }
+    delete[] tmp;
+    *n_written = n;
+    return bad ? SF_ERR_NUMERIC : SF_OK;
+}
+
+const char *sf_status_string(sf_status s) {
+    switch (s) {
+        case SF_OK: return "ok";
+        case SF_ERR_INVALID_ARG: return "invalid argument";
+        case SF_ERR_SIZE: return "image size not supported for the requested levels";
+        case SF_ERR_HIP: return "HIP runtime error";
+        case SF_ERR_OOM: return "out of device memory";
+        case SF_ERR_NUMERIC: return "non-finite energy";
+        case SF_ERR_STATE: return "call not valid in the context's state";
+    }
+    return "unknown status";
+}
+
+void sf_destroy(sf_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+// ---- test support ---------------------------------------------------------
+
+size_t sf_debug_size(sf_ctx *c, int what, int level) {
+    if (!c || level < 0 || level >= c->L) return 0;
+    const LevelDims &d = c->lv[level];
+    switch (what) {
+        case SF_DBG_TEX: return sizeof(float4) * 4 * (size_t)d.N;
+        case SF_DBG_CMASK: return (size_t)d.N;
+        case SF_DBG_WNODE: return sizeof(float) * (size_t)d.G;
+        case SF_DBG_BASE: case SF_DBG_DELTA: case SF_DBG_DX: case SF_DBG_R:
+        case SF_DBG_Z: case SF_DBG_Q: case SF_DBG_DIAG: case SF_DBG_P:
+            return sizeof(float) * 6 * (size_t)d.G;
+        case SF_DBG_REC: return sizeof(float) * SF_REC_PLANES * (size_t)d.N;
+        case SF_DBG_ENERGY: return sizeof(double) * 6;
+    }
+    return 0;
+}
+
+static int node_vec_of(sf_ctx *c, int what) {
+    switch (what) {
+        case SF_DBG_BASE: return NV_BASE;
+        case SF_DBG_DELTA: return NV_DELTA;
+        case SF_DBG_DX: return NV_DX;
+        case SF_DBG_R: return NV_R;
+        case SF_DBG_Z: return NV_Z;
+        case SF_DBG_Q: return NV_Q;
+        case SF_DBG_DIAG: return NV_DIAG;
+        case SF_DBG_P: return c->last_p;
+    }
+    return -1;
+}
+
+static sf_status debug_copy(sf_ctx *c, int what, int level, void *host, size_t bytes,
+                            bool to_device) {
+    if (!c || !host) return SF_ERR_INVALID_ARG;
+    const size_t need = sf_debug_size(c, what, level);
+    if (need == 0) return SF_ERR_INVALID_ARG;
+    if (bytes != need) return SF_ERR_SIZE;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const LevelDims &d = c->lv[level];
+    const hipMemcpyKind kind = to_device ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
+    char *h = (char *)host;
+    auto cp = [&](void *dev, size_t off, size_t n) -> bool {
+        return to_device ? hipMemcpy((char *)dev, h + off, n, kind) == hipSuccess
+                         : hipMemcpy(h + off, (char *)dev, n, kind) == hipSuccess;
+    };
+    bool ok = true;
+    switch (what) {
+        case SF_DBG_TEX: ok = cp(c->tex + d.tex_off, 0, bytes); break;
+        case SF_DBG_CMASK: ok = cp(c->cmask, 0, bytes); break;
+        case SF_DBG_WNODE: ok = cp(c->wnode, 0, bytes); break;
+        case SF_DBG_REC:
+            for (int k = 0; k < SF_REC_PLANES && ok; ++k)
+                ok = cp(c->rec + (size_t)k * c->N0, sizeof(float) * (size_t)k * d.N,
+                        sizeof(float) * d.N);
+            break;
+        case SF_DBG_ENERGY:
+            if (to_device) return SF_ERR_INVALID_ARG;
+            ok = cp(&c->sc->e_lin[0], 0, bytes);
+            break;
+        default: {
+            const int v = node_vec_of(c, what);
+            if (v < 0) return SF_ERR_INVALID_ARG;
+            float *base = c->nodes + (size_t)v * 6 * c->G0;
+            for (int q = 0; q < 6 && ok; ++q)
+                ok = cp(base + (size_t)q * c->G0, sizeof(float) * (size_t)q * d.G,
+                        sizeof(float) * d.G);
+        }
+    }
+    return ok ? SF_OK : SF_ERR_HIP;
+}
+
+sf_status sf_debug_read(sf_ctx *c, int what, int level, void *host_dst, size_t bytes) {
+    return debug_copy(c, what, level, host_dst, bytes, false);
+}
+
+sf_status sf_debug_write(sf_ctx *c, int what, int level, const void *host_src,
+                         size_t bytes) {
+    return debug_copy(c, what, level, (void *)host_src, bytes, true);
+}
+
+sf_status sf_debug_set_images(sf_ctx *c, const float *I_left_t, const float *I_right_t,
+                              const float *I_left_t1, const float *I_right_t1,
+                              const sf_calib *calib) {
+    if (!c) return SF_ERR_INVALID_ARG;
+    const float *img[4] = {I_left_t, I_right_t, I_left_t1, I_right_t1};
+    sf_status s = prepare_frame(c, img, calib, nullptr);
+    if (s != SF_OK) return s;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SF_OK;
+}
+
+sf_status sf_debug_run(sf_ctx *c, int stage, int level) {
+    if (!c || level < 0 || level >= c->L) return SF_ERR_INVALID_ARG;
+    if (!c->have_images) return SF_ERR_STATE;
+    hipStream_t st = c->stream;
+    const LevelArgs a = level_args(c, level);
+    switch (stage) {
+        case SF_STAGE_LEVEL_INIT: enqueue_level_init(c, st, level); break;
+        case SF_STAGE_LINEARIZE: enqueue_linearize(c, st, level); break;
+        case SF_STAGE_APPLY:
+            launch_set_apply_state(st, c->sc);
+            launch_apply(st, a, c->tile, 0, -1);
+            c->last_p = NV_P0;
+            break;
+        case SF_STAGE_PCG: enqueue_pcg(c, st, level, -1); break;
+        case SF_STAGE_GN: enqueue_gn(c, st, level, 0, -1); break;
+        case SF_STAGE_FINISH: launch_finish_level(st, a); break;
+        default: return SF_ERR_INVALID_ARG;
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    return SF_OK;
+}
+
+}  // extern "C"

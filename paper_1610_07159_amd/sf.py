@@ -1,0 +1,206 @@
+"""ctypes binding of the C ABI in include/sf.h (argument marshalling only).
+
+Every function here has the name of the C entry point it wraps and passes
+plain integers (device addresses, a hipStream_t) and ctypes structs; all
+computation happens in libsf.so on the GPU.  Importing this module fails
+loudly if the library has not been built (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsf.so")
+
+SF_OK = 0
+STATUS = {0: "SF_OK", -1: "SF_ERR_INVALID_ARG", -2: "SF_ERR_SIZE",
+          -3: "SF_ERR_HIP", -4: "SF_ERR_OOM", -5: "SF_ERR_NUMERIC",
+          -6: "SF_ERR_STATE"}
+
+# debug / stage enums (include/sf.h)
+SF_DBG_TEX, SF_DBG_CMASK, SF_DBG_WNODE, SF_DBG_BASE, SF_DBG_DELTA = 0, 1, 2, 3, 4
+SF_DBG_DX, SF_DBG_R, SF_DBG_Z, SF_DBG_Q, SF_DBG_DIAG = 5, 6, 7, 8, 9
+SF_DBG_REC, SF_DBG_P, SF_DBG_ENERGY = 10, 11, 12
+SF_STAGE_LEVEL_INIT, SF_STAGE_LINEARIZE, SF_STAGE_APPLY = 0, 1, 2
+SF_STAGE_PCG, SF_STAGE_GN, SF_STAGE_FINISH = 3, 4, 5
+
+
+class SfError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where} failed: {STATUS.get(code, code)}")
+        self.code = code
+
+
+class sf_calib(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("baseline", ctypes.c_float), ("F", ctypes.c_float * 9)]
+
+
+_PARAM_INTS = ("levels", "grid_stride", "gn_iters", "pcg_iters",
+               "max_backtracks", "init_mode", "exec_mode")
+_PARAM_FLOATS = ("w_reg", "w_photo", "w_grad", "w_epi", "w_smooth", "w_mag",
+                 "w_s", "w_m", "w_d", "m_s", "m_m", "m_d", "eps", "eps_p",
+                 "st_gamma", "st_tau")
+
+
+class sf_params(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_int) for n in _PARAM_INTS]
+                + [(n, ctypes.c_float) for n in _PARAM_FLOATS])
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n in _PARAM_INTS + _PARAM_FLOATS}
+
+
+class sf_iter_log(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int), ("gn_iter", ctypes.c_int),
+                ("energy", ctypes.c_double), ("e_photo", ctypes.c_double),
+                ("e_grad", ctypes.c_double), ("e_smooth", ctypes.c_double),
+                ("e_epi", ctypes.c_double), ("e_mag", ctypes.c_double),
+                ("energy_after", ctypes.c_double), ("tau", ctypes.c_float),
+                ("pcg_iters", ctypes.c_int), ("pcg_res", ctypes.c_float * 64),
+                ("n_valid", ctypes.c_int)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    lib.sf_params_default.argtypes = [ctypes.POINTER(sf_params)]
+    lib.sf_create.argtypes = [ctypes.POINTER(P), I, I,
+                              ctypes.POINTER(sf_params), P]
+    lib.sf_solve.argtypes = [P, P, P, P, P, ctypes.POINTER(sf_calib),
+                             ctypes.POINTER(sf_params), P, P, P]
+    lib.sf_get_log.argtypes = [P, ctypes.POINTER(sf_iter_log), I,
+                               ctypes.POINTER(I)]
+    lib.sf_status_string.argtypes = [I]
+    lib.sf_status_string.restype = ctypes.c_char_p
+    lib.sf_destroy.argtypes = [P]
+    lib.sf_destroy.restype = None
+    lib.sf_debug_size.argtypes = [P, I, I]
+    lib.sf_debug_size.restype = ctypes.c_size_t
+    lib.sf_debug_read.argtypes = [P, I, I, P, ctypes.c_size_t]
+    lib.sf_debug_write.argtypes = [P, I, I, P, ctypes.c_size_t]
+    lib.sf_debug_set_images.argtypes = [P, P, P, P, P,
+                                        ctypes.POINTER(sf_calib)]
+    lib.sf_debug_run.argtypes = [P, I, I]
+    for f in ("sf_params_default", "sf_create", "sf_solve", "sf_get_log",
+              "sf_debug_read", "sf_debug_write", "sf_debug_set_images",
+              "sf_debug_run"):
+        getattr(lib, f).restype = I
+    return lib
+
+
+lib = _load()
+
+
+def _check(code, where):
+    if code != SF_OK:
+        raise SfError(code, where)
+
+
+# ---- the C entry points ---------------------------------------------------
+
+def sf_params_default(**overrides) -> sf_params:
+    p = sf_params()
+    _check(lib.sf_params_default(ctypes.byref(p)), "sf_params_default")
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def make_calib(fx, fy, cx, cy, baseline, F) -> sf_calib:
+    c = sf_calib()
+    c.fx, c.fy, c.cx, c.cy, c.baseline = fx, fy, cx, cy, baseline
+    F = np.asarray(F, np.float64).reshape(9)
+    for i in range(9):
+        c.F[i] = float(F[i])
+    return c
+
+
+def sf_create(width: int, height: int, params: sf_params, stream: int = 0):
+    h = ctypes.c_void_p()
+    _check(lib.sf_create(ctypes.byref(h), int(width), int(height),
+                         ctypes.byref(params), ctypes.c_void_p(stream)),
+           "sf_create")
+    return h
+
+
+def sf_solve(ctx, I_left_t: int, I_right_t: int, I_left_t1: int,
+             I_right_t1: int, calib: sf_calib, params: sf_params | None,
+             depth: int, flow3d: int, flows: int = 0):
+    _check(lib.sf_solve(ctx, I_left_t, I_right_t, I_left_t1, I_right_t1,
+                        ctypes.byref(calib),
+                        ctypes.byref(params) if params is not None else None,
+                        depth, flow3d, flows or None), "sf_solve")
+
+
+def sf_get_log(ctx, cap: int = 4096):
+    buf = (sf_iter_log * cap)()
+    n = ctypes.c_int()
+    code = lib.sf_get_log(ctx, buf, cap, ctypes.byref(n))
+    if code not in (SF_OK, -5):
+        _check(code, "sf_get_log")
+    out = []
+    for i in range(n.value):
+        r = buf[i]
+        out.append(dict(level=r.level, gn_iter=r.gn_iter, energy=r.energy,
+                        terms=dict(photo=r.e_photo, grad=r.e_grad,
+                                   smooth=r.e_smooth, epi=r.e_epi,
+                                   mag=r.e_mag),
+                        energy_after=r.energy_after, tau=r.tau,
+                        pcg_res=list(r.pcg_res[:r.pcg_iters]),
+                        n_valid=r.n_valid))
+    return out, code
+
+
+def sf_status_string(code: int) -> str:
+    return lib.sf_status_string(code).decode()
+
+
+def sf_destroy(ctx):
+    lib.sf_destroy(ctx)
+
+
+def sf_debug_size(ctx, what, level) -> int:
+    return lib.sf_debug_size(ctx, what, level)
+
+
+_DTYPE = {SF_DBG_TEX: np.float32, SF_DBG_CMASK: np.uint8,
+          SF_DBG_ENERGY: np.float64}
+
+
+def sf_debug_read(ctx, what, level) -> np.ndarray:
+    n = lib.sf_debug_size(ctx, what, level)
+    if n == 0:
+        raise SfError(-1, "sf_debug_size")
+    dt = _DTYPE.get(what, np.float32)
+    arr = np.empty(n // np.dtype(dt).itemsize, dt)
+    _check(lib.sf_debug_read(ctx, what, level, arr.ctypes.data, n),
+           "sf_debug_read")
+    return arr
+
+
+def sf_debug_write(ctx, what, level, arr):
+    dt = _DTYPE.get(what, np.float32)
+    a = np.ascontiguousarray(arr, dt)
+    _check(lib.sf_debug_write(ctx, what, level, a.ctypes.data, a.nbytes),
+           "sf_debug_write")
+
+
+def sf_debug_set_images(ctx, I_left_t, I_right_t, I_left_t1, I_right_t1,
+                        calib: sf_calib):
+    _check(lib.sf_debug_set_images(ctx, I_left_t, I_right_t, I_left_t1,
+                                   I_right_t1, ctypes.byref(calib)),
+           "sf_debug_set_images")
+
+
+def sf_debug_run(ctx, stage, level):
+    _check(lib.sf_debug_run(ctx, stage, level), "sf_debug_run")

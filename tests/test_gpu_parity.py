@@ -1,0 +1,219 @@
+"""GPU path vs the FP64 oracle, stage by stage and end to end, through the
+C ABI.  Tolerances: per-(level, step) energy within 1e-4 relative and final
+flows within 0.02 px (float32 path vs float64 oracle); per-stage quantities
+as stated at each check."""
+import numpy as np
+import pytest
+
+import oracle.halfway as O
+from synth import make_frame, tiny_plane_config, sized_config
+
+from gpu_util import GpuCase, oracle_params, mask_flip_ok, rel_err
+
+pytestmark = pytest.mark.gpu
+
+MED = dict(levels=3, grid_stride=4, gn_iters=3, pcg_iters=8)
+
+
+def _frame(W, H, seed=5, disp=None):
+    cfg = sized_config(W, H, max_disp=disp if disp is not None else 0.05 * W)
+    imgs, calib, _ = make_frame(cfg, seed)
+    return imgs, calib
+
+
+def _stage_case(W=100, H=76, **kw):
+    prm = dict(MED)
+    prm.update(kw)
+    imgs, calib = _frame(W, H)
+    g = GpuCase(imgs, calib, **prm)
+    g.set_images()
+    return g, imgs, calib, oracle_params(**prm)
+
+
+def _oracle_level(imgs, calib, p, level):
+    pyr = O.pyramid(imgs.astype(np.float64), p.levels)
+    H, W = pyr[level].shape[1:]
+    grid = O.Grid(W, H, p.grid_stride)
+    return O.setup_level(level, pyr, p, O.Calib.from_dict(calib),
+                         np.zeros((6, grid.G))), pyr
+
+
+def _kink_free_delta(ls, scale, seed):
+    """A random delta whose sample positions all keep 1e-3 px from the
+    bilinear interpolant's kinks (integer coordinates), so float32 and
+    float64 take the same interpolation cells."""
+    rng = np.random.default_rng(seed)
+    for _ in range(200):
+        delta = rng.normal(scale=scale, size=(6, ls.grid.G))
+        flows = ls.grid.to_pixels(ls.base + delta)
+        px, py = ls.grid.pixel_xy()
+        P = O.positions(px, py, flows)
+        if np.abs(P - np.round(P)).min() > 1e-3:
+            return delta
+    pytest.skip("no kink-free delta found")
+
+
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("W,H,levels", [(64, 48, 3), (100, 76, 3), (81, 53, 2),
+                                        (640, 480, 5)])
+def test_pyramid_parity(W, H, levels):
+    imgs = np.random.default_rng(1).random((4, H, W)).astype(np.float32)
+    calib = dict(fx=50.0, fy=50.0, cx=(W - 1) / 2, cy=(H - 1) / 2,
+                 baseline=0.1, F=np.array([[0, 0, 0], [0, 0, -1], [0, 1, 0.]]))
+    g = GpuCase(imgs, calib, levels=levels, grid_stride=4)
+    try:
+        g.set_images()
+        pyr = O.pyramid(imgs.astype(np.float64), levels)
+        for l in range(levels):
+            tex = g.read(g.sf.SF_DBG_TEX, l).reshape(4, pyr[l].shape[1], pyr[l].shape[2], 4)
+            # box filter in float32 vs float64: within a few float32 ulps
+            np.testing.assert_allclose(tex[..., 0], pyr[l], rtol=0, atol=2e-7 * (l + 1))
+            for c in range(4):
+                gx, gy = O.image_gradients(pyr[l][c])
+                np.testing.assert_allclose(tex[c, ..., 1], gx, rtol=0, atol=4e-7 * (l + 1))
+                np.testing.assert_allclose(tex[c, ..., 2], gy, rtol=0, atol=4e-7 * (l + 1))
+            assert np.all(tex[..., 3] == 0)
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("level", [0, 2])
+def test_level_init_parity(level):
+    g, imgs, calib, p = _stage_case()
+    try:
+        g.run(g.sf.SF_STAGE_LEVEL_INIT, level)
+        ls, _ = _oracle_level(imgs, calib, p, level)
+        cm = g.read(g.sf.SF_DBG_CMASK, level)
+        _, flips = mask_flip_ok(ls.li, ls.grid, ls.base, p, cm)
+        assert flips == 0
+        np.testing.assert_array_equal(cm.astype(bool), ls.cmask.astype(bool))
+        w = g.read(g.sf.SF_DBG_WNODE, level)
+        np.testing.assert_allclose(w, ls.wnode, rtol=1e-4, atol=1e-5)
+        assert np.all(g.read(g.sf.SF_DBG_BASE, level) == 0)
+        assert np.all(g.read(g.sf.SF_DBG_DELTA, level) == 0)
+    finally:
+        g.close()
+
+
+def _gram_upper(Gx):
+    iu = np.triu_indices(6)
+    return Gx[:, iu[0], iu[1]].T  # (21, N)
+
+
+@pytest.mark.parametrize("level", [0, 2])
+def test_linearize_apply_pcg_parity(level):
+    g, imgs, calib, p = _stage_case()
+    try:
+        g.run(g.sf.SF_STAGE_LEVEL_INIT, level)
+        ls, _ = _oracle_level(imgs, calib, p, level)
+        assert np.array_equal(g.read(g.sf.SF_DBG_CMASK, level).astype(bool),
+                              ls.cmask.astype(bool))
+        delta = _kink_free_delta(ls, 0.4, 10 + level)
+        g.write(g.sf.SF_DBG_DELTA, level, delta.astype(np.float32))
+        delta = g.read(g.sf.SF_DBG_DELTA, level).reshape(6, -1).astype(np.float64)
+        g.run(g.sf.SF_STAGE_LINEARIZE, level)
+
+        # per-pixel records: reweighted gradient (6) and Gauss-Newton block (21)
+        J, r, w = O.robust_rows(ls, delta, p)
+        gpx = np.einsum("nri,nr->in", J, w * r)
+        gram = _gram_upper(np.einsum("nri,nr,nrj->nij", J, w, J))
+        rec = g.read(g.sf.SF_DBG_REC, level).reshape(27, -1)
+        for k in range(6):
+            assert rel_err(rec[k], gpx[k]) < 2e-4, ("grad", k)
+        for k in range(21):
+            assert rel_err(rec[6 + k], gram[k]) < 2e-4, ("gram", k)
+
+        # energy terms at the linearisation point
+        e = O.energy(ls, delta, p)
+        eg = g.read(g.sf.SF_DBG_ENERGY, level)
+        for k, name in enumerate(("photo", "grad", "smooth", "epi", "mag", "total")):
+            assert eg[k] == pytest.approx(e[name], rel=2e-5, abs=1e-6), name
+
+        # right-hand side (r = -grad E) and diag(H)
+        grad, Hm = O.linearize(ls, delta, p)
+        R = g.read(g.sf.SF_DBG_R, level)
+        assert rel_err(R, -grad) < 2e-4
+        D = g.read(g.sf.SF_DBG_DIAG, level)
+        np.testing.assert_allclose(D, Hm.diagonal(), rtol=2e-4)
+
+        # q = H p for a random p
+        pv = np.random.default_rng(3).normal(size=6 * ls.grid.G).astype(np.float32)
+        g.write(g.sf.SF_DBG_Z, level, pv)
+        g.run(g.sf.SF_STAGE_APPLY, level)
+        Q = g.read(g.sf.SF_DBG_Q, level)
+        assert rel_err(Q, Hm @ pv.astype(np.float64)) < 2e-4
+        np.testing.assert_array_equal(g.read(g.sf.SF_DBG_P, level), pv)
+
+        # PCG from x = 0 on the same system
+        g.run(g.sf.SF_STAGE_LINEARIZE, level)
+        g.run(g.sf.SF_STAGE_PCG, level)
+        dx = g.read(g.sf.SF_DBG_DX, level)
+        ref = O.pcg(Hm, -grad, p.pcg_iters)
+        assert rel_err(dx, ref) < 5e-3
+    finally:
+        g.close()
+
+
+def _solve_parity(imgs, calib, prm, e_tol=1e-4, f_tol=0.02):
+    p = oracle_params(**prm)
+    rec = []
+    res = O.solve(imgs.astype(np.float64), calib, p, record=rec)
+    g = GpuCase(imgs, calib, **prm)
+    try:
+        depth, flow3d, flows = g.solve()
+        log, code = g.log()
+    finally:
+        g.close()
+    assert code == 0
+    assert len(log) == len(rec)
+    worst = 0.0
+    for lg, ro in zip(log, rec):
+        assert lg["level"] == ro["level"]
+        rel = abs(lg["energy"] - ro["energy"]) / abs(ro["energy"])
+        worst = max(worst, rel)
+        assert rel <= e_tol, (lg["level"], lg["gn_iter"], lg["energy"], ro["energy"])
+        assert lg["energy_after"] <= lg["energy"]
+    grid = res["grid"]
+    ref_flows = grid.to_pixels(res["total"]).reshape(6, grid.H, grid.W)
+    err = np.abs(flows - ref_flows).max()
+    assert err <= f_tol, err
+    d_ref, f3_ref, _ = O.output(grid, res["total"], O.Calib.from_dict(calib))
+    ok = np.isfinite(d_ref) & np.isfinite(depth)
+    assert np.array_equal(np.isfinite(d_ref), np.isfinite(depth)) or ok.mean() > 0.99
+    return worst, err, log, rec
+
+
+def test_solve_tiny_parity():
+    imgs, calib, _ = make_frame(tiny_plane_config(), 0)
+    prm = dict(levels=3, grid_stride=8, gn_iters=5, pcg_iters=10)
+    _solve_parity(imgs, calib, prm)
+
+
+@pytest.mark.parametrize("W,H,stride", [(100, 76, 4), (160, 120, 4), (96, 72, 2),
+                                        (144, 104, 8)])
+def test_solve_medium_parity(W, H, stride):
+    imgs, calib = _frame(W, H, seed=7)
+    prm = dict(levels=3, grid_stride=stride, gn_iters=4, pcg_iters=10)
+    _solve_parity(imgs, calib, prm)
+
+
+def test_graph_replay_matches_eager_and_repeats():
+    imgs, calib = _frame(128, 96, seed=9)
+    prm = dict(levels=3, grid_stride=4, gn_iters=3, pcg_iters=8)
+    outs = []
+    for mode in (1, 0, 0):
+        g = GpuCase(imgs, calib, exec_mode=mode, **prm)
+        try:
+            first = g.solve()
+            second = g.solve() if mode == 0 else first
+            outs.append((first, second, g.log()[0]))
+        finally:
+            g.close()
+    eager = outs[0][0]
+    for first, second, log in outs[1:]:
+        for a, b in zip(eager, first):
+            np.testing.assert_array_equal(a, b)
+        for a, b in zip(first, second):
+            np.testing.assert_array_equal(a, b)
+        assert [l["energy"] for l in log] == [l["energy"] for l in outs[0][2]]
