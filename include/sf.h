@@ -183,6 +183,26 @@ enum {
 };
 sf_status sf_debug_run(sf_ctx *ctx, int stage, int level);
 
+/* ---- measurement support ---------------------------------------------------
+ * Launches one solver kernel `reps` times back to back on the context's
+ * stream at `level`, on the state left by the last solve (its last
+ * linearisation), between two HIP events recorded on that same stream, and
+ * writes the average duration per launch in milliseconds to *avg_ms.
+ * Synchronises the stream.  The kernel's outputs are scratch afterwards.
+ *  SF_KERNEL_APPLY      q = H p (matrix-free, node tiles)
+ *  SF_KERNEL_LINEARIZE  per-pixel records and energy
+ *  SF_KERNEL_UPDATE     PCG vector update
+ *  SF_KERNEL_RHS        right-hand side and diag(H) (node tiles)
+ * Errors: SF_ERR_STATE before the first solve, SF_ERR_INVALID_ARG. */
+enum {
+    SF_KERNEL_APPLY = 0,
+    SF_KERNEL_LINEARIZE = 1,
+    SF_KERNEL_UPDATE = 2,
+    SF_KERNEL_RHS = 3
+};
+sf_status sf_time_kernel(sf_ctx *ctx, int kernel, int level, int reps,
+                         float *avg_ms);
+
 #ifdef __cplusplus
 }
 #endif

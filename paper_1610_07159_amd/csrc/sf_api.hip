@@ -569,4 +569,45 @@ sf_status sf_debug_run(sf_ctx *c, int stage, int level) {
     return SF_OK;
 }
 
+sf_status sf_time_kernel(sf_ctx *c, int kernel, int level, int reps, float *avg_ms) {
+    if (!c || !avg_ms || level < 0 || level >= c->L || reps < 1) return SF_ERR_INVALID_ARG;
+    if (!c->have_images) return SF_ERR_STATE;
+    hipStream_t st = c->stream;
+    const LevelArgs a = level_args(c, level);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return SF_ERR_HIP;
+    }
+    sf_status s = SF_OK;
+    auto one = [&](int i) {
+        switch (kernel) {
+            case SF_KERNEL_APPLY: launch_apply(st, a, c->tile, 1 + (i & 1), -1); break;
+            case SF_KERNEL_LINEARIZE: launch_energy(st, a, 0, 0, 0.f, 0); break;
+            case SF_KERNEL_UPDATE: launch_update(st, a, 1 + (i & 1), -1); break;
+            case SF_KERNEL_RHS: launch_node_rhs(st, a, c->tile); break;
+        }
+    };
+    if (kernel < SF_KERNEL_APPLY || kernel > SF_KERNEL_RHS) {
+        s = SF_ERR_INVALID_ARG;
+    } else {
+        // the PCG kernels run on an active iteration (as in the solve, not
+        // the first one); the scalars are scratch afterwards
+        launch_set_pcg_state(st, c->sc);
+        one(0);  // warm-up
+        if (hipEventRecord(e0, st) != hipSuccess) s = SF_ERR_HIP;
+        for (int i = 0; i < reps && s == SF_OK; ++i) one(i);
+        if (s == SF_OK && hipEventRecord(e1, st) != hipSuccess) s = SF_ERR_HIP;
+        if (s == SF_OK && hipGetLastError() != hipSuccess) s = SF_ERR_HIP;
+        if (s == SF_OK && hipEventSynchronize(e1) != hipSuccess) s = SF_ERR_HIP;
+        float ms = 0.f;
+        if (s == SF_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) s = SF_ERR_HIP;
+        if (s == SF_OK) *avg_ms = ms / (float)reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return s;
+}
+
 }  // extern "C"

@@ -119,6 +119,7 @@ void launch_finish_level(hipStream_t st, const LevelArgs &a);
 void launch_output(hipStream_t st, const LevelArgs &a, float *depth,
                    float *flow3d, float *flows);
 void launch_set_apply_state(hipStream_t st, DevScalars *sc);
+void launch_set_pcg_state(hipStream_t st, DevScalars *sc);
 size_t node_tile_lds_bytes(const TileCfg &t, int s, int K);
 int energy_blocks(const LevelDims &d);
 int node_tile_blocks(const LevelDims &d, const TileCfg &t);

@@ -1102,6 +1102,18 @@ __global__ void k_set_apply_state(DevScalars *sc) {
     }
 }
 
+// A mid-solve PCG state for timing: active, not the first iteration, so
+// every launch does the full work (p = z + beta p_old, all updates).
+__global__ void k_set_pcg_state(DevScalars *sc) {
+    if (threadIdx.x == 0) {
+        sc->active = 1;
+        sc->first = 0;
+        sc->beta = 0.5f;
+        sc->alpha = 0.f;
+        sc->rz = 1.0;
+    }
+}
+
 }  // namespace
 
 // ---- launchers ----------------------------------------------------------------
@@ -1195,4 +1207,8 @@ void launch_output(hipStream_t st, const LevelArgs &a, float *depth,
 
 void launch_set_apply_state(hipStream_t st, DevScalars *sc) {
     hipLaunchKernelGGL(k_set_apply_state, dim3(1), dim3(64), 0, st, sc);
+}
+
+void launch_set_pcg_state(hipStream_t st, DevScalars *sc) {
+    hipLaunchKernelGGL(k_set_pcg_state, dim3(1), dim3(64), 0, st, sc);
 }

@@ -26,6 +26,7 @@ SF_DBG_DX, SF_DBG_R, SF_DBG_Z, SF_DBG_Q, SF_DBG_DIAG = 5, 6, 7, 8, 9
 SF_DBG_REC, SF_DBG_P, SF_DBG_ENERGY = 10, 11, 12
 SF_STAGE_LEVEL_INIT, SF_STAGE_LINEARIZE, SF_STAGE_APPLY = 0, 1, 2
 SF_STAGE_PCG, SF_STAGE_GN, SF_STAGE_FINISH = 3, 4, 5
+SF_KERNEL_APPLY, SF_KERNEL_LINEARIZE, SF_KERNEL_UPDATE, SF_KERNEL_RHS = 0, 1, 2, 3
 
 
 class SfError(RuntimeError):
@@ -91,9 +92,10 @@ def _load():
     lib.sf_debug_set_images.argtypes = [P, P, P, P, P,
                                         ctypes.POINTER(sf_calib)]
     lib.sf_debug_run.argtypes = [P, I, I]
+    lib.sf_time_kernel.argtypes = [P, I, I, I, ctypes.POINTER(ctypes.c_float)]
     for f in ("sf_params_default", "sf_create", "sf_solve", "sf_get_log",
               "sf_debug_read", "sf_debug_write", "sf_debug_set_images",
-              "sf_debug_run"):
+              "sf_debug_run", "sf_time_kernel"):
         getattr(lib, f).restype = I
     return lib
 
@@ -204,3 +206,12 @@ def sf_debug_set_images(ctx, I_left_t, I_right_t, I_left_t1, I_right_t1,
 
 def sf_debug_run(ctx, stage, level):
     _check(lib.sf_debug_run(ctx, stage, level), "sf_debug_run")
+
+
+def sf_time_kernel(ctx, kernel, level, reps) -> float:
+    """Average milliseconds per launch of one solver kernel (HIP events on
+    the context's stream)."""
+    ms = ctypes.c_float()
+    _check(lib.sf_time_kernel(ctx, kernel, level, reps, ctypes.byref(ms)),
+           "sf_time_kernel")
+    return ms.value

@@ -38,19 +38,19 @@ def _oracle_level(imgs, calib, p, level):
                          np.zeros((6, grid.G))), pyr
 
 
-def _kink_free_delta(ls, scale, seed):
-    """A random delta whose sample positions all keep 1e-3 px from the
-    bilinear interpolant's kinks (integer coordinates), so float32 and
-    float64 take the same interpolation cells."""
-    rng = np.random.default_rng(seed)
-    for _ in range(200):
-        delta = rng.normal(scale=scale, size=(6, ls.grid.G))
-        flows = ls.grid.to_pixels(ls.base + delta)
-        px, py = ls.grid.pixel_xy()
-        P = O.positions(px, py, flows)
-        if np.abs(P - np.round(P)).min() > 1e-3:
-            return delta
-    pytest.skip("no kink-free delta found")
+def _kink_pixels(ls, delta, margin=1e-4):
+    """Pixels with a sample position within `margin` px of an integer
+    coordinate, where the bilinear interpolant has a kink: there float32
+    and float64 may pick different cells, and both one-sided derivatives
+    are valid.  Also returns the nodes such pixels touch."""
+    flows = ls.grid.to_pixels(ls.base + delta)
+    px, py = ls.grid.pixel_xy()
+    P = O.positions(px, py, flows)
+    kink = (np.abs(P - np.round(P)) < margin).any(axis=(0, 1))
+    touched = np.zeros(ls.grid.G, bool)
+    for k in range(4):
+        touched[ls.grid.nodes[k][kink]] = True
+    return kink, touched
 
 
 # ----------------------------------------------------------------------------
@@ -109,10 +109,14 @@ def test_linearize_apply_pcg_parity(level):
         ls, _ = _oracle_level(imgs, calib, p, level)
         assert np.array_equal(g.read(g.sf.SF_DBG_CMASK, level).astype(bool),
                               ls.cmask.astype(bool))
-        delta = _kink_free_delta(ls, 0.4, 10 + level)
+        delta = np.random.default_rng(10 + level).normal(scale=0.4, size=(6, ls.grid.G))
         g.write(g.sf.SF_DBG_DELTA, level, delta.astype(np.float32))
         delta = g.read(g.sf.SF_DBG_DELTA, level).reshape(6, -1).astype(np.float64)
         g.run(g.sf.SF_STAGE_LINEARIZE, level)
+        kink, kink_nodes = _kink_pixels(ls, delta)
+        smooth_px = ~kink
+        nodes6 = np.tile(~kink_nodes, 6)
+        assert smooth_px.mean() > 0.98
 
         # per-pixel records: reweighted gradient (6) and Gauss-Newton block (21)
         J, r, w = O.robust_rows(ls, delta, p)
@@ -120,9 +124,9 @@ def test_linearize_apply_pcg_parity(level):
         gram = _gram_upper(np.einsum("nri,nr,nrj->nij", J, w, J))
         rec = g.read(g.sf.SF_DBG_REC, level).reshape(27, -1)
         for k in range(6):
-            assert rel_err(rec[k], gpx[k]) < 2e-4, ("grad", k)
+            assert rel_err(rec[k][smooth_px], gpx[k][smooth_px]) < 2e-4, ("grad", k)
         for k in range(21):
-            assert rel_err(rec[6 + k], gram[k]) < 2e-4, ("gram", k)
+            assert rel_err(rec[6 + k][smooth_px], gram[k][smooth_px]) < 2e-4, ("gram", k)
 
         # energy terms at the linearisation point
         e = O.energy(ls, delta, p)
@@ -133,16 +137,16 @@ def test_linearize_apply_pcg_parity(level):
         # right-hand side (r = -grad E) and diag(H)
         grad, Hm = O.linearize(ls, delta, p)
         R = g.read(g.sf.SF_DBG_R, level)
-        assert rel_err(R, -grad) < 2e-4
+        assert rel_err(R[nodes6], -grad[nodes6]) < 2e-4
         D = g.read(g.sf.SF_DBG_DIAG, level)
-        np.testing.assert_allclose(D, Hm.diagonal(), rtol=2e-4)
+        np.testing.assert_allclose(D[nodes6], Hm.diagonal()[nodes6], rtol=2e-4)
 
         # q = H p for a random p
         pv = np.random.default_rng(3).normal(size=6 * ls.grid.G).astype(np.float32)
         g.write(g.sf.SF_DBG_Z, level, pv)
         g.run(g.sf.SF_STAGE_APPLY, level)
         Q = g.read(g.sf.SF_DBG_Q, level)
-        assert rel_err(Q, Hm @ pv.astype(np.float64)) < 2e-4
+        assert rel_err(Q[nodes6], (Hm @ pv.astype(np.float64))[nodes6]) < 2e-4
         np.testing.assert_array_equal(g.read(g.sf.SF_DBG_P, level), pv)
 
         # PCG from x = 0 on the same system
