@@ -55,7 +55,7 @@ typedef struct {
 
 /* Energy weights (Eqs. (8)-(10), (14), (18); Appendix A) and schedule.
  *  levels          pyramid levels (coarse-to-fine hierarchy, Sec. 5.3)
- *  grid_stride     warp-grid step in pixels at every level (Sec. 3.3)
+ *  grid_stride     warp-grid step in pixels at every level (Sec. 3.3), 1..8
  *  gn_iters        Gauss-Newton steps per level
  *  pcg_iters       PCG iterations per Gauss-Newton step (1..64)
  *  max_backtracks  step-length halvings after tau = 1 (0..7)
@@ -144,12 +144,12 @@ enum {
     SF_DBG_DELTA = 4,   /* 6 x G_l float: delta unknowns                     */
     SF_DBG_DX = 5,      /* 6 x G_l float: PCG solution (GN step)             */
     SF_DBG_R = 6,       /* 6 x G_l float: PCG residual (initially -grad E)   */
-    SF_DBG_Z = 7,       /* 6 x G_l float: preconditioned residual            */
-    SF_DBG_Q = 8,       /* 6 x G_l float: last H p                           */
+    SF_DBG_Z = 7,       /* 6 x G_l float: preconditioned residual u          */
+    SF_DBG_Q = 8,       /* 6 x G_l float: H u of the first PCG product        */
     SF_DBG_DIAG = 9,    /* 6 x G_l float: diag(H)                            */
     SF_DBG_REC = 10,    /* 27 x N_l float: per-pixel gradient (6) and
                            upper-triangular Gauss-Newton block (21)          */
-    SF_DBG_P = 11,      /* 6 x G_l float: last search direction              */
+    SF_DBG_P = 11,      /* 6 x G_l float: the vector the first product used  */
     SF_DBG_ENERGY = 12  /* 6 double: photo, grad, smooth, epi, mag, total
                            at the last linearisation                         */
 };
@@ -189,10 +189,12 @@ sf_status sf_debug_run(sf_ctx *ctx, int stage, int level);
  * linearisation), between two HIP events recorded on that same stream, and
  * writes the average duration per launch in milliseconds to *avg_ms.
  * Synchronises the stream.  The kernel's outputs are scratch afterwards.
- *  SF_KERNEL_APPLY      q = H p (matrix-free, node tiles)
+ *  SF_KERNEL_APPLY      one PCG iteration: vector updates + w = H u
+ *                       (matrix-free, node tiles)
  *  SF_KERNEL_LINEARIZE  per-pixel records and energy
- *  SF_KERNEL_UPDATE     PCG vector update
+ *  SF_KERNEL_UPDATE     the last PCG iteration's vector update
  *  SF_KERNEL_RHS        right-hand side and diag(H) (node tiles)
+ * The PCG kernels run forced active with fixed step lengths. 
  * Errors: SF_ERR_STATE before the first solve, SF_ERR_INVALID_ARG. */
 enum {
     SF_KERNEL_APPLY = 0,

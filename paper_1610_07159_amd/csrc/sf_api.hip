@@ -22,6 +22,7 @@ struct sf_ctx {
     float4 *tex = nullptr;
     unsigned char *cmask = nullptr;
     float *wnode = nullptr;
+    float *reg = nullptr;
     float *nodes = nullptr;
     float *rec = nullptr;
     float *partials = nullptr;
@@ -35,7 +36,6 @@ struct sf_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool have_images = false;
-    int last_p = NV_P0;
 };
 
 namespace {
@@ -48,7 +48,7 @@ namespace {
 sf_status check_params(const sf_params *p) {
     if (!p) return SF_ERR_INVALID_ARG;
     if (p->levels < 1 || p->levels > SF_MAX_LEVELS) return SF_ERR_INVALID_ARG;
-    if (p->grid_stride < 1 || p->grid_stride > 64) return SF_ERR_INVALID_ARG;
+    if (p->grid_stride < 1 || p->grid_stride > 8) return SF_ERR_INVALID_ARG;
     if (p->gn_iters < 1 || p->gn_iters > 1000) return SF_ERR_INVALID_ARG;
     if (p->pcg_iters < 1 || p->pcg_iters > SF_MAX_PCG) return SF_ERR_INVALID_ARG;
     if (p->max_backtracks < 0 || p->max_backtracks > SF_MAX_TRIALS - 1) return SF_ERR_INVALID_ARG;
@@ -69,20 +69,6 @@ bool same_schedule(const sf_params &a, const sf_params &b) {
     return a.levels == b.levels && a.grid_stride == b.grid_stride &&
            a.gn_iters == b.gn_iters && a.pcg_iters == b.pcg_iters &&
            a.max_backtracks == b.max_backtracks && a.init_mode == b.init_mode;
-}
-
-// Tile shape of the node-tile kernels: about 32 x 32 owned pixels per
-// workgroup, at most 256 nodes.
-TileCfg pick_tile(int s) {
-    TileCfg t;
-    int n = s >= 32 ? 1 : 32 / s;
-    if (n > 16) n = 16;
-    if (n < 2) n = 2;
-    t.tx = n;
-    t.ty = n;
-    t.rb = s >= 8 ? 8 : 2 * s;
-    if (t.rb < 4) t.rb = 4;
-    return t;
 }
 
 void fill_const(const sf_ctx *c, const sf_params &p, const sf_calib &cal, DevConst &k) {
@@ -143,6 +129,7 @@ LevelArgs level_args(sf_ctx *c, int l) {
     a.rec = c->rec;
     a.cmask = c->cmask;
     a.wnode = c->wnode;
+    a.reg = c->reg;
     a.partials = c->partials;
     a.max_blocks = c->max_blocks;
     a.cst = c->dconst;
@@ -166,17 +153,16 @@ void enqueue_level_init(sf_ctx *c, hipStream_t st, int l) {
 
 void enqueue_linearize(sf_ctx *c, hipStream_t st, int l) {
     const LevelArgs a = level_args(c, l);
-    launch_energy(st, a, 0, 0, 0.f, 0);
-    launch_node_rhs(st, a, c->tile);
+    launch_linearize(st, a);
+    launch_rhs(st, a, c->tile);
 }
 
 void enqueue_pcg(sf_ctx *c, hipStream_t st, int l, int log_index) {
     const LevelArgs a = level_args(c, l);
-    for (int i = 0; i < c->prm.pcg_iters; ++i) {
-        launch_apply(st, a, c->tile, i, log_index);
-        launch_update(st, a, i, log_index);
-    }
-    c->last_p = ((c->prm.pcg_iters - 1) & 1) ? NV_P1 : NV_P0;
+    const int n = c->prm.pcg_iters;
+    launch_pcg_first(st, a, c->tile);
+    for (int i = 1; i < n; ++i) launch_pcg_iter(st, a, c->tile, i, log_index, 0);
+    launch_pcg_last(st, a, c->tile, n, log_index, 0);
 }
 
 void enqueue_gn(sf_ctx *c, hipStream_t st, int l, int g, int log_index) {
@@ -184,8 +170,8 @@ void enqueue_gn(sf_ctx *c, hipStream_t st, int l, int g, int log_index) {
     enqueue_pcg(c, st, l, log_index);
     const LevelArgs a = level_args(c, l);
     const int T = c->prm.max_backtracks + 1;
-    for (int j = 0; j < T; ++j) launch_energy(st, a, 1, j, ldexpf(1.f, -j), j);
-    launch_accept(st, a, T, log_index, g, c->prm.pcg_iters);
+    for (int j = 0; j < T; ++j) launch_trial(st, a, j, ldexpf(1.f, -j));
+    launch_accept(st, a, c->tile, T, log_index, g, c->prm.pcg_iters);
 }
 
 void enqueue_levels(sf_ctx *c, hipStream_t st) {
@@ -251,6 +237,7 @@ void free_all(sf_ctx *c) {
     (void)hipFree(c->tex);
     (void)hipFree(c->cmask);
     (void)hipFree(c->wnode);
+    (void)hipFree(c->reg);
     (void)hipFree(c->nodes);
     (void)hipFree(c->rec);
     (void)hipFree(c->partials);
@@ -338,7 +325,9 @@ sf_status sf_create(sf_ctx **out, int width, int height, const sf_params *p,
         mb = mb > gb ? mb : gb;
     }
     c->max_blocks = mb;
-    if (node_tile_lds_bytes(c->tile, st, 12) > 64 * 1024) {
+    if (node_tile_lds_bytes(c->tile, st, 12) > 64 * 1024 ||
+        node_tile_lds_bytes(c->tile, st, 6) > 64 * 1024 ||
+        tile_max_pixels(c->tile, st) > tile_ppt() * tile_threads()) {
         delete c;
         return SF_ERR_INVALID_ARG;
     }
@@ -351,9 +340,10 @@ sf_status sf_create(sf_ctx **out, int width, int height, const sf_params *p,
     ok = ok && hipMalloc(&c->tex, sizeof(float4) * tex_off) == hipSuccess;
     ok = ok && hipMalloc(&c->cmask, c->N0) == hipSuccess;
     ok = ok && hipMalloc(&c->wnode, sizeof(float) * c->G0) == hipSuccess;
+    ok = ok && hipMalloc(&c->reg, sizeof(float) * 16 * c->G0) == hipSuccess;
     ok = ok && hipMalloc(&c->nodes, sizeof(float) * NV_COUNT * 6 * c->G0) == hipSuccess;
     ok = ok && hipMalloc(&c->rec, sizeof(float) * SF_REC_PLANES * c->N0) == hipSuccess;
-    ok = ok && hipMalloc(&c->partials, sizeof(float) * 8 * (size_t)mb) == hipSuccess;
+    ok = ok && hipMalloc(&c->partials, sizeof(float) * PS_COUNT * (size_t)mb) == hipSuccess;
     ok = ok && hipMalloc(&c->dconst, sizeof(DevConst)) == hipSuccess;
     ok = ok && hipMalloc(&c->sc, sizeof(DevScalars)) == hipSuccess;
     ok = ok && hipMalloc(&c->dlog, sizeof(DevLog) * c->nlog) == hipSuccess;
@@ -472,16 +462,16 @@ size_t sf_debug_size(sf_ctx *c, int what, int level) {
     return 0;
 }
 
-static int node_vec_of(sf_ctx *c, int what) {
+static int node_vec_of(sf_ctx *, int what) {
     switch (what) {
         case SF_DBG_BASE: return NV_BASE;
         case SF_DBG_DELTA: return NV_DELTA;
-        case SF_DBG_DX: return NV_DX;
-        case SF_DBG_R: return NV_R;
-        case SF_DBG_Z: return NV_Z;
-        case SF_DBG_Q: return NV_Q;
+        case SF_DBG_DX: return NV_X;
+        case SF_DBG_R: return NV_R0;
+        case SF_DBG_Z: return NV_U;
+        case SF_DBG_Q: return NV_W0;
         case SF_DBG_DIAG: return NV_DIAG;
-        case SF_DBG_P: return c->last_p;
+        case SF_DBG_P: return NV_U;
     }
     return -1;
 }
@@ -554,11 +544,7 @@ sf_status sf_debug_run(sf_ctx *c, int stage, int level) {
     switch (stage) {
         case SF_STAGE_LEVEL_INIT: enqueue_level_init(c, st, level); break;
         case SF_STAGE_LINEARIZE: enqueue_linearize(c, st, level); break;
-        case SF_STAGE_APPLY:
-            launch_set_apply_state(st, c->sc);
-            launch_apply(st, a, c->tile, 0, -1);
-            c->last_p = NV_P0;
-            break;
+        case SF_STAGE_APPLY: launch_pcg_first(st, a, c->tile); break;
         case SF_STAGE_PCG: enqueue_pcg(c, st, level, -1); break;
         case SF_STAGE_GN: enqueue_gn(c, st, level, 0, -1); break;
         case SF_STAGE_FINISH: launch_finish_level(st, a); break;
@@ -583,18 +569,17 @@ sf_status sf_time_kernel(sf_ctx *c, int kernel, int level, int reps, float *avg_
     sf_status s = SF_OK;
     auto one = [&](int i) {
         switch (kernel) {
-            case SF_KERNEL_APPLY: launch_apply(st, a, c->tile, 1 + (i & 1), -1); break;
-            case SF_KERNEL_LINEARIZE: launch_energy(st, a, 0, 0, 0.f, 0); break;
-            case SF_KERNEL_UPDATE: launch_update(st, a, 1 + (i & 1), -1); break;
-            case SF_KERNEL_RHS: launch_node_rhs(st, a, c->tile); break;
+            case SF_KERNEL_APPLY: launch_pcg_iter(st, a, c->tile, 2 + (i & 1), -1, 1); break;
+            case SF_KERNEL_LINEARIZE: launch_linearize(st, a); break;
+            case SF_KERNEL_UPDATE: launch_pcg_last(st, a, c->tile, 2 + (i & 1), -1, 1); break;
+            case SF_KERNEL_RHS: launch_rhs(st, a, c->tile); break;
         }
     };
     if (kernel < SF_KERNEL_APPLY || kernel > SF_KERNEL_RHS) {
         s = SF_ERR_INVALID_ARG;
     } else {
-        // the PCG kernels run on an active iteration (as in the solve, not
-        // the first one); the scalars are scratch afterwards
-        launch_set_pcg_state(st, c->sc);
+        // the PCG kernels are forced active with fixed step lengths so that
+        // every launch does the full work; the state is scratch afterwards
         one(0);  // warm-up
         if (hipEventRecord(e0, st) != hipSuccess) s = SF_ERR_HIP;
         for (int i = 0; i < reps && s == SF_OK; ++i) one(i);

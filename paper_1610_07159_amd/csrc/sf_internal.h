@@ -18,19 +18,33 @@
 #define SF_REC_GRAM 21
 #define SF_REC_PLANES 27
 
-// Node vectors (each 6 planes of G_0 floats).
+// Node vectors (each 6 planes of G_0 floats).  The PCG runs in the
+// single-reduction form: r, w = H u and s = H p alternate between two
+// buffers by iteration parity because neighbouring tiles read them.
 enum {
     NV_BASE = 0,
     NV_DELTA,
-    NV_DX,
-    NV_R,
-    NV_Z,
-    NV_P0,
-    NV_P1,
-    NV_Q,
+    NV_X,      // PCG solution (the Gauss-Newton step)
+    NV_R0,
+    NV_R1,
+    NV_U,      // preconditioned residual
+    NV_W0,
+    NV_W1,
+    NV_S0,
+    NV_S1,
+    NV_P,
     NV_DIAG,
-    NV_TPREV,
+    NV_TPREV,  // total of the level just solved (for prolongation)
     NV_COUNT
+};
+
+// Partial-sum planes (each max_blocks floats).
+enum {
+    PS_E = 0,        // 5 planes: energy terms per workgroup
+    PS_PCG0 = 5,     // 3 planes: r.u, w.u, r.r (even iterations)
+    PS_PCG1 = 8,     // 3 planes: odd iterations
+    PS_MASK = 11,    // 1 plane: valid-pixel counts
+    PS_COUNT = 12
 };
 
 // Sizes of one pyramid level.
@@ -52,15 +66,22 @@ struct DevConst {
     float F[SF_MAX_LEVELS][9];  // fundamental matrix in level pixels
 };
 
-// Device-resident scalars of the solve.  Each is written by the last
-// workgroup of the kernel that reduces it and read by later kernels only.
+// Scalars of one PCG iteration k, stored in slot k + 1 (slot 0 is the
+// state before the first iteration).
+struct PcgHist {
+    double gamma;   // r_k . u_k
+    float alpha, beta;
+    int active;     // iteration k was applied
+    int pad;
+};
+
+// Device-resident scalars of the solve.  Every slot is written by exactly
+// one workgroup (or the last to arrive) and read only by later kernels.
 struct DevScalars {
     unsigned int counter[4];          // arrival counters (reset by the last)
     double e_lin[6];                  // photo, grad, smooth, epi, mag, total
     double e_trial[SF_MAX_TRIALS][6]; // same for each trial step length
-    double rz, rr, pq, pp;            // PCG inner products
-    float alpha, beta;
-    int active, first;
+    PcgHist hist[SF_MAX_PCG + 2];
     int n_valid;
     int pad;
 };
@@ -75,10 +96,10 @@ struct DevLog {
     int n_valid;
 };
 
-// Launch geometry of the node-tile kernels.
+// Launch geometry of the node-tile kernels: tx x ty nodes per 512-thread
+// workgroup, tpn threads per node (tx * ty * tpn = 512, tpn <= 64).
 struct TileCfg {
-    int tx, ty;    // nodes per workgroup
-    int rb;        // pixel rows per strip of the pixel->node reduction
+    int tx, ty, tpn;
 };
 
 // Everything a kernel needs about the current level, by value.
@@ -92,6 +113,7 @@ struct LevelArgs {
     float *rec;            // per-pixel records
     unsigned char *cmask;  // V(x) W(x)
     float *wnode;          // smoothness weights
+    float *reg;            // 16 planes of G_0: per-node regulariser record
     float *partials;       // per-workgroup partial sums
     int max_blocks;        // stride of the partial-sum planes
     const DevConst *cst;
@@ -106,20 +128,23 @@ void launch_downsample(hipStream_t st, const float4 *src, int Ws, int Hs,
                        float4 *dst, int Wd, int Hd);
 void launch_level_init(hipStream_t st, const LevelArgs &a,
                        const LevelDims *coarse, bool coarsest);
-void launch_energy(hipStream_t st, const LevelArgs &a, int mode, int trial,
-                   float tau, int n_trials_before);
-void launch_node_rhs(hipStream_t st, const LevelArgs &a, const TileCfg &t);
-void launch_apply(hipStream_t st, const LevelArgs &a, const TileCfg &t,
-                  int iter, int log_index);
-void launch_update(hipStream_t st, const LevelArgs &a, int iter,
-                   int log_index);
-void launch_accept(hipStream_t st, const LevelArgs &a, int n_trials,
-                   int log_index, int gn_iter, int pcg_iters);
+void launch_linearize(hipStream_t st, const LevelArgs &a);
+void launch_trial(hipStream_t st, const LevelArgs &a, int trial, float tau);
+void launch_rhs(hipStream_t st, const LevelArgs &a, const TileCfg &t);
+void launch_pcg_first(hipStream_t st, const LevelArgs &a, const TileCfg &t);
+void launch_pcg_iter(hipStream_t st, const LevelArgs &a, const TileCfg &t,
+                     int iter, int log_index, int force);
+void launch_pcg_last(hipStream_t st, const LevelArgs &a, const TileCfg &t,
+                     int iter, int log_index, int force);
+void launch_accept(hipStream_t st, const LevelArgs &a, const TileCfg &t,
+                   int n_trials, int log_index, int gn_iter, int pcg_iters);
 void launch_finish_level(hipStream_t st, const LevelArgs &a);
 void launch_output(hipStream_t st, const LevelArgs &a, float *depth,
                    float *flow3d, float *flows);
-void launch_set_apply_state(hipStream_t st, DevScalars *sc);
-void launch_set_pcg_state(hipStream_t st, DevScalars *sc);
+TileCfg pick_tile(int s);
+int tile_threads();
+int tile_max_pixels(const TileCfg &t, int s);
+int tile_ppt();
 size_t node_tile_lds_bytes(const TileCfg &t, int s, int K);
 int energy_blocks(const LevelDims &d);
 int node_tile_blocks(const LevelDims &d, const TileCfg &t);

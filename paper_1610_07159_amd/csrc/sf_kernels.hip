@@ -17,6 +17,9 @@
 
 #include "sf_internal.h"
 
+#define NT_TILE 512   // threads of a node-tile workgroup
+#define PPT 2         // max region pixels per thread (checked on the host)
+
 namespace {
 
 // sign of (s, m, d) in the sample position of camera L0, R0, L1, R1
@@ -70,33 +73,79 @@ __device__ __forceinline__ Bracket bracket(int x, int s, int G) {
     b.i0 = c; b.i1 = c + 1; b.w0 = 1.f - f; b.w1 = f;
     return b;
 }
-// first / last pixel whose bracket contains node i
+// First / last pixel where node i has a nonzero bilinear weight (pixels
+// clamped beyond the last node weigh only on node G-1, those before the
+// first node only on node 0).
 __device__ __forceinline__ int sup_lo(int i, int s) {
-    return i <= 1 ? 0 : ((2 * i - 1) * s) / 2;
+    return i == 0 ? 0 : ((2 * i - 1) * s) / 2;
 }
 __device__ __forceinline__ int sup_hi(int i, int s, int G, int W) {
-    return i >= G - 2 ? W - 1 : min(W - 1, ((2 * i + 3) * s) / 2 - 1);
+    return i >= G - 1 ? W - 1 : min(W - 1, ((2 * i + 3) * s) / 2 - 1);
 }
 
 // ---- reductions ----------------------------------------------------------
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Lane sums with DPP (data-parallel primitives fused into the add): within a
+// row of 16 lanes by quad permutations and mirrors, across rows with
+// readlane.  `width` (a power of two, uniform) is the size of the groups of
+// consecutive lanes summed; every lane of a group receives the group's sum.
+// Must be called with all lanes of the wavefront active.
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dppd(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ float readlane_f(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T dpp_step(T v, int ctrl_id);
+template <>
+__device__ __forceinline__ float dpp_step<float>(float v, int c) {
+    return c == 0 ? dppf<0xB1>(v) : c == 1 ? dppf<0x4E>(v) : c == 2 ? dppf<0x141>(v) : dppf<0x140>(v);
+}
+template <>
+__device__ __forceinline__ double dpp_step<double>(double v, int c) {
+    return c == 0 ? dppd<0xB1>(v) : c == 1 ? dppd<0x4E>(v) : c == 2 ? dppd<0x141>(v) : dppd<0x140>(v);
+}
+__device__ __forceinline__ float rl(float v, int l) { return readlane_f(v, l); }
+__device__ __forceinline__ double rl(double v, int l) { return readlane_d(v, l); }
+
+template <typename T>
+__device__ __forceinline__ T group_sum(T v, int width) {
+    if (width >= 2) v += dpp_step<T>(v, 0);   // quad_perm [1,0,3,2]: lane ^ 1
+    if (width >= 4) v += dpp_step<T>(v, 1);   // quad_perm [2,3,0,1]: lane ^ 2
+    if (width >= 8) v += dpp_step<T>(v, 2);   // row_half_mirror
+    if (width >= 16) v += dpp_step<T>(v, 3);  // row_mirror
+    if (width >= 32) {
+        const T r0 = rl(v, 0), r1 = rl(v, 16), r2 = rl(v, 32), r3 = rl(v, 48);
+        if (width == 32) v = (threadIdx.x & 32) ? r2 + r3 : r0 + r1;
+        else v = (r0 + r1) + (r2 + r3);
+    }
     return v;
 }
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+__device__ __forceinline__ float wave_sum(float v) { return group_sum<float>(v, 64); }
+__device__ __forceinline__ double wave_sum_d(double v) { return group_sum<double>(v, 64); }
 
 // Sums K per-thread values over the (256-thread) block; the result is valid
 // in thread 0.  Fixed order, so bitwise reproducible.
 template <int K>
 __device__ void block_sum(float (&v)[K], float (&out)[K]) {
-    __shared__ float red[4][K];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ float red[16][K];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const float s = wave_sum(v[k]);
@@ -105,23 +154,27 @@ __device__ void block_sum(float (&v)[K], float (&out)[K]) {
     __syncthreads();
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            out[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+        for (int k = 0; k < K; ++k) {
+            float acc = red[0][k];
+            for (int w = 1; w < nw; ++w) acc += red[w][k];
+            out[k] = acc;
+        }
     }
     __syncthreads();
 }
 
-// Sum in double of n partials (plane `plane` of the partial buffer) by the
-// whole block; result valid in thread 0.
+// Sum in double of n partials by the whole block; result valid in every
+// thread.  Fixed order, so bitwise reproducible.
 __device__ double block_sum_partials(const float *part, int n) {
-    __shared__ double red[4];
+    __shared__ double red[16];
     double acc = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) acc += (double)part[i];
     acc = wave_sum_d(acc);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if (lane == 0) red[wv] = acc;
     __syncthreads();
-    double r = ((red[0] + red[1]) + red[2]) + red[3];
+    double r = red[0];
+    for (int w = 1; w < nw; ++w) r += red[w];
     __syncthreads();
     return r;
 }
@@ -261,7 +314,7 @@ __device__ void stage_nodes(const LevelArgs &a, int x0, int y0, float tau,
     if (threadIdx.x == 0) { S.nx0 = nx0; S.ny0 = ny0; }
     const float *base = a.nodes + (long)NV_BASE * 6 * a.G0;
     const float *delta = a.nodes + (long)NV_DELTA * 6 * a.G0;
-    const float *dx = a.nodes + (long)NV_DX * 6 * a.G0;
+    const float *dx = a.nodes + (long)NV_X * 6 * a.G0;
     for (int t = threadIdx.x; t < 6 * cw * ch; t += blockDim.x) {
         const int q = t / (cw * ch), r = t % (cw * ch);
         const int j = r / cw, i = r % cw;
@@ -388,19 +441,66 @@ __device__ __forceinline__ void node_xy(int i, int j, int s, float &gx, float &g
 
 // ---- energy / linearisation kernel -----------------------------------------
 
-// blocks [0, n_pix): 16x16 pixel tiles; blocks [n_pix, grid): 256 nodes each
-// for the regulariser energies.  mode 0 = linearise (records + E at delta),
-// mode 1 = trial energy at delta + tau dx (skipped if an earlier trial of
-// this step was accepted).
-template <bool LIN>
-__global__ __launch_bounds__(SF_BLOCK) void k_energy(LevelArgs a, int trial,
-                                                     float tau, int n_before,
-                                                     int n_pix) {
+// Regulariser energies of node n at delta (+ tau dx): raw E_smooth, E_epi,
+// E_mag contributions (Eqs. (14), (15), (18)).
+__device__ void node_energy(const LevelArgs &a, int n, float tau, float (&part)[5]) {
     const LevelDims &d = a.d;
     const DevConst &C = *a.cst;
+    const int i = n % d.Gx, j = n / d.Gx;
+    const long G0 = a.G0;
+    const float *base = a.nodes + (long)NV_BASE * 6 * G0;
+    const float *delta = a.nodes + (long)NV_DELTA * 6 * G0;
+    const float *dx = a.nodes + (long)NV_X * 6 * G0;
+    float dl[6], tot[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        dl[q] = delta[q * G0 + n];
+        if (tau != 0.f) dl[q] = dl[q] + tau * dx[q * G0 + n];
+        tot[q] = base[q * G0 + n] + dl[q];
+    }
+    const float wi = a.wnode[n];
+    float es = 0.f;
+    const int nb[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int ii = i + nb[k][0], jj = j + nb[k][1];
+        if (ii < 0 || ii >= d.Gx || jj < 0 || jj >= d.Gy) continue;
+        const int m = jj * d.Gx + ii;
+        float acc = 0.f;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            float dm = delta[q * G0 + m];
+            if (tau != 0.f) dm = dm + tau * dx[q * G0 + m];
+            const float df = dl[q] - dm;
+            acc += C.wf[q] * df * df;
+        }
+        es += wi * acc;
+    }
+    float gx, gy;
+    node_xy(i, j, a.s, gx, gy);
+    float e[2], J[2][6];
+    epi_terms(C.F[a.level], gx, gy, tot, e, J);
+    float em = 0.f;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) em += C.mf[q] * dl[q] * dl[q];
+    part[2] = es;
+    part[3] = e[0] * e[0] + e[1] * e[1];
+    part[4] = em;
+}
+
+// blocks [0, n_pix): 16x16 pixel tiles; blocks [n_pix, grid): 256 nodes each
+// for the regulariser energies.
+//  LIN:  per-pixel records and energy partials at delta (summed later by
+//        the right-hand-side kernel).
+//  !LIN: trial energy at delta + tau dx, skipped if an earlier trial of this
+//        step was accepted; the last workgroup to finish sums the partials.
+template <bool LIN>
+__global__ __launch_bounds__(SF_BLOCK) void k_energy(LevelArgs a, int trial,
+                                                     float tau, int n_pix) {
+    const LevelDims &d = a.d;
     if (!LIN) {
         const double e0 = a.sc->e_lin[5];
-        for (int k = 0; k < n_before; ++k)
+        for (int k = 0; k < trial; ++k)
             if (a.sc->e_trial[k][5] <= e0) return;  // uniform over the grid
     }
     __shared__ NodeStage S;
@@ -431,155 +531,45 @@ __global__ __launch_bounds__(SF_BLOCK) void k_energy(LevelArgs a, int trial,
         }
     } else {
         const int n = (bid - n_pix) * SF_BLOCK + threadIdx.x;
-        if (n < d.G) {
-            const int i = n % d.Gx, j = n / d.Gx;
-            const float *base = a.nodes + (long)NV_BASE * 6 * a.G0;
-            const float *delta = a.nodes + (long)NV_DELTA * 6 * a.G0;
-            const float *dx = a.nodes + (long)NV_DX * 6 * a.G0;
-            const float tt = LIN ? 0.f : tau;
-            float dl[6], tot[6];
-#pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                dl[q] = delta[q * a.G0 + n];
-                if (tt != 0.f) dl[q] = dl[q] + tt * dx[q * a.G0 + n];
-                tot[q] = base[q * a.G0 + n] + dl[q];
-            }
-            const float wi = a.wnode[n];
-            float es = 0.f;
-            const int nb[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int ii = i + nb[k][0], jj = j + nb[k][1];
-                if (ii < 0 || ii >= d.Gx || jj < 0 || jj >= d.Gy) continue;
-                const int m = jj * d.Gx + ii;
-                float acc = 0.f;
-#pragma unroll
-                for (int q = 0; q < 6; ++q) {
-                    float dm = delta[q * a.G0 + m];
-                    if (tt != 0.f) dm = dm + tt * dx[q * a.G0 + m];
-                    const float df = dl[q] - dm;
-                    acc += C.wf[q] * df * df;
-                }
-                es += wi * acc;
-            }
-            float gx, gy;
-            node_xy(i, j, a.s, gx, gy);
-            float e[2], J[2][6];
-            epi_terms(C.F[a.level], gx, gy, tot, e, J);
-            float em = 0.f;
-#pragma unroll
-            for (int q = 0; q < 6; ++q) em += C.mf[q] * dl[q] * dl[q];
-            part[2] = es;
-            part[3] = e[0] * e[0] + e[1] * e[1];
-            part[4] = em;
-        }
+        if (n < d.G) node_energy(a, n, LIN ? 0.f : tau, part);
     }
     float tot5[5];
     block_sum<5>(part, tot5);
     const int nb = gridDim.x;
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < 5; ++k) a.partials[(long)k * a.max_blocks + bid] = tot5[k];
+        for (int k = 0; k < 5; ++k) a.partials[(long)(PS_E + k) * a.max_blocks + bid] = tot5[k];
     }
+    if (LIN) return;
     if (last_block(&a.sc->counter[0])) {
+        const DevConst &C = *a.cst;
         double s[5];
-        for (int k = 0; k < 5; ++k) s[k] = block_sum_partials(a.partials + (long)k * a.max_blocks, nb);
+        for (int k = 0; k < 5; ++k)
+            s[k] = block_sum_partials(a.partials + (long)(PS_E + k) * a.max_blocks, nb);
         if (threadIdx.x == 0) {
-            const double E = (double)C.w_photo * s[0] + (double)C.w_grad * s[1] +
-                             (double)C.w_reg * ((double)C.w_smooth * s[2] +
-                                                (double)C.w_epi * s[3] +
-                                                (double)C.w_mag * s[4]);
-            double *dst = LIN ? a.sc->e_lin : a.sc->e_trial[trial];
+            double *dst = a.sc->e_trial[trial];
             for (int k = 0; k < 5; ++k) dst[k] = s[k];
-            dst[5] = E;
+            dst[5] = (double)C.w_photo * s[0] + (double)C.w_grad * s[1] +
+                     (double)C.w_reg * ((double)C.w_smooth * s[2] + (double)C.w_epi * s[3] +
+                                        (double)C.w_mag * s[4]);
         }
     }
 }
 
-// ---- node-tile reduction ---------------------------------------------------
+// ---- node tiles ---------------------------------------------------------------
+//
+// A workgroup owns tx x ty warp nodes.  Its pixel region is every pixel whose
+// bilinear bracket (Eq. (7)) contains one of its nodes.  Per-pixel values are
+// staged in LDS; then the tpn threads of each node sum the node's support
+// rows (weights alpha, or alpha^2 for diagonal entries) and combine their
+// partial sums with fixed-order lane shuffles, so results are bitwise
+// reproducible.  Neighbouring tiles recompute the shared border pixels.
 
-// Accumulates K per-pixel values onto the nodes of a TX x TY tile through the
-// bilinear weights of Eq. (7): value k is weighted by alpha (or alpha^2 if
-// bit k of pow2 is set).  Pass 1 sums each pixel row onto node columns, pass
-// 2 sums rows onto node rows; both in a fixed order.  Result in
-// nodeAcc[(k * TY + tj) * TX + ti].
 struct TileGeom {
     int i0, j0, txa, tya;  // tile origin and clipped size
     int X0, X1, Y0, Y1;    // pixel region
+    int RX, RY;
 };
-
-template <int K, class Fn>
-__device__ void tile_reduce(const LevelArgs &a, const TileCfg &t,
-                            const TileGeom &g, unsigned pow2, float *lds,
-                            float *nodeAcc, Fn fn) {
-    const int s = a.s;
-    const LevelDims &d = a.d;
-    const int RX = g.X1 - g.X0 + 1, RY = g.Y1 - g.Y0 + 1;
-    const int RXs = (t.tx + 1) * s + 2, RYs = (t.ty + 1) * s + 2;
-    float *vals = lds;                                    // K x RB x RXs
-    float *accx = vals + K * t.rb * RXs;                  // K x TX x RYs
-    // brackets of region columns / rows
-    int *bxi = (int *)(accx + K * t.tx * RYs);            // RXs
-    float *bxw0 = (float *)(bxi + RXs);
-    float *bxw1 = bxw0 + RXs;
-    int *byi = (int *)(bxw1 + RXs);                       // RYs
-    float *byw0 = (float *)(byi + RYs);
-    float *byw1 = byw0 + RYs;
-    for (int u = threadIdx.x; u < RX; u += blockDim.x) {
-        const Bracket b = bracket(g.X0 + u, s, d.Gx);
-        bxi[u] = b.i0; bxw0[u] = b.w0; bxw1[u] = b.w1;
-    }
-    for (int u = threadIdx.x; u < RY; u += blockDim.x) {
-        const Bracket b = bracket(g.Y0 + u, s, d.Gy);
-        byi[u] = b.i0; byw0[u] = b.w0; byw1[u] = b.w1;
-    }
-    __syncthreads();
-    for (int yb = g.Y0; yb <= g.Y1; yb += t.rb) {
-        const int nr = min(t.rb, g.Y1 - yb + 1);
-        for (int u = threadIdx.x; u < nr * RX; u += blockDim.x) {
-            const int ry = u / RX, rx = u % RX;
-            float v[K];
-            fn(g.X0 + rx, yb + ry, rx, yb + ry - g.Y0, v);
-#pragma unroll
-            for (int k = 0; k < K; ++k) vals[(k * t.rb + ry) * RXs + rx] = v[k];
-        }
-        __syncthreads();
-        for (int u = threadIdx.x; u < K * g.txa * nr; u += blockDim.x) {
-            const int k = u / (g.txa * nr), rem = u % (g.txa * nr);
-            const int ti = rem / nr, ry = rem % nr;
-            const int i = g.i0 + ti;
-            const int xa = max(sup_lo(i, s), g.X0) - g.X0;
-            const int xb = min(sup_hi(i, s, d.Gx, d.W), g.X1) - g.X0;
-            const bool sq = (pow2 >> k) & 1u;
-            float acc = 0.f;
-            for (int rx = xa; rx <= xb; ++rx) {
-                float w = (bxi[rx] == i ? bxw0[rx] : 0.f) + (bxi[rx] + 1 == i ? bxw1[rx] : 0.f);
-                if (d.Gx == 1) w = bxw0[rx];
-                if (sq) w = w * w;
-                acc += w * vals[(k * t.rb + ry) * RXs + rx];
-            }
-            accx[(k * t.tx + ti) * RYs + (yb - g.Y0 + ry)] = acc;
-        }
-        __syncthreads();
-    }
-    for (int u = threadIdx.x; u < K * g.txa * g.tya; u += blockDim.x) {
-        const int k = u / (g.txa * g.tya), rem = u % (g.txa * g.tya);
-        const int tj = rem / g.txa, ti = rem % g.txa;
-        const int j = g.j0 + tj;
-        const int ya = max(sup_lo(j, s), g.Y0) - g.Y0;
-        const int yb = min(sup_hi(j, s, d.Gy, d.H), g.Y1) - g.Y0;
-        const bool sq = (pow2 >> k) & 1u;
-        float acc = 0.f;
-        for (int ry = ya; ry <= yb; ++ry) {
-            float w = (byi[ry] == j ? byw0[ry] : 0.f) + (byi[ry] + 1 == j ? byw1[ry] : 0.f);
-            if (d.Gy == 1) w = byw0[ry];
-            if (sq) w = w * w;
-            acc += w * accx[(k * t.tx + ti) * RYs + ry];
-        }
-        nodeAcc[(k * t.ty + tj) * t.tx + ti] = acc;
-    }
-    __syncthreads();
-}
 
 __device__ __forceinline__ TileGeom tile_geom(const LevelArgs &a, const TileCfg &t) {
     TileGeom g;
@@ -592,316 +582,617 @@ __device__ __forceinline__ TileGeom tile_geom(const LevelArgs &a, const TileCfg 
     g.X1 = sup_hi(g.i0 + g.txa - 1, a.s, d.Gx, d.W);
     g.Y0 = sup_lo(g.j0, a.s);
     g.Y1 = sup_hi(g.j0 + g.tya - 1, a.s, d.Gy, d.H);
+    g.RX = g.X1 - g.X0 + 1;
+    g.RY = g.Y1 - g.Y0 + 1;
     return g;
 }
 
-// Shared-memory layout sizes (floats) of a node-tile kernel.
+// LDS carve-up of a node-tile kernel
+struct TileLds {
+    int *bxi, *byi;
+    float *bxw0, *bxw1, *byw0, *byw1;
+    float *vals;   // K x RY x RX
+    float *halo;   // 6 x (ty + 2) x (tx + 2)
+    float *ownd;   // 2 x tx x ty scratch per owned node
+};
+
+__host__ __device__ inline int tile_rxs(const TileCfg &t, int s) { return (t.tx + 1) * s + 2; }
+__host__ __device__ inline int tile_rys(const TileCfg &t, int s) { return (t.ty + 1) * s + 2; }
 __host__ __device__ inline size_t tile_lds_floats(const TileCfg &t, int s, int K) {
-    const size_t RXs = (size_t)(t.tx + 1) * s + 2, RYs = (size_t)(t.ty + 1) * s + 2;
-    return (size_t)K * t.rb * RXs + (size_t)K * t.tx * RYs + 3 * RXs + 3 * RYs +
-           (size_t)K * t.tx * t.ty;
+    const size_t RXs = tile_rxs(t, s), RYs = tile_rys(t, s);
+    return 3 * RXs + 3 * RYs + (size_t)K * RXs * RYs + (size_t)6 * (t.tx + 2) * (t.ty + 2) +
+           (size_t)2 * t.tx * t.ty;
 }
 
-// Regulariser gradient / diagonal / product on one node.
+__device__ TileLds tile_lds(float *lds, const TileCfg &t, int s, int K) {
+    const int RXs = tile_rxs(t, s), RYs = tile_rys(t, s);
+    TileLds L;
+    L.bxi = (int *)lds;
+    L.bxw0 = (float *)(L.bxi + RXs);
+    L.bxw1 = L.bxw0 + RXs;
+    L.byi = (int *)(L.bxw1 + RXs);
+    L.byw0 = (float *)(L.byi + RYs);
+    L.byw1 = L.byw0 + RYs;
+    L.vals = L.byw1 + RYs;
+    L.halo = L.vals + (size_t)K * RXs * RYs;
+    L.ownd = L.halo + (size_t)6 * (t.tx + 2) * (t.ty + 2);
+    return L;
+}
+
+__device__ void tile_brackets(const LevelArgs &a, const TileGeom &g, const TileLds &L) {
+    for (int u = threadIdx.x; u < g.RX; u += blockDim.x) {
+        const Bracket b = bracket(g.X0 + u, a.s, a.d.Gx);
+        L.bxi[u] = b.i0; L.bxw0[u] = b.w0; L.bxw1[u] = b.w1;
+    }
+    for (int u = threadIdx.x; u < g.RY; u += blockDim.x) {
+        const Bracket b = bracket(g.Y0 + u, a.s, a.d.Gy);
+        L.byi[u] = b.i0; L.byw0[u] = b.w0; L.byw1[u] = b.w1;
+    }
+}
+
+template <int K, class Fn>
+__device__ __forceinline__ void pixels_to_lds(const TileGeom &g, const TileLds &L, Fn fn) {
+    const int n = g.RX * g.RY;
+    for (int u = threadIdx.x; u < n; u += blockDim.x) {
+        const int rx = u % g.RX, ry = u / g.RX;
+        float v[K];
+        fn(g.X0 + rx, g.Y0 + ry, rx, ry, v);
+#pragma unroll
+        for (int k = 0; k < K; ++k) L.vals[(k * g.RY + ry) * g.RX + rx] = v[k];
+    }
+}
+
+// weight of node i for region column / row u
+__device__ __forceinline__ float bweight(const int *bi, const float *w0, const float *w1,
+                                         int u, int i, int G) {
+    if (G == 1) return w0[u];
+    return (bi[u] == i ? w0[u] : 0.f) + (bi[u] + 1 == i ? w1[u] : 0.f);
+}
+
+// Sum over the support of this thread's node (valid in the thread with
+// sub == 0 of each node group).  A node's support is at most 2S pixels wide
+// and high, and tpn >= 2S, so every thread sums at most one support row,
+// with the columns unrolled; the tpn row sums are combined with fixed-order
+// lane shuffles.
+template <int K, int S>
+__device__ __forceinline__ void lds_to_nodes(const LevelArgs &a, const TileCfg &t,
+                                             const TileGeom &g, const TileLds &L,
+                                             unsigned pow2, float (&acc)[K]) {
+    const int nl = threadIdx.x / t.tpn, sub = threadIdx.x % t.tpn;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.f;
+    if (nl < g.txa * g.tya) {
+        const int i = g.i0 + nl % g.txa, j = g.j0 + nl / g.txa;
+        const int xa = max(sup_lo(i, S), g.X0) - g.X0;
+        const int xb = min(sup_hi(i, S, a.d.Gx, a.d.W), g.X1) - g.X0;
+        const int ya = max(sup_lo(j, S), g.Y0) - g.Y0;
+        const int yb = min(sup_hi(j, S, a.d.Gy, a.d.H), g.Y1) - g.Y0;
+        const int ry = ya + sub;
+        if (ry <= yb) {
+            const float wy = bweight(L.byi, L.byw0, L.byw1, ry, j, a.d.Gy);
+            const float *row = L.vals + ry * g.RX;
+#pragma unroll
+            for (int c = 0; c < 2 * S; ++c) {
+                const int rx = xa + c;
+                if (rx <= xb) {
+                    const float w1 = bweight(L.bxi, L.bxw0, L.bxw1, rx, i, a.d.Gx) * wy;
+                    const float w2 = w1 * w1;
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        acc[k] += (((pow2 >> k) & 1u) ? w2 : w1) * row[k * g.RY * g.RX + rx];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = group_sum<float>(acc[k], t.tpn);
+}
+
+// Regulariser pieces of node (i, j).  The Gauss-Newton matrix of these
+// least-squares terms is 2 J^T J:
 //   smooth (Eq. (14), ordered 4-neighbour pairs on the deltas):
 //     grad += 2 w_reg w_smooth w_f sum_j (w_i + w_j)(D_i - D_j)
 //   epipolar (Eqs. (15)-(17), on totals): grad += 2 w_reg w_epi sum_t e_t de_t
 //   magnitude (Eq. (18), on deltas): grad += 2 w_reg w_mag m_f D_i
-// The Gauss-Newton matrix of these least-squares terms is 2 J^T J.
+// The right-hand-side kernel stores, per node, a record of the pieces the
+// H-products need: the four smoothness coefficients
+// 2 w_reg w_smooth (w_i + w_j) (0 without a neighbour) and the two epipolar
+// gradients scaled by sqrt(2 w_reg w_epi), so that
+//   (H_reg u)_i = sum_j c_j w_f (u_i - u_j) + sum_t J_t (J_t . u_i)
+//                 + 2 w_reg w_mag m_f u_i.
+#define REG_PLANES 16
 
-// ---- right-hand side and PCG start (node tiles) ----------------------------
+__device__ __forceinline__ void nb_offset(int k, int &di, int &dj) {
+    di = k == 0 ? 1 : (k == 1 ? -1 : 0);
+    dj = k == 2 ? 1 : (k == 3 ? -1 : 0);
+}
 
-__global__ __launch_bounds__(SF_BLOCK) void k_node_rhs(LevelArgs a, TileCfg t) {
+// ---- right-hand side and diag(H) (node tiles) ----------------------------
+
+template <int S>
+__global__ __launch_bounds__(NT_TILE) void k_rhs(LevelArgs a, TileCfg t, int n_lin_blocks) {
     extern __shared__ float lds[];
     const LevelDims &d = a.d;
     const DevConst &C = *a.cst;
     const TileGeom g = tile_geom(a, t);
-    float *nodeAcc = lds + (tile_lds_floats(t, a.s, 12) - (size_t)12 * t.tx * t.ty);
-    const float *rec = a.rec;
-    const long N0 = a.N0;
-    tile_reduce<12>(a, t, g, 0xFC0u, lds, nodeAcc,
-                    [&](int x, int y, int, int, float (&v)[12]) {
-                        const long pix = (long)y * d.W + x;
-#pragma unroll
-                        for (int q = 0; q < 6; ++q) v[q] = rec[q * N0 + pix];
-#pragma unroll
-                        for (int q = 0; q < 6; ++q) {
-                            const int tq = q * 6 - (q * (q - 1)) / 2;  // tri(q, q)
-                            v[6 + q] = rec[(6 + tq) * N0 + pix];
-                        }
-                    });
-    float prt[2] = {0.f, 0.f};
-    const int nt = g.txa * g.tya;
-    if ((int)threadIdx.x < nt) {
-        const int ti = threadIdx.x % g.txa, tj = threadIdx.x / g.txa;
-        const int i = g.i0 + ti, j = g.j0 + tj;
-        const long n = (long)j * d.Gx + i;
-        const long G0 = a.G0;
-        float *base = a.nodes + (long)NV_BASE * 6 * G0;
-        float *delta = a.nodes + (long)NV_DELTA * 6 * G0;
-        float grad[6], dg[6], dl[6], tot[6];
+    const TileLds L = tile_lds(lds, t, S, 12);
+    const int tid = threadIdx.x;
+    const int nl = tid / t.tpn, sub = tid % t.tpn;
+    const bool mine = sub == 0 && nl < g.txa * g.tya;
+    const int i = g.i0 + (nl % max(g.txa, 1)), j = g.j0 + nl / max(g.txa, 1);
+    const long G0 = a.G0, n = (long)j * d.Gx + i;
+    const float *base = a.nodes + (long)NV_BASE * 6 * G0;
+    const float *delta = a.nodes + (long)NV_DELTA * 6 * G0;
+    // own node: totals, deltas, neighbour deltas and weights
+    float dl[6], tot[6], dn[4][6], wn[4], wi = 0.f;
+    int has[4];
+    if (mine) {
+        wi = a.wnode[n];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            grad[q] = nodeAcc[(q * t.ty + tj) * t.tx + ti];
-            dg[q] = nodeAcc[((6 + q) * t.ty + tj) * t.tx + ti];
             dl[q] = delta[q * G0 + n];
             tot[q] = base[q * G0 + n] + dl[q];
         }
-        const float wi = a.wnode[n];
-        const float cs = 2.f * C.w_reg * C.w_smooth;
-        const int nb[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int ii = i + nb[k][0], jj = j + nb[k][1];
-            if (ii < 0 || ii >= d.Gx || jj < 0 || jj >= d.Gy) continue;
-            const long m = (long)jj * d.Gx + ii;
-            const float wsum = wi + a.wnode[m];
+            int di, dj;
+            nb_offset(k, di, dj);
+            has[k] = i + di >= 0 && i + di < d.Gx && j + dj >= 0 && j + dj < d.Gy;
+            const long m = has[k] ? (long)(j + dj) * d.Gx + i + di : n;
+            wn[k] = has[k] ? a.wnode[m] : 0.f;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) dn[k][q] = delta[q * G0 + m];
+        }
+    }
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+        // energy at the linearisation point (partials of the linearise
+        // kernel) and the PCG start state
+        double es[5];
+        for (int k = 0; k < 5; ++k)
+            es[k] = block_sum_partials(a.partials + (long)(PS_E + k) * a.max_blocks, n_lin_blocks);
+        if (tid == 0) {
+            for (int k = 0; k < 5; ++k) a.sc->e_lin[k] = es[k];
+            a.sc->e_lin[5] = (double)C.w_photo * es[0] + (double)C.w_grad * es[1] +
+                             (double)C.w_reg * ((double)C.w_smooth * es[2] + (double)C.w_epi * es[3] +
+                                                (double)C.w_mag * es[4]);
+            PcgHist h0;
+            h0.gamma = 0.0; h0.alpha = 0.f; h0.beta = 0.f; h0.active = 1; h0.pad = 0;
+            a.sc->hist[0] = h0;
+        }
+    }
+    tile_brackets(a, g, L);
+    const float *rec = a.rec;
+    const long N0 = a.N0;
+    pixels_to_lds<12>(g, L, [&](int x, int y, int, int, float (&v)[12]) {
+        const long pix = (long)y * d.W + x;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v[q] = rec[q * N0 + pix];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v[6 + q] = rec[(6 + tri(q, q)) * N0 + pix];
+    });
+    __syncthreads();
+    float acc[12];
+    lds_to_nodes<12, S>(a, t, g, L, 0xFC0u, acc);
+    if (mine) {
+        float grad[6], dg[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) { grad[q] = acc[q]; dg[q] = acc[6 + q]; }
+        const float cs = 2.f * C.w_reg * C.w_smooth;
+        float cnb[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            cnb[k] = has[k] ? cs * (wi + wn[k]) : 0.f;
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
-                grad[q] += cs * C.wf[q] * wsum * (dl[q] - delta[q * G0 + m]);
-                dg[q] += cs * C.wf[q] * wsum;
+                grad[q] += cnb[k] * C.wf[q] * (dl[q] - dn[k][q]);
+                dg[q] += cnb[k] * C.wf[q];
             }
         }
         float gx, gy;
-        node_xy(i, j, a.s, gx, gy);
+        node_xy(i, j, S, gx, gy);
         float e[2], J[2][6];
         epi_terms(C.F[a.level], gx, gy, tot, e, J);
         const float ce = 2.f * C.w_reg * C.w_epi, cm = 2.f * C.w_reg * C.w_mag;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            grad[q] += ce * (e[0] * J[0][q] + e[1] * J[1][q]);
-            dg[q] += ce * (J[0][q] * J[0][q] + J[1][q] * J[1][q]);
-            grad[q] += cm * C.mf[q] * dl[q];
-            dg[q] += cm * C.mf[q];
-        }
-        float *X = a.nodes + (long)NV_DX * 6 * G0;
-        float *R = a.nodes + (long)NV_R * 6 * G0;
-        float *Z = a.nodes + (long)NV_Z * 6 * G0;
+        const float se = sqrtf(ce);
+        float *X = a.nodes + (long)NV_X * 6 * G0;
+        float *R = a.nodes + (long)NV_R0 * 6 * G0;
+        float *U = a.nodes + (long)NV_U * 6 * G0;
         float *D = a.nodes + (long)NV_DIAG * 6 * G0;
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
+            grad[q] += ce * (e[0] * J[0][q] + e[1] * J[1][q]) + cm * C.mf[q] * dl[q];
+            dg[q] += ce * (J[0][q] * J[0][q] + J[1][q] * J[1][q]) + cm * C.mf[q];
             const float r = -grad[q];
-            const float z = r / dg[q];
             X[q * G0 + n] = 0.f;
             R[q * G0 + n] = r;
-            Z[q * G0 + n] = z;
+            U[q * G0 + n] = r / dg[q];
             D[q * G0 + n] = dg[q];
-            prt[0] += r * z;
-            prt[1] += r * r;
         }
-    }
-    float tot2[2];
-    block_sum<2>(prt, tot2);
-    const int bid = block_linear();
-    const int nb = gridDim.x * gridDim.y;
-    if (threadIdx.x == 0) {
-        a.partials[bid] = tot2[0];
-        a.partials[(long)a.max_blocks + bid] = tot2[1];
-    }
-    if (last_block(&a.sc->counter[1])) {
-        const double rz = block_sum_partials(a.partials, nb);
-        const double rr = block_sum_partials(a.partials + a.max_blocks, nb);
-        if (threadIdx.x == 0) {
-            a.sc->rz = rz;
-            a.sc->rr = rr;
-            a.sc->active = rz > 1e-30 ? 1 : 0;
-            a.sc->first = 1;
-            a.sc->beta = 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a.reg[k * G0 + n] = cnb[k];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            a.reg[(4 + q) * G0 + n] = se * J[0][q];
+            a.reg[(10 + q) * G0 + n] = se * J[1][q];
         }
     }
 }
 
-// ---- q = H p (node tiles) --------------------------------------------------
+// ---- preconditioned CG in single-reduction form --------------------------
+//
+// Iteration k (x_0 = 0, r_0 = b, u_0 = M^-1 r_0, w_0 = H u_0, M = diag H):
+//   p_k = u_k + beta_k p_{k-1},  s_k = w_k + beta_k s_{k-1}   (s_k = H p_k)
+//   x_{k+1} = x_k + alpha_k p_k,  r_{k+1} = r_k - alpha_k s_k
+//   u_{k+1} = M^-1 r_{k+1},  w_{k+1} = H u_{k+1}
+//   gamma_k = r_k.u_k, delta_k = w_k.u_k (one fused reduction),
+//   beta_k = gamma_k / gamma_{k-1},
+//   alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1})
+// which are the iterates of textbook PCG in exact arithmetic, with one
+// H-product and one global reduction per iteration.  Kernel i (1 <= i < n)
+// forms the scalars of iteration i-1 from kernel i-1's partial sums (every
+// workgroup sums them in the same order), applies iteration i-1 and computes
+// w_i; the first kernel computes w_0, the last one applies iteration n-1.
+// Breakdown: once gamma <= 1e-30 or the curvature p.Hp <= 0 the remaining
+// iterations change nothing.
 
-__global__ __launch_bounds__(SF_BLOCK) void k_apply(LevelArgs a, TileCfg t,
-                                                    int iter) {
-    extern __shared__ float lds[];
-    DevScalars *sc = a.sc;
-    if (!sc->active) return;  // uniform over the grid
-    const LevelDims &d = a.d;
-    const DevConst &C = *a.cst;
-    const TileGeom g = tile_geom(a, t);
-    const long G0 = a.G0;
-    const int first = sc->first;
-    const float beta = sc->beta;
-    const size_t base_f = tile_lds_floats(t, a.s, 6);
-    float *nodeAcc = lds + (base_f - (size_t)6 * t.tx * t.ty);
-    float *pS = lds + base_f;  // 6 x (TY+2) x (TX+2), halo of one node
-    const int HX = t.tx + 2, HY = t.ty + 2;
-    const float *Z = a.nodes + (long)NV_Z * 6 * G0;
-    float *Pc = a.nodes + (long)((iter & 1) ? NV_P1 : NV_P0) * 6 * G0;
-    const float *Po = a.nodes + (long)((iter & 1) ? NV_P0 : NV_P1) * 6 * G0;
-    // p = z + beta p_old on the tile and its halo; owned nodes stored
-    const int hx0 = max(g.i0 - 1, 0), hx1 = min(g.i0 + g.txa, d.Gx - 1);
-    const int hy0 = max(g.j0 - 1, 0), hy1 = min(g.j0 + g.tya, d.Gy - 1);
-    const int hw = hx1 - hx0 + 1, hh = hy1 - hy0 + 1;
-    for (int u = threadIdx.x; u < hw * hh; u += blockDim.x) {
-        const int ni = hx0 + u % hw, nj = hy0 + u / hw;
-        const long n = (long)nj * d.Gx + ni;
-        const bool own = ni >= g.i0 && ni < g.i0 + g.txa && nj >= g.j0 && nj < g.j0 + g.tya;
+
+// Per-thread strided sums of the previous iteration's three partial planes.
+__device__ __forceinline__ void load_pcg_partials(const LevelArgs &a, int i, int nb_prev,
+                                                  double (&acc)[3]) {
+    const float *prev = a.partials + (long)(((i - 1) & 1) ? PS_PCG1 : PS_PCG0) * a.max_blocks;
+    acc[0] = acc[1] = acc[2] = 0.0;
+    for (int b = threadIdx.x; b < nb_prev; b += blockDim.x) {
+        acc[0] += (double)prev[b];
+        acc[1] += (double)prev[a.max_blocks + b];
+        acc[2] += (double)prev[2 * a.max_blocks + b];
+    }
+}
+
+// Block-wide fixed-order sum of the per-thread partial sums, then the
+// scalars of iteration i-1 (thread 0 decides, everyone receives).
+__device__ void pcg_decide(const LevelArgs &a, int i, const double (&acc)[3],
+                           const PcgHist &h, int log_index, int force, float &alpha,
+                           float &beta, int &act) {
+    __shared__ double red[16][3];
+    __shared__ float s_alpha, s_beta;
+    __shared__ int s_act;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            float p = Z[q * G0 + n];
-            if (!first) p = p + beta * Po[q * G0 + n];
-            pS[(q * HY + (nj - g.j0 + 1)) * HX + (ni - g.i0 + 1)] = p;
-            if (own) Pc[q * G0 + n] = p;
+    for (int k = 0; k < 3; ++k) {
+        const double v = wave_sum_d(acc[k]);
+        if (lane == 0) red[wv][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double gam = 0.0, del = 0.0, rr = 0.0;
+        for (int w = 0; w < nw; ++w) { gam += red[w][0]; del += red[w][1]; rr += red[w][2]; }
+        double b = 0.0, pq = del;
+        int ok = h.active;
+        if (ok && i - 1 > 0) {
+            b = gam / h.gamma;
+            pq = del - b * gam / (double)h.alpha;
+        }
+        ok = ok && gam > 1e-30 && pq > 0.0 && isfinite(pq);
+        float al = ok ? (float)(gam / pq) : 0.f;
+        float be = ok ? (float)b : 0.f;
+        if (force) { ok = 1; al = 1e-3f; be = 0.5f; }
+        s_alpha = al;
+        s_beta = be;
+        s_act = ok;
+        if (blockIdx.x == 0 && blockIdx.y == 0) {
+            PcgHist o;
+            o.gamma = gam; o.alpha = al; o.beta = be; o.active = ok; o.pad = 0;
+            a.sc->hist[i] = o;
+            if (log_index >= 0 && i >= 2) a.log[log_index].pcg_res[i - 2] = (float)sqrt(rr);
         }
     }
     __syncthreads();
-    const float *rec = a.rec + 6 * (long)a.N0;
-    const long N0 = a.N0;
-    const int s = a.s;
-    tile_reduce<6>(a, t, g, 0u, lds, nodeAcc,
-                   [&](int x, int y, int, int, float (&v)[6]) {
-                       const Bracket bx = bracket(x, s, d.Gx), by = bracket(y, s, d.Gy);
-                       const int lx0 = bx.i0 - g.i0 + 1, lx1 = bx.i1 - g.i0 + 1;
-                       const int ly0 = by.i0 - g.j0 + 1, ly1 = by.i1 - g.j0 + 1;
-                       float pv[6];
-#pragma unroll
-                       for (int q = 0; q < 6; ++q) {
-                           const float *P = pS + q * HY * HX;
-                           pv[q] = by.w0 * (bx.w0 * P[ly0 * HX + lx0] + bx.w1 * P[ly0 * HX + lx1]) +
-                                   by.w1 * (bx.w0 * P[ly1 * HX + lx0] + bx.w1 * P[ly1 * HX + lx1]);
-                       }
-                       const long pix = (long)y * d.W + x;
-                       float G[21];
-#pragma unroll
-                       for (int k = 0; k < 21; ++k) G[k] = rec[k * N0 + pix];
-#pragma unroll
-                       for (int i = 0; i < 6; ++i) {
-                           float acc = 0.f;
-#pragma unroll
-                           for (int j = 0; j < 6; ++j)
-                               acc += G[i <= j ? tri(i, j) : tri(j, i)] * pv[j];
-                           v[i] = acc;
-                       }
-                   });
-    float prt[2] = {0.f, 0.f};
-    const int nt = g.txa * g.tya;
-    if ((int)threadIdx.x < nt) {
-        const int ti = threadIdx.x % g.txa, tj = threadIdx.x / g.txa;
-        const int i = g.i0 + ti, j = g.j0 + tj;
-        const long n = (long)j * d.Gx + i;
-        const float *base = a.nodes + (long)NV_BASE * 6 * G0;
-        const float *delta = a.nodes + (long)NV_DELTA * 6 * G0;
-        float p[6], q6[6], tot[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            p[q] = pS[(q * HY + tj + 1) * HX + ti + 1];
-            q6[q] = nodeAcc[(q * t.ty + tj) * t.tx + ti];
-            tot[q] = base[q * G0 + n] + delta[q * G0 + n];
-        }
-        const float wi = a.wnode[n];
-        const float cs = 2.f * C.w_reg * C.w_smooth;
-        const int nb[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int ii = i + nb[k][0], jj = j + nb[k][1];
-            if (ii < 0 || ii >= d.Gx || jj < 0 || jj >= d.Gy) continue;
-            const float wsum = wi + a.wnode[(long)jj * d.Gx + ii];
-#pragma unroll
-            for (int q = 0; q < 6; ++q)
-                q6[q] += cs * C.wf[q] * wsum * (p[q] - pS[(q * HY + tj + 1 + nb[k][1]) * HX + ti + 1 + nb[k][0]]);
-        }
-        float gx, gy;
-        node_xy(i, j, a.s, gx, gy);
-        float e[2], J[2][6];
-        epi_terms(C.F[a.level], gx, gy, tot, e, J);
-        float jp0 = 0.f, jp1 = 0.f;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) { jp0 += J[0][q] * p[q]; jp1 += J[1][q] * p[q]; }
-        const float ce = 2.f * C.w_reg * C.w_epi, cm = 2.f * C.w_reg * C.w_mag;
-        float *Q = a.nodes + (long)NV_Q * 6 * G0;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            q6[q] += ce * (J[0][q] * jp0 + J[1][q] * jp1) + cm * C.mf[q] * p[q];
-            Q[q * G0 + n] = q6[q];
-            prt[0] += p[q] * q6[q];
-            prt[1] += p[q] * p[q];
-        }
-    }
-    float tot2[2];
-    block_sum<2>(prt, tot2);
-    const int bid = block_linear();
-    const int nb = gridDim.x * gridDim.y;
-    if (threadIdx.x == 0) {
-        a.partials[bid] = tot2[0];
-        a.partials[(long)a.max_blocks + bid] = tot2[1];
-    }
-    if (last_block(&sc->counter[1])) {
-        const double pq = block_sum_partials(a.partials, nb);
-        const double pp = block_sum_partials(a.partials + a.max_blocks, nb);
-        if (threadIdx.x == 0) {
-            sc->pq = pq;
-            sc->pp = pp;
-            const int act = pq > 1e-30 * pp ? 1 : 0;
-            sc->active = act;
-            sc->alpha = act ? (float)(sc->rz / pq) : 0.f;
-        }
+    alpha = s_alpha;
+    beta = s_beta;
+    act = s_act;
+}
+
+// Copies this workgroup's partials to the next slot (inactive iteration:
+// r and u are unchanged).
+__device__ void carry_partials(const LevelArgs &a, int i) {
+    if (threadIdx.x < 3) {
+        const int bid = block_linear();
+        const long src = (long)(((i - 1) & 1) ? PS_PCG1 : PS_PCG0) * a.max_blocks;
+        const long dst = (long)((i & 1) ? PS_PCG1 : PS_PCG0) * a.max_blocks;
+        a.partials[dst + (long)threadIdx.x * a.max_blocks + bid] =
+            a.partials[src + (long)threadIdx.x * a.max_blocks + bid];
     }
 }
 
-// ---- x += alpha p, r -= alpha q, z = r / diag ------------------------------
-
-__global__ __launch_bounds__(SF_BLOCK) void k_update(LevelArgs a, int iter,
-                                                     int log_index) {
-    DevScalars *sc = a.sc;
-    if (!sc->active) {
-        if (blockIdx.x == 0 && threadIdx.x == 0 && log_index >= 0)
-            a.log[log_index].pcg_res[iter] = (float)sqrt(sc->rr);
-        return;
-    }
+// Every load of an iteration that does not depend on its scalars is issued
+// before the partial sums are reduced, and constants are read once, so the
+// workgroup waits for memory about once.
+template <bool FIRST, int S>
+__global__ __launch_bounds__(NT_TILE) void k_pcg(LevelArgs a, TileCfg t, int i,
+                                                 int log_index, int force, int nb_prev) {
+    extern __shared__ float lds[];
+    const LevelDims &d = a.d;
     const long G0 = a.G0;
-    const float alpha = sc->alpha;
-    float *X = a.nodes + (long)NV_DX * 6 * G0;
-    float *R = a.nodes + (long)NV_R * 6 * G0;
-    float *Z = a.nodes + (long)NV_Z * 6 * G0;
-    const float *Pc = a.nodes + (long)((iter & 1) ? NV_P1 : NV_P0) * 6 * G0;
-    const float *Q = a.nodes + (long)NV_Q * 6 * G0;
+    const TileGeom g = tile_geom(a, t);
+    const TileLds L = tile_lds(lds, t, S, 6);
+    const int tid = threadIdx.x;
+    const float *Rp = a.nodes + (long)(((i - 1) & 1) ? NV_R1 : NV_R0) * 6 * G0;
+    float *Rc = a.nodes + (long)((i & 1) ? NV_R1 : NV_R0) * 6 * G0;
+    const float *Wp = a.nodes + (long)(((i - 1) & 1) ? NV_W1 : NV_W0) * 6 * G0;
+    float *Wc = a.nodes + (long)((i & 1) ? NV_W1 : NV_W0) * 6 * G0;
+    const float *Sp = a.nodes + (long)(((i - 2) & 1) ? NV_S1 : NV_S0) * 6 * G0;
+    float *Sc = a.nodes + (long)(((i - 1) & 1) ? NV_S1 : NV_S0) * 6 * G0;
+    float *U = a.nodes + (long)NV_U * 6 * G0;
+    float *P = a.nodes + (long)NV_P * 6 * G0;
+    float *X = a.nodes + (long)NV_X * 6 * G0;
     const float *D = a.nodes + (long)NV_DIAG * 6 * G0;
-    float prt[2] = {0.f, 0.f};
-    const long n = (long)blockIdx.x * SF_BLOCK + threadIdx.x;
-    if (n < a.d.G) {
+    const float *R0 = a.nodes + (long)NV_R0 * 6 * G0;
+
+    // ---- phase 0: loads --------------------------------------------------
+    float wf[6], cm[6];
+    {
+        const DevConst *C = a.cst;
+        const float c = 2.f * C->w_reg * C->w_mag;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            const long k = q * G0 + n;
-            X[k] = X[k] + alpha * Pc[k];
-            const float r = R[k] - alpha * Q[k];
-            const float z = r / D[k];
-            R[k] = r;
-            Z[k] = z;
-            prt[0] += r * z;
-            prt[1] += r * r;
+        for (int q = 0; q < 6; ++q) { wf[q] = C->wf[q]; cm[q] = c * C->mf[q]; }
+    }
+    double pacc[3] = {0.0, 0.0, 0.0};
+    PcgHist h;
+    h.gamma = 0.0; h.alpha = 0.f; h.beta = 0.f; h.active = 1; h.pad = 0;
+    if (!FIRST) {
+        load_pcg_partials(a, i, nb_prev, pacc);
+        if (tid == 0) h = a.sc->hist[i - 1];
+    }
+    // Gram blocks of this thread's region pixels
+    const float *gram = a.rec + 6 * (long)a.N0;
+    const long N0 = a.N0;
+    const int npx = g.RX * g.RY;
+    float Gm[PPT][21];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int u = tid + k * NT_TILE;
+        if (u < npx) {
+            const long pix = (long)(g.Y0 + u / g.RX) * d.W + g.X0 + u % g.RX;
+#pragma unroll
+            for (int e = 0; e < 21; ++e) Gm[k][e] = gram[e * N0 + pix];
         }
     }
-    float tot2[2];
-    block_sum<2>(prt, tot2);
-    if (threadIdx.x == 0) {
-        a.partials[blockIdx.x] = tot2[0];
-        a.partials[(long)a.max_blocks + blockIdx.x] = tot2[1];
-    }
-    if (last_block(&sc->counter[1])) {
-        const double rz = block_sum_partials(a.partials, gridDim.x);
-        const double rr = block_sum_partials(a.partials + a.max_blocks, gridDim.x);
-        if (threadIdx.x == 0) {
-            sc->rr = rr;
-            if (log_index >= 0) a.log[log_index].pcg_res[iter] = (float)sqrt(rr);
-            if (rz > 1e-30) {
-                sc->beta = (float)(rz / sc->rz);
-                sc->rz = rz;
-                sc->first = 0;
+    // halo node of this thread: the vectors u_i is formed from
+    const int HX = t.tx + 2, HY = t.ty + 2;
+    const int hx0 = max(g.i0 - 1, 0), hx1 = min(g.i0 + g.txa, d.Gx - 1);
+    const int hy0 = max(g.j0 - 1, 0), hy1 = min(g.j0 + g.tya, d.Gy - 1);
+    const int hw = hx1 - hx0 + 1, hh = hy1 - hy0 + 1;
+    const bool hal = tid < hw * hh;
+    const int hni = hx0 + tid % max(hw, 1), hnj = hy0 + tid / max(hw, 1);
+    const long hn = (long)hnj * d.Gx + hni;
+    const bool hown = hal && hni >= g.i0 && hni < g.i0 + g.txa && hnj >= g.j0 && hnj < g.j0 + g.tya;
+    float hv0[6], hv1[6], hv2[6], hv3[6];
+    if (hal) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const long k = q * G0 + hn;
+            if (FIRST) {
+                hv0[q] = U[k];
+                hv1[q] = R0[k];
             } else {
-                sc->active = 0;
+                hv0[q] = Rp[k];
+                hv1[q] = Wp[k];
+                hv2[q] = i > 1 ? Sp[k] : 0.f;
+                hv3[q] = D[k];
             }
         }
     }
+    // owned node of this thread's node group: its regulariser record
+    const int nl = tid / t.tpn, sub = tid % t.tpn;
+    const bool mine = sub == 0 && nl < g.txa * g.tya;
+    const int ti = nl % max(g.txa, 1), tj = nl / max(g.txa, 1);
+    const int i_n = g.i0 + ti, j_n = g.j0 + tj;
+    const long n_own = (long)j_n * d.Gx + i_n;
+    float rg[REG_PLANES];
+    if (mine) {
+#pragma unroll
+        for (int k = 0; k < REG_PLANES; ++k) rg[k] = a.reg[k * G0 + n_own];
+    }
+
+    // ---- phase 1: scalars of iteration i-1 ---------------------------------
+    tile_brackets(a, g, L);
+    float alpha = 0.f, beta = 0.f;
+    int act = 1;
+    if (!FIRST) {
+        pcg_decide(a, i, pacc, h, log_index, force, alpha, beta, act);
+        if (!act) {
+            carry_partials(a, i);
+            return;
+        }
+    }
+
+    // ---- phase 2: u_i on the tile and its halo -----------------------------
+    float ru = 0.f, rr = 0.f, sv6[6], rn6[6];
+    if (hal) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            float uu, rn;
+            if (FIRST) {
+                uu = hv0[q];
+                rn = hv1[q];
+            } else {
+                sv6[q] = i > 1 ? hv1[q] + beta * hv2[q] : hv1[q];
+                rn = hv0[q] - alpha * sv6[q];
+                uu = rn / hv3[q];
+            }
+            rn6[q] = rn;
+            L.halo[(q * HY + (hnj - g.j0 + 1)) * HX + (hni - g.i0 + 1)] = uu;
+            ru += rn * uu;
+            rr += rn * rn;
+        }
+        if (hown) {
+            const int o = (hnj - g.j0) * t.tx + (hni - g.i0);
+            L.ownd[o] = ru;
+            L.ownd[t.tx * t.ty + o] = rr;
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 3: per-pixel block times the interpolated u_i ---------------
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int u = tid + k * NT_TILE;
+        if (u < npx) {
+            const int rx = u % g.RX, ry = u / g.RX;
+            const int bx0 = L.bxi[rx], by0 = L.byi[ry];
+            const float wx0 = L.bxw0[rx], wx1 = L.bxw1[rx], wy0 = L.byw0[ry], wy1 = L.byw1[ry];
+            const int lx0 = bx0 - g.i0 + 1, lx1 = (d.Gx == 1 ? bx0 : bx0 + 1) - g.i0 + 1;
+            const int ly0 = by0 - g.j0 + 1, ly1 = (d.Gy == 1 ? by0 : by0 + 1) - g.j0 + 1;
+            float pv[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const float *Hq = L.halo + q * HY * HX;
+                pv[q] = wy0 * (wx0 * Hq[ly0 * HX + lx0] + wx1 * Hq[ly0 * HX + lx1]) +
+                        wy1 * (wx0 * Hq[ly1 * HX + lx0] + wx1 * Hq[ly1 * HX + lx1]);
+            }
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                float acc = 0.f;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) acc += Gm[k][r <= c ? tri(r, c) : tri(c, r)] * pv[c];
+                L.vals[(r * g.RY + ry) * g.RX + rx] = acc;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 4: sums onto nodes, regularisers ----------------------------
+    float uo[6], po[6], xo[6];
+    if (mine && !FIRST) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const long k = q * G0 + n_own;
+            uo[q] = U[k];
+            po[q] = i > 1 ? P[k] : 0.f;
+            xo[q] = X[k];
+        }
+    }
+    float acc[6];
+    lds_to_nodes<6, S>(a, t, g, L, 0u, acc);
+    float prt[3] = {0.f, 0.f, 0.f};
+    float w6[6], uv[6];
+    if (mine) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) uv[q] = L.halo[(q * HY + tj + 1) * HX + ti + 1];
+        float jp0 = 0.f, jp1 = 0.f;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) { jp0 += rg[4 + q] * uv[q]; jp1 += rg[10 + q] * uv[q]; }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            float sm = 0.f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                int di, dj;
+                nb_offset(k, di, dj);
+                // neighbours outside the grid have coefficient 0; their halo
+                // slot is never written, so it is not read
+                if (rg[k] != 0.f)
+                    sm += rg[k] * (uv[q] - L.halo[(q * HY + tj + 1 + dj) * HX + ti + 1 + di]);
+            }
+            w6[q] = acc[q] + wf[q] * sm + rg[4 + q] * jp0 + rg[10 + q] * jp1 + cm[q] * uv[q];
+            prt[1] += w6[q] * uv[q];
+        }
+        const int o = tj * t.tx + ti;
+        prt[0] = L.ownd[o];
+        prt[2] = L.ownd[t.tx * t.ty + o];
+    }
+    float tot3[3];
+    block_sum<3>(prt, tot3);
+
+    // ---- stores ---------------------------------------------------------------
+    if (hown && !FIRST) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            Sc[q * G0 + hn] = sv6[q];
+            Rc[q * G0 + hn] = rn6[q];
+        }
+    }
+    if (mine) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const long k = q * G0 + n_own;
+            Wc[k] = w6[q];
+            if (!FIRST) {
+                const float pv = i > 1 ? uo[q] + beta * po[q] : uo[q];
+                P[k] = pv;
+                X[k] = xo[q] + alpha * pv;
+                U[k] = uv[q];
+            }
+        }
+    }
+    if (tid == 0) {
+        const long dst = (long)((i & 1) ? PS_PCG1 : PS_PCG0) * a.max_blocks;
+        const int bid = block_linear();
+        for (int k = 0; k < 3; ++k) a.partials[dst + (long)k * a.max_blocks + bid] = tot3[k];
+    }
+}
+
+// Applies iteration n-1 (no H-product) and leaves ||r_n||^2 partials.
+__global__ __launch_bounds__(SF_BLOCK) void k_pcg_last(LevelArgs a, int n_it,
+                                                       int nb_prev, int log_index,
+                                                       int force) {
+    const long G0 = a.G0;
+    const int i = n_it;
+    const float *Rp = a.nodes + (long)(((i - 1) & 1) ? NV_R1 : NV_R0) * 6 * G0;
+    float *Rc = a.nodes + (long)((i & 1) ? NV_R1 : NV_R0) * 6 * G0;
+    const float *Wp = a.nodes + (long)(((i - 1) & 1) ? NV_W1 : NV_W0) * 6 * G0;
+    const float *Sp = a.nodes + (long)(((i - 2) & 1) ? NV_S1 : NV_S0) * 6 * G0;
+    const float *U = a.nodes + (long)NV_U * 6 * G0;
+    float *P = a.nodes + (long)NV_P * 6 * G0;
+    float *X = a.nodes + (long)NV_X * 6 * G0;
+    const long n = (long)blockIdx.x * SF_BLOCK + threadIdx.x;
+    const bool in = n < a.d.G;
+    double pacc[3];
+    load_pcg_partials(a, i, nb_prev, pacc);
+    PcgHist h;
+    h.gamma = 0.0; h.alpha = 0.f; h.beta = 0.f; h.active = 1; h.pad = 0;
+    if (threadIdx.x == 0) h = a.sc->hist[i - 1];
+    float rp[6], wp[6], sp[6], up[6], pp[6], xp[6];
+    if (in) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const long k = q * G0 + n;
+            rp[q] = Rp[k]; wp[q] = Wp[k]; up[q] = U[k]; xp[q] = X[k];
+            sp[q] = i > 1 ? Sp[k] : 0.f;
+            pp[q] = i > 1 ? P[k] : 0.f;
+        }
+    }
+    float alpha, beta;
+    int act;
+    pcg_decide(a, i, pacc, h, log_index, force, alpha, beta, act);
+    float prt[1] = {0.f};
+    if (in) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const long k = q * G0 + n;
+            float rn = rp[q];
+            if (act) {
+                const float sv = i > 1 ? wp[q] + beta * sp[q] : wp[q];
+                const float pv = i > 1 ? up[q] + beta * pp[q] : up[q];
+                P[k] = pv;
+                X[k] = xp[q] + alpha * pv;
+                rn = rn - alpha * sv;
+            }
+            Rc[k] = rn;
+            prt[0] += rn * rn;
+        }
+    }
+    float tot1[1];
+    block_sum<1>(prt, tot1);
+    if (threadIdx.x == 0)
+        a.partials[(long)(((i & 1) ? PS_PCG1 : PS_PCG0) + 2) * a.max_blocks + blockIdx.x] = tot1[0];
 }
 
 // ---- step control: accept the first tau with E_trial <= E ------------------
 
 __global__ __launch_bounds__(SF_BLOCK) void k_accept(LevelArgs a, int n_trials,
                                                      int log_index, int gn_iter,
-                                                     int pcg_iters) {
+                                                     int pcg_iters, int nb_last) {
     const DevScalars *sc = a.sc;
     const double e0 = sc->e_lin[5];
     int kacc = -1;
@@ -912,24 +1203,32 @@ __global__ __launch_bounds__(SF_BLOCK) void k_accept(LevelArgs a, int n_trials,
     const long n = (long)blockIdx.x * SF_BLOCK + threadIdx.x;
     if (kacc >= 0 && n < a.d.G) {
         float *delta = a.nodes + (long)NV_DELTA * 6 * G0;
-        const float *X = a.nodes + (long)NV_DX * 6 * G0;
+        const float *X = a.nodes + (long)NV_X * 6 * G0;
 #pragma unroll
         for (int q = 0; q < 6; ++q) delta[q * G0 + n] = delta[q * G0 + n] + tau * X[q * G0 + n];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && log_index >= 0) {
-        DevLog &L = a.log[log_index];
-        L.level = a.level;
-        L.gn_iter = gn_iter;
-        L.energy = e0;
-        L.e_photo = sc->e_lin[0];
-        L.e_grad = sc->e_lin[1];
-        L.e_smooth = sc->e_lin[2];
-        L.e_epi = sc->e_lin[3];
-        L.e_mag = sc->e_lin[4];
-        L.energy_after = kacc >= 0 ? sc->e_trial[kacc][5] : e0;
-        L.tau = tau;
-        L.pcg_iters = pcg_iters;
-        L.n_valid = sc->n_valid;
+    if (blockIdx.x == 0 && log_index >= 0) {
+        const float *rrp = a.partials +
+                           (long)(((pcg_iters & 1) ? PS_PCG1 : PS_PCG0) + 2) * a.max_blocks;
+        const double rr = block_sum_partials(rrp, nb_last);
+        if (threadIdx.x == 0) {
+            DevLog &Lg = a.log[log_index];
+            Lg.level = a.level;
+            Lg.gn_iter = gn_iter;
+            Lg.energy = e0;
+            Lg.e_photo = sc->e_lin[0];
+            Lg.e_grad = sc->e_lin[1];
+            Lg.e_smooth = sc->e_lin[2];
+            Lg.e_epi = sc->e_lin[3];
+            Lg.e_mag = sc->e_lin[4];
+            Lg.energy_after = kacc >= 0 ? sc->e_trial[kacc][5] : e0;
+            Lg.tau = tau;
+            Lg.pcg_iters = pcg_iters;
+            // an inactive last iteration left r unchanged
+            const bool same = !sc->hist[pcg_iters].active && pcg_iters >= 2;
+            Lg.pcg_res[pcg_iters - 1] = same ? Lg.pcg_res[pcg_iters - 2] : (float)sqrt(rr);
+            Lg.n_valid = sc->n_valid;
+        }
     }
 }
 
@@ -965,7 +1264,7 @@ __global__ __launch_bounds__(SF_BLOCK) void k_prolong(LevelArgs a, int Gxc, int 
 // V(x): all four positions inside the level image; W(x): max_k |d_k| <
 // eps_p (Sec. 4.1); both at the level-start flow.  Also stores the mean of
 // the four warped images for the smoothness weights.
-__global__ __launch_bounds__(SF_BLOCK) void k_masks(LevelArgs a, int n_pix) {
+__global__ __launch_bounds__(SF_BLOCK) void k_masks(LevelArgs a) {
     const LevelDims &d = a.d;
     const DevConst &C = *a.cst;
     __shared__ NodeStage S;
@@ -1002,18 +1301,18 @@ __global__ __launch_bounds__(SF_BLOCK) void k_masks(LevelArgs a, int n_pix) {
     }
     float tot1[1];
     block_sum<1>(cnt, tot1);
-    if (threadIdx.x == 0) a.partials[bid] = tot1[0];
-    if (last_block(&a.sc->counter[2])) {
-        const double c = block_sum_partials(a.partials, gridDim.x);
-        if (threadIdx.x == 0) a.sc->n_valid = (int)c;
-    }
+    if (threadIdx.x == 0) a.partials[(long)PS_MASK * a.max_blocks + bid] = tot1[0];
 }
 
 // w_i = 1 + gamma exp(-lambda_min / tau_l) of the structure tensor of the
 // mean warped image over a 3x3 window at the node's rounded position.
-__global__ __launch_bounds__(SF_BLOCK) void k_node_weights(LevelArgs a) {
-    const long n = (long)blockIdx.x * SF_BLOCK + threadIdx.x;
+__global__ __launch_bounds__(SF_BLOCK) void k_node_weights(LevelArgs a, int n_mask_blocks) {
     const LevelDims &d = a.d;
+    if (blockIdx.x == 0) {
+        const double c = block_sum_partials(a.partials + (long)PS_MASK * a.max_blocks, n_mask_blocks);
+        if (threadIdx.x == 0) a.sc->n_valid = (int)c;
+    }
+    const long n = (long)blockIdx.x * SF_BLOCK + threadIdx.x;
     if (n >= d.G) return;
     const DevConst &C = *a.cst;
     const int i = (int)(n % d.Gx), j = (int)(n / d.Gx);
@@ -1094,34 +1393,36 @@ __global__ __launch_bounds__(SF_BLOCK) void k_output(LevelArgs a, float *depth,
     }
 }
 
-__global__ void k_set_apply_state(DevScalars *sc) {
-    if (threadIdx.x == 0) {
-        sc->active = 1;
-        sc->first = 1;
-        sc->beta = 0.f;
-    }
-}
-
-// A mid-solve PCG state for timing: active, not the first iteration, so
-// every launch does the full work (p = z + beta p_old, all updates).
-__global__ void k_set_pcg_state(DevScalars *sc) {
-    if (threadIdx.x == 0) {
-        sc->active = 1;
-        sc->first = 0;
-        sc->beta = 0.5f;
-        sc->alpha = 0.f;
-        sc->rz = 1.0;
-    }
-}
-
 }  // namespace
 
 // ---- launchers ----------------------------------------------------------------
 
+// Node tile per grid stride: a pixel region of roughly 20-40 px a side, the
+// 256 threads split evenly over the tile's nodes.
+TileCfg pick_tile(int s) {
+    TileCfg t;
+    if (s <= 1) { t.tx = 16; t.ty = 16; t.tpn = 2; }
+    else if (s == 2) { t.tx = 16; t.ty = 8; t.tpn = 4; }
+    else if (s == 3) { t.tx = 8; t.ty = 8; t.tpn = 8; }
+    else if (s == 4) { t.tx = 8; t.ty = 4; t.tpn = 16; }
+    else if (s <= 6) { t.tx = 4; t.ty = 4; t.tpn = 32; }
+    else { t.tx = 4; t.ty = 2; t.tpn = 64; }
+    return t;
+}
+
+int tile_threads() { return NT_TILE; }
+
+// Largest pixel region of a tile: (n + 1) s columns for even s, one more
+// for odd s (floor rounding of the support bounds).
+int tile_max_pixels(const TileCfg &t, int s) {
+    const int ex = (s & 1) ? 1 : 0;
+    return ((t.tx + 1) * s + ex) * ((t.ty + 1) * s + ex);
+}
+
+int tile_ppt() { return PPT; }
+
 size_t node_tile_lds_bytes(const TileCfg &t, int s, int K) {
-    size_t f = tile_lds_floats(t, s, K);
-    if (K == 6) f += (size_t)6 * (t.tx + 2) * (t.ty + 2);
-    return f * sizeof(float);
+    return tile_lds_floats(t, s, K) * sizeof(float);
 }
 
 static int pixel_tiles(const LevelDims &d) {
@@ -1135,6 +1436,12 @@ int energy_blocks(const LevelDims &d) {
 int node_tile_blocks(const LevelDims &d, const TileCfg &t) {
     return ((d.Gx + t.tx - 1) / t.tx) * ((d.Gy + t.ty - 1) / t.ty);
 }
+
+static dim3 tile_grid(const LevelDims &d, const TileCfg &t) {
+    return dim3((d.Gx + t.tx - 1) / t.tx, (d.Gy + t.ty - 1) / t.ty);
+}
+
+static int node_blocks(const LevelDims &d) { return (d.G + SF_BLOCK - 1) / SF_BLOCK; }
 
 void launch_tex_level0(hipStream_t st, const float *const img[4], float4 *tex,
                        int W, int H) {
@@ -1152,63 +1459,84 @@ void launch_downsample(hipStream_t st, const float4 *src, int Ws, int Hs,
 
 void launch_level_init(hipStream_t st, const LevelArgs &a,
                        const LevelDims *coarse, bool coarsest) {
-    const int gn = (a.d.G + SF_BLOCK - 1) / SF_BLOCK;
+    const int gn = node_blocks(a.d);
     hipLaunchKernelGGL(k_prolong, dim3(gn), dim3(SF_BLOCK), 0, st, a,
                        coarse ? coarse->Gx : 1, coarse ? coarse->Gy : 1,
                        coarsest ? 1 : 0);
     const int np = pixel_tiles(a.d);
-    hipLaunchKernelGGL(k_masks, dim3(np), dim3(SF_BLOCK), 0, st, a, np);
-    hipLaunchKernelGGL(k_node_weights, dim3(gn), dim3(SF_BLOCK), 0, st, a);
+    hipLaunchKernelGGL(k_masks, dim3(np), dim3(SF_BLOCK), 0, st, a);
+    hipLaunchKernelGGL(k_node_weights, dim3(gn), dim3(SF_BLOCK), 0, st, a, np);
 }
 
-void launch_energy(hipStream_t st, const LevelArgs &a, int mode, int trial,
-                   float tau, int n_before) {
+void launch_linearize(hipStream_t st, const LevelArgs &a) {
     const int np = pixel_tiles(a.d);
-    const int nb = energy_blocks(a.d);
-    if (mode == 0)
-        hipLaunchKernelGGL(k_energy<true>, dim3(nb), dim3(SF_BLOCK), 0, st, a, trial, tau, n_before, np);
-    else
-        hipLaunchKernelGGL(k_energy<false>, dim3(nb), dim3(SF_BLOCK), 0, st, a, trial, tau, n_before, np);
+    hipLaunchKernelGGL(k_energy<true>, dim3(energy_blocks(a.d)), dim3(SF_BLOCK), 0, st, a, 0,
+                       0.f, np);
 }
 
-void launch_node_rhs(hipStream_t st, const LevelArgs &a, const TileCfg &t) {
-    dim3 grid((a.d.Gx + t.tx - 1) / t.tx, (a.d.Gy + t.ty - 1) / t.ty);
-    hipLaunchKernelGGL(k_node_rhs, grid, dim3(SF_BLOCK), node_tile_lds_bytes(t, a.s, 12), st, a, t);
+void launch_trial(hipStream_t st, const LevelArgs &a, int trial, float tau) {
+    const int np = pixel_tiles(a.d);
+    hipLaunchKernelGGL(k_energy<false>, dim3(energy_blocks(a.d)), dim3(SF_BLOCK), 0, st, a,
+                       trial, tau, np);
 }
 
-void launch_apply(hipStream_t st, const LevelArgs &a, const TileCfg &t, int iter,
-                  int) {
-    dim3 grid((a.d.Gx + t.tx - 1) / t.tx, (a.d.Gy + t.ty - 1) / t.ty);
-    hipLaunchKernelGGL(k_apply, grid, dim3(SF_BLOCK), node_tile_lds_bytes(t, a.s, 6), st, a, t, iter);
+// The node-tile kernels are instantiated per grid stride (1..8).
+#define SF_STRIDE_SWITCH(s, CALL) \
+    switch (s) {                  \
+        case 1: CALL(1); break;   \
+        case 2: CALL(2); break;   \
+        case 3: CALL(3); break;   \
+        case 4: CALL(4); break;   \
+        case 5: CALL(5); break;   \
+        case 6: CALL(6); break;   \
+        case 7: CALL(7); break;   \
+        default: CALL(8); break;  \
+    }
+
+void launch_rhs(hipStream_t st, const LevelArgs &a, const TileCfg &t) {
+#define RHS(S)                                                                          \
+    hipLaunchKernelGGL(k_rhs<S>, tile_grid(a.d, t), dim3(NT_TILE),                      \
+                       node_tile_lds_bytes(t, a.s, 12), st, a, t, energy_blocks(a.d))
+    SF_STRIDE_SWITCH(a.s, RHS)
+#undef RHS
 }
 
-void launch_update(hipStream_t st, const LevelArgs &a, int iter, int log_index) {
-    const int gn = (a.d.G + SF_BLOCK - 1) / SF_BLOCK;
-    hipLaunchKernelGGL(k_update, dim3(gn), dim3(SF_BLOCK), 0, st, a, iter, log_index);
+void launch_pcg_first(hipStream_t st, const LevelArgs &a, const TileCfg &t) {
+#define PCG0(S)                                                                          \
+    hipLaunchKernelGGL((k_pcg<true, S>), tile_grid(a.d, t), dim3(NT_TILE),               \
+                       node_tile_lds_bytes(t, a.s, 6), st, a, t, 0, -1, 0, 0)
+    SF_STRIDE_SWITCH(a.s, PCG0)
+#undef PCG0
 }
 
-void launch_accept(hipStream_t st, const LevelArgs &a, int n_trials,
+void launch_pcg_iter(hipStream_t st, const LevelArgs &a, const TileCfg &t, int iter,
+                     int log_index, int force) {
+#define PCGI(S)                                                                          \
+    hipLaunchKernelGGL((k_pcg<false, S>), tile_grid(a.d, t), dim3(NT_TILE),              \
+                       node_tile_lds_bytes(t, a.s, 6), st, a, t, iter, log_index, force, \
+                       node_tile_blocks(a.d, t))
+    SF_STRIDE_SWITCH(a.s, PCGI)
+#undef PCGI
+}
+
+void launch_pcg_last(hipStream_t st, const LevelArgs &a, const TileCfg &t, int iter,
+                     int log_index, int force) {
+    hipLaunchKernelGGL(k_pcg_last, dim3(node_blocks(a.d)), dim3(SF_BLOCK), 0, st, a, iter,
+                       node_tile_blocks(a.d, t), log_index, force);
+}
+
+void launch_accept(hipStream_t st, const LevelArgs &a, const TileCfg &, int n_trials,
                    int log_index, int gn_iter, int pcg_iters) {
-    const int gn = (a.d.G + SF_BLOCK - 1) / SF_BLOCK;
-    hipLaunchKernelGGL(k_accept, dim3(gn), dim3(SF_BLOCK), 0, st, a, n_trials, log_index,
-                       gn_iter, pcg_iters);
+    hipLaunchKernelGGL(k_accept, dim3(node_blocks(a.d)), dim3(SF_BLOCK), 0, st, a, n_trials,
+                       log_index, gn_iter, pcg_iters, node_blocks(a.d));
 }
 
 void launch_finish_level(hipStream_t st, const LevelArgs &a) {
-    const int gn = (a.d.G + SF_BLOCK - 1) / SF_BLOCK;
-    hipLaunchKernelGGL(k_finish_level, dim3(gn), dim3(SF_BLOCK), 0, st, a);
+    hipLaunchKernelGGL(k_finish_level, dim3(node_blocks(a.d)), dim3(SF_BLOCK), 0, st, a);
 }
 
 void launch_output(hipStream_t st, const LevelArgs &a, float *depth,
                    float *flow3d, float *flows) {
     hipLaunchKernelGGL(k_output, dim3(pixel_tiles(a.d)), dim3(SF_BLOCK), 0, st, a,
                        depth, flow3d, flows);
-}
-
-void launch_set_apply_state(hipStream_t st, DevScalars *sc) {
-    hipLaunchKernelGGL(k_set_apply_state, dim3(1), dim3(64), 0, st, sc);
-}
-
-void launch_set_pcg_state(hipStream_t st, DevScalars *sc) {
-    hipLaunchKernelGGL(k_set_pcg_state, dim3(1), dim3(64), 0, st, sc);
 }

@@ -101,9 +101,9 @@ def _gram_upper(Gx):
     return Gx[:, iu[0], iu[1]].T  # (21, N)
 
 
-@pytest.mark.parametrize("level", [0, 2])
-def test_linearize_apply_pcg_parity(level):
-    g, imgs, calib, p = _stage_case()
+@pytest.mark.parametrize("level,stride", [(0, 4), (2, 4), (0, 8), (1, 2), (0, 3)])
+def test_linearize_apply_pcg_parity(level, stride):
+    g, imgs, calib, p = _stage_case(W=104, H=78, grid_stride=stride)
     try:
         g.run(g.sf.SF_STAGE_LEVEL_INIT, level)
         ls, _ = _oracle_level(imgs, calib, p, level)
@@ -176,7 +176,8 @@ def _solve_parity(imgs, calib, prm, e_tol=1e-4, f_tol=0.02):
         assert lg["level"] == ro["level"]
         rel = abs(lg["energy"] - ro["energy"]) / abs(ro["energy"])
         worst = max(worst, rel)
-        assert rel <= e_tol, (lg["level"], lg["gn_iter"], lg["energy"], ro["energy"])
+        assert rel <= e_tol, (lg["level"], lg["gn_iter"], lg["energy"], ro["energy"],
+                              [l["tau"] for l in log], [r["tau"] for r in rec])
         assert lg["energy_after"] <= lg["energy"]
     grid = res["grid"]
     ref_flows = grid.to_pixels(res["total"]).reshape(6, grid.H, grid.W)
