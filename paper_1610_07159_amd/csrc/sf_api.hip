@@ -327,7 +327,7 @@ sf_status sf_create(sf_ctx **out, int width, int height, const sf_params *p,
     c->max_blocks = mb;
     if (node_tile_lds_bytes(c->tile, st, 12) > 64 * 1024 ||
         node_tile_lds_bytes(c->tile, st, 6) > 64 * 1024 ||
-        tile_max_pixels(c->tile, st) > tile_ppt() * tile_threads()) {
+        tile_max_pixels(c->tile, st) > tile_ppt(st) * tile_threads(st)) {
         delete c;
         return SF_ERR_INVALID_ARG;
     }

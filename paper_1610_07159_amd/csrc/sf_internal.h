@@ -96,8 +96,8 @@ struct DevLog {
     int n_valid;
 };
 
-// Launch geometry of the node-tile kernels: tx x ty nodes per 512-thread
-// workgroup, tpn threads per node (tx * ty * tpn = 512, tpn <= 64).
+// Launch geometry of the node-tile kernels: tx x ty nodes per workgroup,
+// tpn threads per node (the workgroup has tx * ty * tpn threads).
 struct TileCfg {
     int tx, ty, tpn;
 };
@@ -142,9 +142,9 @@ void launch_finish_level(hipStream_t st, const LevelArgs &a);
 void launch_output(hipStream_t st, const LevelArgs &a, float *depth,
                    float *flow3d, float *flows);
 TileCfg pick_tile(int s);
-int tile_threads();
+int tile_threads(int s);
 int tile_max_pixels(const TileCfg &t, int s);
-int tile_ppt();
+int tile_ppt(int s);
 size_t node_tile_lds_bytes(const TileCfg &t, int s, int K);
 int energy_blocks(const LevelDims &d);
 int node_tile_blocks(const LevelDims &d, const TileCfg &t);

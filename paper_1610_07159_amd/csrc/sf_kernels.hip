@@ -17,8 +17,22 @@
 
 #include "sf_internal.h"
 
-#define NT_TILE 512   // threads of a node-tile workgroup
-#define PPT 2         // max region pixels per thread (checked on the host)
+// Node-tile shape per grid stride S: tx x ty nodes, tpn threads per node
+// (tpn >= 2S so one thread sums one support row), NT = tx ty tpn threads
+// and at most PPT region pixels per thread.  256 threads where the register
+// budget allows more than one workgroup per CU, 512 for the largest strides.
+template <int S>
+struct TileTraits {
+    static constexpr int TX = S <= 2 ? 16 : (S <= 4 ? 8 : 4);
+    static constexpr int TY = S == 1 ? 8 : (S == 2 ? 4 : (S <= 4 ? 4 : 2));
+    static constexpr int TPN = S == 1 ? 2 : (S == 2 ? 4 : (S <= 4 ? 8 : (S <= 6 ? 32 : 64)));
+    static constexpr int NT = TX * TY * TPN;
+    static constexpr int MAXPX = ((TX + 1) * S + (S & 1)) * ((TY + 1) * S + (S & 1));
+    static constexpr int PPT = (MAXPX + NT - 1) / NT;
+    static_assert(TPN >= 2 * S && TPN <= 64, "one support row per thread, one wave per node");
+    static_assert(NT == 256 || NT == 512, "block size");
+    static_assert(PPT <= 3, "pixels per thread");
+};
 
 namespace {
 
@@ -710,7 +724,7 @@ __device__ __forceinline__ void nb_offset(int k, int &di, int &dj) {
 // ---- right-hand side and diag(H) (node tiles) ----------------------------
 
 template <int S>
-__global__ __launch_bounds__(NT_TILE) void k_rhs(LevelArgs a, TileCfg t, int n_lin_blocks) {
+__global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(LevelArgs a, TileCfg t, int n_lin_blocks) {
     extern __shared__ float lds[];
     const LevelDims &d = a.d;
     const DevConst &C = *a.cst;
@@ -908,8 +922,10 @@ __device__ void carry_partials(const LevelArgs &a, int i) {
 // before the partial sums are reduced, and constants are read once, so the
 // workgroup waits for memory about once.
 template <bool FIRST, int S>
-__global__ __launch_bounds__(NT_TILE) void k_pcg(LevelArgs a, TileCfg t, int i,
-                                                 int log_index, int force, int nb_prev) {
+__global__ __launch_bounds__(TileTraits<S>::NT) void k_pcg(LevelArgs a, TileCfg t, int i,
+                                                           int log_index, int force, int nb_prev) {
+    constexpr int NT_TILE = TileTraits<S>::NT;
+    constexpr int PPT = TileTraits<S>::PPT;
     extern __shared__ float lds[];
     const LevelDims &d = a.d;
     const long G0 = a.G0;
@@ -1397,20 +1413,39 @@ __global__ __launch_bounds__(SF_BLOCK) void k_output(LevelArgs a, float *depth,
 
 // ---- launchers ----------------------------------------------------------------
 
+// The node-tile kernels are instantiated per grid stride (1..8).
+#define SF_STRIDE_SWITCH(s, CALL) \
+    switch (s) {                  \
+        case 1: CALL(1); break;   \
+        case 2: CALL(2); break;   \
+        case 3: CALL(3); break;   \
+        case 4: CALL(4); break;   \
+        case 5: CALL(5); break;   \
+        case 6: CALL(6); break;   \
+        case 7: CALL(7); break;   \
+        default: CALL(8); break;  \
+    }
+
+
 // Node tile per grid stride: a pixel region of roughly 20-40 px a side, the
 // 256 threads split evenly over the tile's nodes.
-TileCfg pick_tile(int s) {
+template <int S>
+static TileCfg tile_of() {
     TileCfg t;
-    if (s <= 1) { t.tx = 16; t.ty = 16; t.tpn = 2; }
-    else if (s == 2) { t.tx = 16; t.ty = 8; t.tpn = 4; }
-    else if (s == 3) { t.tx = 8; t.ty = 8; t.tpn = 8; }
-    else if (s == 4) { t.tx = 8; t.ty = 4; t.tpn = 16; }
-    else if (s <= 6) { t.tx = 4; t.ty = 4; t.tpn = 32; }
-    else { t.tx = 4; t.ty = 2; t.tpn = 64; }
+    t.tx = TileTraits<S>::TX;
+    t.ty = TileTraits<S>::TY;
+    t.tpn = TileTraits<S>::TPN;
     return t;
 }
 
-int tile_threads() { return NT_TILE; }
+TileCfg pick_tile(int s) {
+#define TILE(S) return tile_of<S>()
+    SF_STRIDE_SWITCH(s, TILE)
+#undef TILE
+    return tile_of<8>();
+}
+
+int tile_threads(int s) { return pick_tile(s).tx * pick_tile(s).ty * pick_tile(s).tpn; }
 
 // Largest pixel region of a tile: (n + 1) s columns for even s, one more
 // for odd s (floor rounding of the support bounds).
@@ -1419,7 +1454,12 @@ int tile_max_pixels(const TileCfg &t, int s) {
     return ((t.tx + 1) * s + ex) * ((t.ty + 1) * s + ex);
 }
 
-int tile_ppt() { return PPT; }
+int tile_ppt(int s) {
+#define PPTS(S) return TileTraits<S>::PPT
+    SF_STRIDE_SWITCH(s, PPTS)
+#undef PPTS
+    return TileTraits<8>::PPT;
+}
 
 size_t node_tile_lds_bytes(const TileCfg &t, int s, int K) {
     return tile_lds_floats(t, s, K) * sizeof(float);
@@ -1480,22 +1520,9 @@ void launch_trial(hipStream_t st, const LevelArgs &a, int trial, float tau) {
                        trial, tau, np);
 }
 
-// The node-tile kernels are instantiated per grid stride (1..8).
-#define SF_STRIDE_SWITCH(s, CALL) \
-    switch (s) {                  \
-        case 1: CALL(1); break;   \
-        case 2: CALL(2); break;   \
-        case 3: CALL(3); break;   \
-        case 4: CALL(4); break;   \
-        case 5: CALL(5); break;   \
-        case 6: CALL(6); break;   \
-        case 7: CALL(7); break;   \
-        default: CALL(8); break;  \
-    }
-
 void launch_rhs(hipStream_t st, const LevelArgs &a, const TileCfg &t) {
 #define RHS(S)                                                                          \
-    hipLaunchKernelGGL(k_rhs<S>, tile_grid(a.d, t), dim3(NT_TILE),                      \
+    hipLaunchKernelGGL(k_rhs<S>, tile_grid(a.d, t), dim3(TileTraits<S>::NT),            \
                        node_tile_lds_bytes(t, a.s, 12), st, a, t, energy_blocks(a.d))
     SF_STRIDE_SWITCH(a.s, RHS)
 #undef RHS
@@ -1503,7 +1530,7 @@ void launch_rhs(hipStream_t st, const LevelArgs &a, const TileCfg &t) {
 
 void launch_pcg_first(hipStream_t st, const LevelArgs &a, const TileCfg &t) {
 #define PCG0(S)                                                                          \
-    hipLaunchKernelGGL((k_pcg<true, S>), tile_grid(a.d, t), dim3(NT_TILE),               \
+    hipLaunchKernelGGL((k_pcg<true, S>), tile_grid(a.d, t), dim3(TileTraits<S>::NT),     \
                        node_tile_lds_bytes(t, a.s, 6), st, a, t, 0, -1, 0, 0)
     SF_STRIDE_SWITCH(a.s, PCG0)
 #undef PCG0
@@ -1512,7 +1539,7 @@ void launch_pcg_first(hipStream_t st, const LevelArgs &a, const TileCfg &t) {
 void launch_pcg_iter(hipStream_t st, const LevelArgs &a, const TileCfg &t, int iter,
                      int log_index, int force) {
 #define PCGI(S)                                                                          \
-    hipLaunchKernelGGL((k_pcg<false, S>), tile_grid(a.d, t), dim3(NT_TILE),              \
+    hipLaunchKernelGGL((k_pcg<false, S>), tile_grid(a.d, t), dim3(TileTraits<S>::NT),    \
                        node_tile_lds_bytes(t, a.s, 6), st, a, t, iter, log_index, force, \
                        node_tile_blocks(a.d, t))
     SF_STRIDE_SWITCH(a.s, PCGI)
