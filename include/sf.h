@@ -123,8 +123,49 @@ typedef struct {
  * if any logged energy is NaN or Inf (the records are still written). */
 sf_status sf_get_log(sf_ctx *ctx, sf_iter_log *out, int cap, int *n_written);
 
+/* ---- batches of frames ------------------------------------------------
+ * A batch solves up to 64 independent frames of any sizes together: every
+ * kernel of the hierarchy runs once per step for all frames (each workgroup
+ * serves one frame; reductions stay per frame), and the whole batch
+ * (pyramids, all levels, outputs) replays as one captured HIP graph.  Each
+ * frame gets the same result as a single-frame solve with the same
+ * parameters and level count. */
+typedef struct {
+    const float *img[4];  /* device H x W float32: left t, right t, left t+1,
+                             right t+1 (Sec. 3.1)                           */
+    int width, height;
+    sf_calib calib;
+    float *depth;         /* device H x W, as in sf_solve                   */
+    float *flow3d;        /* device 3 x H x W, as in sf_solve               */
+    float *flows;         /* device 6 x H x W or NULL                       */
+} sf_frame;
+
+/* Pyramid levels a batch uses for a width x height frame: the largest
+ * L <= max_levels with W / 2^(L-1) >= 40 px (at least 1), reduced until the
+ * coarsest level is at least 8 x 8. */
+int sf_batch_levels(int width, int height, int max_levels);
+
+/* Solves n frames (1..64).  p: as in sf_solve, except that the schedule may
+ * differ from the context's (the batch workspace is rebuilt when the
+ * schedule or the list of frame sizes changes: the first call for a batch
+ * shape allocates, later calls with the same shape allocate nothing).
+ * frames[i] needs four images, depth and flow3d, width and height >= 16 and
+ * a valid calibration, else SF_ERR_INVALID_ARG / SF_ERR_SIZE before
+ * anything is enqueued.  Asynchronous on the context's stream. */
+sf_status sf_solve_batch(sf_ctx *ctx, int n, const sf_frame *frames,
+                         const sf_params *p);
+
+/* Log of frame `frame` of the last batch solve, as sf_get_log. */
+sf_status sf_get_batch_log(sf_ctx *ctx, int frame, sf_iter_log *out, int cap,
+                           int *n_written);
+
 /* Human-readable name of a status code (static string). */
 const char *sf_status_string(sf_status s);
+
+/* The HIP call behind the calling thread's last SF_ERR_HIP / SF_ERR_OOM,
+ * with HIP's error string ("" if none); valid until the thread's next
+ * failing call. */
+const char *sf_last_error(void);
 
 /* Frees the context and all its device memory; NULL-safe.  Synchronises the
  * context's stream first. */
@@ -204,6 +245,11 @@ enum {
 };
 sf_status sf_time_kernel(sf_ctx *ctx, int kernel, int level, int reps,
                          float *avg_ms);
+
+/* The same for the batch workspace: one launch covers every frame of the
+ * last batch that has a level `level`. */
+sf_status sf_time_batch_kernel(sf_ctx *ctx, int kernel, int level, int reps,
+                               float *avg_ms);
 
 #ifdef __cplusplus
 }

@@ -20,6 +20,9 @@ def command(out=LIB):
             "-shared", "-Wall", "-Wno-unused-function",
             # no packed-FP32 instructions in device code
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # multiply-adds fused only within a source expression, so every
+            # instantiation of a kernel (single frame, batched) rounds alike
+            "-ffp-contract=on",
             "-I", os.path.join(ROOT, "include"),
             "-I", os.path.join(HERE, "csrc"),
             "-o", out] + [os.path.join(HERE, s) for s in SOURCES]

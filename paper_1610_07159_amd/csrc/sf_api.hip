@@ -1,48 +1,88 @@
 // Host side of the C ABI declared in include/sf.h: argument validation,
 // workspace allocation, the coarse-to-fine level loop (Algorithm 1 without
 // the occlusion and illumination map updates; Sec. 5.3), HIP graph capture
-// and replay, logging and test access to intermediates.
+// and replay, batches of frames, logging and test access to intermediates.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "sf_internal.h"
+
+namespace {
+
+// Device buffers of one frame.
+struct FrameBuf {
+    int W = 0, H = 0, L = 0;
+    LevelDims lv[SF_MAX_LEVELS]{};
+    long N0 = 0, G0 = 0, tex_len = 0;
+    int max_blocks = 0;
+    int nlog = 0;
+    float4 *tex = nullptr;
+    unsigned char *cmask = nullptr;
+    float *wnode = nullptr, *reg = nullptr, *nodes = nullptr, *rec = nullptr;
+    float *partials = nullptr;
+    DevConst *cst = nullptr;
+    DevScalars *sc = nullptr;
+    DevLog *log = nullptr;
+    FrameIO *io = nullptr;
+};
+
+// A set of frames solved together: their buffers (one device allocation),
+// per-level kernel arguments, staging of per-call constants and the
+// captured graph.  Level slot l holds the frames that have a level l.
+struct Plan {
+    int nf = 0;
+    bool batched = false;
+    int Lmax = 0;
+    sf_params prm{};
+    TileCfg tile{};
+    std::vector<FrameBuf> fr;
+    std::vector<std::vector<LevelArgs>> host;  // [slot] -> args of its frames
+    std::vector<long> slot_off;                // offset of each slot in dtab
+    LevelArgs *dtab = nullptr;
+    char *pool = nullptr;
+    DevConst *dcst = nullptr;  // nf DevConst, then nf FrameIO (one upload)
+    FrameIO *dio = nullptr;
+    char *stage = nullptr;     // pinned copy of the same
+    size_t stage_bytes = 0;
+    hipEvent_t stage_ev = nullptr;
+    bool stage_pending = false;
+    bool have_inputs = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int> shape;  // W, H per frame (batch cache key)
+};
+
+}  // namespace
 
 struct sf_ctx {
     int W = 0, H = 0, device = 0;
     sf_params prm{};
     hipStream_t stream = nullptr;      // caller's stream
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
-    int L = 0;
-    LevelDims lv[SF_MAX_LEVELS]{};
-    TileCfg tile{};
-    long N0 = 0, G0 = 0;
-    int max_blocks = 0;
-    float4 *tex = nullptr;
-    unsigned char *cmask = nullptr;
-    float *wnode = nullptr;
-    float *reg = nullptr;
-    float *nodes = nullptr;
-    float *rec = nullptr;
-    float *partials = nullptr;
-    DevConst *dconst = nullptr;
-    DevConst *hconst = nullptr;  // pinned staging copy
-    DevScalars *sc = nullptr;
-    DevLog *dlog = nullptr;
-    int nlog = 0;
-    hipEvent_t const_ev = nullptr;
-    bool const_pending = false;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    bool have_images = false;
+    Plan single;
+    Plan *batch = nullptr;
 };
 
 namespace {
 
+// Description of the last failed HIP call of this thread (sf_last_error).
+thread_local char g_err[256] = "";
+
+void note_hip_error(const char *what, hipError_t e) {
+    snprintf(g_err, sizeof(g_err), "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
 #define HIP_TRY(x)                                   \
     do {                                             \
-        if ((x) != hipSuccess) return SF_ERR_HIP;    \
+        const hipError_t e_ = (x);                   \
+        if (e_ != hipSuccess) {                      \
+            note_hip_error(#x, e_);                  \
+            return SF_ERR_HIP;                       \
+        }                                            \
     } while (0)
 
 sf_status check_params(const sf_params *p) {
@@ -71,7 +111,18 @@ bool same_schedule(const sf_params &a, const sf_params &b) {
            a.max_backtracks == b.max_backtracks && a.init_mode == b.init_mode;
 }
 
-void fill_const(const sf_ctx *c, const sf_params &p, const sf_calib &cal, DevConst &k) {
+sf_status check_calib(const sf_calib *cal) {
+    if (!cal) return SF_ERR_INVALID_ARG;
+    const float v[] = {cal->fx, cal->fy, cal->cx, cal->cy, cal->baseline};
+    for (float x : v)
+        if (!isfinite(x)) return SF_ERR_INVALID_ARG;
+    if (!(cal->fx > 0.f) || !(cal->fy > 0.f) || !(cal->baseline > 0.f)) return SF_ERR_INVALID_ARG;
+    for (int i = 0; i < 9; ++i)
+        if (!isfinite(cal->F[i])) return SF_ERR_INVALID_ARG;
+    return SF_OK;
+}
+
+void fill_const(int L, const sf_params &p, const sf_calib &cal, DevConst &k) {
     memset(&k, 0, sizeof(k));
     k.w_reg = p.w_reg; k.w_photo = p.w_photo; k.w_grad = p.w_grad;
     k.w_epi = p.w_epi; k.w_smooth = p.w_smooth; k.w_mag = p.w_mag;
@@ -82,7 +133,7 @@ void fill_const(const sf_ctx *c, const sf_params &p, const sf_calib &cal, DevCon
     k.fx = cal.fx; k.fy = cal.fy; k.cx = cal.cx; k.cy = cal.cy; k.baseline = cal.baseline;
     // level-l pixel p_l maps to level-0 pixel 2^l p_l + (2^l - 1)/2; the
     // level fundamental matrix A^T F A / 2^l keeps residuals in level pixels
-    for (int l = 0; l < c->L; ++l) {
+    for (int l = 0; l < L; ++l) {
         const double s = ldexp(1.0, l), o = (s - 1.0) / 2.0;
         const double A[9] = {s, 0, o, 0, s, o, 0, 0, 1};
         double T[9], R[9];
@@ -102,95 +153,297 @@ void fill_const(const sf_ctx *c, const sf_params &p, const sf_calib &cal, DevCon
     }
 }
 
-sf_status upload_const(sf_ctx *c, const sf_params &p, const sf_calib &cal) {
-    DevConst k;
-    fill_const(c, p, cal, k);
-    if (memcmp(&k, c->hconst, sizeof(k)) == 0 && c->have_images) return SF_OK;
-    if (c->const_pending) {
-        HIP_TRY(hipEventSynchronize(c->const_ev));
-        c->const_pending = false;
+// ---- plans -------------------------------------------------------------------
+
+// Level sizes of a W x H frame with L levels; false if a level would be
+// smaller than 8 x 8.
+bool frame_dims(FrameBuf &f, int W, int H, int L, int st) {
+    f.W = W;
+    f.H = H;
+    f.L = L;
+    long tex_off = 0;
+    for (int l = 0; l < L; ++l) {
+        LevelDims &d = f.lv[l];
+        d.W = W >> l;
+        d.H = H >> l;
+        if (d.W < 8 || d.H < 8) return false;
+        d.Gx = (d.W + st - 1) / st;
+        d.Gy = (d.H + st - 1) / st;
+        d.N = d.W * d.H;
+        d.G = d.Gx * d.Gy;
+        d.tex_off = tex_off;
+        tex_off += 4L * d.N;
     }
-    memcpy(c->hconst, &k, sizeof(k));
-    HIP_TRY(hipMemcpyAsync(c->dconst, c->hconst, sizeof(k), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipEventRecord(c->const_ev, c->stream));
-    c->const_pending = true;
+    f.tex_len = tex_off;
+    f.N0 = f.lv[0].N;
+    f.G0 = f.lv[0].G;
+    return true;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+void free_plan(Plan &P) {
+    // best-effort release: errors here cannot be reported to anyone
+    if (P.gexec) (void)hipGraphExecDestroy(P.gexec);
+    if (P.graph) (void)hipGraphDestroy(P.graph);
+    if (P.pool) (void)hipFree(P.pool);
+    if (P.stage) (void)hipHostFree(P.stage);
+    if (P.stage_ev) (void)hipEventDestroy(P.stage_ev);
+    P = Plan();
+}
+
+// Allocates and initialises the workspace of frames of the given sizes and
+// level counts.
+sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shape,
+                     const std::vector<int> &levels, bool batched) {
+    P.prm = prm;
+    P.batched = batched;
+    P.nf = (int)levels.size();
+    P.shape = shape;
+    const int st = prm.grid_stride;
+    P.tile = pick_tile(st);
+    if (node_tile_lds_bytes(P.tile, st, 12) > 64 * 1024 ||
+        node_tile_lds_bytes(P.tile, st, 6) > 64 * 1024 ||
+        tile_max_pixels(P.tile, st) > tile_ppt(st) * tile_threads(st))
+        return SF_ERR_INVALID_ARG;
+    P.fr.resize(P.nf);
+    P.Lmax = 0;
+    // sizes, then one allocation carved in 256-byte aligned pieces
+    size_t off = 0;
+    std::vector<size_t> o(P.nf * 11);
+    for (int f = 0; f < P.nf; ++f) {
+        FrameBuf &F = P.fr[f];
+        if (!frame_dims(F, shape[2 * f], shape[2 * f + 1], levels[f], st)) return SF_ERR_SIZE;
+        P.Lmax = P.Lmax > F.L ? P.Lmax : F.L;
+        int mb = 1;
+        for (int l = 0; l < F.L; ++l) {
+            const LevelDims &d = F.lv[l];
+            mb = mb > energy_blocks(d) ? mb : energy_blocks(d);
+            mb = mb > node_tile_blocks(d, P.tile) ? mb : node_tile_blocks(d, P.tile);
+            const int gb = (d.G + SF_BLOCK - 1) / SF_BLOCK;
+            mb = mb > gb ? mb : gb;
+        }
+        F.max_blocks = mb;
+        F.nlog = F.L * prm.gn_iters;
+        const size_t sz[9] = {sizeof(float4) * (size_t)F.tex_len,
+                              (size_t)F.N0,
+                              sizeof(float) * (size_t)F.G0,
+                              sizeof(float) * 16 * (size_t)F.G0,
+                              sizeof(float) * NV_COUNT * 6 * (size_t)F.G0,
+                              sizeof(float) * SF_REC_PLANES * (size_t)F.N0,
+                              sizeof(float) * PS_COUNT * (size_t)mb,
+                              sizeof(DevScalars),
+                              sizeof(DevLog) * (size_t)F.nlog};
+        for (int k = 0; k < 9; ++k) {
+            o[f * 11 + k] = off;
+            off += align_up(sz[k]);
+        }
+    }
+    const size_t cst_off = off;
+    off += align_up(sizeof(DevConst) * P.nf);
+    const size_t io_off = off;
+    off += align_up(sizeof(FrameIO) * P.nf);
+    const size_t stage_len = off - cst_off;
+    const size_t tab_off = off;
+    long ntab = 0;
+    P.slot_off.assign(P.Lmax, 0);
+    for (int l = 0; l < P.Lmax; ++l) {
+        P.slot_off[l] = ntab;
+        for (int f = 0; f < P.nf; ++f) ntab += P.fr[f].L > l ? 1 : 0;
+    }
+    off += align_up(sizeof(LevelArgs) * (size_t)ntab);
+    hipError_t e = hipMalloc(&P.pool, off);
+    if (e != hipSuccess) {
+        note_hip_error("hipMalloc(workspace)", e);
+        P.pool = nullptr;
+        return SF_ERR_OOM;
+    }
+    e = hipHostMalloc(&P.stage, stage_len, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        note_hip_error("hipHostMalloc(staging)", e);
+        P.stage = nullptr;
+        return SF_ERR_OOM;
+    }
+    memset(P.stage, 0, stage_len);
+    P.stage_bytes = stage_len;
+    HIP_TRY(hipEventCreateWithFlags(&P.stage_ev, hipEventDisableTiming));
+    P.dcst = (DevConst *)(P.pool + cst_off);
+    P.dio = (FrameIO *)(P.pool + io_off);
+    P.dtab = (LevelArgs *)(P.pool + tab_off);
+    for (int f = 0; f < P.nf; ++f) {
+        FrameBuf &F = P.fr[f];
+        F.tex = (float4 *)(P.pool + o[f * 11 + 0]);
+        F.cmask = (unsigned char *)(P.pool + o[f * 11 + 1]);
+        F.wnode = (float *)(P.pool + o[f * 11 + 2]);
+        F.reg = (float *)(P.pool + o[f * 11 + 3]);
+        F.nodes = (float *)(P.pool + o[f * 11 + 4]);
+        F.rec = (float *)(P.pool + o[f * 11 + 5]);
+        F.partials = (float *)(P.pool + o[f * 11 + 6]);
+        F.sc = (DevScalars *)(P.pool + o[f * 11 + 7]);
+        F.log = (DevLog *)(P.pool + o[f * 11 + 8]);
+        F.cst = P.dcst + f;
+        F.io = P.dio + f;
+    }
+    // zeroed workspace: arrival counters must start at 0
+    HIP_TRY(hipMemset(P.pool, 0, off));
+    // per-slot kernel arguments
+    P.host.assign(P.Lmax, {});
+    std::vector<LevelArgs> flat;
+    for (int l = 0; l < P.Lmax; ++l) {
+        for (int f = 0; f < P.nf; ++f) {
+            FrameBuf &F = P.fr[f];
+            if (F.L <= l) continue;
+            LevelArgs a;
+            memset(&a, 0, sizeof(a));
+            a.d = F.lv[l];
+            a.level = l;
+            a.s = st;
+            a.N0 = (int)F.N0;
+            a.G0 = (int)F.G0;
+            a.coarsest = l == F.L - 1;
+            a.Gxc = l + 1 < F.L ? F.lv[l + 1].Gx : 1;
+            a.Gyc = l + 1 < F.L ? F.lv[l + 1].Gy : 1;
+            a.log_base = (F.L - 1 - l) * prm.gn_iters;
+            a.Wf = l > 0 ? F.lv[l - 1].W : 0;
+            a.Hf = l > 0 ? F.lv[l - 1].H : 0;
+            a.tex = F.tex + F.lv[l].tex_off;
+            a.tex_fine = l > 0 ? F.tex + F.lv[l - 1].tex_off : nullptr;
+            a.io = F.io;
+            a.nodes = F.nodes;
+            a.rec = F.rec;
+            a.cmask = F.cmask;
+            a.wnode = F.wnode;
+            a.reg = F.reg;
+            a.partials = F.partials;
+            a.max_blocks = F.max_blocks;
+            a.cst = F.cst;
+            a.sc = F.sc;
+            a.log = F.log;
+            P.host[l].push_back(a);
+            flat.push_back(a);
+        }
+    }
+    if (!flat.empty())
+        HIP_TRY(hipMemcpy(P.dtab, flat.data(), sizeof(LevelArgs) * flat.size(),
+                          hipMemcpyHostToDevice));
+    HIP_TRY(hipDeviceSynchronize());
     return SF_OK;
 }
 
-LevelArgs level_args(sf_ctx *c, int l) {
-    LevelArgs a;
-    a.d = c->lv[l];
-    a.level = l;
-    a.s = c->prm.grid_stride;
-    a.N0 = (int)c->N0;
-    a.G0 = (int)c->G0;
-    a.tex = c->tex + c->lv[l].tex_off;
-    a.nodes = c->nodes;
-    a.rec = c->rec;
-    a.cmask = c->cmask;
-    a.wnode = c->wnode;
-    a.reg = c->reg;
-    a.partials = c->partials;
-    a.max_blocks = c->max_blocks;
-    a.cst = c->dconst;
-    a.sc = c->sc;
-    a.log = c->dlog;
-    return a;
+Launch slot(const Plan &P, int l) {
+    Launch L;
+    L.nf = (int)P.host[l].size();
+    L.host = P.host[l].data();
+    L.dev = P.dtab + P.slot_off[l];
+    L.batched = P.batched;
+    return L;
 }
 
-void enqueue_pyramid(sf_ctx *c, hipStream_t st, const float *const img[4]) {
-    launch_tex_level0(st, img, c->tex + c->lv[0].tex_off, c->W, c->H);
-    for (int l = 1; l < c->L; ++l)
-        launch_downsample(st, c->tex + c->lv[l - 1].tex_off, c->lv[l - 1].W, c->lv[l - 1].H,
-                          c->tex + c->lv[l].tex_off, c->lv[l].W, c->lv[l].H);
+// Uploads per-frame constants (and, for batches, caller buffers) through
+// the pinned staging copy; the previous upload must have landed first.
+sf_status upload(Plan &P, hipStream_t st, const sf_params &prm, const sf_calib *const *cal,
+                 const FrameIO *io) {
+    if (P.stage_pending) {
+        HIP_TRY(hipEventSynchronize(P.stage_ev));
+        P.stage_pending = false;
+    }
+    DevConst *hc = (DevConst *)P.stage;
+    FrameIO *hio = (FrameIO *)(P.stage + ((char *)P.dio - (char *)P.dcst));
+    bool changed = !P.have_inputs;
+    for (int f = 0; f < P.nf; ++f) {
+        DevConst k;
+        fill_const(P.fr[f].L, prm, *cal[f], k);
+        if (memcmp(&k, hc + f, sizeof(k)) != 0) {
+            hc[f] = k;
+            changed = true;
+        }
+        if (io && memcmp(&io[f], hio + f, sizeof(FrameIO)) != 0) {
+            hio[f] = io[f];
+            changed = true;
+        }
+    }
+    if (!changed) return SF_OK;
+    HIP_TRY(hipMemcpyAsync(P.dcst, P.stage, P.stage_bytes, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(P.stage_ev, st));
+    P.stage_pending = true;
+    return SF_OK;
 }
 
-void enqueue_level_init(sf_ctx *c, hipStream_t st, int l) {
-    const LevelArgs a = level_args(c, l);
-    const bool coarsest = (l == c->L - 1);
-    launch_level_init(st, a, coarsest ? nullptr : &c->lv[l + 1], coarsest);
+// ---- the level loop ----------------------------------------------------------
+
+void enqueue_pyramid(const Plan &P, hipStream_t st, const float *const img[4]) {
+    launch_tex_level0(st, slot(P, 0), img);
+    for (int l = 1; l < P.Lmax; ++l) launch_downsample(st, slot(P, l));
 }
 
-void enqueue_linearize(sf_ctx *c, hipStream_t st, int l) {
-    const LevelArgs a = level_args(c, l);
-    launch_linearize(st, a);
-    launch_rhs(st, a, c->tile);
+void enqueue_linearize(const Plan &P, hipStream_t st, int l) {
+    const Launch L = slot(P, l);
+    launch_linearize(st, L);
+    launch_rhs(st, L, P.tile);
 }
 
-void enqueue_pcg(sf_ctx *c, hipStream_t st, int l, int log_index) {
-    const LevelArgs a = level_args(c, l);
-    const int n = c->prm.pcg_iters;
-    launch_pcg_first(st, a, c->tile);
-    for (int i = 1; i < n; ++i) launch_pcg_iter(st, a, c->tile, i, log_index, 0);
-    launch_pcg_last(st, a, c->tile, n, log_index, 0);
+void enqueue_pcg(const Plan &P, hipStream_t st, int l, int gn) {
+    const Launch L = slot(P, l);
+    const int n = P.prm.pcg_iters;
+    launch_pcg_first(st, L, P.tile);
+    for (int i = 1; i < n; ++i) launch_pcg_iter(st, L, P.tile, i, gn, 0);
+    launch_pcg_last(st, L, P.tile, n, gn, 0);
 }
 
-void enqueue_gn(sf_ctx *c, hipStream_t st, int l, int g, int log_index) {
-    enqueue_linearize(c, st, l);
-    enqueue_pcg(c, st, l, log_index);
-    const LevelArgs a = level_args(c, l);
-    const int T = c->prm.max_backtracks + 1;
-    for (int j = 0; j < T; ++j) launch_trial(st, a, j, ldexpf(1.f, -j));
-    launch_accept(st, a, c->tile, T, log_index, g, c->prm.pcg_iters);
+void enqueue_gn(const Plan &P, hipStream_t st, int l, int g, bool log) {
+    enqueue_linearize(P, st, l);
+    enqueue_pcg(P, st, l, log ? g : -1);
+    const Launch L = slot(P, l);
+    const int T = P.prm.max_backtracks + 1;
+    for (int j = 0; j < T; ++j) launch_trial(st, L, j, ldexpf(1.f, -j));
+    launch_accept(st, L, T, log ? g : -1, P.prm.pcg_iters);
 }
 
-void enqueue_levels(sf_ctx *c, hipStream_t st) {
-    int log_index = 0;
-    for (int l = c->L - 1; l >= 0; --l) {
-        enqueue_level_init(c, st, l);
-        for (int g = 0; g < c->prm.gn_iters; ++g) enqueue_gn(c, st, l, g, log_index++);
-        launch_finish_level(st, level_args(c, l));
+void enqueue_levels(const Plan &P, hipStream_t st) {
+    for (int l = P.Lmax - 1; l >= 0; --l) {
+        launch_level_init(st, slot(P, l));
+        for (int g = 0; g < P.prm.gn_iters; ++g) enqueue_gn(P, st, l, g, true);
+        launch_finish_level(st, slot(P, l));
     }
 }
 
-sf_status check_calib(const sf_calib *cal) {
-    if (!cal) return SF_ERR_INVALID_ARG;
-    const float v[] = {cal->fx, cal->fy, cal->cx, cal->cy, cal->baseline};
-    for (float x : v)
-        if (!isfinite(x)) return SF_ERR_INVALID_ARG;
-    if (!(cal->fx > 0.f) || !(cal->fy > 0.f) || !(cal->baseline > 0.f)) return SF_ERR_INVALID_ARG;
-    for (int i = 0; i < 9; ++i)
-        if (!isfinite(cal->F[i])) return SF_ERR_INVALID_ARG;
+// Everything after the inputs are staged: single frames replay the level
+// loop (pyramid and output take the caller's pointers as arguments);
+// batches also run pyramid and output inside the graph, reading the
+// caller's pointers from the uploaded table.
+void enqueue_body(const Plan &P, hipStream_t st) {
+    if (P.batched) enqueue_pyramid(P, st, nullptr);
+    enqueue_levels(P, st);
+    if (P.batched) launch_output(st, slot(P, 0), nullptr, nullptr, nullptr);
+}
+
+sf_status ensure_graph(Plan &P, hipStream_t cap) {
+    if (P.gexec) return SF_OK;
+    HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    enqueue_body(P, cap);
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamEndCapture(cap, &g));
+    if (!g) return SF_ERR_HIP;
+    hipGraphExec_t e = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        note_hip_error("hipGraphInstantiate", ie);
+        (void)hipGraphDestroy(g);
+        return SF_ERR_HIP;
+    }
+    P.graph = g;
+    P.gexec = e;
+    return SF_OK;
+}
+
+sf_status run_body(sf_ctx *c, Plan &P) {
+    if (P.prm.exec_mode == 0) {
+        sf_status s = ensure_graph(P, c->cap_stream);
+        if (s != SF_OK) return s;
+        HIP_TRY(hipGraphLaunch(P.gexec, c->stream));
+    } else {
+        enqueue_body(P, c->stream);
+    }
     return SF_OK;
 }
 
@@ -205,48 +458,89 @@ sf_status prepare_frame(sf_ctx *c, const float *const img[4], const sf_calib *ca
         if (s != SF_OK) return s;
         if (!same_schedule(*p, c->prm)) return SF_ERR_STATE;
         c->prm = *p;
+        c->single.prm = *p;
     }
     HIP_TRY(hipSetDevice(c->device));
-    s = upload_const(c, c->prm, *cal);
+    const sf_calib *cals[1] = {cal};
+    s = upload(c->single, c->stream, c->prm, cals, nullptr);
     if (s != SF_OK) return s;
-    enqueue_pyramid(c, c->stream, img);
-    c->have_images = true;
+    enqueue_pyramid(c->single, c->stream, img);
+    c->single.have_inputs = true;
     return SF_OK;
 }
 
-sf_status ensure_graph(sf_ctx *c) {
-    if (c->gexec) return SF_OK;
-    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    enqueue_levels(c, c->cap_stream);
-    hipGraph_t g = nullptr;
-    if (hipStreamEndCapture(c->cap_stream, &g) != hipSuccess || !g) return SF_ERR_HIP;
-    hipGraphExec_t e = nullptr;
-    if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
-        (void)hipGraphDestroy(g);
+sf_status copy_log(hipStream_t st, const FrameBuf &F, sf_iter_log *out, int cap,
+                   int *n_written) {
+    HIP_TRY(hipStreamSynchronize(st));
+    const int n = cap < F.nlog ? cap : F.nlog;
+    std::vector<DevLog> tmp(F.nlog > 0 ? F.nlog : 1);
+    HIP_TRY(hipMemcpy(tmp.data(), F.log, sizeof(DevLog) * F.nlog, hipMemcpyDeviceToHost));
+    bool bad = false;
+    for (int i = 0; i < n; ++i) {
+        sf_iter_log &o = out[i];
+        const DevLog &d = tmp[i];
+        o.level = d.level;
+        o.gn_iter = d.gn_iter;
+        o.energy = d.energy;
+        o.e_photo = d.e_photo;
+        o.e_grad = d.e_grad;
+        o.e_smooth = d.e_smooth;
+        o.e_epi = d.e_epi;
+        o.e_mag = d.e_mag;
+        o.energy_after = d.energy_after;
+        o.tau = d.tau;
+        o.pcg_iters = d.pcg_iters;
+        for (int k = 0; k < 64; ++k) o.pcg_res[k] = k < SF_MAX_PCG ? d.pcg_res[k] : 0.f;
+        o.n_valid = d.n_valid;
+        if (!isfinite(d.energy) || !isfinite(d.energy_after)) bad = true;
+    }
+    *n_written = n;
+    return bad ? SF_ERR_NUMERIC : SF_OK;
+}
+
+sf_status time_kernel(hipStream_t st, const Plan &P, int kernel, int level, int reps,
+                      float *avg_ms) {
+    const Launch L = slot(P, level);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
         return SF_ERR_HIP;
     }
-    c->graph = g;
-    c->gexec = e;
-    return SF_OK;
+    sf_status s = SF_OK;
+    auto one = [&](int i) {
+        switch (kernel) {
+            case SF_KERNEL_APPLY: launch_pcg_iter(st, L, P.tile, 2 + (i & 1), -1, 1); break;
+            case SF_KERNEL_LINEARIZE: launch_linearize(st, L); break;
+            case SF_KERNEL_UPDATE: launch_pcg_last(st, L, P.tile, 2 + (i & 1), -1, 1); break;
+            case SF_KERNEL_RHS: launch_rhs(st, L, P.tile); break;
+        }
+    };
+    if (kernel < SF_KERNEL_APPLY || kernel > SF_KERNEL_RHS) {
+        s = SF_ERR_INVALID_ARG;
+    } else {
+        // the PCG kernels are forced active with fixed step lengths so that
+        // every launch does the full work; the state is scratch afterwards
+        one(0);  // warm-up
+        if (hipEventRecord(e0, st) != hipSuccess) s = SF_ERR_HIP;
+        for (int i = 0; i < reps && s == SF_OK; ++i) one(i);
+        if (s == SF_OK && hipEventRecord(e1, st) != hipSuccess) s = SF_ERR_HIP;
+        if (s == SF_OK && hipGetLastError() != hipSuccess) s = SF_ERR_HIP;
+        if (s == SF_OK && hipEventSynchronize(e1) != hipSuccess) s = SF_ERR_HIP;
+        float ms = 0.f;
+        if (s == SF_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) s = SF_ERR_HIP;
+        if (s == SF_OK) *avg_ms = ms / (float)reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return s;
 }
 
-void free_all(sf_ctx *c) {
-    // best-effort release: errors here cannot be reported to anyone
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
-    (void)hipFree(c->tex);
-    (void)hipFree(c->cmask);
-    (void)hipFree(c->wnode);
-    (void)hipFree(c->reg);
-    (void)hipFree(c->nodes);
-    (void)hipFree(c->rec);
-    (void)hipFree(c->partials);
-    (void)hipFree(c->dconst);
-    (void)hipFree(c->sc);
-    (void)hipFree(c->dlog);
-    if (c->hconst) (void)hipHostFree(c->hconst);
-    if (c->const_ev) (void)hipEventDestroy(c->const_ev);
-    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+int batch_levels(int W, int H, int max_levels) {
+    int L = 1;
+    while (L < max_levels && (W >> L) >= 40) ++L;
+    while (L > 1 && ((W >> (L - 1)) < 8 || (H >> (L - 1)) < 8)) --L;
+    return L;
 }
 
 }  // namespace
@@ -289,82 +583,27 @@ sf_status sf_create(sf_ctx **out, int width, int height, const sf_params *p,
     sf_status s = check_params(p);
     if (s != SF_OK) return s;
     if (width < 8 || height < 8) return SF_ERR_SIZE;
+    // every level must be at least 8 x 8
+    if ((width >> (p->levels - 1)) < 8 || (height >> (p->levels - 1)) < 8) return SF_ERR_SIZE;
     sf_ctx *c = new (std::nothrow) sf_ctx();
     if (!c) return SF_ERR_OOM;
     c->W = width;
     c->H = height;
     c->prm = *p;
     c->stream = (hipStream_t)hip_stream;
-    c->L = p->levels;
-    const int st = p->grid_stride;
-    long tex_off = 0;
-    for (int l = 0; l < c->L; ++l) {
-        LevelDims &d = c->lv[l];
-        d.W = width >> l;
-        d.H = height >> l;
-        if (d.W < 8 || d.H < 8) {
-            delete c;
-            return SF_ERR_SIZE;
-        }
-        d.Gx = (d.W + st - 1) / st;
-        d.Gy = (d.H + st - 1) / st;
-        d.N = d.W * d.H;
-        d.G = d.Gx * d.Gy;
-        d.tex_off = tex_off;
-        tex_off += 4L * d.N;
-    }
-    c->tile = pick_tile(st);
-    c->N0 = c->lv[0].N;
-    c->G0 = c->lv[0].G;
-    int mb = 1;
-    for (int l = 0; l < c->L; ++l) {
-        const LevelDims &d = c->lv[l];
-        mb = mb > energy_blocks(d) ? mb : energy_blocks(d);
-        mb = mb > node_tile_blocks(d, c->tile) ? mb : node_tile_blocks(d, c->tile);
-        const int gb = (d.G + SF_BLOCK - 1) / SF_BLOCK;
-        mb = mb > gb ? mb : gb;
-    }
-    c->max_blocks = mb;
-    if (node_tile_lds_bytes(c->tile, st, 12) > 64 * 1024 ||
-        node_tile_lds_bytes(c->tile, st, 6) > 64 * 1024 ||
-        tile_max_pixels(c->tile, st) > tile_ppt(st) * tile_threads(st)) {
-        delete c;
-        return SF_ERR_INVALID_ARG;
-    }
-    c->nlog = c->L * p->gn_iters;
-    if (hipGetDevice(&c->device) != hipSuccess) {
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        note_hip_error("sf_create: device / capture stream", e);
         delete c;
         return SF_ERR_HIP;
     }
-    bool ok = true;
-    ok = ok && hipMalloc(&c->tex, sizeof(float4) * tex_off) == hipSuccess;
-    ok = ok && hipMalloc(&c->cmask, c->N0) == hipSuccess;
-    ok = ok && hipMalloc(&c->wnode, sizeof(float) * c->G0) == hipSuccess;
-    ok = ok && hipMalloc(&c->reg, sizeof(float) * 16 * c->G0) == hipSuccess;
-    ok = ok && hipMalloc(&c->nodes, sizeof(float) * NV_COUNT * 6 * c->G0) == hipSuccess;
-    ok = ok && hipMalloc(&c->rec, sizeof(float) * SF_REC_PLANES * c->N0) == hipSuccess;
-    ok = ok && hipMalloc(&c->partials, sizeof(float) * PS_COUNT * (size_t)mb) == hipSuccess;
-    ok = ok && hipMalloc(&c->dconst, sizeof(DevConst)) == hipSuccess;
-    ok = ok && hipMalloc(&c->sc, sizeof(DevScalars)) == hipSuccess;
-    ok = ok && hipMalloc(&c->dlog, sizeof(DevLog) * c->nlog) == hipSuccess;
-    ok = ok && hipHostMalloc(&c->hconst, sizeof(DevConst), hipHostMallocDefault) == hipSuccess;
-    if (!ok) {
-        free_all(c);
+    s = build_plan(c->single, *p, {width, height}, {p->levels}, false);
+    if (s != SF_OK) {
+        free_plan(c->single);
+        (void)hipStreamDestroy(c->cap_stream);
         delete c;
-        return SF_ERR_OOM;
-    }
-    memset(c->hconst, 0, sizeof(DevConst));
-    ok = ok && hipEventCreateWithFlags(&c->const_ev, hipEventDisableTiming) == hipSuccess;
-    ok = ok && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
-    ok = ok && hipMemset(c->sc, 0, sizeof(DevScalars)) == hipSuccess;
-    ok = ok && hipMemset(c->dlog, 0, sizeof(DevLog) * c->nlog) == hipSuccess;
-    ok = ok && hipMemset(c->nodes, 0, sizeof(float) * NV_COUNT * 6 * c->G0) == hipSuccess;
-    ok = ok && hipMemset(c->rec, 0, sizeof(float) * SF_REC_PLANES * c->N0) == hipSuccess;
-    ok = ok && hipDeviceSynchronize() == hipSuccess;
-    if (!ok) {
-        free_all(c);
-        delete c;
-        return SF_ERR_HIP;
+        return s;
     }
     *out = c;
     return SF_OK;
@@ -378,51 +617,87 @@ sf_status sf_solve(sf_ctx *c, const float *I_left_t, const float *I_right_t,
     const float *img[4] = {I_left_t, I_right_t, I_left_t1, I_right_t1};
     sf_status s = prepare_frame(c, img, calib, p);
     if (s != SF_OK) return s;
-    if (c->prm.exec_mode == 0) {
-        s = ensure_graph(c);
+    s = run_body(c, c->single);
+    if (s != SF_OK) return s;
+    launch_output(c->stream, slot(c->single, 0), depth, flow3d, flows);
+    HIP_TRY(hipGetLastError());
+    return SF_OK;
+}
+
+int sf_batch_levels(int width, int height, int max_levels) {
+    if (width < 8 || height < 8 || max_levels < 1) return 0;
+    return batch_levels(width, height, max_levels < SF_MAX_LEVELS ? max_levels : SF_MAX_LEVELS);
+}
+
+sf_status sf_solve_batch(sf_ctx *c, int n, const sf_frame *frames, const sf_params *p) {
+    if (!c || !frames || n < 1 || n > SF_MAX_BATCH) return SF_ERR_INVALID_ARG;
+    const sf_params prm = p ? *p : c->prm;
+    sf_status s = check_params(&prm);
+    if (s != SF_OK) return s;
+    std::vector<int> shape(2 * n), levels(n);
+    std::vector<const sf_calib *> cals(n);
+    std::vector<FrameIO> io(n);
+    for (int f = 0; f < n; ++f) {
+        const sf_frame &F = frames[f];
+        for (int k = 0; k < 4; ++k)
+            if (!F.img[k]) return SF_ERR_INVALID_ARG;
+        if (!F.depth || !F.flow3d) return SF_ERR_INVALID_ARG;
+        if (F.width < 16 || F.height < 16) return SF_ERR_SIZE;
+        s = check_calib(&F.calib);
         if (s != SF_OK) return s;
-        HIP_TRY(hipGraphLaunch(c->gexec, c->stream));
-    } else {
-        enqueue_levels(c, c->stream);
+        shape[2 * f] = F.width;
+        shape[2 * f + 1] = F.height;
+        levels[f] = batch_levels(F.width, F.height, prm.levels);
+        cals[f] = &F.calib;
+        for (int k = 0; k < 4; ++k) io[f].img[k] = F.img[k];
+        io[f].depth = F.depth;
+        io[f].flow3d = F.flow3d;
+        io[f].flows = F.flows;
     }
-    launch_output(c->stream, level_args(c, 0), depth, flow3d, flows);
+    HIP_TRY(hipSetDevice(c->device));
+    Plan *P = c->batch;
+    if (P && (P->shape != shape || !same_schedule(P->prm, prm) ||
+              P->prm.exec_mode != prm.exec_mode)) {
+        // a different batch shape: the old workspace may still be in use
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        free_plan(*P);
+        delete P;
+        c->batch = P = nullptr;
+    }
+    if (!P) {
+        P = new (std::nothrow) Plan();
+        if (!P) return SF_ERR_OOM;
+        s = build_plan(*P, prm, shape, levels, true);
+        if (s != SF_OK) {
+            free_plan(*P);
+            delete P;
+            return s;
+        }
+        c->batch = P;
+    }
+    P->prm = prm;
+    s = upload(*P, c->stream, prm, cals.data(), io.data());
+    if (s != SF_OK) return s;
+    P->have_inputs = true;
+    s = run_body(c, *P);
+    if (s != SF_OK) return s;
     HIP_TRY(hipGetLastError());
     return SF_OK;
 }
 
 sf_status sf_get_log(sf_ctx *c, sf_iter_log *out, int cap, int *n_written) {
     if (!c || !n_written || (cap > 0 && !out) || cap < 0) return SF_ERR_INVALID_ARG;
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    const int n = cap < c->nlog ? cap : c->nlog;
-    DevLog *tmp = new (std::nothrow) DevLog[c->nlog > 0 ? c->nlog : 1];
-    if (!tmp) return SF_ERR_OOM;
-    if (hipMemcpy(tmp, c->dlog, sizeof(DevLog) * c->nlog, hipMemcpyDeviceToHost) != hipSuccess) {
-        delete[] tmp;
-        return SF_ERR_HIP;
-    }
-    bool bad = false;
-    for (int i = 0; i < n; ++i) {
-        sf_iter_log &o = out[i];
-        const DevLog &d = tmp[i];
-        o.level = d.level;
-        o.gn_iter = d.gn_iter;
-        o.energy = d.energy;
-        o.e_photo = d.e_photo;
-        o.e_grad = d.e_grad;
-        o.e_smooth = d.e_smooth;
-        o.e_epi = d.e_epi;
-        o.e_mag = d.e_mag;
-        o.energy_after = d.energy_after;
-        o.tau = d.tau;
-        o.pcg_iters = d.pcg_iters;
-        for (int k = 0; k < 64; ++k) o.pcg_res[k] = k < SF_MAX_PCG ? d.pcg_res[k] : 0.f;
-        o.n_valid = d.n_valid;
-        if (!isfinite(d.energy) || !isfinite(d.energy_after)) bad = true;
-    }
-    delete[] tmp;
-    *n_written = n;
-    return bad ? SF_ERR_NUMERIC : SF_OK;
+    return copy_log(c->stream, c->single.fr[0], out, cap, n_written);
 }
+
+sf_status sf_get_batch_log(sf_ctx *c, int frame, sf_iter_log *out, int cap, int *n_written) {
+    if (!c || !n_written || (cap > 0 && !out) || cap < 0) return SF_ERR_INVALID_ARG;
+    if (!c->batch || !c->batch->have_inputs) return SF_ERR_STATE;
+    if (frame < 0 || frame >= c->batch->nf) return SF_ERR_INVALID_ARG;
+    return copy_log(c->stream, c->batch->fr[frame], out, cap, n_written);
+}
+
+const char *sf_last_error(void) { return g_err; }
 
 const char *sf_status_string(sf_status s) {
     switch (s) {
@@ -440,15 +715,20 @@ const char *sf_status_string(sf_status s) {
 void sf_destroy(sf_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
-    free_all(c);
+    if (c->batch) {
+        free_plan(*c->batch);
+        delete c->batch;
+    }
+    free_plan(c->single);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
 }
 
 // ---- test support ---------------------------------------------------------
 
 size_t sf_debug_size(sf_ctx *c, int what, int level) {
-    if (!c || level < 0 || level >= c->L) return 0;
-    const LevelDims &d = c->lv[level];
+    if (!c || level < 0 || level >= c->single.fr[0].L) return 0;
+    const LevelDims &d = c->single.fr[0].lv[level];
     switch (what) {
         case SF_DBG_TEX: return sizeof(float4) * 4 * (size_t)d.N;
         case SF_DBG_CMASK: return (size_t)d.N;
@@ -462,7 +742,7 @@ size_t sf_debug_size(sf_ctx *c, int what, int level) {
     return 0;
 }
 
-static int node_vec_of(sf_ctx *, int what) {
+static int node_vec_of(int what) {
     switch (what) {
         case SF_DBG_BASE: return NV_BASE;
         case SF_DBG_DELTA: return NV_DELTA;
@@ -483,7 +763,8 @@ static sf_status debug_copy(sf_ctx *c, int what, int level, void *host, size_t b
     if (need == 0) return SF_ERR_INVALID_ARG;
     if (bytes != need) return SF_ERR_SIZE;
     HIP_TRY(hipStreamSynchronize(c->stream));
-    const LevelDims &d = c->lv[level];
+    const FrameBuf &F = c->single.fr[0];
+    const LevelDims &d = F.lv[level];
     const hipMemcpyKind kind = to_device ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
     char *h = (char *)host;
     auto cp = [&](void *dev, size_t off, size_t n) -> bool {
@@ -492,24 +773,24 @@ static sf_status debug_copy(sf_ctx *c, int what, int level, void *host, size_t b
     };
     bool ok = true;
     switch (what) {
-        case SF_DBG_TEX: ok = cp(c->tex + d.tex_off, 0, bytes); break;
-        case SF_DBG_CMASK: ok = cp(c->cmask, 0, bytes); break;
-        case SF_DBG_WNODE: ok = cp(c->wnode, 0, bytes); break;
+        case SF_DBG_TEX: ok = cp(F.tex + d.tex_off, 0, bytes); break;
+        case SF_DBG_CMASK: ok = cp(F.cmask, 0, bytes); break;
+        case SF_DBG_WNODE: ok = cp(F.wnode, 0, bytes); break;
         case SF_DBG_REC:
             for (int k = 0; k < SF_REC_PLANES && ok; ++k)
-                ok = cp(c->rec + (size_t)k * c->N0, sizeof(float) * (size_t)k * d.N,
+                ok = cp(F.rec + (size_t)k * F.N0, sizeof(float) * (size_t)k * d.N,
                         sizeof(float) * d.N);
             break;
         case SF_DBG_ENERGY:
             if (to_device) return SF_ERR_INVALID_ARG;
-            ok = cp(&c->sc->e_lin[0], 0, bytes);
+            ok = cp(&F.sc->e_lin[0], 0, bytes);
             break;
         default: {
-            const int v = node_vec_of(c, what);
+            const int v = node_vec_of(what);
             if (v < 0) return SF_ERR_INVALID_ARG;
-            float *base = c->nodes + (size_t)v * 6 * c->G0;
+            float *base = F.nodes + (size_t)v * 6 * F.G0;
             for (int q = 0; q < 6 && ok; ++q)
-                ok = cp(base + (size_t)q * c->G0, sizeof(float) * (size_t)q * d.G,
+                ok = cp(base + (size_t)q * F.G0, sizeof(float) * (size_t)q * d.G,
                         sizeof(float) * d.G);
         }
     }
@@ -537,17 +818,18 @@ sf_status sf_debug_set_images(sf_ctx *c, const float *I_left_t, const float *I_r
 }
 
 sf_status sf_debug_run(sf_ctx *c, int stage, int level) {
-    if (!c || level < 0 || level >= c->L) return SF_ERR_INVALID_ARG;
-    if (!c->have_images) return SF_ERR_STATE;
+    if (!c || level < 0 || level >= c->single.fr[0].L) return SF_ERR_INVALID_ARG;
+    if (!c->single.have_inputs) return SF_ERR_STATE;
     hipStream_t st = c->stream;
-    const LevelArgs a = level_args(c, level);
+    const Plan &P = c->single;
+    const Launch L = slot(P, level);
     switch (stage) {
-        case SF_STAGE_LEVEL_INIT: enqueue_level_init(c, st, level); break;
-        case SF_STAGE_LINEARIZE: enqueue_linearize(c, st, level); break;
-        case SF_STAGE_APPLY: launch_pcg_first(st, a, c->tile); break;
-        case SF_STAGE_PCG: enqueue_pcg(c, st, level, -1); break;
-        case SF_STAGE_GN: enqueue_gn(c, st, level, 0, -1); break;
-        case SF_STAGE_FINISH: launch_finish_level(st, a); break;
+        case SF_STAGE_LEVEL_INIT: launch_level_init(st, L); break;
+        case SF_STAGE_LINEARIZE: enqueue_linearize(P, st, level); break;
+        case SF_STAGE_APPLY: launch_pcg_first(st, L, P.tile); break;
+        case SF_STAGE_PCG: enqueue_pcg(P, st, level, -1); break;
+        case SF_STAGE_GN: enqueue_gn(P, st, level, 0, false); break;
+        case SF_STAGE_FINISH: launch_finish_level(st, L); break;
         default: return SF_ERR_INVALID_ARG;
     }
     HIP_TRY(hipGetLastError());
@@ -556,43 +838,17 @@ sf_status sf_debug_run(sf_ctx *c, int stage, int level) {
 }
 
 sf_status sf_time_kernel(sf_ctx *c, int kernel, int level, int reps, float *avg_ms) {
-    if (!c || !avg_ms || level < 0 || level >= c->L || reps < 1) return SF_ERR_INVALID_ARG;
-    if (!c->have_images) return SF_ERR_STATE;
-    hipStream_t st = c->stream;
-    const LevelArgs a = level_args(c, level);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIP_TRY(hipEventCreate(&e0));
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return SF_ERR_HIP;
-    }
-    sf_status s = SF_OK;
-    auto one = [&](int i) {
-        switch (kernel) {
-            case SF_KERNEL_APPLY: launch_pcg_iter(st, a, c->tile, 2 + (i & 1), -1, 1); break;
-            case SF_KERNEL_LINEARIZE: launch_linearize(st, a); break;
-            case SF_KERNEL_UPDATE: launch_pcg_last(st, a, c->tile, 2 + (i & 1), -1, 1); break;
-            case SF_KERNEL_RHS: launch_rhs(st, a, c->tile); break;
-        }
-    };
-    if (kernel < SF_KERNEL_APPLY || kernel > SF_KERNEL_RHS) {
-        s = SF_ERR_INVALID_ARG;
-    } else {
-        // the PCG kernels are forced active with fixed step lengths so that
-        // every launch does the full work; the state is scratch afterwards
-        one(0);  // warm-up
-        if (hipEventRecord(e0, st) != hipSuccess) s = SF_ERR_HIP;
-        for (int i = 0; i < reps && s == SF_OK; ++i) one(i);
-        if (s == SF_OK && hipEventRecord(e1, st) != hipSuccess) s = SF_ERR_HIP;
-        if (s == SF_OK && hipGetLastError() != hipSuccess) s = SF_ERR_HIP;
-        if (s == SF_OK && hipEventSynchronize(e1) != hipSuccess) s = SF_ERR_HIP;
-        float ms = 0.f;
-        if (s == SF_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) s = SF_ERR_HIP;
-        if (s == SF_OK) *avg_ms = ms / (float)reps;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    return s;
+    if (!c || !avg_ms || level < 0 || level >= c->single.fr[0].L || reps < 1)
+        return SF_ERR_INVALID_ARG;
+    if (!c->single.have_inputs) return SF_ERR_STATE;
+    return time_kernel(c->stream, c->single, kernel, level, reps, avg_ms);
+}
+
+sf_status sf_time_batch_kernel(sf_ctx *c, int kernel, int level, int reps, float *avg_ms) {
+    if (!c || !avg_ms || reps < 1) return SF_ERR_INVALID_ARG;
+    if (!c->batch || !c->batch->have_inputs) return SF_ERR_STATE;
+    if (level < 0 || level >= c->batch->Lmax) return SF_ERR_INVALID_ARG;
+    return time_kernel(c->stream, *c->batch, kernel, level, reps, avg_ms);
 }
 
 }  // extern "C"

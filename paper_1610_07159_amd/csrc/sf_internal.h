@@ -4,12 +4,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "sf.h"
 
 #define SF_MAX_LEVELS 12
 #define SF_MAX_TRIALS 8
 #define SF_MAX_PCG 64
 #define SF_BLOCK 256
+#define SF_MAX_BATCH 64
 
 // Number of per-pixel record planes: 6 gradient components of the pixel's
 // energy w.r.t. its six flow components, then the 21 upper-triangular
@@ -102,13 +105,28 @@ struct TileCfg {
     int tx, ty, tpn;
 };
 
-// Everything a kernel needs about the current level, by value.
+// Caller buffers of one frame of a batch (device pointers, rewritten on
+// every batch call).
+struct FrameIO {
+    const float *img[4];
+    float *depth, *flow3d, *flows;
+};
+
+// Everything a kernel needs about one frame at the current level.  Passed
+// by value for single-frame launches; batched launches read it from a
+// device table (see FrameMap).
 struct LevelArgs {
     LevelDims d;
     int level;
     int s;                 // grid stride
     int N0, G0;            // plane strides of records / node vectors
+    int coarsest;          // this is the frame's coarsest level
+    int Gxc, Gyc;          // node grid of the next coarser level
+    int log_base;          // log slot of this level's first Gauss-Newton step
+    int Wf, Hf;            // size of the next finer level (pyramid)
     const float4 *tex;     // this level's 4 images (image-major)
+    const float4 *tex_fine;  // the next finer level's images
+    const FrameIO *io;     // caller buffers (batched launches)
     float *nodes;          // base of all node vectors
     float *rec;            // per-pixel records
     unsigned char *cmask;  // V(x) W(x)
@@ -121,25 +139,40 @@ struct LevelArgs {
     DevLog *log;
 };
 
-// Kernel launchers (sf_kernels.hip).
-void launch_tex_level0(hipStream_t st, const float *const img[4], float4 *tex,
-                       int W, int H);
-void launch_downsample(hipStream_t st, const float4 *src, int Ws, int Hs,
-                       float4 *dst, int Wd, int Hd);
-void launch_level_init(hipStream_t st, const LevelArgs &a,
-                       const LevelDims *coarse, bool coarsest);
-void launch_linearize(hipStream_t st, const LevelArgs &a);
-void launch_trial(hipStream_t st, const LevelArgs &a, int trial, float tau);
-void launch_rhs(hipStream_t st, const LevelArgs &a, const TileCfg &t);
-void launch_pcg_first(hipStream_t st, const LevelArgs &a, const TileCfg &t);
-void launch_pcg_iter(hipStream_t st, const LevelArgs &a, const TileCfg &t,
-                     int iter, int log_index, int force);
-void launch_pcg_last(hipStream_t st, const LevelArgs &a, const TileCfg &t,
-                     int iter, int log_index, int force);
-void launch_accept(hipStream_t st, const LevelArgs &a, const TileCfg &t,
-                   int n_trials, int log_index, int gn_iter, int pcg_iters);
-void launch_finish_level(hipStream_t st, const LevelArgs &a);
-void launch_output(hipStream_t st, const LevelArgs &a, float *depth,
+// Kernel argument of a launch over several frames: the workgroups of frame
+// f are [first[f], first[f + 1]) and its arguments are tab[f].
+struct FrameMap {
+    const LevelArgs *tab;
+    int nf;
+    int first[SF_MAX_BATCH + 1];
+};
+
+// One launch target: a single frame (arguments by value) or nf frames
+// (host copies for launch geometry, device table for the kernels).
+struct Launch {
+    int nf;
+    const LevelArgs *host;  // nf entries
+    const LevelArgs *dev;   // device table, used when batched
+    bool batched;
+};
+
+// Kernel launchers (sf_kernels.hip).  `gn` is the Gauss-Newton step within
+// the level (log slot log_base + gn), or -1 for no logging.
+void launch_tex_level0(hipStream_t st, const Launch &L, const float *const img[4]);
+void launch_downsample(hipStream_t st, const Launch &L);
+void launch_level_init(hipStream_t st, const Launch &L);
+void launch_linearize(hipStream_t st, const Launch &L);
+void launch_trial(hipStream_t st, const Launch &L, int trial, float tau);
+void launch_rhs(hipStream_t st, const Launch &L, const TileCfg &t);
+void launch_pcg_first(hipStream_t st, const Launch &L, const TileCfg &t);
+void launch_pcg_iter(hipStream_t st, const Launch &L, const TileCfg &t,
+                     int iter, int gn, int force);
+void launch_pcg_last(hipStream_t st, const Launch &L, const TileCfg &t,
+                     int iter, int gn, int force);
+void launch_accept(hipStream_t st, const Launch &L, int n_trials, int gn,
+                   int pcg_iters);
+void launch_finish_level(hipStream_t st, const Launch &L);
+void launch_output(hipStream_t st, const Launch &L, float *depth,
                    float *flow3d, float *flows);
 TileCfg pick_tile(int s);
 int tile_threads(int s);

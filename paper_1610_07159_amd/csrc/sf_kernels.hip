@@ -193,14 +193,13 @@ __device__ double block_sum_partials(const float *part, int n) {
     return r;
 }
 
-// Arrival at a device-wide counter: true in every thread of the last
-// workgroup of the grid to arrive, which then sees all partials.
-__device__ bool last_block(unsigned int *counter) {
+// Arrival at a frame's counter: true in every thread of the last of the
+// frame's `total` workgroups to arrive, which then sees all partials.
+__device__ bool last_block(unsigned int *counter, unsigned int total) {
     __shared__ int s_last;
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
-        const unsigned int total = gridDim.x * gridDim.y * gridDim.z;
         const unsigned int prev = atomicAdd(counter, 1u);
         s_last = (prev == total - 1) ? 1 : 0;
         if (s_last) atomicExch(counter, 0u);
@@ -210,9 +209,35 @@ __device__ bool last_block(unsigned int *counter) {
     return s_last != 0;
 }
 
-__device__ __forceinline__ int block_linear() {
-    return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+// ---- frame binding ---------------------------------------------------------
+//
+// Every kernel exists in a single-frame form, which takes the frame's
+// LevelArgs by value, and a batched form, which takes a FrameMap: the
+// workgroup finds its frame in the map's block prefix (uniform scalar
+// compares), loads that frame's arguments from the device table and works
+// on its block index within the frame.  Per-frame partial sums, counters,
+// scalars and logs keep every reduction segmented by frame.
+template <bool B>
+using KArg = typename std::conditional<B, FrameMap, LevelArgs>::type;
+
+__device__ __forceinline__ void bind(const LevelArgs &ka, LevelArgs &a, int &bid, int &nblk) {
+    a = ka;
+    bid = blockIdx.x;
+    nblk = gridDim.x;
 }
+__device__ __forceinline__ void bind(const FrameMap &m, LevelArgs &a, int &bid, int &nblk) {
+    const int b = blockIdx.x;
+    int f = 0;
+    for (int k = 1; k < m.nf; ++k) f += b >= m.first[k] ? 1 : 0;
+    a = m.tab[f];
+    bid = b - m.first[f];
+    nblk = m.first[f + 1] - m.first[f];
+}
+#define SF_BIND(ka)              \
+    LevelArgs a;                 \
+    int bid, nblk;               \
+    bind(ka, a, bid, nblk);      \
+    (void)nblk
 
 // ---- bilinear sampling of (I, Gx, Gy) ------------------------------------
 
@@ -255,15 +280,24 @@ struct Img4 {
     const float *p[4];
 };
 
+// Pyramid workgroups cover 64 x 4 texels of one image.
+__host__ __device__ inline int tex_blocks_x(int W) { return (W + 63) / 64; }
+__host__ __device__ inline int tex_blocks(int W, int H) { return tex_blocks_x(W) * ((H + 3) / 4) * 4; }
+
 // Level 0: texel = (I, Gx, Gy, 0) with central-difference gradients
-// (one-sided at the borders).
-__global__ __launch_bounds__(SF_BLOCK) void k_tex0(Img4 in, float4 *tex, int W,
-                                                   int H) {
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int c = blockIdx.z;
+// (one-sided at the borders).  Images come from the argument (single
+// frame) or the frame's caller buffers (batched).
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_tex0(KArg<B> ka, Img4 in) {
+    SF_BIND(ka);
+    const int W = a.d.W, H = a.d.H;
+    const int bx = tex_blocks_x(W), per = bx * ((H + 3) / 4);
+    const int c = bid / per, r = bid % per;
+    const int x = (r % bx) * 64 + (threadIdx.x & 63);
+    const int y = (r / bx) * 4 + (threadIdx.x >> 6);
     if (x >= W || y >= H) return;
-    const float *I = in.p[c];
+    float4 *tex = const_cast<float4 *>(a.tex);
+    const float *I = B ? a.io->img[c] : in.p[c];
     const float v = I[y * W + x];
     float gx, gy;
     if (x == 0) gx = I[y * W + 1] - I[y * W];
@@ -285,14 +319,17 @@ __device__ __forceinline__ float box(const float4 *src, int Ws, int x, int y) {
     return 0.25f * (((a + b) + c) + d);
 }
 
-__global__ __launch_bounds__(SF_BLOCK) void k_texl(const float4 *src, int Ws,
-                                                   int Hs, float4 *dst, int W,
-                                                   int H) {
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int c = blockIdx.z;
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_texl(KArg<B> ka) {
+    SF_BIND(ka);
+    const int W = a.d.W, H = a.d.H, Ws = a.Wf, Hs = a.Hf;
+    const int bx = tex_blocks_x(W), per = bx * ((H + 3) / 4);
+    const int c = bid / per, r = bid % per;
+    const int x = (r % bx) * 64 + (threadIdx.x & 63);
+    const int y = (r / bx) * 4 + (threadIdx.x >> 6);
     if (x >= W || y >= H) return;
-    const float4 *S = src + (long)c * Ws * Hs;
+    float4 *dst = const_cast<float4 *>(a.tex);
+    const float4 *S = a.tex_fine + (long)c * Ws * Hs;
     const float v = box(S, Ws, x, y);
     float gx, gy;
     if (x == 0) gx = box(S, Ws, 1, y) - v;
@@ -308,6 +345,23 @@ __global__ __launch_bounds__(SF_BLOCK) void k_texl(const float4 *src, int Ws,
 
 #define TILE_PX 16       // pixel tile edge of the pixel kernels
 #define TILE_NODES 20    // max nodes per axis a pixel tile touches (s >= 1)
+
+// Workgroup counts of one frame's launches.
+__host__ __device__ inline int pixel_tiles(const LevelDims &d) {
+    return ((d.W + TILE_PX - 1) / TILE_PX) * ((d.H + TILE_PX - 1) / TILE_PX);
+}
+__host__ __device__ inline int node_blocks(const LevelDims &d) {
+    return (d.G + SF_BLOCK - 1) / SF_BLOCK;
+}
+__host__ __device__ inline int energy_blocks_of(const LevelDims &d) {
+    return pixel_tiles(d) + node_blocks(d);
+}
+__host__ __device__ inline int tiles_x_of(const LevelDims &d, const TileCfg &t) {
+    return (d.Gx + t.tx - 1) / t.tx;
+}
+__host__ __device__ inline int node_tiles_of(const LevelDims &d, const TileCfg &t) {
+    return tiles_x_of(d, t) * ((d.Gy + t.ty - 1) / t.ty);
+}
 
 // Node totals (base + delta + tau dx) of the nodes a pixel tile touches,
 // staged in LDS.
@@ -508,10 +562,11 @@ __device__ void node_energy(const LevelArgs &a, int n, float tau, float (&part)[
 //        the right-hand-side kernel).
 //  !LIN: trial energy at delta + tau dx, skipped if an earlier trial of this
 //        step was accepted; the last workgroup to finish sums the partials.
-template <bool LIN>
-__global__ __launch_bounds__(SF_BLOCK) void k_energy(LevelArgs a, int trial,
-                                                     float tau, int n_pix) {
+template <bool B, bool LIN>
+__global__ __launch_bounds__(SF_BLOCK) void k_energy(KArg<B> ka, int trial, float tau) {
+    SF_BIND(ka);
     const LevelDims &d = a.d;
+    const int n_pix = pixel_tiles(d);
     if (!LIN) {
         const double e0 = a.sc->e_lin[5];
         for (int k = 0; k < trial; ++k)
@@ -519,7 +574,6 @@ __global__ __launch_bounds__(SF_BLOCK) void k_energy(LevelArgs a, int trial,
     }
     __shared__ NodeStage S;
     float part[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    const int bid = blockIdx.x;
     if (bid < n_pix) {
         const int tiles_x = (d.W + TILE_PX - 1) / TILE_PX;
         const int x0 = (bid % tiles_x) * TILE_PX, y0 = (bid / tiles_x) * TILE_PX;
@@ -549,13 +603,13 @@ __global__ __launch_bounds__(SF_BLOCK) void k_energy(LevelArgs a, int trial,
     }
     float tot5[5];
     block_sum<5>(part, tot5);
-    const int nb = gridDim.x;
+    const int nb = nblk;
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) a.partials[(long)(PS_E + k) * a.max_blocks + bid] = tot5[k];
     }
     if (LIN) return;
-    if (last_block(&a.sc->counter[0])) {
+    if (last_block(&a.sc->counter[0], (unsigned)nblk)) {
         const DevConst &C = *a.cst;
         double s[5];
         for (int k = 0; k < 5; ++k)
@@ -585,11 +639,12 @@ struct TileGeom {
     int RX, RY;
 };
 
-__device__ __forceinline__ TileGeom tile_geom(const LevelArgs &a, const TileCfg &t) {
+__device__ __forceinline__ TileGeom tile_geom(const LevelArgs &a, const TileCfg &t, int bid) {
     TileGeom g;
     const LevelDims &d = a.d;
-    g.i0 = blockIdx.x * t.tx;
-    g.j0 = blockIdx.y * t.ty;
+    const int tx = tiles_x_of(d, t);
+    g.i0 = (bid % tx) * t.tx;
+    g.j0 = (bid / tx) * t.ty;
     g.txa = min(t.tx, d.Gx - g.i0);
     g.tya = min(t.ty, d.Gy - g.j0);
     g.X0 = sup_lo(g.i0, a.s);
@@ -723,12 +778,14 @@ __device__ __forceinline__ void nb_offset(int k, int &di, int &dj) {
 
 // ---- right-hand side and diag(H) (node tiles) ----------------------------
 
-template <int S>
-__global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(LevelArgs a, TileCfg t, int n_lin_blocks) {
+template <bool B, int S>
+__global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(KArg<B> ka, TileCfg t) {
     extern __shared__ float lds[];
+    SF_BIND(ka);
     const LevelDims &d = a.d;
     const DevConst &C = *a.cst;
-    const TileGeom g = tile_geom(a, t);
+    const int n_lin_blocks = energy_blocks_of(d);
+    const TileGeom g = tile_geom(a, t, bid);
     const TileLds L = tile_lds(lds, t, S, 12);
     const int tid = threadIdx.x;
     const int nl = tid / t.tpn, sub = tid % t.tpn;
@@ -758,7 +815,7 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(LevelArgs a, TileCfg 
             for (int q = 0; q < 6; ++q) dn[k][q] = delta[q * G0 + m];
         }
     }
-    if (blockIdx.x == 0 && blockIdx.y == 0) {
+    if (bid == 0) {
         // energy at the linearisation point (partials of the linearise
         // kernel) and the PCG start state
         double es[5];
@@ -864,7 +921,7 @@ __device__ __forceinline__ void load_pcg_partials(const LevelArgs &a, int i, int
 
 // Block-wide fixed-order sum of the per-thread partial sums, then the
 // scalars of iteration i-1 (thread 0 decides, everyone receives).
-__device__ void pcg_decide(const LevelArgs &a, int i, const double (&acc)[3],
+__device__ void pcg_decide(const LevelArgs &a, int bid, int i, const double (&acc)[3],
                            const PcgHist &h, int log_index, int force, float &alpha,
                            float &beta, int &act) {
     __shared__ double red[16][3];
@@ -893,7 +950,7 @@ __device__ void pcg_decide(const LevelArgs &a, int i, const double (&acc)[3],
         s_alpha = al;
         s_beta = be;
         s_act = ok;
-        if (blockIdx.x == 0 && blockIdx.y == 0) {
+        if (bid == 0) {
             PcgHist o;
             o.gamma = gam; o.alpha = al; o.beta = be; o.active = ok; o.pad = 0;
             a.sc->hist[i] = o;
@@ -908,9 +965,8 @@ __device__ void pcg_decide(const LevelArgs &a, int i, const double (&acc)[3],
 
 // Copies this workgroup's partials to the next slot (inactive iteration:
 // r and u are unchanged).
-__device__ void carry_partials(const LevelArgs &a, int i) {
+__device__ void carry_partials(const LevelArgs &a, int bid, int i) {
     if (threadIdx.x < 3) {
-        const int bid = block_linear();
         const long src = (long)(((i - 1) & 1) ? PS_PCG1 : PS_PCG0) * a.max_blocks;
         const long dst = (long)((i & 1) ? PS_PCG1 : PS_PCG0) * a.max_blocks;
         a.partials[dst + (long)threadIdx.x * a.max_blocks + bid] =
@@ -921,15 +977,18 @@ __device__ void carry_partials(const LevelArgs &a, int i) {
 // Every load of an iteration that does not depend on its scalars is issued
 // before the partial sums are reduced, and constants are read once, so the
 // workgroup waits for memory about once.
-template <bool FIRST, int S>
-__global__ __launch_bounds__(TileTraits<S>::NT) void k_pcg(LevelArgs a, TileCfg t, int i,
-                                                           int log_index, int force, int nb_prev) {
+template <bool B, bool FIRST, int S>
+__global__ __launch_bounds__(TileTraits<S>::NT) void k_pcg(KArg<B> ka, TileCfg t, int i,
+                                                           int gn, int force) {
     constexpr int NT_TILE = TileTraits<S>::NT;
     constexpr int PPT = TileTraits<S>::PPT;
     extern __shared__ float lds[];
+    SF_BIND(ka);
+    const int nb_prev = nblk;  // the previous iteration ran on the same tiles
+    const int log_index = gn >= 0 ? a.log_base + gn : -1;
     const LevelDims &d = a.d;
     const long G0 = a.G0;
-    const TileGeom g = tile_geom(a, t);
+    const TileGeom g = tile_geom(a, t, bid);
     const TileLds L = tile_lds(lds, t, S, 6);
     const int tid = threadIdx.x;
     const float *Rp = a.nodes + (long)(((i - 1) & 1) ? NV_R1 : NV_R0) * 6 * G0;
@@ -1015,9 +1074,9 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_pcg(LevelArgs a, TileCfg 
     float alpha = 0.f, beta = 0.f;
     int act = 1;
     if (!FIRST) {
-        pcg_decide(a, i, pacc, h, log_index, force, alpha, beta, act);
+        pcg_decide(a, bid, i, pacc, h, log_index, force, alpha, beta, act);
         if (!act) {
-            carry_partials(a, i);
+            carry_partials(a, bid, i);
             return;
         }
     }
@@ -1143,15 +1202,17 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_pcg(LevelArgs a, TileCfg 
     }
     if (tid == 0) {
         const long dst = (long)((i & 1) ? PS_PCG1 : PS_PCG0) * a.max_blocks;
-        const int bid = block_linear();
         for (int k = 0; k < 3; ++k) a.partials[dst + (long)k * a.max_blocks + bid] = tot3[k];
     }
 }
 
 // Applies iteration n-1 (no H-product) and leaves ||r_n||^2 partials.
-__global__ __launch_bounds__(SF_BLOCK) void k_pcg_last(LevelArgs a, int n_it,
-                                                       int nb_prev, int log_index,
-                                                       int force) {
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_pcg_last(KArg<B> ka, TileCfg t, int n_it,
+                                                       int gn, int force) {
+    SF_BIND(ka);
+    const int nb_prev = node_tiles_of(a.d, t);
+    const int log_index = gn >= 0 ? a.log_base + gn : -1;
     const long G0 = a.G0;
     const int i = n_it;
     const float *Rp = a.nodes + (long)(((i - 1) & 1) ? NV_R1 : NV_R0) * 6 * G0;
@@ -1161,7 +1222,7 @@ __global__ __launch_bounds__(SF_BLOCK) void k_pcg_last(LevelArgs a, int n_it,
     const float *U = a.nodes + (long)NV_U * 6 * G0;
     float *P = a.nodes + (long)NV_P * 6 * G0;
     float *X = a.nodes + (long)NV_X * 6 * G0;
-    const long n = (long)blockIdx.x * SF_BLOCK + threadIdx.x;
+    const long n = (long)bid * SF_BLOCK + threadIdx.x;
     const bool in = n < a.d.G;
     double pacc[3];
     load_pcg_partials(a, i, nb_prev, pacc);
@@ -1180,7 +1241,7 @@ __global__ __launch_bounds__(SF_BLOCK) void k_pcg_last(LevelArgs a, int n_it,
     }
     float alpha, beta;
     int act;
-    pcg_decide(a, i, pacc, h, log_index, force, alpha, beta, act);
+    pcg_decide(a, bid, i, pacc, h, log_index, force, alpha, beta, act);
     float prt[1] = {0.f};
     if (in) {
 #pragma unroll
@@ -1201,14 +1262,17 @@ __global__ __launch_bounds__(SF_BLOCK) void k_pcg_last(LevelArgs a, int n_it,
     float tot1[1];
     block_sum<1>(prt, tot1);
     if (threadIdx.x == 0)
-        a.partials[(long)(((i & 1) ? PS_PCG1 : PS_PCG0) + 2) * a.max_blocks + blockIdx.x] = tot1[0];
+        a.partials[(long)(((i & 1) ? PS_PCG1 : PS_PCG0) + 2) * a.max_blocks + bid] = tot1[0];
 }
 
 // ---- step control: accept the first tau with E_trial <= E ------------------
 
-__global__ __launch_bounds__(SF_BLOCK) void k_accept(LevelArgs a, int n_trials,
-                                                     int log_index, int gn_iter,
-                                                     int pcg_iters, int nb_last) {
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_accept(KArg<B> ka, int n_trials, int gn_iter,
+                                                     int pcg_iters) {
+    SF_BIND(ka);
+    const int log_index = gn_iter >= 0 ? a.log_base + gn_iter : -1;
+    const int nb_last = node_blocks(a.d);
     const DevScalars *sc = a.sc;
     const double e0 = sc->e_lin[5];
     int kacc = -1;
@@ -1216,14 +1280,14 @@ __global__ __launch_bounds__(SF_BLOCK) void k_accept(LevelArgs a, int n_trials,
         if (sc->e_trial[k][5] <= e0) { kacc = k; break; }
     const float tau = kacc >= 0 ? ldexpf(1.f, -kacc) : 0.f;
     const long G0 = a.G0;
-    const long n = (long)blockIdx.x * SF_BLOCK + threadIdx.x;
+    const long n = (long)bid * SF_BLOCK + threadIdx.x;
     if (kacc >= 0 && n < a.d.G) {
         float *delta = a.nodes + (long)NV_DELTA * 6 * G0;
         const float *X = a.nodes + (long)NV_X * 6 * G0;
 #pragma unroll
         for (int q = 0; q < 6; ++q) delta[q * G0 + n] = delta[q * G0 + n] + tau * X[q * G0 + n];
     }
-    if (blockIdx.x == 0 && log_index >= 0) {
+    if (bid == 0 && log_index >= 0) {
         const float *rrp = a.partials +
                            (long)(((pcg_iters & 1) ? PS_PCG1 : PS_PCG0) + 2) * a.max_blocks;
         const double rr = block_sum_partials(rrp, nb_last);
@@ -1252,9 +1316,11 @@ __global__ __launch_bounds__(SF_BLOCK) void k_accept(LevelArgs a, int n_trials,
 
 // base_l = 2 bilerp(total_{l+1}) at coarse-node coordinate i/2 - 1/4
 // (Sec. 5.3), or zero at the coarsest level; delta = 0.
-__global__ __launch_bounds__(SF_BLOCK) void k_prolong(LevelArgs a, int Gxc, int Gyc,
-                                                      int coarsest) {
-    const long n = (long)blockIdx.x * SF_BLOCK + threadIdx.x;
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_prolong(KArg<B> ka) {
+    SF_BIND(ka);
+    const int Gxc = a.Gxc, Gyc = a.Gyc, coarsest = a.coarsest;
+    const long n = (long)bid * SF_BLOCK + threadIdx.x;
     if (n >= a.d.G) return;
     const long G0 = a.G0;
     float *base = a.nodes + (long)NV_BASE * 6 * G0;
@@ -1280,12 +1346,13 @@ __global__ __launch_bounds__(SF_BLOCK) void k_prolong(LevelArgs a, int Gxc, int 
 // V(x): all four positions inside the level image; W(x): max_k |d_k| <
 // eps_p (Sec. 4.1); both at the level-start flow.  Also stores the mean of
 // the four warped images for the smoothness weights.
-__global__ __launch_bounds__(SF_BLOCK) void k_masks(LevelArgs a) {
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_masks(KArg<B> ka) {
+    SF_BIND(ka);
     const LevelDims &d = a.d;
     const DevConst &C = *a.cst;
     __shared__ NodeStage S;
     const int tiles_x = (d.W + TILE_PX - 1) / TILE_PX;
-    const int bid = blockIdx.x;
     const int x0 = (bid % tiles_x) * TILE_PX, y0 = (bid / tiles_x) * TILE_PX;
     stage_nodes(a, x0, y0, 0.f, S);
     __syncthreads();
@@ -1322,20 +1389,23 @@ __global__ __launch_bounds__(SF_BLOCK) void k_masks(LevelArgs a) {
 
 // w_i = 1 + gamma exp(-lambda_min / tau_l) of the structure tensor of the
 // mean warped image over a 3x3 window at the node's rounded position.
-__global__ __launch_bounds__(SF_BLOCK) void k_node_weights(LevelArgs a, int n_mask_blocks) {
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_node_weights(KArg<B> ka) {
+    SF_BIND(ka);
     const LevelDims &d = a.d;
-    if (blockIdx.x == 0) {
+    const int n_mask_blocks = pixel_tiles(d);
+    if (bid == 0) {
         const double c = block_sum_partials(a.partials + (long)PS_MASK * a.max_blocks, n_mask_blocks);
         if (threadIdx.x == 0) a.sc->n_valid = (int)c;
     }
-    const long n = (long)blockIdx.x * SF_BLOCK + threadIdx.x;
+    const long n = (long)bid * SF_BLOCK + threadIdx.x;
     if (n >= d.G) return;
     const DevConst &C = *a.cst;
     const int i = (int)(n % d.Gx), j = (int)(n / d.Gx);
     const float *Ib = a.rec;
     const int cx = min(((2 * i + 1) * a.s) / 2, d.W - 1);
     const int cy = min(((2 * j + 1) * a.s) / 2, d.H - 1);
-    float A = 0.f, B = 0.f, Cc = 0.f;
+    float A = 0.f, Bt = 0.f, Cc = 0.f;
     for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
             const int xx = min(max(cx + dx, 0), d.W - 1);
@@ -1348,17 +1418,19 @@ __global__ __launch_bounds__(SF_BLOCK) void k_node_weights(LevelArgs a, int n_ma
             else if (yy == d.H - 1) gy = Ib[yy * d.W + xx] - Ib[(yy - 1) * d.W + xx];
             else gy = 0.5f * (Ib[(yy + 1) * d.W + xx] - Ib[(yy - 1) * d.W + xx]);
             A += gx * gx;
-            B += gx * gy;
+            Bt += gx * gy;
             Cc += gy * gy;
         }
     const float h = 0.5f * (A - Cc);
-    const float lmin = 0.5f * (A + Cc) - sqrtf(h * h + B * B);
+    const float lmin = 0.5f * (A + Cc) - sqrtf(h * h + Bt * Bt);
     const float tau = C.st_tau * ldexpf(1.f, 2 * a.level);
     a.wnode[n] = 1.f + C.st_gamma * expf(-fmaxf(lmin, 0.f) / tau);
 }
 
-__global__ __launch_bounds__(SF_BLOCK) void k_finish_level(LevelArgs a) {
-    const long n = (long)blockIdx.x * SF_BLOCK + threadIdx.x;
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_finish_level(KArg<B> ka) {
+    SF_BIND(ka);
+    const long n = (long)bid * SF_BLOCK + threadIdx.x;
     if (n >= a.d.G) return;
     const long G0 = a.G0;
     const float *base = a.nodes + (long)NV_BASE * 6 * G0;
@@ -1370,13 +1442,19 @@ __global__ __launch_bounds__(SF_BLOCK) void k_finish_level(LevelArgs a) {
 
 // ---- output: depth and 3D flow at level 0 -----------------------------------
 
-__global__ __launch_bounds__(SF_BLOCK) void k_output(LevelArgs a, float *depth,
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_output(KArg<B> ka, float *depth,
                                                      float *flow3d, float *flows) {
+    SF_BIND(ka);
+    if (B) {
+        depth = a.io->depth;
+        flow3d = a.io->flow3d;
+        flows = a.io->flows;
+    }
     const LevelDims &d = a.d;
     const DevConst &C = *a.cst;
     __shared__ NodeStage S;
     const int tiles_x = (d.W + TILE_PX - 1) / TILE_PX;
-    const int bid = blockIdx.x;
     const int x0 = (bid % tiles_x) * TILE_PX, y0 = (bid / tiles_x) * TILE_PX;
     stage_nodes(a, x0, y0, 0.f, S);
     __syncthreads();
@@ -1412,6 +1490,29 @@ __global__ __launch_bounds__(SF_BLOCK) void k_output(LevelArgs a, float *depth,
 }  // namespace
 
 // ---- launchers ----------------------------------------------------------------
+
+// Launches the single-frame instantiation `ks` with the frame's arguments by
+// value, or the batched instantiation `kb` over all frames of L with a
+// block map; `blocks(a)` is one frame's workgroup count.
+template <class Blocks, class KB, class KS, class... Args>
+static void go(hipStream_t st, const Launch &L, Blocks blocks, KB kb, KS ks, int threads,
+               size_t lds, Args... args) {
+    if (!L.batched) {
+        const int nb = blocks(L.host[0]);
+        if (nb > 0) hipLaunchKernelGGL(ks, dim3(nb), dim3(threads), lds, st, L.host[0], args...);
+        return;
+    }
+    FrameMap m;
+    m.tab = L.dev;
+    m.nf = L.nf;
+    int acc = 0;
+    for (int f = 0; f < L.nf; ++f) {
+        m.first[f] = acc;
+        acc += blocks(L.host[f]);
+    }
+    for (int f = L.nf; f <= SF_MAX_BATCH; ++f) m.first[f] = acc;
+    if (acc > 0) hipLaunchKernelGGL(kb, dim3(acc), dim3(threads), lds, st, m, args...);
+}
 
 // The node-tile kernels are instantiated per grid stride (1..8).
 #define SF_STRIDE_SWITCH(s, CALL) \
@@ -1465,105 +1566,84 @@ size_t node_tile_lds_bytes(const TileCfg &t, int s, int K) {
     return tile_lds_floats(t, s, K) * sizeof(float);
 }
 
-static int pixel_tiles(const LevelDims &d) {
-    return ((d.W + TILE_PX - 1) / TILE_PX) * ((d.H + TILE_PX - 1) / TILE_PX);
-}
+int energy_blocks(const LevelDims &d) { return energy_blocks_of(d); }
 
-int energy_blocks(const LevelDims &d) {
-    return pixel_tiles(d) + (d.G + SF_BLOCK - 1) / SF_BLOCK;
-}
+int node_tile_blocks(const LevelDims &d, const TileCfg &t) { return node_tiles_of(d, t); }
 
-int node_tile_blocks(const LevelDims &d, const TileCfg &t) {
-    return ((d.Gx + t.tx - 1) / t.tx) * ((d.Gy + t.ty - 1) / t.ty);
-}
+static auto px_blocks = [](const LevelArgs &a) { return pixel_tiles(a.d); };
+static auto nd_blocks = [](const LevelArgs &a) { return node_blocks(a.d); };
+static auto en_blocks = [](const LevelArgs &a) { return energy_blocks_of(a.d); };
+static auto tx_blocks = [](const LevelArgs &a) { return tex_blocks(a.d.W, a.d.H); };
 
-static dim3 tile_grid(const LevelDims &d, const TileCfg &t) {
-    return dim3((d.Gx + t.tx - 1) / t.tx, (d.Gy + t.ty - 1) / t.ty);
-}
-
-static int node_blocks(const LevelDims &d) { return (d.G + SF_BLOCK - 1) / SF_BLOCK; }
-
-void launch_tex_level0(hipStream_t st, const float *const img[4], float4 *tex,
-                       int W, int H) {
+void launch_tex_level0(hipStream_t st, const Launch &L, const float *const img[4]) {
     Img4 in;
-    for (int c = 0; c < 4; ++c) in.p[c] = img[c];
-    dim3 grid((W + 63) / 64, (H + 3) / 4, 4);
-    hipLaunchKernelGGL(k_tex0, grid, dim3(SF_BLOCK), 0, st, in, tex, W, H);
+    for (int c = 0; c < 4; ++c) in.p[c] = img ? img[c] : nullptr;
+    go(st, L, tx_blocks, k_tex0<true>, k_tex0<false>, SF_BLOCK, 0, in);
 }
 
-void launch_downsample(hipStream_t st, const float4 *src, int Ws, int Hs,
-                       float4 *dst, int Wd, int Hd) {
-    dim3 grid((Wd + 63) / 64, (Hd + 3) / 4, 4);
-    hipLaunchKernelGGL(k_texl, grid, dim3(SF_BLOCK), 0, st, src, Ws, Hs, dst, Wd, Hd);
+void launch_downsample(hipStream_t st, const Launch &L) {
+    go(st, L, tx_blocks, k_texl<true>, k_texl<false>, SF_BLOCK, 0);
 }
 
-void launch_level_init(hipStream_t st, const LevelArgs &a,
-                       const LevelDims *coarse, bool coarsest) {
-    const int gn = node_blocks(a.d);
-    hipLaunchKernelGGL(k_prolong, dim3(gn), dim3(SF_BLOCK), 0, st, a,
-                       coarse ? coarse->Gx : 1, coarse ? coarse->Gy : 1,
-                       coarsest ? 1 : 0);
-    const int np = pixel_tiles(a.d);
-    hipLaunchKernelGGL(k_masks, dim3(np), dim3(SF_BLOCK), 0, st, a);
-    hipLaunchKernelGGL(k_node_weights, dim3(gn), dim3(SF_BLOCK), 0, st, a, np);
+void launch_level_init(hipStream_t st, const Launch &L) {
+    go(st, L, nd_blocks, k_prolong<true>, k_prolong<false>, SF_BLOCK, 0);
+    go(st, L, px_blocks, k_masks<true>, k_masks<false>, SF_BLOCK, 0);
+    go(st, L, nd_blocks, k_node_weights<true>, k_node_weights<false>, SF_BLOCK, 0);
 }
 
-void launch_linearize(hipStream_t st, const LevelArgs &a) {
-    const int np = pixel_tiles(a.d);
-    hipLaunchKernelGGL(k_energy<true>, dim3(energy_blocks(a.d)), dim3(SF_BLOCK), 0, st, a, 0,
-                       0.f, np);
+void launch_linearize(hipStream_t st, const Launch &L) {
+    go(st, L, en_blocks, k_energy<true, true>, k_energy<false, true>, SF_BLOCK, 0, 0, 0.f);
 }
 
-void launch_trial(hipStream_t st, const LevelArgs &a, int trial, float tau) {
-    const int np = pixel_tiles(a.d);
-    hipLaunchKernelGGL(k_energy<false>, dim3(energy_blocks(a.d)), dim3(SF_BLOCK), 0, st, a,
-                       trial, tau, np);
+void launch_trial(hipStream_t st, const Launch &L, int trial, float tau) {
+    go(st, L, en_blocks, k_energy<true, false>, k_energy<false, false>, SF_BLOCK, 0, trial, tau);
 }
 
-void launch_rhs(hipStream_t st, const LevelArgs &a, const TileCfg &t) {
-#define RHS(S)                                                                          \
-    hipLaunchKernelGGL(k_rhs<S>, tile_grid(a.d, t), dim3(TileTraits<S>::NT),            \
-                       node_tile_lds_bytes(t, a.s, 12), st, a, t, energy_blocks(a.d))
-    SF_STRIDE_SWITCH(a.s, RHS)
+void launch_rhs(hipStream_t st, const Launch &L, const TileCfg &t) {
+    auto nb = [t](const LevelArgs &a) { return node_tiles_of(a.d, t); };
+    const int s = L.host[0].s;
+#define RHS(S)                                                                           \
+    go(st, L, nb, k_rhs<true, S>, k_rhs<false, S>, TileTraits<S>::NT,                    \
+       node_tile_lds_bytes(t, S, 12), t)
+    SF_STRIDE_SWITCH(s, RHS)
 #undef RHS
 }
 
-void launch_pcg_first(hipStream_t st, const LevelArgs &a, const TileCfg &t) {
+void launch_pcg_first(hipStream_t st, const Launch &L, const TileCfg &t) {
+    auto nb = [t](const LevelArgs &a) { return node_tiles_of(a.d, t); };
+    const int s = L.host[0].s;
 #define PCG0(S)                                                                          \
-    hipLaunchKernelGGL((k_pcg<true, S>), tile_grid(a.d, t), dim3(TileTraits<S>::NT),     \
-                       node_tile_lds_bytes(t, a.s, 6), st, a, t, 0, -1, 0, 0)
-    SF_STRIDE_SWITCH(a.s, PCG0)
+    go(st, L, nb, k_pcg<true, true, S>, k_pcg<false, true, S>, TileTraits<S>::NT,        \
+       node_tile_lds_bytes(t, S, 6), t, 0, -1, 0)
+    SF_STRIDE_SWITCH(s, PCG0)
 #undef PCG0
 }
 
-void launch_pcg_iter(hipStream_t st, const LevelArgs &a, const TileCfg &t, int iter,
-                     int log_index, int force) {
+void launch_pcg_iter(hipStream_t st, const Launch &L, const TileCfg &t, int iter, int gn,
+                     int force) {
+    auto nb = [t](const LevelArgs &a) { return node_tiles_of(a.d, t); };
+    const int s = L.host[0].s;
 #define PCGI(S)                                                                          \
-    hipLaunchKernelGGL((k_pcg<false, S>), tile_grid(a.d, t), dim3(TileTraits<S>::NT),    \
-                       node_tile_lds_bytes(t, a.s, 6), st, a, t, iter, log_index, force, \
-                       node_tile_blocks(a.d, t))
-    SF_STRIDE_SWITCH(a.s, PCGI)
+    go(st, L, nb, k_pcg<true, false, S>, k_pcg<false, false, S>, TileTraits<S>::NT,      \
+       node_tile_lds_bytes(t, S, 6), t, iter, gn, force)
+    SF_STRIDE_SWITCH(s, PCGI)
 #undef PCGI
 }
 
-void launch_pcg_last(hipStream_t st, const LevelArgs &a, const TileCfg &t, int iter,
-                     int log_index, int force) {
-    hipLaunchKernelGGL(k_pcg_last, dim3(node_blocks(a.d)), dim3(SF_BLOCK), 0, st, a, iter,
-                       node_tile_blocks(a.d, t), log_index, force);
+void launch_pcg_last(hipStream_t st, const Launch &L, const TileCfg &t, int iter, int gn,
+                     int force) {
+    go(st, L, nd_blocks, k_pcg_last<true>, k_pcg_last<false>, SF_BLOCK, 0, t, iter, gn, force);
 }
 
-void launch_accept(hipStream_t st, const LevelArgs &a, const TileCfg &, int n_trials,
-                   int log_index, int gn_iter, int pcg_iters) {
-    hipLaunchKernelGGL(k_accept, dim3(node_blocks(a.d)), dim3(SF_BLOCK), 0, st, a, n_trials,
-                       log_index, gn_iter, pcg_iters, node_blocks(a.d));
+void launch_accept(hipStream_t st, const Launch &L, int n_trials, int gn, int pcg_iters) {
+    go(st, L, nd_blocks, k_accept<true>, k_accept<false>, SF_BLOCK, 0, n_trials, gn, pcg_iters);
 }
 
-void launch_finish_level(hipStream_t st, const LevelArgs &a) {
-    hipLaunchKernelGGL(k_finish_level, dim3(node_blocks(a.d)), dim3(SF_BLOCK), 0, st, a);
+void launch_finish_level(hipStream_t st, const Launch &L) {
+    go(st, L, nd_blocks, k_finish_level<true>, k_finish_level<false>, SF_BLOCK, 0);
 }
 
-void launch_output(hipStream_t st, const LevelArgs &a, float *depth,
-                   float *flow3d, float *flows) {
-    hipLaunchKernelGGL(k_output, dim3(pixel_tiles(a.d)), dim3(SF_BLOCK), 0, st, a,
-                       depth, flow3d, flows);
+void launch_output(hipStream_t st, const Launch &L, float *depth, float *flow3d,
+                   float *flows) {
+    go(st, L, px_blocks, k_output<true>, k_output<false>, SF_BLOCK, 0, depth, flow3d, flows);
 }

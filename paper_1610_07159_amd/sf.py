@@ -31,7 +31,12 @@ SF_KERNEL_APPLY, SF_KERNEL_LINEARIZE, SF_KERNEL_UPDATE, SF_KERNEL_RHS = 0, 1, 2,
 
 class SfError(RuntimeError):
     def __init__(self, code, where):
-        super().__init__(f"{where} failed: {STATUS.get(code, code)}")
+        msg = f"{where} failed: {STATUS.get(code, code)}"
+        if code in (-3, -4):
+            detail = lib.sf_last_error().decode()
+            if detail:
+                msg += f" [{detail}]"
+        super().__init__(msg)
         self.code = code
 
 
@@ -66,11 +71,22 @@ class sf_iter_log(ctypes.Structure):
                 ("n_valid", ctypes.c_int)]
 
 
+class sf_frame(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p * 4), ("width", ctypes.c_int),
+                ("height", ctypes.c_int), ("calib", sf_calib),
+                ("depth", ctypes.c_void_p), ("flow3d", ctypes.c_void_p),
+                ("flows", ctypes.c_void_p)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build the HIP library first "
             "(python -c 'import __graft_entry__ as g; g.build()')")
+    # torch ships its own HIP runtime; loading it first makes libsf.so bind
+    # to that same runtime, so device pointers and streams from torch are
+    # valid here (two runtimes in one process do not share devices)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     I = ctypes.c_int
@@ -83,6 +99,8 @@ def _load():
                                ctypes.POINTER(I)]
     lib.sf_status_string.argtypes = [I]
     lib.sf_status_string.restype = ctypes.c_char_p
+    lib.sf_last_error.argtypes = []
+    lib.sf_last_error.restype = ctypes.c_char_p
     lib.sf_destroy.argtypes = [P]
     lib.sf_destroy.restype = None
     lib.sf_debug_size.argtypes = [P, I, I]
@@ -93,9 +111,16 @@ def _load():
                                         ctypes.POINTER(sf_calib)]
     lib.sf_debug_run.argtypes = [P, I, I]
     lib.sf_time_kernel.argtypes = [P, I, I, I, ctypes.POINTER(ctypes.c_float)]
+    lib.sf_time_batch_kernel.argtypes = [P, I, I, I, ctypes.POINTER(ctypes.c_float)]
+    lib.sf_batch_levels.argtypes = [I, I, I]
+    lib.sf_solve_batch.argtypes = [P, I, ctypes.POINTER(sf_frame),
+                                   ctypes.POINTER(sf_params)]
+    lib.sf_get_batch_log.argtypes = [P, I, ctypes.POINTER(sf_iter_log), I,
+                                     ctypes.POINTER(I)]
     for f in ("sf_params_default", "sf_create", "sf_solve", "sf_get_log",
               "sf_debug_read", "sf_debug_write", "sf_debug_set_images",
-              "sf_debug_run", "sf_time_kernel"):
+              "sf_debug_run", "sf_time_kernel", "sf_time_batch_kernel",
+              "sf_batch_levels", "sf_solve_batch", "sf_get_batch_log"):
         getattr(lib, f).restype = I
     return lib
 
@@ -144,12 +169,7 @@ def sf_solve(ctx, I_left_t: int, I_right_t: int, I_left_t1: int,
                         depth, flow3d, flows or None), "sf_solve")
 
 
-def sf_get_log(ctx, cap: int = 4096):
-    buf = (sf_iter_log * cap)()
-    n = ctypes.c_int()
-    code = lib.sf_get_log(ctx, buf, cap, ctypes.byref(n))
-    if code not in (SF_OK, -5):
-        _check(code, "sf_get_log")
+def _log_records(buf, n):
     out = []
     for i in range(n.value):
         r = buf[i]
@@ -160,7 +180,46 @@ def sf_get_log(ctx, cap: int = 4096):
                         energy_after=r.energy_after, tau=r.tau,
                         pcg_res=list(r.pcg_res[:r.pcg_iters]),
                         n_valid=r.n_valid))
-    return out, code
+    return out
+
+
+def sf_get_log(ctx, cap: int = 4096):
+    buf = (sf_iter_log * cap)()
+    n = ctypes.c_int()
+    code = lib.sf_get_log(ctx, buf, cap, ctypes.byref(n))
+    if code not in (SF_OK, -5):
+        _check(code, "sf_get_log")
+    return _log_records(buf, n), code
+
+
+def sf_batch_levels(width: int, height: int, max_levels: int) -> int:
+    return lib.sf_batch_levels(int(width), int(height), int(max_levels))
+
+
+def make_frame(imgs, width, height, calib: sf_calib, depth, flow3d, flows=0):
+    """imgs: four device addresses (left t, right t, left t+1, right t+1)."""
+    f = sf_frame()
+    for k in range(4):
+        f.img[k] = int(imgs[k])
+    f.width, f.height, f.calib = int(width), int(height), calib
+    f.depth, f.flow3d, f.flows = int(depth), int(flow3d), (int(flows) or None)
+    return f
+
+
+def sf_solve_batch(ctx, frames, params: sf_params | None = None):
+    arr = (sf_frame * len(frames))(*frames)
+    _check(lib.sf_solve_batch(ctx, len(frames), arr,
+                              ctypes.byref(params) if params is not None else None),
+           "sf_solve_batch")
+
+
+def sf_get_batch_log(ctx, frame: int, cap: int = 4096):
+    buf = (sf_iter_log * cap)()
+    n = ctypes.c_int()
+    code = lib.sf_get_batch_log(ctx, int(frame), buf, cap, ctypes.byref(n))
+    if code not in (SF_OK, -5):
+        _check(code, "sf_get_batch_log")
+    return _log_records(buf, n), code
 
 
 def sf_status_string(code: int) -> str:
@@ -214,4 +273,12 @@ def sf_time_kernel(ctx, kernel, level, reps) -> float:
     ms = ctypes.c_float()
     _check(lib.sf_time_kernel(ctx, kernel, level, reps, ctypes.byref(ms)),
            "sf_time_kernel")
+    return ms.value
+
+
+def sf_time_batch_kernel(ctx, kernel, level, reps) -> float:
+    """The same over every frame of the last batch (one launch)."""
+    ms = ctypes.c_float()
+    _check(lib.sf_time_batch_kernel(ctx, kernel, level, reps, ctypes.byref(ms)),
+           "sf_time_batch_kernel")
     return ms.value

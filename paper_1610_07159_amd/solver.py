@@ -49,6 +49,35 @@ class SceneFlowSolver:
                     flows.data_ptr() if flows is not None else 0)
         return depth, flow3d, flows
 
+    def solve_batch(self, frames, outs=None, params=None, with_flows=True):
+        """frames: list of (images (4, H_i, W_i) float32 CUDA tensor, calib)
+        of any sizes (up to 64).  Solves them together in one batch of the
+        context (see sf_solve_batch); returns a list of (depth, flow3d,
+        flows) tensors."""
+        import torch
+        if outs is None:
+            outs = []
+            for img, _ in frames:
+                _, H, W = img.shape
+                dev = img.device
+                outs.append((torch.empty((H, W), device=dev),
+                             torch.empty((3, H, W), device=dev),
+                             torch.empty((6, H, W), device=dev) if with_flows else None))
+        recs = []
+        for (img, cal), (depth, flow3d, flows) in zip(frames, outs):
+            assert img.is_cuda and img.dtype == torch.float32 and img.is_contiguous()
+            _, H, W = img.shape
+            c = cal if isinstance(cal, sf.sf_calib) else calib_from_dict(cal)
+            recs.append(sf.make_frame([img[k].data_ptr() for k in range(4)], W, H, c,
+                                      depth.data_ptr(), flow3d.data_ptr(),
+                                      flows.data_ptr() if flows is not None else 0))
+        sf.sf_solve_batch(self.ctx, recs, params)
+        self._batch_frames = recs  # keep the records alive with the call
+        return outs
+
+    def batch_log(self, frame):
+        return sf.sf_get_batch_log(self.ctx, frame)[0]
+
     def log(self):
         return sf.sf_get_log(self.ctx)[0]
 

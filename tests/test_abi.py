@@ -64,3 +64,23 @@ def test_host_validation_without_gpu():
     assert lib.sf_debug_size(None, 0, 0) == 0
     lib.sf_destroy(None)
     assert sf.sf_status_string(-3) == "HIP runtime error"
+
+
+def test_batch_levels_rule_and_validation_without_gpu():
+    from paper_1610_07159_amd import sf
+    lib = sf.lib
+    # the batched workload's resolutions give 4 / 5 / 5 / 6 levels
+    assert [sf.sf_batch_levels(w, h, 6) for w, h in
+            ((320, 240), (640, 480), (960, 540), (1280, 720))] == [4, 5, 5, 6]
+    assert sf.sf_batch_levels(64, 48, 3) == 1
+    assert sf.sf_batch_levels(160, 120, 3) == 3
+    assert sf.sf_batch_levels(159, 120, 3) == 2
+    assert sf.sf_batch_levels(640, 20, 6) == 2  # coarsest level stays >= 8 px
+    assert sf.sf_batch_levels(4, 48, 3) == 0
+    fr = (sf.sf_frame * 1)()
+    p = sf.sf_params_default()
+    assert lib.sf_solve_batch(None, 1, fr, ctypes.byref(p)) == -1
+    n = ctypes.c_int()
+    assert lib.sf_get_batch_log(None, 0, None, 0, ctypes.byref(n)) == -1
+    ms = ctypes.c_float()
+    assert lib.sf_time_batch_kernel(None, 0, 0, 1, ctypes.byref(ms)) == -1
