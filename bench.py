@@ -40,6 +40,14 @@ WORKLOADS = {
                     "moving blobs; stride 4, 6 levels, 10 GN x 20 PCG",
                width=1280, height=720, seed=2,
                params=dict(levels=6, grid_stride=4, gn_iters=10, pcg_iters=20)),
+    "batch": dict(desc="batches of 64 frames, resolutions drawn by seed 3 from "
+                       "320x240 / 640x480 / 960x540 / 1280x720 (4 / 5 / 5 / 6 "
+                       "levels: 1 + floor(log2(W / 40))), displacement 30 px per "
+                       "640 px of width, noise sigma 0.01, two generator scenes "
+                       "per resolution reused across the batch; stride 4, "
+                       "10 GN x 20 PCG, one HIP graph per batch",
+                  n_frames=64, seed=3,
+                  params=dict(levels=6, grid_stride=4, gn_iters=10, pcg_iters=20)),
 }
 
 # Algorithmic bytes of one H p launch (matrix-free, per-pixel Gauss-Newton
@@ -47,6 +55,33 @@ WORKLOADS = {
 # z, p_old, p (write), q (write), base, delta (6 floats each) and w_i.
 APPLY_BYTES_PER_PIXEL = 21 * 4
 APPLY_BYTES_PER_NODE = (6 * 6 + 1) * 4
+
+
+def _gen_frame(args):
+    from synth import make_frame, sized_config
+    W, H, seed = args
+    imgs, calib, _ = make_frame(sized_config(W, H), seed)
+    return imgs, calib
+
+
+def make_batch_workload(w):
+    """Frames of the batched workload: per-frame resolutions from the seed,
+    images from two generator scenes per resolution (rendered in parallel
+    on the host)."""
+    from concurrent.futures import ProcessPoolExecutor
+    from synth import batch_resolutions
+    res = batch_resolutions(w["n_frames"], w["seed"])
+    jobs = sorted({(W, H, 100 + 10 * k + j) for k, (W, H) in enumerate(sorted(set(res)))
+                   for j in range(2)})
+    with ProcessPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        out = dict(zip(jobs, ex.map(_gen_frame, jobs)))
+    frames, count = [], {}
+    for W, H in res:
+        j = count.get((W, H), 0)
+        count[(W, H)] = j + 1
+        key = next(k for k in jobs if k[0] == W and k[1] == H and (k[2] % 10) == j % 2)
+        frames.append(out[key])
+    return res, frames
 
 
 def make_workload(name):
@@ -109,6 +144,63 @@ def cpu_baseline(imgs, calib, params, W, H):
                         "numpy/scipy float64, BLAS limited to 1 thread"))
 
 
+def _short_name(n):
+    import re
+    n = re.sub(r"\(anonymous namespace\)::", "", n)
+    n = re.sub(r"std::conditional<(true|false), FrameMap, LevelArgs>::type", "", n)
+    n = re.sub(r"\(.*\)$", "", n).replace("void ", "")
+    return n
+
+
+def trace_summary(path, focus=("k_pcg",)):
+    """Summary of a rocprofv3 CSV: per kernel (calls, total/avg/min/max us)
+    for a kernel trace, or per kernel the mean counter values per dispatch
+    for a counter-collection file; both also per launch grid for the
+    kernels named in `focus`."""
+    import collections
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    if not rows:
+        print("empty file")
+        return
+    cols = rows[0].keys()
+    grid = [c for c in ("Grid_Size_X", "Grid_Size") if c in cols][0]
+    if "Counter_Name" in cols:
+        acc = collections.OrderedDict()
+        for r in rows:
+            k = (_short_name(r["Kernel_Name"]), r[grid], r["Counter_Name"])
+            a = acc.setdefault(k, [0, 0.0])
+            a[0] += 1
+            a[1] += float(r["Counter_Value"])
+        print(f"{'kernel':44s} {'grid':>10s} {'counter':>12s} {'dispatches':>10s} {'mean':>14s}")
+        for (k, g, c), (n, v) in sorted(acc.items(), key=lambda kv: -kv[1][1]):
+            print(f"{k:44s} {g:>10s} {c:>12s} {n:10d} {v / n:14.1f}")
+        return
+    agg, grids = collections.OrderedDict(), collections.OrderedDict()
+    tot = 0.0
+    for r in rows:
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        k = _short_name(r["Kernel_Name"])
+        a = agg.setdefault(k, [0, 0.0, 1e30, 0.0])
+        a[0] += 1
+        a[1] += d
+        a[2] = min(a[2], d)
+        a[3] = max(a[3], d)
+        tot += d
+        if any(f in k for f in focus):
+            g = grids.setdefault((k, int(r[grid])), [0, 0.0])
+            g[0] += 1
+            g[1] += d
+    print(f"{'kernel':44s} {'calls':>7s} {'total_us':>11s} {'avg_us':>9s} {'min_us':>8s} "
+          f"{'max_us':>9s} {'pct':>6s}")
+    for k, (c, t, mn, mx) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        print(f"{k:44s} {c:7d} {t:11.1f} {t / c:9.2f} {mn:8.2f} {mx:9.2f} {100 * t / tot:6.2f}")
+    print(f"total kernel time: {tot / 1e3:.3f} ms over {len(rows)} dispatches")
+    print("\nby launch grid (total threads in x):")
+    for (k, g), (c, t) in sorted(grids.items(), key=lambda kv: (kv[0][0], -kv[0][1])):
+        print(f"  {k:44s} grid {g:9d}: calls {c:6d}, avg {t / c:8.2f} us")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,7 +214,12 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter "
                          "calibration under rocprofv3 --pmc)")
+    ap.add_argument("--trace-summary", metavar="CSV",
+                    help="summarise a rocprofv3 kernel-trace or counter CSV and exit")
     args = ap.parse_args()
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU "
               "path (frames would shard across GPUs with no exchange); "
@@ -130,19 +227,25 @@ def main():
         sys.exit(2)
 
     import torch
+    torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        # reference dispatch of known traffic: reads and writes exactly
+        # copy_probe_mib MiB
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    if args.workload == "batch":
+        return run_batch(args)
+
     from paper_1610_07159_amd import SceneFlowSolver, sf
 
     w, imgs, calib, scene = make_workload(args.workload)
     W, H = w["width"], w["height"]
     params = dict(w["params"])
-    torch.cuda.set_device(0)
-    if args.copy_probe_mib > 0:
-        n = args.copy_probe_mib * (1 << 20) // 4
-        a = torch.ones(n, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
     img = torch.from_numpy(imgs).cuda().contiguous()
     solver = SceneFlowSolver(W, H, exec_mode=args.exec_mode, **params)
     stream = solver.stream
@@ -207,6 +310,80 @@ def main():
         result["epe_px"] = round(epe(flows, scene, W, H), 4)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(imgs, calib, params, W, H)
+    solver.close()
+    print(json.dumps(result), flush=True)
+
+
+def run_batch(args):
+    """Batches of frames of mixed sizes through sf_solve_batch.  One step is
+    one batch; per-batch GPU time from HIP events on the solver's stream."""
+    import torch
+    from paper_1610_07159_amd import SceneFlowSolver, sf
+    w = WORKLOADS["batch"]
+    params = dict(w["params"])
+    res, frames = make_batch_workload(w)
+    torch.cuda.set_device(0)
+    dev = [(torch.from_numpy(i).cuda().contiguous(), c) for i, c in frames]
+    W0, H0 = res[0]
+    solver = SceneFlowSolver(W0, H0, exec_mode=args.exec_mode, **params)
+    stream = solver.stream
+    prm = sf.sf_params_default(exec_mode=args.exec_mode, **params)
+    outs = None
+    for _ in range(args.warmup):
+        outs = solver.solve_batch(dev, outs=outs, params=prm)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        outs = solver.solve_batch(dev, outs=outs, params=prm)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_batch = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+    total_ms = float(per_batch.sum())
+    n = len(frames)
+    for f in range(n):
+        log = solver.batch_log(f)
+        if not all(np.isfinite(r["energy"]) and np.isfinite(r["energy_after"]) for r in log):
+            raise RuntimeError(f"non-finite energy in the log of frame {f}")
+
+    reps = params["gn_iters"] * params["pcg_iters"]
+    avg_ms = sf.sf_time_batch_kernel(solver.ctx, sf.SF_KERNEL_APPLY, 0, reps)
+    bytes_apply = 0
+    for W, H in res:
+        L = sf.sf_batch_levels(W, H, params["levels"])
+        N0, G0 = level_sizes(W, H, L, params["grid_stride"])[0][2:]
+        bytes_apply += APPLY_BYTES_PER_PIXEL * N0 + APPLY_BYTES_PER_NODE * G0
+    achieved = bytes_apply / (avg_ms * 1e-3) / 1e9
+    ms_frame = total_ms / (args.steps * n)
+    sizes = {f"{W}x{H}": res.count((W, H)) for W, H in sorted(set(res))}
+    result = {
+        "metric": METRIC,
+        "value": round(ms_frame, 4),
+        "unit": "ms/frame",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total_ms / args.steps, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "frames_per_batch": n, "sizes": sizes,
+                   "exec": "hip graph" if args.exec_mode == 0 else "direct launches",
+                   **params},
+        "frames_per_s": round(1e3 / ms_frame, 1),
+        "batch_ms_p50": round(float(np.percentile(per_batch, 50)), 3),
+        "batch_ms_p99": round(float(np.percentile(per_batch, 99)), 3),
+        "wall_ms_per_batch": round(wall * 1e3 / args.steps, 3),
+        "roofline": {"bound": "hbm", "kernel": "k_apply (H p) at level 0, all frames",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_launch": bytes_apply,
+                     "avg_us_per_launch": round(avg_ms * 1e3, 2)},
+    }
     solver.close()
     print(json.dumps(result), flush=True)
 
