@@ -59,7 +59,9 @@ typedef struct {
  *  gn_iters        Gauss-Newton steps per level
  *  pcg_iters       PCG iterations per Gauss-Newton step (1..64)
  *  max_backtracks  step-length halvings after tau = 1 (0..7)
- *  init_mode       0 = zero initialisation of the coarsest level
+ *  init_mode       0 = zero initialisation of the coarsest level; 1 = the
+ *                  learned initialiser (needs levels >= 5 and weights from
+ *                  sf_set_initializer; see below)
  *  exec_mode       0 = replay a captured HIP graph, 1 = enqueue kernels
  *  w_*, m_*        weights of the energy terms; m_s, m_m, m_d must be > 0
  *  eps             pseudo-Huber parameter of Eq. (12)
@@ -158,6 +160,74 @@ sf_status sf_solve_batch(sf_ctx *ctx, int n, const sf_frame *frames,
 /* Log of frame `frame` of the last batch solve, as sf_get_log. */
 sf_status sf_get_batch_log(sf_ctx *ctx, int frame, sf_iter_log *out, int cap,
                            int *n_written);
+
+/* ---- learned coarse-level initialiser ---------------------------------
+ * The paper (Sec. 7) names a smarter initialisation of the coarsest level
+ * as future work.  With init_mode = 1 the solver runs a six-layer 3x3
+ * convolutional network (4 -> 32 -> 32 -> 32 -> 32 -> 32 -> 6 channels,
+ * zero padding, ReLU after the first five; bfloat16 weights and
+ * activations, float32 accumulation on the matrix cores) on the four
+ * level-4 (1/16-resolution) images minus 0.5.  Its output, per pixel
+ * (s_x, s_y, m_x, m_y, d_x, d_y) in level-4 pixels, is sampled bilinearly
+ * (clamp-to-edge) at the coarsest level's warp nodes and converted to that
+ * level's pixels.  Fallback: E of Eq. (8) at zero deltas is evaluated for
+ * the prediction and for the zero initialisation with one common
+ * visibility mask (all four positions inside the image under both) and no
+ * colour pruning; the prediction is used only if its energy is strictly
+ * lower.  Masks and smoothness weights are then taken at the chosen
+ * initialisation as usual.
+ *
+ * Parameter vector (SF_CNN_PARAMS values): per layer the weights in
+ * row-major (c_out, c_in, ky, kx) order followed by the c_out biases. */
+#define SF_CNN_PARAMS 39910
+
+/* Copies the initialiser's parameters: SF_CNN_PARAMS bfloat16 values
+ * (uint16 bit patterns, host memory), bytes = 2 * SF_CNN_PARAMS.  Takes
+ * effect for the following solves, also in a captured graph. */
+sf_status sf_set_initializer(sf_ctx *ctx, const void *weights, size_t bytes);
+
+/* Outcome of the fallback at the last solve with init_mode = 1: *used = 1
+ * if the prediction was kept, and both energies.  Synchronises the stream;
+ * SF_ERR_STATE if no such solve ran. */
+sf_status sf_get_init_result(sf_ctx *ctx, int *used, double *e_pred, double *e_zero);
+
+/* Trainer of the initialiser: batches of B level-4 image quadruples
+ * (device float32 [B][4][H][W], left t, right t, left t+1, right t+1) with
+ * targets (device float32 [B][6][H][W], flows in level-4 pixels).  One
+ * step = forward, L1 loss (mean absolute error over all B 6 H W values),
+ * backpropagation and one Adam update (beta1 0.9, beta2 0.999, eps 1e-8)
+ * of the float32 master parameters; the network itself runs on bfloat16
+ * copies.  Deterministic: fixed-order reductions only. */
+typedef struct sf_trainer sf_trainer;
+sf_status sf_trainer_create(sf_trainer **out, int max_batch, int height, int width,
+                            void *hip_stream);
+/* Sets the float32 master parameters (host, n = SF_CNN_PARAMS) and resets
+ * the Adam state; synchronises. */
+sf_status sf_trainer_set_params(sf_trainer *t, const float *host, size_t n);
+sf_status sf_trainer_get_params(sf_trainer *t, float *host, size_t n);
+/* Network output for `batch` samples into out (device [batch][6][H][W]). */
+sf_status sf_trainer_forward(sf_trainer *t, const float *x, int batch, float *out);
+/* One training step with learning rate lr (lr = 0 computes the gradient
+ * and leaves the parameters unchanged).  loss (host, may be NULL): the
+ * mean absolute error before the update; non-NULL synchronises. */
+sf_status sf_trainer_step(sf_trainer *t, const float *x, const float *target, int batch,
+                          float lr, float *loss);
+/* Test access to the last batch: network input (bf16 NHWC, 16 channels),
+ * post-ReLU activations of layers 0..4 (bf16 NHWC, 32 channels), output
+ * (float [B][6][H][W]), loss gradient (bf16 NHWC, 16 channels), the
+ * gradients w.r.t. the pre-activations of layers 0..4 (bf16 NHWC, 32) and
+ * the parameter gradient (float, SF_CNN_PARAMS). */
+enum {
+    SF_TR_INPUT = 0,
+    SF_TR_ACT = 1,
+    SF_TR_OUT = 2,
+    SF_TR_DOUT = 3,
+    SF_TR_DPRE = 4,
+    SF_TR_GRAD = 5
+};
+size_t sf_trainer_size(sf_trainer *t, int what, int layer);
+sf_status sf_trainer_read(sf_trainer *t, int what, int layer, void *host, size_t bytes);
+void sf_trainer_destroy(sf_trainer *t);
 
 /* Human-readable name of a status code (static string). */
 const char *sf_status_string(sf_status s);

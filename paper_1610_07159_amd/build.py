@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/sf_api.hip", "csrc/sf_kernels.hip"]
+SOURCES = ["csrc/sf_api.hip", "csrc/sf_kernels.hip", "csrc/sf_cnn.hip", "csrc/sf_train.hip"]
 LIB = os.path.join(HERE, "libsf.so")
 ARCH = "gfx950"
 

@@ -9,6 +9,7 @@
 #include <new>
 #include <vector>
 
+#include "sf_cnn.h"
 #include "sf_internal.h"
 
 namespace {
@@ -22,12 +23,27 @@ struct FrameBuf {
     int nlog = 0;
     float4 *tex = nullptr;
     unsigned char *cmask = nullptr;
-    float *wnode = nullptr, *reg = nullptr, *nodes = nullptr, *rec = nullptr;
+    float *wnode = nullptr, *reg = nullptr, *nodes = nullptr;
+    float *gram = nullptr, *grad = nullptr;
     float *partials = nullptr;
     DevConst *cst = nullptr;
     DevScalars *sc = nullptr;
     DevLog *log = nullptr;
     FrameIO *io = nullptr;
+};
+
+// Workspace of the learned initialiser (single-frame contexts with
+// init_mode = 1): float32 parameters, device weights and the activations of
+// one level-4 image quadruple.
+struct CnnRun {
+    bool on = false, have_weights = false;
+    CnnLayout L{};
+    int W4 = 0, H4 = 0;
+    float *flat = nullptr, *out = nullptr;
+    CnnWeights w{};
+    unsigned short *x = nullptr;
+    unsigned short *acts[SF_CNN_LAYERS - 1]{};
+    char *pool = nullptr;
 };
 
 // A set of frames solved together: their buffers (one device allocation),
@@ -54,6 +70,7 @@ struct Plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<int> shape;  // W, H per frame (batch cache key)
+    CnnRun cnn;              // learned initialiser (single frame)
 };
 
 }  // namespace
@@ -92,7 +109,8 @@ sf_status check_params(const sf_params *p) {
     if (p->gn_iters < 1 || p->gn_iters > 1000) return SF_ERR_INVALID_ARG;
     if (p->pcg_iters < 1 || p->pcg_iters > SF_MAX_PCG) return SF_ERR_INVALID_ARG;
     if (p->max_backtracks < 0 || p->max_backtracks > SF_MAX_TRIALS - 1) return SF_ERR_INVALID_ARG;
-    if (p->init_mode != 0) return SF_ERR_INVALID_ARG;
+    if (p->init_mode != 0 && p->init_mode != 1) return SF_ERR_INVALID_ARG;
+    if (p->init_mode == 1 && p->levels <= SF_CNN_INPUT_LEVEL) return SF_ERR_INVALID_ARG;
     if (p->exec_mode != 0 && p->exec_mode != 1) return SF_ERR_INVALID_ARG;
     const float w[] = {p->w_reg, p->w_photo, p->w_grad, p->w_epi, p->w_smooth,
                        p->w_mag, p->w_s, p->w_m, p->w_d, p->st_gamma};
@@ -187,6 +205,7 @@ void free_plan(Plan &P) {
     if (P.gexec) (void)hipGraphExecDestroy(P.gexec);
     if (P.graph) (void)hipGraphDestroy(P.graph);
     if (P.pool) (void)hipFree(P.pool);
+    if (P.cnn.pool) (void)hipFree(P.cnn.pool);
     if (P.stage) (void)hipHostFree(P.stage);
     if (P.stage_ev) (void)hipEventDestroy(P.stage_ev);
     P = Plan();
@@ -225,16 +244,17 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
         }
         F.max_blocks = mb;
         F.nlog = F.L * prm.gn_iters;
-        const size_t sz[9] = {sizeof(float4) * (size_t)F.tex_len,
-                              (size_t)F.N0,
-                              sizeof(float) * (size_t)F.G0,
-                              sizeof(float) * 16 * (size_t)F.G0,
-                              sizeof(float) * NV_COUNT * 6 * (size_t)F.G0,
-                              sizeof(float) * SF_REC_PLANES * (size_t)F.N0,
-                              sizeof(float) * PS_COUNT * (size_t)mb,
-                              sizeof(DevScalars),
-                              sizeof(DevLog) * (size_t)F.nlog};
-        for (int k = 0; k < 9; ++k) {
+        const size_t sz[10] = {sizeof(float4) * (size_t)F.tex_len,
+                               (size_t)F.N0,
+                               sizeof(float) * (size_t)F.G0,
+                               sizeof(float) * 16 * (size_t)F.G0,
+                               sizeof(float) * NV_COUNT * 6 * (size_t)F.G0,
+                               sizeof(float) * SF_GRAM_STRIDE * (size_t)F.N0,
+                               sizeof(float) * PS_COUNT * (size_t)mb,
+                               sizeof(DevScalars),
+                               sizeof(DevLog) * (size_t)F.nlog,
+                               sizeof(float) * SF_GRAD_STRIDE * (size_t)F.N0};
+        for (int k = 0; k < 10; ++k) {
             o[f * 11 + k] = off;
             off += align_up(sz[k]);
         }
@@ -277,7 +297,8 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
         F.wnode = (float *)(P.pool + o[f * 11 + 2]);
         F.reg = (float *)(P.pool + o[f * 11 + 3]);
         F.nodes = (float *)(P.pool + o[f * 11 + 4]);
-        F.rec = (float *)(P.pool + o[f * 11 + 5]);
+        F.gram = (float *)(P.pool + o[f * 11 + 5]);
+        F.grad = (float *)(P.pool + o[f * 11 + 9]);
         F.partials = (float *)(P.pool + o[f * 11 + 6]);
         F.sc = (DevScalars *)(P.pool + o[f * 11 + 7]);
         F.log = (DevLog *)(P.pool + o[f * 11 + 8]);
@@ -310,7 +331,8 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
             a.tex_fine = l > 0 ? F.tex + F.lv[l - 1].tex_off : nullptr;
             a.io = F.io;
             a.nodes = F.nodes;
-            a.rec = F.rec;
+            a.gram = F.gram;
+            a.grad = F.grad;
             a.cmask = F.cmask;
             a.wnode = F.wnode;
             a.reg = F.reg;
@@ -322,6 +344,45 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
             P.host[l].push_back(a);
             flat.push_back(a);
         }
+    }
+    if (prm.init_mode == 1 && !batched) {
+        // network workspace for the frame's level-4 images
+        CnnRun &R = P.cnn;
+        FrameBuf &F = P.fr[0];
+        R.L = cnn_layout();
+        R.W4 = F.lv[SF_CNN_INPUT_LEVEL].W;
+        R.H4 = F.lv[SF_CNN_INPUT_LEVEL].H;
+        const size_t N4 = (size_t)R.W4 * R.H4;
+        const size_t sz[] = {sizeof(float) * R.L.n_params, sizeof(float) * 6 * N4,
+                             2 * (size_t)R.L.dev_w_total, 2 * (size_t)R.L.dev_w_total,
+                             sizeof(float) * R.L.dev_b_total, 2 * 16 * N4,
+                             2 * 32 * N4 * (SF_CNN_LAYERS - 1)};
+        size_t off2[7], tot = 0;
+        for (int k = 0; k < 7; ++k) {
+            off2[k] = tot;
+            tot += align_up(sz[k]);
+        }
+        e = hipMalloc(&R.pool, tot);
+        if (e != hipSuccess) {
+            note_hip_error("hipMalloc(initialiser)", e);
+            R.pool = nullptr;
+            return SF_ERR_OOM;
+        }
+        HIP_TRY(hipMemset(R.pool, 0, tot));
+        R.flat = (float *)(R.pool + off2[0]);
+        R.out = (float *)(R.pool + off2[1]);
+        R.w.wf = (unsigned short *)(R.pool + off2[2]);
+        R.w.wd = (unsigned short *)(R.pool + off2[3]);
+        R.w.bias = (float *)(R.pool + off2[4]);
+        R.x = (unsigned short *)(R.pool + off2[5]);
+        for (int l = 0; l < SF_CNN_LAYERS - 1; ++l)
+            R.acts[l] = (unsigned short *)(R.pool + off2[6]) + (size_t)l * 32 * N4;
+        R.on = true;
+        LevelArgs &a = P.host[F.L - 1][0];
+        a.learned = 1;
+        a.W4 = R.W4;
+        a.H4 = R.H4;
+        a.cnn_out = R.out;
     }
     if (!flat.empty())
         HIP_TRY(hipMemcpy(P.dtab, flat.data(), sizeof(LevelArgs) * flat.size(),
@@ -399,8 +460,19 @@ void enqueue_gn(const Plan &P, hipStream_t st, int l, int g, bool log) {
     launch_accept(st, L, T, log ? g : -1, P.prm.pcg_iters);
 }
 
+// The network on the level-4 images and its candidate for the coarsest
+// level with the fallback energies.
+void enqueue_cnn_init(const Plan &P, hipStream_t st) {
+    const CnnRun &R = P.cnn;
+    const FrameBuf &F = P.fr[0];
+    launch_cnn_input_tex(st, F.tex + F.lv[SF_CNN_INPUT_LEVEL].tex_off, R.x, R.W4 * R.H4);
+    launch_cnn_forward(st, R.L, R.w, R.x, R.acts, R.out, 1, R.H4, R.W4);
+    launch_cnn_candidate(st, slot(P, F.L - 1));
+}
+
 void enqueue_levels(const Plan &P, hipStream_t st) {
     for (int l = P.Lmax - 1; l >= 0; --l) {
+        if (P.cnn.on && l == P.Lmax - 1) enqueue_cnn_init(P, st);
         launch_level_init(st, slot(P, l));
         for (int g = 0; g < P.prm.gn_iters; ++g) enqueue_gn(P, st, l, g, true);
         launch_finish_level(st, slot(P, l));
@@ -617,6 +689,7 @@ sf_status sf_solve(sf_ctx *c, const float *I_left_t, const float *I_right_t,
     const float *img[4] = {I_left_t, I_right_t, I_left_t1, I_right_t1};
     sf_status s = prepare_frame(c, img, calib, p);
     if (s != SF_OK) return s;
+    if (c->single.cnn.on && !c->single.cnn.have_weights) return SF_ERR_STATE;
     s = run_body(c, c->single);
     if (s != SF_OK) return s;
     launch_output(c->stream, slot(c->single, 0), depth, flow3d, flows);
@@ -634,6 +707,7 @@ sf_status sf_solve_batch(sf_ctx *c, int n, const sf_frame *frames, const sf_para
     const sf_params prm = p ? *p : c->prm;
     sf_status s = check_params(&prm);
     if (s != SF_OK) return s;
+    if (prm.init_mode != 0) return SF_ERR_INVALID_ARG;  // batches start from zero
     std::vector<int> shape(2 * n), levels(n);
     std::vector<const sf_calib *> cals(n);
     std::vector<FrameIO> io(n);
@@ -695,6 +769,42 @@ sf_status sf_get_batch_log(sf_ctx *c, int frame, sf_iter_log *out, int cap, int 
     if (!c->batch || !c->batch->have_inputs) return SF_ERR_STATE;
     if (frame < 0 || frame >= c->batch->nf) return SF_ERR_INVALID_ARG;
     return copy_log(c->stream, c->batch->fr[frame], out, cap, n_written);
+}
+
+sf_status sf_set_initializer(sf_ctx *c, const void *weights, size_t bytes) {
+    if (!c || !weights) return SF_ERR_INVALID_ARG;
+    CnnRun &R = c->single.cnn;
+    if (!R.on) return SF_ERR_STATE;
+    if (bytes != 2 * (size_t)R.L.n_params) return SF_ERR_SIZE;
+    const unsigned short *h = (const unsigned short *)weights;
+    std::vector<float> f(R.L.n_params);
+    for (int k = 0; k < R.L.n_params; ++k) {
+        const unsigned u = (unsigned)h[k] << 16;
+        float v;
+        memcpy(&v, &u, 4);
+        if (!isfinite(v)) return SF_ERR_INVALID_ARG;
+        f[k] = v;
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(R.flat, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice));
+    launch_cnn_pack(c->stream, R.L, R.flat, R.w.wf, R.w.wd, R.w.bias);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    R.have_weights = true;
+    return SF_OK;
+}
+
+sf_status sf_get_init_result(sf_ctx *c, int *used, double *e_pred, double *e_zero) {
+    if (!c || !used || !e_pred || !e_zero) return SF_ERR_INVALID_ARG;
+    if (!c->single.cnn.on || !c->single.have_inputs) return SF_ERR_STATE;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    DevScalars sc;
+    HIP_TRY(hipMemcpy(&sc, c->single.fr[0].sc, sizeof(sc), hipMemcpyDeviceToHost));
+    *used = sc.init_used;
+    *e_pred = sc.e_init[0];
+    *e_zero = sc.e_init[1];
+    return SF_OK;
 }
 
 const char *sf_last_error(void) { return g_err; }
@@ -776,11 +886,31 @@ static sf_status debug_copy(sf_ctx *c, int what, int level, void *host, size_t b
         case SF_DBG_TEX: ok = cp(F.tex + d.tex_off, 0, bytes); break;
         case SF_DBG_CMASK: ok = cp(F.cmask, 0, bytes); break;
         case SF_DBG_WNODE: ok = cp(F.wnode, 0, bytes); break;
-        case SF_DBG_REC:
-            for (int k = 0; k < SF_REC_PLANES && ok; ++k)
-                ok = cp(F.rec + (size_t)k * F.N0, sizeof(float) * (size_t)k * d.N,
-                        sizeof(float) * d.N);
+        case SF_DBG_REC: {
+            // records are per pixel on the device, planes at the interface
+            std::vector<float> g((size_t)SF_GRAM_STRIDE * d.N), r((size_t)SF_GRAD_STRIDE * d.N);
+            float *hp = (float *)host;
+            if (to_device) {
+                for (long p = 0; p < d.N; ++p) {
+                    for (int q = 0; q < 6; ++q) r[p * SF_GRAD_STRIDE + q] = hp[(size_t)q * d.N + p];
+                    for (int i = 0, t = 0; i < 6; ++i)
+                        for (int j = i; j < 6; ++j, ++t)
+                            g[p * SF_GRAM_STRIDE + gram_index(i, j)] = hp[(size_t)(6 + t) * d.N + p];
+                }
+                ok = hipMemcpy(F.gram, g.data(), g.size() * sizeof(float), kind) == hipSuccess &&
+                     hipMemcpy(F.grad, r.data(), r.size() * sizeof(float), kind) == hipSuccess;
+            } else {
+                ok = hipMemcpy(g.data(), F.gram, g.size() * sizeof(float), kind) == hipSuccess &&
+                     hipMemcpy(r.data(), F.grad, r.size() * sizeof(float), kind) == hipSuccess;
+                for (long p = 0; ok && p < d.N; ++p) {
+                    for (int q = 0; q < 6; ++q) hp[(size_t)q * d.N + p] = r[p * SF_GRAD_STRIDE + q];
+                    for (int i = 0, t = 0; i < 6; ++i)
+                        for (int j = i; j < 6; ++j, ++t)
+                            hp[(size_t)(6 + t) * d.N + p] = g[p * SF_GRAM_STRIDE + gram_index(i, j)];
+                }
+            }
             break;
+        }
         case SF_DBG_ENERGY:
             if (to_device) return SF_ERR_INVALID_ARG;
             ok = cp(&F.sc->e_lin[0], 0, bytes);

@@ -14,12 +14,30 @@
 #define SF_BLOCK 256
 #define SF_MAX_BATCH 64
 
-// Number of per-pixel record planes: 6 gradient components of the pixel's
-// energy w.r.t. its six flow components, then the 21 upper-triangular
-// entries of its reweighted Gauss-Newton block J^T Omega J.
-#define SF_REC_GRAD 6
-#define SF_REC_GRAM 21
+// Per-pixel linearisation records, one aligned record per pixel so that a
+// pixel is read with whole 16-byte loads:
+//  gram: 24 floats, the reweighted Gauss-Newton block J^T Omega J of the
+//        pixel's six flow components: its diagonal (6), the upper
+//        off-diagonal entries row by row (15), padding (3);
+//  grad: 8 floats, the gradient of the pixel's energy w.r.t. its flows (6);
+//        slot 6 holds the mean warped image from level start until the
+//        first linearisation; slot 7 is padding.
+#define SF_GRAM_STRIDE 24
+#define SF_GRAD_STRIDE 8
+#define SF_GRAD_IBAR 6
+// the test interface's plane layout: 6 gradient planes, then the 21
+// upper-triangular entries of the block row by row
 #define SF_REC_PLANES 27
+
+// Slot of entry (i, j) of a pixel's symmetric block in its gram record.
+__host__ __device__ inline int gram_index(int i, int j) {
+    if (i > j) {
+        const int t = i;
+        i = j;
+        j = t;
+    }
+    return i == j ? i : 6 + i * 5 - (i * (i - 1)) / 2 + (j - i - 1);
+}
 
 // Node vectors (each 6 planes of G_0 floats).  The PCG runs in the
 // single-reduction form: r, w = H u and s = H p alternate between two
@@ -85,8 +103,9 @@ struct DevScalars {
     double e_lin[6];                  // photo, grad, smooth, epi, mag, total
     double e_trial[SF_MAX_TRIALS][6]; // same for each trial step length
     PcgHist hist[SF_MAX_PCG + 2];
+    double e_init[2];  // fallback energies: learned, zero initialisation
+    int init_used;     // the learned initialisation was kept
     int n_valid;
-    int pad;
 };
 
 // Device log record (mirrors sf_iter_log).
@@ -124,11 +143,15 @@ struct LevelArgs {
     int Gxc, Gyc;          // node grid of the next coarser level
     int log_base;          // log slot of this level's first Gauss-Newton step
     int Wf, Hf;            // size of the next finer level (pyramid)
+    int learned;           // coarsest level initialised by the network
+    int W4, H4;            // size of the network's output (level 4)
+    const float *cnn_out;  // network output, 6 planes of W4 x H4
     const float4 *tex;     // this level's 4 images (image-major)
     const float4 *tex_fine;  // the next finer level's images
     const FrameIO *io;     // caller buffers (batched launches)
     float *nodes;          // base of all node vectors
-    float *rec;            // per-pixel records
+    float *gram;           // per-pixel Gauss-Newton blocks (SF_GRAM_STRIDE)
+    float *grad;           // per-pixel gradients (SF_GRAD_STRIDE)
     unsigned char *cmask;  // V(x) W(x)
     float *wnode;          // smoothness weights
     float *reg;            // 16 planes of G_0: per-node regulariser record
@@ -161,6 +184,9 @@ struct Launch {
 void launch_tex_level0(hipStream_t st, const Launch &L, const float *const img[4]);
 void launch_downsample(hipStream_t st, const Launch &L);
 void launch_level_init(hipStream_t st, const Launch &L);
+// network candidate for the coarsest level and the fallback energies
+// (before launch_level_init)
+void launch_cnn_candidate(hipStream_t st, const Launch &L);
 void launch_linearize(hipStream_t st, const Launch &L);
 void launch_trial(hipStream_t st, const Launch &L, int trial, float tau);
 void launch_rhs(hipStream_t st, const Launch &L, const TileCfg &t);

@@ -15,6 +15,7 @@
 // order in double precision.
 #include <math.h>
 
+#include "sf_cnn.h"
 #include "sf_internal.h"
 
 // Node-tile shape per grid stride S: tx x ty nodes, tpn threads per node
@@ -393,6 +394,25 @@ __device__ void stage_nodes(const LevelArgs &a, int x0, int y0, float tau,
     }
 }
 
+// Node values of one vector (6 planes) that a pixel tile touches, staged
+// in LDS like stage_nodes.
+__device__ void stage_vector(const LevelArgs &a, int x0, int y0, const float *vec,
+                             NodeStage &S) {
+    const LevelDims &d = a.d;
+    const int x1 = min(x0 + TILE_PX - 1, d.W - 1);
+    const int y1 = min(y0 + TILE_PX - 1, d.H - 1);
+    const Bracket bx0 = bracket(x0, a.s, d.Gx), bx1 = bracket(x1, a.s, d.Gx);
+    const Bracket by0 = bracket(y0, a.s, d.Gy), by1 = bracket(y1, a.s, d.Gy);
+    const int nx0 = bx0.i0, nx1 = bx1.i1, ny0 = by0.i0, ny1 = by1.i1;
+    const int cw = nx1 - nx0 + 1, ch = ny1 - ny0 + 1;
+    if (threadIdx.x == 0) { S.nx0 = nx0; S.ny0 = ny0; }
+    for (int t = threadIdx.x; t < 6 * cw * ch; t += blockDim.x) {
+        const int q = t / (cw * ch), r = t % (cw * ch);
+        const int j = r / cw, i = r % cw;
+        S.t[q][j][i] = vec[q * a.G0 + (long)(ny0 + j) * d.Gx + (nx0 + i)];
+    }
+}
+
 struct PixelOut {
     float e_photo, e_grad;
     float grad[6];
@@ -591,10 +611,19 @@ __global__ __launch_bounds__(SF_BLOCK) void k_energy(KArg<B> ka, int trial, floa
             part[0] = o.e_photo;
             part[1] = o.e_grad;
             if (LIN) {
+                float g24[SF_GRAM_STRIDE];
 #pragma unroll
-                for (int q = 0; q < 6; ++q) a.rec[(long)q * a.N0 + pix] = o.grad[q];
+                for (int i = 0; i < 6; ++i)
 #pragma unroll
-                for (int t = 0; t < 21; ++t) a.rec[(long)(6 + t) * a.N0 + pix] = o.gram[t];
+                    for (int j = i; j < 6; ++j) g24[gram_index(i, j)] = o.gram[tri(i, j)];
+                g24[21] = g24[22] = g24[23] = 0.f;
+                float4 *gp = reinterpret_cast<float4 *>(a.gram + (long)pix * SF_GRAM_STRIDE);
+#pragma unroll
+                for (int v = 0; v < 6; ++v)
+                    gp[v] = make_float4(g24[4 * v], g24[4 * v + 1], g24[4 * v + 2], g24[4 * v + 3]);
+                float4 *rp = reinterpret_cast<float4 *>(a.grad + (long)pix * SF_GRAD_STRIDE);
+                rp[0] = make_float4(o.grad[0], o.grad[1], o.grad[2], o.grad[3]);
+                rp[1] = make_float4(o.grad[4], o.grad[5], 0.f, 0.f);
             }
         }
     } else {
@@ -832,14 +861,13 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(KArg<B> ka, TileCfg t
         }
     }
     tile_brackets(a, g, L);
-    const float *rec = a.rec;
-    const long N0 = a.N0;
     pixels_to_lds<12>(g, L, [&](int x, int y, int, int, float (&v)[12]) {
         const long pix = (long)y * d.W + x;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) v[q] = rec[q * N0 + pix];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) v[6 + q] = rec[(6 + tri(q, q)) * N0 + pix];
+        const float4 *rp = reinterpret_cast<const float4 *>(a.grad + pix * SF_GRAD_STRIDE);
+        const float4 *gp = reinterpret_cast<const float4 *>(a.gram + pix * SF_GRAM_STRIDE);
+        const float4 r0 = rp[0], r1 = rp[1], g0 = gp[0], g1 = gp[1];
+        v[0] = r0.x; v[1] = r0.y; v[2] = r0.z; v[3] = r0.w; v[4] = r1.x; v[5] = r1.y;
+        v[6] = g0.x; v[7] = g0.y; v[8] = g0.z; v[9] = g0.w; v[10] = g1.x; v[11] = g1.y;
     });
     __syncthreads();
     float acc[12];
@@ -1019,17 +1047,22 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_pcg(KArg<B> ka, TileCfg t
         if (tid == 0) h = a.sc->hist[i - 1];
     }
     // Gram blocks of this thread's region pixels
-    const float *gram = a.rec + 6 * (long)a.N0;
-    const long N0 = a.N0;
     const int npx = g.RX * g.RY;
-    float Gm[PPT][21];
+    float Gm[PPT][SF_GRAM_STRIDE];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int u = tid + k * NT_TILE;
         if (u < npx) {
             const long pix = (long)(g.Y0 + u / g.RX) * d.W + g.X0 + u % g.RX;
+            const float4 *gp = reinterpret_cast<const float4 *>(a.gram + pix * SF_GRAM_STRIDE);
 #pragma unroll
-            for (int e = 0; e < 21; ++e) Gm[k][e] = gram[e * N0 + pix];
+            for (int v = 0; v < 6; ++v) {
+                const float4 t4 = gp[v];
+                Gm[k][4 * v] = t4.x;
+                Gm[k][4 * v + 1] = t4.y;
+                Gm[k][4 * v + 2] = t4.z;
+                Gm[k][4 * v + 3] = t4.w;
+            }
         }
     }
     // halo node of this thread: the vectors u_i is formed from
@@ -1129,7 +1162,7 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_pcg(KArg<B> ka, TileCfg t
             for (int r = 0; r < 6; ++r) {
                 float acc = 0.f;
 #pragma unroll
-                for (int c = 0; c < 6; ++c) acc += Gm[k][r <= c ? tri(r, c) : tri(c, r)] * pv[c];
+                for (int c = 0; c < 6; ++c) acc += Gm[k][gram_index(r, c)] * pv[c];
                 L.vals[(r * g.RY + ry) * g.RX + rx] = acc;
             }
         }
@@ -1314,23 +1347,137 @@ __global__ __launch_bounds__(SF_BLOCK) void k_accept(KArg<B> ka, int n_trials, i
 
 // ---- level start: prolongation, masks, smoothness weights -------------------
 
+// ---- learned initialisation of the coarsest level --------------------------
+
+// Candidate node flows: the network output (level-4 pixels) sampled at the
+// coarsest level's nodes; node position p maps to 2^(l - 4) (p + 1/2) - 1/2
+// in level-4 pixels (pixel-centre convention), clamp-to-edge bilinear, and
+// flows scale by 2^(4 - l).  Stored in the P vector (free at level start).
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_cnn_nodes(KArg<B> ka) {
+    SF_BIND(ka);
+    const long n = (long)bid * SF_BLOCK + threadIdx.x;
+    if (n >= a.d.G) return;
+    const int i = (int)(n % a.d.Gx), j = (int)(n / a.d.Gx);
+    float gx, gy;
+    node_xy(i, j, a.s, gx, gy);
+    const float r = ldexpf(1.f, a.level - SF_CNN_INPUT_LEVEL);
+    const int W4 = a.W4, H4 = a.H4;
+    const float u = fminf(fmaxf(r * (gx + 0.5f) - 0.5f, 0.f), (float)(W4 - 1));
+    const float v = fminf(fmaxf(r * (gy + 0.5f) - 0.5f, 0.f), (float)(H4 - 1));
+    const int x0 = min((int)floorf(u), max(W4 - 2, 0)), y0 = min((int)floorf(v), max(H4 - 2, 0));
+    const int x1 = min(x0 + 1, W4 - 1), y1 = min(y0 + 1, H4 - 1);
+    const float fx = u - (float)x0, fy = v - (float)y0;
+    float *P = a.nodes + (long)NV_P * 6 * a.G0;
+    const long N4 = (long)W4 * H4;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const float *o = a.cnn_out + q * N4;
+        const float val = (1.f - fy) * ((1.f - fx) * o[y0 * W4 + x0] + fx * o[y0 * W4 + x1]) +
+                          fy * ((1.f - fx) * o[y1 * W4 + x0] + fx * o[y1 * W4 + x1]);
+        P[q * a.G0 + n] = val / r;
+    }
+}
+
+// Energies of Eq. (8) at zero deltas for the candidate (P vector) and for
+// the zero initialisation, with the same visibility mask for both (all
+// four positions inside the image under the candidate; the zero flow keeps
+// every position inside) and no colour pruning.  Per-workgroup partials of
+// both totals in the first two energy planes.
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_fallback(KArg<B> ka) {
+    SF_BIND(ka);
+    const LevelDims &d = a.d;
+    const DevConst &C = *a.cst;
+    const int n_pix = pixel_tiles(d);
+    __shared__ NodeStage S;
+    float part[2] = {0.f, 0.f};
+    if (bid < n_pix) {
+        const int tiles_x = (d.W + TILE_PX - 1) / TILE_PX;
+        const int x0 = (bid % tiles_x) * TILE_PX, y0 = (bid / tiles_x) * TILE_PX;
+        stage_vector(a, x0, y0, a.nodes + (long)NV_P * 6 * a.G0, S);
+        __syncthreads();
+        const int x = x0 + (threadIdx.x & (TILE_PX - 1));
+        const int y = y0 + (threadIdx.x / TILE_PX);
+        if (x < d.W && y < d.H) {
+            float f[6];
+            pixel_flows(a, x, y, S, f);
+            bool V = true;
+#pragma unroll
+            for (int cam = 0; cam < 4; ++cam) {
+                const float px = (((float)x + sgn(cam, 0) * f[0]) + sgn(cam, 1) * f[2]) + sgn(cam, 2) * f[4];
+                const float py = (((float)y + sgn(cam, 0) * f[1]) + sgn(cam, 1) * f[3]) + sgn(cam, 2) * f[5];
+                V = V && px >= 0.f && px <= (float)(d.W - 1) && py >= 0.f && py <= (float)(d.H - 1);
+            }
+            const float c = V ? 1.f : 0.f;
+            const float z[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            PixelOut o;
+            pixel_terms<false>(a, x, y, f, c, o);
+            part[0] = C.w_photo * o.e_photo + C.w_grad * o.e_grad;
+            pixel_terms<false>(a, x, y, z, c, o);
+            part[1] = C.w_photo * o.e_photo + C.w_grad * o.e_grad;
+        }
+    } else {
+        const long n = (long)(bid - n_pix) * SF_BLOCK + threadIdx.x;
+        if (n < d.G) {
+            const int i = (int)(n % d.Gx), j = (int)(n / d.Gx);
+            float gx, gy;
+            node_xy(i, j, a.s, gx, gy);
+            const float *P = a.nodes + (long)NV_P * 6 * a.G0;
+            float tot[6], zero[6], e[2], J[2][6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                tot[q] = P[q * a.G0 + n];
+                zero[q] = 0.f;
+            }
+            const float ce = C.w_reg * C.w_epi;
+            epi_terms(C.F[a.level], gx, gy, tot, e, J);
+            part[0] = ce * (e[0] * e[0] + e[1] * e[1]);
+            epi_terms(C.F[a.level], gx, gy, zero, e, J);
+            part[1] = ce * (e[0] * e[0] + e[1] * e[1]);
+        }
+    }
+    float tot2[2];
+    block_sum<2>(part, tot2);
+    if (threadIdx.x == 0) {
+        a.partials[(long)PS_E * a.max_blocks + bid] = tot2[0];
+        a.partials[(long)(PS_E + 1) * a.max_blocks + bid] = tot2[1];
+    }
+}
+
 // base_l = 2 bilerp(total_{l+1}) at coarse-node coordinate i/2 - 1/4
-// (Sec. 5.3), or zero at the coarsest level; delta = 0.
+// (Sec. 5.3); at the coarsest level zero, or the network's candidate if the
+// fallback energies favour it (ties keep zero); delta = 0.
 template <bool B>
 __global__ __launch_bounds__(SF_BLOCK) void k_prolong(KArg<B> ka) {
     SF_BIND(ka);
     const int Gxc = a.Gxc, Gyc = a.Gyc, coarsest = a.coarsest;
+    int use_cnn = 0;
+    if (coarsest && a.learned) {
+        const int nb = energy_blocks_of(a.d);
+        const double ec = block_sum_partials(a.partials + (long)PS_E * a.max_blocks, nb);
+        const double ez = block_sum_partials(a.partials + (long)(PS_E + 1) * a.max_blocks, nb);
+        use_cnn = ec < ez ? 1 : 0;
+        if (bid == 0 && threadIdx.x == 0) {
+            a.sc->e_init[0] = ec;
+            a.sc->e_init[1] = ez;
+            a.sc->init_used = use_cnn;
+        }
+    }
     const long n = (long)bid * SF_BLOCK + threadIdx.x;
     if (n >= a.d.G) return;
     const long G0 = a.G0;
     float *base = a.nodes + (long)NV_BASE * 6 * G0;
     float *delta = a.nodes + (long)NV_DELTA * 6 * G0;
     const float *tp = a.nodes + (long)NV_TPREV * 6 * G0;
+    const float *cand = a.nodes + (long)NV_P * 6 * G0;
     const int i = (int)(n % a.d.Gx), j = (int)(n / a.d.Gx);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         float v = 0.f;
-        if (!coarsest) {
+        if (coarsest) {
+            v = use_cnn ? cand[q * G0 + n] : 0.f;
+        } else {
             // fine node i has coarse coordinate (2i - 1)/4: the bracket rule
             // with stride 2
             const Bracket bx = bracket(i, 2, Gxc), by = bracket(j, 2, Gyc);
@@ -1379,7 +1526,7 @@ __global__ __launch_bounds__(SF_BLOCK) void k_masks(KArg<B> ka) {
         const bool Wm = dmax < C.eps_p;
         const int pix = y * d.W + x;
         a.cmask[pix] = (V && Wm) ? 1 : 0;
-        a.rec[pix] = 0.25f * (((I[0] + I[1]) + I[2]) + I[3]);
+        a.grad[(long)pix * SF_GRAD_STRIDE + SF_GRAD_IBAR] = 0.25f * (((I[0] + I[1]) + I[2]) + I[3]);
         cnt[0] = (V && Wm) ? 1.f : 0.f;
     }
     float tot1[1];
@@ -1402,7 +1549,8 @@ __global__ __launch_bounds__(SF_BLOCK) void k_node_weights(KArg<B> ka) {
     if (n >= d.G) return;
     const DevConst &C = *a.cst;
     const int i = (int)(n % d.Gx), j = (int)(n / d.Gx);
-    const float *Ib = a.rec;
+    // mean warped image of pixel (x, y), stored by the mask kernel
+    auto Ib = [&](int x, int y) { return a.grad[((long)y * d.W + x) * SF_GRAD_STRIDE + SF_GRAD_IBAR]; };
     const int cx = min(((2 * i + 1) * a.s) / 2, d.W - 1);
     const int cy = min(((2 * j + 1) * a.s) / 2, d.H - 1);
     float A = 0.f, Bt = 0.f, Cc = 0.f;
@@ -1411,12 +1559,12 @@ __global__ __launch_bounds__(SF_BLOCK) void k_node_weights(KArg<B> ka) {
             const int xx = min(max(cx + dx, 0), d.W - 1);
             const int yy = min(max(cy + dy, 0), d.H - 1);
             float gx, gy;
-            if (xx == 0) gx = Ib[yy * d.W + 1] - Ib[yy * d.W];
-            else if (xx == d.W - 1) gx = Ib[yy * d.W + xx] - Ib[yy * d.W + xx - 1];
-            else gx = 0.5f * (Ib[yy * d.W + xx + 1] - Ib[yy * d.W + xx - 1]);
-            if (yy == 0) gy = Ib[d.W + xx] - Ib[xx];
-            else if (yy == d.H - 1) gy = Ib[yy * d.W + xx] - Ib[(yy - 1) * d.W + xx];
-            else gy = 0.5f * (Ib[(yy + 1) * d.W + xx] - Ib[(yy - 1) * d.W + xx]);
+            if (xx == 0) gx = Ib(1, yy) - Ib(0, yy);
+            else if (xx == d.W - 1) gx = Ib(xx, yy) - Ib(xx - 1, yy);
+            else gx = 0.5f * (Ib(xx + 1, yy) - Ib(xx - 1, yy));
+            if (yy == 0) gy = Ib(xx, 1) - Ib(xx, 0);
+            else if (yy == d.H - 1) gy = Ib(xx, yy) - Ib(xx, yy - 1);
+            else gy = 0.5f * (Ib(xx, yy + 1) - Ib(xx, yy - 1));
             A += gx * gx;
             Bt += gx * gy;
             Cc += gy * gy;
@@ -1583,6 +1731,11 @@ void launch_tex_level0(hipStream_t st, const Launch &L, const float *const img[4
 
 void launch_downsample(hipStream_t st, const Launch &L) {
     go(st, L, tx_blocks, k_texl<true>, k_texl<false>, SF_BLOCK, 0);
+}
+
+void launch_cnn_candidate(hipStream_t st, const Launch &L) {
+    go(st, L, nd_blocks, k_cnn_nodes<true>, k_cnn_nodes<false>, SF_BLOCK, 0);
+    go(st, L, en_blocks, k_fallback<true>, k_fallback<false>, SF_BLOCK, 0);
 }
 
 void launch_level_init(hipStream_t st, const Launch &L) {

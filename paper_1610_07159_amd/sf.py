@@ -27,6 +27,8 @@ SF_DBG_REC, SF_DBG_P, SF_DBG_ENERGY = 10, 11, 12
 SF_STAGE_LEVEL_INIT, SF_STAGE_LINEARIZE, SF_STAGE_APPLY = 0, 1, 2
 SF_STAGE_PCG, SF_STAGE_GN, SF_STAGE_FINISH = 3, 4, 5
 SF_KERNEL_APPLY, SF_KERNEL_LINEARIZE, SF_KERNEL_UPDATE, SF_KERNEL_RHS = 0, 1, 2, 3
+SF_CNN_PARAMS = 39910
+SF_TR_INPUT, SF_TR_ACT, SF_TR_OUT, SF_TR_DOUT, SF_TR_DPRE, SF_TR_GRAD = 0, 1, 2, 3, 4, 5
 
 
 class SfError(RuntimeError):
@@ -117,6 +119,26 @@ def _load():
                                    ctypes.POINTER(sf_params)]
     lib.sf_get_batch_log.argtypes = [P, I, ctypes.POINTER(sf_iter_log), I,
                                      ctypes.POINTER(I)]
+    F = ctypes.c_float
+    D = ctypes.c_double
+    S = ctypes.c_size_t
+    lib.sf_set_initializer.argtypes = [P, P, S]
+    lib.sf_get_init_result.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(D),
+                                       ctypes.POINTER(D)]
+    lib.sf_trainer_create.argtypes = [ctypes.POINTER(P), I, I, I, P]
+    lib.sf_trainer_set_params.argtypes = [P, P, S]
+    lib.sf_trainer_get_params.argtypes = [P, P, S]
+    lib.sf_trainer_forward.argtypes = [P, P, I, P]
+    lib.sf_trainer_step.argtypes = [P, P, P, I, F, ctypes.POINTER(F)]
+    lib.sf_trainer_size.argtypes = [P, I, I]
+    lib.sf_trainer_size.restype = S
+    lib.sf_trainer_read.argtypes = [P, I, I, P, S]
+    lib.sf_trainer_destroy.argtypes = [P]
+    lib.sf_trainer_destroy.restype = None
+    for f in ("sf_set_initializer", "sf_get_init_result", "sf_trainer_create",
+              "sf_trainer_set_params", "sf_trainer_get_params", "sf_trainer_forward",
+              "sf_trainer_step", "sf_trainer_read"):
+        getattr(lib, f).restype = I
     for f in ("sf_params_default", "sf_create", "sf_solve", "sf_get_log",
               "sf_debug_read", "sf_debug_write", "sf_debug_set_images",
               "sf_debug_run", "sf_time_kernel", "sf_time_batch_kernel",
@@ -282,3 +304,79 @@ def sf_time_batch_kernel(ctx, kernel, level, reps) -> float:
     _check(lib.sf_time_batch_kernel(ctx, kernel, level, reps, ctypes.byref(ms)),
            "sf_time_batch_kernel")
     return ms.value
+
+
+# ---- learned initialiser --------------------------------------------------
+
+def bf16_bits(values) -> np.ndarray:
+    """float values -> bfloat16 bit patterns (uint16), round to nearest even."""
+    f = np.ascontiguousarray(values, np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    return (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF).astype(np.uint16)
+
+
+def sf_set_initializer(ctx, weights):
+    """weights: SF_CNN_PARAMS values (float, rounded to bfloat16 here) or
+    uint16 bfloat16 bit patterns."""
+    w = np.asarray(weights)
+    bits = w if w.dtype == np.uint16 else bf16_bits(w)
+    bits = np.ascontiguousarray(bits)
+    _check(lib.sf_set_initializer(ctx, bits.ctypes.data, bits.nbytes), "sf_set_initializer")
+
+
+def sf_get_init_result(ctx):
+    used, ep, ez = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+    _check(lib.sf_get_init_result(ctx, ctypes.byref(used), ctypes.byref(ep), ctypes.byref(ez)),
+           "sf_get_init_result")
+    return bool(used.value), ep.value, ez.value
+
+
+def sf_trainer_create(max_batch, height, width, stream=0):
+    h = ctypes.c_void_p()
+    _check(lib.sf_trainer_create(ctypes.byref(h), int(max_batch), int(height), int(width),
+                                 ctypes.c_void_p(stream)), "sf_trainer_create")
+    return h
+
+
+def sf_trainer_set_params(t, flat):
+    a = np.ascontiguousarray(flat, np.float32)
+    _check(lib.sf_trainer_set_params(t, a.ctypes.data, a.size), "sf_trainer_set_params")
+
+
+def sf_trainer_get_params(t):
+    a = np.empty(SF_CNN_PARAMS, np.float32)
+    _check(lib.sf_trainer_get_params(t, a.ctypes.data, a.size), "sf_trainer_get_params")
+    return a
+
+
+def sf_trainer_forward(t, x, batch, out):
+    _check(lib.sf_trainer_forward(t, x, int(batch), out), "sf_trainer_forward")
+
+
+def sf_trainer_step(t, x, target, batch, lr, want_loss=True):
+    loss = ctypes.c_float()
+    _check(lib.sf_trainer_step(t, x, target, int(batch), float(lr),
+                               ctypes.byref(loss) if want_loss else None), "sf_trainer_step")
+    return loss.value if want_loss else None
+
+
+_TR_DTYPE = {SF_TR_INPUT: np.uint16, SF_TR_ACT: np.uint16, SF_TR_OUT: np.float32,
+             SF_TR_DOUT: np.uint16, SF_TR_DPRE: np.uint16, SF_TR_GRAD: np.float32}
+
+
+def sf_trainer_read(t, what, layer=0):
+    n = lib.sf_trainer_size(t, what, layer)
+    if n == 0:
+        raise SfError(-1, "sf_trainer_size")
+    dt = _TR_DTYPE[what]
+    a = np.empty(n // np.dtype(dt).itemsize, dt)
+    _check(lib.sf_trainer_read(t, what, layer, a.ctypes.data, n), "sf_trainer_read")
+    return a
+
+
+def bf16_to_float(bits) -> np.ndarray:
+    return (np.asarray(bits, np.uint16).astype(np.uint32) << 16).view(np.float32)
+
+
+def sf_trainer_destroy(t):
+    lib.sf_trainer_destroy(t)
