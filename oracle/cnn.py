@@ -261,26 +261,26 @@ def choose_init(li, grid, F_l, p, base_cnn):
     return (np.asarray(base_cnn, np.float64) if use else zero), bool(use), e_cnn, e_zero
 
 
-def predict_coarsest(flat, images, p):
+def predict_coarsest(flat, images, p, bf16=False):
     """Whole inference path on a frame (4, H, W): pyramid, network on level
     4, sampling at the coarsest level's nodes.  Needs p.levels >= 5."""
     assert p.levels > INPUT_LEVEL
     pyr = HW.pyramid(np.asarray(images, np.float64), p.levels)
-    out, _ = forward(flat, network_input(pyr[INPUT_LEVEL]))
+    out, _ = forward(flat, network_input(pyr[INPUT_LEVEL]), bf16=bf16)
     lc = p.levels - 1
     H, W = pyr[lc].shape[1:]
     grid = HW.Grid(W, H, p.grid_stride)
     return sample_at_nodes(out[0], grid, lc), out[0]
 
 
-def solve_learned(flat, images, calib, p, record=None):
+def solve_learned(flat, images, calib, p, record=None, bf16=False):
     """The solve of Algorithm 1 started from the learned initialisation with
     the fallback: predict, choose against zero at the coarsest level, then
     the usual hierarchy.  Returns (oracle solve result, used_prediction,
     E_pred, E_zero)."""
     if isinstance(calib, dict):
         calib = HW.Calib.from_dict(calib)
-    cand, _ = predict_coarsest(flat, images, p)
+    cand, _ = predict_coarsest(flat, images, p, bf16=bf16)
     lc = p.levels - 1
     pyr = HW.pyramid(np.asarray(images, np.float64), p.levels)
     li = HW.LevelImages.build(pyr[lc])

@@ -1,0 +1,226 @@
+"""The learned initialiser on the GPU (bf16 MFMA network, trainer, and its
+use in the solve) against the FP64 oracle of oracle/cnn.py run in its
+bfloat16-emulating mode (the same roundings of weights, input, hidden
+activations and gradients, exact sums).  The two then differ only where
+float32 accumulation puts a value on the other side of a bfloat16 rounding
+boundary (one unit in the last place, 2^-8 relative), and such flips
+propagate through later layers; the tolerances below allow that and
+nothing more."""
+import numpy as np
+import pytest
+
+import oracle.cnn as C
+import oracle.halfway as O
+from synth import make_frame, sized_config
+
+from gpu_util import GpuCase, oracle_params
+
+pytestmark = pytest.mark.gpu
+
+ULP = 2.0 ** -7
+
+
+def _close_bf16(gpu, ref, what, frac=0.995, max_rel=0.05, norm_rel=5e-3):
+    gpu = np.asarray(gpu, np.float64)
+    ref = np.asarray(ref, np.float64)
+    err = np.abs(gpu - ref)
+    scale = max(np.abs(ref).max(), 1e-30)
+    ok = err <= ULP * np.abs(ref) + 1e-6 * scale
+    assert ok.mean() >= frac, (what, ok.mean())
+    assert err.max() <= max_rel * scale, (what, err.max() / scale)
+    assert np.linalg.norm(err) <= norm_rel * max(np.linalg.norm(ref), 1e-30), what
+
+
+def _nchw(bits, B, H, W, C_):
+    from paper_1610_07159_amd import sf
+    return sf.bf16_to_float(bits).reshape(B, H, W, C_).transpose(0, 3, 1, 2)
+
+
+def _trainer(B, H, W, flat):
+    import torch
+    from paper_1610_07159_amd import sf
+    t = sf.sf_trainer_create(B, H, W, torch.cuda.current_stream().cuda_stream)
+    sf.sf_trainer_set_params(t, flat)
+    return t
+
+
+def _params(seed, noise=0.02):
+    rng = np.random.default_rng(seed)
+    flat = C.init_params(seed) + rng.normal(0, noise, C.N_PARAMS)
+    return flat.astype(np.float32)
+
+
+def test_forward_matches_oracle():
+    import torch
+    from paper_1610_07159_amd import sf
+    B, H, W = 2, 30, 40  # rows of 40 px: two full 16-px segments and a ragged one
+    flat = _params(1)
+    imgs = np.random.default_rng(2).random((B, 4, H, W)).astype(np.float32)
+    t = _trainer(B, H, W, flat)
+    try:
+        x = torch.from_numpy(imgs).cuda()
+        out = torch.empty((B, 6, H, W), device="cuda")
+        sf.sf_trainer_forward(t, x.data_ptr(), B, out.data_ptr())
+        ref, acts = C.forward(flat.astype(np.float64), imgs.astype(np.float64) - 0.5, bf16=True)
+        xin = _nchw(sf.sf_trainer_read(t, sf.SF_TR_INPUT), B, H, W, 16)
+        np.testing.assert_array_equal(xin[:, :4], acts[0])
+        assert np.all(xin[:, 4:] == 0)
+        for l in range(5):
+            a = _nchw(sf.sf_trainer_read(t, sf.SF_TR_ACT, l), B, H, W, 32)
+            _close_bf16(a, acts[l + 1], f"act{l}")
+        _close_bf16(out.cpu().numpy(), ref, "out")
+    finally:
+        sf.sf_trainer_destroy(t)
+
+
+def test_backward_and_adam_match_oracle():
+    import torch
+    from paper_1610_07159_amd import sf
+    B, H, W = 2, 24, 33
+    flat = _params(3)
+    rng = np.random.default_rng(4)
+    imgs = rng.random((B, 4, H, W)).astype(np.float32)
+    tgt = (0.5 * rng.normal(size=(B, 6, H, W))).astype(np.float32)
+    t = _trainer(B, H, W, flat)
+    try:
+        x = torch.from_numpy(imgs).cuda()
+        y = torch.from_numpy(tgt).cuda()
+        loss = sf.sf_trainer_step(t, x.data_ptr(), y.data_ptr(), B, 0.0)
+        np.testing.assert_array_equal(sf.sf_trainer_get_params(t), flat)  # lr = 0
+        f64 = flat.astype(np.float64)
+        out, acts = C.forward(f64, imgs.astype(np.float64) - 0.5, bf16=True)
+        loss_ref, dout = C.l1_loss(out, tgt, bf16=True)
+        assert loss == pytest.approx(loss_ref, rel=1e-3)
+        gd = _nchw(sf.sf_trainer_read(t, sf.SF_TR_DOUT), B, H, W, 16)
+        assert np.all(gd[:, 6:] == 0)
+        assert (gd[:, :6] == dout).mean() >= 0.999  # sign flips only where out ~ target
+        hid = C.hidden_gradients(f64, acts, dout, bf16=True)
+        for l in range(5):
+            d = _nchw(sf.sf_trainer_read(t, sf.SF_TR_DPRE, l), B, H, W, 32)
+            _close_bf16(d, hid[l], f"dpre{l}", frac=0.99, max_rel=0.1, norm_rel=1e-2)
+        g = sf.sf_trainer_read(t, sf.SF_TR_GRAD).astype(np.float64)
+        g_ref = C.backward(f64, acts, dout, bf16=True)
+        L = C.unpack(np.arange(C.N_PARAMS))
+        k = 0
+        for l, (Wl, bl) in enumerate(L):
+            n = Wl.size + bl.size
+            gl, rl = g[k:k + n], g_ref[k:k + n]
+            assert np.linalg.norm(gl - rl) <= 1e-2 * np.linalg.norm(rl), l
+            k += n
+        # Adam: the lr = 0 step counted as step 1; step 2 with lr on the
+        # same batch (same gradient, parameters unchanged by step 1)
+        lr = 1e-3
+        sf.sf_trainer_step(t, x.data_ptr(), y.data_ptr(), B, lr, want_loss=False)
+        p_gpu = sf.sf_trainer_get_params(t).astype(np.float64)
+        p1, m, v = C.adam_step(f64, g_ref, np.zeros(C.N_PARAMS), np.zeros(C.N_PARAMS), 1, 0.0)
+        p_ref, _, _ = C.adam_step(p1, g_ref, m, v, 2, lr)
+        dev = np.abs(p_gpu - p_ref)
+        assert (dev <= 0.02 * lr).mean() >= 0.98
+        assert dev.max() <= 2.5 * lr
+    finally:
+        sf.sf_trainer_destroy(t)
+
+
+def test_training_lowers_the_loss():
+    import torch
+    from paper_1610_07159_amd import sf
+    B, H, W = 4, 20, 28
+    rng = np.random.default_rng(5)
+    imgs = rng.random((B, 4, H, W)).astype(np.float32)
+    tgt = np.repeat((imgs[:, :1] - imgs[:, 1:2]), 6, axis=1).astype(np.float32)
+    t = _trainer(B, H, W, C.init_params(6).astype(np.float32))
+    try:
+        x = torch.from_numpy(imgs).cuda()
+        y = torch.from_numpy(np.ascontiguousarray(tgt)).cuda()
+        losses = [sf.sf_trainer_step(t, x.data_ptr(), y.data_ptr(), B, 3e-3) for _ in range(60)]
+        assert np.isfinite(losses).all()
+        assert losses[-1] < 0.6 * losses[0], losses[::10]
+    finally:
+        sf.sf_trainer_destroy(t)
+
+
+# ---- the initialiser inside the solve ----------------------------------------
+
+PRM = dict(levels=5, grid_stride=4, gn_iters=2, pcg_iters=6)
+
+
+def _frame(seed=30, W=256, H=192):
+    imgs, calib, scene = make_frame(sized_config(W, H, max_disp=12.0), seed)
+    return imgs, calib, scene
+
+
+def _solve(imgs, calib, init_mode, weights=None):
+    from paper_1610_07159_amd import sf
+    g = GpuCase(imgs, calib, exec_mode=0, init_mode=init_mode, **PRM)
+    try:
+        if weights is not None:
+            sf.sf_set_initializer(g.ctx, weights)
+        res = g.solve()
+        log, code = g.log()
+        info = sf.sf_get_init_result(g.ctx) if init_mode == 1 else None
+    finally:
+        g.close()
+    assert code == 0
+    return res, log, info
+
+
+def test_fallback_rejects_a_bad_network_and_matches_zero_init():
+    imgs, calib, _ = _frame()
+    bad = np.random.default_rng(7).normal(0, 3.0, C.N_PARAMS).astype(np.float32)
+    res1, log1, (used, ep, ez) = _solve(imgs, calib, 1, bad)
+    res0, log0, _ = _solve(imgs, calib, 0)
+    assert not used and ep > ez
+    for a, b in zip(res0, res1):
+        np.testing.assert_array_equal(a, b)
+    assert [r["energy"] for r in log0] == [r["energy"] for r in log1]
+
+
+def _constant_network(scene, W, H):
+    """All weights zero, output biases = the generator's mean halfway flow
+    at level 4 (bf16-representable after rounding): the network's output is
+    exactly constant."""
+    pos, ok = scene.halfway_truth()
+    from synth import halfway_flows_from_positions
+    s, m, d = halfway_flows_from_positions(pos)
+    mean = np.concatenate([s, m, d]).reshape(6, -1)[:, ok.reshape(-1)].mean(1) / 16.0
+    flat = np.zeros(C.N_PARAMS)
+    L = C.unpack(np.arange(C.N_PARAMS))
+    off = C.N_PARAMS - L[-1][1].size
+    flat[off:] = C.bf16_round(mean)
+    return flat
+
+
+def test_constant_network_solve_matches_oracle():
+    imgs, calib, scene = _frame(seed=31)
+    flat = _constant_network(scene, 256, 192)
+    res, log, (used, ep, ez) = _solve(imgs, calib, 1, flat.astype(np.float32))
+    p = oracle_params(**PRM)
+    rec = []
+    ref, used_ref, ep_ref, ez_ref = C.solve_learned(flat, imgs.astype(np.float64), calib, p,
+                                                   record=rec, bf16=True)
+    assert used == used_ref
+    assert ep == pytest.approx(ep_ref, rel=1e-4) and ez == pytest.approx(ez_ref, rel=1e-4)
+    assert len(log) == len(rec)
+    for lg, ro in zip(log, rec):
+        assert abs(lg["energy"] - ro["energy"]) <= 1e-4 * abs(ro["energy"])
+    grid = ref["grid"]
+    flows = grid.to_pixels(ref["total"]).reshape(6, grid.H, grid.W)
+    assert np.abs(res[2] - flows).max() <= 0.02
+
+
+def test_random_network_fallback_energies_match_oracle():
+    imgs, calib, _ = _frame(seed=32)
+    flat = _params(8, noise=0.0).astype(np.float64)
+    _, _, (used, ep, ez) = _solve(imgs, calib, 1, flat.astype(np.float32))
+    p = oracle_params(**PRM)
+    cand, _ = C.predict_coarsest(flat, imgs.astype(np.float64), p, bf16=True)
+    pyr = O.pyramid(imgs.astype(np.float64), p.levels)
+    li = O.LevelImages.build(pyr[4])
+    H, W = li.shape
+    grid = O.Grid(W, H, p.grid_stride)
+    F4 = O.level_calib_F(O.Calib.from_dict(calib).F, 4)
+    ep_ref, ez_ref = C.fallback_energies(li, grid, F4, p, cand, np.zeros_like(cand))
+    assert ez == pytest.approx(ez_ref, rel=1e-5)
+    assert ep == pytest.approx(ep_ref, rel=2e-3)
+    if abs(ep_ref - ez_ref) > 5e-3 * ez_ref:
+        assert used == (ep_ref < ez_ref)
