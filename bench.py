@@ -40,6 +40,14 @@ WORKLOADS = {
                     "moving blobs; stride 4, 6 levels, 10 GN x 20 PCG",
                width=1280, height=720, seed=2,
                params=dict(levels=6, grid_stride=4, gn_iters=10, pcg_iters=20)),
+    "learned": dict(desc="learned-init vs plain at equal EPE: 16 held-out 640x480 "
+                         "generator frames (seeds 1000000..1000015, 30 px displacement); "
+                         "plain = zero initialisation, 10 GN x 20 PCG per level; learned = "
+                         "the stored initialiser (trained on 256 frames, seeds 0..255) with "
+                         "the energy fallback, fewest GN steps per level reaching the plain "
+                         "EPE; stride 4, 5 levels",
+                    width=640, height=480, n_eval=16,
+                    params=dict(levels=5, grid_stride=4, gn_iters=10, pcg_iters=20)),
     "batch": dict(desc="batches of 64 frames, resolutions drawn by seed 3 from "
                        "320x240 / 640x480 / 960x540 / 1280x720 (4 / 5 / 5 / 6 "
                        "levels: 1 + floor(log2(W / 40))), displacement 30 px per "
@@ -240,6 +248,8 @@ def main():
         del a, b
     if args.workload == "batch":
         return run_batch(args)
+    if args.workload == "learned":
+        return run_learned(args)
 
     from paper_1610_07159_amd import SceneFlowSolver, sf
 
@@ -311,6 +321,52 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(imgs, calib, params, W, H)
     solver.close()
+    print(json.dumps(result), flush=True)
+
+
+def run_learned(args):
+    """Equal-EPE comparison of the learned initialiser with the plain
+    solver; value = ms/frame of the learned solve at the plain EPE."""
+    from paper_1610_07159_amd import train_init as T
+    w = WORKLOADS["learned"]
+    W, H = w["width"], w["height"]
+    params = dict(w["params"])
+    weights = np.load(os.path.join(ROOT, "paper_1610_07159_amd", "weights", "init_640x480.npy"),
+                      allow_pickle=False)
+    frames = T.render_frames(W, H, range(1_000_000, 1_000_000 + w["n_eval"]), True, 8,
+                             log=lambda m: None)
+    plain, _, ms_plain = T.solve_flows(frames, W, H, timed=True, **params)
+    epe_plain = float(np.mean([T.epe(f, fr["truth"], W, H) for f, fr in zip(plain, frames)]))
+    sweep, reach = [], None
+    for n in range(1, params["gn_iters"] + 1):
+        fl, used, ms = T.solve_flows(frames, W, H, init_mode=1, weights=weights, timed=True,
+                                     **dict(params, gn_iters=n))
+        e = float(np.mean([T.epe(f, fr["truth"], W, H) for f, fr in zip(fl, frames)]))
+        sweep.append(dict(gn_iters=n, epe_px=round(e, 4), ms_per_frame=round(ms, 3),
+                          prediction_kept=int(sum(used))))
+        if e <= epe_plain:
+            reach = sweep[-1]
+            break
+    result = {
+        "metric": METRIC,
+        "value": reach["ms_per_frame"] if reach else None,
+        "unit": "ms/frame",
+        "n_gpus": 1,
+        "steps": 3 * w["n_eval"],
+        "warmup": w["n_eval"],
+        "ms_per_step": reach["ms_per_frame"] if reach else None,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 solve, bf16 initialiser",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], **params},
+        "plain": {"gn_iters": params["gn_iters"], "epe_px": round(epe_plain, 4),
+                  "ms_per_frame": round(ms_plain, 3)},
+        "learned_at_equal_epe": reach,
+        "speedup_at_equal_epe": round(ms_plain / reach["ms_per_frame"], 3) if reach else None,
+        "learned_sweep": sweep,
+    }
     print(json.dumps(result), flush=True)
 
 
