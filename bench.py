@@ -92,6 +92,54 @@ def make_batch_workload(w):
     return res, frames
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1610_07159_amd", "csrc", "sf_kernels.hip")
+
+
+def source_hash():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the level-0 H-product from the committed
+    counter summary (profiles/pcg_apply_<workload>_traffic.txt), or None if
+    it is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"pcg_apply_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != source_hash():
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
+def learned_vs_plain(solver_params, frames):
+    """Compact equal-EPE comparison for the headline line (see --workload
+    learned for the full sweep); frames rendered beforehand."""
+    from paper_1610_07159_amd import train_init as T
+    W, H = 640, 480
+    n_eval = len(frames)
+    weights = np.load(os.path.join(ROOT, "paper_1610_07159_amd", "weights", "init_640x480.npy"),
+                      allow_pickle=False)
+    plain, _, ms_plain = T.solve_flows(frames, W, H, timed=True, **solver_params)
+    e_plain = float(np.mean([T.epe(f, fr["truth"], W, H) for f, fr in zip(plain, frames)]))
+    for n in range(1, solver_params["gn_iters"] + 1):
+        fl, used, ms = T.solve_flows(frames, W, H, init_mode=1, weights=weights, timed=True,
+                                     **dict(solver_params, gn_iters=n))
+        e = float(np.mean([T.epe(f, fr["truth"], W, H) for f, fr in zip(fl, frames)]))
+        if e <= e_plain:
+            return dict(eval_frames=n_eval, plain_epe_px=round(e_plain, 4),
+                        plain_ms_per_frame=round(ms_plain, 3), learned_gn_iters=n,
+                        learned_epe_px=round(e, 4), learned_ms_per_frame=round(ms, 3),
+                        speedup=round(ms_plain / ms, 3), prediction_kept=int(sum(used)))
+    return dict(eval_frames=n_eval, plain_epe_px=round(e_plain, 4), reached=False)
+
+
 def make_workload(name):
     from synth import make_frame, vga_config, hd_config, tiny_plane_config
     w = WORKLOADS[name]
@@ -209,6 +257,42 @@ def trace_summary(path, focus=("k_pcg",)):
         print(f"  {k:44s} grid {g:9d}: calls {c:6d}, avg {t / c:8.2f} us")
 
 
+def traffic_report(fetch_csv, write_csv, kernel, copy_mib):
+    """HBM bytes per launch of `kernel` (its largest launch grid) from two
+    rocprofv3 counter CSVs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each
+    counter scaled by what it reads for the copy probe of copy_mib MiB
+    (which reads and writes exactly that much).  Prints the summary that
+    bench.py reads back as roofline.traffic."""
+    import collections
+    import csv
+
+    def per_kernel(path, counter):
+        acc = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                acc[(_short_name(r["Kernel_Name"]), int(r["Grid_Size"]))].append(
+                    float(r["Counter_Value"]))
+        return acc
+    f = per_kernel(fetch_csv, "FETCH_SIZE")
+    w = per_kernel(write_csv, "WRITE_SIZE")
+    expect = copy_mib * 1024.0
+    copy_w = min((v for (k, g), vs in w.items() if "copyBuffer" in k for v in vs),
+                 key=lambda v: abs(v - expect))
+    copy_f = max(v for (k, g), vs in f.items() if "copyBuffer" in k for v in vs)
+    ff, fw = expect / copy_f, expect / copy_w
+    key = max((kg for kg in f if kg[0] == kernel), key=lambda kg: kg[1])
+    mf = float(np.mean(f[key]))
+    mw = float(np.mean(w[key]))
+    traffic = int(round((mf * ff + mw * fw) * 1024))
+    print(f"# copy probe {copy_mib} MiB: FETCH_SIZE reads {copy_f:.1f} KiB (factor {ff:.4f}), "
+          f"WRITE_SIZE reads {copy_w:.1f} KiB (factor {fw:.4f})")
+    print(f"# {kernel}, launch grid {key[1]} threads: FETCH_SIZE {mf:.1f} KiB, WRITE_SIZE "
+          f"{mw:.1f} KiB per dispatch (means over {len(f[key])} / {len(w[key])} dispatches)")
+    print(f"kernel = {kernel}")
+    print(f"source_sha256 = {source_hash()}")
+    print(f"traffic_bytes_per_launch = {traffic}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +301,8 @@ def main():
     ap.add_argument("--workload", default="vga", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-epe", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-init vs plain comparison")
     ap.add_argument("--exec-mode", type=int, default=0,
                     help="0 = captured HIP graph, 1 = direct launches")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -224,9 +310,15 @@ def main():
                          "calibration under rocprofv3 --pmc)")
     ap.add_argument("--trace-summary", metavar="CSV",
                     help="summarise a rocprofv3 kernel-trace or counter CSV and exit")
+    ap.add_argument("--traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL"),
+                    help="HBM traffic per launch of KERNEL from two counter CSVs "
+                         "(calibrated by the copy probe) and exit")
     args = ap.parse_args()
     if args.trace_summary:
         trace_summary(args.trace_summary)
+        return
+    if args.traffic:
+        traffic_report(*args.traffic, copy_mib=args.copy_probe_mib or 512)
         return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU "
@@ -234,6 +326,15 @@ def main():
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    # host process pools render before anything touches the GPU
+    pre = {}
+    if args.workload == "batch":
+        pre["batch"] = make_batch_workload(WORKLOADS["batch"])
+    if args.workload == "learned" or (args.workload == "vga" and not args.no_learned):
+        from paper_1610_07159_amd.train_init import render_frames
+        n_eval = WORKLOADS["learned"]["n_eval"]
+        pre["eval"] = render_frames(640, 480, range(1_000_000, 1_000_000 + n_eval), True, 8,
+                                    log=lambda m: None)
     import torch
     torch.cuda.set_device(0)
     if args.copy_probe_mib > 0:
@@ -247,9 +348,9 @@ def main():
         torch.cuda.synchronize()
         del a, b
     if args.workload == "batch":
-        return run_batch(args)
+        return run_batch(args, pre["batch"])
     if args.workload == "learned":
-        return run_learned(args)
+        return run_learned(args, pre["eval"])
 
     from paper_1610_07159_amd import SceneFlowSolver, sf
 
@@ -310,7 +411,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_apply (H p) at level 0",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None,
+                     "traffic": (measured_traffic(args.workload)
+                                 if args.exec_mode == 0 else None),
                      "bytes_per_launch": bytes_apply,
                      "avg_us_per_launch": round(bytes_apply / achieved / 1e3, 2),
                      "apply_us_per_level": per_level},
@@ -318,13 +420,15 @@ def main():
     }
     if not args.no_epe:
         result["epe_px"] = round(epe(flows, scene, W, H), 4)
+    if args.workload == "vga" and not args.no_learned:
+        result["learned_vs_plain"] = learned_vs_plain(params, pre["eval"])
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(imgs, calib, params, W, H)
     solver.close()
     print(json.dumps(result), flush=True)
 
 
-def run_learned(args):
+def run_learned(args, frames):
     """Equal-EPE comparison of the learned initialiser with the plain
     solver; value = ms/frame of the learned solve at the plain EPE."""
     from paper_1610_07159_amd import train_init as T
@@ -333,8 +437,6 @@ def run_learned(args):
     params = dict(w["params"])
     weights = np.load(os.path.join(ROOT, "paper_1610_07159_amd", "weights", "init_640x480.npy"),
                       allow_pickle=False)
-    frames = T.render_frames(W, H, range(1_000_000, 1_000_000 + w["n_eval"]), True, 8,
-                             log=lambda m: None)
     plain, _, ms_plain = T.solve_flows(frames, W, H, timed=True, **params)
     epe_plain = float(np.mean([T.epe(f, fr["truth"], W, H) for f, fr in zip(plain, frames)]))
     sweep, reach = [], None
@@ -370,15 +472,14 @@ def run_learned(args):
     print(json.dumps(result), flush=True)
 
 
-def run_batch(args):
+def run_batch(args, workload):
     """Batches of frames of mixed sizes through sf_solve_batch.  One step is
     one batch; per-batch GPU time from HIP events on the solver's stream."""
     import torch
     from paper_1610_07159_amd import SceneFlowSolver, sf
     w = WORKLOADS["batch"]
     params = dict(w["params"])
-    res, frames = make_batch_workload(w)
-    torch.cuda.set_device(0)
+    res, frames = workload
     dev = [(torch.from_numpy(i).cuda().contiguous(), c) for i, c in frames]
     W0, H0 = res[0]
     solver = SceneFlowSolver(W0, H0, exec_mode=args.exec_mode, **params)
@@ -437,7 +538,7 @@ def run_batch(args):
         "roofline": {"bound": "hbm", "kernel": "k_apply (H p) at level 0, all frames",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": bytes_apply,
+                     "traffic": measured_traffic("batch"), "bytes_per_launch": bytes_apply,
                      "avg_us_per_launch": round(avg_ms * 1e3, 2)},
     }
     solver.close()
