@@ -305,6 +305,9 @@ def main():
                     help="skip the learned-init vs plain comparison")
     ap.add_argument("--exec-mode", type=int, default=0,
                     help="0 = captured HIP graph, 1 = direct launches")
+    ap.add_argument("--tile-mode", type=int, default=1,
+                    help="PCG tile shapes: 0 = default, 1 = autotuned (timed on the "
+                         "warm-up solve), 2 / 3 = the alternative shapes")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter "
                          "calibration under rocprofv3 --pmc)")
@@ -358,7 +361,8 @@ def main():
     W, H = w["width"], w["height"]
     params = dict(w["params"])
     img = torch.from_numpy(imgs).cuda().contiguous()
-    solver = SceneFlowSolver(W, H, exec_mode=args.exec_mode, **params)
+    solver = SceneFlowSolver(W, H, exec_mode=args.exec_mode, tile_mode=args.tile_mode,
+                             **params)
     stream = solver.stream
     out = (torch.empty((H, W), device="cuda"), torch.empty((3, H, W), device="cuda"),
            torch.empty((6, H, W), device="cuda"))
@@ -405,7 +409,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["desc"], "width": W, "height": H,
                    "exec": "hip graph" if args.exec_mode == 0 else "direct launches",
-                   **params},
+                   "tile_mode": args.tile_mode, **params},
         "frames_per_s": round(1e3 / ms, 2),
         "wall_ms_per_frame": round(wall * 1e3 / args.steps, 4),
         "roofline": {"bound": "hbm", "kernel": "k_apply (H p) at level 0",
@@ -482,9 +486,10 @@ def run_batch(args, workload):
     res, frames = workload
     dev = [(torch.from_numpy(i).cuda().contiguous(), c) for i, c in frames]
     W0, H0 = res[0]
-    solver = SceneFlowSolver(W0, H0, exec_mode=args.exec_mode, **params)
+    solver = SceneFlowSolver(W0, H0, exec_mode=args.exec_mode, tile_mode=args.tile_mode,
+                             **params)
     stream = solver.stream
-    prm = sf.sf_params_default(exec_mode=args.exec_mode, **params)
+    prm = sf.sf_params_default(exec_mode=args.exec_mode, tile_mode=args.tile_mode, **params)
     outs = None
     for _ in range(args.warmup):
         outs = solver.solve_batch(dev, outs=outs, params=prm)
@@ -530,7 +535,7 @@ def run_batch(args, workload):
         "data": "synthetic",
         "config": {"workload": w["desc"], "frames_per_batch": n, "sizes": sizes,
                    "exec": "hip graph" if args.exec_mode == 0 else "direct launches",
-                   **params},
+                   "tile_mode": args.tile_mode, **params},
         "frames_per_s": round(1e3 / ms_frame, 1),
         "batch_ms_p50": round(float(np.percentile(per_batch, 50)), 3),
         "batch_ms_p99": round(float(np.percentile(per_batch, 99)), 3),

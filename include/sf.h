@@ -63,6 +63,14 @@ typedef struct {
  *                  learned initialiser (needs levels >= 5 and weights from
  *                  sf_set_initializer; see below)
  *  exec_mode       0 = replay a captured HIP graph, 1 = enqueue kernels
+ *  tile_mode       node-tile shape of the PCG kernels: 0 = default per
+ *                  stride; 1 = autotuned (each candidate shape is timed on
+ *                  the first solve of a frame size or batch shape and the
+ *                  fastest is cached per device, stride and level sizes, in
+ *                  the process and, if the environment variable
+ *                  SF_TUNE_CACHE names a file, in that file); 2, 3 = the
+ *                  alternative shapes (strides 2, 4, 8; others use the
+ *                  default)
  *  w_*, m_*        weights of the energy terms; m_s, m_m, m_d must be > 0
  *  eps             pseudo-Huber parameter of Eq. (12)
  *  eps_p           colour-pruning threshold of Sec. 4.1
@@ -72,7 +80,7 @@ typedef struct {
  *                  eigenvalue analysis; this map is the library's reading). */
 typedef struct {
     int levels, grid_stride, gn_iters, pcg_iters, max_backtracks, init_mode;
-    int exec_mode;
+    int exec_mode, tile_mode;
     float w_reg, w_photo, w_grad, w_epi, w_smooth, w_mag;
     float w_s, w_m, w_d, m_s, m_m, m_d;
     float eps, eps_p, st_gamma, st_tau;

@@ -4,9 +4,13 @@
 // and replay, batches of frames, logging and test access to intermediates.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "sf_cnn.h"
@@ -54,7 +58,9 @@ struct Plan {
     bool batched = false;
     int Lmax = 0;
     sf_params prm{};
-    TileCfg tile{};
+    TileCfg tile{};                    // right-hand-side kernel
+    TileCfg ptile[SF_MAX_LEVELS]{};    // PCG kernels, per level slot
+    bool tuned = false;
     std::vector<FrameBuf> fr;
     std::vector<std::vector<LevelArgs>> host;  // [slot] -> args of its frames
     std::vector<long> slot_off;                // offset of each slot in dtab
@@ -112,6 +118,7 @@ sf_status check_params(const sf_params *p) {
     if (p->init_mode != 0 && p->init_mode != 1) return SF_ERR_INVALID_ARG;
     if (p->init_mode == 1 && p->levels <= SF_CNN_INPUT_LEVEL) return SF_ERR_INVALID_ARG;
     if (p->exec_mode != 0 && p->exec_mode != 1) return SF_ERR_INVALID_ARG;
+    if (p->tile_mode < 0 || p->tile_mode > 3) return SF_ERR_INVALID_ARG;
     const float w[] = {p->w_reg, p->w_photo, p->w_grad, p->w_epi, p->w_smooth,
                        p->w_mag, p->w_s, p->w_m, p->w_d, p->st_gamma};
     for (float v : w)
@@ -126,7 +133,8 @@ sf_status check_params(const sf_params *p) {
 bool same_schedule(const sf_params &a, const sf_params &b) {
     return a.levels == b.levels && a.grid_stride == b.grid_stride &&
            a.gn_iters == b.gn_iters && a.pcg_iters == b.pcg_iters &&
-           a.max_backtracks == b.max_backtracks && a.init_mode == b.init_mode;
+           a.max_backtracks == b.max_backtracks && a.init_mode == b.init_mode &&
+           a.tile_mode == b.tile_mode;
 }
 
 sf_status check_calib(const sf_calib *cal) {
@@ -222,9 +230,17 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
     const int st = prm.grid_stride;
     P.tile = pick_tile(st);
     if (node_tile_lds_bytes(P.tile, st, 12) > 64 * 1024 ||
-        node_tile_lds_bytes(P.tile, st, 6) > 64 * 1024 ||
         tile_max_pixels(P.tile, st) > tile_ppt(st) * tile_threads(st))
         return SF_ERR_INVALID_ARG;
+    for (int v = 0; v < tile_variants(st); ++v) {
+        const TileCfg t = pick_pcg_tile(st, v);
+        if (node_tile_lds_bytes(t, st, 6) > 64 * 1024 ||
+            tile_max_pixels(t, st) > tile_ppt(st, v) * tile_threads(t))
+            return SF_ERR_INVALID_ARG;
+    }
+    const int forced = prm.tile_mode >= 2 ? prm.tile_mode - 1 : 0;
+    for (int l = 0; l < SF_MAX_LEVELS; ++l) P.ptile[l] = pick_pcg_tile(st, forced);
+    P.tuned = prm.tile_mode != 1;
     P.fr.resize(P.nf);
     P.Lmax = 0;
     // sizes, then one allocation carved in 256-byte aligned pieces
@@ -238,6 +254,10 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
         for (int l = 0; l < F.L; ++l) {
             const LevelDims &d = F.lv[l];
             mb = mb > energy_blocks(d) ? mb : energy_blocks(d);
+            for (int v = 0; v < tile_variants(st); ++v) {
+                const int nt = node_tile_blocks(d, pick_pcg_tile(st, v));
+                mb = mb > nt ? mb : nt;
+            }
             mb = mb > node_tile_blocks(d, P.tile) ? mb : node_tile_blocks(d, P.tile);
             const int gb = (d.G + SF_BLOCK - 1) / SF_BLOCK;
             mb = mb > gb ? mb : gb;
@@ -446,9 +466,10 @@ void enqueue_linearize(const Plan &P, hipStream_t st, int l) {
 void enqueue_pcg(const Plan &P, hipStream_t st, int l, int gn) {
     const Launch L = slot(P, l);
     const int n = P.prm.pcg_iters;
-    launch_pcg_first(st, L, P.tile);
-    for (int i = 1; i < n; ++i) launch_pcg_iter(st, L, P.tile, i, gn, 0);
-    launch_pcg_last(st, L, P.tile, n, gn, 0);
+    const TileCfg &t = P.ptile[l];
+    launch_pcg_first(st, L, t);
+    for (int i = 1; i < n; ++i) launch_pcg_iter(st, L, t, i, gn, 0);
+    launch_pcg_last(st, L, t, n, gn, 0);
 }
 
 void enqueue_gn(const Plan &P, hipStream_t st, int l, int g, bool log) {
@@ -508,7 +529,106 @@ sf_status ensure_graph(Plan &P, hipStream_t cap) {
     return SF_OK;
 }
 
+// ---- PCG tile autotuner --------------------------------------------------------
+//
+// Per level slot, every candidate shape of the PCG iteration kernel is timed
+// (forced active, HIP events, after two warm-up launches) on the plan's own
+// buffers before the first solve, and the fastest is kept.  Choices are
+// cached per (device architecture, stride, sizes of the slot's frames) in
+// the process and, if SF_TUNE_CACHE names a file, in that file (one
+// "key variant" line per entry).
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const Plan &P, int l, int device) {
+    hipDeviceProp_t prop;
+    std::string arch = "gfx";
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
+    for (char &ch : arch)
+        if (ch == ' ' || ch == ':') ch = '_';
+    std::string k = arch + "/s" + std::to_string(P.prm.grid_stride) + "/";
+    for (const LevelArgs &a : P.host[l]) k += std::to_string(a.d.W) + "x" + std::to_string(a.d.H) + ",";
+    return k;
+}
+
+void tune_cache_load() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = getenv("SF_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char key[1024];
+    int v;
+    while (fscanf(f, "%1023s %d", key, &v) == 2) g_tune[key] = v;
+    fclose(f);
+}
+
+void tune_cache_store(const std::string &key, int v) {
+    g_tune[key] = v;
+    const char *path = getenv("SF_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d\n", key.c_str(), v);
+    fclose(f);
+}
+
+sf_status autotune(sf_ctx *c, Plan &P) {
+    const int st = P.prm.grid_stride;
+    const int nv = tile_variants(st);
+    hipStream_t s = c->stream;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_cache_load();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    sf_status rc = SF_OK;
+    for (int l = 0; l < P.Lmax && rc == SF_OK; ++l) {
+        const std::string key = tune_key(P, l, c->device);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end() && it->second >= 0 && it->second < nv) {
+            P.ptile[l] = pick_pcg_tile(st, it->second);
+            continue;
+        }
+        const Launch L = slot(P, l);
+        int best = 0;
+        float best_ms = 1e30f;
+        for (int v = 0; v < nv && rc == SF_OK; ++v) {
+            const TileCfg t = pick_pcg_tile(st, v);
+            const int reps = 10;
+            for (int i = 0; i < 2; ++i) launch_pcg_iter(s, L, t, 2 + (i & 1), -1, 1);
+            if (hipEventRecord(e0, s) != hipSuccess) rc = SF_ERR_HIP;
+            for (int i = 0; i < reps && rc == SF_OK; ++i) launch_pcg_iter(s, L, t, 2 + (i & 1), -1, 1);
+            float ms = 0.f;
+            if (rc == SF_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                                hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = SF_ERR_HIP;
+            if (rc == SF_OK && ms < best_ms) {
+                best_ms = ms;
+                best = v;
+            }
+        }
+        if (rc == SF_OK) {
+            P.ptile[l] = pick_pcg_tile(st, best);
+            tune_cache_store(key, best);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == SF_OK && hipGetLastError() != hipSuccess) rc = SF_ERR_HIP;
+    if (rc == SF_OK) P.tuned = true;
+    return rc;
+}
+
 sf_status run_body(sf_ctx *c, Plan &P) {
+    if (!P.tuned) {
+        sf_status s = autotune(c, P);
+        if (s != SF_OK) return s;
+    }
     if (P.prm.exec_mode == 0) {
         sf_status s = ensure_graph(P, c->cap_stream);
         if (s != SF_OK) return s;
@@ -582,9 +702,9 @@ sf_status time_kernel(hipStream_t st, const Plan &P, int kernel, int level, int 
     sf_status s = SF_OK;
     auto one = [&](int i) {
         switch (kernel) {
-            case SF_KERNEL_APPLY: launch_pcg_iter(st, L, P.tile, 2 + (i & 1), -1, 1); break;
+            case SF_KERNEL_APPLY: launch_pcg_iter(st, L, P.ptile[level], 2 + (i & 1), -1, 1); break;
             case SF_KERNEL_LINEARIZE: launch_linearize(st, L); break;
-            case SF_KERNEL_UPDATE: launch_pcg_last(st, L, P.tile, 2 + (i & 1), -1, 1); break;
+            case SF_KERNEL_UPDATE: launch_pcg_last(st, L, P.ptile[level], 2 + (i & 1), -1, 1); break;
             case SF_KERNEL_RHS: launch_rhs(st, L, P.tile); break;
         }
     };
@@ -956,7 +1076,7 @@ sf_status sf_debug_run(sf_ctx *c, int stage, int level) {
     switch (stage) {
         case SF_STAGE_LEVEL_INIT: launch_level_init(st, L); break;
         case SF_STAGE_LINEARIZE: enqueue_linearize(P, st, level); break;
-        case SF_STAGE_APPLY: launch_pcg_first(st, L, P.tile); break;
+        case SF_STAGE_APPLY: launch_pcg_first(st, L, P.ptile[level]); break;
         case SF_STAGE_PCG: enqueue_pcg(P, st, level, -1); break;
         case SF_STAGE_GN: enqueue_gn(P, st, level, 0, false); break;
         case SF_STAGE_FINISH: launch_finish_level(st, L); break;

@@ -122,6 +122,7 @@ struct DevLog {
 // tpn threads per node (the workgroup has tx * ty * tpn threads).
 struct TileCfg {
     int tx, ty, tpn;
+    int v;  // shape variant (PCG kernels)
 };
 
 // Caller buffers of one frame of a batch (device pointers, rewritten on
@@ -201,9 +202,14 @@ void launch_finish_level(hipStream_t st, const Launch &L);
 void launch_output(hipStream_t st, const Launch &L, float *depth,
                    float *flow3d, float *flows);
 TileCfg pick_tile(int s);
+// PCG tile shapes: tile_variants(s) shapes per stride, variant 0 = pick_tile
+int tile_variants(int s);
+TileCfg pick_pcg_tile(int s, int v);
 int tile_threads(int s);
+int tile_threads(const TileCfg &t);
 int tile_max_pixels(const TileCfg &t, int s);
 int tile_ppt(int s);
+int tile_ppt(int s, int v);
 size_t node_tile_lds_bytes(const TileCfg &t, int s, int K);
 int energy_blocks(const LevelDims &d);
 int node_tile_blocks(const LevelDims &d, const TileCfg &t);

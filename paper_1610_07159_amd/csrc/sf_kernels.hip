@@ -18,20 +18,38 @@
 #include "sf_cnn.h"
 #include "sf_internal.h"
 
-// Node-tile shape per grid stride S: tx x ty nodes, tpn threads per node
-// (tpn >= 2S so one thread sums one support row), NT = tx ty tpn threads
-// and at most PPT region pixels per thread.  256 threads where the register
-// budget allows more than one workgroup per CU, 512 for the largest strides.
-template <int S>
-struct TileTraits {
+// Node-tile shape per grid stride S and variant V: tx x ty nodes, tpn
+// threads per node (tpn >= 2S so one thread sums one support row),
+// NT = tx ty tpn threads and at most PPT region pixels per thread.
+// Variant 0 (every kernel): 256 threads where the register budget allows
+// more than one workgroup per CU, 512 for the largest strides.  Variants 1
+// and 2 (the PCG kernels at strides 2, 4, 8, chosen by the autotuner):
+// twice the nodes per tile (fewer re-read halo pixels, 512 threads) and a
+// smaller tile (more workgroups for small levels).
+template <int S, int V>
+struct TileShape {
     static constexpr int TX = S <= 2 ? 16 : (S <= 4 ? 8 : 4);
     static constexpr int TY = S == 1 ? 8 : (S == 2 ? 4 : (S <= 4 ? 4 : 2));
     static constexpr int TPN = S == 1 ? 2 : (S == 2 ? 4 : (S <= 4 ? 8 : (S <= 6 ? 32 : 64)));
+};
+template <> struct TileShape<2, 1> { static constexpr int TX = 16, TY = 8, TPN = 4; };
+template <> struct TileShape<2, 2> { static constexpr int TX = 8, TY = 4, TPN = 8; };
+template <> struct TileShape<4, 1> { static constexpr int TX = 8, TY = 8, TPN = 8; };
+template <> struct TileShape<4, 2> { static constexpr int TX = 4, TY = 4, TPN = 16; };
+template <> struct TileShape<8, 1> { static constexpr int TX = 2, TY = 4, TPN = 64; };
+template <> struct TileShape<8, 2> { static constexpr int TX = 2, TY = 2, TPN = 64; };
+
+template <int S, int V = 0>
+struct TileTraits {
+    static constexpr int TX = TileShape<S, V>::TX;
+    static constexpr int TY = TileShape<S, V>::TY;
+    static constexpr int TPN = TileShape<S, V>::TPN;
     static constexpr int NT = TX * TY * TPN;
     static constexpr int MAXPX = ((TX + 1) * S + (S & 1)) * ((TY + 1) * S + (S & 1));
     static constexpr int PPT = (MAXPX + NT - 1) / NT;
     static_assert(TPN >= 2 * S && TPN <= 64, "one support row per thread, one wave per node");
     static_assert(NT == 256 || NT == 512, "block size");
+    static_assert(NT <= 512 || PPT <= 2, "registers");
     static_assert(PPT <= 3, "pixels per thread");
 };
 
@@ -1005,11 +1023,11 @@ __device__ void carry_partials(const LevelArgs &a, int bid, int i) {
 // Every load of an iteration that does not depend on its scalars is issued
 // before the partial sums are reduced, and constants are read once, so the
 // workgroup waits for memory about once.
-template <bool B, bool FIRST, int S>
-__global__ __launch_bounds__(TileTraits<S>::NT) void k_pcg(KArg<B> ka, TileCfg t, int i,
-                                                           int gn, int force) {
-    constexpr int NT_TILE = TileTraits<S>::NT;
-    constexpr int PPT = TileTraits<S>::PPT;
+template <bool B, bool FIRST, int S, int V>
+__global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, TileCfg t, int i,
+                                                              int gn, int force) {
+    constexpr int NT_TILE = TileTraits<S, V>::NT;
+    constexpr int PPT = TileTraits<S, V>::PPT;
     extern __shared__ float lds[];
     SF_BIND(ka);
     const int nb_prev = nblk;  // the previous iteration ran on the same tiles
@@ -1678,12 +1696,13 @@ static void go(hipStream_t st, const Launch &L, Blocks blocks, KB kb, KS ks, int
 
 // Node tile per grid stride: a pixel region of roughly 20-40 px a side, the
 // 256 threads split evenly over the tile's nodes.
-template <int S>
+template <int S, int V = 0>
 static TileCfg tile_of() {
     TileCfg t;
-    t.tx = TileTraits<S>::TX;
-    t.ty = TileTraits<S>::TY;
-    t.tpn = TileTraits<S>::TPN;
+    t.tx = TileTraits<S, V>::TX;
+    t.ty = TileTraits<S, V>::TY;
+    t.tpn = TileTraits<S, V>::TPN;
+    t.v = V;
     return t;
 }
 
@@ -1694,7 +1713,18 @@ TileCfg pick_tile(int s) {
     return tile_of<8>();
 }
 
-int tile_threads(int s) { return pick_tile(s).tx * pick_tile(s).ty * pick_tile(s).tpn; }
+int tile_variants(int s) { return s == 2 || s == 4 || s == 8 ? 3 : 1; }
+
+TileCfg pick_pcg_tile(int s, int v) {
+    if (v <= 0 || v >= tile_variants(s)) return pick_tile(s);
+    if (s == 2) return v == 1 ? tile_of<2, 1>() : tile_of<2, 2>();
+    if (s == 4) return v == 1 ? tile_of<4, 1>() : tile_of<4, 2>();
+    return v == 1 ? tile_of<8, 1>() : tile_of<8, 2>();
+}
+
+int tile_threads(const TileCfg &t) { return t.tx * t.ty * t.tpn; }
+
+int tile_threads(int s) { return tile_threads(pick_tile(s)); }
 
 // Largest pixel region of a tile: (n + 1) s columns for even s, one more
 // for odd s (floor rounding of the support bounds).
@@ -1708,6 +1738,13 @@ int tile_ppt(int s) {
     SF_STRIDE_SWITCH(s, PPTS)
 #undef PPTS
     return TileTraits<8>::PPT;
+}
+
+int tile_ppt(int s, int v) {
+    if (v <= 0 || v >= tile_variants(s)) return tile_ppt(s);
+    if (s == 2) return v == 1 ? TileTraits<2, 1>::PPT : TileTraits<2, 2>::PPT;
+    if (s == 4) return v == 1 ? TileTraits<4, 1>::PPT : TileTraits<4, 2>::PPT;
+    return v == 1 ? TileTraits<8, 1>::PPT : TileTraits<8, 2>::PPT;
 }
 
 size_t node_tile_lds_bytes(const TileCfg &t, int s, int K) {
@@ -1762,13 +1799,34 @@ void launch_rhs(hipStream_t st, const Launch &L, const TileCfg &t) {
 #undef RHS
 }
 
+// The PCG kernels per (stride, variant): the tile in t says which.
+#define SF_PCG_SWITCH(s, v, CALL)                          \
+    if ((s) == 2 && (v) == 1) { CALL(2, 1); }              \
+    else if ((s) == 2 && (v) == 2) { CALL(2, 2); }         \
+    else if ((s) == 4 && (v) == 1) { CALL(4, 1); }         \
+    else if ((s) == 4 && (v) == 2) { CALL(4, 2); }         \
+    else if ((s) == 8 && (v) == 1) { CALL(8, 1); }         \
+    else if ((s) == 8 && (v) == 2) { CALL(8, 2); }         \
+    else {                                                 \
+        switch (s) {                                       \
+            case 1: CALL(1, 0); break;                     \
+            case 2: CALL(2, 0); break;                     \
+            case 3: CALL(3, 0); break;                     \
+            case 4: CALL(4, 0); break;                     \
+            case 5: CALL(5, 0); break;                     \
+            case 6: CALL(6, 0); break;                     \
+            case 7: CALL(7, 0); break;                     \
+            default: CALL(8, 0); break;                    \
+        }                                                  \
+    }
+
 void launch_pcg_first(hipStream_t st, const Launch &L, const TileCfg &t) {
     auto nb = [t](const LevelArgs &a) { return node_tiles_of(a.d, t); };
     const int s = L.host[0].s;
-#define PCG0(S)                                                                          \
-    go(st, L, nb, k_pcg<true, true, S>, k_pcg<false, true, S>, TileTraits<S>::NT,        \
+#define PCG0(S, V)                                                                            \
+    go(st, L, nb, k_pcg<true, true, S, V>, k_pcg<false, true, S, V>, TileTraits<S, V>::NT,    \
        node_tile_lds_bytes(t, S, 6), t, 0, -1, 0)
-    SF_STRIDE_SWITCH(s, PCG0)
+    SF_PCG_SWITCH(s, t.v, PCG0)
 #undef PCG0
 }
 
@@ -1776,10 +1834,10 @@ void launch_pcg_iter(hipStream_t st, const Launch &L, const TileCfg &t, int iter
                      int force) {
     auto nb = [t](const LevelArgs &a) { return node_tiles_of(a.d, t); };
     const int s = L.host[0].s;
-#define PCGI(S)                                                                          \
-    go(st, L, nb, k_pcg<true, false, S>, k_pcg<false, false, S>, TileTraits<S>::NT,      \
+#define PCGI(S, V)                                                                            \
+    go(st, L, nb, k_pcg<true, false, S, V>, k_pcg<false, false, S, V>, TileTraits<S, V>::NT,  \
        node_tile_lds_bytes(t, S, 6), t, iter, gn, force)
-    SF_STRIDE_SWITCH(s, PCGI)
+    SF_PCG_SWITCH(s, t.v, PCGI)
 #undef PCGI
 }
 
