@@ -291,14 +291,17 @@ sf_status sf_debug_set_images(sf_ctx *ctx, const float *I_left_t,
  *  SF_STAGE_APPLY        q = H p with p = the current SF_DBG_Z vector
  *  SF_STAGE_PCG          pcg_iters PCG iterations from x = 0
  *  SF_STAGE_GN           one full Gauss-Newton step with step control
- *  SF_STAGE_FINISH       store base + delta as the level's total        */
+ *  SF_STAGE_FINISH       store base + delta as the level's total
+ *  SF_STAGE_MASKS        masks and smoothness weights at the current base
+ *                        (the level set-up without the prolongation)    */
 enum {
     SF_STAGE_LEVEL_INIT = 0,
     SF_STAGE_LINEARIZE = 1,
     SF_STAGE_APPLY = 2,
     SF_STAGE_PCG = 3,
     SF_STAGE_GN = 4,
-    SF_STAGE_FINISH = 5
+    SF_STAGE_FINISH = 5,
+    SF_STAGE_MASKS = 6
 };
 sf_status sf_debug_run(sf_ctx *ctx, int stage, int level);
 

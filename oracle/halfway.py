@@ -327,6 +327,12 @@ def pixel_terms(li: LevelImages, grid: Grid, flows):
     g_k = grad I_a(P_a) - grad I_b(P_b), with grad I the gradient images
     sampled bilinearly (gradient constancy)."""
     px, py = grid.pixel_xy()
+    return pixel_terms_xy(li, px, py, flows)
+
+
+def pixel_terms_xy(li: LevelImages, px, py, flows):
+    """pixel_terms for the pixels at integer coordinates (px, py) with
+    their flows (6, n)."""
     P = positions(px, py, flows)
     val = np.empty((4, px.shape[0]))
     dI = np.empty((4, 2, px.shape[0]))     # d I_c / d P
@@ -522,6 +528,76 @@ def robust_rows(ls: LevelState, delta, p: Params):
             r[:, row] = t.g[k, rr]
             w[:, row] = ls.cmask * p.w_grad / gph[k]
     return J, r, w
+
+
+# ---------------------------------------------------------------------------
+# the same quantities on a sample of pixels or nodes (full-size checks)
+# ---------------------------------------------------------------------------
+
+def flows_at(grid: Grid, nodes6, pix):
+    """Eq. (7) flows (6, n) of the pixels with flat indices pix."""
+    nodes6 = np.asarray(nodes6, np.float64).reshape(6, grid.G)
+    out = np.zeros((6, len(pix)))
+    for k in range(4):
+        out += grid.alpha[k][pix] * nodes6[:, grid.nodes[k][pix]]
+    return out
+
+
+def rows_at(ls: LevelState, delta, p: Params, pix):
+    """robust_rows evaluated for the pixels pix only: J (n, 18, 6), r, w."""
+    grid = ls.grid
+    pix = np.asarray(pix, np.int64)
+    fl = flows_at(grid, ls.base + delta, pix)
+    px = (pix % grid.W).astype(np.float64)
+    py = (pix // grid.W).astype(np.float64)
+    t = pixel_terms_xy(ls.li, px, py, fl)
+    n = len(pix)
+    cm = ls.cmask[pix]
+    ph = phi(t.d, p.eps)
+    gph = phi(np.sqrt((t.g ** 2).sum(1)), p.eps)
+    J = np.empty((n, 18, 6))
+    r = np.empty((n, 18))
+    w = np.empty((n, 18))
+    J[:, 0:6, :] = np.transpose(t.Jd, (2, 0, 1))
+    r[:, 0:6] = t.d.T
+    w[:, 0:6] = (cm * p.w_photo / ph).T
+    for k in range(6):
+        for rr in range(2):
+            row = 6 + 2 * k + rr
+            J[:, row, :] = t.Jg[k, rr].T
+            r[:, row] = t.g[k, rr]
+            w[:, row] = cm * p.w_grad / gph[k]
+    return J, r, w
+
+
+def node_rows(ls: LevelState, delta, p: Params, nodes, u):
+    """For the nodes listed: the gradient of E (6, n), diag(H) (6, n) and
+    (H u) (6, n) for a vector u (6, G), from the pixels in each node's
+    support and the regularisers (the rows of linearize's grad and H)."""
+    grid = ls.grid
+    nodes = np.asarray(nodes, np.int64)
+    u = np.asarray(u, np.float64).reshape(6, grid.G)
+    total = ls.base + delta
+    rr, Jr, _ = reg_terms(grid, delta, total, ls.wnode, ls.F_l, p)
+    g_reg = (2.0 * (Jr.T @ rr)).reshape(6, grid.G)
+    JtJ = (Jr.T @ Jr).tocsr()
+    Hu_reg = (2.0 * (JtJ @ u.reshape(-1))).reshape(6, grid.G)
+    d_reg = (2.0 * JtJ.diagonal()).reshape(6, grid.G)
+    grad = np.zeros((6, len(nodes)))
+    diag = np.zeros((6, len(nodes)))
+    Hu = np.zeros((6, len(nodes)))
+    for t_, n in enumerate(nodes):
+        sup = np.nonzero((grid.nodes == n).any(0) & (
+            np.where(grid.nodes == n, grid.alpha, 0.0).sum(0) != 0.0))[0]
+        a_n = np.where(grid.nodes[:, sup] == n, grid.alpha[:, sup], 0.0).sum(0)
+        J, r, w = rows_at(ls, delta, p, sup)
+        gpx = np.einsum("nri,nr->ni", J, w * r)
+        Gx = np.einsum("nri,nr,nrj->nij", J, w, J)
+        v = flows_at(grid, u, sup)                         # interpolated u
+        grad[:, t_] = (a_n[:, None] * gpx).sum(0) + g_reg[:, n]
+        diag[:, t_] = (a_n[:, None] ** 2 * np.einsum("nii->ni", Gx)).sum(0) + d_reg[:, n]
+        Hu[:, t_] = (a_n[:, None] * np.einsum("nij,jn->ni", Gx, v)).sum(0) + Hu_reg[:, n]
+    return grad, diag, Hu
 
 
 def linearize(ls: LevelState, delta, p: Params):

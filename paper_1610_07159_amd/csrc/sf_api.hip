@@ -1080,6 +1080,7 @@ sf_status sf_debug_run(sf_ctx *c, int stage, int level) {
         case SF_STAGE_PCG: enqueue_pcg(P, st, level, -1); break;
         case SF_STAGE_GN: enqueue_gn(P, st, level, 0, false); break;
         case SF_STAGE_FINISH: launch_finish_level(st, L); break;
+        case SF_STAGE_MASKS: launch_level_masks(st, L); break;
         default: return SF_ERR_INVALID_ARG;
     }
     HIP_TRY(hipGetLastError());

@@ -185,6 +185,8 @@ struct Launch {
 void launch_tex_level0(hipStream_t st, const Launch &L, const float *const img[4]);
 void launch_downsample(hipStream_t st, const Launch &L);
 void launch_level_init(hipStream_t st, const Launch &L);
+// masks and smoothness weights at the current base (part of level init)
+void launch_level_masks(hipStream_t st, const Launch &L);
 // network candidate for the coarsest level and the fallback energies
 // (before launch_level_init)
 void launch_cnn_candidate(hipStream_t st, const Launch &L);

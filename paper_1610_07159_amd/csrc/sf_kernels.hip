@@ -1119,6 +1119,23 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
 #pragma unroll
         for (int k = 0; k < REG_PLANES; ++k) rg[k] = a.reg[k * G0 + n_own];
     }
+    // the owned node's u, p and x: read here in single-frame launches (one
+    // fewer dependent memory round trip, same occupancy); batched launches,
+    // which stream from HBM, read them after the LDS phases to keep the
+    // register count (and occupancy) lower
+    float uo[6], po[6], xo[6];
+    auto load_own = [&]() {
+        if (mine && !FIRST) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const long k = q * G0 + n_own;
+                uo[q] = U[k];
+                po[q] = i > 1 ? P[k] : 0.f;
+                xo[q] = X[k];
+            }
+        }
+    };
+    if (!B) load_own();
 
     // ---- phase 1: scalars of iteration i-1 ---------------------------------
     tile_brackets(a, g, L);
@@ -1188,16 +1205,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     __syncthreads();
 
     // ---- phase 4: sums onto nodes, regularisers ----------------------------
-    float uo[6], po[6], xo[6];
-    if (mine && !FIRST) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            const long k = q * G0 + n_own;
-            uo[q] = U[k];
-            po[q] = i > 1 ? P[k] : 0.f;
-            xo[q] = X[k];
-        }
-    }
+    if (B) load_own();
     float acc[6];
     lds_to_nodes<6, S>(a, t, g, L, 0u, acc);
     float prt[3] = {0.f, 0.f, 0.f};
@@ -1775,10 +1783,14 @@ void launch_cnn_candidate(hipStream_t st, const Launch &L) {
     go(st, L, en_blocks, k_fallback<true>, k_fallback<false>, SF_BLOCK, 0);
 }
 
-void launch_level_init(hipStream_t st, const Launch &L) {
-    go(st, L, nd_blocks, k_prolong<true>, k_prolong<false>, SF_BLOCK, 0);
+void launch_level_masks(hipStream_t st, const Launch &L) {
     go(st, L, px_blocks, k_masks<true>, k_masks<false>, SF_BLOCK, 0);
     go(st, L, nd_blocks, k_node_weights<true>, k_node_weights<false>, SF_BLOCK, 0);
+}
+
+void launch_level_init(hipStream_t st, const Launch &L) {
+    go(st, L, nd_blocks, k_prolong<true>, k_prolong<false>, SF_BLOCK, 0);
+    launch_level_masks(st, L);
 }
 
 void launch_linearize(hipStream_t st, const Launch &L) {

@@ -621,3 +621,30 @@ def test_level_fundamental_matrix(level):
         lh = np.append(l, 1.0)
         rh = np.append(r, 1.0)
         assert lh @ Fl @ rh == pytest.approx((l0 @ Fm @ r0) / k, rel=1e-12)
+
+
+def test_sampled_rows_and_node_rows_equal_full_assembly():
+    """The sampled evaluators used by the full-size GPU checks give the
+    same numbers as the full robust_rows / linearize."""
+    imgs, calib, _ = make_frame(tiny_plane_config(), 0)
+    p = O.Params(levels=1, grid_stride=8)
+    pyr = O.pyramid(imgs.astype(np.float64), 1)
+    grid = O.Grid(64, 48, 8)
+    rng = np.random.default_rng(3)
+    base = rng.normal(0, 0.3, (6, grid.G))
+    ls = O.setup_level(0, pyr, p, O.Calib.from_dict(calib), base)
+    delta = rng.normal(0, 0.2, (6, grid.G))
+    J, r, w = O.robust_rows(ls, delta, p)
+    pix = rng.choice(grid.N, 40, replace=False)
+    Js, rs, ws = O.rows_at(ls, delta, p, pix)
+    np.testing.assert_allclose(Js, J[pix], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(rs, r[pix], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(ws, w[pix], rtol=0, atol=1e-13)
+    grad, H = O.linearize(ls, delta, p)
+    u = rng.normal(size=6 * grid.G)
+    nodes = rng.choice(grid.G, 12, replace=False)
+    g, dg, Hu = O.node_rows(ls, delta, p, nodes, u)
+    idx = (np.arange(6)[:, None] * grid.G + nodes[None]).reshape(6, -1)
+    np.testing.assert_allclose(g, grad[idx], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(dg, H.diagonal()[idx], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(Hu, (H @ u)[idx], rtol=1e-12, atol=1e-11)
