@@ -704,46 +704,70 @@ __device__ __forceinline__ TileGeom tile_geom(const LevelArgs &a, const TileCfg 
 }
 
 // LDS carve-up of a node-tile kernel
+// Records in LDS are whole 16-byte vectors so that a pixel's or a node's
+// components move with one or two vector accesses (and rows of records
+// spread over the banks): per-pixel values in records of KP floats (K
+// rounded up to a multiple of 4), halo nodes in records of 8 floats, and
+// each region column / row's bilinear bracket as one float4 (first node
+// index as int bits, its weight, the next node's weight).
 struct TileLds {
-    int *bxi, *byi;
-    float *bxw0, *bxw1, *byw0, *byw1;
-    float *vals;   // K x RY x RX
-    float *halo;   // 6 x (ty + 2) x (tx + 2)
-    float *ownd;   // 2 x tx x ty scratch per owned node
+    float4 *bx, *by;  // brackets of region columns / rows
+    float *vals;      // RY x RX records of KP floats
+    float *halo;      // (ty + 2) x (tx + 2) records of 8 floats
+    float *ownd;      // 2 x tx x ty scratch per owned node
 };
 
+__host__ __device__ constexpr int rec_pad(int K) { return (K + 3) / 4 * 4; }
 __host__ __device__ inline int tile_rxs(const TileCfg &t, int s) { return (t.tx + 1) * s + 2; }
 __host__ __device__ inline int tile_rys(const TileCfg &t, int s) { return (t.ty + 1) * s + 2; }
 __host__ __device__ inline size_t tile_lds_floats(const TileCfg &t, int s, int K) {
     const size_t RXs = tile_rxs(t, s), RYs = tile_rys(t, s);
-    return 3 * RXs + 3 * RYs + (size_t)K * RXs * RYs + (size_t)6 * (t.tx + 2) * (t.ty + 2) +
-           (size_t)2 * t.tx * t.ty;
+    return 4 * RXs + 4 * RYs + (size_t)rec_pad(K) * RXs * RYs +
+           (size_t)8 * (t.tx + 2) * (t.ty + 2) + (size_t)2 * t.tx * t.ty;
 }
 
 __device__ TileLds tile_lds(float *lds, const TileCfg &t, int s, int K) {
     const int RXs = tile_rxs(t, s), RYs = tile_rys(t, s);
     TileLds L;
-    L.bxi = (int *)lds;
-    L.bxw0 = (float *)(L.bxi + RXs);
-    L.bxw1 = L.bxw0 + RXs;
-    L.byi = (int *)(L.bxw1 + RXs);
-    L.byw0 = (float *)(L.byi + RYs);
-    L.byw1 = L.byw0 + RYs;
-    L.vals = L.byw1 + RYs;
-    L.halo = L.vals + (size_t)K * RXs * RYs;
-    L.ownd = L.halo + (size_t)6 * (t.tx + 2) * (t.ty + 2);
+    L.bx = reinterpret_cast<float4 *>(lds);
+    L.by = L.bx + RXs;
+    L.vals = reinterpret_cast<float *>(L.by + RYs);
+    L.halo = L.vals + (size_t)rec_pad(K) * RXs * RYs;
+    L.ownd = L.halo + (size_t)8 * (t.tx + 2) * (t.ty + 2);
     return L;
 }
 
 __device__ void tile_brackets(const LevelArgs &a, const TileGeom &g, const TileLds &L) {
     for (int u = threadIdx.x; u < g.RX; u += blockDim.x) {
         const Bracket b = bracket(g.X0 + u, a.s, a.d.Gx);
-        L.bxi[u] = b.i0; L.bxw0[u] = b.w0; L.bxw1[u] = b.w1;
+        L.bx[u] = make_float4(__int_as_float(b.i0), b.w0, b.w1, 0.f);
     }
     for (int u = threadIdx.x; u < g.RY; u += blockDim.x) {
         const Bracket b = bracket(g.Y0 + u, a.s, a.d.Gy);
-        L.byi[u] = b.i0; L.byw0[u] = b.w0; L.byw1[u] = b.w1;
+        L.by[u] = make_float4(__int_as_float(b.i0), b.w0, b.w1, 0.f);
     }
+}
+
+// K floats of a record at p (16-byte aligned) / into a record
+template <int K>
+__device__ __forceinline__ void rec_load(const float *p, float (&v)[K]) {
+    const float4 *p4 = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+    for (int m = 0; m < rec_pad(K) / 4; ++m) {
+        const float4 t4 = p4[m];
+        if (4 * m + 0 < K) v[4 * m + 0] = t4.x;
+        if (4 * m + 1 < K) v[4 * m + 1] = t4.y;
+        if (4 * m + 2 < K) v[4 * m + 2] = t4.z;
+        if (4 * m + 3 < K) v[4 * m + 3] = t4.w;
+    }
+}
+template <int K>
+__device__ __forceinline__ void rec_store(float *p, const float (&v)[K]) {
+    float4 *p4 = reinterpret_cast<float4 *>(p);
+#pragma unroll
+    for (int m = 0; m < rec_pad(K) / 4; ++m)
+        p4[m] = make_float4(v[4 * m], 4 * m + 1 < K ? v[4 * m + 1] : 0.f,
+                            4 * m + 2 < K ? v[4 * m + 2] : 0.f, 4 * m + 3 < K ? v[4 * m + 3] : 0.f);
 }
 
 template <int K, class Fn>
@@ -753,16 +777,15 @@ __device__ __forceinline__ void pixels_to_lds(const TileGeom &g, const TileLds &
         const int rx = u % g.RX, ry = u / g.RX;
         float v[K];
         fn(g.X0 + rx, g.Y0 + ry, rx, ry, v);
-#pragma unroll
-        for (int k = 0; k < K; ++k) L.vals[(k * g.RY + ry) * g.RX + rx] = v[k];
+        rec_store<K>(L.vals + (size_t)u * rec_pad(K), v);
     }
 }
 
-// weight of node i for region column / row u
-__device__ __forceinline__ float bweight(const int *bi, const float *w0, const float *w1,
-                                         int u, int i, int G) {
-    if (G == 1) return w0[u];
-    return (bi[u] == i ? w0[u] : 0.f) + (bi[u] + 1 == i ? w1[u] : 0.f);
+// weight of node i in a region column's / row's bracket
+__device__ __forceinline__ float bweight(const float4 b, int i, int G) {
+    if (G == 1) return b.y;
+    const int i0 = __float_as_int(b.x);
+    return (i0 == i ? b.y : 0.f) + (i0 + 1 == i ? b.z : 0.f);
 }
 
 // Sum over the support of this thread's node (valid in the thread with
@@ -785,17 +808,18 @@ __device__ __forceinline__ void lds_to_nodes(const LevelArgs &a, const TileCfg &
         const int yb = min(sup_hi(j, S, a.d.Gy, a.d.H), g.Y1) - g.Y0;
         const int ry = ya + sub;
         if (ry <= yb) {
-            const float wy = bweight(L.byi, L.byw0, L.byw1, ry, j, a.d.Gy);
-            const float *row = L.vals + ry * g.RX;
+            const float wy = bweight(L.by[ry], j, a.d.Gy);
+            const float *row = L.vals + (size_t)ry * g.RX * rec_pad(K);
 #pragma unroll
             for (int c = 0; c < 2 * S; ++c) {
                 const int rx = xa + c;
                 if (rx <= xb) {
-                    const float w1 = bweight(L.bxi, L.bxw0, L.bxw1, rx, i, a.d.Gx) * wy;
+                    const float w1 = bweight(L.bx[rx], i, a.d.Gx) * wy;
                     const float w2 = w1 * w1;
+                    float v[K];
+                    rec_load<K>(row + (size_t)rx * rec_pad(K), v);
 #pragma unroll
-                    for (int k = 0; k < K; ++k)
-                        acc[k] += (((pow2 >> k) & 1u) ? w2 : w1) * row[k * g.RY * g.RX + rx];
+                    for (int k = 0; k < K; ++k) acc[k] += (((pow2 >> k) & 1u) ? w2 : w1) * v[k];
                 }
             }
         }
@@ -827,7 +851,7 @@ __device__ __forceinline__ void nb_offset(int k, int &di, int &dj) {
 
 template <bool B, int S>
 __global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(KArg<B> ka, TileCfg t) {
-    extern __shared__ float lds[];
+    extern __shared__ __attribute__((aligned(16))) float lds[];
     SF_BIND(ka);
     const LevelDims &d = a.d;
     const DevConst &C = *a.cst;
@@ -1028,7 +1052,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
                                                               int gn, int force) {
     constexpr int NT_TILE = TileTraits<S, V>::NT;
     constexpr int PPT = TileTraits<S, V>::PPT;
-    extern __shared__ float lds[];
+    extern __shared__ __attribute__((aligned(16))) float lds[];
     SF_BIND(ka);
     const int nb_prev = nblk;  // the previous iteration ran on the same tiles
     const int log_index = gn >= 0 ? a.log_base + gn : -1;
@@ -1084,7 +1108,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
         }
     }
     // halo node of this thread: the vectors u_i is formed from
-    const int HX = t.tx + 2, HY = t.ty + 2;
+    const int HX = t.tx + 2;
     const int hx0 = max(g.i0 - 1, 0), hx1 = min(g.i0 + g.txa, d.Gx - 1);
     const int hy0 = max(g.j0 - 1, 0), hy1 = min(g.j0 + g.tya, d.Gy - 1);
     const int hw = hx1 - hx0 + 1, hh = hy1 - hy0 + 1;
@@ -1150,7 +1174,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     }
 
     // ---- phase 2: u_i on the tile and its halo -----------------------------
-    float ru = 0.f, rr = 0.f, sv6[6], rn6[6];
+    float ru = 0.f, rr = 0.f, sv6[6], rn6[6], uh[6];
     if (hal) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
@@ -1164,10 +1188,11 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
                 uu = rn / hv3[q];
             }
             rn6[q] = rn;
-            L.halo[(q * HY + (hnj - g.j0 + 1)) * HX + (hni - g.i0 + 1)] = uu;
+            uh[q] = uu;
             ru += rn * uu;
             rr += rn * rn;
         }
+        rec_store<6>(L.halo + (size_t)((hnj - g.j0 + 1) * HX + (hni - g.i0 + 1)) * 8, uh);
         if (hown) {
             const int o = (hnj - g.j0) * t.tx + (hni - g.i0);
             L.ownd[o] = ru;
@@ -1182,24 +1207,29 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
         const int u = tid + k * NT_TILE;
         if (u < npx) {
             const int rx = u % g.RX, ry = u / g.RX;
-            const int bx0 = L.bxi[rx], by0 = L.byi[ry];
-            const float wx0 = L.bxw0[rx], wx1 = L.bxw1[rx], wy0 = L.byw0[ry], wy1 = L.byw1[ry];
+            const float4 bxr = L.bx[rx], byr = L.by[ry];
+            const int bx0 = __float_as_int(bxr.x), by0 = __float_as_int(byr.x);
+            const float wx0 = bxr.y, wx1 = bxr.z, wy0 = byr.y, wy1 = byr.z;
             const int lx0 = bx0 - g.i0 + 1, lx1 = (d.Gx == 1 ? bx0 : bx0 + 1) - g.i0 + 1;
             const int ly0 = by0 - g.j0 + 1, ly1 = (d.Gy == 1 ? by0 : by0 + 1) - g.j0 + 1;
+            float c00[6], c01[6], c10[6], c11[6];
+            rec_load<6>(L.halo + (size_t)(ly0 * HX + lx0) * 8, c00);
+            rec_load<6>(L.halo + (size_t)(ly0 * HX + lx1) * 8, c01);
+            rec_load<6>(L.halo + (size_t)(ly1 * HX + lx0) * 8, c10);
+            rec_load<6>(L.halo + (size_t)(ly1 * HX + lx1) * 8, c11);
             float pv[6];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                const float *Hq = L.halo + q * HY * HX;
-                pv[q] = wy0 * (wx0 * Hq[ly0 * HX + lx0] + wx1 * Hq[ly0 * HX + lx1]) +
-                        wy1 * (wx0 * Hq[ly1 * HX + lx0] + wx1 * Hq[ly1 * HX + lx1]);
-            }
+            for (int q = 0; q < 6; ++q)
+                pv[q] = wy0 * (wx0 * c00[q] + wx1 * c01[q]) + wy1 * (wx0 * c10[q] + wx1 * c11[q]);
+            float hv[6];
 #pragma unroll
             for (int r = 0; r < 6; ++r) {
                 float acc = 0.f;
 #pragma unroll
                 for (int c = 0; c < 6; ++c) acc += Gm[k][gram_index(r, c)] * pv[c];
-                L.vals[(r * g.RY + ry) * g.RX + rx] = acc;
+                hv[r] = acc;
             }
+            rec_store<6>(L.vals + (size_t)u * 8, hv);
         }
     }
     __syncthreads();
@@ -1211,24 +1241,27 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     float prt[3] = {0.f, 0.f, 0.f};
     float w6[6], uv[6];
     if (mine) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) uv[q] = L.halo[(q * HY + tj + 1) * HX + ti + 1];
+        rec_load<6>(L.halo + (size_t)((tj + 1) * HX + ti + 1) * 8, uv);
         float jp0 = 0.f, jp1 = 0.f;
 #pragma unroll
         for (int q = 0; q < 6; ++q) { jp0 += rg[4 + q] * uv[q]; jp1 += rg[10 + q] * uv[q]; }
+        float sm[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int di, dj;
+            nb_offset(k, di, dj);
+            // neighbours outside the grid have coefficient 0; their halo
+            // record is never written, so it is not read
+            if (rg[k] != 0.f) {
+                float un[6];
+                rec_load<6>(L.halo + (size_t)((tj + 1 + dj) * HX + ti + 1 + di) * 8, un);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) sm[q] += rg[k] * (uv[q] - un[q]);
+            }
+        }
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            float sm = 0.f;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                int di, dj;
-                nb_offset(k, di, dj);
-                // neighbours outside the grid have coefficient 0; their halo
-                // slot is never written, so it is not read
-                if (rg[k] != 0.f)
-                    sm += rg[k] * (uv[q] - L.halo[(q * HY + tj + 1 + dj) * HX + ti + 1 + di]);
-            }
-            w6[q] = acc[q] + wf[q] * sm + rg[4 + q] * jp0 + rg[10 + q] * jp1 + cm[q] * uv[q];
+            w6[q] = acc[q] + wf[q] * sm[q] + rg[4 + q] * jp0 + rg[10 + q] * jp1 + cm[q] * uv[q];
             prt[1] += w6[q] * uv[q];
         }
         const int o = tj * t.tx + ti;
