@@ -712,7 +712,8 @@ __device__ __forceinline__ TileGeom tile_geom(const LevelArgs &a, const TileCfg 
 // index as int bits, its weight, the next node's weight).
 struct TileLds {
     float4 *bx, *by;  // brackets of region columns / rows
-    float *vals;      // RY x RX records of KP floats
+    int pitch;        // floats per row of records
+    float *vals;      // RY rows of RX records of KP floats
     float *halo;      // (ty + 2) x (tx + 2) records of 8 floats
     float *ownd;      // 2 x tx x ty scratch per owned node
 };
@@ -720,9 +721,15 @@ struct TileLds {
 __host__ __device__ constexpr int rec_pad(int K) { return (K + 3) / 4 * 4; }
 __host__ __device__ inline int tile_rxs(const TileCfg &t, int s) { return (t.tx + 1) * s + 2; }
 __host__ __device__ inline int tile_rys(const TileCfg &t, int s) { return (t.ty + 1) * s + 2; }
+// Row pitch (floats) of the per-pixel records: a multiple of 32 floats plus
+// 4, so that the rows a node's threads read at one column fall on
+// different 16-byte bank groups.
+__host__ __device__ inline int tile_pitch(const TileCfg &t, int s, int K) {
+    return (tile_rxs(t, s) * rec_pad(K) + 31) / 32 * 32 + 4;
+}
 __host__ __device__ inline size_t tile_lds_floats(const TileCfg &t, int s, int K) {
     const size_t RXs = tile_rxs(t, s), RYs = tile_rys(t, s);
-    return 4 * RXs + 4 * RYs + (size_t)rec_pad(K) * RXs * RYs +
+    return 4 * RXs + 4 * RYs + (size_t)tile_pitch(t, s, K) * RYs +
            (size_t)8 * (t.tx + 2) * (t.ty + 2) + (size_t)2 * t.tx * t.ty;
 }
 
@@ -731,8 +738,9 @@ __device__ TileLds tile_lds(float *lds, const TileCfg &t, int s, int K) {
     TileLds L;
     L.bx = reinterpret_cast<float4 *>(lds);
     L.by = L.bx + RXs;
+    L.pitch = tile_pitch(t, s, K);
     L.vals = reinterpret_cast<float *>(L.by + RYs);
-    L.halo = L.vals + (size_t)rec_pad(K) * RXs * RYs;
+    L.halo = L.vals + (size_t)L.pitch * RYs;
     L.ownd = L.halo + (size_t)8 * (t.tx + 2) * (t.ty + 2);
     return L;
 }
@@ -777,7 +785,7 @@ __device__ __forceinline__ void pixels_to_lds(const TileGeom &g, const TileLds &
         const int rx = u % g.RX, ry = u / g.RX;
         float v[K];
         fn(g.X0 + rx, g.Y0 + ry, rx, ry, v);
-        rec_store<K>(L.vals + (size_t)u * rec_pad(K), v);
+        rec_store<K>(L.vals + (size_t)ry * L.pitch + rx * rec_pad(K), v);
     }
 }
 
@@ -809,7 +817,7 @@ __device__ __forceinline__ void lds_to_nodes(const LevelArgs &a, const TileCfg &
         const int ry = ya + sub;
         if (ry <= yb) {
             const float wy = bweight(L.by[ry], j, a.d.Gy);
-            const float *row = L.vals + (size_t)ry * g.RX * rec_pad(K);
+            const float *row = L.vals + (size_t)ry * L.pitch;
 #pragma unroll
             for (int c = 0; c < 2 * S; ++c) {
                 const int rx = xa + c;
@@ -1229,7 +1237,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
                 for (int c = 0; c < 6; ++c) acc += Gm[k][gram_index(r, c)] * pv[c];
                 hv[r] = acc;
             }
-            rec_store<6>(L.vals + (size_t)u * 8, hv);
+            rec_store<6>(L.vals + (size_t)ry * L.pitch + rx * 8, hv);
         }
     }
     __syncthreads();
