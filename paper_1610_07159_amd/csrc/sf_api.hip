@@ -268,7 +268,7 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
                                (size_t)F.N0,
                                sizeof(float) * (size_t)F.G0,
                                sizeof(float) * 16 * (size_t)F.G0,
-                               sizeof(float) * NV_COUNT * 6 * (size_t)F.G0,
+                               sizeof(float) * NV_COUNT * 8 * (size_t)F.G0,
                                sizeof(float) * SF_GRAM_STRIDE * (size_t)F.N0,
                                sizeof(float) * PS_COUNT * (size_t)mb,
                                sizeof(DevScalars),
@@ -1036,12 +1036,23 @@ static sf_status debug_copy(sf_ctx *c, int what, int level, void *host, size_t b
             ok = cp(&F.sc->e_lin[0], 0, bytes);
             break;
         default: {
+            // node records on the device, six planes at the interface
             const int v = node_vec_of(what);
             if (v < 0) return SF_ERR_INVALID_ARG;
-            float *base = F.nodes + (size_t)v * 6 * F.G0;
-            for (int q = 0; q < 6 && ok; ++q)
-                ok = cp(base + (size_t)q * F.G0, sizeof(float) * (size_t)q * d.G,
-                        sizeof(float) * d.G);
+            float *base = F.nodes + (size_t)v * 8 * F.G0;
+            std::vector<float> rec((size_t)8 * d.G, 0.f);
+            float *hp = (float *)host;
+            if (to_device) {
+                ok = hipMemcpy(rec.data(), base, rec.size() * sizeof(float),
+                               hipMemcpyDeviceToHost) == hipSuccess;
+                for (long n = 0; ok && n < d.G; ++n)
+                    for (int q = 0; q < 6; ++q) rec[n * 8 + q] = hp[(size_t)q * d.G + n];
+                ok = ok && hipMemcpy(base, rec.data(), rec.size() * sizeof(float), kind) == hipSuccess;
+            } else {
+                ok = hipMemcpy(rec.data(), base, rec.size() * sizeof(float), kind) == hipSuccess;
+                for (long n = 0; ok && n < d.G; ++n)
+                    for (int q = 0; q < 6; ++q) hp[(size_t)q * d.G + n] = rec[n * 8 + q];
+            }
         }
     }
     return ok ? SF_OK : SF_ERR_HIP;

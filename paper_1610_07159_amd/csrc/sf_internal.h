@@ -39,7 +39,8 @@ __host__ __device__ inline int gram_index(int i, int j) {
     return i == j ? i : 6 + i * 5 - (i * (i - 1)) / 2 + (j - i - 1);
 }
 
-// Node vectors (each 6 planes of G_0 floats).  The PCG runs in the
+// Node vectors (each G_0 records of 8 floats: s_x, s_y, m_x, m_y, d_x, d_y
+// and 2 padding).  The PCG runs in the
 // single-reduction form: r, w = H u and s = H p alternate between two
 // buffers by iteration parity because neighbouring tiles read them.
 enum {
@@ -155,7 +156,7 @@ struct LevelArgs {
     float *grad;           // per-pixel gradients (SF_GRAD_STRIDE)
     unsigned char *cmask;  // V(x) W(x)
     float *wnode;          // smoothness weights
-    float *reg;            // 16 planes of G_0: per-node regulariser record
+    float *reg;            // per-node regulariser record, 16 floats per node
     float *partials;       // per-workgroup partial sums
     int max_blocks;        // stride of the partial-sum planes
     const DevConst *cst;

@@ -252,6 +252,24 @@ __device__ __forceinline__ void bind(const FrameMap &m, LevelArgs &a, int &bid, 
     bid = b - m.first[f];
     nblk = m.first[f + 1] - m.first[f];
 }
+// ---- node vectors ------------------------------------------------------------
+//
+// A node vector holds one 8-float record per node (s_x, s_y, m_x, m_y, d_x,
+// d_y, 2 pad) so that a node's components move with one 16-byte and one
+// 8-byte access; vector v of the level starts at nodes + v * 8 G_0.
+__device__ __forceinline__ float *nvec(const LevelArgs &a, int v) {
+    return a.nodes + (size_t)v * 8 * a.G0;
+}
+__device__ __forceinline__ void ld6(const float *vec, long n, float (&x)[6]) {
+    const float4 p = *reinterpret_cast<const float4 *>(vec + n * 8);
+    const float2 q = *reinterpret_cast<const float2 *>(vec + n * 8 + 4);
+    x[0] = p.x; x[1] = p.y; x[2] = p.z; x[3] = p.w; x[4] = q.x; x[5] = q.y;
+}
+__device__ __forceinline__ void st6(float *vec, long n, const float (&x)[6]) {
+    *reinterpret_cast<float4 *>(vec + n * 8) = make_float4(x[0], x[1], x[2], x[3]);
+    *reinterpret_cast<float2 *>(vec + n * 8 + 4) = make_float2(x[4], x[5]);
+}
+
 #define SF_BIND(ka)              \
     LevelArgs a;                 \
     int bid, nblk;               \
@@ -399,20 +417,26 @@ __device__ void stage_nodes(const LevelArgs &a, int x0, int y0, float tau,
     const int nx0 = bx0.i0, nx1 = bx1.i1, ny0 = by0.i0, ny1 = by1.i1;
     const int cw = nx1 - nx0 + 1, ch = ny1 - ny0 + 1;
     if (threadIdx.x == 0) { S.nx0 = nx0; S.ny0 = ny0; }
-    const float *base = a.nodes + (long)NV_BASE * 6 * a.G0;
-    const float *delta = a.nodes + (long)NV_DELTA * 6 * a.G0;
-    const float *dx = a.nodes + (long)NV_X * 6 * a.G0;
-    for (int t = threadIdx.x; t < 6 * cw * ch; t += blockDim.x) {
-        const int q = t / (cw * ch), r = t % (cw * ch);
-        const int j = r / cw, i = r % cw;
+    const float *base = nvec(a, NV_BASE);
+    const float *delta = nvec(a, NV_DELTA);
+    const float *dx = nvec(a, NV_X);
+    for (int t = threadIdx.x; t < cw * ch; t += blockDim.x) {
+        const int j = t / cw, i = t % cw;
         const long n = (long)(ny0 + j) * d.Gx + (nx0 + i);
-        float dl = delta[q * a.G0 + n];
-        if (tau != 0.f) dl = dl + tau * dx[q * a.G0 + n];
-        S.t[q][j][i] = base[q * a.G0 + n] + dl;
+        float b[6], dl[6], x[6];
+        ld6(base, n, b);
+        ld6(delta, n, dl);
+        if (tau != 0.f) ld6(dx, n, x);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            float v = dl[q];
+            if (tau != 0.f) v = v + tau * x[q];
+            S.t[q][j][i] = b[q] + v;
+        }
     }
 }
 
-// Node values of one vector (6 planes) that a pixel tile touches, staged
+// Node values of one vector that a pixel tile touches, staged
 // in LDS like stage_nodes.
 __device__ void stage_vector(const LevelArgs &a, int x0, int y0, const float *vec,
                              NodeStage &S) {
@@ -424,10 +448,12 @@ __device__ void stage_vector(const LevelArgs &a, int x0, int y0, const float *ve
     const int nx0 = bx0.i0, nx1 = bx1.i1, ny0 = by0.i0, ny1 = by1.i1;
     const int cw = nx1 - nx0 + 1, ch = ny1 - ny0 + 1;
     if (threadIdx.x == 0) { S.nx0 = nx0; S.ny0 = ny0; }
-    for (int t = threadIdx.x; t < 6 * cw * ch; t += blockDim.x) {
-        const int q = t / (cw * ch), r = t % (cw * ch);
-        const int j = r / cw, i = r % cw;
-        S.t[q][j][i] = vec[q * a.G0 + (long)(ny0 + j) * d.Gx + (nx0 + i)];
+    for (int t = threadIdx.x; t < cw * ch; t += blockDim.x) {
+        const int j = t / cw, i = t % cw;
+        float v[6];
+        ld6(vec, (long)(ny0 + j) * d.Gx + (nx0 + i), v);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) S.t[q][j][i] = v[q];
     }
 }
 
@@ -553,16 +579,17 @@ __device__ void node_energy(const LevelArgs &a, int n, float tau, float (&part)[
     const LevelDims &d = a.d;
     const DevConst &C = *a.cst;
     const int i = n % d.Gx, j = n / d.Gx;
-    const long G0 = a.G0;
-    const float *base = a.nodes + (long)NV_BASE * 6 * G0;
-    const float *delta = a.nodes + (long)NV_DELTA * 6 * G0;
-    const float *dx = a.nodes + (long)NV_X * 6 * G0;
-    float dl[6], tot[6];
+    const float *base = nvec(a, NV_BASE);
+    const float *delta = nvec(a, NV_DELTA);
+    const float *dx = nvec(a, NV_X);
+    float dl[6], tot[6], b[6], x[6];
+    ld6(delta, n, dl);
+    ld6(base, n, b);
+    if (tau != 0.f) ld6(dx, n, x);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
-        dl[q] = delta[q * G0 + n];
-        if (tau != 0.f) dl[q] = dl[q] + tau * dx[q * G0 + n];
-        tot[q] = base[q * G0 + n] + dl[q];
+        if (tau != 0.f) dl[q] = dl[q] + tau * x[q];
+        tot[q] = b[q] + dl[q];
     }
     const float wi = a.wnode[n];
     float es = 0.f;
@@ -572,12 +599,15 @@ __device__ void node_energy(const LevelArgs &a, int n, float tau, float (&part)[
         const int ii = i + nb[k][0], jj = j + nb[k][1];
         if (ii < 0 || ii >= d.Gx || jj < 0 || jj >= d.Gy) continue;
         const int m = jj * d.Gx + ii;
+        float dm[6], xm[6];
+        ld6(delta, m, dm);
+        if (tau != 0.f) ld6(dx, m, xm);
         float acc = 0.f;
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            float dm = delta[q * G0 + m];
-            if (tau != 0.f) dm = dm + tau * dx[q * G0 + m];
-            const float df = dl[q] - dm;
+            float v = dm[q];
+            if (tau != 0.f) v = v + tau * xm[q];
+            const float df = dl[q] - v;
             acc += C.wf[q] * df * df;
         }
         es += wi * acc;
@@ -842,8 +872,8 @@ __device__ __forceinline__ void lds_to_nodes(const LevelArgs &a, const TileCfg &
 //     grad += 2 w_reg w_smooth w_f sum_j (w_i + w_j)(D_i - D_j)
 //   epipolar (Eqs. (15)-(17), on totals): grad += 2 w_reg w_epi sum_t e_t de_t
 //   magnitude (Eq. (18), on deltas): grad += 2 w_reg w_mag m_f D_i
-// The right-hand-side kernel stores, per node, a record of the pieces the
-// H-products need: the four smoothness coefficients
+// The right-hand-side kernel stores, per node, a 16-float record of the
+// pieces the H-products need: the four smoothness coefficients
 // 2 w_reg w_smooth (w_i + w_j) (0 without a neighbour) and the two epipolar
 // gradients scaled by sqrt(2 w_reg w_epi), so that
 //   (H_reg u)_i = sum_j c_j w_f (u_i - u_j) + sum_t J_t (J_t . u_i)
@@ -870,19 +900,19 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(KArg<B> ka, TileCfg t
     const int nl = tid / t.tpn, sub = tid % t.tpn;
     const bool mine = sub == 0 && nl < g.txa * g.tya;
     const int i = g.i0 + (nl % max(g.txa, 1)), j = g.j0 + nl / max(g.txa, 1);
-    const long G0 = a.G0, n = (long)j * d.Gx + i;
-    const float *base = a.nodes + (long)NV_BASE * 6 * G0;
-    const float *delta = a.nodes + (long)NV_DELTA * 6 * G0;
+    const long n = (long)j * d.Gx + i;
+    const float *base = nvec(a, NV_BASE);
+    const float *delta = nvec(a, NV_DELTA);
     // own node: totals, deltas, neighbour deltas and weights
     float dl[6], tot[6], dn[4][6], wn[4], wi = 0.f;
     int has[4];
     if (mine) {
         wi = a.wnode[n];
+        float b[6];
+        ld6(delta, n, dl);
+        ld6(base, n, b);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            dl[q] = delta[q * G0 + n];
-            tot[q] = base[q * G0 + n] + dl[q];
-        }
+        for (int q = 0; q < 6; ++q) tot[q] = b[q] + dl[q];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             int di, dj;
@@ -890,8 +920,7 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(KArg<B> ka, TileCfg t
             has[k] = i + di >= 0 && i + di < d.Gx && j + dj >= 0 && j + dj < d.Gy;
             const long m = has[k] ? (long)(j + dj) * d.Gx + i + di : n;
             wn[k] = has[k] ? a.wnode[m] : 0.f;
-#pragma unroll
-            for (int q = 0; q < 6; ++q) dn[k][q] = delta[q * G0 + m];
+            ld6(delta, m, dn[k]);
         }
     }
     if (bid == 0) {
@@ -943,27 +972,24 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(KArg<B> ka, TileCfg t
         epi_terms(C.F[a.level], gx, gy, tot, e, J);
         const float ce = 2.f * C.w_reg * C.w_epi, cm = 2.f * C.w_reg * C.w_mag;
         const float se = sqrtf(ce);
-        float *X = a.nodes + (long)NV_X * 6 * G0;
-        float *R = a.nodes + (long)NV_R0 * 6 * G0;
-        float *U = a.nodes + (long)NV_U * 6 * G0;
-        float *D = a.nodes + (long)NV_DIAG * 6 * G0;
+        float rv[6], uv[6];
+        const float zero[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             grad[q] += ce * (e[0] * J[0][q] + e[1] * J[1][q]) + cm * C.mf[q] * dl[q];
             dg[q] += ce * (J[0][q] * J[0][q] + J[1][q] * J[1][q]) + cm * C.mf[q];
-            const float r = -grad[q];
-            X[q * G0 + n] = 0.f;
-            R[q * G0 + n] = r;
-            U[q * G0 + n] = r / dg[q];
-            D[q * G0 + n] = dg[q];
+            rv[q] = -grad[q];
+            uv[q] = rv[q] / dg[q];
         }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) a.reg[k * G0 + n] = cnb[k];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            a.reg[(4 + q) * G0 + n] = se * J[0][q];
-            a.reg[(10 + q) * G0 + n] = se * J[1][q];
-        }
+        st6(nvec(a, NV_X), n, zero);
+        st6(nvec(a, NV_R0), n, rv);
+        st6(nvec(a, NV_U), n, uv);
+        st6(nvec(a, NV_DIAG), n, dg);
+        float4 *rg4 = reinterpret_cast<float4 *>(a.reg + n * REG_PLANES);
+        rg4[0] = make_float4(cnb[0], cnb[1], cnb[2], cnb[3]);
+        rg4[1] = make_float4(se * J[0][0], se * J[0][1], se * J[0][2], se * J[0][3]);
+        rg4[2] = make_float4(se * J[0][4], se * J[0][5], se * J[1][0], se * J[1][1]);
+        rg4[3] = make_float4(se * J[1][2], se * J[1][3], se * J[1][4], se * J[1][5]);
     }
 }
 
@@ -1065,21 +1091,20 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     const int nb_prev = nblk;  // the previous iteration ran on the same tiles
     const int log_index = gn >= 0 ? a.log_base + gn : -1;
     const LevelDims &d = a.d;
-    const long G0 = a.G0;
     const TileGeom g = tile_geom(a, t, bid);
     const TileLds L = tile_lds(lds, t, S, 6);
     const int tid = threadIdx.x;
-    const float *Rp = a.nodes + (long)(((i - 1) & 1) ? NV_R1 : NV_R0) * 6 * G0;
-    float *Rc = a.nodes + (long)((i & 1) ? NV_R1 : NV_R0) * 6 * G0;
-    const float *Wp = a.nodes + (long)(((i - 1) & 1) ? NV_W1 : NV_W0) * 6 * G0;
-    float *Wc = a.nodes + (long)((i & 1) ? NV_W1 : NV_W0) * 6 * G0;
-    const float *Sp = a.nodes + (long)(((i - 2) & 1) ? NV_S1 : NV_S0) * 6 * G0;
-    float *Sc = a.nodes + (long)(((i - 1) & 1) ? NV_S1 : NV_S0) * 6 * G0;
-    float *U = a.nodes + (long)NV_U * 6 * G0;
-    float *P = a.nodes + (long)NV_P * 6 * G0;
-    float *X = a.nodes + (long)NV_X * 6 * G0;
-    const float *D = a.nodes + (long)NV_DIAG * 6 * G0;
-    const float *R0 = a.nodes + (long)NV_R0 * 6 * G0;
+    const float *Rp = nvec(a, ((i - 1) & 1) ? NV_R1 : NV_R0);
+    float *Rc = nvec(a, (i & 1) ? NV_R1 : NV_R0);
+    const float *Wp = nvec(a, ((i - 1) & 1) ? NV_W1 : NV_W0);
+    float *Wc = nvec(a, (i & 1) ? NV_W1 : NV_W0);
+    const float *Sp = nvec(a, ((i - 2) & 1) ? NV_S1 : NV_S0);
+    float *Sc = nvec(a, ((i - 1) & 1) ? NV_S1 : NV_S0);
+    float *U = nvec(a, NV_U);
+    float *P = nvec(a, NV_P);
+    float *X = nvec(a, NV_X);
+    const float *D = nvec(a, NV_DIAG);
+    const float *R0 = nvec(a, NV_R0);
 
     // ---- phase 0: loads --------------------------------------------------
     float wf[6], cm[6];
@@ -1126,18 +1151,19 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     const bool hown = hal && hni >= g.i0 && hni < g.i0 + g.txa && hnj >= g.j0 && hnj < g.j0 + g.tya;
     float hv0[6], hv1[6], hv2[6], hv3[6];
     if (hal) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            const long k = q * G0 + hn;
-            if (FIRST) {
-                hv0[q] = U[k];
-                hv1[q] = R0[k];
+        if (FIRST) {
+            ld6(U, hn, hv0);
+            ld6(R0, hn, hv1);
+        } else {
+            ld6(Rp, hn, hv0);
+            ld6(Wp, hn, hv1);
+            if (i > 1) {
+                ld6(Sp, hn, hv2);
             } else {
-                hv0[q] = Rp[k];
-                hv1[q] = Wp[k];
-                hv2[q] = i > 1 ? Sp[k] : 0.f;
-                hv3[q] = D[k];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) hv2[q] = 0.f;
             }
+            ld6(D, hn, hv3);
         }
     }
     // owned node of this thread's node group: its regulariser record
@@ -1149,7 +1175,13 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     float rg[REG_PLANES];
     if (mine) {
 #pragma unroll
-        for (int k = 0; k < REG_PLANES; ++k) rg[k] = a.reg[k * G0 + n_own];
+        for (int k = 0; k < REG_PLANES / 4; ++k) {
+            const float4 t4 = reinterpret_cast<const float4 *>(a.reg + n_own * REG_PLANES)[k];
+            rg[4 * k] = t4.x;
+            rg[4 * k + 1] = t4.y;
+            rg[4 * k + 2] = t4.z;
+            rg[4 * k + 3] = t4.w;
+        }
     }
     // the owned node's u, p and x: read here in single-frame launches (one
     // fewer dependent memory round trip, same occupancy); batched launches,
@@ -1158,12 +1190,13 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     float uo[6], po[6], xo[6];
     auto load_own = [&]() {
         if (mine && !FIRST) {
+            ld6(U, n_own, uo);
+            ld6(X, n_own, xo);
+            if (i > 1) {
+                ld6(P, n_own, po);
+            } else {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                const long k = q * G0 + n_own;
-                uo[q] = U[k];
-                po[q] = i > 1 ? P[k] : 0.f;
-                xo[q] = X[k];
+                for (int q = 0; q < 6; ++q) po[q] = 0.f;
             }
         }
     };
@@ -1281,23 +1314,21 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
 
     // ---- stores ---------------------------------------------------------------
     if (hown && !FIRST) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            Sc[q * G0 + hn] = sv6[q];
-            Rc[q * G0 + hn] = rn6[q];
-        }
+        st6(Sc, hn, sv6);
+        st6(Rc, hn, rn6);
     }
     if (mine) {
+        st6(Wc, n_own, w6);
+        if (!FIRST) {
+            float pn[6], xn[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            const long k = q * G0 + n_own;
-            Wc[k] = w6[q];
-            if (!FIRST) {
-                const float pv = i > 1 ? uo[q] + beta * po[q] : uo[q];
-                P[k] = pv;
-                X[k] = xo[q] + alpha * pv;
-                U[k] = uv[q];
+            for (int q = 0; q < 6; ++q) {
+                pn[q] = i > 1 ? uo[q] + beta * po[q] : uo[q];
+                xn[q] = xo[q] + alpha * pn[q];
             }
+            st6(P, n_own, pn);
+            st6(X, n_own, xn);
+            st6(U, n_own, uv);
         }
     }
     if (tid == 0) {
@@ -1313,15 +1344,14 @@ __global__ __launch_bounds__(SF_BLOCK) void k_pcg_last(KArg<B> ka, TileCfg t, in
     SF_BIND(ka);
     const int nb_prev = node_tiles_of(a.d, t);
     const int log_index = gn >= 0 ? a.log_base + gn : -1;
-    const long G0 = a.G0;
     const int i = n_it;
-    const float *Rp = a.nodes + (long)(((i - 1) & 1) ? NV_R1 : NV_R0) * 6 * G0;
-    float *Rc = a.nodes + (long)((i & 1) ? NV_R1 : NV_R0) * 6 * G0;
-    const float *Wp = a.nodes + (long)(((i - 1) & 1) ? NV_W1 : NV_W0) * 6 * G0;
-    const float *Sp = a.nodes + (long)(((i - 2) & 1) ? NV_S1 : NV_S0) * 6 * G0;
-    const float *U = a.nodes + (long)NV_U * 6 * G0;
-    float *P = a.nodes + (long)NV_P * 6 * G0;
-    float *X = a.nodes + (long)NV_X * 6 * G0;
+    const float *Rp = nvec(a, ((i - 1) & 1) ? NV_R1 : NV_R0);
+    float *Rc = nvec(a, (i & 1) ? NV_R1 : NV_R0);
+    const float *Wp = nvec(a, ((i - 1) & 1) ? NV_W1 : NV_W0);
+    const float *Sp = nvec(a, ((i - 2) & 1) ? NV_S1 : NV_S0);
+    const float *U = nvec(a, NV_U);
+    float *P = nvec(a, NV_P);
+    float *X = nvec(a, NV_X);
     const long n = (long)bid * SF_BLOCK + threadIdx.x;
     const bool in = n < a.d.G;
     double pacc[3];
@@ -1331,12 +1361,16 @@ __global__ __launch_bounds__(SF_BLOCK) void k_pcg_last(KArg<B> ka, TileCfg t, in
     if (threadIdx.x == 0) h = a.sc->hist[i - 1];
     float rp[6], wp[6], sp[6], up[6], pp[6], xp[6];
     if (in) {
+        ld6(Rp, n, rp);
+        ld6(Wp, n, wp);
+        ld6(U, n, up);
+        ld6(X, n, xp);
+        if (i > 1) {
+            ld6(Sp, n, sp);
+            ld6(P, n, pp);
+        } else {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            const long k = q * G0 + n;
-            rp[q] = Rp[k]; wp[q] = Wp[k]; up[q] = U[k]; xp[q] = X[k];
-            sp[q] = i > 1 ? Sp[k] : 0.f;
-            pp[q] = i > 1 ? P[k] : 0.f;
+            for (int q = 0; q < 6; ++q) sp[q] = pp[q] = 0.f;
         }
     }
     float alpha, beta;
@@ -1344,20 +1378,23 @@ __global__ __launch_bounds__(SF_BLOCK) void k_pcg_last(KArg<B> ka, TileCfg t, in
     pcg_decide(a, bid, i, pacc, h, log_index, force, alpha, beta, act);
     float prt[1] = {0.f};
     if (in) {
+        float rn[6], pn[6], xn[6];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            const long k = q * G0 + n;
-            float rn = rp[q];
+            rn[q] = rp[q];
             if (act) {
                 const float sv = i > 1 ? wp[q] + beta * sp[q] : wp[q];
-                const float pv = i > 1 ? up[q] + beta * pp[q] : up[q];
-                P[k] = pv;
-                X[k] = xp[q] + alpha * pv;
-                rn = rn - alpha * sv;
+                pn[q] = i > 1 ? up[q] + beta * pp[q] : up[q];
+                xn[q] = xp[q] + alpha * pn[q];
+                rn[q] = rn[q] - alpha * sv;
             }
-            Rc[k] = rn;
-            prt[0] += rn * rn;
+            prt[0] += rn[q] * rn[q];
         }
+        if (act) {
+            st6(P, n, pn);
+            st6(X, n, xn);
+        }
+        st6(Rc, n, rn);
     }
     float tot1[1];
     block_sum<1>(prt, tot1);
@@ -1379,13 +1416,15 @@ __global__ __launch_bounds__(SF_BLOCK) void k_accept(KArg<B> ka, int n_trials, i
     for (int k = 0; k < n_trials; ++k)
         if (sc->e_trial[k][5] <= e0) { kacc = k; break; }
     const float tau = kacc >= 0 ? ldexpf(1.f, -kacc) : 0.f;
-    const long G0 = a.G0;
     const long n = (long)bid * SF_BLOCK + threadIdx.x;
     if (kacc >= 0 && n < a.d.G) {
-        float *delta = a.nodes + (long)NV_DELTA * 6 * G0;
-        const float *X = a.nodes + (long)NV_X * 6 * G0;
+        float *delta = nvec(a, NV_DELTA);
+        float dl[6], x[6];
+        ld6(delta, n, dl);
+        ld6(nvec(a, NV_X), n, x);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) delta[q * G0 + n] = delta[q * G0 + n] + tau * X[q * G0 + n];
+        for (int q = 0; q < 6; ++q) dl[q] = dl[q] + tau * x[q];
+        st6(delta, n, dl);
     }
     if (bid == 0 && log_index >= 0) {
         const float *rrp = a.partials +
@@ -1435,15 +1474,16 @@ __global__ __launch_bounds__(SF_BLOCK) void k_cnn_nodes(KArg<B> ka) {
     const int x0 = min((int)floorf(u), max(W4 - 2, 0)), y0 = min((int)floorf(v), max(H4 - 2, 0));
     const int x1 = min(x0 + 1, W4 - 1), y1 = min(y0 + 1, H4 - 1);
     const float fx = u - (float)x0, fy = v - (float)y0;
-    float *P = a.nodes + (long)NV_P * 6 * a.G0;
     const long N4 = (long)W4 * H4;
+    float cand[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         const float *o = a.cnn_out + q * N4;
         const float val = (1.f - fy) * ((1.f - fx) * o[y0 * W4 + x0] + fx * o[y0 * W4 + x1]) +
                           fy * ((1.f - fx) * o[y1 * W4 + x0] + fx * o[y1 * W4 + x1]);
-        P[q * a.G0 + n] = val / r;
+        cand[q] = val / r;
     }
+    st6(nvec(a, NV_P), n, cand);
 }
 
 // Energies of Eq. (8) at zero deltas for the candidate (P vector) and for
@@ -1462,7 +1502,7 @@ __global__ __launch_bounds__(SF_BLOCK) void k_fallback(KArg<B> ka) {
     if (bid < n_pix) {
         const int tiles_x = (d.W + TILE_PX - 1) / TILE_PX;
         const int x0 = (bid % tiles_x) * TILE_PX, y0 = (bid / tiles_x) * TILE_PX;
-        stage_vector(a, x0, y0, a.nodes + (long)NV_P * 6 * a.G0, S);
+        stage_vector(a, x0, y0, nvec(a, NV_P), S);
         __syncthreads();
         const int x = x0 + (threadIdx.x & (TILE_PX - 1));
         const int y = y0 + (threadIdx.x / TILE_PX);
@@ -1490,13 +1530,10 @@ __global__ __launch_bounds__(SF_BLOCK) void k_fallback(KArg<B> ka) {
             const int i = (int)(n % d.Gx), j = (int)(n / d.Gx);
             float gx, gy;
             node_xy(i, j, a.s, gx, gy);
-            const float *P = a.nodes + (long)NV_P * 6 * a.G0;
             float tot[6], zero[6], e[2], J[2][6];
+            ld6(nvec(a, NV_P), n, tot);
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                tot[q] = P[q * a.G0 + n];
-                zero[q] = 0.f;
-            }
+            for (int q = 0; q < 6; ++q) zero[q] = 0.f;
             const float ce = C.w_reg * C.w_epi;
             epi_terms(C.F[a.level], gx, gy, tot, e, J);
             part[0] = ce * (e[0] * e[0] + e[1] * e[1]);
@@ -1533,28 +1570,33 @@ __global__ __launch_bounds__(SF_BLOCK) void k_prolong(KArg<B> ka) {
     }
     const long n = (long)bid * SF_BLOCK + threadIdx.x;
     if (n >= a.d.G) return;
-    const long G0 = a.G0;
-    float *base = a.nodes + (long)NV_BASE * 6 * G0;
-    float *delta = a.nodes + (long)NV_DELTA * 6 * G0;
-    const float *tp = a.nodes + (long)NV_TPREV * 6 * G0;
-    const float *cand = a.nodes + (long)NV_P * 6 * G0;
+    const float *tp = nvec(a, NV_TPREV);
     const int i = (int)(n % a.d.Gx), j = (int)(n / a.d.Gx);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        float v = 0.f;
-        if (coarsest) {
-            v = use_cnn ? cand[q * G0 + n] : 0.f;
+    float v[6];
+    const float zero[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (coarsest) {
+        if (use_cnn) {
+            ld6(nvec(a, NV_P), n, v);
         } else {
-            // fine node i has coarse coordinate (2i - 1)/4: the bracket rule
-            // with stride 2
-            const Bracket bx = bracket(i, 2, Gxc), by = bracket(j, 2, Gyc);
-            const float *T = tp + q * G0;
-            v = 2.f * (by.w0 * (bx.w0 * T[by.i0 * Gxc + bx.i0] + bx.w1 * T[by.i0 * Gxc + bx.i1]) +
-                       by.w1 * (bx.w0 * T[by.i1 * Gxc + bx.i0] + bx.w1 * T[by.i1 * Gxc + bx.i1]));
+#pragma unroll
+            for (int q = 0; q < 6; ++q) v[q] = 0.f;
         }
-        base[q * G0 + n] = v;
-        delta[q * G0 + n] = 0.f;
+    } else {
+        // fine node i has coarse coordinate (2i - 1)/4: the bracket rule
+        // with stride 2
+        const Bracket bx = bracket(i, 2, Gxc), by = bracket(j, 2, Gyc);
+        float t00[6], t01[6], t10[6], t11[6];
+        ld6(tp, by.i0 * Gxc + bx.i0, t00);
+        ld6(tp, by.i0 * Gxc + bx.i1, t01);
+        ld6(tp, by.i1 * Gxc + bx.i0, t10);
+        ld6(tp, by.i1 * Gxc + bx.i1, t11);
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            v[q] = 2.f * (by.w0 * (bx.w0 * t00[q] + bx.w1 * t01[q]) +
+                          by.w1 * (bx.w0 * t10[q] + bx.w1 * t11[q]));
     }
+    st6(nvec(a, NV_BASE), n, v);
+    st6(nvec(a, NV_DELTA), n, zero);
 }
 
 // V(x): all four positions inside the level image; W(x): max_k |d_k| <
@@ -1647,12 +1689,12 @@ __global__ __launch_bounds__(SF_BLOCK) void k_finish_level(KArg<B> ka) {
     SF_BIND(ka);
     const long n = (long)bid * SF_BLOCK + threadIdx.x;
     if (n >= a.d.G) return;
-    const long G0 = a.G0;
-    const float *base = a.nodes + (long)NV_BASE * 6 * G0;
-    const float *delta = a.nodes + (long)NV_DELTA * 6 * G0;
-    float *tp = a.nodes + (long)NV_TPREV * 6 * G0;
+    float b[6], dl[6];
+    ld6(nvec(a, NV_BASE), n, b);
+    ld6(nvec(a, NV_DELTA), n, dl);
 #pragma unroll
-    for (int q = 0; q < 6; ++q) tp[q * G0 + n] = base[q * G0 + n] + delta[q * G0 + n];
+    for (int q = 0; q < 6; ++q) b[q] = b[q] + dl[q];
+    st6(nvec(a, NV_TPREV), n, b);
 }
 
 // ---- output: depth and 3D flow at level 0 -----------------------------------
