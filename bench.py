@@ -63,6 +63,15 @@ WORKLOADS = {
 # z, p_old, p (write), q (write), base, delta (6 floats each) and w_i.
 APPLY_BYTES_PER_PIXEL = 21 * 4
 APPLY_BYTES_PER_NODE = (6 * 6 + 1) * 4
+# node-block products: the five stored 21-float blocks per node instead of
+# the per-pixel records
+APPLY_NB_BYTES_PER_NODE = 5 * 21 * 4 + APPLY_BYTES_PER_NODE
+
+
+def apply_bytes(N0, G0, apply_mode):
+    if apply_mode == 1:
+        return APPLY_NB_BYTES_PER_NODE * G0
+    return APPLY_BYTES_PER_PIXEL * N0 + APPLY_BYTES_PER_NODE * G0
 
 
 def _gen_frame(args):
@@ -101,11 +110,12 @@ def source_hash():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, apply_mode=0):
     """HBM bytes per launch of the level-0 H-product from the committed
-    counter summary (profiles/pcg_apply_<workload>_traffic.txt), or None if
-    it is missing or was taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", f"pcg_apply_{workload}_traffic.txt")
+    counter summary (profiles/pcg_apply_<workload>[_nb]_traffic.txt), or
+    None if it is missing or was taken on a different kernel source."""
+    tag = "_nb" if apply_mode == 1 else ""
+    path = os.path.join(ROOT, "profiles", f"pcg_apply_{workload}{tag}_traffic.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -180,7 +190,9 @@ def cpu_baseline(imgs, calib, params, W, H):
     (sum of level pixel counts / level-0 pixel count)."""
     from threadpoolctl import threadpool_limits
     import oracle.halfway as O
-    p = O.Params(**params)
+    import dataclasses
+    names = {f.name for f in dataclasses.fields(O.Params)}
+    p = O.Params(**{k: v for k, v in params.items() if k in names})
     with threadpool_limits(limits=1):
         pyr = O.pyramid(imgs.astype(np.float64), p.levels)
         grid = O.Grid(W, H, p.grid_stride)
@@ -305,6 +317,9 @@ def main():
                     help="skip the learned-init vs plain comparison")
     ap.add_argument("--exec-mode", type=int, default=0,
                     help="0 = captured HIP graph, 1 = direct launches")
+    ap.add_argument("--apply-mode", type=int, default=0, choices=(0, 1),
+                    help="0: matrix-free products from the pixel records, "
+                         "1: per-node blocks")
     ap.add_argument("--tile-mode", type=int, default=1,
                     help="PCG tile shapes: 0 = default, 1 = autotuned (timed on the "
                          "warm-up solve), 2 / 3 = the alternative shapes")
@@ -361,6 +376,7 @@ def main():
     W, H = w["width"], w["height"]
     params = dict(w["params"])
     img = torch.from_numpy(imgs).cuda().contiguous()
+    params["apply_mode"] = args.apply_mode
     solver = SceneFlowSolver(W, H, exec_mode=args.exec_mode, tile_mode=args.tile_mode,
                              **params)
     stream = solver.stream
@@ -389,7 +405,7 @@ def main():
     avg_ms = sf.sf_time_kernel(solver.ctx, sf.SF_KERNEL_APPLY, 0, reps)
     sizes = level_sizes(W, H, params["levels"], params["grid_stride"])
     N0, G0 = sizes[0][2], sizes[0][3]
-    bytes_apply = APPLY_BYTES_PER_PIXEL * N0 + APPLY_BYTES_PER_NODE * G0
+    bytes_apply = apply_bytes(N0, G0, args.apply_mode)
     achieved = bytes_apply / (avg_ms * 1e-3) / 1e9
     per_level = [round(sf.sf_time_kernel(solver.ctx, sf.SF_KERNEL_APPLY, l, reps) * 1e3, 2)
                  for l in range(params["levels"])]
@@ -412,10 +428,12 @@ def main():
                    "tile_mode": args.tile_mode, **params},
         "frames_per_s": round(1e3 / ms, 2),
         "wall_ms_per_frame": round(wall * 1e3 / args.steps, 4),
-        "roofline": {"bound": "hbm", "kernel": "k_apply (H p) at level 0",
+        "roofline": {"bound": "hbm",
+                     "kernel": ("k_pcg node-block H p" if args.apply_mode == 1
+                                else "k_pcg matrix-free H p") + " at level 0",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": (measured_traffic(args.workload)
+                     "traffic": (measured_traffic(args.workload, args.apply_mode)
                                  if args.exec_mode == 0 else None),
                      "bytes_per_launch": bytes_apply,
                      "avg_us_per_launch": round(bytes_apply / achieved / 1e3, 2),
@@ -482,7 +500,7 @@ def run_batch(args, workload):
     import torch
     from paper_1610_07159_amd import SceneFlowSolver, sf
     w = WORKLOADS["batch"]
-    params = dict(w["params"])
+    params = dict(w["params"], apply_mode=args.apply_mode)
     res, frames = workload
     dev = [(torch.from_numpy(i).cuda().contiguous(), c) for i, c in frames]
     W0, H0 = res[0]
@@ -516,7 +534,7 @@ def run_batch(args, workload):
     for W, H in res:
         L = sf.sf_batch_levels(W, H, params["levels"])
         N0, G0 = level_sizes(W, H, L, params["grid_stride"])[0][2:]
-        bytes_apply += APPLY_BYTES_PER_PIXEL * N0 + APPLY_BYTES_PER_NODE * G0
+        bytes_apply += apply_bytes(N0, G0, args.apply_mode)
     achieved = bytes_apply / (avg_ms * 1e-3) / 1e9
     ms_frame = total_ms / (args.steps * n)
     sizes = {f"{W}x{H}": res.count((W, H)) for W, H in sorted(set(res))}
@@ -540,10 +558,13 @@ def run_batch(args, workload):
         "batch_ms_p50": round(float(np.percentile(per_batch, 50)), 3),
         "batch_ms_p99": round(float(np.percentile(per_batch, 99)), 3),
         "wall_ms_per_batch": round(wall * 1e3 / args.steps, 3),
-        "roofline": {"bound": "hbm", "kernel": "k_apply (H p) at level 0, all frames",
+        "roofline": {"bound": "hbm",
+                     "kernel": ("k_pcg node-block H p" if args.apply_mode == 1
+                                else "k_pcg matrix-free H p") + " at level 0, all frames",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("batch"), "bytes_per_launch": bytes_apply,
+                     "traffic": measured_traffic("batch", args.apply_mode),
+                     "bytes_per_launch": bytes_apply,
                      "avg_us_per_launch": round(avg_ms * 1e3, 2)},
     }
     solver.close()

@@ -70,7 +70,15 @@ typedef struct {
  *                  the process and, if the environment variable
  *                  SF_TUNE_CACHE names a file, in that file); 2, 3 = the
  *                  alternative shapes (strides 2, 4, 8; others use the
- *                  default)
+ *                  default); ignored with apply_mode 1
+ *  apply_mode      how the PCG kernels form H u (Sec. 5.2): 0 = matrix-free
+ *                  from the per-pixel Gauss-Newton records (the transpose
+ *                  of the bilinear interpolation, Eq. (7), applied on every
+ *                  product); 1 = from per-node 6x6 blocks
+ *                  H_nm = sum_x a_n(x) a_m(x) J^T Omega J (x) of each node
+ *                  and its eight neighbours, assembled once per
+ *                  Gauss-Newton step (the paper's precomputed per-node
+ *                  blocks; 120 floats of extra workspace per node)
  *  w_*, m_*        weights of the energy terms; m_s, m_m, m_d must be > 0
  *  eps             pseudo-Huber parameter of Eq. (12)
  *  eps_p           colour-pruning threshold of Sec. 4.1
@@ -80,7 +88,7 @@ typedef struct {
  *                  eigenvalue analysis; this map is the library's reading). */
 typedef struct {
     int levels, grid_stride, gn_iters, pcg_iters, max_backtracks, init_mode;
-    int exec_mode, tile_mode;
+    int exec_mode, tile_mode, apply_mode;
     float w_reg, w_photo, w_grad, w_epi, w_smooth, w_mag;
     float w_s, w_m, w_d, m_s, m_m, m_d;
     float eps, eps_p, st_gamma, st_tau;
@@ -316,13 +324,15 @@ sf_status sf_debug_run(sf_ctx *ctx, int stage, int level);
  *  SF_KERNEL_LINEARIZE  per-pixel records and energy
  *  SF_KERNEL_UPDATE     the last PCG iteration's vector update
  *  SF_KERNEL_RHS        right-hand side and diag(H) (node tiles)
+ *  SF_KERNEL_BLOCKS     per-node block assembly (apply_mode 1 only)
  * The PCG kernels run forced active with fixed step lengths. 
  * Errors: SF_ERR_STATE before the first solve, SF_ERR_INVALID_ARG. */
 enum {
     SF_KERNEL_APPLY = 0,
     SF_KERNEL_LINEARIZE = 1,
     SF_KERNEL_UPDATE = 2,
-    SF_KERNEL_RHS = 3
+    SF_KERNEL_RHS = 3,
+    SF_KERNEL_BLOCKS = 4
 };
 sf_status sf_time_kernel(sf_ctx *ctx, int kernel, int level, int reps,
                          float *avg_ms);

@@ -29,6 +29,7 @@ struct FrameBuf {
     unsigned char *cmask = nullptr;
     float *wnode = nullptr, *reg = nullptr, *nodes = nullptr;
     float *gram = nullptr, *grad = nullptr;
+    float *blk = nullptr;  // node-block apply mode only
     float *partials = nullptr;
     DevConst *cst = nullptr;
     DevScalars *sc = nullptr;
@@ -119,6 +120,7 @@ sf_status check_params(const sf_params *p) {
     if (p->init_mode == 1 && p->levels <= SF_CNN_INPUT_LEVEL) return SF_ERR_INVALID_ARG;
     if (p->exec_mode != 0 && p->exec_mode != 1) return SF_ERR_INVALID_ARG;
     if (p->tile_mode < 0 || p->tile_mode > 3) return SF_ERR_INVALID_ARG;
+    if (p->apply_mode != 0 && p->apply_mode != 1) return SF_ERR_INVALID_ARG;
     const float w[] = {p->w_reg, p->w_photo, p->w_grad, p->w_epi, p->w_smooth,
                        p->w_mag, p->w_s, p->w_m, p->w_d, p->st_gamma};
     for (float v : w)
@@ -134,7 +136,7 @@ bool same_schedule(const sf_params &a, const sf_params &b) {
     return a.levels == b.levels && a.grid_stride == b.grid_stride &&
            a.gn_iters == b.gn_iters && a.pcg_iters == b.pcg_iters &&
            a.max_backtracks == b.max_backtracks && a.init_mode == b.init_mode &&
-           a.tile_mode == b.tile_mode;
+           a.tile_mode == b.tile_mode && a.apply_mode == b.apply_mode;
 }
 
 sf_status check_calib(const sf_calib *cal) {
@@ -238,9 +240,13 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
             tile_max_pixels(t, st) > tile_ppt(st, v) * tile_threads(t))
             return SF_ERR_INVALID_ARG;
     }
+    const bool nb = prm.apply_mode == 1;
+    if (nb && blk_tile_lds_bytes(st) > 64 * 1024) return SF_ERR_INVALID_ARG;
     const int forced = prm.tile_mode >= 2 ? prm.tile_mode - 1 : 0;
-    for (int l = 0; l < SF_MAX_LEVELS; ++l) P.ptile[l] = pick_pcg_tile(st, forced);
-    P.tuned = prm.tile_mode != 1;
+    for (int l = 0; l < SF_MAX_LEVELS; ++l)
+        P.ptile[l] = nb ? pick_nb_tile() : pick_pcg_tile(st, forced);
+    // the node-block PCG kernel has a single shape
+    P.tuned = nb || prm.tile_mode != 1;
     P.fr.resize(P.nf);
     P.Lmax = 0;
     // sizes, then one allocation carved in 256-byte aligned pieces
@@ -259,12 +265,14 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
                 mb = mb > nt ? mb : nt;
             }
             mb = mb > node_tile_blocks(d, P.tile) ? mb : node_tile_blocks(d, P.tile);
+            const int nbt = node_tile_blocks(d, pick_nb_tile());
+            mb = mb > nbt ? mb : nbt;
             const int gb = (d.G + SF_BLOCK - 1) / SF_BLOCK;
             mb = mb > gb ? mb : gb;
         }
         F.max_blocks = mb;
         F.nlog = F.L * prm.gn_iters;
-        const size_t sz[10] = {sizeof(float4) * (size_t)F.tex_len,
+        const size_t sz[11] = {sizeof(float4) * (size_t)F.tex_len,
                                (size_t)F.N0,
                                sizeof(float) * (size_t)F.G0,
                                sizeof(float) * 16 * (size_t)F.G0,
@@ -273,8 +281,9 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
                                sizeof(float) * PS_COUNT * (size_t)mb,
                                sizeof(DevScalars),
                                sizeof(DevLog) * (size_t)F.nlog,
-                               sizeof(float) * SF_GRAD_STRIDE * (size_t)F.N0};
-        for (int k = 0; k < 10; ++k) {
+                               sizeof(float) * SF_GRAD_STRIDE * (size_t)F.N0,
+                               nb ? sizeof(float) * SF_BLK_STRIDE * (size_t)F.G0 : 0};
+        for (int k = 0; k < 11; ++k) {
             o[f * 11 + k] = off;
             off += align_up(sz[k]);
         }
@@ -319,6 +328,7 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
         F.nodes = (float *)(P.pool + o[f * 11 + 4]);
         F.gram = (float *)(P.pool + o[f * 11 + 5]);
         F.grad = (float *)(P.pool + o[f * 11 + 9]);
+        F.blk = nb ? (float *)(P.pool + o[f * 11 + 10]) : nullptr;
         F.partials = (float *)(P.pool + o[f * 11 + 6]);
         F.sc = (DevScalars *)(P.pool + o[f * 11 + 7]);
         F.log = (DevLog *)(P.pool + o[f * 11 + 8]);
@@ -356,6 +366,7 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
             a.cmask = F.cmask;
             a.wnode = F.wnode;
             a.reg = F.reg;
+            a.blk = F.blk;
             a.partials = F.partials;
             a.max_blocks = F.max_blocks;
             a.cst = F.cst;
@@ -461,6 +472,7 @@ void enqueue_linearize(const Plan &P, hipStream_t st, int l) {
     const Launch L = slot(P, l);
     launch_linearize(st, L);
     launch_rhs(st, L, P.tile);
+    if (P.prm.apply_mode == 1) launch_blocks(st, L);
 }
 
 void enqueue_pcg(const Plan &P, hipStream_t st, int l, int gn) {
@@ -706,9 +718,11 @@ sf_status time_kernel(hipStream_t st, const Plan &P, int kernel, int level, int 
             case SF_KERNEL_LINEARIZE: launch_linearize(st, L); break;
             case SF_KERNEL_UPDATE: launch_pcg_last(st, L, P.ptile[level], 2 + (i & 1), -1, 1); break;
             case SF_KERNEL_RHS: launch_rhs(st, L, P.tile); break;
+            case SF_KERNEL_BLOCKS: launch_blocks(st, L); break;
         }
     };
-    if (kernel < SF_KERNEL_APPLY || kernel > SF_KERNEL_RHS) {
+    if (kernel < SF_KERNEL_APPLY || kernel > SF_KERNEL_BLOCKS ||
+        (kernel == SF_KERNEL_BLOCKS && P.prm.apply_mode != 1)) {
         s = SF_ERR_INVALID_ARG;
     } else {
         // the PCG kernels are forced active with fixed step lengths so that

@@ -25,6 +25,12 @@
 #define SF_GRAM_STRIDE 24
 #define SF_GRAD_STRIDE 8
 #define SF_GRAD_IBAR 6
+// Per-node system-matrix blocks (the node-block apply mode): for each node
+// n = (i, j) the symmetric 6x6 blocks H_nm = sum_x a_n(x) a_m(x) G(x) of its
+// pairs with m = n, (i+1, j), (i, j+1), (i+1, j+1), (i-1, j+1), in that
+// order, each in the gram record layout (24 floats).
+#define SF_BLK_TYPES 5
+#define SF_BLK_STRIDE (SF_BLK_TYPES * SF_GRAM_STRIDE)
 // the test interface's plane layout: 6 gradient planes, then the 21
 // upper-triangular entries of the block row by row
 #define SF_REC_PLANES 27
@@ -157,6 +163,7 @@ struct LevelArgs {
     unsigned char *cmask;  // V(x) W(x)
     float *wnode;          // smoothness weights
     float *reg;            // per-node regulariser record, 16 floats per node
+    float *blk;            // per-node blocks (SF_BLK_STRIDE), node-block mode
     float *partials;       // per-workgroup partial sums
     int max_blocks;        // stride of the partial-sum planes
     const DevConst *cst;
@@ -194,6 +201,9 @@ void launch_cnn_candidate(hipStream_t st, const Launch &L);
 void launch_linearize(hipStream_t st, const Launch &L);
 void launch_trial(hipStream_t st, const Launch &L, int trial, float tau);
 void launch_rhs(hipStream_t st, const Launch &L, const TileCfg &t);
+// per-node blocks from the pixel records (node-block apply mode, once per
+// Gauss-Newton step after launch_linearize)
+void launch_blocks(hipStream_t st, const Launch &L);
 void launch_pcg_first(hipStream_t st, const Launch &L, const TileCfg &t);
 void launch_pcg_iter(hipStream_t st, const Launch &L, const TileCfg &t,
                      int iter, int gn, int force);
@@ -208,6 +218,12 @@ TileCfg pick_tile(int s);
 // PCG tile shapes: tile_variants(s) shapes per stride, variant 0 = pick_tile
 int tile_variants(int s);
 TileCfg pick_pcg_tile(int s, int v);
+// PCG tile of the node-block apply mode (any stride; v = SF_TILE_NB)
+#define SF_TILE_NB 3
+TileCfg pick_nb_tile();
+// block-assembly tile per stride and its LDS bytes
+TileCfg pick_blk_tile(int s);
+size_t blk_tile_lds_bytes(int s);
 int tile_threads(int s);
 int tile_threads(const TileCfg &t);
 int tile_max_pixels(const TileCfg &t, int s);

@@ -38,6 +38,9 @@ template <> struct TileShape<4, 1> { static constexpr int TX = 8, TY = 8, TPN = 
 template <> struct TileShape<4, 2> { static constexpr int TX = 4, TY = 4, TPN = 16; };
 template <> struct TileShape<8, 1> { static constexpr int TX = 2, TY = 4, TPN = 64; };
 template <> struct TileShape<8, 2> { static constexpr int TX = 2, TY = 2, TPN = 64; };
+// S = 0: the node-block apply mode (any stride): 8 x 8 nodes, four threads
+// per node share its nine block products.
+template <> struct TileShape<0, 0> { static constexpr int TX = 8, TY = 8, TPN = 4; };
 
 template <int S, int V = 0>
 struct TileTraits {
@@ -46,7 +49,7 @@ struct TileTraits {
     static constexpr int TPN = TileShape<S, V>::TPN;
     static constexpr int NT = TX * TY * TPN;
     static constexpr int MAXPX = ((TX + 1) * S + (S & 1)) * ((TY + 1) * S + (S & 1));
-    static constexpr int PPT = (MAXPX + NT - 1) / NT;
+    static constexpr int PPT = S == 0 ? 1 : (MAXPX + NT - 1) / NT;
     static_assert(TPN >= 2 * S && TPN <= 64, "one support row per thread, one wave per node");
     static_assert(NT == 256 || NT == 512, "block size");
     static_assert(NT <= 512 || PPT <= 2, "registers");
@@ -993,6 +996,115 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(KArg<B> ka, TileCfg t
     }
 }
 
+// ---- per-node system-matrix blocks (node-block apply mode) -----------------
+//
+// The data term's Gauss-Newton matrix couples nodes that share a pixel's
+// bilinear bracket (Eq. (7)): H_nm = sum_x a_n(x) a_m(x) G(x), symmetric
+// since a_n a_m is a scalar and G(x) is symmetric, and H_mn = H_nm.  Node n
+// stores the blocks of its pairs with itself and with the nodes E, S, SE
+// and SW of it; the other four neighbours' blocks are the stored blocks of
+// those neighbours.  The products a_n a_m are separable, so the thread of
+// (node, support row r) sums the row's columns with the column weights
+// bx_i bx_{i+di} for di = 0, +1, -1 and scales the three sums by the row
+// weights by_j^2 (same row of nodes) and by_j by_{j+1} (next row).
+
+// Assembly tile per stride: tx x ty nodes, tpn >= 2S threads per node, the
+// pixel region's 21-float records under 64 KB of LDS.
+template <int S> struct BlkShape;
+template <> struct BlkShape<1> { static constexpr int TX = 16, TY = 8, TPN = 2; };
+template <> struct BlkShape<2> { static constexpr int TX = 16, TY = 4, TPN = 4; };
+template <> struct BlkShape<3> { static constexpr int TX = 8, TY = 4, TPN = 8; };
+template <> struct BlkShape<4> { static constexpr int TX = 8, TY = 2, TPN = 8; };
+template <> struct BlkShape<5> { static constexpr int TX = 4, TY = 2, TPN = 16; };
+template <> struct BlkShape<6> { static constexpr int TX = 4, TY = 2, TPN = 16; };
+template <> struct BlkShape<7> { static constexpr int TX = 2, TY = 2, TPN = 16; };
+template <> struct BlkShape<8> { static constexpr int TX = 2, TY = 1, TPN = 32; };
+template <int S>
+struct BlkTraits {
+    static constexpr int NT = BlkShape<S>::TX * BlkShape<S>::TY * BlkShape<S>::TPN;
+    static_assert(BlkShape<S>::TPN >= 2 * S && BlkShape<S>::TPN <= 64, "one support row per thread");
+    static_assert(NT % 64 == 0 && NT <= 256, "whole wavefronts");
+};
+
+// partner offset of block type k (self, E, S, SE, SW)
+__host__ __device__ inline void blk_offset(int k, int &di, int &dj) {
+    di = (k == 1 || k == 3) ? 1 : (k == 4 ? -1 : 0);
+    dj = k >= 2 ? 1 : 0;
+}
+
+template <bool B, int S>
+__global__ __launch_bounds__(BlkTraits<S>::NT) void k_blocks(KArg<B> ka, TileCfg t) {
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    SF_BIND(ka);
+    const LevelDims &d = a.d;
+    const TileGeom g = tile_geom(a, t, bid);
+    const TileLds L = tile_lds(lds, t, S, 21);
+    tile_brackets(a, g, L);
+    pixels_to_lds<21>(g, L, [&](int x, int y, int, int, float (&v)[21]) {
+        const float4 *gp = reinterpret_cast<const float4 *>(a.gram + ((long)y * d.W + x) * SF_GRAM_STRIDE);
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            const float4 t4 = gp[m];
+            v[4 * m] = t4.x; v[4 * m + 1] = t4.y; v[4 * m + 2] = t4.z; v[4 * m + 3] = t4.w;
+        }
+        v[20] = gp[5].x;
+    });
+    __syncthreads();
+    const int nl = threadIdx.x / t.tpn, sub = threadIdx.x % t.tpn;
+    const bool valid = nl < g.txa * g.tya;
+    const int i = g.i0 + nl % max(g.txa, 1), j = g.j0 + nl / max(g.txa, 1);
+    float c0[21], cp[21], cm[21];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) c0[k] = cp[k] = cm[k] = 0.f;
+    float r_same = 0.f, r_next = 0.f;
+    if (valid) {
+        const int xa = max(sup_lo(i, S), g.X0) - g.X0;
+        const int xb = min(sup_hi(i, S, d.Gx, d.W), g.X1) - g.X0;
+        const int ya = max(sup_lo(j, S), g.Y0) - g.Y0;
+        const int yb = min(sup_hi(j, S, d.Gy, d.H), g.Y1) - g.Y0;
+        const int ry = ya + sub;
+        if (ry <= yb) {
+            const float4 byr = L.by[ry];
+            const float vj = bweight(byr, j, d.Gy);
+            const float vn = j + 1 < d.Gy ? bweight(byr, j + 1, d.Gy) : 0.f;
+            r_same = vj * vj;
+            r_next = vj * vn;
+            const float *row = L.vals + (size_t)ry * L.pitch;
+#pragma unroll
+            for (int c = 0; c < 2 * S; ++c) {
+                const int rx = xa + c;
+                if (rx <= xb) {
+                    const float4 b = L.bx[rx];
+                    const float wi = bweight(b, i, d.Gx);
+                    const float wp = i + 1 < d.Gx ? bweight(b, i + 1, d.Gx) : 0.f;
+                    const float wm = i >= 1 ? bweight(b, i - 1, d.Gx) : 0.f;
+                    const float a0 = wi * wi, ap = wi * wp, am = wi * wm;
+                    float G[21];
+                    rec_load<21>(row + (size_t)rx * rec_pad(21), G);
+#pragma unroll
+                    for (int k = 0; k < 21; ++k) {
+                        c0[k] += a0 * G[k];
+                        cp[k] += ap * G[k];
+                        cm[k] += am * G[k];
+                    }
+                }
+            }
+        }
+    }
+    float *dst = a.blk + ((long)j * d.Gx + i) * SF_BLK_STRIDE;
+#pragma unroll
+    for (int kb = 0; kb < SF_BLK_TYPES; ++kb) {
+        const float rw = kb < 2 ? r_same : r_next;
+        float o[21];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) {
+            const float src = (kb == 0 || kb == 2) ? c0[k] : ((kb == 4) ? cm[k] : cp[k]);
+            o[k] = group_sum<float>(rw * src, t.tpn);
+        }
+        if (valid && sub == kb % t.tpn) rec_store<21>(dst + kb * SF_GRAM_STRIDE, o);
+    }
+}
+
 // ---- preconditioned CG in single-reduction form --------------------------
 //
 // Iteration k (x_0 = 0, r_0 = b, u_0 = M^-1 r_0, w_0 = H u_0, M = diag H):
@@ -1078,6 +1190,18 @@ __device__ void carry_partials(const LevelArgs &a, int bid, int i) {
     }
 }
 
+// Block products of a node in the node-block mode, split over its four
+// threads: task q of thread `sub` is block type k (-1: none); with `own` it
+// is the node's block of type k times u at the partner n + off(k), else the
+// block of type k stored by n - off(k) (whose partner is n) times u there.
+// Together: H_nn u_n + sum over the eight neighbours m of H_nm u_m.
+__device__ __forceinline__ void nb_task(int sub, int q, int &k, bool &own) {
+    if (q == 0) k = sub == 0 ? 0 : (sub == 2 ? 4 : 2);
+    else if (q == 1) k = (sub & 1) ? 3 : 1;
+    else k = sub == 3 ? 4 : -1;
+    own = sub < 2 || (sub == 2 && q == 0);
+}
+
 // Every load of an iteration that does not depend on its scalars is issued
 // before the partial sums are reduced, and constants are read once, so the
 // workgroup waits for memory about once.
@@ -1121,27 +1245,54 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
         load_pcg_partials(a, i, nb_prev, pacc);
         if (tid == 0) h = a.sc->hist[i - 1];
     }
-    // Gram blocks of this thread's region pixels
-    const int npx = g.RX * g.RY;
+    // owned node of this thread's node group
+    const int HX = t.tx + 2;
+    const int nl = tid / t.tpn, sub = tid % t.tpn;
+    const bool mine = sub == 0 && nl < g.txa * g.tya;
+    const int ti = nl % max(g.txa, 1), tj = nl / max(g.txa, 1);
+    const int i_n = g.i0 + ti, j_n = g.j0 + tj;
+    const long n_own = (long)j_n * d.Gx + i_n;
+    // S > 0: Gram blocks of this thread's region pixels; S = 0: the node
+    // blocks of this thread's share of its node's nine block products, and
+    // the halo records of the u they multiply (-1: no such neighbour)
+    const int npx = S > 0 ? g.RX * g.RY : 0;
     float Gm[PPT][SF_GRAM_STRIDE];
+    float Bk[3][21];
+    int bu[3] = {-1, -1, -1};
+    if constexpr (S > 0) {
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int u = tid + k * NT_TILE;
-        if (u < npx) {
-            const long pix = (long)(g.Y0 + u / g.RX) * d.W + g.X0 + u % g.RX;
-            const float4 *gp = reinterpret_cast<const float4 *>(a.gram + pix * SF_GRAM_STRIDE);
+        for (int k = 0; k < PPT; ++k) {
+            const int u = tid + k * NT_TILE;
+            if (u < npx) {
+                const long pix = (long)(g.Y0 + u / g.RX) * d.W + g.X0 + u % g.RX;
+                const float4 *gp = reinterpret_cast<const float4 *>(a.gram + pix * SF_GRAM_STRIDE);
 #pragma unroll
-            for (int v = 0; v < 6; ++v) {
-                const float4 t4 = gp[v];
-                Gm[k][4 * v] = t4.x;
-                Gm[k][4 * v + 1] = t4.y;
-                Gm[k][4 * v + 2] = t4.z;
-                Gm[k][4 * v + 3] = t4.w;
+                for (int v = 0; v < 6; ++v) {
+                    const float4 t4 = gp[v];
+                    Gm[k][4 * v] = t4.x;
+                    Gm[k][4 * v + 1] = t4.y;
+                    Gm[k][4 * v + 2] = t4.z;
+                    Gm[k][4 * v + 3] = t4.w;
+                }
+            }
+        }
+    } else {
+        const bool valid = nl < g.txa * g.tya;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            int k, di, dj;
+            bool own;
+            nb_task(sub, q, k, own);
+            blk_offset(k, di, dj);
+            const int pi = own ? i_n + di : i_n - di, pj = own ? j_n + dj : j_n - dj;
+            if (valid && k >= 0 && pi >= 0 && pi < d.Gx && pj >= 0 && pj < d.Gy) {
+                bu[q] = (tj + 1 + pj - j_n) * HX + (ti + 1 + pi - i_n);
+                const long owner = own ? n_own : (long)pj * d.Gx + pi;
+                rec_load<21>(a.blk + owner * SF_BLK_STRIDE + k * SF_GRAM_STRIDE, Bk[q]);
             }
         }
     }
     // halo node of this thread: the vectors u_i is formed from
-    const int HX = t.tx + 2;
     const int hx0 = max(g.i0 - 1, 0), hx1 = min(g.i0 + g.txa, d.Gx - 1);
     const int hy0 = max(g.j0 - 1, 0), hy1 = min(g.j0 + g.tya, d.Gy - 1);
     const int hw = hx1 - hx0 + 1, hh = hy1 - hy0 + 1;
@@ -1166,12 +1317,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
             ld6(D, hn, hv3);
         }
     }
-    // owned node of this thread's node group: its regulariser record
-    const int nl = tid / t.tpn, sub = tid % t.tpn;
-    const bool mine = sub == 0 && nl < g.txa * g.tya;
-    const int ti = nl % max(g.txa, 1), tj = nl / max(g.txa, 1);
-    const int i_n = g.i0 + ti, j_n = g.j0 + tj;
-    const long n_own = (long)j_n * d.Gx + i_n;
+    // the owned node's regulariser record
     float rg[REG_PLANES];
     if (mine) {
 #pragma unroll
@@ -1203,7 +1349,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     if (!B) load_own();
 
     // ---- phase 1: scalars of iteration i-1 ---------------------------------
-    tile_brackets(a, g, L);
+    if constexpr (S > 0) tile_brackets(a, g, L);
     float alpha = 0.f, beta = 0.f;
     int act = 1;
     if (!FIRST) {
@@ -1243,6 +1389,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     __syncthreads();
 
     // ---- phase 3: per-pixel block times the interpolated u_i ---------------
+    if constexpr (S > 0) {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int u = tid + k * NT_TILE;
@@ -1274,11 +1421,31 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
         }
     }
     __syncthreads();
+    }
 
     // ---- phase 4: sums onto nodes, regularisers ----------------------------
     if (B) load_own();
     float acc[6];
-    lds_to_nodes<6, S>(a, t, g, L, 0u, acc);
+    if constexpr (S > 0) {
+        lds_to_nodes<6, S>(a, t, g, L, 0u, acc);
+    } else {
+        // the node's block products, summed over its threads in fixed order
+#pragma unroll
+        for (int r = 0; r < 6; ++r) acc[r] = 0.f;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (bu[q] >= 0) {
+                float un[6];
+                rec_load<6>(L.halo + (size_t)bu[q] * 8, un);
+#pragma unroll
+                for (int r = 0; r < 6; ++r)
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) acc[r] += Bk[q][gram_index(r, c)] * un[c];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 6; ++r) acc[r] = group_sum<float>(acc[r], TileTraits<S, V>::TPN);
+    }
     float prt[3] = {0.f, 0.f, 0.f};
     float w6[6], uv[6];
     if (mine) {
@@ -1813,6 +1980,31 @@ TileCfg pick_pcg_tile(int s, int v) {
     return v == 1 ? tile_of<8, 1>() : tile_of<8, 2>();
 }
 
+TileCfg pick_nb_tile() {
+    TileCfg t = tile_of<0>();
+    t.v = SF_TILE_NB;
+    return t;
+}
+
+template <int S>
+static TileCfg blk_tile_of() {
+    TileCfg t;
+    t.tx = BlkShape<S>::TX;
+    t.ty = BlkShape<S>::TY;
+    t.tpn = BlkShape<S>::TPN;
+    t.v = 0;
+    return t;
+}
+
+TileCfg pick_blk_tile(int s) {
+#define BTILE(S) return blk_tile_of<S>()
+    SF_STRIDE_SWITCH(s, BTILE)
+#undef BTILE
+    return blk_tile_of<8>();
+}
+
+size_t blk_tile_lds_bytes(int s) { return node_tile_lds_bytes(pick_blk_tile(s), s, 21); }
+
 int tile_threads(const TileCfg &t) { return t.tx * t.ty * t.tpn; }
 
 int tile_threads(int s) { return tile_threads(pick_tile(s)); }
@@ -1896,7 +2088,8 @@ void launch_rhs(hipStream_t st, const Launch &L, const TileCfg &t) {
 
 // The PCG kernels per (stride, variant): the tile in t says which.
 #define SF_PCG_SWITCH(s, v, CALL)                          \
-    if ((s) == 2 && (v) == 1) { CALL(2, 1); }              \
+    if ((v) == SF_TILE_NB) { CALL(0, 0); }                 \
+    else if ((s) == 2 && (v) == 1) { CALL(2, 1); }         \
     else if ((s) == 2 && (v) == 2) { CALL(2, 2); }         \
     else if ((s) == 4 && (v) == 1) { CALL(4, 1); }         \
     else if ((s) == 4 && (v) == 2) { CALL(4, 2); }         \
@@ -1934,6 +2127,17 @@ void launch_pcg_iter(hipStream_t st, const Launch &L, const TileCfg &t, int iter
        node_tile_lds_bytes(t, S, 6), t, iter, gn, force)
     SF_PCG_SWITCH(s, t.v, PCGI)
 #undef PCGI
+}
+
+void launch_blocks(hipStream_t st, const Launch &L) {
+    const int s = L.host[0].s;
+    const TileCfg t = pick_blk_tile(s);
+    auto nb = [t](const LevelArgs &a) { return node_tiles_of(a.d, t); };
+#define BLK(S)                                                                            \
+    go(st, L, nb, k_blocks<true, S>, k_blocks<false, S>, BlkTraits<S>::NT,                \
+       node_tile_lds_bytes(t, S, 21), t)
+    SF_STRIDE_SWITCH(s, BLK)
+#undef BLK
 }
 
 void launch_pcg_last(hipStream_t st, const Launch &L, const TileCfg &t, int iter, int gn,

@@ -26,7 +26,7 @@ SF_DBG_DX, SF_DBG_R, SF_DBG_Z, SF_DBG_Q, SF_DBG_DIAG = 5, 6, 7, 8, 9
 SF_DBG_REC, SF_DBG_P, SF_DBG_ENERGY = 10, 11, 12
 SF_STAGE_LEVEL_INIT, SF_STAGE_LINEARIZE, SF_STAGE_APPLY = 0, 1, 2
 SF_STAGE_PCG, SF_STAGE_GN, SF_STAGE_FINISH, SF_STAGE_MASKS = 3, 4, 5, 6
-SF_KERNEL_APPLY, SF_KERNEL_LINEARIZE, SF_KERNEL_UPDATE, SF_KERNEL_RHS = 0, 1, 2, 3
+SF_KERNEL_APPLY, SF_KERNEL_LINEARIZE, SF_KERNEL_UPDATE, SF_KERNEL_RHS, SF_KERNEL_BLOCKS = 0, 1, 2, 3, 4
 SF_CNN_PARAMS = 39910
 SF_TR_INPUT, SF_TR_ACT, SF_TR_OUT, SF_TR_DOUT, SF_TR_DPRE, SF_TR_GRAD = 0, 1, 2, 3, 4, 5
 
@@ -49,7 +49,8 @@ class sf_calib(ctypes.Structure):
 
 
 _PARAM_INTS = ("levels", "grid_stride", "gn_iters", "pcg_iters",
-               "max_backtracks", "init_mode", "exec_mode", "tile_mode")
+               "max_backtracks", "init_mode", "exec_mode", "tile_mode",
+               "apply_mode")
 _PARAM_FLOATS = ("w_reg", "w_photo", "w_grad", "w_epi", "w_smooth", "w_mag",
                  "w_s", "w_m", "w_d", "m_s", "m_m", "m_d", "eps", "eps_p",
                  "st_gamma", "st_tau")

@@ -44,12 +44,12 @@ def _batch(frames, exec_mode=0, repeat=1, **prm):
     return results, logs
 
 
-@pytest.mark.parametrize("stride", [4, 8])
-def test_batch_matches_single_frames_bitwise(stride):
+@pytest.mark.parametrize("stride,apply", [(4, 0), (8, 0), (4, 1), (8, 1)])
+def test_batch_matches_single_frames_bitwise(stride, apply):
     from paper_1610_07159_amd import sf
     sizes = [(160, 120), (96, 72), (128, 96), (100, 76), (200, 150)]
     frames = _frames(sizes)
-    prm = dict(PRM, grid_stride=stride)
+    prm = dict(PRM, grid_stride=stride, apply_mode=apply)
     (res, res2), logs = _batch(frames, exec_mode=0, repeat=2, **prm)
     for f, ((imgs, calib), (W, H)) in enumerate(zip(frames, sizes)):
         L = sf.sf_batch_levels(W, H, prm["levels"])

@@ -101,9 +101,13 @@ def _gram_upper(Gx):
     return Gx[:, iu[0], iu[1]].T  # (21, N)
 
 
-@pytest.mark.parametrize("level,stride", [(0, 4), (2, 4), (0, 8), (1, 2), (0, 3)])
-def test_linearize_apply_pcg_parity(level, stride):
-    g, imgs, calib, p = _stage_case(W=104, H=78, grid_stride=stride)
+@pytest.mark.parametrize("level,stride,apply", [
+    (0, 4, 0), (2, 4, 0), (0, 8, 0), (1, 2, 0), (0, 3, 0),
+    # node-block products: every assembly tile shape (strides 1..8)
+    (0, 4, 1), (2, 4, 1), (0, 8, 1), (1, 2, 1), (0, 3, 1), (0, 5, 1), (0, 6, 1),
+    (0, 7, 1), (2, 1, 1)])
+def test_linearize_apply_pcg_parity(level, stride, apply):
+    g, imgs, calib, p = _stage_case(W=104, H=78, grid_stride=stride, apply_mode=apply)
     try:
         g.run(g.sf.SF_STAGE_LEVEL_INIT, level)
         ls, _ = _oracle_level(imgs, calib, p, level)
@@ -195,17 +199,26 @@ def test_solve_tiny_parity():
     _solve_parity(imgs, calib, prm)
 
 
-@pytest.mark.parametrize("W,H,stride", [(100, 76, 4), (160, 120, 4), (96, 72, 2),
-                                        (144, 104, 8)])
-def test_solve_medium_parity(W, H, stride):
+@pytest.mark.parametrize("W,H,stride,apply", [(100, 76, 4, 0), (160, 120, 4, 0), (96, 72, 2, 0),
+                                              (144, 104, 8, 0), (100, 76, 4, 1),
+                                              (160, 120, 4, 1), (96, 72, 2, 1),
+                                              (144, 104, 8, 1), (90, 70, 3, 1)])
+def test_solve_medium_parity(W, H, stride, apply):
     imgs, calib = _frame(W, H, seed=7)
-    prm = dict(levels=3, grid_stride=stride, gn_iters=4, pcg_iters=10)
+    prm = dict(levels=3, grid_stride=stride, gn_iters=4, pcg_iters=10, apply_mode=apply)
     _solve_parity(imgs, calib, prm)
 
 
-def test_graph_replay_matches_eager_and_repeats():
+def test_solve_tiny_parity_node_blocks():
+    imgs, calib, _ = make_frame(tiny_plane_config(), 0)
+    prm = dict(levels=3, grid_stride=8, gn_iters=5, pcg_iters=10, apply_mode=1)
+    _solve_parity(imgs, calib, prm)
+
+
+@pytest.mark.parametrize("apply", [0, 1])
+def test_graph_replay_matches_eager_and_repeats(apply):
     imgs, calib = _frame(128, 96, seed=9)
-    prm = dict(levels=3, grid_stride=4, gn_iters=3, pcg_iters=8)
+    prm = dict(levels=3, grid_stride=4, gn_iters=3, pcg_iters=8, apply_mode=apply)
     outs = []
     for mode in (1, 0, 0):
         g = GpuCase(imgs, calib, exec_mode=mode, **prm)
