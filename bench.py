@@ -69,7 +69,7 @@ APPLY_NB_BYTES_PER_NODE = 5 * 21 * 4 + APPLY_BYTES_PER_NODE
 
 
 def apply_bytes(N0, G0, apply_mode):
-    if apply_mode == 1:
+    if apply_mode >= 1:
         return APPLY_NB_BYTES_PER_NODE * G0
     return APPLY_BYTES_PER_PIXEL * N0 + APPLY_BYTES_PER_NODE * G0
 
@@ -114,7 +114,7 @@ def measured_traffic(workload, apply_mode=0):
     """HBM bytes per launch of the level-0 H-product from the committed
     counter summary (profiles/pcg_apply_<workload>[_nb]_traffic.txt), or
     None if it is missing or was taken on a different kernel source."""
-    tag = "_nb" if apply_mode == 1 else ""
+    tag = "_nb" if apply_mode >= 1 else ""
     path = os.path.join(ROOT, "profiles", f"pcg_apply_{workload}{tag}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -220,7 +220,7 @@ def _short_name(n):
     return n
 
 
-def trace_summary(path, focus=("k_pcg",)):
+def trace_summary(path, focus=("k_",)):
     """Summary of a rocprofv3 CSV: per kernel (calls, total/avg/min/max us)
     for a kernel trace, or per kernel the mean counter values per dispatch
     for a counter-collection file; both also per launch grid for the
@@ -317,9 +317,10 @@ def main():
                     help="skip the learned-init vs plain comparison")
     ap.add_argument("--exec-mode", type=int, default=0,
                     help="0 = captured HIP graph, 1 = direct launches")
-    ap.add_argument("--apply-mode", type=int, default=0, choices=(0, 1),
+    ap.add_argument("--apply-mode", type=int, default=2, choices=(0, 1, 2),
                     help="0: matrix-free products from the pixel records, "
-                         "1: per-node blocks")
+                         "1: per-node blocks, 2: per-node blocks and one-workgroup "
+                         "PCG at levels of at most 336 nodes")
     ap.add_argument("--tile-mode", type=int, default=1,
                     help="PCG tile shapes: 0 = default, 1 = autotuned (timed on the "
                          "warm-up solve), 2 / 3 = the alternative shapes")
@@ -429,7 +430,7 @@ def main():
         "frames_per_s": round(1e3 / ms, 2),
         "wall_ms_per_frame": round(wall * 1e3 / args.steps, 4),
         "roofline": {"bound": "hbm",
-                     "kernel": ("k_pcg node-block H p" if args.apply_mode == 1
+                     "kernel": ("k_pcg node-block H p" if args.apply_mode >= 1
                                 else "k_pcg matrix-free H p") + " at level 0",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -456,7 +457,7 @@ def run_learned(args, frames):
     from paper_1610_07159_amd import train_init as T
     w = WORKLOADS["learned"]
     W, H = w["width"], w["height"]
-    params = dict(w["params"])
+    params = dict(w["params"], apply_mode=args.apply_mode)
     weights = np.load(os.path.join(ROOT, "paper_1610_07159_amd", "weights", "init_640x480.npy"),
                       allow_pickle=False)
     plain, _, ms_plain = T.solve_flows(frames, W, H, timed=True, **params)
@@ -559,7 +560,7 @@ def run_batch(args, workload):
         "batch_ms_p99": round(float(np.percentile(per_batch, 99)), 3),
         "wall_ms_per_batch": round(wall * 1e3 / args.steps, 3),
         "roofline": {"bound": "hbm",
-                     "kernel": ("k_pcg node-block H p" if args.apply_mode == 1
+                     "kernel": ("k_pcg node-block H p" if args.apply_mode >= 1
                                 else "k_pcg matrix-free H p") + " at level 0, all frames",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -78,7 +78,9 @@ typedef struct {
  *                  H_nm = sum_x a_n(x) a_m(x) J^T Omega J (x) of each node
  *                  and its eight neighbours, assembled once per
  *                  Gauss-Newton step (the paper's precomputed per-node
- *                  blocks; 120 floats of extra workspace per node)
+ *                  blocks; 120 floats of extra workspace per node); 2 = as
+ *                  1, and levels with at most 336 nodes run all PCG
+ *                  iterations of a Gauss-Newton step in one workgroup
  *  w_*, m_*        weights of the energy terms; m_s, m_m, m_d must be > 0
  *  eps             pseudo-Huber parameter of Eq. (12)
  *  eps_p           colour-pruning threshold of Sec. 4.1
@@ -95,8 +97,10 @@ typedef struct {
 } sf_params;
 
 /* Fills *out with the paper's "Figures 5, 6, 8" parameter column
- * (Appendix A), w_smooth = w_mag = 1, eps = 0.001, eps_p = 0.2, and the
- * schedule levels 3, stride 8, 5 GN x 10 PCG, 4 backtracks. */
+ * (Appendix A), w_smooth = w_mag = 1, eps = 0.001, eps_p = 0.2, the
+ * schedule levels 3, stride 8, 5 GN x 10 PCG, 4 backtracks, and the
+ * node-block products with one-workgroup PCG at small levels
+ * (apply_mode 2). */
 sf_status sf_params_default(sf_params *out);
 
 /* Creates a context for width x height frames on the current HIP device,
@@ -323,8 +327,10 @@ sf_status sf_debug_run(sf_ctx *ctx, int stage, int level);
  *                       (matrix-free, node tiles)
  *  SF_KERNEL_LINEARIZE  per-pixel records and energy
  *  SF_KERNEL_UPDATE     the last PCG iteration's vector update
- *  SF_KERNEL_RHS        right-hand side and diag(H) (node tiles)
- *  SF_KERNEL_BLOCKS     per-node block assembly (apply_mode 1 only)
+ *  SF_KERNEL_RHS        right-hand side and diag(H) (node tiles; with
+ *                       apply_mode >= 1 together with the per-node blocks)
+ *  SF_KERNEL_BLOCKS     right-hand side and per-node blocks (apply_mode >= 1
+ *                       only; the same kernel as SF_KERNEL_RHS there)
  * The PCG kernels run forced active with fixed step lengths. 
  * Errors: SF_ERR_STATE before the first solve, SF_ERR_INVALID_ARG. */
 enum {

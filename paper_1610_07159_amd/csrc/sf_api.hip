@@ -120,7 +120,7 @@ sf_status check_params(const sf_params *p) {
     if (p->init_mode == 1 && p->levels <= SF_CNN_INPUT_LEVEL) return SF_ERR_INVALID_ARG;
     if (p->exec_mode != 0 && p->exec_mode != 1) return SF_ERR_INVALID_ARG;
     if (p->tile_mode < 0 || p->tile_mode > 3) return SF_ERR_INVALID_ARG;
-    if (p->apply_mode != 0 && p->apply_mode != 1) return SF_ERR_INVALID_ARG;
+    if (p->apply_mode < 0 || p->apply_mode > 2) return SF_ERR_INVALID_ARG;
     const float w[] = {p->w_reg, p->w_photo, p->w_grad, p->w_epi, p->w_smooth,
                        p->w_mag, p->w_s, p->w_m, p->w_d, p->st_gamma};
     for (float v : w)
@@ -240,7 +240,7 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
             tile_max_pixels(t, st) > tile_ppt(st, v) * tile_threads(t))
             return SF_ERR_INVALID_ARG;
     }
-    const bool nb = prm.apply_mode == 1;
+    const bool nb = prm.apply_mode >= 1;
     if (nb && blk_tile_lds_bytes(st) > 64 * 1024) return SF_ERR_INVALID_ARG;
     const int forced = prm.tile_mode >= 2 ? prm.tile_mode - 1 : 0;
     for (int l = 0; l < SF_MAX_LEVELS; ++l)
@@ -471,17 +471,24 @@ void enqueue_pyramid(const Plan &P, hipStream_t st, const float *const img[4]) {
 void enqueue_linearize(const Plan &P, hipStream_t st, int l) {
     const Launch L = slot(P, l);
     launch_linearize(st, L);
-    launch_rhs(st, L, P.tile);
-    if (P.prm.apply_mode == 1) launch_blocks(st, L);
+    if (P.prm.apply_mode >= 1)
+        launch_rhs_blocks(st, L);
+    else
+        launch_rhs(st, L, P.tile);
 }
 
+// With apply_mode 2 the frames of a slot with at most SF_SMALL_G nodes run
+// their PCG in one workgroup each and the others in the multi-kernel form,
+// so a frame takes the same path alone or in any batch.
 void enqueue_pcg(const Plan &P, hipStream_t st, int l, int gn) {
     const Launch L = slot(P, l);
     const int n = P.prm.pcg_iters;
+    const bool sm = P.prm.apply_mode == 2;
+    if (sm) launch_pcg_small(st, L, n, gn);
     const TileCfg &t = P.ptile[l];
-    launch_pcg_first(st, L, t);
-    for (int i = 1; i < n; ++i) launch_pcg_iter(st, L, t, i, gn, 0);
-    launch_pcg_last(st, L, t, n, gn, 0);
+    launch_pcg_first(st, L, t, sm);
+    for (int i = 1; i < n; ++i) launch_pcg_iter(st, L, t, i, gn, 0, sm);
+    launch_pcg_last(st, L, t, n, gn, 0, sm);
 }
 
 void enqueue_gn(const Plan &P, hipStream_t st, int l, int g, bool log) {
@@ -489,7 +496,9 @@ void enqueue_gn(const Plan &P, hipStream_t st, int l, int g, bool log) {
     enqueue_pcg(P, st, l, log ? g : -1);
     const Launch L = slot(P, l);
     const int T = P.prm.max_backtracks + 1;
-    for (int j = 0; j < T; ++j) launch_trial(st, L, j, ldexpf(1.f, -j));
+    // tau = 1 alone (usually accepted), then the shorter steps together
+    launch_trials(st, L, 0, 1);
+    if (T > 1) launch_trials(st, L, 1, T - 1);
     launch_accept(st, L, T, log ? g : -1, P.prm.pcg_iters);
 }
 
@@ -717,12 +726,17 @@ sf_status time_kernel(hipStream_t st, const Plan &P, int kernel, int level, int 
             case SF_KERNEL_APPLY: launch_pcg_iter(st, L, P.ptile[level], 2 + (i & 1), -1, 1); break;
             case SF_KERNEL_LINEARIZE: launch_linearize(st, L); break;
             case SF_KERNEL_UPDATE: launch_pcg_last(st, L, P.ptile[level], 2 + (i & 1), -1, 1); break;
-            case SF_KERNEL_RHS: launch_rhs(st, L, P.tile); break;
-            case SF_KERNEL_BLOCKS: launch_blocks(st, L); break;
+            case SF_KERNEL_RHS:
+                if (P.prm.apply_mode >= 1)
+                    launch_rhs_blocks(st, L);
+                else
+                    launch_rhs(st, L, P.tile);
+                break;
+            case SF_KERNEL_BLOCKS: launch_rhs_blocks(st, L); break;
         }
     };
     if (kernel < SF_KERNEL_APPLY || kernel > SF_KERNEL_BLOCKS ||
-        (kernel == SF_KERNEL_BLOCKS && P.prm.apply_mode != 1)) {
+        (kernel == SF_KERNEL_BLOCKS && P.prm.apply_mode < 1)) {
         s = SF_ERR_INVALID_ARG;
     } else {
         // the PCG kernels are forced active with fixed step lengths so that
@@ -763,6 +777,7 @@ sf_status sf_params_default(sf_params *out) {
     out->max_backtracks = 4;
     out->init_mode = 0;
     out->exec_mode = 0;
+    out->apply_mode = 2;
     out->w_reg = 0.5f;
     out->w_photo = 0.5f;
     out->w_grad = 5.0f;

@@ -72,7 +72,8 @@ enum {
     PS_PCG0 = 5,     // 3 planes: r.u, w.u, r.r (even iterations)
     PS_PCG1 = 8,     // 3 planes: odd iterations
     PS_MASK = 11,    // 1 plane: valid-pixel counts
-    PS_COUNT = 12
+    PS_TRIAL = 12,   // 5 planes per further trial of a multi-trial launch
+    PS_COUNT = PS_TRIAL + 5 * (SF_MAX_TRIALS - 1)
 };
 
 // Sizes of one pyramid level.
@@ -199,16 +200,26 @@ void launch_level_masks(hipStream_t st, const Launch &L);
 // (before launch_level_init)
 void launch_cnn_candidate(hipStream_t st, const Launch &L);
 void launch_linearize(hipStream_t st, const Launch &L);
-void launch_trial(hipStream_t st, const Launch &L, int trial, float tau);
+// energies of trials first .. first+count-1 (tau = 2^-trial) in one launch;
+// every workgroup returns at once if an earlier trial was accepted
+void launch_trials(hipStream_t st, const Launch &L, int first, int count);
 void launch_rhs(hipStream_t st, const Launch &L, const TileCfg &t);
-// per-node blocks from the pixel records (node-block apply mode, once per
-// Gauss-Newton step after launch_linearize)
-void launch_blocks(hipStream_t st, const Launch &L);
-void launch_pcg_first(hipStream_t st, const Launch &L, const TileCfg &t);
+// right-hand side, diag(H) and the per-node blocks from the pixel records
+// (node-block apply mode; replaces launch_rhs after launch_linearize)
+void launch_rhs_blocks(hipStream_t st, const Launch &L);
+// skip_small: frames with at most SF_SMALL_G nodes are left out (their PCG
+// runs in launch_pcg_small)
+void launch_pcg_first(hipStream_t st, const Launch &L, const TileCfg &t,
+                      bool skip_small = false);
 void launch_pcg_iter(hipStream_t st, const Launch &L, const TileCfg &t,
-                     int iter, int gn, int force);
+                     int iter, int gn, int force, bool skip_small = false);
 void launch_pcg_last(hipStream_t st, const Launch &L, const TileCfg &t,
-                     int iter, int gn, int force);
+                     int iter, int gn, int force, bool skip_small = false);
+// all pcg_iters iterations of a level in one workgroup per frame, for the
+// frames with at most SF_SMALL_G nodes (node-block mode; replaces first /
+// iter / last for them)
+#define SF_SMALL_G 336
+void launch_pcg_small(hipStream_t st, const Launch &L, int n_it, int gn);
 void launch_accept(hipStream_t st, const Launch &L, int n_trials, int gn,
                    int pcg_iters);
 void launch_finish_level(hipStream_t st, const Launch &L);

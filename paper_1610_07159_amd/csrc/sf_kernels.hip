@@ -633,8 +633,12 @@ __device__ void node_energy(const LevelArgs &a, int n, float tau, float (&part)[
 //        the right-hand-side kernel).
 //  !LIN: trial energy at delta + tau dx, skipped if an earlier trial of this
 //        step was accepted; the last workgroup to finish sums the partials.
+// Partial-sum planes of the t-th trial of a launch (the linearisation and
+// single trials use PS_E).
+__device__ __forceinline__ int trial_plane(int t) { return t == 0 ? PS_E : PS_TRIAL + 5 * (t - 1); }
+
 template <bool B, bool LIN>
-__global__ __launch_bounds__(SF_BLOCK) void k_energy(KArg<B> ka, int trial, float tau) {
+__global__ __launch_bounds__(SF_BLOCK) void k_energy(KArg<B> ka, int trial, int n_tr) {
     SF_BIND(ka);
     const LevelDims &d = a.d;
     const int n_pix = pixel_tiles(d);
@@ -644,62 +648,70 @@ __global__ __launch_bounds__(SF_BLOCK) void k_energy(KArg<B> ka, int trial, floa
             if (a.sc->e_trial[k][5] <= e0) return;  // uniform over the grid
     }
     __shared__ NodeStage S;
-    float part[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    if (bid < n_pix) {
-        const int tiles_x = (d.W + TILE_PX - 1) / TILE_PX;
-        const int x0 = (bid % tiles_x) * TILE_PX, y0 = (bid / tiles_x) * TILE_PX;
-        stage_nodes(a, x0, y0, LIN ? 0.f : tau, S);
-        __syncthreads();
-        const int x = x0 + (threadIdx.x & (TILE_PX - 1));
-        const int y = y0 + (threadIdx.x / TILE_PX);
-        if (x < d.W && y < d.H) {
-            float f[6];
-            pixel_flows(a, x, y, S, f);
-            const int pix = y * d.W + x;
-            const float c = a.cmask[pix] ? 1.f : 0.f;
-            PixelOut o;
-            pixel_terms<LIN>(a, x, y, f, c, o);
-            part[0] = o.e_photo;
-            part[1] = o.e_grad;
-            if (LIN) {
-                float g24[SF_GRAM_STRIDE];
+    for (int t = 0; t < n_tr; ++t) {
+        const float tau = LIN ? 0.f : ldexpf(1.f, -(trial + t));
+        float part[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        if (bid < n_pix) {
+            const int tiles_x = (d.W + TILE_PX - 1) / TILE_PX;
+            const int x0 = (bid % tiles_x) * TILE_PX, y0 = (bid / tiles_x) * TILE_PX;
+            stage_nodes(a, x0, y0, tau, S);
+            __syncthreads();
+            const int x = x0 + (threadIdx.x & (TILE_PX - 1));
+            const int y = y0 + (threadIdx.x / TILE_PX);
+            if (x < d.W && y < d.H) {
+                float f[6];
+                pixel_flows(a, x, y, S, f);
+                const int pix = y * d.W + x;
+                const float c = a.cmask[pix] ? 1.f : 0.f;
+                PixelOut o;
+                pixel_terms<LIN>(a, x, y, f, c, o);
+                part[0] = o.e_photo;
+                part[1] = o.e_grad;
+                if (LIN) {
+                    float g24[SF_GRAM_STRIDE];
 #pragma unroll
-                for (int i = 0; i < 6; ++i)
+                    for (int i = 0; i < 6; ++i)
 #pragma unroll
-                    for (int j = i; j < 6; ++j) g24[gram_index(i, j)] = o.gram[tri(i, j)];
-                g24[21] = g24[22] = g24[23] = 0.f;
-                float4 *gp = reinterpret_cast<float4 *>(a.gram + (long)pix * SF_GRAM_STRIDE);
+                        for (int j = i; j < 6; ++j) g24[gram_index(i, j)] = o.gram[tri(i, j)];
+                    g24[21] = g24[22] = g24[23] = 0.f;
+                    float4 *gp = reinterpret_cast<float4 *>(a.gram + (long)pix * SF_GRAM_STRIDE);
 #pragma unroll
-                for (int v = 0; v < 6; ++v)
-                    gp[v] = make_float4(g24[4 * v], g24[4 * v + 1], g24[4 * v + 2], g24[4 * v + 3]);
-                float4 *rp = reinterpret_cast<float4 *>(a.grad + (long)pix * SF_GRAD_STRIDE);
-                rp[0] = make_float4(o.grad[0], o.grad[1], o.grad[2], o.grad[3]);
-                rp[1] = make_float4(o.grad[4], o.grad[5], 0.f, 0.f);
+                    for (int v = 0; v < 6; ++v)
+                        gp[v] = make_float4(g24[4 * v], g24[4 * v + 1], g24[4 * v + 2], g24[4 * v + 3]);
+                    float4 *rp = reinterpret_cast<float4 *>(a.grad + (long)pix * SF_GRAD_STRIDE);
+                    rp[0] = make_float4(o.grad[0], o.grad[1], o.grad[2], o.grad[3]);
+                    rp[1] = make_float4(o.grad[4], o.grad[5], 0.f, 0.f);
+                }
             }
+        } else {
+            const int n = (bid - n_pix) * SF_BLOCK + threadIdx.x;
+            if (n < d.G) node_energy(a, n, tau, part);
         }
-    } else {
-        const int n = (bid - n_pix) * SF_BLOCK + threadIdx.x;
-        if (n < d.G) node_energy(a, n, LIN ? 0.f : tau, part);
-    }
-    float tot5[5];
-    block_sum<5>(part, tot5);
-    const int nb = nblk;
-    if (threadIdx.x == 0) {
+        // (the block sum's barriers also keep the next trial's staging
+        // from overwriting S while it is read)
+        float tot5[5];
+        block_sum<5>(part, tot5);
+        if (threadIdx.x == 0) {
+            const int base = trial_plane(t);
 #pragma unroll
-        for (int k = 0; k < 5; ++k) a.partials[(long)(PS_E + k) * a.max_blocks + bid] = tot5[k];
+            for (int k = 0; k < 5; ++k) a.partials[(long)(base + k) * a.max_blocks + bid] = tot5[k];
+        }
     }
     if (LIN) return;
+    const int nb = nblk;
     if (last_block(&a.sc->counter[0], (unsigned)nblk)) {
         const DevConst &C = *a.cst;
-        double s[5];
-        for (int k = 0; k < 5; ++k)
-            s[k] = block_sum_partials(a.partials + (long)(PS_E + k) * a.max_blocks, nb);
-        if (threadIdx.x == 0) {
-            double *dst = a.sc->e_trial[trial];
-            for (int k = 0; k < 5; ++k) dst[k] = s[k];
-            dst[5] = (double)C.w_photo * s[0] + (double)C.w_grad * s[1] +
-                     (double)C.w_reg * ((double)C.w_smooth * s[2] + (double)C.w_epi * s[3] +
-                                        (double)C.w_mag * s[4]);
+        for (int t = 0; t < n_tr; ++t) {
+            double s[5];
+            for (int k = 0; k < 5; ++k)
+                s[k] = block_sum_partials(a.partials + (long)(trial_plane(t) + k) * a.max_blocks, nb);
+            if (threadIdx.x == 0) {
+                double *dst = a.sc->e_trial[trial + t];
+                for (int k = 0; k < 5; ++k) dst[k] = s[k];
+                dst[5] = (double)C.w_photo * s[0] + (double)C.w_grad * s[1] +
+                         (double)C.w_reg * ((double)C.w_smooth * s[2] + (double)C.w_epi * s[3] +
+                                            (double)C.w_mag * s[4]);
+            }
         }
     }
 }
@@ -890,26 +902,18 @@ __device__ __forceinline__ void nb_offset(int k, int &di, int &dj) {
 
 // ---- right-hand side and diag(H) (node tiles) ----------------------------
 
-template <bool B, int S>
-__global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(KArg<B> ka, TileCfg t) {
-    extern __shared__ __attribute__((aligned(16))) float lds[];
-    SF_BIND(ka);
-    const LevelDims &d = a.d;
-    const DevConst &C = *a.cst;
-    const int n_lin_blocks = energy_blocks_of(d);
-    const TileGeom g = tile_geom(a, t, bid);
-    const TileLds L = tile_lds(lds, t, S, 12);
-    const int tid = threadIdx.x;
-    const int nl = tid / t.tpn, sub = tid % t.tpn;
-    const bool mine = sub == 0 && nl < g.txa * g.tya;
-    const int i = g.i0 + (nl % max(g.txa, 1)), j = g.j0 + nl / max(g.txa, 1);
-    const long n = (long)j * d.Gx + i;
-    const float *base = nvec(a, NV_BASE);
-    const float *delta = nvec(a, NV_DELTA);
-    // own node: totals, deltas, neighbour deltas and weights
+// A node's own part of the right-hand-side kernels: its deltas, totals and
+// neighbours (loaded before the pixel phase), then, from the data term's
+// gradient and diagonal summed over its support, the regularisers, r, u,
+// diag(H) and the regulariser record.
+struct RhsNode {
     float dl[6], tot[6], dn[4][6], wn[4], wi = 0.f;
     int has[4];
-    if (mine) {
+
+    __device__ void load(const LevelArgs &a, int i, int j, long n) {
+        const LevelDims &d = a.d;
+        const float *base = nvec(a, NV_BASE);
+        const float *delta = nvec(a, NV_DELTA);
         wi = a.wnode[n];
         float b[6];
         ld6(delta, n, dl);
@@ -926,38 +930,14 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(KArg<B> ka, TileCfg t
             ld6(delta, m, dn[k]);
         }
     }
-    if (bid == 0) {
-        // energy at the linearisation point (partials of the linearise
-        // kernel) and the PCG start state
-        double es[5];
-        for (int k = 0; k < 5; ++k)
-            es[k] = block_sum_partials(a.partials + (long)(PS_E + k) * a.max_blocks, n_lin_blocks);
-        if (tid == 0) {
-            for (int k = 0; k < 5; ++k) a.sc->e_lin[k] = es[k];
-            a.sc->e_lin[5] = (double)C.w_photo * es[0] + (double)C.w_grad * es[1] +
-                             (double)C.w_reg * ((double)C.w_smooth * es[2] + (double)C.w_epi * es[3] +
-                                                (double)C.w_mag * es[4]);
-            PcgHist h0;
-            h0.gamma = 0.0; h0.alpha = 0.f; h0.beta = 0.f; h0.active = 1; h0.pad = 0;
-            a.sc->hist[0] = h0;
-        }
-    }
-    tile_brackets(a, g, L);
-    pixels_to_lds<12>(g, L, [&](int x, int y, int, int, float (&v)[12]) {
-        const long pix = (long)y * d.W + x;
-        const float4 *rp = reinterpret_cast<const float4 *>(a.grad + pix * SF_GRAD_STRIDE);
-        const float4 *gp = reinterpret_cast<const float4 *>(a.gram + pix * SF_GRAM_STRIDE);
-        const float4 r0 = rp[0], r1 = rp[1], g0 = gp[0], g1 = gp[1];
-        v[0] = r0.x; v[1] = r0.y; v[2] = r0.z; v[3] = r0.w; v[4] = r1.x; v[5] = r1.y;
-        v[6] = g0.x; v[7] = g0.y; v[8] = g0.z; v[9] = g0.w; v[10] = g1.x; v[11] = g1.y;
-    });
-    __syncthreads();
-    float acc[12];
-    lds_to_nodes<12, S>(a, t, g, L, 0xFC0u, acc);
-    if (mine) {
+
+    template <int S>
+    __device__ void finish(const LevelArgs &a, int i, int j, long n, const float (&gdata)[6],
+                           const float (&ddata)[6]) const {
+        const DevConst &C = *a.cst;
         float grad[6], dg[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) { grad[q] = acc[q]; dg[q] = acc[6 + q]; }
+        for (int q = 0; q < 6; ++q) { grad[q] = gdata[q]; dg[q] = ddata[q]; }
         const float cs = 2.f * C.w_reg * C.w_smooth;
         float cnb[4];
 #pragma unroll
@@ -994,6 +974,60 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(KArg<B> ka, TileCfg t
         rg4[2] = make_float4(se * J[0][4], se * J[0][5], se * J[1][0], se * J[1][1]);
         rg4[3] = make_float4(se * J[1][2], se * J[1][3], se * J[1][4], se * J[1][5]);
     }
+};
+
+// Workgroup 0 of a right-hand-side kernel: the energy at the linearisation
+// point (the linearise kernel's partials) and the PCG start state.
+__device__ void rhs_level_scalars(const LevelArgs &a) {
+    const DevConst &C = *a.cst;
+    const int n_lin_blocks = energy_blocks_of(a.d);
+    double es[5];
+    for (int k = 0; k < 5; ++k)
+        es[k] = block_sum_partials(a.partials + (long)(PS_E + k) * a.max_blocks, n_lin_blocks);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 5; ++k) a.sc->e_lin[k] = es[k];
+        a.sc->e_lin[5] = (double)C.w_photo * es[0] + (double)C.w_grad * es[1] +
+                         (double)C.w_reg * ((double)C.w_smooth * es[2] + (double)C.w_epi * es[3] +
+                                            (double)C.w_mag * es[4]);
+        PcgHist h0;
+        h0.gamma = 0.0; h0.alpha = 0.f; h0.beta = 0.f; h0.active = 1; h0.pad = 0;
+        a.sc->hist[0] = h0;
+    }
+}
+
+template <bool B, int S>
+__global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(KArg<B> ka, TileCfg t) {
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    SF_BIND(ka);
+    const LevelDims &d = a.d;
+    const TileGeom g = tile_geom(a, t, bid);
+    const TileLds L = tile_lds(lds, t, S, 12);
+    const int tid = threadIdx.x;
+    const int nl = tid / t.tpn, sub = tid % t.tpn;
+    const bool mine = sub == 0 && nl < g.txa * g.tya;
+    const int i = g.i0 + (nl % max(g.txa, 1)), j = g.j0 + nl / max(g.txa, 1);
+    const long n = (long)j * d.Gx + i;
+    RhsNode nd;
+    if (mine) nd.load(a, i, j, n);
+    if (bid == 0) rhs_level_scalars(a);
+    tile_brackets(a, g, L);
+    pixels_to_lds<12>(g, L, [&](int x, int y, int, int, float (&v)[12]) {
+        const long pix = (long)y * d.W + x;
+        const float4 *rp = reinterpret_cast<const float4 *>(a.grad + pix * SF_GRAD_STRIDE);
+        const float4 *gp = reinterpret_cast<const float4 *>(a.gram + pix * SF_GRAM_STRIDE);
+        const float4 r0 = rp[0], r1 = rp[1], g0 = gp[0], g1 = gp[1];
+        v[0] = r0.x; v[1] = r0.y; v[2] = r0.z; v[3] = r0.w; v[4] = r1.x; v[5] = r1.y;
+        v[6] = g0.x; v[7] = g0.y; v[8] = g0.z; v[9] = g0.w; v[10] = g1.x; v[11] = g1.y;
+    });
+    __syncthreads();
+    float acc[12];
+    lds_to_nodes<12, S>(a, t, g, L, 0xFC0u, acc);
+    if (mine) {
+        float gd[6], dd[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) { gd[q] = acc[q]; dd[q] = acc[6 + q]; }
+        nd.finish<S>(a, i, j, n, gd, dd);
+    }
 }
 
 // ---- per-node system-matrix blocks (node-block apply mode) -----------------
@@ -1007,16 +1041,20 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(KArg<B> ka, TileCfg t
 // (node, support row r) sums the row's columns with the column weights
 // bx_i bx_{i+di} for di = 0, +1, -1 and scales the three sums by the row
 // weights by_j^2 (same row of nodes) and by_j by_{j+1} (next row).
+// The same kernel forms the right-hand side: the data gradient is summed
+// over the same support rows, and diag(H)'s data part is the diagonal of
+// the self block.
 
 // Assembly tile per stride: tx x ty nodes, tpn >= 2S threads per node, the
-// pixel region's 21-float records under 64 KB of LDS.
+// pixel region's 27-float records (gradient, Gauss-Newton block) under
+// 64 KB of LDS.
 template <int S> struct BlkShape;
 template <> struct BlkShape<1> { static constexpr int TX = 16, TY = 8, TPN = 2; };
 template <> struct BlkShape<2> { static constexpr int TX = 16, TY = 4, TPN = 4; };
 template <> struct BlkShape<3> { static constexpr int TX = 8, TY = 4, TPN = 8; };
 template <> struct BlkShape<4> { static constexpr int TX = 8, TY = 2, TPN = 8; };
 template <> struct BlkShape<5> { static constexpr int TX = 4, TY = 2, TPN = 16; };
-template <> struct BlkShape<6> { static constexpr int TX = 4, TY = 2, TPN = 16; };
+template <> struct BlkShape<6> { static constexpr int TX = 2, TY = 2, TPN = 16; };
 template <> struct BlkShape<7> { static constexpr int TX = 2, TY = 2, TPN = 16; };
 template <> struct BlkShape<8> { static constexpr int TX = 2, TY = 1, TPN = 32; };
 template <int S>
@@ -1033,27 +1071,38 @@ __host__ __device__ inline void blk_offset(int k, int &di, int &dj) {
 }
 
 template <bool B, int S>
-__global__ __launch_bounds__(BlkTraits<S>::NT) void k_blocks(KArg<B> ka, TileCfg t) {
+__global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, TileCfg t) {
     extern __shared__ __attribute__((aligned(16))) float lds[];
     SF_BIND(ka);
     const LevelDims &d = a.d;
     const TileGeom g = tile_geom(a, t, bid);
-    const TileLds L = tile_lds(lds, t, S, 21);
+    const TileLds L = tile_lds(lds, t, S, 27);
+    const int nl = threadIdx.x / t.tpn, sub = threadIdx.x % t.tpn;
+    const bool valid = nl < g.txa * g.tya;
+    const bool mine = valid && sub == 0;
+    const int i = g.i0 + nl % max(g.txa, 1), j = g.j0 + nl / max(g.txa, 1);
+    const long n = (long)j * d.Gx + i;
+    RhsNode nd;
+    if (mine) nd.load(a, i, j, n);
+    if (bid == 0) rhs_level_scalars(a);
     tile_brackets(a, g, L);
-    pixels_to_lds<21>(g, L, [&](int x, int y, int, int, float (&v)[21]) {
-        const float4 *gp = reinterpret_cast<const float4 *>(a.gram + ((long)y * d.W + x) * SF_GRAM_STRIDE);
+    pixels_to_lds<27>(g, L, [&](int x, int y, int, int, float (&v)[27]) {
+        const long pix = (long)y * d.W + x;
+        const float4 *rp = reinterpret_cast<const float4 *>(a.grad + pix * SF_GRAD_STRIDE);
+        const float4 *gp = reinterpret_cast<const float4 *>(a.gram + pix * SF_GRAM_STRIDE);
+        const float4 r0 = rp[0], r1 = rp[1];
+        v[0] = r0.x; v[1] = r0.y; v[2] = r0.z; v[3] = r0.w; v[4] = r1.x; v[5] = r1.y;
 #pragma unroll
         for (int m = 0; m < 5; ++m) {
             const float4 t4 = gp[m];
-            v[4 * m] = t4.x; v[4 * m + 1] = t4.y; v[4 * m + 2] = t4.z; v[4 * m + 3] = t4.w;
+            v[6 + 4 * m] = t4.x; v[7 + 4 * m] = t4.y; v[8 + 4 * m] = t4.z; v[9 + 4 * m] = t4.w;
         }
-        v[20] = gp[5].x;
+        v[26] = gp[5].x;
     });
     __syncthreads();
-    const int nl = threadIdx.x / t.tpn, sub = threadIdx.x % t.tpn;
-    const bool valid = nl < g.txa * g.tya;
-    const int i = g.i0 + nl % max(g.txa, 1), j = g.j0 + nl / max(g.txa, 1);
-    float c0[21], cp[21], cm[21];
+    float gs[6], c0[21], cp[21], cm[21];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gs[k] = 0.f;
 #pragma unroll
     for (int k = 0; k < 21; ++k) c0[k] = cp[k] = cm[k] = 0.f;
     float r_same = 0.f, r_next = 0.f;
@@ -1078,20 +1127,26 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_blocks(KArg<B> ka, TileCfg
                     const float wi = bweight(b, i, d.Gx);
                     const float wp = i + 1 < d.Gx ? bweight(b, i + 1, d.Gx) : 0.f;
                     const float wm = i >= 1 ? bweight(b, i - 1, d.Gx) : 0.f;
+                    const float w1 = wi * vj;
                     const float a0 = wi * wi, ap = wi * wp, am = wi * wm;
-                    float G[21];
-                    rec_load<21>(row + (size_t)rx * rec_pad(21), G);
+                    float v[27];
+                    rec_load<27>(row + (size_t)rx * rec_pad(27), v);
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) gs[k] += w1 * v[k];
 #pragma unroll
                     for (int k = 0; k < 21; ++k) {
-                        c0[k] += a0 * G[k];
-                        cp[k] += ap * G[k];
-                        cm[k] += am * G[k];
+                        c0[k] += a0 * v[6 + k];
+                        cp[k] += ap * v[6 + k];
+                        cm[k] += am * v[6 + k];
                     }
                 }
             }
         }
     }
-    float *dst = a.blk + ((long)j * d.Gx + i) * SF_BLK_STRIDE;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gs[k] = group_sum<float>(gs[k], t.tpn);
+    float *dst = a.blk + n * SF_BLK_STRIDE;
+    float sd[6];
 #pragma unroll
     for (int kb = 0; kb < SF_BLK_TYPES; ++kb) {
         const float rw = kb < 2 ? r_same : r_next;
@@ -1101,8 +1156,13 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_blocks(KArg<B> ka, TileCfg
             const float src = (kb == 0 || kb == 2) ? c0[k] : ((kb == 4) ? cm[k] : cp[k]);
             o[k] = group_sum<float>(rw * src, t.tpn);
         }
+        if (kb == 0) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) sd[q] = o[gram_index(q, q)];
+        }
         if (valid && sub == kb % t.tpn) rec_store<21>(dst + kb * SF_GRAM_STRIDE, o);
     }
+    if (mine) nd.finish<S>(a, i, j, n, gs, sd);
 }
 
 // ---- preconditioned CG in single-reduction form --------------------------
@@ -1123,60 +1183,49 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_blocks(KArg<B> ka, TileCfg
 // iterations change nothing.
 
 
-// Per-thread strided sums of the previous iteration's three partial planes.
+// Per-lane strided sums of the previous iteration's three partial planes;
+// every wavefront of every workgroup loads and sums all of them in the same
+// order.
 __device__ __forceinline__ void load_pcg_partials(const LevelArgs &a, int i, int nb_prev,
                                                   double (&acc)[3]) {
     const float *prev = a.partials + (long)(((i - 1) & 1) ? PS_PCG1 : PS_PCG0) * a.max_blocks;
     acc[0] = acc[1] = acc[2] = 0.0;
-    for (int b = threadIdx.x; b < nb_prev; b += blockDim.x) {
+    for (int b = threadIdx.x & 63; b < nb_prev; b += 64) {
         acc[0] += (double)prev[b];
         acc[1] += (double)prev[a.max_blocks + b];
         acc[2] += (double)prev[2 * a.max_blocks + b];
     }
 }
 
-// Block-wide fixed-order sum of the per-thread partial sums, then the
-// scalars of iteration i-1 (thread 0 decides, everyone receives).
-__device__ void pcg_decide(const LevelArgs &a, int bid, int i, const double (&acc)[3],
-                           const PcgHist &h, int log_index, int force, float &alpha,
-                           float &beta, int &act) {
-    __shared__ double red[16][3];
-    __shared__ float s_alpha, s_beta;
-    __shared__ int s_act;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double v = wave_sum_d(acc[k]);
-        if (lane == 0) red[wv][k] = v;
+// The scalars of iteration i-1 from the lane sums: every wavefront reduces
+// the same values in the same order and decides alike, so no workgroup
+// barrier is needed.  `rec` and `rr` are recorded by workgroup 0 at the end
+// of the kernel (record_decision), after its last barrier, so that no
+// barrier waits for those stores.
+__device__ void pcg_decide(int i, const double (&acc)[3], const PcgHist &h, int force,
+                           float &alpha, float &beta, int &act, PcgHist &rec, double &rr) {
+    const double gam = wave_sum_d(acc[0]), del = wave_sum_d(acc[1]);
+    rr = wave_sum_d(acc[2]);
+    double b = 0.0, pq = del;
+    int ok = h.active;
+    if (ok && i - 1 > 0) {
+        b = gam / h.gamma;
+        pq = del - b * gam / (double)h.alpha;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double gam = 0.0, del = 0.0, rr = 0.0;
-        for (int w = 0; w < nw; ++w) { gam += red[w][0]; del += red[w][1]; rr += red[w][2]; }
-        double b = 0.0, pq = del;
-        int ok = h.active;
-        if (ok && i - 1 > 0) {
-            b = gam / h.gamma;
-            pq = del - b * gam / (double)h.alpha;
-        }
-        ok = ok && gam > 1e-30 && pq > 0.0 && isfinite(pq);
-        float al = ok ? (float)(gam / pq) : 0.f;
-        float be = ok ? (float)b : 0.f;
-        if (force) { ok = 1; al = 1e-3f; be = 0.5f; }
-        s_alpha = al;
-        s_beta = be;
-        s_act = ok;
-        if (bid == 0) {
-            PcgHist o;
-            o.gamma = gam; o.alpha = al; o.beta = be; o.active = ok; o.pad = 0;
-            a.sc->hist[i] = o;
-            if (log_index >= 0 && i >= 2) a.log[log_index].pcg_res[i - 2] = (float)sqrt(rr);
-        }
-    }
-    __syncthreads();
-    alpha = s_alpha;
-    beta = s_beta;
-    act = s_act;
+    ok = ok && gam > 1e-30 && pq > 0.0 && isfinite(pq);
+    float al = ok ? (float)(gam / pq) : 0.f;
+    float be = ok ? (float)b : 0.f;
+    if (force) { ok = 1; al = 1e-3f; be = 0.5f; }
+    rec.gamma = gam; rec.alpha = al; rec.beta = be; rec.active = ok; rec.pad = 0;
+    alpha = al;
+    beta = be;
+    act = ok;
+}
+
+__device__ __forceinline__ void record_decision(const LevelArgs &a, int i, int log_index,
+                                                const PcgHist &rec, double rr) {
+    a.sc->hist[i] = rec;
+    if (log_index >= 0 && i >= 2) a.log[log_index].pcg_res[i - 2] = (float)sqrt(rr);
 }
 
 // Copies this workgroup's partials to the next slot (inactive iteration:
@@ -1243,7 +1292,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     h.gamma = 0.0; h.alpha = 0.f; h.beta = 0.f; h.active = 1; h.pad = 0;
     if (!FIRST) {
         load_pcg_partials(a, i, nb_prev, pacc);
-        if (tid == 0) h = a.sc->hist[i - 1];
+        h = a.sc->hist[i - 1];
     }
     // owned node of this thread's node group
     const int HX = t.tx + 2;
@@ -1352,10 +1401,13 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     if constexpr (S > 0) tile_brackets(a, g, L);
     float alpha = 0.f, beta = 0.f;
     int act = 1;
+    PcgHist rec;
+    double rr_prev = 0.0;
     if (!FIRST) {
-        pcg_decide(a, bid, i, pacc, h, log_index, force, alpha, beta, act);
+        pcg_decide(i, pacc, h, force, alpha, beta, act, rec, rr_prev);
         if (!act) {
             carry_partials(a, bid, i);
+            if (bid == 0 && tid == 0) record_decision(a, i, log_index, rec, rr_prev);
             return;
         }
     }
@@ -1501,6 +1553,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     if (tid == 0) {
         const long dst = (long)((i & 1) ? PS_PCG1 : PS_PCG0) * a.max_blocks;
         for (int k = 0; k < 3; ++k) a.partials[dst + (long)k * a.max_blocks + bid] = tot3[k];
+        if (!FIRST && bid == 0) record_decision(a, i, log_index, rec, rr_prev);
     }
 }
 
@@ -1523,9 +1576,7 @@ __global__ __launch_bounds__(SF_BLOCK) void k_pcg_last(KArg<B> ka, TileCfg t, in
     const bool in = n < a.d.G;
     double pacc[3];
     load_pcg_partials(a, i, nb_prev, pacc);
-    PcgHist h;
-    h.gamma = 0.0; h.alpha = 0.f; h.beta = 0.f; h.active = 1; h.pad = 0;
-    if (threadIdx.x == 0) h = a.sc->hist[i - 1];
+    const PcgHist h = a.sc->hist[i - 1];
     float rp[6], wp[6], sp[6], up[6], pp[6], xp[6];
     if (in) {
         ld6(Rp, n, rp);
@@ -1542,7 +1593,9 @@ __global__ __launch_bounds__(SF_BLOCK) void k_pcg_last(KArg<B> ka, TileCfg t, in
     }
     float alpha, beta;
     int act;
-    pcg_decide(a, bid, i, pacc, h, log_index, force, alpha, beta, act);
+    PcgHist rec;
+    double rr_prev;
+    pcg_decide(i, pacc, h, force, alpha, beta, act, rec, rr_prev);
     float prt[1] = {0.f};
     if (in) {
         float rn[6], pn[6], xn[6];
@@ -1565,8 +1618,278 @@ __global__ __launch_bounds__(SF_BLOCK) void k_pcg_last(KArg<B> ka, TileCfg t, in
     }
     float tot1[1];
     block_sum<1>(prt, tot1);
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         a.partials[(long)(((i & 1) ? PS_PCG1 : PS_PCG0) + 2) * a.max_blocks + bid] = tot1[0];
+        if (bid == 0) record_decision(a, i, log_index, rec, rr_prev);
+    }
+}
+
+#define SMALL_NT 1024
+#define SMALL_NPW 21  // nodes per wavefront, three lanes each
+static_assert(SMALL_NT / 64 * SMALL_NPW == SF_SMALL_G, "small-level capacity");
+
+// ---- whole PCG of a small level in one workgroup (node blocks) ------------
+//
+// For levels with at most SF_SMALL_G nodes the n PCG iterations of a
+// Gauss-Newton step run in one workgroup per frame: three lanes per node
+// (21 nodes per wavefront), each holding three of the node's nine blocks in
+// registers and two of its six components of x, r, p, s, w and diag(H); u
+// is exchanged through LDS records and the three inner products through a
+// fixed-order workgroup reduction, so every iteration costs two barriers
+// instead of a kernel launch and a round trip through memory.  The
+// iterates, history entries, logged residual norms and the final partial
+// sum read by the step control are those of the multi-kernel form.
+
+// A value every lane holds the same copy of, moved to scalar registers.
+__device__ __forceinline__ double uniform_d(double v) {
+    const unsigned long long b = __double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ float uniform_f(float v) {
+    return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
+}
+
+// Block products of a node's three lanes: task q of lane `sub` is block
+// type k, the node's own (partner n + off(k)) or the one stored by
+// n - off(k) (whose partner is n).
+__device__ __forceinline__ void small_task(int sub, int q, int &k, bool &own) {
+    if (sub == 0) { k = q; own = true; }                   // self, E, S
+    else if (sub == 1) { k = q == 2 ? 1 : 3 + q; own = q < 2; }  // SE, SW, E of W
+    else { k = 2 + q; own = false; }                        // S of N, SE of NW, SW of NE
+}
+
+template <bool B>
+__global__ __launch_bounds__(SMALL_NT) void k_pcg_small(KArg<B> ka, int n_it, int gn) {
+    __shared__ __attribute__((aligned(16))) float su[SF_SMALL_G * 8];
+    // each lane's third block (registers hold the first two)
+    __shared__ __attribute__((aligned(16))) float sb[SMALL_NT * SF_GRAM_STRIDE];
+    // per lane: its block products (6) and epipolar pair sums (2); two spare
+    // records for the idle last lane of a wavefront, which reads past it
+    __shared__ __attribute__((aligned(16))) float sx[(SMALL_NT + 2) * 8];
+    __shared__ float red[SMALL_NT / 64][3];
+    // decisions and logged residual norms, written out after the loop
+    __shared__ PcgHist shist[SF_MAX_PCG + 1];
+    __shared__ double sres[SF_MAX_PCG];
+    SF_BIND(ka);
+    (void)nblk;
+    const LevelDims &d = a.d;
+    if (d.G > SF_SMALL_G) return;  // the host never launches such a level
+    const int log_index = gn >= 0 ? a.log_base + gn : -1;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int sub = lane % 3;
+    const int n = wv * SMALL_NPW + lane / 3;
+    const bool valid = lane < 3 * SMALL_NPW && n < d.G;
+    const int i_n = valid ? n % d.Gx : 0, j_n = valid ? n / d.Gx : 0;
+    const int c0 = 2 * sub;  // this lane's two components
+    // A missing partner gets a zero block and the node's own u record, so
+    // that every lane issues the same loads and products (adding +0 leaves
+    // the sums unchanged).
+    float Bk[2][21];
+    int pn[3];
+    float *myb = sb + threadIdx.x * SF_GRAM_STRIDE;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        int k, di, dj;
+        bool own;
+        small_task(sub, q, k, own);
+        blk_offset(k, di, dj);
+        const int pi = own ? i_n + di : i_n - di, pj = own ? j_n + dj : j_n - dj;
+        const bool has = valid && pi >= 0 && pi < d.Gx && pj >= 0 && pj < d.Gy;
+        pn[q] = has ? pj * d.Gx + pi : (valid ? n : 0);
+        float t[21];
+#pragma unroll
+        for (int e = 0; e < 21; ++e) t[e] = 0.f;
+        if (has) {
+            const long owner = own ? (long)n : (long)pn[q];
+            rec_load<21>(a.blk + owner * SF_BLK_STRIDE + k * SF_GRAM_STRIDE, t);
+        }
+        if (q < 2) {
+#pragma unroll
+            for (int e = 0; e < 21; ++e) Bk[q][e] = t[e];
+        } else {
+            rec_store<21>(myb, t);
+        }
+    }
+    float cnb[4] = {0.f, 0.f, 0.f, 0.f}, J0o[2] = {0.f, 0.f}, J1o[2] = {0.f, 0.f};
+    int nbr[4];
+    float r2[2] = {0.f, 0.f}, u2[2] = {0.f, 0.f}, D2[2] = {1.f, 1.f};
+    float x2[2] = {0.f, 0.f}, p2[2] = {0.f, 0.f}, s2[2] = {0.f, 0.f}, w2[2] = {0.f, 0.f};
+    float wf2[2], cm2[2];
+    {
+        const DevConst *C = a.cst;
+        const float c = 2.f * C->w_reg * C->w_mag;
+        wf2[0] = C->wf[c0]; wf2[1] = C->wf[c0 + 1];
+        cm2[0] = c * C->mf[c0]; cm2[1] = c * C->mf[c0 + 1];
+    }
+    if (valid) {
+        const float2 rv = *reinterpret_cast<const float2 *>(nvec(a, NV_R0) + (long)n * 8 + c0);
+        const float2 uv = *reinterpret_cast<const float2 *>(nvec(a, NV_U) + (long)n * 8 + c0);
+        const float2 dv = *reinterpret_cast<const float2 *>(nvec(a, NV_DIAG) + (long)n * 8 + c0);
+        r2[0] = rv.x; r2[1] = rv.y; u2[0] = uv.x; u2[1] = uv.y; D2[0] = dv.x; D2[1] = dv.y;
+        float rg[REG_PLANES];
+        rec_load<REG_PLANES>(a.reg + (long)n * REG_PLANES, rg);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cnb[k] = rg[k];
+        // this lane's components of the two epipolar rows
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            J0o[j] = sub == 0 ? rg[4 + j] : (sub == 1 ? rg[6 + j] : rg[8 + j]);
+            J1o[j] = sub == 0 ? rg[10 + j] : (sub == 1 ? rg[12 + j] : rg[14 + j]);
+        }
+    }
+    // neighbours without a smoothness coefficient read the node's own u
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int di, dj;
+        nb_offset(k, di, dj);
+        nbr[k] = valid && cnb[k] != 0.f ? (j_n + dj) * d.Gx + i_n + di : (valid ? n : 0);
+    }
+
+    double gsum = 0.0, dsum = 0.0, rsum = 0.0;  // inner products of iteration i-1
+    double hg = 0.0;                            // gamma of iteration i-2
+    float ha = 0.f;                             // alpha of iteration i-2
+    int act = 1;
+    for (int i = 0; i <= n_it; ++i) {
+        if (i > 0) {
+            // scalars of iteration i-1 (every thread computes the same)
+            double b = 0.0, pq = dsum;
+            int ok = act;
+            if (ok && i - 1 > 0) {
+                b = gsum / hg;
+                pq = dsum - b * gsum / (double)ha;
+            }
+            ok = ok && gsum > 1e-30 && pq > 0.0 && isfinite(pq);
+            const float al = uniform_f(ok ? (float)(gsum / pq) : 0.f);
+            const float be = uniform_f(ok ? (float)b : 0.f);
+            if (threadIdx.x == 0) {
+                // an inactive iteration leaves every later one inactive with
+                // the same sums (the multi-kernel form carries its partials)
+                for (int m = i; m <= (ok ? i : n_it); ++m) {
+                    PcgHist o;
+                    o.gamma = gsum; o.alpha = al; o.beta = be; o.active = ok; o.pad = 0;
+                    shist[m] = o;
+                    if (m >= 2) sres[m - 2] = rsum;
+                }
+            }
+            hg = gsum;
+            ha = al;
+            act = ok;
+            if (!ok) break;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                s2[j] = i > 1 ? w2[j] + be * s2[j] : w2[j];
+                p2[j] = i > 1 ? u2[j] + be * p2[j] : u2[j];
+                x2[j] = x2[j] + al * p2[j];
+                r2[j] = r2[j] - al * s2[j];
+                u2[j] = r2[j] / D2[j];
+            }
+            if (i == n_it) {
+                rsum = 0.0;  // ||r_n||^2 below
+                break;
+            }
+        }
+        // u_i into LDS; w_i = H u_i
+        if (valid) *reinterpret_cast<float2 *>(su + n * 8 + c0) = make_float2(u2[0], u2[1]);
+        __syncthreads();
+        float y[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        {
+            float un[3][6];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) rec_load<6>(su + pn[q] * 8, un[q]);
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int r = 0; r < 6; ++r)
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) y[r] += Bk[q][gram_index(r, c)] * un[q][c];
+            float b2[21];
+            rec_load<21>(myb, b2);
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) y[r] += b2[gram_index(r, c)] * un[2][c];
+        }
+        // the node's sums over its three lanes in lane order, and the
+        // epipolar projections J_t . u from the lanes' component pairs,
+        // exchanged through LDS records (the three lanes share a wavefront,
+        // whose LDS accesses are performed in order)
+        {
+            const float e0 = J0o[0] * u2[0] + J0o[1] * u2[1];
+            const float e1 = J1o[0] * u2[0] + J1o[1] * u2[1];
+            float4 *mx = reinterpret_cast<float4 *>(sx + threadIdx.x * 8);
+            mx[0] = make_float4(y[0], y[1], y[2], y[3]);
+            mx[1] = make_float4(y[4], y[5], e0, e1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        float w2s[2] = {0.f, 0.f}, jp0 = 0.f, jp1 = 0.f;
+        const float *gx = sx + (threadIdx.x - sub) * 8;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const float2 yc = *reinterpret_cast<const float2 *>(gx + t * 8 + c0);
+            const float2 ee = *reinterpret_cast<const float2 *>(gx + t * 8 + 6);
+            w2s[0] += yc.x;
+            w2s[1] += yc.y;
+            jp0 += ee.x;
+            jp1 += ee.y;
+        }
+        float ru = 0.f, wu = 0.f, rr = 0.f;
+        if (valid) {
+            float sm[2] = {0.f, 0.f};
+            float2 un[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) un[k] = *reinterpret_cast<const float2 *>(su + nbr[k] * 8 + c0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                sm[0] += cnb[k] * (u2[0] - un[k].x);
+                sm[1] += cnb[k] * (u2[1] - un[k].y);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                w2[j] = w2s[j] + wf2[j] * sm[j] + J0o[j] * jp0 + J1o[j] * jp1 + cm2[j] * u2[j];
+                ru += r2[j] * u2[j];
+                wu += w2[j] * u2[j];
+                rr += r2[j] * r2[j];
+            }
+        }
+        // wavefront sums in float (as a workgroup's partial in the
+        // multi-kernel form), the wavefronts' sums in double: every
+        // 16-lane row adds them in the same order
+        const float t0 = wave_sum(ru), t1 = wave_sum(wu), t2 = wave_sum(rr);
+        if (lane == 0) { red[wv][0] = t0; red[wv][1] = t1; red[wv][2] = t2; }
+        __syncthreads();
+        {
+            const int rw = lane & 15;
+            const double g0 = rw < nw ? (double)red[rw][0] : 0.0;
+            const double g1 = rw < nw ? (double)red[rw][1] : 0.0;
+            const double g2 = rw < nw ? (double)red[rw][2] : 0.0;
+            gsum = uniform_d(group_sum<double>(g0, 16));
+            dsum = uniform_d(group_sum<double>(g1, 16));
+            rsum = uniform_d(group_sum<double>(g2, 16));
+        }
+    }
+    if (act) {
+        // ||r_n||^2 for the step control's log
+        const float rr = valid ? r2[0] * r2[0] + r2[1] * r2[1] : 0.f;
+        const float t2 = wave_sum(rr);
+        __syncthreads();
+        if (lane == 0) red[wv][2] = t2;
+        __syncthreads();
+        const int rw = lane & 15;
+        rsum = group_sum<double>(rw < nw ? (double)red[rw][2] : 0.0, 16);
+    }
+    if (valid) *reinterpret_cast<float2 *>(nvec(a, NV_X) + (long)n * 8 + c0) = make_float2(x2[0], x2[1]);
+    __syncthreads();
+    for (int m = threadIdx.x + 1; m <= n_it; m += blockDim.x) {
+        a.sc->hist[m] = shist[m];
+        if (log_index >= 0 && m >= 2) a.log[log_index].pcg_res[m - 2] = (float)sqrt(sres[m - 2]);
+    }
+    if (threadIdx.x < node_blocks(d)) {
+        a.partials[(long)(((n_it & 1) ? PS_PCG1 : PS_PCG0) + 2) * a.max_blocks + threadIdx.x] =
+            threadIdx.x == 0 ? (float)rsum : 0.f;
+    }
 }
 
 // ---- step control: accept the first tau with E_trial <= E ------------------
@@ -2003,7 +2326,7 @@ TileCfg pick_blk_tile(int s) {
     return blk_tile_of<8>();
 }
 
-size_t blk_tile_lds_bytes(int s) { return node_tile_lds_bytes(pick_blk_tile(s), s, 21); }
+size_t blk_tile_lds_bytes(int s) { return node_tile_lds_bytes(pick_blk_tile(s), s, 27); }
 
 int tile_threads(const TileCfg &t) { return t.tx * t.ty * t.tpn; }
 
@@ -2069,11 +2392,11 @@ void launch_level_init(hipStream_t st, const Launch &L) {
 }
 
 void launch_linearize(hipStream_t st, const Launch &L) {
-    go(st, L, en_blocks, k_energy<true, true>, k_energy<false, true>, SF_BLOCK, 0, 0, 0.f);
+    go(st, L, en_blocks, k_energy<true, true>, k_energy<false, true>, SF_BLOCK, 0, 0, 1);
 }
 
-void launch_trial(hipStream_t st, const Launch &L, int trial, float tau) {
-    go(st, L, en_blocks, k_energy<true, false>, k_energy<false, false>, SF_BLOCK, 0, trial, tau);
+void launch_trials(hipStream_t st, const Launch &L, int first, int count) {
+    go(st, L, en_blocks, k_energy<true, false>, k_energy<false, false>, SF_BLOCK, 0, first, count);
 }
 
 void launch_rhs(hipStream_t st, const Launch &L, const TileCfg &t) {
@@ -2108,8 +2431,14 @@ void launch_rhs(hipStream_t st, const Launch &L, const TileCfg &t) {
         }                                                  \
     }
 
-void launch_pcg_first(hipStream_t st, const Launch &L, const TileCfg &t) {
-    auto nb = [t](const LevelArgs &a) { return node_tiles_of(a.d, t); };
+// Frames with at most SF_SMALL_G nodes are skipped by the multi-kernel PCG
+// when `skip_small` (their PCG runs in launch_pcg_small).
+static bool small_frame(const LevelArgs &a) { return a.d.G <= SF_SMALL_G; }
+
+void launch_pcg_first(hipStream_t st, const Launch &L, const TileCfg &t, bool skip_small) {
+    auto nb = [t, skip_small](const LevelArgs &a) {
+        return skip_small && small_frame(a) ? 0 : node_tiles_of(a.d, t);
+    };
     const int s = L.host[0].s;
 #define PCG0(S, V)                                                                            \
     go(st, L, nb, k_pcg<true, true, S, V>, k_pcg<false, true, S, V>, TileTraits<S, V>::NT,    \
@@ -2119,8 +2448,10 @@ void launch_pcg_first(hipStream_t st, const Launch &L, const TileCfg &t) {
 }
 
 void launch_pcg_iter(hipStream_t st, const Launch &L, const TileCfg &t, int iter, int gn,
-                     int force) {
-    auto nb = [t](const LevelArgs &a) { return node_tiles_of(a.d, t); };
+                     int force, bool skip_small) {
+    auto nb = [t, skip_small](const LevelArgs &a) {
+        return skip_small && small_frame(a) ? 0 : node_tiles_of(a.d, t);
+    };
     const int s = L.host[0].s;
 #define PCGI(S, V)                                                                            \
     go(st, L, nb, k_pcg<true, false, S, V>, k_pcg<false, false, S, V>, TileTraits<S, V>::NT,  \
@@ -2129,20 +2460,35 @@ void launch_pcg_iter(hipStream_t st, const Launch &L, const TileCfg &t, int iter
 #undef PCGI
 }
 
-void launch_blocks(hipStream_t st, const Launch &L) {
+void launch_rhs_blocks(hipStream_t st, const Launch &L) {
     const int s = L.host[0].s;
     const TileCfg t = pick_blk_tile(s);
     auto nb = [t](const LevelArgs &a) { return node_tiles_of(a.d, t); };
 #define BLK(S)                                                                            \
-    go(st, L, nb, k_blocks<true, S>, k_blocks<false, S>, BlkTraits<S>::NT,                \
-       node_tile_lds_bytes(t, S, 21), t)
+    go(st, L, nb, k_rhs_blocks<true, S>, k_rhs_blocks<false, S>, BlkTraits<S>::NT,        \
+       node_tile_lds_bytes(t, S, 27), t)
     SF_STRIDE_SWITCH(s, BLK)
 #undef BLK
 }
 
+// One workgroup per small frame with a wavefront per 21 of its nodes (the
+// largest small frame of the launch sets the count).
+void launch_pcg_small(hipStream_t st, const Launch &L, int n_it, int gn) {
+    auto one = [](const LevelArgs &a) { return small_frame(a) ? 1 : 0; };
+    int gmax = 0;
+    for (int f = 0; f < L.nf; ++f)
+        if (small_frame(L.host[f])) gmax = gmax > L.host[f].d.G ? gmax : L.host[f].d.G;
+    if (gmax == 0) return;
+    const int threads = 64 * ((gmax + SMALL_NPW - 1) / SMALL_NPW);
+    go(st, L, one, k_pcg_small<true>, k_pcg_small<false>, threads, 0, n_it, gn);
+}
+
 void launch_pcg_last(hipStream_t st, const Launch &L, const TileCfg &t, int iter, int gn,
-                     int force) {
-    go(st, L, nd_blocks, k_pcg_last<true>, k_pcg_last<false>, SF_BLOCK, 0, t, iter, gn, force);
+                     int force, bool skip_small) {
+    auto nb = [skip_small](const LevelArgs &a) {
+        return skip_small && small_frame(a) ? 0 : node_blocks(a.d);
+    };
+    go(st, L, nb, k_pcg_last<true>, k_pcg_last<false>, SF_BLOCK, 0, t, iter, gn, force);
 }
 
 void launch_accept(hipStream_t st, const Launch &L, int n_trials, int gn, int pcg_iters) {

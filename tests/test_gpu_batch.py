@@ -44,7 +44,7 @@ def _batch(frames, exec_mode=0, repeat=1, **prm):
     return results, logs
 
 
-@pytest.mark.parametrize("stride,apply", [(4, 0), (8, 0), (4, 1), (8, 1)])
+@pytest.mark.parametrize("stride,apply", [(4, 0), (8, 0), (4, 1), (8, 1), (4, 2), (8, 2)])
 def test_batch_matches_single_frames_bitwise(stride, apply):
     from paper_1610_07159_amd import sf
     sizes = [(160, 120), (96, 72), (128, 96), (100, 76), (200, 150)]

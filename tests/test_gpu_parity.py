@@ -105,7 +105,10 @@ def _gram_upper(Gx):
     (0, 4, 0), (2, 4, 0), (0, 8, 0), (1, 2, 0), (0, 3, 0),
     # node-block products: every assembly tile shape (strides 1..8)
     (0, 4, 1), (2, 4, 1), (0, 8, 1), (1, 2, 1), (0, 3, 1), (0, 5, 1), (0, 6, 1),
-    (0, 7, 1), (2, 1, 1)])
+    (0, 7, 1), (2, 1, 1),
+    # whole-PCG single-workgroup kernel (levels of at most 336 nodes; 21 x 16
+    # = 336 at stride 5 fills it exactly)
+    (2, 4, 2), (0, 8, 2), (1, 4, 2), (0, 6, 2), (0, 5, 2)])
 def test_linearize_apply_pcg_parity(level, stride, apply):
     g, imgs, calib, p = _stage_case(W=104, H=78, grid_stride=stride, apply_mode=apply)
     try:
@@ -202,20 +205,23 @@ def test_solve_tiny_parity():
 @pytest.mark.parametrize("W,H,stride,apply", [(100, 76, 4, 0), (160, 120, 4, 0), (96, 72, 2, 0),
                                               (144, 104, 8, 0), (100, 76, 4, 1),
                                               (160, 120, 4, 1), (96, 72, 2, 1),
-                                              (144, 104, 8, 1), (90, 70, 3, 1)])
+                                              (144, 104, 8, 1), (90, 70, 3, 1),
+                                              (100, 76, 4, 2), (160, 120, 4, 2),
+                                              (96, 72, 2, 2), (144, 104, 8, 2)])
 def test_solve_medium_parity(W, H, stride, apply):
     imgs, calib = _frame(W, H, seed=7)
     prm = dict(levels=3, grid_stride=stride, gn_iters=4, pcg_iters=10, apply_mode=apply)
     _solve_parity(imgs, calib, prm)
 
 
-def test_solve_tiny_parity_node_blocks():
+@pytest.mark.parametrize("apply", [1, 2])
+def test_solve_tiny_parity_node_blocks(apply):
     imgs, calib, _ = make_frame(tiny_plane_config(), 0)
-    prm = dict(levels=3, grid_stride=8, gn_iters=5, pcg_iters=10, apply_mode=1)
+    prm = dict(levels=3, grid_stride=8, gn_iters=5, pcg_iters=10, apply_mode=apply)
     _solve_parity(imgs, calib, prm)
 
 
-@pytest.mark.parametrize("apply", [0, 1])
+@pytest.mark.parametrize("apply", [0, 1, 2])
 def test_graph_replay_matches_eager_and_repeats(apply):
     imgs, calib = _frame(128, 96, seed=9)
     prm = dict(levels=3, grid_stride=4, gn_iters=3, pcg_iters=8, apply_mode=apply)
