@@ -440,6 +440,8 @@ def main():
                      "avg_us_per_launch": round(bytes_apply / achieved / 1e3, 2),
                      "apply_us_per_level": per_level},
         "final_energy": log[-1]["energy_after"],
+        "accepted_tau": {str(t): sum(1 for r in log if r["tau"] == t)
+                         for t in sorted({r["tau"] for r in log}, reverse=True)},
     }
     if not args.no_epe:
         result["epe_px"] = round(epe(flows, scene, W, H), 4)

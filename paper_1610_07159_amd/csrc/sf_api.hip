@@ -335,7 +335,7 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
         F.cst = P.dcst + f;
         F.io = P.dio + f;
     }
-    // zeroed workspace: arrival counters must start at 0
+    // zeroed workspace
     HIP_TRY(hipMemset(P.pool, 0, off));
     // per-slot kernel arguments
     P.host.assign(P.Lmax, {});
@@ -497,8 +497,8 @@ void enqueue_gn(const Plan &P, hipStream_t st, int l, int g, bool log) {
     const Launch L = slot(P, l);
     const int T = P.prm.max_backtracks + 1;
     // tau = 1 alone (usually accepted), then the shorter steps together
-    launch_trials(st, L, 0, 1);
-    if (T > 1) launch_trials(st, L, 1, T - 1);
+    launch_trial0(st, L);
+    if (T > 1) launch_trials_rest(st, L, T - 1);
     launch_accept(st, L, T, log ? g : -1, P.prm.pcg_iters);
 }
 

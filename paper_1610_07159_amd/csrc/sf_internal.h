@@ -105,11 +105,10 @@ struct PcgHist {
 };
 
 // Device-resident scalars of the solve.  Every slot is written by exactly
-// one workgroup (or the last to arrive) and read only by later kernels.
+// one workgroup and read only by later kernels.
 struct DevScalars {
-    unsigned int counter[4];          // arrival counters (reset by the last)
     double e_lin[6];                  // photo, grad, smooth, epi, mag, total
-    double e_trial[SF_MAX_TRIALS][6]; // same for each trial step length
+    double e_trial[SF_MAX_TRIALS][6]; // the accepted trial's terms
     PcgHist hist[SF_MAX_PCG + 2];
     double e_init[2];  // fallback energies: learned, zero initialisation
     int init_used;     // the learned initialisation was kept
@@ -200,9 +199,10 @@ void launch_level_masks(hipStream_t st, const Launch &L);
 // (before launch_level_init)
 void launch_cnn_candidate(hipStream_t st, const Launch &L);
 void launch_linearize(hipStream_t st, const Launch &L);
-// energies of trials first .. first+count-1 (tau = 2^-trial) in one launch;
-// every workgroup returns at once if an earlier trial was accepted
-void launch_trials(hipStream_t st, const Launch &L, int first, int count);
+// step control: the energy at tau = 1, then (each workgroup returning at
+// once if tau = 1 was accepted) the n_rest shorter steps 2^-1 .. 2^-n_rest
+void launch_trial0(hipStream_t st, const Launch &L);
+void launch_trials_rest(hipStream_t st, const Launch &L, int n_rest);
 void launch_rhs(hipStream_t st, const Launch &L, const TileCfg &t);
 // right-hand side, diag(H) and the per-node blocks from the pixel records
 // (node-block apply mode; replaces launch_rhs after launch_linearize)

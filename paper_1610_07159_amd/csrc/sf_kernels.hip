@@ -10,9 +10,10 @@
 //     per-pixel quantities onto nodes, done as a deterministic two-pass
 //     separable reduction in LDS, plus the regularisers of Eqs. (14)-(18);
 //   * node-wise kernels for the PCG vector updates and step control.
-// Every cross-workgroup sum is deterministic: each workgroup writes a
-// partial, and the last workgroup to arrive sums all partials in a fixed
-// order in double precision.
+// Every cross-workgroup sum is deterministic and needs no atomics or
+// device-scope fences: each workgroup writes a partial, and the kernels
+// that consume the sum add all partials in a fixed order in double
+// precision (every consuming workgroup obtaining the same value).
 #include <math.h>
 
 #include "sf_cnn.h"
@@ -201,6 +202,34 @@ __device__ void block_sum(float (&v)[K], float (&out)[K]) {
 
 // Sum in double of n partials by the whole block; result valid in every
 // thread.  Fixed order, so bitwise reproducible.
+// K planes at once (plane(k) gives plane k): every load is issued before
+// the first barrier, and each plane is summed in the same order as by
+// block_sum_partials.
+template <int K, class PlaneFn>
+__device__ void block_sum_planes(PlaneFn plane, int n, double (&out)[K]) {
+    __shared__ double red[16][K];
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += (double)plane(k)[i];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        acc[k] = wave_sum_d(acc[k]);
+        if (lane == 0) red[wv][k] = acc[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double r = red[0][k];
+        for (int w = 1; w < nw; ++w) r += red[w][k];
+        out[k] = r;
+    }
+    __syncthreads();
+}
+
 __device__ double block_sum_partials(const float *part, int n) {
     __shared__ double red[16];
     double acc = 0.0;
@@ -215,21 +244,6 @@ __device__ double block_sum_partials(const float *part, int n) {
     return r;
 }
 
-// Arrival at a frame's counter: true in every thread of the last of the
-// frame's `total` workgroups to arrive, which then sees all partials.
-__device__ bool last_block(unsigned int *counter, unsigned int total) {
-    __shared__ int s_last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned int prev = atomicAdd(counter, 1u);
-        s_last = (prev == total - 1) ? 1 : 0;
-        if (s_last) atomicExch(counter, 0u);
-    }
-    __syncthreads();
-    if (s_last) __threadfence();
-    return s_last != 0;
-}
 
 // ---- frame binding ---------------------------------------------------------
 //
@@ -237,7 +251,7 @@ __device__ bool last_block(unsigned int *counter, unsigned int total) {
 // LevelArgs by value, and a batched form, which takes a FrameMap: the
 // workgroup finds its frame in the map's block prefix (uniform scalar
 // compares), loads that frame's arguments from the device table and works
-// on its block index within the frame.  Per-frame partial sums, counters,
+// on its block index within the frame.  Per-frame partial sums,
 // scalars and logs keep every reduction segmented by frame.
 template <bool B>
 using KArg = typename std::conditional<B, FrameMap, LevelArgs>::type;
@@ -627,91 +641,136 @@ __device__ void node_energy(const LevelArgs &a, int n, float tau, float (&part)[
     part[4] = em;
 }
 
-// blocks [0, n_pix): 16x16 pixel tiles; blocks [n_pix, grid): 256 nodes each
-// for the regulariser energies.
-//  LIN:  per-pixel records and energy partials at delta (summed later by
-//        the right-hand-side kernel).
-//  !LIN: trial energy at delta + tau dx, skipped if an earlier trial of this
-//        step was accepted; the last workgroup to finish sums the partials.
-// Partial-sum planes of the t-th trial of a launch (the linearisation and
-// single trials use PS_E).
-__device__ __forceinline__ int trial_plane(int t) { return t == 0 ? PS_E : PS_TRIAL + 5 * (t - 1); }
+// Energy grid: blocks [0, n_pix) are 16x16 pixel tiles, blocks
+// [n_pix, grid) 256 nodes each for the regulariser energies.  With LIN the
+// per-pixel records and the energy at delta (summed by the right-hand-side
+// kernel); otherwise a trial energy at delta + tau dx (summed by the step
+// control).
 
-template <bool B, bool LIN>
-__global__ __launch_bounds__(SF_BLOCK) void k_energy(KArg<B> ka, int trial, int n_tr) {
-    SF_BIND(ka);
+// Energy terms of one energy-grid workgroup's share at step length tau:
+// pixel tile `tile` (16 x 16 pixels; with LIN also its Gauss-Newton
+// records) or, past the pixel tiles, a block of nodes (regularisers).
+// Uses S for the tile's node totals and ends with a barrier, so a caller
+// may stage the next tile into S right away.
+template <bool LIN>
+__device__ void energy_tile(const LevelArgs &a, int tile, float tau, NodeStage &S,
+                            float (&part)[5]) {
     const LevelDims &d = a.d;
     const int n_pix = pixel_tiles(d);
-    if (!LIN) {
-        const double e0 = a.sc->e_lin[5];
-        for (int k = 0; k < trial; ++k)
-            if (a.sc->e_trial[k][5] <= e0) return;  // uniform over the grid
-    }
-    __shared__ NodeStage S;
-    for (int t = 0; t < n_tr; ++t) {
-        const float tau = LIN ? 0.f : ldexpf(1.f, -(trial + t));
-        float part[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-        if (bid < n_pix) {
-            const int tiles_x = (d.W + TILE_PX - 1) / TILE_PX;
-            const int x0 = (bid % tiles_x) * TILE_PX, y0 = (bid / tiles_x) * TILE_PX;
-            stage_nodes(a, x0, y0, tau, S);
-            __syncthreads();
-            const int x = x0 + (threadIdx.x & (TILE_PX - 1));
-            const int y = y0 + (threadIdx.x / TILE_PX);
-            if (x < d.W && y < d.H) {
-                float f[6];
-                pixel_flows(a, x, y, S, f);
-                const int pix = y * d.W + x;
-                const float c = a.cmask[pix] ? 1.f : 0.f;
-                PixelOut o;
-                pixel_terms<LIN>(a, x, y, f, c, o);
-                part[0] = o.e_photo;
-                part[1] = o.e_grad;
-                if (LIN) {
-                    float g24[SF_GRAM_STRIDE];
+    if (tile < n_pix) {
+        const int tiles_x = (d.W + TILE_PX - 1) / TILE_PX;
+        const int x0 = (tile % tiles_x) * TILE_PX, y0 = (tile / tiles_x) * TILE_PX;
+        stage_nodes(a, x0, y0, tau, S);
+        __syncthreads();
+        const int x = x0 + (threadIdx.x & (TILE_PX - 1));
+        const int y = y0 + (threadIdx.x / TILE_PX);
+        if (x < d.W && y < d.H) {
+            float f[6];
+            pixel_flows(a, x, y, S, f);
+            const int pix = y * d.W + x;
+            const float c = a.cmask[pix] ? 1.f : 0.f;
+            PixelOut o;
+            pixel_terms<LIN>(a, x, y, f, c, o);
+            part[0] += o.e_photo;
+            part[1] += o.e_grad;
+            if (LIN) {
+                float g24[SF_GRAM_STRIDE];
 #pragma unroll
-                    for (int i = 0; i < 6; ++i)
+                for (int i = 0; i < 6; ++i)
 #pragma unroll
-                        for (int j = i; j < 6; ++j) g24[gram_index(i, j)] = o.gram[tri(i, j)];
-                    g24[21] = g24[22] = g24[23] = 0.f;
-                    float4 *gp = reinterpret_cast<float4 *>(a.gram + (long)pix * SF_GRAM_STRIDE);
+                    for (int j = i; j < 6; ++j) g24[gram_index(i, j)] = o.gram[tri(i, j)];
+                g24[21] = g24[22] = g24[23] = 0.f;
+                float4 *gp = reinterpret_cast<float4 *>(a.gram + (long)pix * SF_GRAM_STRIDE);
 #pragma unroll
-                    for (int v = 0; v < 6; ++v)
-                        gp[v] = make_float4(g24[4 * v], g24[4 * v + 1], g24[4 * v + 2], g24[4 * v + 3]);
-                    float4 *rp = reinterpret_cast<float4 *>(a.grad + (long)pix * SF_GRAD_STRIDE);
-                    rp[0] = make_float4(o.grad[0], o.grad[1], o.grad[2], o.grad[3]);
-                    rp[1] = make_float4(o.grad[4], o.grad[5], 0.f, 0.f);
-                }
+                for (int v = 0; v < 6; ++v)
+                    gp[v] = make_float4(g24[4 * v], g24[4 * v + 1], g24[4 * v + 2], g24[4 * v + 3]);
+                float4 *rp = reinterpret_cast<float4 *>(a.grad + (long)pix * SF_GRAD_STRIDE);
+                rp[0] = make_float4(o.grad[0], o.grad[1], o.grad[2], o.grad[3]);
+                rp[1] = make_float4(o.grad[4], o.grad[5], 0.f, 0.f);
             }
-        } else {
-            const int n = (bid - n_pix) * SF_BLOCK + threadIdx.x;
-            if (n < d.G) node_energy(a, n, tau, part);
         }
-        // (the block sum's barriers also keep the next trial's staging
-        // from overwriting S while it is read)
+        __syncthreads();
+    } else {
+        const int n = (tile - n_pix) * SF_BLOCK + threadIdx.x;
+        if (n < d.G) {
+            float pn[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+            node_energy(a, n, tau, pn);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) part[k] += pn[k];
+        }
+    }
+}
+
+// The energy grid: one workgroup per pixel tile and per node block, each
+// writing its five partial sums to the planes PS_E (the linearisation, or
+// the full step tau = 1 of the step control).  The consumers reduce them.
+template <bool B, bool LIN>
+__global__ __launch_bounds__(SF_BLOCK) void k_energy(KArg<B> ka, float tau) {
+    SF_BIND(ka);
+    (void)nblk;
+    __shared__ NodeStage S;
+    float part[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    energy_tile<LIN>(a, bid, LIN ? 0.f : tau, S, part);
+    float tot5[5];
+    block_sum<5>(part, tot5);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) a.partials[(long)(PS_E + k) * a.max_blocks + bid] = tot5[k];
+    }
+}
+
+// Energy terms of a trial from its five partial planes (n entries from
+// plane `base`), summed by one wavefront in a fixed order, and the total
+// E (the weights of Eqs. (8)-(10)).  Every caller obtains the same values.
+__device__ void trial_energy_wave(const LevelArgs &a, int base, int n, double (&e)[6]) {
+    const int lane = threadIdx.x & 63;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const float *p0 = a.partials + (long)base * a.max_blocks;
+    for (int b = lane; b < n; b += 64)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) acc[k] += (double)p0[(long)k * a.max_blocks + b];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) e[k] = wave_sum_d(acc[k]);
+    const DevConst &C = *a.cst;
+    e[5] = (double)C.w_photo * e[0] + (double)C.w_grad * e[1] +
+           (double)C.w_reg * ((double)C.w_smooth * e[2] + (double)C.w_epi * e[3] +
+                              (double)C.w_mag * e[4]);
+}
+
+// Workgroups of the shorter-step trials of a frame (a fixed, small grid
+// that strides over the energy tiles).
+__host__ __device__ inline int rest_blocks_of(const LevelDims &d) {
+    const int n = energy_blocks_of(d);
+    return n < 128 ? n : 128;
+}
+
+// Trials tau = 1/2, 1/4, ... (n_rest of them), evaluated only if tau = 1
+// was rejected: every workgroup first sums the tau = 1 partials itself and
+// returns at once on acceptance.  Partials of trial t go to plane
+// PS_TRIAL + 5 (t - 1).
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_trials_rest(KArg<B> ka, int n_rest) {
+    SF_BIND(ka);
+    __shared__ NodeStage S;
+    __shared__ int s_go;
+    if (threadIdx.x < 64) {
+        double e[6];
+        trial_energy_wave(a, PS_E, energy_blocks_of(a.d), e);
+        if (threadIdx.x == 0) s_go = !(e[5] <= a.sc->e_lin[5]);
+    }
+    __syncthreads();
+    if (!s_go) return;
+    const int n_tiles = energy_blocks_of(a.d);
+    for (int t = 1; t <= n_rest; ++t) {
+        const float tau = ldexpf(1.f, -t);
+        float part[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int tile = bid; tile < n_tiles; tile += nblk) energy_tile<false>(a, tile, tau, S, part);
         float tot5[5];
         block_sum<5>(part, tot5);
         if (threadIdx.x == 0) {
-            const int base = trial_plane(t);
 #pragma unroll
-            for (int k = 0; k < 5; ++k) a.partials[(long)(base + k) * a.max_blocks + bid] = tot5[k];
-        }
-    }
-    if (LIN) return;
-    const int nb = nblk;
-    if (last_block(&a.sc->counter[0], (unsigned)nblk)) {
-        const DevConst &C = *a.cst;
-        for (int t = 0; t < n_tr; ++t) {
-            double s[5];
             for (int k = 0; k < 5; ++k)
-                s[k] = block_sum_partials(a.partials + (long)(trial_plane(t) + k) * a.max_blocks, nb);
-            if (threadIdx.x == 0) {
-                double *dst = a.sc->e_trial[trial + t];
-                for (int k = 0; k < 5; ++k) dst[k] = s[k];
-                dst[5] = (double)C.w_photo * s[0] + (double)C.w_grad * s[1] +
-                         (double)C.w_reg * ((double)C.w_smooth * s[2] + (double)C.w_epi * s[3] +
-                                            (double)C.w_mag * s[4]);
-            }
+                a.partials[(long)(PS_TRIAL + 5 * (t - 1) + k) * a.max_blocks + bid] = tot5[k];
         }
     }
 }
@@ -982,8 +1041,8 @@ __device__ void rhs_level_scalars(const LevelArgs &a) {
     const DevConst &C = *a.cst;
     const int n_lin_blocks = energy_blocks_of(a.d);
     double es[5];
-    for (int k = 0; k < 5; ++k)
-        es[k] = block_sum_partials(a.partials + (long)(PS_E + k) * a.max_blocks, n_lin_blocks);
+    const float *p0 = a.partials + (long)PS_E * a.max_blocks;
+    block_sum_planes<5>([&](int k) { return p0 + (long)k * a.max_blocks; }, n_lin_blocks, es);
     if (threadIdx.x == 0) {
         for (int k = 0; k < 5; ++k) a.sc->e_lin[k] = es[k];
         a.sc->e_lin[5] = (double)C.w_photo * es[0] + (double)C.w_grad * es[1] +
@@ -1898,13 +1957,28 @@ template <bool B>
 __global__ __launch_bounds__(SF_BLOCK) void k_accept(KArg<B> ka, int n_trials, int gn_iter,
                                                      int pcg_iters) {
     SF_BIND(ka);
+    __shared__ int s_k;
+    __shared__ double s_e[6];
     const int log_index = gn_iter >= 0 ? a.log_base + gn_iter : -1;
     const int nb_last = node_blocks(a.d);
     const DevScalars *sc = a.sc;
     const double e0 = sc->e_lin[5];
-    int kacc = -1;
-    for (int k = 0; k < n_trials; ++k)
-        if (sc->e_trial[k][5] <= e0) { kacc = k; break; }
+    if (threadIdx.x < 64) {
+        // the first trial with E_trial <= E, from the trial kernels' partials
+        double e[6];
+        trial_energy_wave(a, PS_E, energy_blocks_of(a.d), e);
+        int kacc = e[5] <= e0 ? 0 : -1;
+        for (int t = 1; t < n_trials && kacc < 0; ++t) {
+            trial_energy_wave(a, PS_TRIAL + 5 * (t - 1), rest_blocks_of(a.d), e);
+            if (e[5] <= e0) kacc = t;
+        }
+        if (threadIdx.x == 0) {
+            s_k = kacc;
+            for (int k = 0; k < 6; ++k) s_e[k] = e[k];
+        }
+    }
+    __syncthreads();
+    const int kacc = s_k;
     const float tau = kacc >= 0 ? ldexpf(1.f, -kacc) : 0.f;
     const long n = (long)bid * SF_BLOCK + threadIdx.x;
     if (kacc >= 0 && n < a.d.G) {
@@ -1916,27 +1990,34 @@ __global__ __launch_bounds__(SF_BLOCK) void k_accept(KArg<B> ka, int n_trials, i
         for (int q = 0; q < 6; ++q) dl[q] = dl[q] + tau * x[q];
         st6(delta, n, dl);
     }
-    if (bid == 0 && log_index >= 0) {
-        const float *rrp = a.partials +
-                           (long)(((pcg_iters & 1) ? PS_PCG1 : PS_PCG0) + 2) * a.max_blocks;
-        const double rr = block_sum_partials(rrp, nb_last);
+    if (bid == 0) {
+        double rr = 0.0;
+        if (log_index >= 0) {
+            const float *rrp = a.partials +
+                               (long)(((pcg_iters & 1) ? PS_PCG1 : PS_PCG0) + 2) * a.max_blocks;
+            rr = block_sum_partials(rrp, nb_last);
+        }
         if (threadIdx.x == 0) {
-            DevLog &Lg = a.log[log_index];
-            Lg.level = a.level;
-            Lg.gn_iter = gn_iter;
-            Lg.energy = e0;
-            Lg.e_photo = sc->e_lin[0];
-            Lg.e_grad = sc->e_lin[1];
-            Lg.e_smooth = sc->e_lin[2];
-            Lg.e_epi = sc->e_lin[3];
-            Lg.e_mag = sc->e_lin[4];
-            Lg.energy_after = kacc >= 0 ? sc->e_trial[kacc][5] : e0;
-            Lg.tau = tau;
-            Lg.pcg_iters = pcg_iters;
-            // an inactive last iteration left r unchanged
-            const bool same = !sc->hist[pcg_iters].active && pcg_iters >= 2;
-            Lg.pcg_res[pcg_iters - 1] = same ? Lg.pcg_res[pcg_iters - 2] : (float)sqrt(rr);
-            Lg.n_valid = sc->n_valid;
+            if (kacc >= 0)
+                for (int k = 0; k < 6; ++k) a.sc->e_trial[kacc][k] = s_e[k];
+            if (log_index >= 0) {
+                DevLog &Lg = a.log[log_index];
+                Lg.level = a.level;
+                Lg.gn_iter = gn_iter;
+                Lg.energy = e0;
+                Lg.e_photo = sc->e_lin[0];
+                Lg.e_grad = sc->e_lin[1];
+                Lg.e_smooth = sc->e_lin[2];
+                Lg.e_epi = sc->e_lin[3];
+                Lg.e_mag = sc->e_lin[4];
+                Lg.energy_after = kacc >= 0 ? s_e[5] : e0;
+                Lg.tau = tau;
+                Lg.pcg_iters = pcg_iters;
+                // an inactive last iteration left r unchanged
+                const bool same = !sc->hist[pcg_iters].active && pcg_iters >= 2;
+                Lg.pcg_res[pcg_iters - 1] = same ? Lg.pcg_res[pcg_iters - 2] : (float)sqrt(rr);
+                Lg.n_valid = sc->n_valid;
+            }
         }
     }
 }
@@ -2049,8 +2130,10 @@ __global__ __launch_bounds__(SF_BLOCK) void k_prolong(KArg<B> ka) {
     int use_cnn = 0;
     if (coarsest && a.learned) {
         const int nb = energy_blocks_of(a.d);
-        const double ec = block_sum_partials(a.partials + (long)PS_E * a.max_blocks, nb);
-        const double ez = block_sum_partials(a.partials + (long)(PS_E + 1) * a.max_blocks, nb);
+        double e2[2];
+        const float *p0 = a.partials + (long)PS_E * a.max_blocks;
+        block_sum_planes<2>([&](int k) { return p0 + (long)k * a.max_blocks; }, nb, e2);
+        const double ec = e2[0], ez = e2[1];
         use_cnn = ec < ez ? 1 : 0;
         if (bid == 0 && threadIdx.x == 0) {
             a.sc->e_init[0] = ec;
@@ -2392,11 +2475,16 @@ void launch_level_init(hipStream_t st, const Launch &L) {
 }
 
 void launch_linearize(hipStream_t st, const Launch &L) {
-    go(st, L, en_blocks, k_energy<true, true>, k_energy<false, true>, SF_BLOCK, 0, 0, 1);
+    go(st, L, en_blocks, k_energy<true, true>, k_energy<false, true>, SF_BLOCK, 0, 0.f);
 }
 
-void launch_trials(hipStream_t st, const Launch &L, int first, int count) {
-    go(st, L, en_blocks, k_energy<true, false>, k_energy<false, false>, SF_BLOCK, 0, first, count);
+void launch_trial0(hipStream_t st, const Launch &L) {
+    go(st, L, en_blocks, k_energy<true, false>, k_energy<false, false>, SF_BLOCK, 0, 1.f);
+}
+
+void launch_trials_rest(hipStream_t st, const Launch &L, int n_rest) {
+    auto nb = [](const LevelArgs &a) { return rest_blocks_of(a.d); };
+    go(st, L, nb, k_trials_rest<true>, k_trials_rest<false>, SF_BLOCK, 0, n_rest);
 }
 
 void launch_rhs(hipStream_t st, const Launch &L, const TileCfg &t) {
