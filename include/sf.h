@@ -305,7 +305,13 @@ sf_status sf_debug_set_images(sf_ctx *ctx, const float *I_left_t,
  *  SF_STAGE_GN           one full Gauss-Newton step with step control
  *  SF_STAGE_FINISH       store base + delta as the level's total
  *  SF_STAGE_MASKS        masks and smoothness weights at the current base
- *                        (the level set-up without the prolongation)    */
+ *                        (the level set-up without the prolongation)
+ *  SF_STAGE_STEP         the step control alone (the library's reading;
+ *                        the paper states none): delta +=
+ *                        tau dx with dx = the current SF_DBG_DX and tau the
+ *                        first of 1, 1/2, ..., 2^-max_backtracks whose
+ *                        energy does not exceed E at the last
+ *                        SF_STAGE_LINEARIZE (delta unchanged if none)   */
 enum {
     SF_STAGE_LEVEL_INIT = 0,
     SF_STAGE_LINEARIZE = 1,
@@ -313,7 +319,8 @@ enum {
     SF_STAGE_PCG = 3,
     SF_STAGE_GN = 4,
     SF_STAGE_FINISH = 5,
-    SF_STAGE_MASKS = 6
+    SF_STAGE_MASKS = 6,
+    SF_STAGE_STEP = 7
 };
 sf_status sf_debug_run(sf_ctx *ctx, int stage, int level);
 

@@ -491,15 +491,20 @@ void enqueue_pcg(const Plan &P, hipStream_t st, int l, int gn) {
     launch_pcg_last(st, L, t, n, gn, 0, sm);
 }
 
+// Step control with the PCG solution in x: tau = 1 alone (usually
+// accepted), then the shorter steps together, then the update of delta.
+void enqueue_step(const Plan &P, hipStream_t st, int l, int g) {
+    const Launch L = slot(P, l);
+    const int T = P.prm.max_backtracks + 1;
+    launch_trial0(st, L);
+    if (T > 1) launch_trials_rest(st, L, T - 1);
+    launch_accept(st, L, T, g, P.prm.pcg_iters);
+}
+
 void enqueue_gn(const Plan &P, hipStream_t st, int l, int g, bool log) {
     enqueue_linearize(P, st, l);
     enqueue_pcg(P, st, l, log ? g : -1);
-    const Launch L = slot(P, l);
-    const int T = P.prm.max_backtracks + 1;
-    // tau = 1 alone (usually accepted), then the shorter steps together
-    launch_trial0(st, L);
-    if (T > 1) launch_trials_rest(st, L, T - 1);
-    launch_accept(st, L, T, log ? g : -1, P.prm.pcg_iters);
+    enqueue_step(P, st, l, log ? g : -1);
 }
 
 // The network on the level-4 images and its candidate for the coarsest
@@ -1121,6 +1126,7 @@ sf_status sf_debug_run(sf_ctx *c, int stage, int level) {
         case SF_STAGE_GN: enqueue_gn(P, st, level, 0, false); break;
         case SF_STAGE_FINISH: launch_finish_level(st, L); break;
         case SF_STAGE_MASKS: launch_level_masks(st, L); break;
+        case SF_STAGE_STEP: enqueue_step(P, st, level, -1); break;
         default: return SF_ERR_INVALID_ARG;
     }
     HIP_TRY(hipGetLastError());

@@ -166,6 +166,47 @@ def test_linearize_apply_pcg_parity(level, stride, apply):
         g.close()
 
 
+@pytest.mark.parametrize("apply", [0, 2])
+def test_step_control_parity(apply):
+    """Step control alone (SF_STAGE_STEP) against the oracle's rule: delta
+    moves by tau dx for the first tau in 1, 1/2, ..., 1/16 whose energy does
+    not exceed E(delta), or stays.  dx is the oracle's Gauss-Newton step
+    scaled so that tau = 1, a shorter step and no step are each chosen;
+    cases whose trial energies lie within 1e-4 of E(delta) (where float32
+    and float64 may decide differently) are not counted."""
+    g, imgs, calib, p = _stage_case(W=104, H=78, grid_stride=4, apply_mode=apply,
+                                    max_backtracks=4)
+    level = 1
+    try:
+        g.run(g.sf.SF_STAGE_LEVEL_INIT, level)
+        ls, _ = _oracle_level(imgs, calib, p, level)
+        delta = np.random.default_rng(4).normal(scale=0.3, size=(6, ls.grid.G))
+        g.write(g.sf.SF_DBG_DELTA, level, delta.astype(np.float32))
+        delta = g.read(g.sf.SF_DBG_DELTA, level).reshape(6, -1).astype(np.float64)
+        grad, Hm = O.linearize(ls, delta, p)
+        step = O.pcg(Hm, -grad, 40).reshape(6, -1)
+        e0 = O.energy(ls, delta, p)["total"]
+        taus = [2.0 ** -k for k in range(5)]
+        seen = set()
+        for scale in (1.0, 12.0, 40.0, -1.0):
+            dx = (scale * step).astype(np.float32)
+            g.write(g.sf.SF_DBG_DELTA, level, delta.astype(np.float32))
+            g.run(g.sf.SF_STAGE_LINEARIZE, level)
+            g.write(g.sf.SF_DBG_DX, level, dx)
+            g.run(g.sf.SF_STAGE_STEP, level)
+            got = g.read(g.sf.SF_DBG_DELTA, level).reshape(6, -1).astype(np.float64)
+            et = [O.energy(ls, delta + t * dx.astype(np.float64), p)["total"] for t in taus]
+            if min(abs(e - e0) for e in et) < 1e-4 * abs(e0):
+                continue
+            tau = next((t for t, e in zip(taus, et) if e <= e0), 0.0)
+            want = delta + tau * dx.astype(np.float64)
+            np.testing.assert_allclose(got, want, rtol=0, atol=1e-5 * (1 + np.abs(want).max()))
+            seen.add("full" if tau == 1.0 else ("none" if tau == 0.0 else "short"))
+        assert seen == {"full", "short", "none"}, seen
+    finally:
+        g.close()
+
+
 def _solve_parity(imgs, calib, prm, e_tol=1e-4, f_tol=0.02):
     p = oracle_params(**prm)
     rec = []
