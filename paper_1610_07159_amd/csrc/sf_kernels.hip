@@ -202,6 +202,32 @@ __device__ void block_sum(float (&v)[K], float (&out)[K]) {
 
 // Sum in double of n partials by the whole block; result valid in every
 // thread.  Fixed order, so bitwise reproducible.
+// acc[k] += get(k, i) for i = first, first + step, ... < n, in that order,
+// with the loads of U indices issued together (an index past n reads entry
+// 0 and adds +0), so a long stride loop costs one memory round trip per U
+// steps instead of one per step.
+template <int K, int U, class Get>
+__device__ __forceinline__ void strided_sums(int first, int step, int n, Get get,
+                                             double (&acc)[K]) {
+    for (int i0 = first; i0 < n; i0 += U * step) {
+        float v[U][K];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * step;
+            const bool ok = i < n;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const float t = get(k, ok ? i : 0);
+                v[u][k] = ok ? t : 0.f;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[k] += (double)v[u][k];
+    }
+}
+
 // K planes at once (plane(k) gives plane k): every load is issued before
 // the first barrier, and each plane is summed in the same order as by
 // block_sum_partials.
@@ -211,9 +237,7 @@ __device__ void block_sum_planes(PlaneFn plane, int n, double (&out)[K]) {
     double acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
-#pragma unroll
-        for (int k = 0; k < K; ++k) acc[k] += (double)plane(k)[i];
+    strided_sums<K, 8>(threadIdx.x, blockDim.x, n, [&](int k, int i) { return plane(k)[i]; }, acc);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -232,8 +256,9 @@ __device__ void block_sum_planes(PlaneFn plane, int n, double (&out)[K]) {
 
 __device__ double block_sum_partials(const float *part, int n) {
     __shared__ double red[16];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += (double)part[i];
+    double a1[1] = {0.0};
+    strided_sums<1, 8>(threadIdx.x, blockDim.x, n, [&](int, int i) { return part[i]; }, a1);
+    double acc = a1[0];
     acc = wave_sum_d(acc);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if (lane == 0) red[wv] = acc;
@@ -726,9 +751,8 @@ __device__ void trial_energy_wave(const LevelArgs &a, int base, int n, double (&
     const int lane = threadIdx.x & 63;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const float *p0 = a.partials + (long)base * a.max_blocks;
-    for (int b = lane; b < n; b += 64)
-#pragma unroll
-        for (int k = 0; k < 5; ++k) acc[k] += (double)p0[(long)k * a.max_blocks + b];
+    strided_sums<5, 8>(lane, 64, n, [&](int k, int b) { return p0[(long)k * a.max_blocks + b]; },
+                       acc);
 #pragma unroll
     for (int k = 0; k < 5; ++k) e[k] = wave_sum_d(acc[k]);
     const DevConst &C = *a.cst;
@@ -882,14 +906,29 @@ __device__ __forceinline__ void rec_store(float *p, const float (&v)[K]) {
                             4 * m + 2 < K ? v[4 * m + 2] : 0.f, 4 * m + 3 < K ? v[4 * m + 3] : 0.f);
 }
 
+// (unrolled so that the loads of several pixels are in flight together:
+// one memory round trip per unrolled step instead of per pixel)
 template <int K, class Fn>
 __device__ __forceinline__ void pixels_to_lds(const TileGeom &g, const TileLds &L, Fn fn) {
     const int n = g.RX * g.RY;
-    for (int u = threadIdx.x; u < n; u += blockDim.x) {
-        const int rx = u % g.RX, ry = u / g.RX;
-        float v[K];
-        fn(g.X0 + rx, g.Y0 + ry, rx, ry, v);
-        rec_store<K>(L.vals + (size_t)ry * L.pitch + rx * rec_pad(K), v);
+    constexpr int U = K <= 12 ? 4 : 2;
+    for (int u0 = threadIdx.x; u0 < n; u0 += U * blockDim.x) {
+        float v[U][K];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            // past the region: reload its first pixel, not stored
+            const int u = u0 + q * blockDim.x < n ? u0 + q * blockDim.x : 0;
+            const int rx = u % g.RX, ry = u / g.RX;
+            fn(g.X0 + rx, g.Y0 + ry, rx, ry, v[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int u = u0 + q * blockDim.x;
+            if (u < n) {
+                const int rx = u % g.RX, ry = u / g.RX;
+                rec_store<K>(L.vals + (size_t)ry * L.pitch + rx * rec_pad(K), v[q]);
+            }
+        }
     }
 }
 
@@ -904,12 +943,14 @@ __device__ __forceinline__ float bweight(const float4 b, int i, int G) {
 // sub == 0 of each node group).  A node's support is at most 2S pixels wide
 // and high, and tpn >= 2S, so every thread sums at most one support row,
 // with the columns unrolled; the tpn row sums are combined with fixed-order
-// lane shuffles.
-template <int K, int S>
+// lane shuffles.  TPN (= t.tpn) is a compile-time constant so that the
+// shuffle sequence and the thread split fold to straight-line code.
+template <int K, int S, int TPN>
 __device__ __forceinline__ void lds_to_nodes(const LevelArgs &a, const TileCfg &t,
                                              const TileGeom &g, const TileLds &L,
                                              unsigned pow2, float (&acc)[K]) {
-    const int nl = threadIdx.x / t.tpn, sub = threadIdx.x % t.tpn;
+    (void)t;
+    const int nl = threadIdx.x / TPN, sub = threadIdx.x % TPN;
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.f;
     if (nl < g.txa * g.tya) {
@@ -937,7 +978,7 @@ __device__ __forceinline__ void lds_to_nodes(const LevelArgs &a, const TileCfg &
         }
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = group_sum<float>(acc[k], t.tpn);
+    for (int k = 0; k < K; ++k) acc[k] = group_sum<float>(acc[k], TPN);
 }
 
 // Regulariser pieces of node (i, j).  The Gauss-Newton matrix of these
@@ -1062,7 +1103,8 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(KArg<B> ka, TileCfg t
     const TileGeom g = tile_geom(a, t, bid);
     const TileLds L = tile_lds(lds, t, S, 12);
     const int tid = threadIdx.x;
-    const int nl = tid / t.tpn, sub = tid % t.tpn;
+    constexpr int TPN = TileTraits<S>::TPN;
+    const int nl = tid / TPN, sub = tid % TPN;
     const bool mine = sub == 0 && nl < g.txa * g.tya;
     const int i = g.i0 + (nl % max(g.txa, 1)), j = g.j0 + nl / max(g.txa, 1);
     const long n = (long)j * d.Gx + i;
@@ -1080,7 +1122,7 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(KArg<B> ka, TileCfg t
     });
     __syncthreads();
     float acc[12];
-    lds_to_nodes<12, S>(a, t, g, L, 0xFC0u, acc);
+    lds_to_nodes<12, S, TileTraits<S>::TPN>(a, t, g, L, 0xFC0u, acc);
     if (mine) {
         float gd[6], dd[6];
 #pragma unroll
@@ -1136,7 +1178,8 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, Til
     const LevelDims &d = a.d;
     const TileGeom g = tile_geom(a, t, bid);
     const TileLds L = tile_lds(lds, t, S, 27);
-    const int nl = threadIdx.x / t.tpn, sub = threadIdx.x % t.tpn;
+    constexpr int TPN = BlkShape<S>::TPN;
+    const int nl = threadIdx.x / TPN, sub = threadIdx.x % TPN;
     const bool valid = nl < g.txa * g.tya;
     const bool mine = valid && sub == 0;
     const int i = g.i0 + nl % max(g.txa, 1), j = g.j0 + nl / max(g.txa, 1);
@@ -1203,7 +1246,7 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, Til
         }
     }
 #pragma unroll
-    for (int k = 0; k < 6; ++k) gs[k] = group_sum<float>(gs[k], t.tpn);
+    for (int k = 0; k < 6; ++k) gs[k] = group_sum<float>(gs[k], TPN);
     float *dst = a.blk + n * SF_BLK_STRIDE;
     float sd[6];
 #pragma unroll
@@ -1213,13 +1256,13 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, Til
 #pragma unroll
         for (int k = 0; k < 21; ++k) {
             const float src = (kb == 0 || kb == 2) ? c0[k] : ((kb == 4) ? cm[k] : cp[k]);
-            o[k] = group_sum<float>(rw * src, t.tpn);
+            o[k] = group_sum<float>(rw * src, TPN);
         }
         if (kb == 0) {
 #pragma unroll
             for (int q = 0; q < 6; ++q) sd[q] = o[gram_index(q, q)];
         }
-        if (valid && sub == kb % t.tpn) rec_store<21>(dst + kb * SF_GRAM_STRIDE, o);
+        if (valid && sub == kb % TPN) rec_store<21>(dst + kb * SF_GRAM_STRIDE, o);
     }
     if (mine) nd.finish<S>(a, i, j, n, gs, sd);
 }
@@ -1249,11 +1292,8 @@ __device__ __forceinline__ void load_pcg_partials(const LevelArgs &a, int i, int
                                                   double (&acc)[3]) {
     const float *prev = a.partials + (long)(((i - 1) & 1) ? PS_PCG1 : PS_PCG0) * a.max_blocks;
     acc[0] = acc[1] = acc[2] = 0.0;
-    for (int b = threadIdx.x & 63; b < nb_prev; b += 64) {
-        acc[0] += (double)prev[b];
-        acc[1] += (double)prev[a.max_blocks + b];
-        acc[2] += (double)prev[2 * a.max_blocks + b];
-    }
+    strided_sums<3, 8>(threadIdx.x & 63, 64, nb_prev,
+                       [&](int k, int b) { return prev[(long)k * a.max_blocks + b]; }, acc);
 }
 
 // The scalars of iteration i-1 from the lane sums: every wavefront reduces
@@ -1355,7 +1395,8 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     }
     // owned node of this thread's node group
     const int HX = t.tx + 2;
-    const int nl = tid / t.tpn, sub = tid % t.tpn;
+    constexpr int TPN = TileTraits<S, V>::TPN;
+    const int nl = tid / TPN, sub = tid % TPN;
     const bool mine = sub == 0 && nl < g.txa * g.tya;
     const int ti = nl % max(g.txa, 1), tj = nl / max(g.txa, 1);
     const int i_n = g.i0 + ti, j_n = g.j0 + tj;
@@ -1538,7 +1579,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     if (B) load_own();
     float acc[6];
     if constexpr (S > 0) {
-        lds_to_nodes<6, S>(a, t, g, L, 0u, acc);
+        lds_to_nodes<6, S, TileTraits<S, V>::TPN>(a, t, g, L, 0u, acc);
     } else {
         // the node's block products, summed over its threads in fixed order
 #pragma unroll
