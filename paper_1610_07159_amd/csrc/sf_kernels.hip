@@ -179,7 +179,9 @@ __device__ __forceinline__ double wave_sum_d(double v) { return group_sum<double
 
 // Sums K per-thread values over the (256-thread) block; the result is valid
 // in thread 0.  Fixed order, so bitwise reproducible.
-template <int K>
+// REUSE: a second barrier lets the caller reuse the reduction buffer (a
+// later call); at the end of a kernel it is not needed.
+template <int K, bool REUSE = true>
 __device__ void block_sum(float (&v)[K], float (&out)[K]) {
     __shared__ float red[16][K];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -197,7 +199,7 @@ __device__ void block_sum(float (&v)[K], float (&out)[K]) {
             out[k] = acc;
         }
     }
-    __syncthreads();
+    if (REUSE) __syncthreads();
 }
 
 // Sum in double of n partials by the whole block; result valid in every
@@ -737,7 +739,7 @@ __global__ __launch_bounds__(SF_BLOCK) void k_energy(KArg<B> ka, float tau) {
     float part[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     energy_tile<LIN>(a, bid, LIN ? 0.f : tau, S, part);
     float tot5[5];
-    block_sum<5>(part, tot5);
+    block_sum<5, false>(part, tot5);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) a.partials[(long)(PS_E + k) * a.max_blocks + bid] = tot5[k];
@@ -1606,19 +1608,21 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
 #pragma unroll
         for (int q = 0; q < 6; ++q) { jp0 += rg[4 + q] * uv[q]; jp1 += rg[10 + q] * uv[q]; }
         float sm[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        // neighbours outside the grid have coefficient 0 and no halo
+        // record: they read the node's own record (adding exactly 0), so
+        // the four loads issue together
+        float un[4][6];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             int di, dj;
             nb_offset(k, di, dj);
-            // neighbours outside the grid have coefficient 0; their halo
-            // record is never written, so it is not read
-            if (rg[k] != 0.f) {
-                float un[6];
-                rec_load<6>(L.halo + (size_t)((tj + 1 + dj) * HX + ti + 1 + di) * 8, un);
-#pragma unroll
-                for (int q = 0; q < 6; ++q) sm[q] += rg[k] * (uv[q] - un[q]);
-            }
+            if (rg[k] == 0.f) di = dj = 0;
+            rec_load<6>(L.halo + (size_t)((tj + 1 + dj) * HX + ti + 1 + di) * 8, un[k]);
         }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) sm[q] += rg[k] * (uv[q] - un[k][q]);
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             w6[q] = acc[q] + wf[q] * sm[q] + rg[4 + q] * jp0 + rg[10 + q] * jp1 + cm[q] * uv[q];
@@ -1629,7 +1633,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
         prt[2] = L.ownd[t.tx * t.ty + o];
     }
     float tot3[3];
-    block_sum<3>(prt, tot3);
+    block_sum<3, false>(prt, tot3);
 
     // ---- stores ---------------------------------------------------------------
     if (hown && !FIRST) {
@@ -1717,7 +1721,7 @@ __global__ __launch_bounds__(SF_BLOCK) void k_pcg_last(KArg<B> ka, TileCfg t, in
         st6(Rc, n, rn);
     }
     float tot1[1];
-    block_sum<1>(prt, tot1);
+    block_sum<1, false>(prt, tot1);
     if (threadIdx.x == 0) {
         a.partials[(long)(((i & 1) ? PS_PCG1 : PS_PCG0) + 2) * a.max_blocks + bid] = tot1[0];
         if (bid == 0) record_decision(a, i, log_index, rec, rr_prev);
@@ -1777,7 +1781,8 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_small(KArg<B> ka, int n_it, in
     const LevelDims &d = a.d;
     if (d.G > SF_SMALL_G) return;  // the host never launches such a level
     const int log_index = gn >= 0 ? a.log_base + gn : -1;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int sub = lane % 3;
     const int n = wv * SMALL_NPW + lane / 3;
     const bool valid = lane < 3 * SMALL_NPW && n < d.G;
@@ -1847,36 +1852,20 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_small(KArg<B> ka, int n_it, in
         nbr[k] = valid && cnb[k] != 0.f ? (j_n + dj) * d.Gx + i_n + di : (valid ? n : 0);
     }
 
-    double gsum = 0.0, dsum = 0.0, rsum = 0.0;  // inner products of iteration i-1
-    double hg = 0.0;                            // gamma of iteration i-2
-    float ha = 0.f;                             // alpha of iteration i-2
+    // The PCG scalars are reduced and decided by wavefront 0 at the end of
+    // each pass and handed to every thread through LDS: one more barrier,
+    // but the double-precision decision runs once instead of in every
+    // wavefront.
+    __shared__ float s_dec[2];
+    __shared__ int s_act;
+    double rsum = 0.0;         // (wavefront 0) r.r of the last pass
+    double hg = 0.0;           // (wavefront 0) gamma of the previous pass
+    float ha = 0.f;            // (wavefront 0) alpha of the previous pass
+    float al = 0.f, be = 0.f;  // scalars of iteration i-1
     int act = 1;
     for (int i = 0; i <= n_it; ++i) {
         if (i > 0) {
-            // scalars of iteration i-1 (every thread computes the same)
-            double b = 0.0, pq = dsum;
-            int ok = act;
-            if (ok && i - 1 > 0) {
-                b = gsum / hg;
-                pq = dsum - b * gsum / (double)ha;
-            }
-            ok = ok && gsum > 1e-30 && pq > 0.0 && isfinite(pq);
-            const float al = uniform_f(ok ? (float)(gsum / pq) : 0.f);
-            const float be = uniform_f(ok ? (float)b : 0.f);
-            if (threadIdx.x == 0) {
-                // an inactive iteration leaves every later one inactive with
-                // the same sums (the multi-kernel form carries its partials)
-                for (int m = i; m <= (ok ? i : n_it); ++m) {
-                    PcgHist o;
-                    o.gamma = gsum; o.alpha = al; o.beta = be; o.active = ok; o.pad = 0;
-                    shist[m] = o;
-                    if (m >= 2) sres[m - 2] = rsum;
-                }
-            }
-            hg = gsum;
-            ha = al;
-            act = ok;
-            if (!ok) break;
+            if (!act) break;
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 s2[j] = i > 1 ? w2[j] + be * s2[j] : w2[j];
@@ -1885,10 +1874,7 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_small(KArg<B> ka, int n_it, in
                 r2[j] = r2[j] - al * s2[j];
                 u2[j] = r2[j] / D2[j];
             }
-            if (i == n_it) {
-                rsum = 0.0;  // ||r_n||^2 below
-                break;
-            }
+            if (i == n_it) break;  // ||r_n||^2 below
         }
         // u_i into LDS; w_i = H u_i
         if (valid) *reinterpret_cast<float2 *>(su + n * 8 + c0) = make_float2(u2[0], u2[1]);
@@ -1960,15 +1946,40 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_small(KArg<B> ka, int n_it, in
         const float t0 = wave_sum(ru), t1 = wave_sum(wu), t2 = wave_sum(rr);
         if (lane == 0) { red[wv][0] = t0; red[wv][1] = t1; red[wv][2] = t2; }
         __syncthreads();
-        {
+        if (wv == 0) {
+            // scalars of iteration i from this pass's sums
             const int rw = lane & 15;
-            const double g0 = rw < nw ? (double)red[rw][0] : 0.0;
-            const double g1 = rw < nw ? (double)red[rw][1] : 0.0;
-            const double g2 = rw < nw ? (double)red[rw][2] : 0.0;
-            gsum = uniform_d(group_sum<double>(g0, 16));
-            dsum = uniform_d(group_sum<double>(g1, 16));
-            rsum = uniform_d(group_sum<double>(g2, 16));
+            const double gsum = uniform_d(group_sum<double>(rw < nw ? (double)red[rw][0] : 0.0, 16));
+            const double dsum = uniform_d(group_sum<double>(rw < nw ? (double)red[rw][1] : 0.0, 16));
+            rsum = uniform_d(group_sum<double>(rw < nw ? (double)red[rw][2] : 0.0, 16));
+            double b = 0.0, pq = dsum;
+            if (i > 0) {
+                b = gsum / hg;
+                pq = dsum - b * gsum / (double)ha;
+            }
+            const int ok = gsum > 1e-30 && pq > 0.0 && isfinite(pq);
+            const float aln = ok ? (float)(gsum / pq) : 0.f;
+            const float ben = ok ? (float)b : 0.f;
+            if (lane == 0) {
+                // an inactive iteration leaves every later one inactive with
+                // the same sums (the multi-kernel form carries its partials)
+                for (int m = i + 1; m <= (ok ? i + 1 : n_it); ++m) {
+                    PcgHist o;
+                    o.gamma = gsum; o.alpha = aln; o.beta = ben; o.active = ok; o.pad = 0;
+                    shist[m] = o;
+                    if (m >= 2) sres[m - 2] = rsum;
+                }
+                s_dec[0] = aln;
+                s_dec[1] = ben;
+                s_act = ok;
+            }
+            hg = gsum;
+            ha = aln;
         }
+        __syncthreads();
+        al = uniform_f(s_dec[0]);
+        be = uniform_f(s_dec[1]);
+        act = __builtin_amdgcn_readfirstlane(s_act);
     }
     if (act) {
         // ||r_n||^2 for the step control's log
