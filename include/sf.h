@@ -70,7 +70,9 @@ typedef struct {
  *                  the process and, if the environment variable
  *                  SF_TUNE_CACHE names a file, in that file); 2, 3 = the
  *                  alternative shapes (strides 2, 4, 8; others use the
- *                  default); ignored with apply_mode 1
+ *                  default); with apply_mode 1, 2 the same choice among
+ *                  the node-block tiles (8 x 8 nodes; 16 x 8; 8 x 4;
+ *                  4 = 4 x 4, which the matrix-free mode treats as 0)
  *  apply_mode      how the PCG kernels form H u (Sec. 5.2): 0 = matrix-free
  *                  from the per-pixel Gauss-Newton records (the transpose
  *                  of the bilinear interpolation, Eq. (7), applied on every

@@ -119,7 +119,7 @@ sf_status check_params(const sf_params *p) {
     if (p->init_mode != 0 && p->init_mode != 1) return SF_ERR_INVALID_ARG;
     if (p->init_mode == 1 && p->levels <= SF_CNN_INPUT_LEVEL) return SF_ERR_INVALID_ARG;
     if (p->exec_mode != 0 && p->exec_mode != 1) return SF_ERR_INVALID_ARG;
-    if (p->tile_mode < 0 || p->tile_mode > 3) return SF_ERR_INVALID_ARG;
+    if (p->tile_mode < 0 || p->tile_mode > 4) return SF_ERR_INVALID_ARG;
     if (p->apply_mode < 0 || p->apply_mode > 2) return SF_ERR_INVALID_ARG;
     const float w[] = {p->w_reg, p->w_photo, p->w_grad, p->w_epi, p->w_smooth,
                        p->w_mag, p->w_s, p->w_m, p->w_d, p->st_gamma};
@@ -244,9 +244,8 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
     if (nb && blk_tile_lds_bytes(st) > 64 * 1024) return SF_ERR_INVALID_ARG;
     const int forced = prm.tile_mode >= 2 ? prm.tile_mode - 1 : 0;
     for (int l = 0; l < SF_MAX_LEVELS; ++l)
-        P.ptile[l] = nb ? pick_nb_tile() : pick_pcg_tile(st, forced);
-    // the node-block PCG kernel has a single shape
-    P.tuned = nb || prm.tile_mode != 1;
+        P.ptile[l] = nb ? pick_nb_tile(forced) : pick_pcg_tile(st, forced);
+    P.tuned = prm.tile_mode != 1;
     P.fr.resize(P.nf);
     P.Lmax = 0;
     // sizes, then one allocation carved in 256-byte aligned pieces
@@ -265,8 +264,10 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
                 mb = mb > nt ? mb : nt;
             }
             mb = mb > node_tile_blocks(d, P.tile) ? mb : node_tile_blocks(d, P.tile);
-            const int nbt = node_tile_blocks(d, pick_nb_tile());
-            mb = mb > nbt ? mb : nbt;
+            for (int v = 0; v < SF_NB_VARIANTS; ++v) {
+                const int nbt = node_tile_blocks(d, pick_nb_tile(v));
+                mb = mb > nbt ? mb : nbt;
+            }
             const int gb = (d.G + SF_BLOCK - 1) / SF_BLOCK;
             mb = mb > gb ? mb : gb;
         }
@@ -558,7 +559,7 @@ sf_status ensure_graph(Plan &P, hipStream_t cap) {
 // ---- PCG tile autotuner --------------------------------------------------------
 //
 // Per level slot, every candidate shape of the PCG iteration kernel is timed
-// (forced active, HIP events, after two warm-up launches) on the plan's own
+// (forced active, as graph replays timed with HIP events) on the plan's own
 // buffers before the first solve, and the fastest is kept.  Choices are
 // cached per (device architecture, stride, sizes of the slot's frames) in
 // the process and, if SF_TUNE_CACHE names a file, in that file (one
@@ -574,7 +575,8 @@ std::string tune_key(const Plan &P, int l, int device) {
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
     for (char &ch : arch)
         if (ch == ' ' || ch == ':') ch = '_';
-    std::string k = arch + "/s" + std::to_string(P.prm.grid_stride) + "/";
+    std::string k = arch + "/s" + std::to_string(P.prm.grid_stride) +
+                    (P.prm.apply_mode >= 1 ? "/nb/" : "/");
     for (const LevelArgs &a : P.host[l]) k += std::to_string(a.d.W) + "x" + std::to_string(a.d.H) + ",";
     return k;
 }
@@ -604,7 +606,9 @@ void tune_cache_store(const std::string &key, int v) {
 
 sf_status autotune(sf_ctx *c, Plan &P) {
     const int st = P.prm.grid_stride;
-    const int nv = tile_variants(st);
+    const bool nb = P.prm.apply_mode >= 1;
+    const int nv = nb ? SF_NB_VARIANTS : tile_variants(st);
+    auto pick = [&](int v) { return nb ? pick_nb_tile(v) : pick_pcg_tile(st, v); };
     hipStream_t s = c->stream;
     std::lock_guard<std::mutex> lock(g_tune_mu);
     tune_cache_load();
@@ -616,30 +620,51 @@ sf_status autotune(sf_ctx *c, Plan &P) {
         const std::string key = tune_key(P, l, c->device);
         auto it = g_tune.find(key);
         if (it != g_tune.end() && it->second >= 0 && it->second < nv) {
-            P.ptile[l] = pick_pcg_tile(st, it->second);
+            P.ptile[l] = pick(it->second);
             continue;
         }
         const Launch L = slot(P, l);
-        int best = 0;
-        float best_ms = 1e30f;
+        // Each candidate's forced iterations are captured into a graph and
+        // timed as graph replays (as the solve runs them; direct launches
+        // would time the host's launch rate), in three rounds over the
+        // candidates keeping each one's best, so that clock ramp-up and
+        // noise do not favour a position.
+        const int reps = 20;
+        float best_v[SF_NB_VARIANTS > 3 ? SF_NB_VARIANTS : 3];
+        hipGraph_t gv[SF_NB_VARIANTS > 3 ? SF_NB_VARIANTS : 3] = {};
+        hipGraphExec_t ev[SF_NB_VARIANTS > 3 ? SF_NB_VARIANTS : 3] = {};
+        for (int v = 0; v < nv; ++v) best_v[v] = 1e30f;
         for (int v = 0; v < nv && rc == SF_OK; ++v) {
-            const TileCfg t = pick_pcg_tile(st, v);
-            const int reps = 10;
-            for (int i = 0; i < 2; ++i) launch_pcg_iter(s, L, t, 2 + (i & 1), -1, 1);
-            if (hipEventRecord(e0, s) != hipSuccess) rc = SF_ERR_HIP;
-            for (int i = 0; i < reps && rc == SF_OK; ++i) launch_pcg_iter(s, L, t, 2 + (i & 1), -1, 1);
-            float ms = 0.f;
-            if (rc == SF_OK && (hipEventRecord(e1, s) != hipSuccess ||
-                                hipEventSynchronize(e1) != hipSuccess ||
-                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            const TileCfg t = pick(v);
+            if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
                 rc = SF_ERR_HIP;
-            if (rc == SF_OK && ms < best_ms) {
-                best_ms = ms;
-                best = v;
+                break;
+            }
+            for (int i = 0; i < reps; ++i) launch_pcg_iter(c->cap_stream, L, t, 2 + (i & 1), -1, 1);
+            if (hipStreamEndCapture(c->cap_stream, &gv[v]) != hipSuccess || !gv[v] ||
+                hipGraphInstantiate(&ev[v], gv[v], nullptr, nullptr, 0) != hipSuccess)
+                rc = SF_ERR_HIP;
+        }
+        for (int round = 0; round < 4 && rc == SF_OK; ++round) {
+            for (int v = 0; v < nv && rc == SF_OK; ++v) {
+                float ms = 0.f;
+                if (hipGraphLaunch(ev[v], s) != hipSuccess || hipEventRecord(e0, s) != hipSuccess ||
+                    hipGraphLaunch(ev[v], s) != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+                    hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                    rc = SF_ERR_HIP;
+                if (rc == SF_OK && ms < best_v[v]) best_v[v] = ms;
             }
         }
+        for (int v = 0; v < nv; ++v) {
+            if (ev[v]) (void)hipGraphExecDestroy(ev[v]);
+            if (gv[v]) (void)hipGraphDestroy(gv[v]);
+        }
+        int best = 0;
+        for (int v = 1; v < nv; ++v)
+            if (best_v[v] < best_v[best]) best = v;
         if (rc == SF_OK) {
-            P.ptile[l] = pick_pcg_tile(st, best);
+            P.ptile[l] = pick(best);
             tune_cache_store(key, best);
         }
     }

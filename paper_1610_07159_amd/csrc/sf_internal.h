@@ -229,9 +229,12 @@ TileCfg pick_tile(int s);
 // PCG tile shapes: tile_variants(s) shapes per stride, variant 0 = pick_tile
 int tile_variants(int s);
 TileCfg pick_pcg_tile(int s, int v);
-// PCG tile of the node-block apply mode (any stride; v = SF_TILE_NB)
+// PCG tiles of the node-block apply modes (any stride): SF_NB_VARIANTS
+// shapes, 8 x 8 (default), 16 x 8, 8 x 4 and 4 x 4 nodes, 4 threads per
+// node; TileCfg.v = SF_TILE_NB + variant
 #define SF_TILE_NB 3
-TileCfg pick_nb_tile();
+#define SF_NB_VARIANTS 4
+TileCfg pick_nb_tile(int v = 0);
 // block-assembly tile per stride and its LDS bytes
 TileCfg pick_blk_tile(int s);
 size_t blk_tile_lds_bytes(int s);

@@ -42,6 +42,9 @@ template <> struct TileShape<8, 2> { static constexpr int TX = 2, TY = 2, TPN = 
 // S = 0: the node-block apply mode (any stride): 8 x 8 nodes, four threads
 // per node share its nine block products.
 template <> struct TileShape<0, 0> { static constexpr int TX = 8, TY = 8, TPN = 4; };
+template <> struct TileShape<0, 1> { static constexpr int TX = 16, TY = 8, TPN = 4; };
+template <> struct TileShape<0, 2> { static constexpr int TX = 8, TY = 4, TPN = 4; };
+template <> struct TileShape<0, 3> { static constexpr int TX = 4, TY = 4, TPN = 4; };
 
 template <int S, int V = 0>
 struct TileTraits {
@@ -52,7 +55,7 @@ struct TileTraits {
     static constexpr int MAXPX = ((TX + 1) * S + (S & 1)) * ((TY + 1) * S + (S & 1));
     static constexpr int PPT = S == 0 ? 1 : (MAXPX + NT - 1) / NT;
     static_assert(TPN >= 2 * S && TPN <= 64, "one support row per thread, one wave per node");
-    static_assert(NT == 256 || NT == 512, "block size");
+    static_assert(NT == 256 || NT == 512 || (S == 0 && (NT == 128 || NT == 64)), "block size");
     static_assert(NT <= 512 || PPT <= 2, "registers");
     static_assert(PPT <= 3, "pixels per thread");
 };
@@ -2438,9 +2441,11 @@ TileCfg pick_pcg_tile(int s, int v) {
     return v == 1 ? tile_of<8, 1>() : tile_of<8, 2>();
 }
 
-TileCfg pick_nb_tile() {
-    TileCfg t = tile_of<0>();
-    t.v = SF_TILE_NB;
+TileCfg pick_nb_tile(int v) {
+    if (v < 0 || v >= SF_NB_VARIANTS) v = 0;
+    TileCfg t = v == 1 ? tile_of<0, 1>()
+                       : (v == 2 ? tile_of<0, 2>() : (v == 3 ? tile_of<0, 3>() : tile_of<0, 0>()));
+    t.v = SF_TILE_NB + v;
     return t;
 }
 
@@ -2552,6 +2557,9 @@ void launch_rhs(hipStream_t st, const Launch &L, const TileCfg &t) {
 // The PCG kernels per (stride, variant): the tile in t says which.
 #define SF_PCG_SWITCH(s, v, CALL)                          \
     if ((v) == SF_TILE_NB) { CALL(0, 0); }                 \
+    else if ((v) == SF_TILE_NB + 1) { CALL(0, 1); }        \
+    else if ((v) == SF_TILE_NB + 2) { CALL(0, 2); }        \
+    else if ((v) == SF_TILE_NB + 3) { CALL(0, 3); }        \
     else if ((s) == 2 && (v) == 1) { CALL(2, 1); }         \
     else if ((s) == 2 && (v) == 2) { CALL(2, 2); }         \
     else if ((s) == 4 && (v) == 1) { CALL(4, 1); }         \

@@ -284,24 +284,28 @@ def test_graph_replay_matches_eager_and_repeats(apply):
         assert [l["energy"] for l in log] == [l["energy"] for l in outs[0][2]]
 
 
+@pytest.mark.parametrize("apply", [0, 2])
 @pytest.mark.parametrize("W,H,stride,mode", [(100, 76, 4, 2), (100, 76, 4, 3), (96, 72, 2, 2),
                                              (96, 72, 2, 3), (144, 104, 8, 2),
-                                             (144, 104, 8, 3)])
-def test_solve_pcg_tile_variants(W, H, stride, mode):
-    """The alternative PCG tile shapes give the oracle's solve too."""
+                                             (144, 104, 8, 3), (100, 76, 4, 4)])
+def test_solve_pcg_tile_variants(W, H, stride, mode, apply):
+    """The alternative PCG tile shapes (matrix-free per stride, node-block
+    16 x 8, 8 x 4 and 4 x 4 nodes) give the oracle's solve too."""
     imgs, calib = _frame(W, H, seed=7)
-    prm = dict(levels=3, grid_stride=stride, gn_iters=4, pcg_iters=10, tile_mode=mode)
+    prm = dict(levels=3, grid_stride=stride, gn_iters=4, pcg_iters=10, tile_mode=mode,
+               apply_mode=apply)
     _solve_parity(imgs, calib, prm)
 
 
-def test_autotuned_tiles_parity_and_cache(tmp_path, monkeypatch):
+@pytest.mark.parametrize("apply", [0, 2])
+def test_autotuned_tiles_parity_and_cache(tmp_path, monkeypatch, apply):
     """tile_mode 1: every level's shape is timed on the first solve and
     cached (process and SF_TUNE_CACHE file); a second context reuses the
     cache and gives the same result bitwise."""
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("SF_TUNE_CACHE", str(cache))
     imgs, calib = _frame(160, 120, seed=7)
-    prm = dict(levels=3, grid_stride=4, gn_iters=4, pcg_iters=10, tile_mode=1)
+    prm = dict(levels=3, grid_stride=4, gn_iters=4, pcg_iters=10, tile_mode=1, apply_mode=apply)
     _solve_parity(imgs, calib, prm)
     g = GpuCase(imgs, calib, **prm)
     try:
@@ -320,4 +324,4 @@ def test_autotuned_tiles_parity_and_cache(tmp_path, monkeypatch):
     # set (a shape tuned earlier in the session); at least the file parses
     for ln in filter(None, lines):
         key, v = ln.split()
-        assert "/s4/" in key and v in ("0", "1", "2")
+        assert "/s4/" in key and v in ("0", "1", "2", "3")
