@@ -323,7 +323,7 @@ def main():
                          "PCG at levels of at most 336 nodes")
     ap.add_argument("--tile-mode", type=int, default=1,
                     help="PCG tile shapes: 0 = default, 1 = autotuned (timed on the "
-                         "warm-up solve), 2 / 3 = the alternative shapes")
+                         "warm-up solve), 2 / 3 / 4 = the alternative shapes")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter "
                          "calibration under rocprofv3 --pmc)")
