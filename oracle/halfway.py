@@ -782,27 +782,31 @@ def prolong(total_c, grid_c: Grid, grid_f: Grid):
     return 2.0 * out.reshape(6, -1)
 
 
-def setup_level(level, pyr, p: Params, calib: Calib, base):
+def setup_level(level, pyr, p: Params, calib: Calib, base, delta0=None):
+    """Level set-up at the level-start flow base + delta0 (delta0 = 0
+    unless the level starts from a temporal initialisation)."""
     li = LevelImages.build(pyr[level])
     H, W = li.shape
     grid = Grid(W, H, p.grid_stride)
-    V, Wm = masks(li, grid, base, p)
-    wnode = node_weights(li, grid, base, level, p)
+    start = base if delta0 is None else np.asarray(base, np.float64) + delta0
+    V, Wm = masks(li, grid, start, p)
+    wnode = node_weights(li, grid, start, level, p)
     return LevelState(level, li, grid, np.asarray(base, np.float64),
                       (V & Wm).astype(np.float64), wnode,
                       level_calib_F(calib.F, level))
 
 
-def solve(images, calib, p: Params, init_coarsest=None, record=None):
+def solve(images, calib, p: Params, init_coarsest=None, record=None, init_deltas=None):
     """Algorithm 1 without the occlusion/illumination map updates: for each
     level from coarsest to finest, prolongate the coarser total, start the
-    delta at zero, freeze masks and weights, run gn_iters Gauss-Newton
-    steps.  Returns a dict with the finest-level grid, total node flows
-    (6, G) and the per-level totals."""
+    delta at zero (or at init_deltas[level], the temporal initialisation),
+    freeze masks and weights, run gn_iters Gauss-Newton steps.  Returns a
+    dict with the finest-level grid, total node flows (6, G) and the
+    per-level totals, deltas and grids."""
     if isinstance(calib, dict):
         calib = Calib.from_dict(calib)
     pyr = pyramid(images, p.levels)
-    totals = {}
+    totals, deltas, grids = {}, {}, {}
     total = None
     grid_prev = None
     for level in range(p.levels - 1, -1, -1):
@@ -813,14 +817,73 @@ def solve(images, calib, p: Params, init_coarsest=None, record=None):
                     else np.asarray(init_coarsest, np.float64).reshape(6, -1))
         else:
             base = prolong(total, grid_prev, grid)
-        ls = setup_level(level, pyr, p, calib, base)
-        delta = np.zeros((6, grid.G))
+        delta = (np.zeros((6, grid.G)) if init_deltas is None
+                 else np.asarray(init_deltas[level], np.float64).reshape(6, grid.G))
+        ls = setup_level(level, pyr, p, calib, base,
+                         None if init_deltas is None else delta)
         for _ in range(p.gn_iters):
             delta = gn_step(ls, delta, p, record)
         total = ls.base + delta
         totals[level] = total
+        deltas[level] = delta
+        grids[level] = grid
         grid_prev = grid
-    return dict(grid=grid_prev, total=total, totals=totals)
+    return dict(grid=grid_prev, total=total, totals=totals, deltas=deltas, grids=grids)
+
+
+# ---------------------------------------------------------------------------
+# temporal initialisation (Sec. 5.3)
+# ---------------------------------------------------------------------------
+
+def sample_nodes(grid: Grid, field6, x, y):
+    """Bilinear sample of a node field (c, G) at level-pixel positions
+    (x, y): node (i, j) sits at ((i + 1/2) s - 1/2, (j + 1/2) s - 1/2); the
+    node coordinate is clamped to the grid."""
+    f = np.asarray(field6, np.float64).reshape(-1, grid.Gy, grid.Gx)
+
+    def axis(pos, G):
+        u = np.clip((np.asarray(pos, np.float64) + 0.5) / grid.s - 0.5, 0.0, G - 1.0)
+        i0 = np.minimum(np.floor(u), max(G - 2, 0)).astype(np.int64)
+        return i0, np.minimum(i0 + 1, G - 1), u - i0
+
+    i0, i1, fx = axis(x, grid.Gx)
+    j0, j1, fy = axis(y, grid.Gy)
+    return ((1 - fy) * ((1 - fx) * f[:, j0, i0] + fx * f[:, j0, i1]) +
+            fy * ((1 - fx) * f[:, j1, i0] + fx * f[:, j1, i1]))
+
+
+def temporal_init(prev_totals, prev_deltas, grids):
+    """Per-level initial deltas of the next frame from the previous one
+    (Sec. 5.3: constant velocity, the motion flow propagates the flows, each
+    level's delta transferred separately).
+    reading: the halfway domain moves by 2 m per frame (the stereo average
+    of the positions is x - m at t and x + m at t + 1), so node y of the next
+    frame takes the previous delta at y - 2 m(y), with m the motion
+    components of the previous frame's level total at node y:
+    delta_init(y) = delta_prev(y - 2 m_prev(y)), sampled by sample_nodes."""
+    out = {}
+    for level, grid in grids.items():
+        gx, gy = grid.node_xy()
+        m = np.asarray(prev_totals[level], np.float64).reshape(6, -1)[2:4]
+        out[level] = sample_nodes(grid, prev_deltas[level], gx - 2.0 * m[0], gy - 2.0 * m[1])
+    return out
+
+
+def solve_sequence(frames, calib, p: Params, record=None):
+    """Solves a video frame by frame: the first frame from zero, every
+    later one from temporal_init of the previous result.  Returns the list
+    of solve results (record, if given, collects one list per frame)."""
+    out, prev = [], None
+    for images in frames:
+        rec = [] if record is not None else None
+        init = None if prev is None else temporal_init(prev["totals"], prev["deltas"],
+                                                        prev["grids"])
+        res = solve(images, calib, p, record=rec, init_deltas=init)
+        if record is not None:
+            record.append(rec)
+        out.append(res)
+        prev = res
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -288,10 +288,11 @@ class Scene:
         Xu = np.stack([(z + (u - cx) * zu) / f, (v - cy) * zu / f, zu])
         Xv = np.stack([(u - cx) * zv / f, (z + (v - cy) * zv) / f, zv])
         if t:
+            # constant velocity: X_t = X_0 + t M
             m, mu, mv = self.motion(u, v)
-            X = X + m
-            Xu = Xu + mu
-            Xv = Xv + mv
+            X = X + t * m
+            Xu = Xu + t * mu
+            Xv = Xv + t * mv
         return X, Xu, Xv
 
     def project(self, X, cam):
@@ -327,12 +328,12 @@ class Scene:
         """(u, v) with pi_cam(X_t(u, v)) = (px, py), by Newton's method."""
         if self._plane:
             f, cx, cy, B = self.f, self.cx, self.cy, self.B
-            zt = self.Z0 + (self.T[2] if t else 0.0)
+            zt = self.Z0 + t * self.T[2]
             X = (px - cx) * zt / f + cam * B
             Y = (py - cy) * zt / f
             if t:
-                X = X - self.T[0]
-                Y = Y - self.T[1]
+                X = X - t * self.T[0]
+                Y = Y - t * self.T[1]
             return f * X / self.Z0 + cx, f * Y / self.Z0 + cy
         u = np.array(px, np.float64, copy=True)
         v = np.array(py, np.float64, copy=True)
@@ -356,13 +357,14 @@ class Scene:
                 break
         return u, v
 
-    def render(self, noise=True):
-        """(4, H, W) float32 images in the order L0, R0, L1, R1."""
+    def render(self, noise=True, t0=0):
+        """(4, H, W) float32 images in the order L0, R0, L1, R1, taken at
+        times t0 and t0 + 1 of the constant-velocity motion."""
         W, H = self.cfg.width, self.cfg.height
         py, px = np.mgrid[0:H, 0:W].astype(np.float64)
         out = np.empty((4, H, W), np.float32)
         for k in range(4):
-            u, v = self.surface_coords(_CAM[k], _TIME[k], px, py)
+            u, v = self.surface_coords(_CAM[k], _TIME[k] + t0, px, py)
             img = self.texture(u, v)
             if noise and self.cfg.noise_sigma > 0:
                 img = img + self.noise_rng.normal(0.0, self.cfg.noise_sigma,
@@ -371,16 +373,16 @@ class Scene:
         return out
 
     # ---- ground truth ----------------------------------------------------
-    def projections(self, u, v):
+    def projections(self, u, v, t0=0):
         """The four image positions (x, y) of surface point (u, v):
-        order L0, R0, L1, R1."""
+        order L0, R0, L1, R1 (times t0, t0, t0 + 1, t0 + 1)."""
         out = []
         for k in range(4):
-            X, _, _ = self.point(u, v, _TIME[k])
+            X, _, _ = self.point(u, v, _TIME[k] + t0)
             out.append(self.project(X, _CAM[k]))
         return out
 
-    def halfway_truth(self, width=None, height=None, scale=1.0, iters=40):
+    def halfway_truth(self, width=None, height=None, scale=1.0, iters=40, t0=0):
         """Ground-truth correspondences of every halfway-domain pixel x: the
         surface point whose four projections average to x.  Returns
         (P, ok) with P of shape (4, 2, H, W) (positions in L0, R0, L1, R1,
@@ -396,11 +398,11 @@ class Scene:
         v = ty.copy()
         h = 1e-4
         for _ in range(iters):
-            P = self.projections(u, v)
+            P = self.projections(u, v, t0)
             mx = sum(p[0] for p in P) / 4.0 - tx
             my = sum(p[1] for p in P) / 4.0 - ty
-            Pu = self.projections(u + h, v)
-            Pv = self.projections(u, v + h)
+            Pu = self.projections(u + h, v, t0)
+            Pv = self.projections(u, v + h, t0)
             a = (sum(p[0] for p in Pu) / 4.0 - tx - mx) / h
             b = (sum(p[0] for p in Pv) / 4.0 - tx - mx) / h
             c = (sum(p[1] for p in Pu) / 4.0 - ty - my) / h
@@ -410,7 +412,7 @@ class Scene:
             v = v - (-c * mx + a * my) / det
             if float(np.max(np.abs(mx)) + np.max(np.abs(my))) < 1e-9:
                 break
-        P = self.projections(u, v)
+        P = self.projections(u, v, t0)
         res = np.abs(sum(p[0] for p in P) / 4.0 - tx) + \
             np.abs(sum(p[1] for p in P) / 4.0 - ty)
         pos = np.empty((4, 2, H, W))
@@ -447,6 +449,13 @@ def make_frame(cfg: SceneConfig, seed: int, noise=True):
     scene)."""
     sc = Scene(cfg, seed)
     return sc.render(noise=noise), calib_of(sc), sc
+
+
+def make_sequence(cfg: SceneConfig, seed: int, n_frames: int, noise=True):
+    """A constant-velocity video of one scene: n_frames quadruples, frame
+    k taken at times k and k + 1.  Returns (list of images, calib, scene)."""
+    sc = Scene(cfg, seed)
+    return [sc.render(noise=noise, t0=k) for k in range(n_frames)], calib_of(sc), sc
 
 
 def batch_resolutions(n: int, seed: int):
