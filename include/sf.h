@@ -83,6 +83,17 @@ typedef struct {
  *                  blocks; 120 floats of extra workspace per node); 2 = as
  *                  1, and levels with at most 336 nodes run all PCG
  *                  iterations of a Gauss-Newton step in one workgroup
+ *  temporal        1 = video mode (Sec. 5.3): every sf_solve after the first
+ *                  starts each level's delta from the previous sf_solve of
+ *                  the context, transferred by its motion flow under
+ *                  constant velocity (node y takes the previous delta at
+ *                  y - 2 m(y), m the motion components of the previous
+ *                  level total at y, bilinear on the node grid, clamped;
+ *                  masks and weights are then taken at base + delta).  The
+ *                  first solve after sf_create or sf_reset_sequence starts
+ *                  from zero.  Single-frame solves with init_mode 0 only
+ *                  (sf_solve_batch rejects it); 32 floats of state per node
+ *                  and level.
  *  w_*, m_*        weights of the energy terms; m_s, m_m, m_d must be > 0
  *  eps             pseudo-Huber parameter of Eq. (12)
  *  eps_p           colour-pruning threshold of Sec. 4.1
@@ -92,7 +103,7 @@ typedef struct {
  *                  eigenvalue analysis; this map is the library's reading). */
 typedef struct {
     int levels, grid_stride, gn_iters, pcg_iters, max_backtracks, init_mode;
-    int exec_mode, tile_mode, apply_mode;
+    int exec_mode, tile_mode, apply_mode, temporal;
     float w_reg, w_photo, w_grad, w_epi, w_smooth, w_mag;
     float w_s, w_m, w_d, m_s, m_m, m_d;
     float eps, eps_p, st_gamma, st_tau;
@@ -262,6 +273,11 @@ const char *sf_last_error(void);
 /* Frees the context and all its device memory; NULL-safe.  Synchronises the
  * context's stream first. */
 void sf_destroy(sf_ctx *ctx);
+
+/* Video mode (sf_params.temporal = 1): forgets the previous solve, so the
+ * next sf_solve starts from zero (a new sequence).  Synchronises the
+ * context's stream.  Errors: SF_ERR_INVALID_ARG, SF_ERR_HIP. */
+sf_status sf_reset_sequence(sf_ctx *ctx);
 
 /* ---- test support: per-stage access to intermediates --------------------
  * These entry points exist so that tests can compare each stage with an

@@ -29,7 +29,8 @@ struct FrameBuf {
     unsigned char *cmask = nullptr;
     float *wnode = nullptr, *reg = nullptr, *nodes = nullptr;
     float *gram = nullptr, *grad = nullptr;
-    float *blk = nullptr;  // node-block apply mode only
+    float *blk = nullptr;   // node-block apply mode only
+    float *prev = nullptr;  // temporal state (16 floats per node of every level)
     float *partials = nullptr;
     DevConst *cst = nullptr;
     DevScalars *sc = nullptr;
@@ -121,6 +122,8 @@ sf_status check_params(const sf_params *p) {
     if (p->exec_mode != 0 && p->exec_mode != 1) return SF_ERR_INVALID_ARG;
     if (p->tile_mode < 0 || p->tile_mode > 4) return SF_ERR_INVALID_ARG;
     if (p->apply_mode < 0 || p->apply_mode > 2) return SF_ERR_INVALID_ARG;
+    if (p->temporal != 0 && p->temporal != 1) return SF_ERR_INVALID_ARG;
+    if (p->temporal == 1 && p->init_mode != 0) return SF_ERR_INVALID_ARG;
     const float w[] = {p->w_reg, p->w_photo, p->w_grad, p->w_epi, p->w_smooth,
                        p->w_mag, p->w_s, p->w_m, p->w_d, p->st_gamma};
     for (float v : w)
@@ -136,7 +139,8 @@ bool same_schedule(const sf_params &a, const sf_params &b) {
     return a.levels == b.levels && a.grid_stride == b.grid_stride &&
            a.gn_iters == b.gn_iters && a.pcg_iters == b.pcg_iters &&
            a.max_backtracks == b.max_backtracks && a.init_mode == b.init_mode &&
-           a.tile_mode == b.tile_mode && a.apply_mode == b.apply_mode;
+           a.tile_mode == b.tile_mode && a.apply_mode == b.apply_mode &&
+           a.temporal == b.temporal;
 }
 
 sf_status check_calib(const sf_calib *cal) {
@@ -250,7 +254,7 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
     P.Lmax = 0;
     // sizes, then one allocation carved in 256-byte aligned pieces
     size_t off = 0;
-    std::vector<size_t> o(P.nf * 11);
+    std::vector<size_t> o(P.nf * 12);
     for (int f = 0; f < P.nf; ++f) {
         FrameBuf &F = P.fr[f];
         if (!frame_dims(F, shape[2 * f], shape[2 * f + 1], levels[f], st)) return SF_ERR_SIZE;
@@ -273,7 +277,9 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
         }
         F.max_blocks = mb;
         F.nlog = F.L * prm.gn_iters;
-        const size_t sz[11] = {sizeof(float4) * (size_t)F.tex_len,
+        long g_all = 0;
+        for (int l = 0; l < F.L; ++l) g_all += F.lv[l].G;
+        const size_t sz[12] = {sizeof(float4) * (size_t)F.tex_len,
                                (size_t)F.N0,
                                sizeof(float) * (size_t)F.G0,
                                sizeof(float) * 16 * (size_t)F.G0,
@@ -283,9 +289,10 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
                                sizeof(DevScalars),
                                sizeof(DevLog) * (size_t)F.nlog,
                                sizeof(float) * SF_GRAD_STRIDE * (size_t)F.N0,
-                               nb ? sizeof(float) * SF_BLK_STRIDE * (size_t)F.G0 : 0};
-        for (int k = 0; k < 11; ++k) {
-            o[f * 11 + k] = off;
+                               nb ? sizeof(float) * SF_BLK_STRIDE * (size_t)F.G0 : 0,
+                               prm.temporal ? sizeof(float) * 16 * (size_t)g_all : 0};
+        for (int k = 0; k < 12; ++k) {
+            o[f * 12 + k] = off;
             off += align_up(sz[k]);
         }
     }
@@ -322,17 +329,18 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
     P.dtab = (LevelArgs *)(P.pool + tab_off);
     for (int f = 0; f < P.nf; ++f) {
         FrameBuf &F = P.fr[f];
-        F.tex = (float4 *)(P.pool + o[f * 11 + 0]);
-        F.cmask = (unsigned char *)(P.pool + o[f * 11 + 1]);
-        F.wnode = (float *)(P.pool + o[f * 11 + 2]);
-        F.reg = (float *)(P.pool + o[f * 11 + 3]);
-        F.nodes = (float *)(P.pool + o[f * 11 + 4]);
-        F.gram = (float *)(P.pool + o[f * 11 + 5]);
-        F.grad = (float *)(P.pool + o[f * 11 + 9]);
-        F.blk = nb ? (float *)(P.pool + o[f * 11 + 10]) : nullptr;
-        F.partials = (float *)(P.pool + o[f * 11 + 6]);
-        F.sc = (DevScalars *)(P.pool + o[f * 11 + 7]);
-        F.log = (DevLog *)(P.pool + o[f * 11 + 8]);
+        F.tex = (float4 *)(P.pool + o[f * 12 + 0]);
+        F.cmask = (unsigned char *)(P.pool + o[f * 12 + 1]);
+        F.wnode = (float *)(P.pool + o[f * 12 + 2]);
+        F.reg = (float *)(P.pool + o[f * 12 + 3]);
+        F.nodes = (float *)(P.pool + o[f * 12 + 4]);
+        F.gram = (float *)(P.pool + o[f * 12 + 5]);
+        F.grad = (float *)(P.pool + o[f * 12 + 9]);
+        F.blk = nb ? (float *)(P.pool + o[f * 12 + 10]) : nullptr;
+        F.prev = prm.temporal ? (float *)(P.pool + o[f * 12 + 11]) : nullptr;
+        F.partials = (float *)(P.pool + o[f * 12 + 6]);
+        F.sc = (DevScalars *)(P.pool + o[f * 12 + 7]);
+        F.log = (DevLog *)(P.pool + o[f * 12 + 8]);
         F.cst = P.dcst + f;
         F.io = P.dio + f;
     }
@@ -368,6 +376,13 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
             a.wnode = F.wnode;
             a.reg = F.reg;
             a.blk = F.blk;
+            a.temporal = prm.temporal;
+            a.prev = nullptr;
+            if (prm.temporal) {
+                long goff = 0;
+                for (int k = 0; k < l; ++k) goff += F.lv[k].G;
+                a.prev = F.prev + 16 * goff;
+            }
             a.partials = F.partials;
             a.max_blocks = F.max_blocks;
             a.cst = F.cst;
@@ -886,7 +901,8 @@ sf_status sf_solve_batch(sf_ctx *c, int n, const sf_frame *frames, const sf_para
     const sf_params prm = p ? *p : c->prm;
     sf_status s = check_params(&prm);
     if (s != SF_OK) return s;
-    if (prm.init_mode != 0) return SF_ERR_INVALID_ARG;  // batches start from zero
+    // batches start from zero and keep no temporal state
+    if (prm.init_mode != 0 || prm.temporal != 0) return SF_ERR_INVALID_ARG;
     std::vector<int> shape(2 * n), levels(n);
     std::vector<const sf_calib *> cals(n);
     std::vector<FrameIO> io(n);
@@ -999,6 +1015,15 @@ const char *sf_status_string(sf_status s) {
         case SF_ERR_STATE: return "call not valid in the context's state";
     }
     return "unknown status";
+}
+
+sf_status sf_reset_sequence(sf_ctx *c) {
+    if (!c) return SF_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->device));
+    for (FrameBuf &F : c->single.fr)
+        HIP_TRY(hipMemsetAsync(&F.sc->have_prev, 0, sizeof(int), c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SF_OK;
 }
 
 void sf_destroy(sf_ctx *c) {

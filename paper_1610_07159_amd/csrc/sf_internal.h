@@ -113,6 +113,7 @@ struct DevScalars {
     double e_init[2];  // fallback energies: learned, zero initialisation
     int init_used;     // the learned initialisation was kept
     int n_valid;
+    int have_prev;     // the temporal state holds a finished solve
 };
 
 // Device log record (mirrors sf_iter_log).
@@ -152,6 +153,9 @@ struct LevelArgs {
     int log_base;          // log slot of this level's first Gauss-Newton step
     int Wf, Hf;            // size of the next finer level (pyramid)
     int learned;           // coarsest level initialised by the network
+    int temporal;          // initialise the deltas from the previous solve
+    float *prev;           // temporal state of this level: G records of the
+                           // previous solve's delta, then G of its total
     int W4, H4;            // size of the network's output (level 4)
     const float *cnn_out;  // network output, 6 planes of W4 x H4
     const float4 *tex;     // this level's 4 images (image-major)

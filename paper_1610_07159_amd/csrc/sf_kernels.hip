@@ -2175,9 +2175,32 @@ __global__ __launch_bounds__(SF_BLOCK) void k_fallback(KArg<B> ka) {
     }
 }
 
+// Bilinear sample of a level's node records at level-pixel position (x, y):
+// node coordinate (x + 1/2) / s - 1/2, clamped to the grid.
+__device__ __forceinline__ void sample_node_records(const float *rec, const LevelDims &d, int s,
+                                                    float x, float y, float (&out)[6]) {
+    const float u = fminf(fmaxf((x + 0.5f) / (float)s - 0.5f, 0.f), (float)(d.Gx - 1));
+    const float v = fminf(fmaxf((y + 0.5f) / (float)s - 0.5f, 0.f), (float)(d.Gy - 1));
+    const int i0 = min((int)floorf(u), max(d.Gx - 2, 0)), i1 = min(i0 + 1, d.Gx - 1);
+    const int j0 = min((int)floorf(v), max(d.Gy - 2, 0)), j1 = min(j0 + 1, d.Gy - 1);
+    const float fx = u - (float)i0, fy = v - (float)j0;
+    float f00[6], f01[6], f10[6], f11[6];
+    ld6(rec, (long)j0 * d.Gx + i0, f00);
+    ld6(rec, (long)j0 * d.Gx + i1, f01);
+    ld6(rec, (long)j1 * d.Gx + i0, f10);
+    ld6(rec, (long)j1 * d.Gx + i1, f11);
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        out[q] = (1.f - fy) * ((1.f - fx) * f00[q] + fx * f01[q]) +
+                 fy * ((1.f - fx) * f10[q] + fx * f11[q]);
+}
+
 // base_l = 2 bilerp(total_{l+1}) at coarse-node coordinate i/2 - 1/4
 // (Sec. 5.3); at the coarsest level zero, or the network's candidate if the
-// fallback energies favour it (ties keep zero); delta = 0.
+// fallback energies favour it (ties keep zero).  delta = 0, or with the
+// temporal initialisation (Sec. 5.3, constant velocity) the previous
+// solve's delta of this level at y - 2 m(y), m the motion components of the
+// previous total at node y.
 template <bool B>
 __global__ __launch_bounds__(SF_BLOCK) void k_prolong(KArg<B> ka) {
     SF_BIND(ka);
@@ -2224,7 +2247,17 @@ __global__ __launch_bounds__(SF_BLOCK) void k_prolong(KArg<B> ka) {
                           by.w1 * (bx.w0 * t10[q] + bx.w1 * t11[q]));
     }
     st6(nvec(a, NV_BASE), n, v);
-    st6(nvec(a, NV_DELTA), n, zero);
+    if (a.temporal && a.sc->have_prev) {
+        const LevelDims &d = a.d;
+        float tp[6], dl[6];
+        ld6(a.prev + (long)8 * d.G, n, tp);
+        float gx, gy;
+        node_xy(i, j, a.s, gx, gy);
+        sample_node_records(a.prev, d, a.s, gx - 2.f * tp[2], gy - 2.f * tp[3], dl);
+        st6(nvec(a, NV_DELTA), n, dl);
+    } else {
+        st6(nvec(a, NV_DELTA), n, zero);
+    }
 }
 
 // V(x): all four positions inside the level image; W(x): max_k |d_k| <
@@ -2323,6 +2356,13 @@ __global__ __launch_bounds__(SF_BLOCK) void k_finish_level(KArg<B> ka) {
 #pragma unroll
     for (int q = 0; q < 6; ++q) b[q] = b[q] + dl[q];
     st6(nvec(a, NV_TPREV), n, b);
+    if (a.temporal) {
+        // this level's state for the next solve (read only by the next
+        // solve's level start)
+        st6(a.prev, n, dl);
+        st6(a.prev + (long)8 * a.d.G, n, b);
+        if (a.level == 0 && n == 0) a.sc->have_prev = 1;
+    }
 }
 
 // ---- output: depth and 3D flow at level 0 -----------------------------------

@@ -50,7 +50,7 @@ class sf_calib(ctypes.Structure):
 
 _PARAM_INTS = ("levels", "grid_stride", "gn_iters", "pcg_iters",
                "max_backtracks", "init_mode", "exec_mode", "tile_mode",
-               "apply_mode")
+               "apply_mode", "temporal")
 _PARAM_FLOATS = ("w_reg", "w_photo", "w_grad", "w_epi", "w_smooth", "w_mag",
                  "w_s", "w_m", "w_d", "m_s", "m_m", "m_d", "eps", "eps_p",
                  "st_gamma", "st_tau")
@@ -106,6 +106,7 @@ def _load():
     lib.sf_last_error.restype = ctypes.c_char_p
     lib.sf_destroy.argtypes = [P]
     lib.sf_destroy.restype = None
+    lib.sf_reset_sequence.argtypes = [P]
     lib.sf_debug_size.argtypes = [P, I, I]
     lib.sf_debug_size.restype = ctypes.c_size_t
     lib.sf_debug_read.argtypes = [P, I, I, P, ctypes.c_size_t]
@@ -251,6 +252,10 @@ def sf_status_string(code: int) -> str:
 
 def sf_destroy(ctx):
     lib.sf_destroy(ctx)
+
+
+def sf_reset_sequence(ctx):
+    _check(lib.sf_reset_sequence(ctx), "sf_reset_sequence")
 
 
 def sf_debug_size(ctx, what, level) -> int:

@@ -81,6 +81,10 @@ class SceneFlowSolver:
     def log(self):
         return sf.sf_get_log(self.ctx)[0]
 
+    def reset_sequence(self):
+        """Video mode: the next solve starts a new sequence (from zero)."""
+        sf.sf_reset_sequence(self.ctx)
+
     def close(self):
         if self.ctx is not None:
             sf.sf_destroy(self.ctx)

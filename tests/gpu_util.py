@@ -38,6 +38,11 @@ class GpuCase:
     def ptrs(self):
         return [self.img[k].data_ptr() for k in range(4)]
 
+    def load(self, images):
+        """Replaces the device images (the next frame of a sequence)."""
+        self.images_np = np.asarray(images, np.float32)
+        self.img.copy_(self.torch.from_numpy(self.images_np))
+
     def set_images(self):
         self.sf.sf_debug_set_images(self.ctx, *self.ptrs(), self.cal)
 

@@ -50,10 +50,13 @@ def test_host_validation_without_gpu():
     for field, bad in (("levels", 0), ("levels", 99), ("pcg_iters", 65),
                        ("grid_stride", 0), ("m_m", 0.0), ("w_photo", -1.0),
                        ("max_backtracks", 9), ("exec_mode", 3), ("tile_mode", 5),
-                       ("init_mode", 2), ("apply_mode", 3), ("apply_mode", -1),
+                       ("init_mode", 2), ("apply_mode", 3), ("apply_mode", -1), ("temporal", 2),
                        ("eps", float("nan"))):
         q = sf.sf_params_default(**{field: bad})
         assert lib.sf_create(ctypes.byref(h), 64, 48, ctypes.byref(q), None) == -1, field
+    # video mode needs the zero initialisation of the first frame
+    q = sf.sf_params_default(levels=5, init_mode=1, temporal=1)
+    assert lib.sf_create(ctypes.byref(h), 640, 480, ctypes.byref(q), None) == -1
     # levels that would shrink below 8 x 8 pixels
     q = sf.sf_params_default(levels=4)
     assert lib.sf_create(ctypes.byref(h), 60, 40, ctypes.byref(q), None) == -2
