@@ -89,6 +89,7 @@ class Params:
     eps_p: float = 0.2
     st_gamma: float = 4.0
     st_tau: float = 1e-3
+    illum: bool = False  # illumination correction (Sec. 5.3)
 
     def flow_weights(self):
         """w_f per unknown component (s_x, s_y, m_x, m_y, d_x, d_y)."""
@@ -160,19 +161,23 @@ def image_gradients(img):
 
 @dataclass
 class LevelImages:
-    """The four images of one level with their gradient images."""
+    """The four images of one level with their gradient images, and the
+    illumination correction of the level (per halfway-domain pixel,
+    subtracted from both right-camera samples; None = no correction)."""
     I: np.ndarray   # (4, H, W)
     Gx: np.ndarray  # (4, H, W)
     Gy: np.ndarray  # (4, H, W)
+    illum: np.ndarray | None = None  # (H * W,)
 
     @staticmethod
-    def build(imgs4):
+    def build(imgs4, illum=None):
         imgs4 = np.asarray(imgs4, np.float64)
         gx = np.empty_like(imgs4)
         gy = np.empty_like(imgs4)
         for c in range(4):
             gx[c], gy[c] = image_gradients(imgs4[c])
-        return LevelImages(imgs4, gx, gy)
+        return LevelImages(imgs4, gx, gy,
+                           None if illum is None else np.asarray(illum, np.float64).reshape(-1))
 
     @property
     def shape(self):
@@ -342,6 +347,12 @@ def pixel_terms_xy(li: LevelImages, px, py, flows):
         val[c], dI[c, 0], dI[c, 1] = sample(li.I[c], P[c, 0], P[c, 1])
         gv[c, 0], dG[c, 0, 0], dG[c, 0, 1] = sample(li.Gx[c], P[c, 0], P[c, 1])
         gv[c, 1], dG[c, 1, 0], dG[c, 1, 1] = sample(li.Gy[c], P[c, 0], P[c, 1])
+    if li.illum is not None:
+        # normalised right-camera intensities (the correction does not
+        # depend on the flows; gradients are unaffected by an offset)
+        corr = li.illum[(np.asarray(py, np.int64) * li.shape[1] + np.asarray(px, np.int64))]
+        val[1] -= corr
+        val[3] -= corr
     N = px.shape[0]
     d = np.empty((6, N))
     g = np.empty((6, 2, N))
@@ -782,10 +793,11 @@ def prolong(total_c, grid_c: Grid, grid_f: Grid):
     return 2.0 * out.reshape(6, -1)
 
 
-def setup_level(level, pyr, p: Params, calib: Calib, base, delta0=None):
+def setup_level(level, pyr, p: Params, calib: Calib, base, delta0=None, illum=None):
     """Level set-up at the level-start flow base + delta0 (delta0 = 0
-    unless the level starts from a temporal initialisation)."""
-    li = LevelImages.build(pyr[level])
+    unless the level starts from a temporal initialisation), with the
+    level's illumination correction (None = none)."""
+    li = LevelImages.build(pyr[level], illum)
     H, W = li.shape
     grid = Grid(W, H, p.grid_stride)
     start = base if delta0 is None else np.asarray(base, np.float64) + delta0
@@ -819,16 +831,82 @@ def solve(images, calib, p: Params, init_coarsest=None, record=None, init_deltas
             base = prolong(total, grid_prev, grid)
         delta = (np.zeros((6, grid.G)) if init_deltas is None
                  else np.asarray(init_deltas[level], np.float64).reshape(6, grid.G))
+        illum = None
+        if p.illum:
+            illum = np.zeros(grid.N) if total is None else illum_next
         ls = setup_level(level, pyr, p, calib, base,
-                         None if init_deltas is None else delta)
+                         None if init_deltas is None else delta, illum)
         for _ in range(p.gn_iters):
             delta = gn_step(ls, delta, p, record)
         total = ls.base + delta
         totals[level] = total
         deltas[level] = delta
         grids[level] = grid
+        if p.illum and level > 0:
+            Hf, Wf = pyr[level - 1].shape[1:]
+            illum_next = illumination_map(ls.li, grid, total, Wf, Hf)
         grid_prev = grid
     return dict(grid=grid_prev, total=total, totals=totals, deltas=deltas, grids=grids)
+
+
+# ---------------------------------------------------------------------------
+# illumination correction (Sec. 5.3)
+# ---------------------------------------------------------------------------
+
+#: Gaussian of the illumination extraction, in level pixels (Sec. 5.3)
+ILLUM_SIGMA = 3.2
+
+
+def illumination_residual(li: LevelImages, grid: Grid, total):
+    """Intensity residual between the two stereo pairs in the halfway
+    domain at the level's final flow.
+    reading: e(x) = ((I_R0(P_R0) - I_L0(P_L0)) + (I_R1(P_R1) - I_L1(P_L1))) / 2
+    on the raw images (the absolute left/right difference, re-estimated on
+    every level), 0 where a position lies outside its image (V = 0)."""
+    flows = grid.to_pixels(total)
+    px, py = grid.pixel_xy()
+    P = positions(px, py, flows)
+    H, W = li.shape
+    V = np.ones(grid.N, bool)
+    val = np.empty((4, grid.N))
+    for c in range(4):
+        V &= (P[c, 0] >= 0) & (P[c, 0] <= W - 1) & (P[c, 1] >= 0) & (P[c, 1] <= H - 1)
+        val[c] = sample(li.I[c], P[c, 0], P[c, 1])[0]
+    e = 0.5 * ((val[1] - val[0]) + (val[3] - val[2]))
+    return np.where(V, e, 0.0).reshape(H, W)
+
+
+def gaussian_blur(img, sigma=ILLUM_SIGMA):
+    """Separable Gaussian, taps k = -R..R with R = ceil(3 sigma), weights
+    exp(-k^2 / (2 sigma^2)) normalised to 1, clamp-to-edge borders (rows,
+    then columns)."""
+    R = int(math.ceil(3.0 * sigma))
+    k = np.arange(-R, R + 1)
+    w = np.exp(-(k ** 2) / (2.0 * sigma * sigma))
+    w /= w.sum()
+    img = np.asarray(img, np.float64)
+    H, W = img.shape
+    xi = np.clip(np.arange(W)[:, None] + k[None, :], 0, W - 1)
+    tmp = (img[:, xi] * w).sum(-1)
+    yi = np.clip(np.arange(H)[:, None] + k[None, :], 0, H - 1)
+    return np.einsum("ykx,k->yx", tmp[yi], w)
+
+
+def box_upsample(img, Wf, Hf):
+    """Box filter to the next finer level: fine pixel (x, y) takes coarse
+    pixel (x // 2, y // 2), clamped to the coarse image."""
+    img = np.asarray(img, np.float64)
+    H, W = img.shape
+    yi = np.minimum(np.arange(Hf) // 2, H - 1)
+    xi = np.minimum(np.arange(Wf) // 2, W - 1)
+    return img[yi][:, xi]
+
+
+def illumination_map(li: LevelImages, grid: Grid, total, Wf, Hf):
+    """The next finer level's correction (Sec. 5.3): the low-frequency part
+    of the stereo residual (Gaussian, sigma = 3.2 px), box-upsampled; flat
+    (Hf * Wf,).  The coarsest level has none (zero)."""
+    return box_upsample(gaussian_blur(illumination_residual(li, grid, total)), Wf, Hf).reshape(-1)
 
 
 # ---------------------------------------------------------------------------

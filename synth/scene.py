@@ -51,6 +51,10 @@ class SceneConfig:
     noise_sigma: float = 0.0
     noise_octaves: int = 4
     noise_period: float = 64.0
+    # right-camera response: I_R = gain I + bias + ramp (x / W - 1/2)
+    right_gain: float = 1.0
+    right_bias: float = 0.0
+    right_ramp: float = 0.0
     extra: dict = field(default_factory=dict)
 
     @property
@@ -366,6 +370,9 @@ class Scene:
         for k in range(4):
             u, v = self.surface_coords(_CAM[k], _TIME[k] + t0, px, py)
             img = self.texture(u, v)
+            if _CAM[k] == 1:
+                c = self.cfg
+                img = c.right_gain * img + c.right_bias + c.right_ramp * (px / W - 0.5)
             if noise and self.cfg.noise_sigma > 0:
                 img = img + self.noise_rng.normal(0.0, self.cfg.noise_sigma,
                                                   img.shape)

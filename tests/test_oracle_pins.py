@@ -721,3 +721,59 @@ def test_sequence_of_the_translating_plane_starts_closer():
     err_seq = np.abs(grid.to_pixels(res[1]["total"]).reshape(6, grid.H, grid.W) - truth)[:, ok]
     err_zero = np.abs(grid.to_pixels(zero["total"]).reshape(6, grid.H, grid.W) - truth)[:, ok]
     assert err_seq.mean() < err_zero.mean()
+
+
+# ---- illumination correction (Sec. 5.3) ---------------------------------------
+
+def test_gaussian_blur_and_box_upsample():
+    """The separable blur equals scipy's Gaussian filter with the same
+    radius (ceil(3 sigma) = 10 taps a side) and nearest-edge borders; the
+    box upsample equals repeating each pixel 2 x 2 (odd sizes clamp)."""
+    import scipy.ndimage as ndi
+    rng = np.random.default_rng(8)
+    img = rng.normal(size=(23, 37))
+    ref = ndi.gaussian_filter(img, O.ILLUM_SIGMA, mode="nearest",
+                              truncate=math.ceil(3 * O.ILLUM_SIGMA) / O.ILLUM_SIGMA)
+    np.testing.assert_allclose(O.gaussian_blur(img), ref, rtol=0, atol=1e-12)
+    up = O.box_upsample(img, 74, 46)
+    np.testing.assert_array_equal(up, np.repeat(np.repeat(img, 2, 0), 2, 1))
+    up = O.box_upsample(img, 75, 47)
+    assert up.shape == (47, 75)
+    np.testing.assert_array_equal(up[-1, -1], img[-1, -1])
+
+
+def test_illumination_residual_recovers_a_right_camera_offset():
+    """Right images = left images + b and zero flow: the stereo residual is
+    b at every pixel, the blurred map is b, and with the correction applied
+    the stereo differences vanish."""
+    rng = np.random.default_rng(9)
+    left = rng.uniform(0.2, 0.8, (2, 20, 30))
+    imgs = np.stack([left[0], left[0] + 0.07, left[1], left[1] + 0.07])
+    li = O.LevelImages.build(imgs)
+    grid = O.Grid(30, 20, 4)
+    e = O.illumination_residual(li, grid, np.zeros((6, grid.G)))
+    np.testing.assert_allclose(e, 0.07, rtol=0, atol=1e-12)
+    m = O.illumination_map(li, grid, np.zeros((6, grid.G)), 30, 20)
+    np.testing.assert_allclose(m, 0.07, rtol=0, atol=1e-12)
+    li2 = O.LevelImages.build(imgs, np.full(grid.N, 0.07))
+    t = O.pixel_terms(li2, grid, np.zeros((6, grid.N)))
+    np.testing.assert_allclose(t.d[[0, 1]], 0.0, atol=1e-12)  # stereo pairs
+
+
+def test_illumination_correction_helps_a_biased_right_camera():
+    """The translating plane with a right camera of different gain and
+    offset: the corrected solve ends closer to the true flows."""
+    from dataclasses import replace
+    cfg = replace(tiny_plane_config(), right_gain=1.1, right_bias=0.08, right_ramp=0.05)
+    sc = Scene(cfg, 0)
+    imgs = sc.render(noise=False).astype(np.float64)
+    from synth.scene import calib_of
+    calib = calib_of(sc)
+    truth = np.concatenate(halfway_flows_from_positions(sc.halfway_truth()[0]))
+    errs = []
+    for on in (False, True):
+        p = O.Params(levels=3, grid_stride=8, gn_iters=5, pcg_iters=10, illum=on)
+        res = O.solve(imgs, calib, p)
+        g = res["grid"]
+        errs.append(np.abs(g.to_pixels(res["total"]).reshape(6, g.H, g.W) - truth).mean())
+    assert errs[1] < errs[0]
