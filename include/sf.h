@@ -94,6 +94,14 @@ typedef struct {
  *                  from zero.  Single-frame solves with init_mode 0 only
  *                  (sf_solve_batch rejects it); 32 floats of state per node
  *                  and level.
+ *  illum           1 = illumination correction (Sec. 5.3): after each level
+ *                  the stereo residual ((I_R0 - I_L0) + (I_R1 - I_L1)) / 2
+ *                  of the raw images at the final flow (0 where a position
+ *                  leaves its image) is low-passed (Gaussian, sigma 3.2 px,
+ *                  10 taps a side, clamped borders), box-upsampled to the
+ *                  next finer level and subtracted there from both
+ *                  right-camera samples (masks and energies); the coarsest
+ *                  level has none.  3 floats of workspace per pixel.
  *  w_*, m_*        weights of the energy terms; m_s, m_m, m_d must be > 0
  *  eps             pseudo-Huber parameter of Eq. (12)
  *  eps_p           colour-pruning threshold of Sec. 4.1
@@ -103,7 +111,7 @@ typedef struct {
  *                  eigenvalue analysis; this map is the library's reading). */
 typedef struct {
     int levels, grid_stride, gn_iters, pcg_iters, max_backtracks, init_mode;
-    int exec_mode, tile_mode, apply_mode, temporal;
+    int exec_mode, tile_mode, apply_mode, temporal, illum;
     float w_reg, w_photo, w_grad, w_epi, w_smooth, w_mag;
     float w_s, w_m, w_d, m_s, m_m, m_d;
     float eps, eps_p, st_gamma, st_tau;

@@ -31,6 +31,7 @@ struct FrameBuf {
     float *gram = nullptr, *grad = nullptr;
     float *blk = nullptr;   // node-block apply mode only
     float *prev = nullptr;  // temporal state (16 floats per node of every level)
+    float *illum = nullptr; // illumination map and its two scratch planes (3 x N0)
     float *partials = nullptr;
     DevConst *cst = nullptr;
     DevScalars *sc = nullptr;
@@ -124,6 +125,7 @@ sf_status check_params(const sf_params *p) {
     if (p->apply_mode < 0 || p->apply_mode > 2) return SF_ERR_INVALID_ARG;
     if (p->temporal != 0 && p->temporal != 1) return SF_ERR_INVALID_ARG;
     if (p->temporal == 1 && p->init_mode != 0) return SF_ERR_INVALID_ARG;
+    if (p->illum != 0 && p->illum != 1) return SF_ERR_INVALID_ARG;
     const float w[] = {p->w_reg, p->w_photo, p->w_grad, p->w_epi, p->w_smooth,
                        p->w_mag, p->w_s, p->w_m, p->w_d, p->st_gamma};
     for (float v : w)
@@ -140,7 +142,7 @@ bool same_schedule(const sf_params &a, const sf_params &b) {
            a.gn_iters == b.gn_iters && a.pcg_iters == b.pcg_iters &&
            a.max_backtracks == b.max_backtracks && a.init_mode == b.init_mode &&
            a.tile_mode == b.tile_mode && a.apply_mode == b.apply_mode &&
-           a.temporal == b.temporal;
+           a.temporal == b.temporal && a.illum == b.illum;
 }
 
 sf_status check_calib(const sf_calib *cal) {
@@ -254,7 +256,7 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
     P.Lmax = 0;
     // sizes, then one allocation carved in 256-byte aligned pieces
     size_t off = 0;
-    std::vector<size_t> o(P.nf * 12);
+    std::vector<size_t> o(P.nf * 13);
     for (int f = 0; f < P.nf; ++f) {
         FrameBuf &F = P.fr[f];
         if (!frame_dims(F, shape[2 * f], shape[2 * f + 1], levels[f], st)) return SF_ERR_SIZE;
@@ -279,7 +281,7 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
         F.nlog = F.L * prm.gn_iters;
         long g_all = 0;
         for (int l = 0; l < F.L; ++l) g_all += F.lv[l].G;
-        const size_t sz[12] = {sizeof(float4) * (size_t)F.tex_len,
+        const size_t sz[13] = {sizeof(float4) * (size_t)F.tex_len,
                                (size_t)F.N0,
                                sizeof(float) * (size_t)F.G0,
                                sizeof(float) * 16 * (size_t)F.G0,
@@ -290,9 +292,10 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
                                sizeof(DevLog) * (size_t)F.nlog,
                                sizeof(float) * SF_GRAD_STRIDE * (size_t)F.N0,
                                nb ? sizeof(float) * SF_BLK_STRIDE * (size_t)F.G0 : 0,
-                               prm.temporal ? sizeof(float) * 16 * (size_t)g_all : 0};
-        for (int k = 0; k < 12; ++k) {
-            o[f * 12 + k] = off;
+                               prm.temporal ? sizeof(float) * 16 * (size_t)g_all : 0,
+                               prm.illum ? sizeof(float) * 3 * (size_t)F.N0 : 0};
+        for (int k = 0; k < 13; ++k) {
+            o[f * 13 + k] = off;
             off += align_up(sz[k]);
         }
     }
@@ -329,18 +332,19 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
     P.dtab = (LevelArgs *)(P.pool + tab_off);
     for (int f = 0; f < P.nf; ++f) {
         FrameBuf &F = P.fr[f];
-        F.tex = (float4 *)(P.pool + o[f * 12 + 0]);
-        F.cmask = (unsigned char *)(P.pool + o[f * 12 + 1]);
-        F.wnode = (float *)(P.pool + o[f * 12 + 2]);
-        F.reg = (float *)(P.pool + o[f * 12 + 3]);
-        F.nodes = (float *)(P.pool + o[f * 12 + 4]);
-        F.gram = (float *)(P.pool + o[f * 12 + 5]);
-        F.grad = (float *)(P.pool + o[f * 12 + 9]);
-        F.blk = nb ? (float *)(P.pool + o[f * 12 + 10]) : nullptr;
-        F.prev = prm.temporal ? (float *)(P.pool + o[f * 12 + 11]) : nullptr;
-        F.partials = (float *)(P.pool + o[f * 12 + 6]);
-        F.sc = (DevScalars *)(P.pool + o[f * 12 + 7]);
-        F.log = (DevLog *)(P.pool + o[f * 12 + 8]);
+        F.tex = (float4 *)(P.pool + o[f * 13 + 0]);
+        F.cmask = (unsigned char *)(P.pool + o[f * 13 + 1]);
+        F.wnode = (float *)(P.pool + o[f * 13 + 2]);
+        F.reg = (float *)(P.pool + o[f * 13 + 3]);
+        F.nodes = (float *)(P.pool + o[f * 13 + 4]);
+        F.gram = (float *)(P.pool + o[f * 13 + 5]);
+        F.grad = (float *)(P.pool + o[f * 13 + 9]);
+        F.blk = nb ? (float *)(P.pool + o[f * 13 + 10]) : nullptr;
+        F.prev = prm.temporal ? (float *)(P.pool + o[f * 13 + 11]) : nullptr;
+        F.illum = prm.illum ? (float *)(P.pool + o[f * 13 + 12]) : nullptr;
+        F.partials = (float *)(P.pool + o[f * 13 + 6]);
+        F.sc = (DevScalars *)(P.pool + o[f * 13 + 7]);
+        F.log = (DevLog *)(P.pool + o[f * 13 + 8]);
         F.cst = P.dcst + f;
         F.io = P.dio + f;
     }
@@ -377,6 +381,9 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
             a.reg = F.reg;
             a.blk = F.blk;
             a.temporal = prm.temporal;
+            a.illum = F.illum;
+            a.ill_e = F.illum ? F.illum + F.N0 : nullptr;
+            a.ill_t = F.illum ? F.illum + 2 * F.N0 : nullptr;
             a.prev = nullptr;
             if (prm.temporal) {
                 long goff = 0;
@@ -535,10 +542,12 @@ void enqueue_cnn_init(const Plan &P, hipStream_t st) {
 
 void enqueue_levels(const Plan &P, hipStream_t st) {
     for (int l = P.Lmax - 1; l >= 0; --l) {
+        if (P.prm.illum) launch_illum_zero(st, slot(P, l));
         if (P.cnn.on && l == P.Lmax - 1) enqueue_cnn_init(P, st);
         launch_level_init(st, slot(P, l));
         for (int g = 0; g < P.prm.gn_iters; ++g) enqueue_gn(P, st, l, g, true);
         launch_finish_level(st, slot(P, l));
+        if (P.prm.illum) launch_illum_next(st, slot(P, l));
     }
 }
 

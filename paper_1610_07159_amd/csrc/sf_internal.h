@@ -154,6 +154,10 @@ struct LevelArgs {
     int Wf, Hf;            // size of the next finer level (pyramid)
     int learned;           // coarsest level initialised by the network
     int temporal;          // initialise the deltas from the previous solve
+    float *illum;          // illumination correction of this level's pixels
+                           // (nullptr: none); the next finer level's is
+                           // written into the same buffer after this level
+    float *ill_e, *ill_t;  // its scratch: residual and horizontal blur
     float *prev;           // temporal state of this level: G records of the
                            // previous solve's delta, then G of its total
     int W4, H4;            // size of the network's output (level 4)
@@ -227,6 +231,10 @@ void launch_pcg_small(hipStream_t st, const Launch &L, int n_it, int gn);
 void launch_accept(hipStream_t st, const Launch &L, int n_trials, int gn,
                    int pcg_iters);
 void launch_finish_level(hipStream_t st, const Launch &L);
+// illumination correction: zero map at each frame's coarsest level start;
+// after a level (not the finest) the next finer level's map
+void launch_illum_zero(hipStream_t st, const Launch &L);
+void launch_illum_next(hipStream_t st, const Launch &L);
 void launch_output(hipStream_t st, const Launch &L, float *depth,
                    float *flow3d, float *flows);
 TileCfg pick_tile(int s);

@@ -525,6 +525,12 @@ __device__ __forceinline__ void pixel_terms(const LevelArgs &a, int x, int y,
         const float py = (((float)y + sgn(cam, 0) * f[1]) + sgn(cam, 1) * f[3]) + sgn(cam, 2) * f[5];
         sample3(a.tex + (long)cam * d.N, d.W, d.H, px, py, S[cam]);
     }
+    if (a.illum) {
+        // illumination correction of the right-camera samples
+        const float cr = a.illum[(long)y * d.W + x];
+        S[1].v[0] -= cr;
+        S[3].v[0] -= cr;
+    }
     const float eps2 = C.eps * C.eps;
     o.e_photo = 0.f;
     o.e_grad = 0.f;
@@ -2290,9 +2296,15 @@ __global__ __launch_bounds__(SF_BLOCK) void k_masks(KArg<B> ka) {
             sample3(a.tex + (long)cam * d.N, d.W, d.H, px, py, sm);
             I[cam] = sm.v[0];
         }
+        float Ic[4] = {I[0], I[1], I[2], I[3]};
+        if (a.illum) {
+            const float cr = a.illum[(long)y * d.W + x];
+            Ic[1] -= cr;
+            Ic[3] -= cr;
+        }
         float dmax = 0.f;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) dmax = fmaxf(dmax, fabsf(I[pair_a(k)] - I[pair_b(k)]));
+        for (int k = 0; k < 6; ++k) dmax = fmaxf(dmax, fabsf(Ic[pair_a(k)] - Ic[pair_b(k)]));
         const bool Wm = dmax < C.eps_p;
         const int pix = y * d.W + x;
         a.cmask[pix] = (V && Wm) ? 1 : 0;
@@ -2363,6 +2375,91 @@ __global__ __launch_bounds__(SF_BLOCK) void k_finish_level(KArg<B> ka) {
         st6(a.prev + (long)8 * a.d.G, n, b);
         if (a.level == 0 && n == 0) a.sc->have_prev = 1;
     }
+}
+
+// ---- illumination correction (Sec. 5.3) ----------------------------------------
+//
+// After a level: the stereo residual of the raw images at the final flow,
+// ((I_R0 - I_L0) + (I_R1 - I_L1)) / 2 per halfway pixel (0 where a position
+// leaves its image), low-passed by a separable Gaussian (sigma 3.2 px, 10
+// taps a side, clamped borders) and box-upsampled to the next finer level,
+// whose right-camera samples it corrects.
+
+#define ILLUM_SIGMA 3.2f
+#define ILLUM_R 10  // ceil(3 sigma)
+
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_illum_resid(KArg<B> ka) {
+    SF_BIND(ka);
+    const LevelDims &d = a.d;
+    __shared__ NodeStage S;
+    const int tiles_x = (d.W + TILE_PX - 1) / TILE_PX;
+    const int x0 = (bid % tiles_x) * TILE_PX, y0 = (bid / tiles_x) * TILE_PX;
+    stage_nodes(a, x0, y0, 0.f, S);
+    __syncthreads();
+    const int x = x0 + (threadIdx.x & (TILE_PX - 1));
+    const int y = y0 + (threadIdx.x / TILE_PX);
+    if (x < d.W && y < d.H) {
+        float f[6];
+        pixel_flows(a, x, y, S, f);
+        bool V = true;
+        float I[4];
+#pragma unroll
+        for (int cam = 0; cam < 4; ++cam) {
+            const float px = (((float)x + sgn(cam, 0) * f[0]) + sgn(cam, 1) * f[2]) + sgn(cam, 2) * f[4];
+            const float py = (((float)y + sgn(cam, 0) * f[1]) + sgn(cam, 1) * f[3]) + sgn(cam, 2) * f[5];
+            V = V && px >= 0.f && px <= (float)(d.W - 1) && py >= 0.f && py <= (float)(d.H - 1);
+            Samp sm;
+            sample3(a.tex + (long)cam * d.N, d.W, d.H, px, py, sm);
+            I[cam] = sm.v[0];
+        }
+        a.ill_e[(long)y * d.W + x] = V ? 0.5f * ((I[1] - I[0]) + (I[3] - I[2])) : 0.f;
+    }
+}
+
+__device__ __forceinline__ float illum_weight(int k) {
+    return expf(-(float)(k * k) / (2.f * ILLUM_SIGMA * ILLUM_SIGMA));
+}
+
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_illum_blur_x(KArg<B> ka) {
+    SF_BIND(ka);
+    const LevelDims &d = a.d;
+    const long n = (long)bid * SF_BLOCK + threadIdx.x;
+    if (n >= d.N) return;
+    const int x = (int)(n % d.W), y = (int)(n / d.W);
+    float acc = 0.f, ws = 0.f;
+    for (int k = -ILLUM_R; k <= ILLUM_R; ++k) {
+        const float w = illum_weight(k);
+        acc += w * a.ill_e[(long)y * d.W + min(max(x + k, 0), d.W - 1)];
+        ws += w;
+    }
+    a.ill_t[n] = acc / ws;
+}
+
+// one thread per pixel of the next finer level (Wf x Hf)
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_illum_up(KArg<B> ka) {
+    SF_BIND(ka);
+    const LevelDims &d = a.d;
+    const long n = (long)bid * SF_BLOCK + threadIdx.x;
+    if (n >= (long)a.Wf * a.Hf) return;
+    const int xf = (int)(n % a.Wf), yf = (int)(n / a.Wf);
+    const int xc = min(xf / 2, d.W - 1), yc = min(yf / 2, d.H - 1);
+    float acc = 0.f, ws = 0.f;
+    for (int k = -ILLUM_R; k <= ILLUM_R; ++k) {
+        const float w = illum_weight(k);
+        acc += w * a.ill_t[(long)min(max(yc + k, 0), d.H - 1) * d.W + xc];
+        ws += w;
+    }
+    a.illum[n] = acc / ws;
+}
+
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_illum_zero(KArg<B> ka) {
+    SF_BIND(ka);
+    const long n = (long)bid * SF_BLOCK + threadIdx.x;
+    if (n < a.d.N) a.illum[n] = 0.f;
 }
 
 // ---- output: depth and 3D flow at level 0 -----------------------------------
@@ -2681,6 +2778,25 @@ void launch_pcg_last(hipStream_t st, const Launch &L, const TileCfg &t, int iter
 
 void launch_accept(hipStream_t st, const Launch &L, int n_trials, int gn, int pcg_iters) {
     go(st, L, nd_blocks, k_accept<true>, k_accept<false>, SF_BLOCK, 0, n_trials, gn, pcg_iters);
+}
+
+void launch_illum_zero(hipStream_t st, const Launch &L) {
+    auto nb = [](const LevelArgs &a) {
+        return a.illum && a.coarsest ? (a.d.N + SF_BLOCK - 1) / SF_BLOCK : 0;
+    };
+    go(st, L, nb, k_illum_zero<true>, k_illum_zero<false>, SF_BLOCK, 0);
+}
+
+void launch_illum_next(hipStream_t st, const Launch &L) {
+    auto on = [](const LevelArgs &a) { return a.illum && a.level > 0; };
+    auto nr = [on](const LevelArgs &a) { return on(a) ? pixel_tiles(a.d) : 0; };
+    auto nx = [on](const LevelArgs &a) { return on(a) ? (a.d.N + SF_BLOCK - 1) / SF_BLOCK : 0; };
+    auto nu = [on](const LevelArgs &a) {
+        return on(a) ? (int)(((long)a.Wf * a.Hf + SF_BLOCK - 1) / SF_BLOCK) : 0;
+    };
+    go(st, L, nr, k_illum_resid<true>, k_illum_resid<false>, SF_BLOCK, 0);
+    go(st, L, nx, k_illum_blur_x<true>, k_illum_blur_x<false>, SF_BLOCK, 0);
+    go(st, L, nu, k_illum_up<true>, k_illum_up<false>, SF_BLOCK, 0);
 }
 
 void launch_finish_level(hipStream_t st, const Launch &L) {

@@ -50,7 +50,7 @@ class sf_calib(ctypes.Structure):
 
 _PARAM_INTS = ("levels", "grid_stride", "gn_iters", "pcg_iters",
                "max_backtracks", "init_mode", "exec_mode", "tile_mode",
-               "apply_mode", "temporal")
+               "apply_mode", "temporal", "illum")
 _PARAM_FLOATS = ("w_reg", "w_photo", "w_grad", "w_epi", "w_smooth", "w_mag",
                  "w_s", "w_m", "w_d", "m_s", "m_m", "m_d", "eps", "eps_p",
                  "st_gamma", "st_tau")
