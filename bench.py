@@ -64,6 +64,13 @@ WORKLOADS = {
                        "over frames 1..9 (frame 0 starts the sequence); stride 4, 5 levels",
                   width=640, height=480, seed=5, n_frames=10,
                   params=dict(levels=5, grid_stride=4, gn_iters=10, pcg_iters=20)),
+    "illum": dict(desc="illumination correction on/off: 8 640x480 generator frames "
+                       "(seeds 2000000..2000007, 30 px displacement) whose right camera "
+                       "responds with gain 1.08, offset 0.06 and a horizontal ramp of 0.08; "
+                       "EPE and ms/frame of the plain and the corrected solve; stride 4, "
+                       "5 levels, 10 GN x 20 PCG",
+                  width=640, height=480, n_eval=8, gain=1.08, bias=0.06, ramp=0.08,
+                  params=dict(levels=5, grid_stride=4, gn_iters=10, pcg_iters=20)),
 }
 
 # Algorithmic bytes of one H p launch (matrix-free, per-pixel Gauss-Newton
@@ -176,6 +183,74 @@ def make_video_workload(w):
     with ProcessPoolExecutor(max_workers=8) as ex:
         out = list(ex.map(_render_video_frame, [(w["seed"], k) for k in range(w["n_frames"])]))
     return out, calib_of(Scene(vga_config(), w["seed"]))
+
+
+def _render_illum_frame(args):
+    from dataclasses import replace
+    from synth import Scene, vga_config
+    seed, gain, bias, ramp = args
+    sc = Scene(replace(vga_config(), right_gain=gain, right_bias=bias, right_ramp=ramp), seed)
+    pos, ok = sc.halfway_truth()
+    from synth import calib_of
+    return sc.render(), calib_of(sc), (pos.astype(np.float32), ok)
+
+
+def make_illum_workload(w):
+    from concurrent.futures import ProcessPoolExecutor
+    jobs = [(2_000_000 + k, w["gain"], w["bias"], w["ramp"]) for k in range(w["n_eval"])]
+    with ProcessPoolExecutor(max_workers=8) as ex:
+        return list(ex.map(_render_illum_frame, jobs))
+
+
+def run_illum(args, frames):
+    """EPE and time of the solve with and without illumination correction
+    on frames whose right camera has a different response."""
+    import torch
+    from paper_1610_07159_amd import SceneFlowSolver
+    from paper_1610_07159_amd import train_init as T
+    w = WORKLOADS["illum"]
+    W, H = w["width"], w["height"]
+    params = dict(w["params"], apply_mode=args.apply_mode)
+    dev = [torch.from_numpy(f).cuda().contiguous() for f, _, _ in frames]
+    out_rows = {}
+    for on in (0, 1):
+        solver = SceneFlowSolver(W, H, exec_mode=args.exec_mode, tile_mode=args.tile_mode,
+                                 illum=on, **params)
+        out = (torch.empty((H, W), device="cuda"), torch.empty((3, H, W), device="cuda"),
+               torch.empty((6, H, W), device="cuda"))
+        try:
+            solver.solve(dev[0], frames[0][1], out=out)  # warm-up (graph, tiles)
+            epes, times = [], []
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            for img, (_, calib, truth) in zip(dev, frames):
+                e0.record(solver.stream)
+                solver.solve(img, calib, out=out)
+                e1.record(solver.stream)
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+                epes.append(T.epe(out[2].cpu().numpy(), truth, W, H))
+        finally:
+            solver.close()
+        out_rows["corrected" if on else "plain"] = dict(
+            epe_px=round(float(np.mean(epes)), 4), ms_per_frame=round(float(np.mean(times)), 3))
+    result = {
+        "metric": METRIC,
+        "value": out_rows["corrected"]["ms_per_frame"],
+        "unit": "ms/frame",
+        "n_gpus": 1,
+        "steps": len(dev),
+        "warmup": 1,
+        "ms_per_step": out_rows["corrected"]["ms_per_frame"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], **params},
+        **out_rows,
+    }
+    print(json.dumps(result), flush=True)
 
 
 def run_video(args, workload):
@@ -449,6 +524,8 @@ def main():
         pre["batch"] = make_batch_workload(WORKLOADS["batch"])
     if args.workload == "video":
         pre["video"] = make_video_workload(WORKLOADS["video"])
+    if args.workload == "illum":
+        pre["illum"] = make_illum_workload(WORKLOADS["illum"])
     if args.workload == "learned" or (args.workload == "vga" and not args.no_learned):
         from paper_1610_07159_amd.train_init import render_frames
         n_eval = WORKLOADS["learned"]["n_eval"]
@@ -472,6 +549,8 @@ def main():
         return run_learned(args, pre["eval"])
     if args.workload == "video":
         return run_video(args, pre["video"])
+    if args.workload == "illum":
+        return run_illum(args, pre["illum"])
 
     from paper_1610_07159_amd import SceneFlowSolver, sf
 
