@@ -90,6 +90,7 @@ class Params:
     st_gamma: float = 4.0
     st_tau: float = 1e-3
     illum: bool = False  # illumination correction (Sec. 5.3)
+    occlusion: bool = False  # occlusion maps from a z-buffer (Sec. 5.3)
 
     def flow_weights(self):
         """w_f per unknown component (s_x, s_y, m_x, m_y, d_x, d_y)."""
@@ -711,7 +712,7 @@ def gn_step(ls: LevelState, delta, p: Params, record=None):
 # level set-up: visibility, pruning and smoothness weights
 # ---------------------------------------------------------------------------
 
-def masks(li: LevelImages, grid: Grid, total, p: Params):
+def masks(li: LevelImages, grid: Grid, total, p: Params, occ=None):
     """V(x) and W(x) of Eq. (11) at the level-start flow.
     reading: V(x) = 1 iff all four positions lie inside the level image
     (occlusion maps are not built); W(x) = 1 iff max_k |d_k(x)| < eps_p.
@@ -723,6 +724,8 @@ def masks(li: LevelImages, grid: Grid, total, p: Params):
     V = np.ones(grid.N, bool)
     for c in range(4):
         V &= (P[c, 0] >= 0) & (P[c, 0] <= W - 1) & (P[c, 1] >= 0) & (P[c, 1] <= H - 1)
+    if occ is not None:
+        V &= np.asarray(occ, bool).reshape(-1)
     t = pixel_terms(li, grid, flows)
     Wm = np.abs(t.d).max(0) < p.eps_p
     return V, Wm
@@ -793,15 +796,16 @@ def prolong(total_c, grid_c: Grid, grid_f: Grid):
     return 2.0 * out.reshape(6, -1)
 
 
-def setup_level(level, pyr, p: Params, calib: Calib, base, delta0=None, illum=None):
+def setup_level(level, pyr, p: Params, calib: Calib, base, delta0=None, illum=None,
+                occ=None):
     """Level set-up at the level-start flow base + delta0 (delta0 = 0
     unless the level starts from a temporal initialisation), with the
-    level's illumination correction (None = none)."""
+    level's illumination correction and occlusion map (None = none)."""
     li = LevelImages.build(pyr[level], illum)
     H, W = li.shape
     grid = Grid(W, H, p.grid_stride)
     start = base if delta0 is None else np.asarray(base, np.float64) + delta0
-    V, Wm = masks(li, grid, start, p)
+    V, Wm = masks(li, grid, start, p, occ)
     wnode = node_weights(li, grid, start, level, p)
     return LevelState(level, li, grid, np.asarray(base, np.float64),
                       (V & Wm).astype(np.float64), wnode,
@@ -834,8 +838,9 @@ def solve(images, calib, p: Params, init_coarsest=None, record=None, init_deltas
         illum = None
         if p.illum:
             illum = np.zeros(grid.N) if total is None else illum_next
+        occ = occ_next if (p.occlusion and total is not None) else None
         ls = setup_level(level, pyr, p, calib, base,
-                         None if init_deltas is None else delta, illum)
+                         None if init_deltas is None else delta, illum, occ)
         for _ in range(p.gn_iters):
             delta = gn_step(ls, delta, p, record)
         total = ls.base + delta
@@ -845,6 +850,9 @@ def solve(images, calib, p: Params, init_coarsest=None, record=None, init_deltas
         if p.illum and level > 0:
             Hf, Wf = pyr[level - 1].shape[1:]
             illum_next = illumination_map(ls.li, grid, total, Wf, Hf)
+        if p.occlusion and level > 0:
+            Hf, Wf = pyr[level - 1].shape[1:]
+            occ_next = box_upsample(occlusion_map(grid, total), Wf, Hf) > 0.5
         grid_prev = grid
     return dict(grid=grid_prev, total=total, totals=totals, deltas=deltas, grids=grids)
 
@@ -907,6 +915,154 @@ def illumination_map(li: LevelImages, grid: Grid, total, Wf, Hf):
     of the stereo residual (Gaussian, sigma = 3.2 px), box-upsampled; flat
     (Hf * Wf,).  The coarsest level has none (zero)."""
     return box_upsample(gaussian_blur(illumination_residual(li, grid, total)), Wf, Hf).reshape(-1)
+
+
+# ---------------------------------------------------------------------------
+# occlusion maps (Sec. 5.3)
+# ---------------------------------------------------------------------------
+
+#: relative disparity tolerance of the z-buffer test
+OCC_TOL = 0.02
+#: longest triangle edge (px, in the camera) that is rendered
+OCC_EDGE = 2.0
+
+
+def _halfway_triangles(H, W):
+    """Triangulation of the halfway pixel grid: every quad (x, y), (x+1, y),
+    (x, y+1), (x+1, y+1) split along its (x+1, y)-(x, y+1) diagonal; (n, 3)
+    flat pixel indices."""
+    idx = np.arange(H * W).reshape(H, W)
+    a = idx[:-1, :-1].ravel()
+    b = idx[:-1, 1:].ravel()
+    c = idx[1:, :-1].ravel()
+    d = idx[1:, 1:].ravel()
+    return np.concatenate([np.stack([a, b, c], 1), np.stack([b, d, c], 1)])
+
+
+def _edge(ax, ay, bx, by, qx, qy):
+    """Twice the signed area of (a, b, q): > 0 if q is left of a -> b."""
+    return (bx - ax) * (qy - ay) - (by - ay) * (qx - ax)
+
+
+def _occlusion(grid: Grid, total, margin=0.0, margin_rel=0.0):
+    """Visibility from a z-buffer of the triangulated geometry (Sec. 5.3).
+    reading: each halfway pixel is a vertex of the mesh that triangulates
+    the halfway grid; in camera c a vertex sits at P_c and carries the
+    stereo disparity of its time t, D_t = P_Lt.x - P_Rt.x (larger = nearer;
+    depth f B / D_t).  A triangle is rendered in camera c unless an edge is
+    longer than OCC_EDGE px there (it spans a depth discontinuity), a vertex
+    has D_t <= 0, or it has zero area; it covers the integer pixel centres q
+    on or inside it and writes its barycentric interpolation of D_t there;
+    the z-buffer keeps the largest value per pixel (0 where nothing is
+    drawn).  A halfway pixel is visible in c unless its nearest pixel
+    centre floor(P_c + 1/2) is in the image, D_t > 0 and D_t < (1 -
+    OCC_TOL) times the z-buffer there; visible overall if visible in all
+    four views.
+    margin > 0 (px; margin_rel relative, for the disparity test) also finds
+    the pixels whose result could change if positions moved by less than
+    margin: every decision is taken both ways where its deciding quantity is
+    within the margin of its threshold (z-buffers of the certain and of the
+    possible writes).  Returns (visibility (N,) bool, fragile (N,) bool)."""
+    flows = grid.to_pixels(total)
+    px, py = grid.pixel_xy()
+    P = positions(px, py, flows)
+    H, W = grid.H, grid.W
+    N = grid.N
+    D0 = P[0, 0] - P[1, 0]
+    D1 = P[2, 0] - P[3, 0]
+    disp = (D0, D0, D1, D1)
+    tri = _halfway_triangles(H, W)
+    vis = np.ones(N, bool)
+    frag = np.zeros(N, bool)
+    for cam in range(4):
+        X, Y, D = P[cam, 0], P[cam, 1], disp[cam]
+        ax, ay, ad = X[tri[:, 0]], Y[tri[:, 0]], D[tri[:, 0]]
+        bx, by, bd = X[tri[:, 1]], Y[tri[:, 1]], D[tri[:, 1]]
+        cx, cy, cd = X[tri[:, 2]], Y[tri[:, 2]], D[tri[:, 2]]
+        lab = np.hypot(bx - ax, by - ay)
+        lbc = np.hypot(cx - bx, cy - by)
+        lca = np.hypot(ax - cx, ay - cy)
+        lmax = np.maximum(np.maximum(lab, lbc), lca)
+        dmin = np.minimum(np.minimum(ad, bd), cd)
+        area = _edge(ax, ay, bx, by, cx, cy)
+        scale = lab + lbc + lca
+        keep_lo = (lmax <= OCC_EDGE - margin) & (dmin > margin) & (np.abs(area) > margin * scale)
+        keep_hi = (lmax <= OCC_EDGE + margin) & (dmin > -margin) & (np.abs(area) > -margin * scale)
+        if margin == 0.0:
+            keep_hi = keep_lo
+        sg = np.where(area < 0, -1.0, 1.0)
+        safe = np.where(area == 0, 1.0, area)
+        x0 = np.ceil(np.minimum(np.minimum(ax, bx), cx) - margin).astype(np.int64)
+        y0 = np.ceil(np.minimum(np.minimum(ay, by), cy) - margin).astype(np.int64)
+        x1 = np.floor(np.maximum(np.maximum(ax, bx), cx) + margin).astype(np.int64)
+        y1 = np.floor(np.maximum(np.maximum(ay, by), cy) + margin).astype(np.int64)
+        zlo = np.zeros(N)
+        zhi = np.zeros(N)
+        span = int(np.ceil(OCC_EDGE + 2 * margin)) + 1
+        for oy in range(span):
+            for ox in range(span):
+                qx = x0 + ox
+                qy = y0 + oy
+                inb = (qx <= x1) & (qy <= y1) & (qx >= 0) & (qx < W) & (qy >= 0) & (qy < H)
+                E_bc = _edge(bx, by, cx, cy, qx, qy)
+                E_ca = _edge(cx, cy, ax, ay, qx, qy)
+                E_ab = _edge(ax, ay, bx, by, qx, qy)
+                e_bc, e_ca, e_ab = sg * E_bc, sg * E_ca, sg * E_ab
+                ins_lo = (e_bc >= margin * lbc) & (e_ca >= margin * lca) & (e_ab >= margin * lab)
+                ins_hi = (e_bc >= -margin * lbc) & (e_ca >= -margin * lca) & (e_ab >= -margin * lab)
+                # barycentric interpolation: the weight of a vertex is the
+                # area opposite it over the whole area
+                z = (E_bc * ad + E_ca * bd + E_ab * cd) / safe
+                q = np.where(inb, qy * W + qx, 0)
+                w_lo = inb & keep_lo & ins_lo
+                w_hi = inb & keep_hi & ins_hi
+                np.maximum.at(zlo, q[w_lo], z[w_lo])
+                np.maximum.at(zhi, q[w_hi], z[w_hi])
+        # the test at the nearest pixel centre, both ways where it is fragile
+        fx = X - np.floor(X)
+        fy = Y - np.floor(Y)
+        res = []
+        for rx in (0.0, 1.0):
+            for ry in (0.0, 1.0):
+                for zb in (zlo, zhi):
+                    for dr in (-margin_rel, margin_rel):
+                        nx = np.floor(X + 0.5)
+                        ny = np.floor(Y + 0.5)
+                        if margin > 0:
+                            nx = np.where(np.abs(fx - 0.5) < margin, np.floor(X) + rx, nx)
+                            ny = np.where(np.abs(fy - 0.5) < margin, np.floor(Y) + ry, ny)
+                        qx = nx.astype(np.int64)
+                        qy = ny.astype(np.int64)
+                        inb = (qx >= 0) & (qx < W) & (qy >= 0) & (qy < H)
+                        dd = D + dr * np.abs(D) + (margin if dr > 0 else -margin) * (margin > 0)
+                        q = np.where(inb, qy * W + qx, 0)
+                        occl = inb & (dd > 0) & (dd < (1.0 - OCC_TOL) * zb[q])
+                        res.append(~occl)
+        nominal = res[0] if margin == 0.0 else None
+        if margin == 0.0:
+            vc = nominal
+            fc = np.zeros(N, bool)
+        else:
+            stack = np.stack(res)
+            vc = stack.all(0)
+            fc = stack.any(0) & ~stack.all(0)
+        vis &= vc
+        frag |= fc
+    return vis, frag
+
+
+def occlusion_map(grid: Grid, total):
+    """Visibility of every halfway pixel in all four views, (H, W) float
+    0/1, from a z-buffer of the current geometry (Sec. 5.3; the reading is
+    stated in _occlusion)."""
+    return _occlusion(grid, total)[0].reshape(grid.H, grid.W).astype(np.float64)
+
+
+def occlusion_fragile(grid: Grid, total, margin=1e-3, margin_rel=5e-4):
+    """Pixels whose visibility could flip if the positions moved by less
+    than margin px (or disparities by margin_rel relative): where a float32
+    evaluation of the same geometry may legitimately differ; (H, W) bool."""
+    return _occlusion(grid, total, margin, margin_rel)[1].reshape(grid.H, grid.W)
 
 
 # ---------------------------------------------------------------------------

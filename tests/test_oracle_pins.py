@@ -777,3 +777,117 @@ def test_illumination_correction_helps_a_biased_right_camera():
         g = res["grid"]
         errs.append(np.abs(g.to_pixels(res["total"]).reshape(6, g.H, g.W) - truth).mean())
     assert errs[1] < errs[0]
+
+
+# ---- occlusion maps (Sec. 5.3) -------------------------------------------------
+
+def _strip_flows(grid, a, b, Df, Db):
+    """Per-pixel flows (stride 1) of a fronto-parallel strip of disparity Df
+    over columns [a, b) in front of a background of disparity Db, no motion:
+    s.x = -D / 2 so that P_L.x = x + D / 2 and P_R.x = x - D / 2."""
+    px, _ = grid.pixel_xy()
+    D = np.where((px >= a) & (px < b), Df, Db)
+    tot = np.zeros((6, grid.G))
+    tot[0] = -D / 2
+    return tot
+
+
+@pytest.mark.parametrize("a,b", [(15, 25), (9, 30), (12, 14), (20, 23)])
+def test_occlusion_strip_closed_form(a, b):
+    """A strip of disparity 10 (columns [a, b), b - a >= 2) in front of a
+    background of disparity 2.  In the left views strip column x lands on
+    x + 5 and background column x on x + 1, so the strip covers the pixel
+    centres a + 5 .. b + 4 and hides the background columns right of it
+    whose x + 1 falls there: max(b, a + 4) .. b + 3.  In the right views
+    (x - 5 and x - 1) it hides a - 4 .. min(a - 1, b - 5).  Nothing else is
+    occluded: the triangles that join strip and background are longer than
+    2 px and are not drawn."""
+    W, H = 44, 9
+    g = O.Grid(W, H, 1)
+    vis = O.occlusion_map(g, _strip_flows(g, a, b, 10.0, 2.0))
+    hidden = set(range(a - 4, min(a - 1, b - 5) + 1)) | set(range(max(b, a + 4), b + 4))
+    expect = np.array([0.0 if x in hidden else 1.0 for x in range(W)])
+    np.testing.assert_array_equal(vis, np.tile(expect, (H, 1)))
+
+
+def test_occlusion_of_a_plane_is_empty():
+    """Constant flows (a fronto-parallel plane seen with uniform motion):
+    every pixel is visible in every view."""
+    g = O.Grid(30, 20, 5)
+    tot = np.zeros((6, g.G))
+    tot[:, :] = np.array([-2.3, 0.1, 0.7, -0.4, 0.2, 0.05])[:, None]
+    assert np.all(O.occlusion_map(g, tot) == 1.0)
+    assert not O.occlusion_fragile(g, tot).any()
+
+
+def _brute_visibility(P, D, W, H, tol, max_edge):
+    """Independent z-buffer: every pixel centre against every triangle of the
+    halfway grid, barycentric coordinates from a 2x2 linear solve."""
+    vis = np.ones(H * W, bool)
+    for cam in range(4):
+        X, Y, Dc = P[cam, 0], P[cam, 1], D[cam]
+        zb = np.zeros(H * W)
+        tris = []
+        for y in range(H - 1):
+            for x in range(W - 1):
+                i00, i10, i01, i11 = y * W + x, y * W + x + 1, (y + 1) * W + x, (y + 1) * W + x + 1
+                tris += [(i00, i10, i01), (i10, i11, i01)]
+        for t in tris:
+            v = np.array([[X[k], Y[k]] for k in t])
+            if max(np.linalg.norm(v[i] - v[(i + 1) % 3]) for i in range(3)) > max_edge:
+                continue
+            if min(Dc[k] for k in t) <= 0:
+                continue
+            M = np.array([v[1] - v[0], v[2] - v[0]]).T
+            if abs(np.linalg.det(M)) < 1e-12:
+                continue
+            for qy in range(H):
+                for qx in range(W):
+                    lb, lc = np.linalg.solve(M, np.array([qx, qy]) - v[0])
+                    lam = (1 - lb - lc, lb, lc)
+                    if min(lam) >= 0:
+                        z = sum(l * Dc[k] for l, k in zip(lam, t))
+                        zb[qy * W + qx] = max(zb[qy * W + qx], z)
+        for i in range(H * W):
+            nx, ny = math.floor(X[i] + 0.5), math.floor(Y[i] + 0.5)
+            if 0 <= nx < W and 0 <= ny < H and Dc[i] > 0 and Dc[i] < (1 - tol) * zb[ny * W + nx]:
+                vis[i] = False
+    return vis
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_occlusion_matches_brute_force(seed):
+    rng = _rng(seed)
+    W, H = 9, 7
+    g = O.Grid(W, H, 1)
+    px, py = g.pixel_xy()
+    fg = (px >= 3) & (px < 6) & (py >= 2)
+    D = np.where(fg, 4.5, 1.5) + 0.3 * rng.standard_normal(g.N)
+    D[rng.integers(0, g.N, 2)] = -0.5
+    tot = np.zeros((6, g.G))
+    tot[4] = 0.2 * rng.standard_normal(g.N)
+    tot[5] = 0.2 * rng.standard_normal(g.N)
+    tot[0] = -D / 2 + tot[4]
+    tot[1] = 0.2 * rng.standard_normal(g.N)
+    tot[2] = 0.3 * rng.standard_normal(g.N)
+    tot[3] = 0.3 * rng.standard_normal(g.N)
+    P = O.positions(px, py, tot)
+    Ds = [P[0, 0] - P[1, 0], P[0, 0] - P[1, 0], P[2, 0] - P[3, 0], P[2, 0] - P[3, 0]]
+    ref = _brute_visibility(P, Ds, W, H, O.OCC_TOL, O.OCC_EDGE)
+    got = O.occlusion_map(g, tot).reshape(-1) > 0.5
+    assert (~ref).sum() > 0
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_occlusion_solve_of_the_translating_plane_is_unchanged():
+    """The fold-free plane scene has nothing occluded at any level, so the
+    solve with occlusion maps equals the one without."""
+    sc = Scene(tiny_plane_config(), 0)
+    imgs = sc.render(noise=False).astype(np.float64)
+    from synth.scene import calib_of
+    calib = calib_of(sc)
+    out = []
+    for on in (False, True):
+        p = O.Params(levels=3, grid_stride=8, gn_iters=2, pcg_iters=6, occlusion=on)
+        out.append(O.solve(imgs, calib, p)["total"])
+    np.testing.assert_array_equal(out[0], out[1])
