@@ -102,6 +102,19 @@ typedef struct {
  *                  next finer level and subtracted there from both
  *                  right-camera samples (masks and energies); the coarsest
  *                  level has none.  3 floats of workspace per pixel.
+ *  occlusion       1 = occlusion maps (Sec. 5.3): after each level but the
+ *                  finest the mesh that triangulates the halfway pixel grid
+ *                  is rendered into the four views with a z-buffer of
+ *                  stereo disparity (triangles with an edge longer than
+ *                  2 px in a view, a vertex of disparity <= 0 or zero area
+ *                  are skipped; pixel centres on or inside a triangle take
+ *                  its barycentric disparity; the largest value is kept); a
+ *                  halfway pixel is occluded if, in some view, its nearest
+ *                  pixel centre is in the image and its own disparity is
+ *                  positive and below 0.98 times the z-buffer there.  The
+ *                  map is box-upsampled to the next finer level and removes
+ *                  occluded pixels from its V(x) (the coarsest level has
+ *                  none).  About 17 bytes of workspace per pixel.
  *  w_*, m_*        weights of the energy terms; m_s, m_m, m_d must be > 0
  *  eps             pseudo-Huber parameter of Eq. (12)
  *  eps_p           colour-pruning threshold of Sec. 4.1
@@ -111,7 +124,7 @@ typedef struct {
  *                  eigenvalue analysis; this map is the library's reading). */
 typedef struct {
     int levels, grid_stride, gn_iters, pcg_iters, max_backtracks, init_mode;
-    int exec_mode, tile_mode, apply_mode, temporal, illum;
+    int exec_mode, tile_mode, apply_mode, temporal, illum, occlusion;
     float w_reg, w_photo, w_grad, w_epi, w_smooth, w_mag;
     float w_s, w_m, w_d, m_s, m_m, m_d;
     float eps, eps_p, st_gamma, st_tau;
@@ -307,8 +320,11 @@ enum {
     SF_DBG_REC = 10,    /* 27 x N_l float: per-pixel gradient (6) and
                            upper-triangular Gauss-Newton block (21)          */
     SF_DBG_P = 11,      /* 6 x G_l float: the vector the first product used  */
-    SF_DBG_ENERGY = 12  /* 6 double: photo, grad, smooth, epi, mag, total
+    SF_DBG_ENERGY = 12, /* 6 double: photo, grad, smooth, epi, mag, total
                            at the last linearisation                         */
+    SF_DBG_OCC = 13     /* N_l uint8: the occlusion map level l reads, 1 =
+                           visible (written by SF_STAGE_OCC at level l + 1;
+                           occlusion = 1 only)                               */
 };
 size_t sf_debug_size(sf_ctx *ctx, int what, int level);
 sf_status sf_debug_read(sf_ctx *ctx, int what, int level, void *host_dst,
@@ -337,7 +353,9 @@ sf_status sf_debug_set_images(sf_ctx *ctx, const float *I_left_t,
  *                        tau dx with dx = the current SF_DBG_DX and tau the
  *                        first of 1, 1/2, ..., 2^-max_backtracks whose
  *                        energy does not exceed E at the last
- *                        SF_STAGE_LINEARIZE (delta unchanged if none)   */
+ *                        SF_STAGE_LINEARIZE (delta unchanged if none)
+ *  SF_STAGE_OCC          the occlusion map of level - 1 from this level's
+ *                        base + delta (level >= 1, occlusion = 1)        */
 enum {
     SF_STAGE_LEVEL_INIT = 0,
     SF_STAGE_LINEARIZE = 1,
@@ -346,7 +364,8 @@ enum {
     SF_STAGE_GN = 4,
     SF_STAGE_FINISH = 5,
     SF_STAGE_MASKS = 6,
-    SF_STAGE_STEP = 7
+    SF_STAGE_STEP = 7,
+    SF_STAGE_OCC = 8
 };
 sf_status sf_debug_run(sf_ctx *ctx, int stage, int level);
 

@@ -18,7 +18,8 @@
 
 namespace {
 
-// Device buffers of one frame.
+// Device buffers of one frame (SF_FRAME_BUFS sub-allocations of the pool).
+#define SF_FRAME_BUFS 16
 struct FrameBuf {
     int W = 0, H = 0, L = 0;
     LevelDims lv[SF_MAX_LEVELS]{};
@@ -32,6 +33,9 @@ struct FrameBuf {
     float *blk = nullptr;   // node-block apply mode only
     float *prev = nullptr;  // temporal state (16 floats per node of every level)
     float *illum = nullptr; // illumination map and its two scratch planes (3 x N0)
+    unsigned char *occ = nullptr;  // occlusion map of the level being solved (N0)
+    float *occ_pos = nullptr;      // its scratch: 10 planes of N_1 ...
+    unsigned *occ_zb = nullptr;    // ... and 4 z-buffers of N_1
     float *partials = nullptr;
     DevConst *cst = nullptr;
     DevScalars *sc = nullptr;
@@ -126,6 +130,7 @@ sf_status check_params(const sf_params *p) {
     if (p->temporal != 0 && p->temporal != 1) return SF_ERR_INVALID_ARG;
     if (p->temporal == 1 && p->init_mode != 0) return SF_ERR_INVALID_ARG;
     if (p->illum != 0 && p->illum != 1) return SF_ERR_INVALID_ARG;
+    if (p->occlusion != 0 && p->occlusion != 1) return SF_ERR_INVALID_ARG;
     const float w[] = {p->w_reg, p->w_photo, p->w_grad, p->w_epi, p->w_smooth,
                        p->w_mag, p->w_s, p->w_m, p->w_d, p->st_gamma};
     for (float v : w)
@@ -142,7 +147,7 @@ bool same_schedule(const sf_params &a, const sf_params &b) {
            a.gn_iters == b.gn_iters && a.pcg_iters == b.pcg_iters &&
            a.max_backtracks == b.max_backtracks && a.init_mode == b.init_mode &&
            a.tile_mode == b.tile_mode && a.apply_mode == b.apply_mode &&
-           a.temporal == b.temporal && a.illum == b.illum;
+           a.temporal == b.temporal && a.illum == b.illum && a.occlusion == b.occlusion;
 }
 
 sf_status check_calib(const sf_calib *cal) {
@@ -256,7 +261,7 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
     P.Lmax = 0;
     // sizes, then one allocation carved in 256-byte aligned pieces
     size_t off = 0;
-    std::vector<size_t> o(P.nf * 13);
+    std::vector<size_t> o(P.nf * SF_FRAME_BUFS);
     for (int f = 0; f < P.nf; ++f) {
         FrameBuf &F = P.fr[f];
         if (!frame_dims(F, shape[2 * f], shape[2 * f + 1], levels[f], st)) return SF_ERR_SIZE;
@@ -281,7 +286,9 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
         F.nlog = F.L * prm.gn_iters;
         long g_all = 0;
         for (int l = 0; l < F.L; ++l) g_all += F.lv[l].G;
-        const size_t sz[13] = {sizeof(float4) * (size_t)F.tex_len,
+        const size_t n1 = F.L > 1 ? (size_t)F.lv[1].N : 0;
+        const bool occ = prm.occlusion && F.L > 1;
+        const size_t sz[SF_FRAME_BUFS] = {sizeof(float4) * (size_t)F.tex_len,
                                (size_t)F.N0,
                                sizeof(float) * (size_t)F.G0,
                                sizeof(float) * 16 * (size_t)F.G0,
@@ -293,9 +300,12 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
                                sizeof(float) * SF_GRAD_STRIDE * (size_t)F.N0,
                                nb ? sizeof(float) * SF_BLK_STRIDE * (size_t)F.G0 : 0,
                                prm.temporal ? sizeof(float) * 16 * (size_t)g_all : 0,
-                               prm.illum ? sizeof(float) * 3 * (size_t)F.N0 : 0};
-        for (int k = 0; k < 13; ++k) {
-            o[f * 13 + k] = off;
+                               prm.illum ? sizeof(float) * 3 * (size_t)F.N0 : 0,
+                               occ ? (size_t)F.N0 : 0,
+                               occ ? sizeof(float) * 10 * n1 : 0,
+                               occ ? sizeof(unsigned) * 4 * n1 : 0};
+        for (int k = 0; k < SF_FRAME_BUFS; ++k) {
+            o[f * SF_FRAME_BUFS + k] = off;
             off += align_up(sz[k]);
         }
     }
@@ -332,19 +342,24 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
     P.dtab = (LevelArgs *)(P.pool + tab_off);
     for (int f = 0; f < P.nf; ++f) {
         FrameBuf &F = P.fr[f];
-        F.tex = (float4 *)(P.pool + o[f * 13 + 0]);
-        F.cmask = (unsigned char *)(P.pool + o[f * 13 + 1]);
-        F.wnode = (float *)(P.pool + o[f * 13 + 2]);
-        F.reg = (float *)(P.pool + o[f * 13 + 3]);
-        F.nodes = (float *)(P.pool + o[f * 13 + 4]);
-        F.gram = (float *)(P.pool + o[f * 13 + 5]);
-        F.grad = (float *)(P.pool + o[f * 13 + 9]);
-        F.blk = nb ? (float *)(P.pool + o[f * 13 + 10]) : nullptr;
-        F.prev = prm.temporal ? (float *)(P.pool + o[f * 13 + 11]) : nullptr;
-        F.illum = prm.illum ? (float *)(P.pool + o[f * 13 + 12]) : nullptr;
-        F.partials = (float *)(P.pool + o[f * 13 + 6]);
-        F.sc = (DevScalars *)(P.pool + o[f * 13 + 7]);
-        F.log = (DevLog *)(P.pool + o[f * 13 + 8]);
+        F.tex = (float4 *)(P.pool + o[f * SF_FRAME_BUFS + 0]);
+        F.cmask = (unsigned char *)(P.pool + o[f * SF_FRAME_BUFS + 1]);
+        F.wnode = (float *)(P.pool + o[f * SF_FRAME_BUFS + 2]);
+        F.reg = (float *)(P.pool + o[f * SF_FRAME_BUFS + 3]);
+        F.nodes = (float *)(P.pool + o[f * SF_FRAME_BUFS + 4]);
+        F.gram = (float *)(P.pool + o[f * SF_FRAME_BUFS + 5]);
+        F.grad = (float *)(P.pool + o[f * SF_FRAME_BUFS + 9]);
+        F.blk = nb ? (float *)(P.pool + o[f * SF_FRAME_BUFS + 10]) : nullptr;
+        F.prev = prm.temporal ? (float *)(P.pool + o[f * SF_FRAME_BUFS + 11]) : nullptr;
+        F.illum = prm.illum ? (float *)(P.pool + o[f * SF_FRAME_BUFS + 12]) : nullptr;
+        if (prm.occlusion && F.L > 1) {
+            F.occ = (unsigned char *)(P.pool + o[f * SF_FRAME_BUFS + 13]);
+            F.occ_pos = (float *)(P.pool + o[f * SF_FRAME_BUFS + 14]);
+            F.occ_zb = (unsigned *)(P.pool + o[f * SF_FRAME_BUFS + 15]);
+        }
+        F.partials = (float *)(P.pool + o[f * SF_FRAME_BUFS + 6]);
+        F.sc = (DevScalars *)(P.pool + o[f * SF_FRAME_BUFS + 7]);
+        F.log = (DevLog *)(P.pool + o[f * SF_FRAME_BUFS + 8]);
         F.cst = P.dcst + f;
         F.io = P.dio + f;
     }
@@ -384,6 +399,11 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
             a.illum = F.illum;
             a.ill_e = F.illum ? F.illum + F.N0 : nullptr;
             a.ill_t = F.illum ? F.illum + 2 * F.N0 : nullptr;
+            // the map a level reads is written after the next coarser one
+            a.occ = F.occ && l < F.L - 1 ? F.occ : nullptr;
+            a.occ_next = F.occ && l > 0 ? F.occ : nullptr;
+            a.occ_pos = F.occ_pos;
+            a.occ_zb = F.occ_zb;
             a.prev = nullptr;
             if (prm.temporal) {
                 long goff = 0;
@@ -548,6 +568,7 @@ void enqueue_levels(const Plan &P, hipStream_t st) {
         for (int g = 0; g < P.prm.gn_iters; ++g) enqueue_gn(P, st, l, g, true);
         launch_finish_level(st, slot(P, l));
         if (P.prm.illum) launch_illum_next(st, slot(P, l));
+        if (P.prm.occlusion) launch_occ_next(st, slot(P, l));
     }
 }
 
@@ -1061,6 +1082,7 @@ size_t sf_debug_size(sf_ctx *c, int what, int level) {
             return sizeof(float) * 6 * (size_t)d.G;
         case SF_DBG_REC: return sizeof(float) * SF_REC_PLANES * (size_t)d.N;
         case SF_DBG_ENERGY: return sizeof(double) * 6;
+        case SF_DBG_OCC: return c->single.fr[0].occ ? (size_t)d.N : 0;
     }
     return 0;
 }
@@ -1098,6 +1120,7 @@ static sf_status debug_copy(sf_ctx *c, int what, int level, void *host, size_t b
     switch (what) {
         case SF_DBG_TEX: ok = cp(F.tex + d.tex_off, 0, bytes); break;
         case SF_DBG_CMASK: ok = cp(F.cmask, 0, bytes); break;
+        case SF_DBG_OCC: ok = cp(F.occ, 0, bytes); break;
         case SF_DBG_WNODE: ok = cp(F.wnode, 0, bytes); break;
         case SF_DBG_REC: {
             // records are per pixel on the device, planes at the interface
@@ -1186,6 +1209,10 @@ sf_status sf_debug_run(sf_ctx *c, int stage, int level) {
         case SF_STAGE_FINISH: launch_finish_level(st, L); break;
         case SF_STAGE_MASKS: launch_level_masks(st, L); break;
         case SF_STAGE_STEP: enqueue_step(P, st, level, -1); break;
+        case SF_STAGE_OCC:
+            if (level == 0 || !P.fr[0].occ) return SF_ERR_INVALID_ARG;
+            launch_occ_next(st, L);
+            break;
         default: return SF_ERR_INVALID_ARG;
     }
     HIP_TRY(hipGetLastError());

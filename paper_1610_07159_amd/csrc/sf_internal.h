@@ -158,6 +158,12 @@ struct LevelArgs {
                            // (nullptr: none); the next finer level's is
                            // written into the same buffer after this level
     float *ill_e, *ill_t;  // its scratch: residual and horizontal blur
+    const unsigned char *occ;  // occlusion map of this level's pixels, 1 =
+                               // visible (nullptr: none)
+    unsigned char *occ_next;   // the next finer level's map, written after
+                               // this level (nullptr: none)
+    float *occ_pos;            // scratch: 10 planes of N (positions, disparities)
+    unsigned *occ_zb;          // scratch: 4 z-buffers of N (float bits)
     float *prev;           // temporal state of this level: G records of the
                            // previous solve's delta, then G of its total
     int W4, H4;            // size of the network's output (level 4)
@@ -235,6 +241,8 @@ void launch_finish_level(hipStream_t st, const Launch &L);
 // after a level (not the finest) the next finer level's map
 void launch_illum_zero(hipStream_t st, const Launch &L);
 void launch_illum_next(hipStream_t st, const Launch &L);
+// occlusion map of the next finer level from this level's final flow
+void launch_occ_next(hipStream_t st, const Launch &L);
 void launch_output(hipStream_t st, const Launch &L, float *depth,
                    float *flow3d, float *flows);
 TileCfg pick_tile(int s);

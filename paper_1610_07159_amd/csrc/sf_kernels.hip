@@ -2296,6 +2296,7 @@ __global__ __launch_bounds__(SF_BLOCK) void k_masks(KArg<B> ka) {
             sample3(a.tex + (long)cam * d.N, d.W, d.H, px, py, sm);
             I[cam] = sm.v[0];
         }
+        if (a.occ && !a.occ[(long)y * d.W + x]) V = false;
         float Ic[4] = {I[0], I[1], I[2], I[3]};
         if (a.illum) {
             const float cr = a.illum[(long)y * d.W + x];
@@ -2460,6 +2461,148 @@ __global__ __launch_bounds__(SF_BLOCK) void k_illum_zero(KArg<B> ka) {
     SF_BIND(ka);
     const long n = (long)bid * SF_BLOCK + threadIdx.x;
     if (n < a.d.N) a.illum[n] = 0.f;
+}
+
+// ---- occlusion maps (Sec. 5.3) ---------------------------------------------
+//
+// After a level (but the finest) the halfway pixel grid, triangulated (each
+// quad (x, y), (x+1, y), (x, y+1), (x+1, y+1) split along its
+// (x+1, y)-(x, y+1) diagonal), is rendered into the four views with a
+// z-buffer of stereo disparity D_t = P_Lt.x - P_Rt.x (larger = nearer).
+// A triangle is skipped if one of its edges is longer than OCC_EDGE px in
+// the view (it spans a depth discontinuity), a vertex has D_t <= 0 or its
+// area is zero; the pixel centres on or inside it take its barycentric
+// D_t and the largest value wins (atomic max on the float bits: exact for
+// positive floats and independent of the order).  A halfway pixel is
+// occluded if, in some view, its nearest pixel centre lies in the image and
+// 0 < D_t < (1 - OCC_TOL) z there.  The map is box-upsampled (fine pixel
+// (x, y) takes coarse (x/2, y/2), clamped) and removes the occluded pixels
+// from the next finer level's V(x).
+
+#define OCC_TOL 0.02f
+#define OCC_EDGE 2.0f
+
+// Positions of every pixel in the four views and its two disparities:
+// planes 2c, 2c + 1 = P_c.x, P_c.y; 8 = D_0; 9 = D_1.  Also clears the
+// four z-buffers.
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_occ_pos(KArg<B> ka) {
+    SF_BIND(ka);
+    const LevelDims &d = a.d;
+    __shared__ NodeStage S;
+    const int tiles_x = (d.W + TILE_PX - 1) / TILE_PX;
+    const int x0 = (bid % tiles_x) * TILE_PX, y0 = (bid / tiles_x) * TILE_PX;
+    stage_nodes(a, x0, y0, 0.f, S);
+    __syncthreads();
+    const int x = x0 + (threadIdx.x & (TILE_PX - 1));
+    const int y = y0 + (threadIdx.x / TILE_PX);
+    if (x < d.W && y < d.H) {
+        float f[6];
+        pixel_flows(a, x, y, S, f);
+        const long n = (long)y * d.W + x;
+        float P[8];
+#pragma unroll
+        for (int cam = 0; cam < 4; ++cam) {
+            P[2 * cam] = (((float)x + sgn(cam, 0) * f[0]) + sgn(cam, 1) * f[2]) + sgn(cam, 2) * f[4];
+            P[2 * cam + 1] = (((float)y + sgn(cam, 0) * f[1]) + sgn(cam, 1) * f[3]) + sgn(cam, 2) * f[5];
+            a.occ_pos[(long)(2 * cam) * d.N + n] = P[2 * cam];
+            a.occ_pos[(long)(2 * cam + 1) * d.N + n] = P[2 * cam + 1];
+            a.occ_zb[(long)cam * d.N + n] = 0u;
+        }
+        a.occ_pos[8L * d.N + n] = P[0] - P[2];  // L0.x - R0.x
+        a.occ_pos[9L * d.N + n] = P[4] - P[6];  // L1.x - R1.x
+    }
+}
+
+__device__ __forceinline__ float occ_edge(float ax, float ay, float bx, float by, float qx,
+                                          float qy) {
+    return (bx - ax) * (qy - ay) - (by - ay) * (qx - ax);
+}
+
+// Renders one triangle into the z-buffer `zb` (W x H).  The edge test also
+// rejects NaN coordinates; after it the bounding box spans at most three
+// pixel centres per axis.
+__device__ __forceinline__ void occ_triangle(int W, int H, unsigned *zb, float ax, float ay,
+                                             float ad, float bx, float by, float bd, float cx,
+                                             float cy, float cd) {
+    const float e2 = OCC_EDGE * OCC_EDGE;
+    const float lab = (bx - ax) * (bx - ax) + (by - ay) * (by - ay);
+    const float lbc = (cx - bx) * (cx - bx) + (cy - by) * (cy - by);
+    const float lca = (ax - cx) * (ax - cx) + (ay - cy) * (ay - cy);
+    if (!(lab <= e2 && lbc <= e2 && lca <= e2)) return;
+    if (!(ad > 0.f && bd > 0.f && cd > 0.f)) return;
+    const float area = occ_edge(ax, ay, bx, by, cx, cy);
+    if (area == 0.f) return;
+    const float sg = area < 0.f ? -1.f : 1.f;
+    const float lo_x = fminf(fminf(ax, bx), cx), hi_x = fmaxf(fmaxf(ax, bx), cx);
+    const float lo_y = fminf(fminf(ay, by), cy), hi_y = fmaxf(fmaxf(ay, by), cy);
+    if (hi_x < 0.f || hi_y < 0.f || lo_x > (float)(W - 1) || lo_y > (float)(H - 1)) return;
+    const int qx0 = max((int)ceilf(lo_x), 0), qx1 = min((int)floorf(hi_x), W - 1);
+    const int qy0 = max((int)ceilf(lo_y), 0), qy1 = min((int)floorf(hi_y), H - 1);
+    for (int qy = qy0; qy <= qy1; ++qy) {
+        for (int qx = qx0; qx <= qx1; ++qx) {
+            const float fx = (float)qx, fy = (float)qy;
+            const float e_bc = occ_edge(bx, by, cx, cy, fx, fy);
+            const float e_ca = occ_edge(cx, cy, ax, ay, fx, fy);
+            const float e_ab = occ_edge(ax, ay, bx, by, fx, fy);
+            if (sg * e_bc >= 0.f && sg * e_ca >= 0.f && sg * e_ab >= 0.f) {
+                // barycentric weights: the area opposite a vertex over the whole
+                const float z = (e_bc * ad + e_ca * bd + e_ab * cd) / area;
+                if (z > 0.f) atomicMax(zb + (long)qy * W + qx, __float_as_uint(z));
+            }
+        }
+    }
+}
+
+// One thread per (view, quad): the quad's two triangles in that view.
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_occ_raster(KArg<B> ka) {
+    SF_BIND(ka);
+    const LevelDims &d = a.d;
+    const long nq = (long)(d.W - 1) * (d.H - 1);
+    const long t = (long)bid * SF_BLOCK + threadIdx.x;
+    if (t >= 4 * nq) return;
+    const int cam = (int)(t / nq);
+    const long q = t % nq;
+    const int x = (int)(q % (d.W - 1)), y = (int)(q / (d.W - 1));
+    const float *X = a.occ_pos + (long)(2 * cam) * d.N;
+    const float *Y = X + d.N;
+    const float *D = a.occ_pos + (long)(8 + (cam >> 1)) * d.N;
+    const long ia = (long)y * d.W + x, ib = ia + 1, ic = ia + d.W, id = ic + 1;
+    unsigned *zb = a.occ_zb + (long)cam * d.N;
+    occ_triangle(d.W, d.H, zb, X[ia], Y[ia], D[ia], X[ib], Y[ib], D[ib], X[ic], Y[ic], D[ic]);
+    occ_triangle(d.W, d.H, zb, X[ib], Y[ib], D[ib], X[id], Y[id], D[id], X[ic], Y[ic], D[ic]);
+}
+
+// One thread per pixel of this level: the z-buffer test in the four views,
+// written to the fine pixels that box upsampling assigns to it.
+template <bool B>
+__global__ __launch_bounds__(SF_BLOCK) void k_occ_test(KArg<B> ka) {
+    SF_BIND(ka);
+    const LevelDims &d = a.d;
+    const long n = (long)bid * SF_BLOCK + threadIdx.x;
+    if (n >= d.N) return;
+    const int x = (int)(n % d.W), y = (int)(n / d.W);
+    bool vis = true;
+#pragma unroll
+    for (int cam = 0; cam < 4; ++cam) {
+        const float X = a.occ_pos[(long)(2 * cam) * d.N + n];
+        const float Y = a.occ_pos[(long)(2 * cam + 1) * d.N + n];
+        const float D = a.occ_pos[(long)(8 + (cam >> 1)) * d.N + n];
+        const float nx = floorf(X + 0.5f), ny = floorf(Y + 0.5f);
+        if (nx >= 0.f && nx <= (float)(d.W - 1) && ny >= 0.f && ny <= (float)(d.H - 1) &&
+            D > 0.f) {
+            const float z =
+                __uint_as_float(a.occ_zb[(long)cam * d.N + (long)ny * d.W + (long)nx]);
+            if (D < (1.f - OCC_TOL) * z) vis = false;
+        }
+    }
+    // fine pixels (xf, yf) with (min(xf / 2, W - 1), min(yf / 2, H - 1)) = (x, y);
+    // the finer level is at most 2 W + 1 by 2 H + 1 pixels
+    const int xa = 2 * x, xb = min(x == d.W - 1 ? a.Wf - 1 : 2 * x + 1, a.Wf - 1);
+    const int ya = 2 * y, yb = min(y == d.H - 1 ? a.Hf - 1 : 2 * y + 1, a.Hf - 1);
+    for (int yf = ya; yf <= yb; ++yf)
+        for (int xf = xa; xf <= xb; ++xf) a.occ_next[(long)yf * a.Wf + xf] = vis ? 1 : 0;
 }
 
 // ---- output: depth and 3D flow at level 0 -----------------------------------
@@ -2797,6 +2940,19 @@ void launch_illum_next(hipStream_t st, const Launch &L) {
     go(st, L, nr, k_illum_resid<true>, k_illum_resid<false>, SF_BLOCK, 0);
     go(st, L, nx, k_illum_blur_x<true>, k_illum_blur_x<false>, SF_BLOCK, 0);
     go(st, L, nu, k_illum_up<true>, k_illum_up<false>, SF_BLOCK, 0);
+}
+
+void launch_occ_next(hipStream_t st, const Launch &L) {
+    auto on = [](const LevelArgs &a) { return a.occ_next != nullptr; };
+    auto np = [on](const LevelArgs &a) { return on(a) ? pixel_tiles(a.d) : 0; };
+    auto nq = [on](const LevelArgs &a) {
+        const long q = 4L * (a.d.W - 1) * (a.d.H - 1);
+        return on(a) && q > 0 ? (int)((q + SF_BLOCK - 1) / SF_BLOCK) : 0;
+    };
+    auto nt = [on](const LevelArgs &a) { return on(a) ? (a.d.N + SF_BLOCK - 1) / SF_BLOCK : 0; };
+    go(st, L, np, k_occ_pos<true>, k_occ_pos<false>, SF_BLOCK, 0);
+    go(st, L, nq, k_occ_raster<true>, k_occ_raster<false>, SF_BLOCK, 0);
+    go(st, L, nt, k_occ_test<true>, k_occ_test<false>, SF_BLOCK, 0);
 }
 
 void launch_finish_level(hipStream_t st, const Launch &L) {

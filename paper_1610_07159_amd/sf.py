@@ -23,9 +23,10 @@ STATUS = {0: "SF_OK", -1: "SF_ERR_INVALID_ARG", -2: "SF_ERR_SIZE",
 # debug / stage enums (include/sf.h)
 SF_DBG_TEX, SF_DBG_CMASK, SF_DBG_WNODE, SF_DBG_BASE, SF_DBG_DELTA = 0, 1, 2, 3, 4
 SF_DBG_DX, SF_DBG_R, SF_DBG_Z, SF_DBG_Q, SF_DBG_DIAG = 5, 6, 7, 8, 9
-SF_DBG_REC, SF_DBG_P, SF_DBG_ENERGY = 10, 11, 12
+SF_DBG_REC, SF_DBG_P, SF_DBG_ENERGY, SF_DBG_OCC = 10, 11, 12, 13
 SF_STAGE_LEVEL_INIT, SF_STAGE_LINEARIZE, SF_STAGE_APPLY = 0, 1, 2
 SF_STAGE_PCG, SF_STAGE_GN, SF_STAGE_FINISH, SF_STAGE_MASKS, SF_STAGE_STEP = 3, 4, 5, 6, 7
+SF_STAGE_OCC = 8
 SF_KERNEL_APPLY, SF_KERNEL_LINEARIZE, SF_KERNEL_UPDATE, SF_KERNEL_RHS, SF_KERNEL_BLOCKS = 0, 1, 2, 3, 4
 SF_CNN_PARAMS = 39910
 SF_TR_INPUT, SF_TR_ACT, SF_TR_OUT, SF_TR_DOUT, SF_TR_DPRE, SF_TR_GRAD = 0, 1, 2, 3, 4, 5
@@ -50,7 +51,7 @@ class sf_calib(ctypes.Structure):
 
 _PARAM_INTS = ("levels", "grid_stride", "gn_iters", "pcg_iters",
                "max_backtracks", "init_mode", "exec_mode", "tile_mode",
-               "apply_mode", "temporal", "illum")
+               "apply_mode", "temporal", "illum", "occlusion")
 _PARAM_FLOATS = ("w_reg", "w_photo", "w_grad", "w_epi", "w_smooth", "w_mag",
                  "w_s", "w_m", "w_d", "m_s", "m_m", "m_d", "eps", "eps_p",
                  "st_gamma", "st_tau")
@@ -263,7 +264,7 @@ def sf_debug_size(ctx, what, level) -> int:
 
 
 _DTYPE = {SF_DBG_TEX: np.float32, SF_DBG_CMASK: np.uint8,
-          SF_DBG_ENERGY: np.float64}
+          SF_DBG_ENERGY: np.float64, SF_DBG_OCC: np.uint8}
 
 
 def sf_debug_read(ctx, what, level) -> np.ndarray:

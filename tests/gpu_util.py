@@ -8,13 +8,14 @@ import oracle.halfway as O
 PARAM_FIELDS = ("levels", "grid_stride", "gn_iters", "pcg_iters",
                 "max_backtracks", "w_reg", "w_photo", "w_grad", "w_epi",
                 "w_smooth", "w_mag", "w_s", "w_m", "w_d", "m_s", "m_m", "m_d",
-                "eps", "eps_p", "st_gamma", "st_tau", "illum")
+                "eps", "eps_p", "st_gamma", "st_tau", "illum", "occlusion")
 
 
 def oracle_params(**kw):
     out = {k: v for k, v in kw.items() if k in PARAM_FIELDS}
-    if "illum" in out:
-        out["illum"] = bool(out["illum"])
+    for k in ("illum", "occlusion"):
+        if k in out:
+            out[k] = bool(out[k])
     return O.Params(**out)
 
 

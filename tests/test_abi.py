@@ -51,6 +51,7 @@ def test_host_validation_without_gpu():
                        ("grid_stride", 0), ("m_m", 0.0), ("w_photo", -1.0),
                        ("max_backtracks", 9), ("exec_mode", 3), ("tile_mode", 5),
                        ("init_mode", 2), ("apply_mode", 3), ("apply_mode", -1), ("temporal", 2), ("illum", 2),
+                       ("occlusion", 2), ("occlusion", -1),
                        ("eps", float("nan"))):
         q = sf.sf_params_default(**{field: bad})
         assert lib.sf_create(ctypes.byref(h), 64, 48, ctypes.byref(q), None) == -1, field
