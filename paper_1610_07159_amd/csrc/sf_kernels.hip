@@ -286,9 +286,25 @@ __device__ double block_sum_partials(const float *part, int n) {
 template <bool B>
 using KArg = typename std::conditional<B, FrameMap, LevelArgs>::type;
 
+// XCD-aware block order of single-frame launches.  The dispatcher hands
+// workgroup b of a launch to XCD b mod 8, and each XCD has its own L2; this
+// bijection gives every XCD one contiguous range of logical blocks (XCD x
+// takes the ceil/floor(n/8) indices after those of XCDs 0..x-1), so
+// neighbouring tiles, whose halos overlap, run on the same XCD and share
+// its L2 (at 640x480 the level-0 PCG iteration fetches 30 % fewer bytes and
+// runs 6 % faster).  Batched launches keep the hardware order: there the
+// same remap, or one in chunks of 32 or 128 blocks, cut the fetched bytes
+// too but made the level-0 iteration 2-3 % slower.  Results do not depend
+// on which physical workgroup runs a logical block.
+__device__ __forceinline__ int xcd_block(int b, int n) {
+    const int q = n >> 3, r = n & 7;
+    const int x = b & 7, k = b >> 3;
+    return x * q + min(x, r) + k;
+}
+
 __device__ __forceinline__ void bind(const LevelArgs &ka, LevelArgs &a, int &bid, int &nblk) {
     a = ka;
-    bid = blockIdx.x;
+    bid = xcd_block(blockIdx.x, gridDim.x);
     nblk = gridDim.x;
 }
 __device__ __forceinline__ void bind(const FrameMap &m, LevelArgs &a, int &bid, int &nblk) {
