@@ -5,8 +5,9 @@ One "step" is one whole solve of one frame (pyramid, 5 levels x 10
 Gauss-Newton steps x 20 PCG iterations, step control, depth/3D-flow output)
 with the four input images already resident in device memory.  Prints one
 JSON line.  Besides the headline number it reports the roofline of the
-dominant kernel (the matrix-free H p of the PCG at the finest level, timed
-live with HIP events on the solver's stream) and, unless
+dominant kernel (the PCG iteration's H p at the finest level: node blocks
+by default, matrix-free with --apply-mode 0; timed live with HIP events on
+the solver's stream) and, unless
 --no-cpu-baseline, the FP64 CPU oracle timed on a bounded sample of the
 same workload on the host.
 """
@@ -46,8 +47,17 @@ WORKLOADS = {
                          "the stored initialiser (trained on 256 frames, seeds 0..255) with "
                          "the energy fallback, fewest GN steps per level reaching the plain "
                          "EPE; stride 4, 5 levels",
-                    width=640, height=480, n_eval=16,
+                    width=640, height=480, n_eval=16, weights="init_640x480.npy",
                     params=dict(levels=5, grid_stride=4, gn_iters=10, pcg_iters=20)),
+    "learned_hd": dict(desc="learned-init vs plain at equal EPE: 16 held-out 1280x720 "
+                            "generator frames (seeds 1000000..1000015, 80 px displacement, "
+                            "two moving blobs); plain = zero initialisation, 10 GN x 20 PCG "
+                            "per level; learned = the stored 1280x720 initialiser (trained on "
+                            "256 frames, seeds 0..255) with the energy fallback, fewest GN "
+                            "steps per level reaching the plain EPE; stride 4, 6 levels",
+                       width=1280, height=720, n_eval=16, weights="init_1280x720.npy",
+                       max_disp=80.0, blobs=2,
+                       params=dict(levels=6, grid_stride=4, gn_iters=10, pcg_iters=20)),
     "batch": dict(desc="batches of 64 frames, resolutions drawn by seed 3 from "
                        "320x240 / 640x480 / 960x540 / 1280x720 (4 / 5 / 5 / 6 "
                        "levels: 1 + floor(log2(W / 40))), displacement 30 px per "
@@ -518,6 +528,8 @@ def main():
     ap.add_argument("--tile-mode", type=int, default=1,
                     help="PCG tile shapes: 0 = default, 1 = autotuned (timed on the "
                          "warm-up solve), 2 / 3 / 4 = the alternative shapes")
+    ap.add_argument("--grid-stride", type=int, default=0,
+                    help="warp-grid stride of the single-frame workloads (0: the workload's)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter "
                          "calibration under rocprofv3 --pmc)")
@@ -554,6 +566,13 @@ def main():
         n_eval = WORKLOADS["learned"]["n_eval"]
         pre["eval"] = render_frames(640, 480, range(1_000_000, 1_000_000 + n_eval), True, 8,
                                     log=lambda m: None)
+    if args.workload == "learned_hd":
+        from paper_1610_07159_amd.train_init import render_frames
+        w = WORKLOADS["learned_hd"]
+        pre["eval"] = render_frames(w["width"], w["height"],
+                                    range(1_000_000, 1_000_000 + w["n_eval"]), True, 16,
+                                    log=lambda m: print(m, file=sys.stderr, flush=True),
+                                    max_disp=w["max_disp"], blobs=w["blobs"])
     import torch
     torch.cuda.set_device(0)
     if args.copy_probe_mib > 0:
@@ -568,8 +587,8 @@ def main():
         del a, b
     if args.workload == "batch":
         return run_batch(args, pre["batch"])
-    if args.workload == "learned":
-        return run_learned(args, pre["eval"])
+    if args.workload in ("learned", "learned_hd"):
+        return run_learned(args, pre["eval"], args.workload)
     if args.workload == "video":
         return run_video(args, pre["video"])
     if args.workload == "illum":
@@ -583,6 +602,8 @@ def main():
     w, imgs, calib, scene = make_workload(args.workload)
     W, H = w["width"], w["height"]
     params = dict(w["params"])
+    if args.grid_stride:
+        params["grid_stride"] = args.grid_stride
     img = torch.from_numpy(imgs).cuda().contiguous()
     params["apply_mode"] = args.apply_mode
     solver = SceneFlowSolver(W, H, exec_mode=args.exec_mode, tile_mode=args.tile_mode,
@@ -642,7 +663,8 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": (measured_traffic(args.workload, args.apply_mode)
-                                 if args.exec_mode == 0 else None),
+                                 if args.exec_mode == 0 and params["grid_stride"]
+                                 == w["params"]["grid_stride"] else None),
                      "bytes_per_launch": bytes_apply,
                      "avg_us_per_launch": round(bytes_apply / achieved / 1e3, 2),
                      "apply_us_per_level": per_level},
@@ -660,14 +682,14 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def run_learned(args, frames):
+def run_learned(args, frames, name="learned"):
     """Equal-EPE comparison of the learned initialiser with the plain
     solver; value = ms/frame of the learned solve at the plain EPE."""
     from paper_1610_07159_amd import train_init as T
-    w = WORKLOADS["learned"]
+    w = WORKLOADS[name]
     W, H = w["width"], w["height"]
     params = dict(w["params"], apply_mode=args.apply_mode)
-    weights = np.load(os.path.join(ROOT, "paper_1610_07159_amd", "weights", "init_640x480.npy"),
+    weights = np.load(os.path.join(ROOT, "paper_1610_07159_amd", "weights", w["weights"]),
                       allow_pickle=False)
     plain, _, ms_plain = T.solve_flows(frames, W, H, timed=True, **params)
     epe_plain = float(np.mean([T.epe(f, fr["truth"], W, H) for f, fr in zip(plain, frames)]))

@@ -50,8 +50,8 @@ def box_restrict(a, level=LEVEL_IN):
 
 def _render(args):
     from synth import make_frame, sized_config
-    W, H, seed, truth = args
-    imgs, calib, scene = make_frame(sized_config(W, H), seed)
+    W, H, seed, truth, max_disp, blobs = args
+    imgs, calib, scene = make_frame(sized_config(W, H, max_disp=max_disp, n_blobs=blobs), seed)
     out = dict(imgs=imgs, calib=calib, seed=seed)
     if truth:
         pos, ok = scene.halfway_truth()
@@ -59,9 +59,11 @@ def _render(args):
     return out
 
 
-def render_frames(W, H, seeds, truth, workers, log=print):
+def render_frames(W, H, seeds, truth, workers, log=print, max_disp=None, blobs=0):
+    """Generator frames of size W x H (displacement 30 px per 640 px of
+    width unless max_disp is given; blobs independently moving blobs)."""
     from concurrent.futures import ProcessPoolExecutor
-    jobs = [(W, H, s, truth) for s in seeds]
+    jobs = [(W, H, s, truth, max_disp, blobs) for s in seeds]
     out = []
     with ProcessPoolExecutor(max_workers=workers) as ex:
         for f in ex.map(_render, jobs, chunksize=1):
@@ -171,6 +173,10 @@ def main():
     ap.add_argument("--eval", type=int, default=16)
     ap.add_argument("--width", type=int, default=640)
     ap.add_argument("--height", type=int, default=480)
+    ap.add_argument("--levels", type=int, default=SCHEDULE["levels"])
+    ap.add_argument("--max-disp", type=float, default=None,
+                    help="largest image displacement in px (default 30 per 640 px of width)")
+    ap.add_argument("--blobs", type=int, default=0, help="independently moving blobs")
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=2e-3)
@@ -180,17 +186,19 @@ def main():
     args = ap.parse_args()
     log = lambda m: print(m, flush=True)  # noqa: E731
     W, H = args.width, args.height
+    sched_full = dict(SCHEDULE, levels=args.levels)
+    scene = dict(max_disp=args.max_disp, blobs=args.blobs)
     t0 = time.time()
-    train_frames = render_frames(W, H, range(args.frames), False, args.workers, log)
+    train_frames = render_frames(W, H, range(args.frames), False, args.workers, log, **scene)
     log(f"rendered {len(train_frames)} training frames in {time.time() - t0:.0f} s")
     t1 = time.time()
     eval_frames = render_frames(W, H, range(1_000_000, 1_000_000 + args.eval), True,
-                                args.workers, log)
+                                args.workers, log, **scene)
     log(f"rendered {len(eval_frames)} evaluation frames with truth in {time.time() - t1:.0f} s")
 
     import torch
     torch.cuda.set_device(0)
-    flows, _, _ = solve_flows(train_frames, W, H, **SCHEDULE)
+    flows, _, _ = solve_flows(train_frames, W, H, **sched_full)
     x = np.stack([box_restrict(f["imgs"]) for f in train_frames]).astype(np.float32)
     y = np.stack([box_restrict(fl) / (1 << LEVEL_IN) for fl in flows]).astype(np.float32)
     log(f"targets from the plain solver: {y.shape}")
@@ -199,11 +207,11 @@ def main():
     log(f"trained in {time.time() - t2:.1f} s")
     np.save(args.out, params)
 
-    plain, _, ms_plain = solve_flows(eval_frames, W, H, timed=True, **SCHEDULE)
+    plain, _, ms_plain = solve_flows(eval_frames, W, H, timed=True, **sched_full)
     epe_plain = float(np.mean([epe(fl, f["truth"], W, H) for fl, f in zip(plain, eval_frames)]))
     sweep = []
-    for n in range(1, SCHEDULE["gn_iters"] + 1):
-        sched = dict(SCHEDULE, gn_iters=n)
+    for n in range(1, sched_full["gn_iters"] + 1):
+        sched = dict(sched_full, gn_iters=n)
         fl, used, ms = solve_flows(eval_frames, W, H, init_mode=1, weights=params, timed=True,
                                    **sched)
         e = float(np.mean([epe(a, f["truth"], W, H) for a, f in zip(fl, eval_frames)]))
@@ -212,15 +220,16 @@ def main():
         log(f"learned init, {n} GN/level: EPE {e:.4f} px, {ms:.2f} ms/frame, "
             f"prediction kept on {sum(used)}/{len(used)} frames")
     zero_sweep = []
-    for n in range(1, SCHEDULE["gn_iters"] + 1):
-        fl, _, ms = solve_flows(eval_frames, W, H, timed=True, **dict(SCHEDULE, gn_iters=n))
+    for n in range(1, sched_full["gn_iters"] + 1):
+        fl, _, ms = solve_flows(eval_frames, W, H, timed=True, **dict(sched_full, gn_iters=n))
         e = float(np.mean([epe(a, f["truth"], W, H) for a, f in zip(fl, eval_frames)]))
         zero_sweep.append(dict(gn_iters=n, epe_px=round(e, 4), ms_per_frame=round(ms, 3)))
     reach = next((s for s in sweep if s["epe_px"] <= epe_plain), None)
     report = dict(
-        frames=args.frames, eval_frames=args.eval, size=f"{W}x{H}", schedule=SCHEDULE,
+        frames=args.frames, eval_frames=args.eval, size=f"{W}x{H}", schedule=sched_full,
+        max_disp=args.max_disp, blobs=args.blobs,
         epochs=args.epochs, batch=args.batch, lr=args.lr, loss_curve=[round(c, 5) for c in curve],
-        plain=dict(gn_iters=SCHEDULE["gn_iters"], epe_px=round(epe_plain, 4),
+        plain=dict(gn_iters=sched_full["gn_iters"], epe_px=round(epe_plain, 4),
                    ms_per_frame=round(ms_plain, 3)),
         learned_sweep=sweep, zero_init_sweep=zero_sweep,
         equal_epe=(dict(gn_iters=reach["gn_iters"], ms_per_frame=reach["ms_per_frame"],
