@@ -224,3 +224,38 @@ def test_random_network_fallback_energies_match_oracle():
     assert ep == pytest.approx(ep_ref, rel=2e-3)
     if abs(ep_ref - ez_ref) > 5e-3 * ez_ref:
         assert used == (ep_ref < ez_ref)
+
+
+# ---- the stored networks -------------------------------------------------------
+
+@pytest.mark.parametrize("W,H,levels,max_disp,blobs,name", [
+    (640, 480, 5, None, 0, "init_640x480.npy"),
+    (1280, 720, 6, 80.0, 2, "init_1280x720.npy")])
+def test_stored_initialiser_is_kept_and_starts_lower(W, H, levels, max_disp, blobs, name):
+    """Each shipped network on a frame outside its training and evaluation
+    seeds: the fallback keeps the prediction, and after two Gauss-Newton
+    steps per level the solve ends at a lower energy than from zero."""
+    import os
+    from paper_1610_07159_amd import sf
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    weights = np.load(os.path.join(root, "paper_1610_07159_amd", "weights", name),
+                      allow_pickle=False)
+    imgs, calib, _ = make_frame(sized_config(W, H, max_disp=max_disp, n_blobs=blobs),
+                                1_000_050)
+    prm = dict(levels=levels, grid_stride=4, gn_iters=2, pcg_iters=20)
+    final = {}
+    for mode in (0, 1):
+        g = GpuCase(imgs, calib, exec_mode=0, init_mode=mode, **prm)
+        try:
+            if mode:
+                sf.sf_set_initializer(g.ctx, weights)
+            g.solve()
+            log, code = g.log()
+            if mode:
+                used, ep, ez = sf.sf_get_init_result(g.ctx)
+        finally:
+            g.close()
+        assert code == 0
+        final[mode] = log[-1]["energy_after"]
+    assert used and ep < ez
+    assert final[1] < final[0]

@@ -196,3 +196,19 @@ def test_fallback_prefers_the_true_motion_and_rejects_garbage():
     garbage = np.random.default_rng(11).normal(0, 5.0, (6, grid.G))
     base, used, e_g, e_z2 = C.choose_init(li, grid, F_l, p, garbage)
     assert not used and e_g >= e_z2 and np.all(base == 0)
+
+
+@pytest.mark.parametrize("name", ["init_640x480", "init_1280x720"])
+def test_stored_networks_load_safely(name):
+    """The shipped parameters are plain float32 arrays of the network's size
+    (no pickled objects), with a report of their equal-EPE evaluation."""
+    import json
+    import os
+    root = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_1610_07159_amd", "weights")
+    w = np.load(os.path.join(root, name + ".npy"), allow_pickle=False)
+    assert w.dtype == np.float32 and w.shape == (C.N_PARAMS,)
+    assert np.isfinite(w).all()
+    with open(os.path.join(root, name + "_report.json")) as f:
+        rep = json.load(f)
+    assert rep["equal_epe"]["gn_iters"] < rep["plain"]["gn_iters"]
