@@ -31,11 +31,15 @@ def _check_frame(log, rec, flows, res, e_tol=1e-4, f_tol=0.02):
     assert err <= f_tol, err
 
 
-@pytest.mark.parametrize("apply,stride", [(0, 4), (2, 4), (2, 8)])
-def test_sequence_parity(apply, stride):
+@pytest.mark.parametrize("apply,stride,extra", [
+    (0, 4, {}), (2, 4, {}), (2, 8, {}),
+    # every map of Sec. 5.3 at once: illumination correction and occlusion
+    # maps on top of the temporal initialisation
+    (2, 4, dict(illum=1, occlusion=1))])
+def test_sequence_parity(apply, stride, extra):
     frames, calib = _sequence()
     prm = dict(levels=3, grid_stride=stride, gn_iters=3, pcg_iters=8, apply_mode=apply,
-               temporal=1)
+               temporal=1, **extra)
     p = oracle_params(**prm)
     recs = []
     res = O.solve_sequence([f.astype(np.float64) for f in frames], calib, p, record=recs)
