@@ -435,7 +435,9 @@ def test_generator_plane_truth_matches_closed_form():
     cf = _plane_closed_form(grid)
     got = np.concatenate([s.reshape(2, -1), m.reshape(2, -1), d.reshape(2, -1)])
     np.testing.assert_allclose(got, cf, atol=1e-8)
-    # spot values printed in the survey of the closed form
+    # by hand: D_t = f B / Z_t = 60 * 0.1 / Z_t with Z_0 = 2 m and Z_1 = 2.02 m;
+    # D_0 = -2 s_x + 2 d_x and D_1 = -2 s_x - 2 d_x (Eqs. (1)-(6)), so
+    # s_x = -(D_0 + D_1) / 4 and d_x = (D_0 - D_1) / 4
     assert cf[0, 0] == pytest.approx(-1.492574, abs=1e-6)
     assert cf[4, 0] == pytest.approx(0.0074257, abs=1e-7)
 
