@@ -26,10 +26,15 @@ matrix-free).  Readings of points the paper leaves open are marked
 "reading:" where they are applied.
 
 Parity pins: every function here is pinned by a test in tests/test_oracle_*.py
-except the structure-tensor smoothness weight w_i (`node_weights`): the paper
-names only its ingredients (eigenvalues of a 3x3-window autocorrelation
-matrix, high for featureless regions), so its formula is a reading and its
-value is "parity unpinned"; tests pin only that it is computed as stated.
+against closed forms, library routines, finite differences or invariants.
+The structure-tensor smoothness weight w_i (`node_weights`) is the one
+reading of a formula the paper does not print (it names only the
+ingredients: eigenvalues of a 3x3-window autocorrelation matrix, high for
+featureless regions); its ingredients are pinned (the warp, the gradient
+convention, the window and its centre, the smaller eigenvalue against
+numpy.linalg.eigvalsh and a hand-derived quadratic-image tensor, the 4^l
+scaling of tau_l), while the choice of the map w = 1 + gamma exp(-l / tau)
+itself has no external truth.
 """
 from __future__ import annotations
 
@@ -734,13 +739,17 @@ def masks(li: LevelImages, grid: Grid, total, p: Params, occ=None):
 def node_weights(li: LevelImages, grid: Grid, total, level, p: Params):
     """Smoothness weight w_i of Eq. (14) (Sec. 4.3): structure-tensor
     analysis of a 3x3 pixel window at each node.
-    reading (formula not given by the paper; parity unpinned in value):
+    reading (the paper does not print the formula; see the module notes
+    for what pins it):
     I_bar = mean of the four images warped to the halfway domain by the
     level-start flow; A_i = sum over the 3x3 window around the node's
-    rounded position (indices clamped) of grad I_bar grad I_bar^T, with
-    the gradient-image convention of `image_gradients`; lambda_min = the
+    rounded position of grad I_bar grad I_bar^T, with the gradient-image
+    convention of `image_gradients`; the rounded position is clamped into
+    the image (the last node row or column can lie beyond it) and window
+    rows or columns beyond the border repeat the border; lambda_min = the
     smaller eigenvalue; w_i = 1 + gamma exp(-lambda_min / tau_l) with
-    tau_l = st_tau 4^l.  High for featureless regions as required."""
+    tau_l = st_tau 4^l (squared gradients grow fourfold per coarser level
+    at equal structure).  High for featureless regions as required."""
     flows = grid.to_pixels(total)
     px, py = grid.pixel_xy()
     P = positions(px, py, flows)

@@ -893,3 +893,175 @@ def test_occlusion_solve_of_the_translating_plane_is_unchanged():
         p = O.Params(levels=3, grid_stride=8, gn_iters=2, pcg_iters=6, occlusion=on)
         out.append(O.solve(imgs, calib, p)["total"])
     np.testing.assert_array_equal(out[0], out[1])
+
+
+# --------------------------------------------------------------------------
+# Smoothness weights w_i (Sec. 4.3): structure tensor of the mean warped
+# image over a 3x3 window at the node, smaller eigenvalue, w = 1 + gamma
+# exp(-lambda_min / tau_l).  The map from lambda_min to w is the library's
+# reading; every ingredient is pinned here: the warp, the gradient
+# convention, the window and its centre, the eigenvalue, tau_l.
+# --------------------------------------------------------------------------
+
+def _quadratic(a, b, ox=0.0, oy=0.0, H=40, W=56):
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    return a * (x - ox) ** 2 + b * (y - oy) ** 2
+
+
+def test_node_weights_constant_and_ramp_are_featureless():
+    """A constant image and a linear ramp have a rank-deficient structure
+    tensor (lambda_min = 0), so every node gets 1 + gamma."""
+    p = O.Params(st_gamma=4.0, st_tau=1e-3)
+    grid = O.Grid(56, 40, 4)
+    y, x = np.mgrid[0:40, 0:56].astype(np.float64)
+    for img in (np.full((40, 56), 0.42), 0.01 * x - 0.02 * y + 0.3):
+        li = O.LevelImages.build(np.stack([img] * 4))
+        w = O.node_weights(li, grid, np.zeros((6, grid.G)), 0, p)
+        np.testing.assert_allclose(w, 1.0 + p.st_gamma, rtol=0, atol=1e-9)
+
+
+def test_node_weights_quadratic_closed_form():
+    """I = a x^2 + b y^2: inside the image the central differences are
+    exactly 2 a x and 2 b y, so the 3x3 window at pixel (cx, cy) sums to
+    A = 4 [[a^2 (9 cx^2 + 6), 9 a b cx cy], [9 a b cx cy, b^2 (9 cy^2 + 6)]]
+    (sum over dx in {-1, 0, 1} of (cx + dx)^2 = 3 cx^2 + 2).  Nodes sit at
+    (i + 1/2) s - 1/2 and the window is centred on the rounded position.
+    Camera c sees the quadratic Q_c = a_c x^2 + b_c y^2 shifted by the
+    integer offset that the flows (s, m, d) put on it (Eqs. (1)-(6)), so the
+    mean warped image is the quadratic with the mean coefficients a, b
+    wherever no sample is clamped (unwarped, the mean would carry a linear
+    term, since the a_c differ)."""
+    ac = 1e-3 * np.array([1.0, 1.3, 0.7, 1.0])
+    bc = -7e-4 * np.array([1.0, 0.8, 1.2, 1.0])
+    a, b = ac.mean(), bc.mean()
+    flows = np.array([1.0, 0.0, 0.0, 1.0, 1.0, -1.0])   # s, m, d (x, y)
+    signs = np.array([[-1, -1, 1], [1, -1, -1], [-1, 1, -1], [1, 1, 1]], float)
+    imgs = []
+    for c in range(4):
+        off = signs[c, 0] * flows[0:2] + signs[c, 1] * flows[2:4] + signs[c, 2] * flows[4:6]
+        imgs.append(_quadratic(ac[c], bc[c], off[0], off[1]))   # I_c(x + off) = Q_c(x)
+    li = O.LevelImages.build(np.stack(imgs))
+    for s in (4, 5):
+        grid = O.Grid(56, 40, s)
+        total = np.repeat(flows[:, None], grid.G, 1)
+        nx, ny = grid.node_xy()
+        cx = np.floor(nx + 0.5)
+        cy = np.floor(ny + 0.5)
+        A = 4.0 * np.array([[a * a * (9 * cx ** 2 + 6), 9 * a * b * cx * cy],
+                            [9 * a * b * cx * cy, b * b * (9 * cy ** 2 + 6)]])
+        lmin = np.array([np.linalg.eigvalsh(A[:, :, k])[0] for k in range(grid.G)])
+        # the window and its central differences stay 3 px inside the image
+        # (the warps move samples by up to 3 px)
+        inner = (cx >= 5) & (cx <= 56 - 6) & (cy >= 5) & (cy <= 40 - 6)
+        assert inner.sum() >= 20
+        for tau in (1e-5, 2e-5):
+            p = O.Params(st_gamma=4.0, st_tau=tau)
+            w = O.node_weights(li, grid, total, 0, p)
+            want = 1.0 + 4.0 * np.exp(-lmin / tau)
+            np.testing.assert_allclose(w[inner], want[inner], rtol=1e-12)
+            # the weights are not saturated: they distinguish lambda_min
+            # from lambda_max and from an off-centre window
+            assert np.ptp(want[inner]) > 0.3
+
+
+def test_node_weights_match_eigvalsh_on_random_images():
+    """Random smooth images at zero flow: the mean warped image is the mean
+    of the four images (exact samples), its gradients are numpy.gradient's,
+    and the window tensor's smaller eigenvalue comes from
+    numpy.linalg.eigvalsh.  A node whose rounded position falls outside the
+    image (the last node row or column when the stride does not divide the
+    size) is centred on the nearest border pixel, and window rows or
+    columns beyond the border repeat the border."""
+    rng = _rng(40)
+    imgs = _smooth_images(rng, 30, 44) * 0.05
+    li = O.LevelImages.build(imgs)
+    p = O.Params(st_gamma=4.0, st_tau=2e-5)
+    for s in (3, 4, 8):
+        grid = O.Grid(44, 30, s)
+        w = O.node_weights(li, grid, np.zeros((6, grid.G)), 0, p)
+        gy, gx = np.gradient(imgs.mean(0))
+        nx, ny = grid.node_xy()
+        want = np.empty(grid.G)
+        for k in range(grid.G):
+            cx = min(int(np.floor(nx[k] + 0.5)), 43)
+            cy = min(int(np.floor(ny[k] + 0.5)), 29)
+            A = np.zeros((2, 2))
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    yy = min(max(cy + dy, 0), 29)
+                    xx = min(max(cx + dx, 0), 43)
+                    g = np.array([gx[yy, xx], gy[yy, xx]])
+                    A += np.outer(g, g)
+            want[k] = 1.0 + 4.0 * math.exp(-max(np.linalg.eigvalsh(A)[0], 0.0) / 2e-5)
+        np.testing.assert_allclose(w, want, rtol=1e-10)
+        assert np.ptp(w) > 0.3
+
+
+def test_node_weights_tau_scales_four_per_level():
+    """Gradients double per coarser level at equal structure (squared: x4),
+    so tau_l = tau 4^l makes level l on an image scaled by 2^l give the
+    level-0 weights of the unscaled image."""
+    imgs = _smooth_images(_rng(41), 30, 44) * 0.05
+    grid = O.Grid(44, 30, 4)
+    p = O.Params(st_gamma=4.0, st_tau=2e-5)
+    w0 = O.node_weights(O.LevelImages.build(imgs), grid, np.zeros((6, grid.G)), 0, p)
+    assert np.ptp(w0) > 0.3
+    for l in (1, 2, 3):
+        wl = O.node_weights(O.LevelImages.build(imgs * 2.0 ** l), grid,
+                            np.zeros((6, grid.G)), l, p)
+        np.testing.assert_allclose(wl, w0, rtol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# E_smooth (Eq. (14)) and E_mag (Eq. (18)): values in closed form
+# --------------------------------------------------------------------------
+
+def test_smooth_energy_of_a_delta_ramp():
+    """Delta_f = c_f i + e_f j on node (i, j): every horizontal neighbour
+    pair differs by c_f and every vertical one by e_f.  Summing over ordered
+    pairs as Eq. (14) is written, node n contributes
+    w_n (h_n sum_f w_f c_f^2 + v_n sum_f w_f e_f^2), with h_n / v_n its
+    number of horizontal / vertical neighbours (2 inside, 1 on the border
+    rows or columns).  Over ordered pairs w_i and w_j weightings give the
+    same sum, so only the pair count and the per-component weights are
+    at stake.  Evaluated through energy() on a non-zero, rough base: the
+    term acts on the deltas, not the totals."""
+    p = O.Params()
+    imgs = _smooth_images(_rng(42), 28, 40)
+    for (W, H, s) in ((40, 28, 4), (40, 28, 8), (40, 28, 13)):
+        grid = O.Grid(W, H, s)
+        rng = _rng(43 + s)
+        base = rng.normal(scale=2.0, size=(6, grid.G))
+        wnode = rng.uniform(1.0, 5.0, grid.G)
+        c = rng.normal(size=6)
+        e = rng.normal(size=6)
+        j, i = np.mgrid[0:grid.Gy, 0:grid.Gx]
+        delta = c[:, None] * i.reshape(-1)[None] + e[:, None] * j.reshape(-1)[None]
+        hn = (np.minimum(i, 1) + np.minimum(grid.Gx - 1 - i, 1)).reshape(-1)
+        vn = (np.minimum(j, 1) + np.minimum(grid.Gy - 1 - j, 1)).reshape(-1)
+        wf = np.array([p.w_s, p.w_s, p.w_m, p.w_m, p.w_d, p.w_d])
+        want = float((wnode * (hn * (wf * c * c).sum() + vn * (wf * e * e).sum())).sum())
+        ls = _level(imgs, s, base=base, wnode=wnode)
+        got = O.energy(ls, delta, p)["smooth"]
+        assert got == pytest.approx(want, rel=1e-12)
+        # a constant delta is not penalised at all, whatever the base
+        assert O.energy(ls, np.repeat(c[:, None], grid.G, 1), p)["smooth"] == \
+            pytest.approx(0.0, abs=1e-20)
+
+
+def test_magnitude_energy_of_a_constant_delta():
+    """Delta_f = c_f on every node gives E_mag = G sum_f m_f c_f^2, the same
+    on any base (the term acts on the deltas: Sec. 5.1 asks only the deltas
+    to stay small), and zero for a zero delta on a large base."""
+    p = O.Params()
+    imgs = _smooth_images(_rng(44), 24, 32)
+    grid = O.Grid(32, 24, 4)
+    c = _rng(45).normal(size=6)
+    mf = np.array([p.m_s, p.m_s, p.m_m, p.m_m, p.m_d, p.m_d])
+    want = grid.G * float((mf * c * c).sum())
+    delta = np.repeat(c[:, None], grid.G, 1)
+    for scale in (0.0, 1.0, 5.0):
+        base = _rng(46).normal(scale=scale, size=(6, grid.G))
+        ls = _level(imgs, 4, base=base)
+        assert O.energy(ls, delta, p)["mag"] == pytest.approx(want, rel=1e-12)
+        assert O.energy(ls, np.zeros((6, grid.G)), p)["mag"] == 0.0
