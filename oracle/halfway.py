@@ -1140,10 +1140,18 @@ def output(grid: Grid, total, calib: Calib):
     left camera; depth = Z_0 and flow3d = X_1 - X_0 (reading of "dense 3D
     geometry and its motion").  Returns depth (H, W), flow3d (3, H, W) and
     the per-pixel flows (6, H, W)."""
+    flows = grid.to_pixels(total)
+    return output_from_flows(flows, grid.W, grid.H, calib)
+
+
+def output_from_flows(flows, W, H, calib):
+    """`output` for per-pixel flows (6, H*W) (s_x, s_y, m_x, m_y, d_x, d_y
+    planes of a W x H level-0 image) instead of node totals."""
     if isinstance(calib, dict):
         calib = Calib.from_dict(calib)
-    flows = grid.to_pixels(total)
-    px, py = grid.pixel_xy()
+    flows = np.asarray(flows, np.float64).reshape(6, -1)
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    px, py = x.reshape(-1), y.reshape(-1)
     P = positions(px, py, flows)
     Xs = []
     for cl, cr in ((0, 1), (2, 3)):
@@ -1153,9 +1161,9 @@ def output(grid: Grid, total, calib: Calib):
         X = np.stack([(P[cl, 0] - calib.cx) * Z / calib.fx,
                       (P[cl, 1] - calib.cy) * Z / calib.fy, Z])
         Xs.append(X)
-    depth = Xs[0][2].reshape(grid.H, grid.W)
-    flow3d = (Xs[1] - Xs[0]).reshape(3, grid.H, grid.W)
-    return depth, flow3d, flows.reshape(6, grid.H, grid.W)
+    depth = Xs[0][2].reshape(H, W)
+    flow3d = (Xs[1] - Xs[0]).reshape(3, H, W)
+    return depth, flow3d, flows.reshape(6, H, W)
 
 
 def residual_count(grid: Grid):

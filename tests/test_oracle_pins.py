@@ -1065,3 +1065,34 @@ def test_magnitude_energy_of_a_constant_delta():
         ls = _level(imgs, 4, base=base)
         assert O.energy(ls, delta, p)["mag"] == pytest.approx(want, rel=1e-12)
         assert O.energy(ls, np.zeros((6, grid.G)), p)["mag"] == 0.0
+
+
+def test_output_recovers_random_points_with_distinct_focal_lengths():
+    """Dense geometry and motion (Sec. 3): for every halfway pixel x pick a
+    depth Z_0 and a 3D motion M, place the point (X, Y, Z_0) whose four
+    projections into the rectified pair at t and t + 1 (focal lengths
+    f_x != f_y, principal point off-centre, baseline B along x) average to
+    x, derive the halfway flows from the four positions, and require the
+    output to return Z_0 and M exactly."""
+    rng = _rng(47)
+    H, W = 12, 16
+    fx, fy, cx, cy, B = 70.0, 83.0, 7.3, 4.1, 0.12
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    Z0 = rng.uniform(1.5, 4.0, (H, W))
+    M = rng.normal(scale=0.05, size=(3, H, W))
+    Z1 = Z0 + M[2]
+    # mean of the four x projections: fx/4 [ (2X - B)/Z0 + (2 (X + Mx) - B)/Z1 ] + cx
+    a, b = 1.0 / Z0, 1.0 / Z1
+    X = ((x - cx) * 4.0 / fx + B * a - (2.0 * M[0] - B) * b) / (2.0 * (a + b))
+    Y = ((y - cy) * 2.0 / fy - M[1] * b) / (a + b)
+    P = np.array([[fx * X / Z0 + cx, fy * Y / Z0 + cy],
+                  [fx * (X - B) / Z0 + cx, fy * Y / Z0 + cy],
+                  [fx * (X + M[0]) / Z1 + cx, fy * (Y + M[1]) / Z1 + cy],
+                  [fx * (X + M[0] - B) / Z1 + cx, fy * (Y + M[1]) / Z1 + cy]])
+    np.testing.assert_allclose(P[:, 0].mean(0), x, atol=1e-12)
+    np.testing.assert_allclose(P[:, 1].mean(0), y, atol=1e-12)
+    s, m, d = halfway_flows_from_positions(P)
+    flows = np.concatenate([s, m, d]).reshape(6, -1)
+    depth, flow3d, _ = O.output_from_flows(flows, W, H, O.Calib(fx, fy, cx, cy, B))
+    np.testing.assert_allclose(depth, Z0, rtol=1e-12)
+    np.testing.assert_allclose(flow3d, M, atol=1e-12)
