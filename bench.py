@@ -30,31 +30,32 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "vga": dict(desc="640x480 float32 quadruple, smooth Gaussian depth 1.5-4 m, "
                      "4-octave value-noise texture, smooth 3D motion up to 30 px, "
-                     "noise sigma 0.01; stride 4, 5 levels, 10 GN x 20 PCG",
+                     "noise sigma 0.01",
                 width=640, height=480, seed=1,
                 params=dict(levels=5, grid_stride=4, gn_iters=10, pcg_iters=20)),
-    "tiny": dict(desc="64x48 translating textured plane; stride 8, 3 levels, "
-                      "5 GN x 10 PCG",
+    "tiny": dict(desc="64x48 translating textured plane",
                  width=64, height=48, seed=0,
                  params=dict(levels=3, grid_stride=8, gn_iters=5, pcg_iters=10)),
     "hd": dict(desc="1280x720 float32 quadruple, up to 80 px displacement, two "
-                    "moving blobs; stride 4, 6 levels, 10 GN x 20 PCG",
+                    "moving blobs",
                width=1280, height=720, seed=2,
                params=dict(levels=6, grid_stride=4, gn_iters=10, pcg_iters=20)),
     "learned": dict(desc="learned-init vs plain at equal EPE: 16 held-out 640x480 "
                          "generator frames (seeds 1000000..1000015, 30 px displacement); "
-                         "plain = zero initialisation, 10 GN x 20 PCG per level; learned = "
-                         "the stored initialiser (trained on 256 frames, seeds 0..255) with "
-                         "the energy fallback, fewest GN steps per level reaching the plain "
-                         "EPE; stride 4, 5 levels",
+                         "target = mean EPE of the plain solver (zero initialisation) at "
+                         "10 GN x 20 PCG per level; plain and learned (the stored "
+                         "initialiser, trained on 256 frames, seeds 0..255, with the energy "
+                         "fallback) each at the fewest GN steps per level reaching it; "
+                         "stride 4, 5 levels",
                     width=640, height=480, n_eval=16, weights="init_640x480.npy",
                     params=dict(levels=5, grid_stride=4, gn_iters=10, pcg_iters=20)),
     "learned_hd": dict(desc="learned-init vs plain at equal EPE: 16 held-out 1280x720 "
                             "generator frames (seeds 1000000..1000015, 80 px displacement, "
-                            "two moving blobs); plain = zero initialisation, 10 GN x 20 PCG "
-                            "per level; learned = the stored 1280x720 initialiser (trained on "
-                            "256 frames, seeds 0..255) with the energy fallback, fewest GN "
-                            "steps per level reaching the plain EPE; stride 4, 6 levels",
+                            "two moving blobs); target = mean EPE of the plain solver (zero "
+                            "initialisation) at 10 GN x 20 PCG per level; plain and learned "
+                            "(the stored 1280x720 initialiser, trained on 256 frames, seeds "
+                            "0..255, with the energy fallback) each at the fewest GN steps "
+                            "per level reaching it; stride 4, 6 levels",
                        width=1280, height=720, n_eval=16, weights="init_1280x720.npy",
                        max_disp=80.0, blobs=2,
                        params=dict(levels=6, grid_stride=4, gn_iters=10, pcg_iters=20)),
@@ -66,6 +67,13 @@ WORKLOADS = {
                        "10 GN x 20 PCG, one HIP graph per batch",
                   n_frames=64, seed=3,
                   params=dict(levels=6, grid_stride=4, gn_iters=10, pcg_iters=20)),
+    "batch_learned": dict(desc="learned-init + batched vs plain batched at equal EPE: the "
+                               "batched workload's 64 frames (320x240 frames have 4 levels "
+                               "and start from zero; the others run the network); target = "
+                               "mean EPE of plain batches (zero initialisation) at 10 GN x "
+                               "20 PCG per level; plain and learned batches each at the "
+                               "fewest GN steps per level reaching it",
+                          weights="init_640x480.npy"),
     "video": dict(desc="video mode vs plain at equal EPE: a 10-frame constant-velocity "
                        "640x480 generator sequence (seed 5, 30 px displacement per frame, "
                        "independent noise per frame); plain = every frame from zero, "
@@ -89,13 +97,18 @@ WORKLOADS = {
                       params=dict(levels=5, grid_stride=4, gn_iters=10, pcg_iters=20)),
 }
 
-# Algorithmic bytes of one H p launch (matrix-free, per-pixel Gauss-Newton
-# blocks): per pixel the 21 upper-triangular floats of its block; per node
-# z, p_old, p (write), q (write), base, delta (6 floats each) and w_i.
+# Bytes one PCG iteration kernel (H u plus the vector updates) must move per
+# node at level 0, counting every value it loads or stores once.  Node
+# vectors are 6 floats (stored as 8-float records; 24 B accessed): it reads
+# r, w, s, diag (for u and the halo) and u, x, p (the owned node), and writes
+# s, r, w, p, x, u; plus the 16-float regulariser record.
+VEC_BYTES = 6 * 4
+APPLY_BYTES_PER_NODE = (7 + 6) * VEC_BYTES + 16 * 4          # 376 B
+# matrix-free products: the 21 distinct floats of each pixel's
+# Gauss-Newton block on top of the node traffic
 APPLY_BYTES_PER_PIXEL = 21 * 4
-APPLY_BYTES_PER_NODE = (6 * 6 + 1) * 4
-# node-block products: the five stored 21-float blocks per node instead of
-# the per-pixel records
+# node-block products: the five stored 21-float blocks per node (self, E,
+# S, SE, SW) on top of the node traffic: 420 + 376 = 796 B per node
 APPLY_NB_BYTES_PER_NODE = 5 * 21 * 4 + APPLY_BYTES_PER_NODE
 
 
@@ -105,24 +118,37 @@ def apply_bytes(N0, G0, apply_mode):
     return APPLY_BYTES_PER_PIXEL * N0 + APPLY_BYTES_PER_NODE * G0
 
 
+def describe(desc, params):
+    """Workload description with the schedule actually run."""
+    gn = f"{params['gn_iters']} GN"
+    if params.get("gn_fine"):
+        gn = f"{params['gn_fine']} GN on the two finest levels and {params['gn_iters']} GN"
+    return (f"{desc}; stride {params['grid_stride']}, {params['levels']} levels, "
+            f"{gn} x {params['pcg_iters']} PCG")
+
+
 def _gen_frame(args):
     from synth import make_frame, sized_config
-    W, H, seed = args
-    imgs, calib, _ = make_frame(sized_config(W, H), seed)
+    W, H, seed, truth = args
+    imgs, calib, scene = make_frame(sized_config(W, H), seed)
+    if truth:
+        pos, ok = scene.halfway_truth()
+        return imgs, calib, (pos.astype(np.float32), ok)
     return imgs, calib
 
 
-def make_batch_workload(w):
+def make_batch_workload(w, truth=False):
     """Frames of the batched workload: per-frame resolutions from the seed,
     images from two generator scenes per resolution (rendered in parallel
-    on the host)."""
+    on the host); with truth, each frame also carries the generator's
+    halfway correspondences."""
     from concurrent.futures import ProcessPoolExecutor
     from synth import batch_resolutions
     res = batch_resolutions(w["n_frames"], w["seed"])
     jobs = sorted({(W, H, 100 + 10 * k + j) for k, (W, H) in enumerate(sorted(set(res)))
                    for j in range(2)})
     with ProcessPoolExecutor(max_workers=min(8, len(jobs))) as ex:
-        out = dict(zip(jobs, ex.map(_gen_frame, jobs)))
+        out = dict(zip(jobs, ex.map(_gen_frame, [j + (truth,) for j in jobs])))
     frames, count = [], {}
     for W, H in res:
         j = count.get((W, H), 0)
@@ -159,26 +185,67 @@ def measured_traffic(workload, apply_mode=0):
     return int(vals["traffic_bytes_per_launch"])
 
 
+def equal_epe_sweeps(run, full):
+    """Equal-EPE comparison of the learned initialisation with the plain
+    solver.  The target is the plain solver's mean EPE at the full schedule
+    (`full` Gauss-Newton steps per level); for each method the number of
+    steps per level is swept upward from 1 and the first (fastest) setting
+    whose mean EPE reaches the target is reported.  run(init_mode, n)
+    returns (mean EPE, result row)."""
+    target, full_row = run(0, full)
+    out = {"target_epe_px": round(target, 4), "plain_full_schedule": full_row}
+    for name, mode in (("plain", 0), ("learned", 1)):
+        sweep, reach = [], None
+        for n in range(1, full + 1):
+            if mode == 0 and n == full:
+                e, row = target, full_row
+            else:
+                e, row = run(mode, n)
+            sweep.append(row)
+            if e <= target:
+                reach = row
+                break
+        out[name + "_sweep"] = sweep
+        out[name + "_at_target"] = reach
+    p, l = out["plain_at_target"], out["learned_at_target"]
+    out["speedup_at_equal_epe"] = (round(p["ms_per_frame"] / l["ms_per_frame"], 3)
+                                   if p and l else None)
+    return out
+
+
+def single_frame_runner(frames, W, H, params, weights):
+    """run(init_mode, n) of equal_epe_sweeps for single-frame solves of
+    rendered frames (GPU time per frame, graph replay)."""
+    from paper_1610_07159_amd import train_init as T
+
+    def run(init_mode, n):
+        fl, used, ms = T.solve_flows(frames, W, H, init_mode=init_mode,
+                                     weights=weights if init_mode else None, timed=True,
+                                     **dict(params, gn_iters=n))
+        e = float(np.mean([T.epe(f, fr["truth"], W, H) for f, fr in zip(fl, frames)]))
+        row = dict(gn_iters=n, epe_px=round(e, 4), ms_per_frame=round(ms, 3))
+        if init_mode:
+            row["prediction_kept"] = int(sum(used))
+        return e, row
+    return run
+
+
 def learned_vs_plain(solver_params, frames):
     """Compact equal-EPE comparison for the headline line (see --workload
-    learned for the full sweep); frames rendered beforehand."""
-    from paper_1610_07159_amd import train_init as T
-    W, H = 640, 480
-    n_eval = len(frames)
+    learned); frames rendered beforehand."""
     weights = np.load(os.path.join(ROOT, "paper_1610_07159_amd", "weights", "init_640x480.npy"),
                       allow_pickle=False)
-    plain, _, ms_plain = T.solve_flows(frames, W, H, timed=True, **solver_params)
-    e_plain = float(np.mean([T.epe(f, fr["truth"], W, H) for f, fr in zip(plain, frames)]))
-    for n in range(1, solver_params["gn_iters"] + 1):
-        fl, used, ms = T.solve_flows(frames, W, H, init_mode=1, weights=weights, timed=True,
-                                     **dict(solver_params, gn_iters=n))
-        e = float(np.mean([T.epe(f, fr["truth"], W, H) for f, fr in zip(fl, frames)]))
-        if e <= e_plain:
-            return dict(eval_frames=n_eval, plain_epe_px=round(e_plain, 4),
-                        plain_ms_per_frame=round(ms_plain, 3), learned_gn_iters=n,
-                        learned_epe_px=round(e, 4), learned_ms_per_frame=round(ms, 3),
-                        speedup=round(ms_plain / ms, 3), prediction_kept=int(sum(used)))
-    return dict(eval_frames=n_eval, plain_epe_px=round(e_plain, 4), reached=False)
+    r = equal_epe_sweeps(single_frame_runner(frames, 640, 480, solver_params, weights),
+                         solver_params["gn_iters"])
+    p, l = r["plain_at_target"], r["learned_at_target"]
+    return dict(eval_frames=len(frames), target_epe_px=r["target_epe_px"],
+                plain_gn_iters=p["gn_iters"], plain_epe_px=p["epe_px"],
+                plain_ms_per_frame=p["ms_per_frame"],
+                learned_gn_iters=l["gn_iters"] if l else None,
+                learned_epe_px=l["epe_px"] if l else None,
+                learned_ms_per_frame=l["ms_per_frame"] if l else None,
+                prediction_kept=l["prediction_kept"] if l else None,
+                speedup=r["speedup_at_equal_epe"])
 
 
 def _render_video_frame(args):
@@ -387,33 +454,62 @@ def epe(flows, scene, W, H):
     return float((err / 4.0)[inside].mean())
 
 
-def cpu_baseline(imgs, calib, params, W, H):
-    """The FP64 oracle on a bounded sample of the same frame: the level-0
-    set-up plus one Gauss-Newton step (linearise, assemble, PCG, step
-    control) at level 0; scaled to a frame as (set-up + gn_iters steps) x
-    (sum of level pixel counts / level-0 pixel count)."""
+def cpu_model():
+    """The host CPU's model name and logical CPU count (from /proc/cpuinfo)."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
+def _oracle_solve_seconds(imgs, calib, params, gn_iters, threads):
     from threadpoolctl import threadpool_limits
-    import oracle.halfway as O
     import dataclasses
+    import oracle.halfway as O
     names = {f.name for f in dataclasses.fields(O.Params)}
-    p = O.Params(**{k: v for k, v in params.items() if k in names})
-    with threadpool_limits(limits=1):
-        pyr = O.pyramid(imgs.astype(np.float64), p.levels)
-        grid = O.Grid(W, H, p.grid_stride)
+    p = O.Params(**{k: v for k, v in dict(params, gn_iters=gn_iters).items() if k in names})
+    with threadpool_limits(limits=threads):
         t0 = time.perf_counter()
-        ls = O.setup_level(0, pyr, p, O.Calib.from_dict(calib), np.zeros((6, grid.G)))
-        t1 = time.perf_counter()
-        O.gn_step(ls, np.zeros((6, grid.G)), p)
-        t2 = time.perf_counter()
-    sizes = level_sizes(W, H, p.levels, p.grid_stride)
-    scale = sum(s[2] for s in sizes) / sizes[0][2]
-    ms = ((t1 - t0) + p.gn_iters * (t2 - t1)) * scale * 1e3
+        O.solve(imgs.astype(np.float64), calib, p)
+        return time.perf_counter() - t0
+
+
+def cpu_baseline(imgs, calib, params, W, H):
+    """The FP64 oracle on a bounded sample of the same frame: two whole
+    solves (pyramid, every level's set-up, Gauss-Newton steps with PCG and
+    step control, output) with 1 and with 2 Gauss-Newton steps per level,
+    BLAS limited to one thread.  Their difference is the cost of one step on
+    every level, so a frame of gn_iters steps costs t1 + (gn_iters - 1)
+    (t2 - t1)."""
+    t1 = _oracle_solve_seconds(imgs, calib, params, 1, 1)
+    t2 = _oracle_solve_seconds(imgs, calib, params, 2, 1)
+    n = params["gn_iters"]
+    ms = (t1 + (n - 1) * (t2 - t1)) * 1e3
+    model, ncpu = cpu_model()
     return dict(value=round(ms, 1), unit="ms/frame", cores=1, kind="oracle",
-                sample=(f"level-0 set-up ({t1 - t0:.2f} s) and one level-0 "
-                        f"Gauss-Newton step ({t2 - t1:.2f} s, {W}x{H} px, "
-                        f"{p.pcg_iters} PCG) of the same frame, scaled by "
-                        f"{p.gn_iters} steps and sum(N_l)/N_0 = {scale:.3f}; "
-                        "numpy/scipy float64, BLAS limited to 1 thread"))
+                cpu=model, host_cpus=ncpu,
+                sample=(f"whole oracle solves of the same {W}x{H} frame with 1 and 2 "
+                        f"Gauss-Newton steps per level ({t1:.1f} s, {t2:.1f} s; "
+                        f"{params['levels']} levels, {params['pcg_iters']} PCG), extrapolated "
+                        f"linearly to {n} steps per level; numpy/scipy float64, BLAS "
+                        "limited to 1 thread"))
+
+
+def cpu_full(imgs, calib, params, W, H):
+    """Whole oracle solves at the full schedule, BLAS on every host CPU and
+    on one thread (minutes each)."""
+    model, ncpu = cpu_model()
+    out = dict(cpu=model, host_cpus=ncpu, workload=f"{W}x{H}", **params)
+    for threads in (ncpu, 1):
+        out[f"seconds_threads_{threads}"] = round(
+            _oracle_solve_seconds(imgs, calib, params, params["gn_iters"], threads), 2)
+        print(json.dumps(out), file=sys.stderr, flush=True)
+    return out
 
 
 def _short_name(n):
@@ -516,6 +612,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="vga", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--weights", default=None,
+                    help="initialiser file under paper_1610_07159_amd/weights/ for the "
+                         "batch_learned workload (default: the workload's)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time whole oracle solves of the workload (all host CPUs and one "
+                         "thread) and exit")
     ap.add_argument("--no-epe", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-init vs plain comparison")
@@ -530,6 +632,17 @@ def main():
                          "warm-up solve), 2 / 3 / 4 = the alternative shapes")
     ap.add_argument("--grid-stride", type=int, default=0,
                     help="warp-grid stride of the single-frame workloads (0: the workload's)")
+    ap.add_argument("--pcg-iters", type=int, default=0,
+                    help="PCG iterations per Gauss-Newton step of the single-frame "
+                         "workloads (0: the workload's)")
+    ap.add_argument("--gn-iters", type=int, default=0,
+                    help="Gauss-Newton steps per level of the single-frame workloads "
+                         "(0: the workload's)")
+    ap.add_argument("--gn-fine", type=int, default=0,
+                    help="Gauss-Newton steps on the two finest levels (the paper's split "
+                         "schedule; 0: as every level)")
+    ap.add_argument("--levels", type=int, default=0,
+                    help="pyramid levels of the single-frame workloads (0: the workload's)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter "
                          "calibration under rocprofv3 --pmc)")
@@ -551,10 +664,20 @@ def main():
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.cpu_full:
+        w, imgs, calib, _ = make_workload(args.workload)
+        params = dict(w["params"])
+        if args.grid_stride:
+            params["grid_stride"] = args.grid_stride
+        print(json.dumps(cpu_full(imgs, calib, params, w["width"], w["height"])), flush=True)
+        return
+
     # host process pools render before anything touches the GPU
     pre = {}
     if args.workload == "batch":
         pre["batch"] = make_batch_workload(WORKLOADS["batch"])
+    if args.workload == "batch_learned":
+        pre["batch"] = make_batch_workload(WORKLOADS["batch"], truth=True)
     if args.workload == "video":
         pre["video"] = make_video_workload(WORKLOADS["video"])
     if args.workload == "illum":
@@ -587,6 +710,8 @@ def main():
         del a, b
     if args.workload == "batch":
         return run_batch(args, pre["batch"])
+    if args.workload == "batch_learned":
+        return run_batch_learned(args, pre["batch"])
     if args.workload in ("learned", "learned_hd"):
         return run_learned(args, pre["eval"], args.workload)
     if args.workload == "video":
@@ -604,6 +729,14 @@ def main():
     params = dict(w["params"])
     if args.grid_stride:
         params["grid_stride"] = args.grid_stride
+    if args.pcg_iters:
+        params["pcg_iters"] = args.pcg_iters
+    if args.gn_iters:
+        params["gn_iters"] = args.gn_iters
+    if args.gn_fine:
+        params["gn_fine"] = args.gn_fine
+    if args.levels:
+        params["levels"] = args.levels
     img = torch.from_numpy(imgs).cuda().contiguous()
     params["apply_mode"] = args.apply_mode
     solver = SceneFlowSolver(W, H, exec_mode=args.exec_mode, tile_mode=args.tile_mode,
@@ -652,7 +785,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w["desc"], "width": W, "height": H,
+        "config": {"workload": describe(w["desc"], params), "width": W, "height": H,
                    "exec": "hip graph" if args.exec_mode == 0 else "direct launches",
                    "tile_mode": args.tile_mode, **params},
         "frames_per_s": round(1e3 / ms, 2),
@@ -663,8 +796,8 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": (measured_traffic(args.workload, args.apply_mode)
-                                 if args.exec_mode == 0 and params["grid_stride"]
-                                 == w["params"]["grid_stride"] else None),
+                                 if args.exec_mode == 0 and params == dict(
+                                     w["params"], apply_mode=args.apply_mode) else None),
                      "bytes_per_launch": bytes_apply,
                      "avg_us_per_launch": round(bytes_apply / achieved / 1e3, 2),
                      "apply_us_per_level": per_level},
@@ -685,24 +818,14 @@ def main():
 def run_learned(args, frames, name="learned"):
     """Equal-EPE comparison of the learned initialiser with the plain
     solver; value = ms/frame of the learned solve at the plain EPE."""
-    from paper_1610_07159_amd import train_init as T
     w = WORKLOADS[name]
     W, H = w["width"], w["height"]
     params = dict(w["params"], apply_mode=args.apply_mode)
     weights = np.load(os.path.join(ROOT, "paper_1610_07159_amd", "weights", w["weights"]),
                       allow_pickle=False)
-    plain, _, ms_plain = T.solve_flows(frames, W, H, timed=True, **params)
-    epe_plain = float(np.mean([T.epe(f, fr["truth"], W, H) for f, fr in zip(plain, frames)]))
-    sweep, reach = [], None
-    for n in range(1, params["gn_iters"] + 1):
-        fl, used, ms = T.solve_flows(frames, W, H, init_mode=1, weights=weights, timed=True,
-                                     **dict(params, gn_iters=n))
-        e = float(np.mean([T.epe(f, fr["truth"], W, H) for f, fr in zip(fl, frames)]))
-        sweep.append(dict(gn_iters=n, epe_px=round(e, 4), ms_per_frame=round(ms, 3),
-                          prediction_kept=int(sum(used))))
-        if e <= epe_plain:
-            reach = sweep[-1]
-            break
+    r = equal_epe_sweeps(single_frame_runner(frames, W, H, params, weights),
+                         params["gn_iters"])
+    reach = r["learned_at_target"]
     result = {
         "metric": METRIC,
         "value": reach["ms_per_frame"] if reach else None,
@@ -717,11 +840,98 @@ def run_learned(args, frames, name="learned"):
         "dtype": "f32 solve, bf16 initialiser",
         "data": "synthetic",
         "config": {"workload": w["desc"], **params},
-        "plain": {"gn_iters": params["gn_iters"], "epe_px": round(epe_plain, 4),
-                  "ms_per_frame": round(ms_plain, 3)},
-        "learned_at_equal_epe": reach,
-        "speedup_at_equal_epe": round(ms_plain / reach["ms_per_frame"], 3) if reach else None,
-        "learned_sweep": sweep,
+        **r,
+    }
+    print(json.dumps(result), flush=True)
+
+
+def epe_device(flows, pos, ok):
+    """The EPE of `epe` on the GPU (float64): flows (6, H, W), the
+    generator's halfway correspondences pos (4, 2, H, W) and validity ok
+    (H, W), all device tensors."""
+    import torch
+    H, W = flows.shape[1:]
+    yy, xx = torch.meshgrid(torch.arange(H, device=flows.device, dtype=torch.float64),
+                            torch.arange(W, device=flows.device, dtype=torch.float64),
+                            indexing="ij")
+    f = flows.double()
+    pos = pos.double()
+    signs = ((-1, -1, 1), (1, -1, -1), (-1, 1, -1), (1, 1, 1))
+    err = torch.zeros((H, W), device=flows.device, dtype=torch.float64)
+    inside = ok.clone()
+    for c, (a, b, d) in enumerate(signs):
+        px = xx + a * f[0] + b * f[2] + d * f[4]
+        py = yy + a * f[1] + b * f[3] + d * f[5]
+        err += torch.hypot(px - pos[c, 0], py - pos[c, 1])
+        inside &= ((pos[c, 0] >= 0) & (pos[c, 0] <= W - 1) & (pos[c, 1] >= 0)
+                   & (pos[c, 1] <= H - 1))
+    return float((err / 4.0)[inside].mean())
+
+
+def run_batch_learned(args, workload):
+    """Equal-EPE comparison of batches started from the learned
+    initialisation with plain batches (zero initialisation), on the batched
+    workload; value = ms/frame of the learned batch at the plain EPE."""
+    import torch
+    from paper_1610_07159_amd import SceneFlowSolver, sf
+    w = WORKLOADS["batch_learned"]
+    params = dict(WORKLOADS["batch"]["params"], apply_mode=args.apply_mode)
+    res, frames = workload
+    n = len(frames)
+    dev = [(torch.from_numpy(i).cuda().contiguous(), c) for i, c, _ in frames]
+    truth = [(torch.from_numpy(t[0]).cuda(), torch.from_numpy(t[1]).cuda())
+             for _, _, t in frames]
+    weights = np.load(os.path.join(ROOT, "paper_1610_07159_amd", "weights",
+                                   args.weights or w["weights"]), allow_pickle=False)
+    W0, H0 = res[0]
+    solver = SceneFlowSolver(W0, H0, exec_mode=args.exec_mode, tile_mode=args.tile_mode,
+                             **params)
+    sf.sf_set_initializer(solver.ctx, weights)
+    reps = max(1, args.steps)
+
+    def run(init_mode, n_gn):
+        prm = sf.sf_params_default(exec_mode=args.exec_mode, tile_mode=args.tile_mode,
+                                   **dict(params, gn_iters=n_gn, init_mode=init_mode))
+        outs = solver.solve_batch(dev, params=prm)  # workspace, tiles, graph
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(solver.stream)
+        for _ in range(reps):
+            outs = solver.solve_batch(dev, outs=outs, params=prm)
+        ev[1].record(solver.stream)
+        torch.cuda.synchronize()
+        batch_ms = ev[0].elapsed_time(ev[1]) / reps
+        e = float(np.mean([epe_device(o[2], *t) for o, t in zip(outs, truth)]))
+        row = dict(gn_iters=n_gn, epe_px=round(e, 4), ms_per_frame=round(batch_ms / n, 4),
+                   batch_ms=round(batch_ms, 3))
+        if init_mode:
+            used = [solver.batch_init_result(f)[0] for f in range(n)]
+            row["network_frames"] = sum(u >= 0 for u in used)
+            row["prediction_kept"] = sum(u == 1 for u in used)
+        return e, row
+
+    r = equal_epe_sweeps(run, params["gn_iters"])
+    solver.close()
+    reach = r["learned_at_target"]
+    sizes = {f"{W}x{H}": res.count((W, H)) for W, H in sorted(set(res))}
+    result = {
+        "metric": METRIC,
+        "value": reach["ms_per_frame"] if reach else None,
+        "unit": "ms/frame",
+        "n_gpus": 1,
+        "steps": reps,
+        "warmup": 1,
+        "ms_per_step": reach["batch_ms"] if reach else None,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 solve, bf16 initialiser",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "frames_per_batch": n, "sizes": sizes,
+                   "weights": args.weights or w["weights"],
+                   "exec": "hip graph" if args.exec_mode == 0 else "direct launches",
+                   "tile_mode": args.tile_mode, **params},
+        **r,
     }
     print(json.dumps(result), flush=True)
 

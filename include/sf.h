@@ -57,11 +57,16 @@ typedef struct {
  *  levels          pyramid levels (coarse-to-fine hierarchy, Sec. 5.3)
  *  grid_stride     warp-grid step in pixels at every level (Sec. 3.3), 1..8
  *  gn_iters        Gauss-Newton steps per level
+ *  gn_fine         if > 0, Gauss-Newton steps on the two finest levels
+ *                  instead (the paper's real-time schedule, Sec. 6.2: 2 on
+ *                  the two finest levels, 5 on the others); 0 = gn_iters
  *  pcg_iters       PCG iterations per Gauss-Newton step (1..64)
  *  max_backtracks  step-length halvings after tau = 1 (0..7)
  *  init_mode       0 = zero initialisation of the coarsest level; 1 = the
- *                  learned initialiser (needs levels >= 5 and weights from
- *                  sf_set_initializer; see below)
+ *                  learned initialiser (needs weights from
+ *                  sf_set_initializer and, in single-frame contexts,
+ *                  levels >= 5; batch frames with fewer levels start from
+ *                  zero; see below)
  *  exec_mode       0 = replay a captured HIP graph, 1 = enqueue kernels
  *  tile_mode       node-tile shape of the PCG kernels: 0 = default per
  *                  stride; 1 = autotuned (each candidate shape is timed on
@@ -124,7 +129,7 @@ typedef struct {
  *                  eigenvalue analysis; this map is the library's reading). */
 typedef struct {
     int levels, grid_stride, gn_iters, pcg_iters, max_backtracks, init_mode;
-    int exec_mode, tile_mode, apply_mode, temporal, illum, occlusion;
+    int exec_mode, tile_mode, apply_mode, temporal, illum, occlusion, gn_fine;
     float w_reg, w_photo, w_grad, w_epi, w_smooth, w_mag;
     float w_s, w_m, w_d, m_s, m_m, m_d;
     float eps, eps_p, st_gamma, st_tau;
@@ -148,7 +153,7 @@ sf_status sf_create(sf_ctx **out, int width, int height, const sf_params *p,
 /* Solves one frame.  Inputs: the four device images of the context's size
  * (left t, right t, left t+1, right t+1; Sec. 3.1), calibration, and
  * optional params (NULL = creation-time params; a non-NULL p may change
- * weights but must keep levels, grid_stride, gn_iters, pcg_iters and
+ * weights but must keep levels, grid_stride, gn_iters, gn_fine, pcg_iters and
  * max_backtracks, else SF_ERR_STATE).  Outputs (device, caller-owned):
  *  depth   H x W: depth Z_t of each halfway-domain pixel at time t in the
  *          left camera (metres), NaN where the disparity is <= 0;
@@ -237,13 +242,33 @@ sf_status sf_get_batch_log(sf_ctx *ctx, int frame, sf_iter_log *out, int cap,
 
 /* Copies the initialiser's parameters: SF_CNN_PARAMS bfloat16 values
  * (uint16 bit patterns, host memory), bytes = 2 * SF_CNN_PARAMS.  Takes
- * effect for the following solves, also in a captured graph. */
+ * effect for the following solves, also in a captured graph.  A context of
+ * either init_mode accepts them (the first call allocates the weight
+ * buffers); they serve its single-frame solves and its batches alike.
+ * SF_ERR_SIZE for another byte count, SF_ERR_INVALID_ARG for a non-finite
+ * value. */
 sf_status sf_set_initializer(sf_ctx *ctx, const void *weights, size_t bytes);
 
 /* Outcome of the fallback at the last solve with init_mode = 1: *used = 1
  * if the prediction was kept, and both energies.  Synchronises the stream;
  * SF_ERR_STATE if no such solve ran. */
 sf_status sf_get_init_result(sf_ctx *ctx, int *used, double *e_pred, double *e_zero);
+
+/* Batches with init_mode = 1: every frame with at least 5 levels (so that
+ * it has a level 4 for the network's input) is initialised as above, with
+ * its own fallback decision; frames of one level-4 size share one forward
+ * pass.  Frames with fewer levels start from zero.  Each frame gets the
+ * result of its single-frame solve with the same parameters and level
+ * count.  sf_solve_batch returns SF_ERR_STATE if init_mode = 1 and no
+ * weights were set.
+ *
+ * Outcome of the fallback for frame `frame` of the last batch: as
+ * sf_get_init_result; *used = -1 (energies NaN) for a frame with fewer than
+ * 5 levels.  Synchronises the stream; SF_ERR_STATE if the last batch did
+ * not run with init_mode = 1, SF_ERR_INVALID_ARG for a frame index outside
+ * it. */
+sf_status sf_get_batch_init_result(sf_ctx *ctx, int frame, int *used, double *e_pred,
+                                   double *e_zero);
 
 /* Trainer of the initialiser: batches of B level-4 image quadruples
  * (device float32 [B][4][H][W], left t, right t, left t+1, right t+1) with

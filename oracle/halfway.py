@@ -76,6 +76,7 @@ class Params:
     levels: int = 3
     grid_stride: int = 8
     gn_iters: int = 5
+    gn_fine: int = 0  # if > 0: steps on the two finest levels (Sec. 6.2 schedule)
     pcg_iters: int = 10
     max_backtracks: int = 4
     w_reg: float = 0.5
@@ -96,6 +97,12 @@ class Params:
     st_tau: float = 1e-3
     illum: bool = False  # illumination correction (Sec. 5.3)
     occlusion: bool = False  # occlusion maps from a z-buffer (Sec. 5.3)
+
+    def gn_at(self, level):
+        """Gauss-Newton steps at a level.  The paper's real-time runs use
+        2 steps on the two finest levels and 5 on the others (Sec. 6.2);
+        gn_fine > 0 selects such a split, else every level takes gn_iters."""
+        return self.gn_fine if (self.gn_fine > 0 and level < 2) else self.gn_iters
 
     def flow_weights(self):
         """w_f per unknown component (s_x, s_y, m_x, m_y, d_x, d_y)."""
@@ -825,7 +832,7 @@ def solve(images, calib, p: Params, init_coarsest=None, record=None, init_deltas
     """Algorithm 1 without the occlusion/illumination map updates: for each
     level from coarsest to finest, prolongate the coarser total, start the
     delta at zero (or at init_deltas[level], the temporal initialisation),
-    freeze masks and weights, run gn_iters Gauss-Newton steps.  Returns a
+    freeze masks and weights, run gn_at(level) Gauss-Newton steps.  Returns a
     dict with the finest-level grid, total node flows (6, G) and the
     per-level totals, deltas and grids."""
     if isinstance(calib, dict):
@@ -850,7 +857,7 @@ def solve(images, calib, p: Params, init_coarsest=None, record=None, init_deltas
         occ = occ_next if (p.occlusion and total is not None) else None
         ls = setup_level(level, pyr, p, calib, base,
                          None if init_deltas is None else delta, illum, occ)
-        for _ in range(p.gn_iters):
+        for _ in range(p.gn_at(level)):
             delta = gn_step(ls, delta, p, record)
         total = ls.base + delta
         totals[level] = total

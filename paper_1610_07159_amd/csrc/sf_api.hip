@@ -43,17 +43,32 @@ struct FrameBuf {
     FrameIO *io = nullptr;
 };
 
-// Workspace of the learned initialiser (single-frame contexts with
-// init_mode = 1): float32 parameters, device weights and the activations of
-// one level-4 image quadruple.
-struct CnnRun {
-    bool on = false, have_weights = false;
+// Network weights of a context (sf_set_initializer): the float32
+// parameters and the bf16 device copies the kernels read.
+struct CnnNet {
+    bool have_weights = false;
     CnnLayout L{};
-    int W4 = 0, H4 = 0;
-    float *flat = nullptr, *out = nullptr;
+    float *flat = nullptr;
     CnnWeights w{};
+    char *pool = nullptr;
+};
+
+// Learned-initialiser workspace of a plan (init_mode = 1).  Frames with a
+// level 4 are grouped by its size, and one forward pass per group serves
+// all of its frames: per group their bf16 input quadruples, hidden
+// activations and float outputs, frame by frame.  Frames with fewer levels
+// start from zero.
+struct CnnGroup {
+    int W4 = 0, H4 = 0;
+    std::vector<int> frames;
     unsigned short *x = nullptr;
     unsigned short *acts[SF_CNN_LAYERS - 1]{};
+    float *out = nullptr;
+};
+struct CnnRun {
+    bool on = false;
+    std::vector<CnnGroup> groups;
+    std::vector<bool> slot_has;   // level slot holds a network-initialised coarsest level
     char *pool = nullptr;
 };
 
@@ -83,7 +98,8 @@ struct Plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<int> shape;  // W, H per frame (batch cache key)
-    CnnRun cnn;              // learned initialiser (single frame)
+    CnnRun cnn;              // learned initialiser
+    const CnnNet *net = nullptr;
 };
 
 }  // namespace
@@ -95,6 +111,7 @@ struct sf_ctx {
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
     Plan single;
     Plan *batch = nullptr;
+    CnnNet net;
 };
 
 namespace {
@@ -120,6 +137,7 @@ sf_status check_params(const sf_params *p) {
     if (p->levels < 1 || p->levels > SF_MAX_LEVELS) return SF_ERR_INVALID_ARG;
     if (p->grid_stride < 1 || p->grid_stride > 8) return SF_ERR_INVALID_ARG;
     if (p->gn_iters < 1 || p->gn_iters > 1000) return SF_ERR_INVALID_ARG;
+    if (p->gn_fine < 0 || p->gn_fine > 1000) return SF_ERR_INVALID_ARG;
     if (p->pcg_iters < 1 || p->pcg_iters > SF_MAX_PCG) return SF_ERR_INVALID_ARG;
     if (p->max_backtracks < 0 || p->max_backtracks > SF_MAX_TRIALS - 1) return SF_ERR_INVALID_ARG;
     if (p->init_mode != 0 && p->init_mode != 1) return SF_ERR_INVALID_ARG;
@@ -144,11 +162,14 @@ sf_status check_params(const sf_params *p) {
 
 bool same_schedule(const sf_params &a, const sf_params &b) {
     return a.levels == b.levels && a.grid_stride == b.grid_stride &&
-           a.gn_iters == b.gn_iters && a.pcg_iters == b.pcg_iters &&
+           a.gn_iters == b.gn_iters && a.gn_fine == b.gn_fine && a.pcg_iters == b.pcg_iters &&
            a.max_backtracks == b.max_backtracks && a.init_mode == b.init_mode &&
            a.tile_mode == b.tile_mode && a.apply_mode == b.apply_mode &&
            a.temporal == b.temporal && a.illum == b.illum && a.occlusion == b.occlusion;
 }
+
+// Gauss-Newton steps at level l: gn_fine on the two finest levels if set.
+int gn_at(const sf_params &p, int l) { return (p.gn_fine > 0 && l < 2) ? p.gn_fine : p.gn_iters; }
 
 sf_status check_calib(const sf_calib *cal) {
     if (!cal) return SF_ERR_INVALID_ARG;
@@ -235,8 +256,9 @@ void free_plan(Plan &P) {
 // Allocates and initialises the workspace of frames of the given sizes and
 // level counts.
 sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shape,
-                     const std::vector<int> &levels, bool batched) {
+                     const std::vector<int> &levels, bool batched, const CnnNet *net) {
     P.prm = prm;
+    P.net = net;
     P.batched = batched;
     P.nf = (int)levels.size();
     P.shape = shape;
@@ -283,7 +305,8 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
             mb = mb > gb ? mb : gb;
         }
         F.max_blocks = mb;
-        F.nlog = F.L * prm.gn_iters;
+        F.nlog = 0;
+        for (int l = 0; l < F.L; ++l) F.nlog += gn_at(prm, l);
         long g_all = 0;
         for (int l = 0; l < F.L; ++l) g_all += F.lv[l].G;
         const size_t n1 = F.L > 1 ? (size_t)F.lv[1].N : 0;
@@ -365,6 +388,60 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
     }
     // zeroed workspace
     HIP_TRY(hipMemset(P.pool, 0, off));
+    // learned initialiser: frames with a level 4, grouped by its size
+    std::vector<const float *> cnn_out(P.nf, nullptr);
+    if (prm.init_mode == 1) {
+        CnnRun &R = P.cnn;
+        for (int f = 0; f < P.nf; ++f) {
+            const FrameBuf &F = P.fr[f];
+            if (F.L <= SF_CNN_INPUT_LEVEL) continue;
+            const int W4 = F.lv[SF_CNN_INPUT_LEVEL].W, H4 = F.lv[SF_CNN_INPUT_LEVEL].H;
+            CnnGroup *g = nullptr;
+            for (CnnGroup &q : R.groups)
+                if (q.W4 == W4 && q.H4 == H4) g = &q;
+            if (!g) {
+                R.groups.emplace_back();
+                g = &R.groups.back();
+                g->W4 = W4;
+                g->H4 = H4;
+            }
+            g->frames.push_back(f);
+        }
+        size_t tot = 0;
+        std::vector<size_t> goff;
+        for (const CnnGroup &g : R.groups) {
+            const size_t n = (size_t)g.W4 * g.H4 * g.frames.size();
+            goff.push_back(tot);
+            tot += align_up(2 * 16 * n) + align_up(2 * 32 * n * (SF_CNN_LAYERS - 1)) +
+                   align_up(sizeof(float) * 6 * n);
+        }
+        if (tot > 0) {
+            e = hipMalloc(&R.pool, tot);
+            if (e != hipSuccess) {
+                note_hip_error("hipMalloc(initialiser)", e);
+                R.pool = nullptr;
+                return SF_ERR_OOM;
+            }
+            HIP_TRY(hipMemset(R.pool, 0, tot));
+        }
+        R.slot_has.assign(P.Lmax, false);
+        for (size_t k = 0; k < R.groups.size(); ++k) {
+            CnnGroup &g = R.groups[k];
+            const size_t n4 = (size_t)g.W4 * g.H4, n = n4 * g.frames.size();
+            char *b = R.pool + goff[k];
+            g.x = (unsigned short *)b;
+            b += align_up(2 * 16 * n);
+            for (int l = 0; l < SF_CNN_LAYERS - 1; ++l)
+                g.acts[l] = (unsigned short *)b + (size_t)l * 32 * n;
+            b += align_up(2 * 32 * n * (SF_CNN_LAYERS - 1));
+            g.out = (float *)b;
+            for (size_t i = 0; i < g.frames.size(); ++i) {
+                cnn_out[g.frames[i]] = g.out + 6 * n4 * i;
+                R.slot_has[P.fr[g.frames[i]].L - 1] = true;
+            }
+        }
+        R.on = !R.groups.empty();
+    }
     // per-slot kernel arguments
     P.host.assign(P.Lmax, {});
     std::vector<LevelArgs> flat;
@@ -382,7 +459,8 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
             a.coarsest = l == F.L - 1;
             a.Gxc = l + 1 < F.L ? F.lv[l + 1].Gx : 1;
             a.Gyc = l + 1 < F.L ? F.lv[l + 1].Gy : 1;
-            a.log_base = (F.L - 1 - l) * prm.gn_iters;
+            a.log_base = 0;  // coarsest level first
+            for (int k = l + 1; k < F.L; ++k) a.log_base += gn_at(prm, k);
             a.Wf = l > 0 ? F.lv[l - 1].W : 0;
             a.Hf = l > 0 ? F.lv[l - 1].H : 0;
             a.tex = F.tex + F.lv[l].tex_off;
@@ -415,48 +493,15 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
             a.cst = F.cst;
             a.sc = F.sc;
             a.log = F.log;
+            if (cnn_out[f] && l == F.L - 1) {
+                a.learned = 1;
+                a.W4 = F.lv[SF_CNN_INPUT_LEVEL].W;
+                a.H4 = F.lv[SF_CNN_INPUT_LEVEL].H;
+                a.cnn_out = cnn_out[f];
+            }
             P.host[l].push_back(a);
             flat.push_back(a);
         }
-    }
-    if (prm.init_mode == 1 && !batched) {
-        // network workspace for the frame's level-4 images
-        CnnRun &R = P.cnn;
-        FrameBuf &F = P.fr[0];
-        R.L = cnn_layout();
-        R.W4 = F.lv[SF_CNN_INPUT_LEVEL].W;
-        R.H4 = F.lv[SF_CNN_INPUT_LEVEL].H;
-        const size_t N4 = (size_t)R.W4 * R.H4;
-        const size_t sz[] = {sizeof(float) * R.L.n_params, sizeof(float) * 6 * N4,
-                             2 * (size_t)R.L.dev_w_total, 2 * (size_t)R.L.dev_w_total,
-                             sizeof(float) * R.L.dev_b_total, 2 * 16 * N4,
-                             2 * 32 * N4 * (SF_CNN_LAYERS - 1)};
-        size_t off2[7], tot = 0;
-        for (int k = 0; k < 7; ++k) {
-            off2[k] = tot;
-            tot += align_up(sz[k]);
-        }
-        e = hipMalloc(&R.pool, tot);
-        if (e != hipSuccess) {
-            note_hip_error("hipMalloc(initialiser)", e);
-            R.pool = nullptr;
-            return SF_ERR_OOM;
-        }
-        HIP_TRY(hipMemset(R.pool, 0, tot));
-        R.flat = (float *)(R.pool + off2[0]);
-        R.out = (float *)(R.pool + off2[1]);
-        R.w.wf = (unsigned short *)(R.pool + off2[2]);
-        R.w.wd = (unsigned short *)(R.pool + off2[3]);
-        R.w.bias = (float *)(R.pool + off2[4]);
-        R.x = (unsigned short *)(R.pool + off2[5]);
-        for (int l = 0; l < SF_CNN_LAYERS - 1; ++l)
-            R.acts[l] = (unsigned short *)(R.pool + off2[6]) + (size_t)l * 32 * N4;
-        R.on = true;
-        LevelArgs &a = P.host[F.L - 1][0];
-        a.learned = 1;
-        a.W4 = R.W4;
-        a.H4 = R.H4;
-        a.cnn_out = R.out;
     }
     if (!flat.empty())
         HIP_TRY(hipMemcpy(P.dtab, flat.data(), sizeof(LevelArgs) * flat.size(),
@@ -550,22 +595,30 @@ void enqueue_gn(const Plan &P, hipStream_t st, int l, int g, bool log) {
     enqueue_step(P, st, l, log ? g : -1);
 }
 
-// The network on the level-4 images and its candidate for the coarsest
-// level with the fallback energies.
-void enqueue_cnn_init(const Plan &P, hipStream_t st) {
-    const CnnRun &R = P.cnn;
-    const FrameBuf &F = P.fr[0];
-    launch_cnn_input_tex(st, F.tex + F.lv[SF_CNN_INPUT_LEVEL].tex_off, R.x, R.W4 * R.H4);
-    launch_cnn_forward(st, R.L, R.w, R.x, R.acts, R.out, 1, R.H4, R.W4);
-    launch_cnn_candidate(st, slot(P, F.L - 1));
+// The network on the level-4 images of every frame that uses it: each
+// frame's texels to the bf16 input, then one forward pass per size group.
+void enqueue_cnn_forward(const Plan &P, hipStream_t st) {
+    for (const CnnGroup &g : P.cnn.groups) {
+        const int n4 = g.W4 * g.H4;
+        for (size_t i = 0; i < g.frames.size(); ++i) {
+            const FrameBuf &F = P.fr[g.frames[i]];
+            launch_cnn_input_tex(st, F.tex + F.lv[SF_CNN_INPUT_LEVEL].tex_off,
+                                 g.x + (size_t)16 * n4 * i, n4);
+        }
+        launch_cnn_forward(st, P.net->L, P.net->w, g.x, g.acts, g.out, (int)g.frames.size(),
+                           g.H4, g.W4);
+    }
 }
 
 void enqueue_levels(const Plan &P, hipStream_t st) {
     for (int l = P.Lmax - 1; l >= 0; --l) {
         if (P.prm.illum) launch_illum_zero(st, slot(P, l));
-        if (P.cnn.on && l == P.Lmax - 1) enqueue_cnn_init(P, st);
+        if (P.cnn.on && l == P.Lmax - 1) enqueue_cnn_forward(P, st);
+        // candidates and fallback energies of the frames whose coarsest
+        // level this is
+        if (P.cnn.on && P.cnn.slot_has[l]) launch_cnn_candidate(st, slot(P, l));
         launch_level_init(st, slot(P, l));
-        for (int g = 0; g < P.prm.gn_iters; ++g) enqueue_gn(P, st, l, g, true);
+        for (int g = 0; g < gn_at(P.prm, l); ++g) enqueue_gn(P, st, l, g, true);
         launch_finish_level(st, slot(P, l));
         if (P.prm.illum) launch_illum_next(st, slot(P, l));
         if (P.prm.occlusion) launch_occ_next(st, slot(P, l));
@@ -838,6 +891,32 @@ int batch_levels(int W, int H, int max_levels) {
     return L;
 }
 
+// Allocates the context's network weight buffers (once).
+sf_status ensure_net(sf_ctx *c) {
+    CnnNet &N = c->net;
+    if (N.pool) return SF_OK;
+    N.L = cnn_layout();
+    const size_t sz[] = {sizeof(float) * N.L.n_params, 2 * (size_t)N.L.dev_w_total,
+                         2 * (size_t)N.L.dev_w_total, sizeof(float) * N.L.dev_b_total};
+    size_t off[4], tot = 0;
+    for (int k = 0; k < 4; ++k) {
+        off[k] = tot;
+        tot += align_up(sz[k]);
+    }
+    const hipError_t e = hipMalloc(&N.pool, tot);
+    if (e != hipSuccess) {
+        note_hip_error("hipMalloc(initialiser weights)", e);
+        N.pool = nullptr;
+        return SF_ERR_OOM;
+    }
+    HIP_TRY(hipMemset(N.pool, 0, tot));
+    N.flat = (float *)(N.pool + off[0]);
+    N.w.wf = (unsigned short *)(N.pool + off[1]);
+    N.w.wd = (unsigned short *)(N.pool + off[2]);
+    N.w.bias = (float *)(N.pool + off[3]);
+    return SF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -894,8 +973,10 @@ sf_status sf_create(sf_ctx **out, int width, int height, const sf_params *p,
         delete c;
         return SF_ERR_HIP;
     }
-    s = build_plan(c->single, *p, {width, height}, {p->levels}, false);
+    if (p->init_mode == 1) s = ensure_net(c);
+    if (s == SF_OK) s = build_plan(c->single, *p, {width, height}, {p->levels}, false, &c->net);
     if (s != SF_OK) {
+        if (c->net.pool) (void)hipFree(c->net.pool);
         free_plan(c->single);
         (void)hipStreamDestroy(c->cap_stream);
         delete c;
@@ -913,7 +994,7 @@ sf_status sf_solve(sf_ctx *c, const float *I_left_t, const float *I_right_t,
     const float *img[4] = {I_left_t, I_right_t, I_left_t1, I_right_t1};
     sf_status s = prepare_frame(c, img, calib, p);
     if (s != SF_OK) return s;
-    if (c->single.cnn.on && !c->single.cnn.have_weights) return SF_ERR_STATE;
+    if (c->single.cnn.on && !c->net.have_weights) return SF_ERR_STATE;
     s = run_body(c, c->single);
     if (s != SF_OK) return s;
     launch_output(c->stream, slot(c->single, 0), depth, flow3d, flows);
@@ -931,8 +1012,10 @@ sf_status sf_solve_batch(sf_ctx *c, int n, const sf_frame *frames, const sf_para
     const sf_params prm = p ? *p : c->prm;
     sf_status s = check_params(&prm);
     if (s != SF_OK) return s;
-    // batches start from zero and keep no temporal state
-    if (prm.init_mode != 0 || prm.temporal != 0) return SF_ERR_INVALID_ARG;
+    // batches keep no temporal state; the learned initialisation needs the
+    // context's network
+    if (prm.temporal != 0) return SF_ERR_INVALID_ARG;
+    if (prm.init_mode == 1 && !c->net.have_weights) return SF_ERR_STATE;
     std::vector<int> shape(2 * n), levels(n);
     std::vector<const sf_calib *> cals(n);
     std::vector<FrameIO> io(n);
@@ -966,7 +1049,7 @@ sf_status sf_solve_batch(sf_ctx *c, int n, const sf_frame *frames, const sf_para
     if (!P) {
         P = new (std::nothrow) Plan();
         if (!P) return SF_ERR_OOM;
-        s = build_plan(*P, prm, shape, levels, true);
+        s = build_plan(*P, prm, shape, levels, true, &c->net);
         if (s != SF_OK) {
             free_plan(*P);
             delete P;
@@ -998,12 +1081,11 @@ sf_status sf_get_batch_log(sf_ctx *c, int frame, sf_iter_log *out, int cap, int 
 
 sf_status sf_set_initializer(sf_ctx *c, const void *weights, size_t bytes) {
     if (!c || !weights) return SF_ERR_INVALID_ARG;
-    CnnRun &R = c->single.cnn;
-    if (!R.on) return SF_ERR_STATE;
-    if (bytes != 2 * (size_t)R.L.n_params) return SF_ERR_SIZE;
+    if (bytes != 2 * (size_t)cnn_layout().n_params) return SF_ERR_SIZE;
+    const int n = cnn_layout().n_params;
     const unsigned short *h = (const unsigned short *)weights;
-    std::vector<float> f(R.L.n_params);
-    for (int k = 0; k < R.L.n_params; ++k) {
+    std::vector<float> f(n);
+    for (int k = 0; k < n; ++k) {
         const unsigned u = (unsigned)h[k] << 16;
         float v;
         memcpy(&v, &u, 4);
@@ -1011,25 +1093,50 @@ sf_status sf_set_initializer(sf_ctx *c, const void *weights, size_t bytes) {
         f[k] = v;
     }
     HIP_TRY(hipSetDevice(c->device));
+    sf_status s = ensure_net(c);
+    if (s != SF_OK) return s;
+    CnnNet &N = c->net;
     HIP_TRY(hipStreamSynchronize(c->stream));
-    HIP_TRY(hipMemcpy(R.flat, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice));
-    launch_cnn_pack(c->stream, R.L, R.flat, R.w.wf, R.w.wd, R.w.bias);
+    HIP_TRY(hipMemcpy(N.flat, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice));
+    launch_cnn_pack(c->stream, N.L, N.flat, N.w.wf, N.w.wd, N.w.bias);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));
-    R.have_weights = true;
+    N.have_weights = true;
     return SF_OK;
 }
 
-sf_status sf_get_init_result(sf_ctx *c, int *used, double *e_pred, double *e_zero) {
-    if (!c || !used || !e_pred || !e_zero) return SF_ERR_INVALID_ARG;
-    if (!c->single.cnn.on || !c->single.have_inputs) return SF_ERR_STATE;
+namespace {
+sf_status init_result(sf_ctx *c, const Plan &P, int frame, int *used, double *e_pred,
+                      double *e_zero) {
+    const FrameBuf &F = P.fr[frame];
+    if (F.L <= SF_CNN_INPUT_LEVEL) {
+        *used = -1;
+        *e_pred = *e_zero = nan("");
+        return SF_OK;
+    }
     HIP_TRY(hipStreamSynchronize(c->stream));
     DevScalars sc;
-    HIP_TRY(hipMemcpy(&sc, c->single.fr[0].sc, sizeof(sc), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&sc, F.sc, sizeof(sc), hipMemcpyDeviceToHost));
     *used = sc.init_used;
     *e_pred = sc.e_init[0];
     *e_zero = sc.e_init[1];
     return SF_OK;
+}
+}  // namespace
+
+sf_status sf_get_init_result(sf_ctx *c, int *used, double *e_pred, double *e_zero) {
+    if (!c || !used || !e_pred || !e_zero) return SF_ERR_INVALID_ARG;
+    if (!c->single.cnn.on || !c->single.have_inputs) return SF_ERR_STATE;
+    return init_result(c, c->single, 0, used, e_pred, e_zero);
+}
+
+sf_status sf_get_batch_init_result(sf_ctx *c, int frame, int *used, double *e_pred,
+                                   double *e_zero) {
+    if (!c || !used || !e_pred || !e_zero) return SF_ERR_INVALID_ARG;
+    const Plan *P = c->batch;
+    if (!P || !P->have_inputs || P->prm.init_mode != 1) return SF_ERR_STATE;
+    if (frame < 0 || frame >= P->nf) return SF_ERR_INVALID_ARG;
+    return init_result(c, *P, frame, used, e_pred, e_zero);
 }
 
 const char *sf_last_error(void) { return g_err; }
@@ -1064,6 +1171,7 @@ void sf_destroy(sf_ctx *c) {
         delete c->batch;
     }
     free_plan(c->single);
+    if (c->net.pool) (void)hipFree(c->net.pool);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
 }

@@ -341,24 +341,65 @@ __device__ __forceinline__ void st6(float *vec, long n, const float (&x)[6]) {
 
 // ---- bilinear sampling of (I, Gx, Gy) ------------------------------------
 
-// Value of the three channels at (px, py) and the derivatives of their
-// bilinear interpolants; clamp-to-edge coordinates, zero derivative in a
-// clamped direction.  All accesses stay inside the W x H image for any
-// input, NaN included.
+// A sample coordinate x + dlt (x the integer pixel, dlt the displacement
+// of Eqs. (1)-(6)) taken apart into its bilinear cell and fraction without
+// forming x + dlt in float32: the fraction keeps the precision of the
+// displacement (2^-20 px for |dlt| < 16) instead of that of the absolute
+// coordinate (2^-14 px beyond 512 px), so cell choices at the interpolant's
+// kinks and the weights follow the exact position far more closely.
+// `in` is the exact test 0 <= x + dlt <= n - 1; outside, the coordinate is
+// clamped to the nearest end (fraction 0 at 0, 1 in cell n - 2 at n - 1).
+// A NaN or huge displacement clamps to the low end, outside.
+struct AxisPos {
+    int i0;     // cell: samples i0 and i0 + 1
+    float fr;   // fraction in [0, 1]
+    bool in;
+};
+__device__ __forceinline__ AxisPos axis_pos(int x, float dlt, int n) {
+    constexpr float LIM = 1.0e7f;
+    float k = floorf(dlt);
+    float fr = dlt - k;  // exact: dlt and k share the exponent range, fr in [0, 1)
+    if (!(fabsf(dlt) < LIM)) {
+        k = dlt > 0.f ? LIM : -LIM;
+        fr = 0.f;
+    }
+    const long xi = (long)x + (long)k;
+    AxisPos a;
+    a.in = xi >= 0 && (xi < n - 1 || (xi == n - 1 && fr == 0.f));
+    if (xi < 0) {
+        a.i0 = 0;
+        a.fr = 0.f;
+    } else if (xi >= n - 1) {
+        a.i0 = n - 2;
+        a.fr = 1.f;
+    } else {
+        a.i0 = (int)xi;
+        a.fr = fr;
+    }
+    return a;
+}
+
+// Displacement of camera cam's position from the halfway pixel (Eqs.
+// (1)-(6)): signs of s, m, d per camera, x and y components.
+__device__ __forceinline__ float cam_dx(int cam, const float (&f)[6]) {
+    return (sgn(cam, 0) * f[0] + sgn(cam, 1) * f[2]) + sgn(cam, 2) * f[4];
+}
+__device__ __forceinline__ float cam_dy(int cam, const float (&f)[6]) {
+    return (sgn(cam, 0) * f[1] + sgn(cam, 1) * f[3]) + sgn(cam, 2) * f[5];
+}
+
+// Value of the three channels at a sample position and the derivatives of
+// their bilinear interpolants; clamp-to-edge coordinates, zero derivative
+// in a clamped direction.  All accesses stay inside the W x H image.
 struct Samp {
     float v[3];   // I, Gx, Gy
     float dx[3];  // d/dpx
     float dy[3];  // d/dpy
 };
 __device__ __forceinline__ void sample3(const float4 *__restrict__ img, int W,
-                                        int H, float px, float py, Samp &o) {
-    const bool inx = (px >= 0.f) && (px <= (float)(W - 1));
-    const bool iny = (py >= 0.f) && (py <= (float)(H - 1));
-    const float cx = fminf(fmaxf(px, 0.f), (float)(W - 1));
-    const float cy = fminf(fmaxf(py, 0.f), (float)(H - 1));
-    const int x0 = min((int)floorf(cx), W - 2);
-    const int y0 = min((int)floorf(cy), H - 2);
-    const float fx = cx - (float)x0, fy = cy - (float)y0;
+                                        const AxisPos &px, const AxisPos &py, Samp &o) {
+    const int x0 = px.i0, y0 = py.i0;
+    const float fx = px.fr, fy = py.fr;
     const float4 a = img[y0 * W + x0];
     const float4 b = img[y0 * W + x0 + 1];
     const float4 c = img[(y0 + 1) * W + x0];
@@ -369,8 +410,8 @@ __device__ __forceinline__ void sample3(const float4 *__restrict__ img, int W,
     for (int ch = 0; ch < 3; ++ch) {
         o.v[ch] = (1.f - fy) * ((1.f - fx) * ta[ch] + fx * tb[ch]) +
                   fy * ((1.f - fx) * tc[ch] + fx * td[ch]);
-        o.dx[ch] = inx ? ((1.f - fy) * (tb[ch] - ta[ch]) + fy * (td[ch] - tc[ch])) : 0.f;
-        o.dy[ch] = iny ? ((1.f - fx) * (tc[ch] - ta[ch]) + fx * (td[ch] - tb[ch])) : 0.f;
+        o.dx[ch] = px.in ? ((1.f - fy) * (tb[ch] - ta[ch]) + fy * (td[ch] - tc[ch])) : 0.f;
+        o.dy[ch] = py.in ? ((1.f - fx) * (tc[ch] - ta[ch]) + fx * (td[ch] - tb[ch])) : 0.f;
     }
 }
 
@@ -537,9 +578,9 @@ __device__ __forceinline__ void pixel_terms(const LevelArgs &a, int x, int y,
     Samp S[4];
 #pragma unroll
     for (int cam = 0; cam < 4; ++cam) {
-        const float px = (((float)x + sgn(cam, 0) * f[0]) + sgn(cam, 1) * f[2]) + sgn(cam, 2) * f[4];
-        const float py = (((float)y + sgn(cam, 0) * f[1]) + sgn(cam, 1) * f[3]) + sgn(cam, 2) * f[5];
-        sample3(a.tex + (long)cam * d.N, d.W, d.H, px, py, S[cam]);
+        const AxisPos px = axis_pos(x, cam_dx(cam, f), d.W);
+        const AxisPos py = axis_pos(y, cam_dy(cam, f), d.H);
+        sample3(a.tex + (long)cam * d.N, d.W, px, py, S[cam]);
     }
     if (a.illum) {
         // illumination correction of the right-camera samples
@@ -2159,11 +2200,8 @@ __global__ __launch_bounds__(SF_BLOCK) void k_fallback(KArg<B> ka) {
             pixel_flows(a, x, y, S, f);
             bool V = true;
 #pragma unroll
-            for (int cam = 0; cam < 4; ++cam) {
-                const float px = (((float)x + sgn(cam, 0) * f[0]) + sgn(cam, 1) * f[2]) + sgn(cam, 2) * f[4];
-                const float py = (((float)y + sgn(cam, 0) * f[1]) + sgn(cam, 1) * f[3]) + sgn(cam, 2) * f[5];
-                V = V && px >= 0.f && px <= (float)(d.W - 1) && py >= 0.f && py <= (float)(d.H - 1);
-            }
+            for (int cam = 0; cam < 4; ++cam)
+                V = V && axis_pos(x, cam_dx(cam, f), d.W).in && axis_pos(y, cam_dy(cam, f), d.H).in;
             const float c = V ? 1.f : 0.f;
             const float z[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             PixelOut o;
@@ -2305,11 +2343,11 @@ __global__ __launch_bounds__(SF_BLOCK) void k_masks(KArg<B> ka) {
         float I[4];
 #pragma unroll
         for (int cam = 0; cam < 4; ++cam) {
-            const float px = (((float)x + sgn(cam, 0) * f[0]) + sgn(cam, 1) * f[2]) + sgn(cam, 2) * f[4];
-            const float py = (((float)y + sgn(cam, 0) * f[1]) + sgn(cam, 1) * f[3]) + sgn(cam, 2) * f[5];
-            V = V && px >= 0.f && px <= (float)(d.W - 1) && py >= 0.f && py <= (float)(d.H - 1);
+            const AxisPos px = axis_pos(x, cam_dx(cam, f), d.W);
+            const AxisPos py = axis_pos(y, cam_dy(cam, f), d.H);
+            V = V && px.in && py.in;
             Samp sm;
-            sample3(a.tex + (long)cam * d.N, d.W, d.H, px, py, sm);
+            sample3(a.tex + (long)cam * d.N, d.W, px, py, sm);
             I[cam] = sm.v[0];
         }
         if (a.occ && !a.occ[(long)y * d.W + x]) V = false;
@@ -2423,11 +2461,11 @@ __global__ __launch_bounds__(SF_BLOCK) void k_illum_resid(KArg<B> ka) {
         float I[4];
 #pragma unroll
         for (int cam = 0; cam < 4; ++cam) {
-            const float px = (((float)x + sgn(cam, 0) * f[0]) + sgn(cam, 1) * f[2]) + sgn(cam, 2) * f[4];
-            const float py = (((float)y + sgn(cam, 0) * f[1]) + sgn(cam, 1) * f[3]) + sgn(cam, 2) * f[5];
-            V = V && px >= 0.f && px <= (float)(d.W - 1) && py >= 0.f && py <= (float)(d.H - 1);
+            const AxisPos px = axis_pos(x, cam_dx(cam, f), d.W);
+            const AxisPos py = axis_pos(y, cam_dy(cam, f), d.H);
+            V = V && px.in && py.in;
             Samp sm;
-            sample3(a.tex + (long)cam * d.N, d.W, d.H, px, py, sm);
+            sample3(a.tex + (long)cam * d.N, d.W, px, py, sm);
             I[cam] = sm.v[0];
         }
         a.ill_e[(long)y * d.W + x] = V ? 0.5f * ((I[1] - I[0]) + (I[3] - I[2])) : 0.f;
@@ -2650,13 +2688,14 @@ __global__ __launch_bounds__(SF_BLOCK) void k_output(KArg<B> ka, float *depth,
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         const int cl = t == 0 ? 0 : 2, cr = t == 0 ? 1 : 3;
-        const float lx = (((float)x + sgn(cl, 0) * f[0]) + sgn(cl, 1) * f[2]) + sgn(cl, 2) * f[4];
-        const float ly = (((float)y + sgn(cl, 0) * f[1]) + sgn(cl, 1) * f[3]) + sgn(cl, 2) * f[5];
-        const float rx = (((float)x + sgn(cr, 0) * f[0]) + sgn(cr, 1) * f[2]) + sgn(cr, 2) * f[4];
-        const float disp = lx - rx;
+        // the pixel coordinate cancels in the disparity and is taken
+        // relative to the principal point first, so neither rounds at the
+        // scale of the image size
+        const float dl = cam_dx(cl, f), dr = cam_dx(cr, f);
+        const float disp = dl - dr;
         const float Z = disp > 0.f ? C.fx * C.baseline / disp : __builtin_nanf("");
-        X[t][0] = (lx - C.cx) * Z / C.fx;
-        X[t][1] = (ly - C.cy) * Z / C.fy;
+        X[t][0] = (((float)x - C.cx) + dl) * Z / C.fx;
+        X[t][1] = (((float)y - C.cy) + cam_dy(cl, f)) * Z / C.fy;
         X[t][2] = Z;
     }
     depth[pix] = X[0][2];
@@ -2812,9 +2851,13 @@ void launch_downsample(hipStream_t st, const Launch &L) {
     go(st, L, tx_blocks, k_texl<true>, k_texl<false>, SF_BLOCK, 0);
 }
 
+// Only the frames whose coarsest level is initialised by the network get
+// workgroups (a batch may mix them with frames that start from zero).
 void launch_cnn_candidate(hipStream_t st, const Launch &L) {
-    go(st, L, nd_blocks, k_cnn_nodes<true>, k_cnn_nodes<false>, SF_BLOCK, 0);
-    go(st, L, en_blocks, k_fallback<true>, k_fallback<false>, SF_BLOCK, 0);
+    auto nd = [](const LevelArgs &a) { return a.learned ? node_blocks(a.d) : 0; };
+    auto en = [](const LevelArgs &a) { return a.learned ? energy_blocks_of(a.d) : 0; };
+    go(st, L, nd, k_cnn_nodes<true>, k_cnn_nodes<false>, SF_BLOCK, 0);
+    go(st, L, en, k_fallback<true>, k_fallback<false>, SF_BLOCK, 0);
 }
 
 void launch_level_masks(hipStream_t st, const Launch &L) {

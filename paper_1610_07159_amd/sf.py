@@ -51,7 +51,7 @@ class sf_calib(ctypes.Structure):
 
 _PARAM_INTS = ("levels", "grid_stride", "gn_iters", "pcg_iters",
                "max_backtracks", "init_mode", "exec_mode", "tile_mode",
-               "apply_mode", "temporal", "illum", "occlusion")
+               "apply_mode", "temporal", "illum", "occlusion", "gn_fine")
 _PARAM_FLOATS = ("w_reg", "w_photo", "w_grad", "w_epi", "w_smooth", "w_mag",
                  "w_s", "w_m", "w_d", "m_s", "m_m", "m_d", "eps", "eps_p",
                  "st_gamma", "st_tau")
@@ -128,6 +128,8 @@ def _load():
     lib.sf_set_initializer.argtypes = [P, P, S]
     lib.sf_get_init_result.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(D),
                                        ctypes.POINTER(D)]
+    lib.sf_get_batch_init_result.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(D),
+                                             ctypes.POINTER(D)]
     lib.sf_trainer_create.argtypes = [ctypes.POINTER(P), I, I, I, P]
     lib.sf_trainer_set_params.argtypes = [P, P, S]
     lib.sf_trainer_get_params.argtypes = [P, P, S]
@@ -138,7 +140,8 @@ def _load():
     lib.sf_trainer_read.argtypes = [P, I, I, P, S]
     lib.sf_trainer_destroy.argtypes = [P]
     lib.sf_trainer_destroy.restype = None
-    for f in ("sf_set_initializer", "sf_get_init_result", "sf_trainer_create",
+    for f in ("sf_set_initializer", "sf_get_init_result", "sf_get_batch_init_result",
+              "sf_trainer_create",
               "sf_trainer_set_params", "sf_trainer_get_params", "sf_trainer_forward",
               "sf_trainer_step", "sf_trainer_read"):
         getattr(lib, f).restype = I
@@ -336,6 +339,15 @@ def sf_get_init_result(ctx):
     _check(lib.sf_get_init_result(ctx, ctypes.byref(used), ctypes.byref(ep), ctypes.byref(ez)),
            "sf_get_init_result")
     return bool(used.value), ep.value, ez.value
+
+
+def sf_get_batch_init_result(ctx, frame):
+    """(used, e_pred, e_zero) of batch frame `frame`; used = -1 for a frame
+    with too few levels for the network (it started from zero)."""
+    used, ep, ez = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+    _check(lib.sf_get_batch_init_result(ctx, int(frame), ctypes.byref(used), ctypes.byref(ep),
+                                        ctypes.byref(ez)), "sf_get_batch_init_result")
+    return used.value, ep.value, ez.value
 
 
 def sf_trainer_create(max_batch, height, width, stream=0):

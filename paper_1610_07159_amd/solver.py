@@ -78,6 +78,11 @@ class SceneFlowSolver:
     def batch_log(self, frame):
         return sf.sf_get_batch_log(self.ctx, frame)[0]
 
+    def batch_init_result(self, frame):
+        """(used, e_pred, e_zero) of a batch frame solved with init_mode 1
+        (used = -1: too few levels for the network, started from zero)."""
+        return sf.sf_get_batch_init_result(self.ctx, frame)
+
     def log(self):
         return sf.sf_get_log(self.ctx)[0]
 

@@ -4,9 +4,13 @@
         --out init_640x480.npy --report report.json
 
 1. Renders seeded generator frames (training seeds 0.., evaluation seeds
-   1,000,000..) in a process pool on the host.
-2. Targets: the plain solver's (zero initialisation) level-0 flows of each
-   training frame, restricted to level 4 (16 x 16 box average / 16).
+   1,000,000..) in a pool of host processes started before anything
+   touches the GPU; training frames stream through the GPU as they arrive,
+   so only their level-4 data is kept.
+2. Inputs: the level-4 intensities of the solver's own float32 pyramid (the
+   images the network sees at inference).  Targets: the plain solver's
+   (zero initialisation) level-0 flows of each training frame, restricted
+   to level 4 (16 x 16 box average / 16).
 3. Trains the network on the level-4 image quadruples with the GPU trainer
    (sf_trainer_*: bf16 matrix-core forward/backward, L1 loss, Adam with a
    cosine learning-rate decay), batches drawn by a seeded shuffle.
@@ -87,6 +91,106 @@ def epe(flows, truth, W, H):
     return float((err / 4.0)[inside].mean())
 
 
+def start_pool(workers):
+    """A process pool whose workers are all running before the caller
+    touches the GPU (they render on the host only)."""
+    from concurrent.futures import ProcessPoolExecutor
+    ex = ProcessPoolExecutor(max_workers=workers)
+    list(ex.map(time.sleep, [0.2] * (2 * workers)))
+    return ex
+
+
+def level4_intensities(solver, H, W):
+    """The four level-4 images of the solver's last frame from its own
+    pyramid (float32 texels (I, G_x, G_y, 0)), shape (4, H >> 4, W >> 4)."""
+    from paper_1610_07159_amd import sf
+    tex = sf.sf_debug_read(solver.ctx, sf.SF_DBG_TEX, LEVEL_IN)
+    return tex.reshape(4, H >> LEVEL_IN, W >> LEVEL_IN, 4)[..., 0].copy()
+
+
+def stream_training_data(ex, W, H, seeds, sched, log=print, max_disp=None, blobs=0):
+    """Renders the training frames in the pool and solves each on the GPU
+    as it arrives (plain solver, zero initialisation); returns the level-4
+    inputs x (N, 4, h, w) and targets y (N, 6, h, w), float32."""
+    import torch
+    from paper_1610_07159_amd import SceneFlowSolver
+    jobs = [(W, H, s, False, max_disp, blobs) for s in seeds]
+    solver = SceneFlowSolver(W, H, **sched)
+    xs, ys = [], []
+    try:
+        out = (torch.empty((H, W), device="cuda"), torch.empty((3, H, W), device="cuda"),
+               torch.empty((6, H, W), device="cuda"))
+        for k, f in enumerate(ex.map(_render, jobs, chunksize=1)):
+            img = torch.from_numpy(f["imgs"]).cuda()
+            solver.solve(img, f["calib"], out=out)
+            xs.append(level4_intensities(solver, H, W))
+            # restriction to level 4 (16 x 16 box average, floor sizes) on
+            # the device: only the small target crosses to the host
+            k = 1 << LEVEL_IN
+            fl = out[2][:, :(H // k) * k, :(W // k) * k]
+            ys.append((torch.nn.functional.avg_pool2d(fl[None], k)[0] / k).cpu().numpy())
+            if (k + 1) % 100 == 0:
+                log(f"  rendered and solved {k + 1}/{len(jobs)}")
+    finally:
+        solver.close()
+    return np.stack(xs), np.stack(ys)
+
+
+def epe_gpu(flows, truth):
+    """epe() on the GPU: flows (6, H, W) device tensor, truth (pos, ok) host
+    arrays."""
+    import torch
+    pos, ok = truth
+    dev = flows.device
+    H, W = flows.shape[1:]
+    yy, xx = torch.meshgrid(torch.arange(H, device=dev, dtype=torch.float64),
+                            torch.arange(W, device=dev, dtype=torch.float64), indexing="ij")
+    f = flows.double()
+    p = torch.from_numpy(np.asarray(pos)).to(dev).double()
+    inside = torch.from_numpy(np.asarray(ok)).to(dev).clone()
+    err = torch.zeros((H, W), device=dev, dtype=torch.float64)
+    for c, (a, b, d) in enumerate(((-1, -1, 1), (1, -1, -1), (-1, 1, -1), (1, 1, 1))):
+        px = xx + a * f[0] + b * f[2] + d * f[4]
+        py = yy + a * f[1] + b * f[3] + d * f[5]
+        err += torch.hypot(px - p[c, 0], py - p[c, 1])
+        inside &= (p[c, 0] >= 0) & (p[c, 0] <= W - 1) & (p[c, 1] >= 0) & (p[c, 1] <= H - 1)
+    return float((err / 4.0)[inside].mean())
+
+
+def eval_sweep(frames, W, H, sched, init_mode, weights, n):
+    """Mean EPE (GPU) and GPU ms/frame of solves with n Gauss-Newton steps
+    per level; prediction-kept count for init_mode 1."""
+    import torch
+    from paper_1610_07159_amd import SceneFlowSolver, sf
+    solver = SceneFlowSolver(W, H, init_mode=init_mode, **dict(sched, gn_iters=n))
+    try:
+        if init_mode:
+            sf.sf_set_initializer(solver.ctx, weights)
+        out = (torch.empty((H, W), device="cuda"), torch.empty((3, H, W), device="cuda"),
+               torch.empty((6, H, W), device="cuda"))
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        epes, ms, used = [], [], 0
+        for f in frames:
+            img = torch.from_numpy(f["imgs"]).cuda()
+            solver.solve(img, f["calib"], out=out)  # graph, tiles, caches
+            e0.record(solver.stream)
+            solver.solve(img, f["calib"], out=out)
+            e1.record(solver.stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+            epes.append(epe_gpu(out[2], f["truth"]))
+            if init_mode:
+                used += int(sf.sf_get_init_result(solver.ctx)[0])
+    finally:
+        solver.close()
+    row = dict(gn_iters=n, epe_px=round(float(np.mean(epes)), 4),
+               ms_per_frame=round(float(np.mean(ms)), 3))
+    if init_mode:
+        row["prediction_kept"] = used
+    return float(np.mean(epes)), row
+
+
 def solve_flows(frames, W, H, init_mode=0, weights=None, timed=False, **sched):
     """Runs the solver on every frame; returns per-frame level-0 flows and,
     if timed, the mean GPU time per frame (HIP events, graph replay)."""
@@ -155,6 +259,44 @@ def train_gpu(x, y, epochs, batch, lr, seed, init_seed=0, log=print):
         sf.sf_trainer_destroy(t)
 
 
+def conv_flops(B, h, w):
+    """Multiply-adds x 2 of one forward pass of the network on B inputs of
+    h x w (3 x 3 convolutions 4 -> 32 -> 32 -> 32 -> 32 -> 32 -> 6)."""
+    chans = (4, 32, 32, 32, 32, 32, 6)
+    return 2 * 9 * B * h * w * sum(a * b for a, b in zip(chans[:-1], chans[1:]))
+
+
+def profile_trainer(h, w, batch, steps, log=print):
+    """Times `steps` trainer steps (forward, L1 loss, backward, Adam) on
+    random inputs; reports the achieved rate counting forward + input
+    gradient + weight gradient as 3 forward passes of flops."""
+    import torch
+    from paper_1610_07159_amd import sf
+    t = sf.sf_trainer_create(batch, h, w, torch.cuda.current_stream().cuda_stream)
+    try:
+        sf.sf_trainer_set_params(t, he_init(0))
+        g = torch.Generator(device="cuda").manual_seed(0)
+        x = torch.rand((batch, 4, h, w), device="cuda", generator=g)
+        y = torch.randn((batch, 6, h, w), device="cuda", generator=g)
+        for _ in range(5):
+            sf.sf_trainer_step(t, x.data_ptr(), y.data_ptr(), batch, 1e-4, want_loss=False)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            sf.sf_trainer_step(t, x.data_ptr(), y.data_ptr(), batch, 1e-4, want_loss=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+    finally:
+        sf.sf_trainer_destroy(t)
+    tflops = 3 * conv_flops(batch, h, w) / (ms * 1e-3) / 1e12
+    log(json.dumps(dict(batch=batch, height=h, width=w, steps=steps, ms_per_step=round(ms, 4),
+                        step_tflop=round(3 * conv_flops(batch, h, w) / 1e12, 5),
+                        tflop_per_s=round(tflops, 2))))
+
+
 def he_init(seed):
     """He-normal weights (std sqrt(2 / fan_in)), zero biases, last layer
     scaled by 0.1 (small initial predictions); flat layout of sf.h."""
@@ -183,61 +325,68 @@ def main():
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--out", default="init_weights.npy")
     ap.add_argument("--report", default="init_report.json")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="only time this many trainer steps on random level-4 inputs of "
+                         "the frame size (batch --batch) and exit")
     args = ap.parse_args()
     log = lambda m: print(m, flush=True)  # noqa: E731
+    if args.profile_steps:
+        return profile_trainer(args.width >> LEVEL_IN, args.height >> LEVEL_IN, args.batch,
+                               args.profile_steps, log)
     W, H = args.width, args.height
     sched_full = dict(SCHEDULE, levels=args.levels)
     scene = dict(max_disp=args.max_disp, blobs=args.blobs)
+    # host workers first: nothing has touched the GPU yet
+    ex = start_pool(args.workers)
     t0 = time.time()
-    train_frames = render_frames(W, H, range(args.frames), False, args.workers, log, **scene)
-    log(f"rendered {len(train_frames)} training frames in {time.time() - t0:.0f} s")
-    t1 = time.time()
-    eval_frames = render_frames(W, H, range(1_000_000, 1_000_000 + args.eval), True,
-                                args.workers, log, **scene)
-    log(f"rendered {len(eval_frames)} evaluation frames with truth in {time.time() - t1:.0f} s")
+    eval_seeds = range(1_000_000, 1_000_000 + args.eval)
+    eval_frames = list(ex.map(_render, [(W, H, s, True, args.max_disp, args.blobs)
+                                        for s in eval_seeds], chunksize=1))
+    log(f"rendered {len(eval_frames)} evaluation frames with truth in {time.time() - t0:.0f} s")
 
     import torch
     torch.cuda.set_device(0)
-    flows, _, _ = solve_flows(train_frames, W, H, **sched_full)
-    x = np.stack([box_restrict(f["imgs"]) for f in train_frames]).astype(np.float32)
-    y = np.stack([box_restrict(fl) / (1 << LEVEL_IN) for fl in flows]).astype(np.float32)
-    log(f"targets from the plain solver: {y.shape}")
+    t1 = time.time()
+    x, y = stream_training_data(ex, W, H, range(args.frames), sched_full, log, **scene)
+    ex.shutdown()
+    log(f"{len(x)} training frames rendered and solved in {time.time() - t1:.0f} s; "
+        f"inputs {x.shape}, targets {y.shape}")
     t2 = time.time()
     params, curve = train_gpu(x, y, args.epochs, args.batch, args.lr, seed=1, log=log)
     log(f"trained in {time.time() - t2:.1f} s")
     np.save(args.out, params)
 
-    plain, _, ms_plain = solve_flows(eval_frames, W, H, timed=True, **sched_full)
-    epe_plain = float(np.mean([epe(fl, f["truth"], W, H) for fl, f in zip(plain, eval_frames)]))
-    sweep = []
-    for n in range(1, sched_full["gn_iters"] + 1):
-        sched = dict(sched_full, gn_iters=n)
-        fl, used, ms = solve_flows(eval_frames, W, H, init_mode=1, weights=params, timed=True,
-                                   **sched)
-        e = float(np.mean([epe(a, f["truth"], W, H) for a, f in zip(fl, eval_frames)]))
-        sweep.append(dict(gn_iters=n, epe_px=round(e, 4), ms_per_frame=round(ms, 3),
-                          init_used=int(sum(used))))
-        log(f"learned init, {n} GN/level: EPE {e:.4f} px, {ms:.2f} ms/frame, "
-            f"prediction kept on {sum(used)}/{len(used)} frames")
-    zero_sweep = []
-    for n in range(1, sched_full["gn_iters"] + 1):
-        fl, _, ms = solve_flows(eval_frames, W, H, timed=True, **dict(sched_full, gn_iters=n))
-        e = float(np.mean([epe(a, f["truth"], W, H) for a, f in zip(fl, eval_frames)]))
-        zero_sweep.append(dict(gn_iters=n, epe_px=round(e, 4), ms_per_frame=round(ms, 3)))
-    reach = next((s for s in sweep if s["epe_px"] <= epe_plain), None)
+    # equal EPE: target = plain at the full schedule; fewest steps per level
+    # reaching it for plain and learned
+    full = sched_full["gn_iters"]
+    target, full_row = eval_sweep(eval_frames, W, H, sched_full, 0, None, full)
+    log(f"plain, {full} GN/level: EPE {target:.4f} px, {full_row['ms_per_frame']} ms/frame")
+    sweeps, reach = {}, {}
+    for name, mode in (("plain", 0), ("learned", 1)):
+        sweeps[name], reach[name] = [], None
+        for n in range(1, full + 1):
+            e, row = (target, full_row) if (mode == 0 and n == full) else \
+                eval_sweep(eval_frames, W, H, sched_full, mode, params, n)
+            sweeps[name].append(row)
+            log(f"{name}, {n} GN/level: {row}")
+            if e <= target:
+                reach[name] = row
+                break
+    speedup = (round(reach["plain"]["ms_per_frame"] / reach["learned"]["ms_per_frame"], 3)
+               if reach["plain"] and reach["learned"] else None)
     report = dict(
-        frames=args.frames, eval_frames=args.eval, size=f"{W}x{H}", schedule=sched_full,
-        max_disp=args.max_disp, blobs=args.blobs,
-        epochs=args.epochs, batch=args.batch, lr=args.lr, loss_curve=[round(c, 5) for c in curve],
-        plain=dict(gn_iters=sched_full["gn_iters"], epe_px=round(epe_plain, 4),
-                   ms_per_frame=round(ms_plain, 3)),
-        learned_sweep=sweep, zero_init_sweep=zero_sweep,
-        equal_epe=(dict(gn_iters=reach["gn_iters"], ms_per_frame=reach["ms_per_frame"],
-                        speedup=round(ms_plain / reach["ms_per_frame"], 3))
-                   if reach else None))
+        frames=args.frames, eval_frames=args.eval, eval_seeds=[eval_seeds[0], eval_seeds[-1]],
+        size=f"{W}x{H}", schedule=sched_full, max_disp=args.max_disp, blobs=args.blobs,
+        epochs=args.epochs, batch=args.batch, lr=args.lr,
+        loss_curve=[round(c, 5) for c in curve], target_epe_px=round(target, 4),
+        plain_full_schedule=full_row, plain_sweep=sweeps["plain"],
+        learned_sweep=sweeps["learned"], plain_at_target=reach["plain"],
+        learned_at_target=reach["learned"], speedup_at_equal_epe=speedup,
+        command="python -m paper_1610_07159_amd.train_init " + " ".join(sys.argv[1:]))
     with open(args.report, "w") as f:
         json.dump(report, f, indent=1)
-    log(json.dumps(dict(plain=report["plain"], equal_epe=report["equal_epe"])))
+    log(json.dumps(dict(target=report["target_epe_px"], plain=reach["plain"],
+                        learned=reach["learned"], speedup=speedup)))
 
 
 if __name__ == "__main__":

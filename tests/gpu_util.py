@@ -5,7 +5,7 @@ import numpy as np
 
 import oracle.halfway as O
 
-PARAM_FIELDS = ("levels", "grid_stride", "gn_iters", "pcg_iters",
+PARAM_FIELDS = ("levels", "grid_stride", "gn_iters", "gn_fine", "pcg_iters",
                 "max_backtracks", "w_reg", "w_photo", "w_grad", "w_epi",
                 "w_smooth", "w_mag", "w_s", "w_m", "w_d", "m_s", "m_m", "m_d",
                 "eps", "eps_p", "st_gamma", "st_tau", "illum", "occlusion")
@@ -109,3 +109,75 @@ def rel_err(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _output_bound(flows, W, H, calib, dP):
+    """Worst-case error of the Sec. 3 output (depth Z_0, 3D flow X_1 - X_0)
+    when every position of Eqs. (1)-(6) is off by at most dP px: a disparity
+    is off by at most 2 dP, so Z = f_x B / disp by at most
+    Z 2dP / (disp - 2dP) (|dZ/d disp| = Z^2 / (f_x B) to first order), and the
+    back-projection X = (x - c_x) Z / f_x by at most
+    (|x - c_x| dZ + (Z + dZ) dP) / f_x.  Returns (dZ_0, dflow3d (3, N),
+    disp (2, N))."""
+    if isinstance(calib, dict):
+        calib = O.Calib.from_dict(calib)
+    flows = np.asarray(flows, np.float64).reshape(6, -1)
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    P = O.positions(x.reshape(-1), y.reshape(-1), flows)
+    dX, dZs, disps = [], [], []
+    for cl, cr in ((0, 1), (2, 3)):
+        disp = P[cl, 0] - P[cr, 0]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            Z = calib.fx * calib.baseline / disp
+            dZ = Z * 2 * dP / (disp - 2 * dP)
+        dZ = dZ + 4e-7 * np.abs(Z)          # float32 rounding of the division
+        ex = (np.abs(P[cl, 0] - calib.cx) * dZ + (np.abs(Z) + dZ) * dP) / calib.fx
+        ey = (np.abs(P[cl, 1] - calib.cy) * dZ + (np.abs(Z) + dZ) * dP) / calib.fy
+        dX.append(np.stack([ex, ey, dZ]) + 4e-7 * np.abs(Z))
+        dZs.append(dZ)
+        disps.append(disp)
+    return dZs[0], dX[0] + dX[1], np.stack(disps)
+
+
+def check_output(depth, flow3d, flows_gpu, W, H, calib, flows_ref=None, flow_err=0.0):
+    """Parity of the solve's output (Sec. 3: depth of the halfway pixel and
+    its 3D motion, reading R18).
+
+    Arithmetic: depth and flow3d against the oracle's output evaluated on the
+    GPU's own per-pixel flows; the two differ only by the float32 rounding of
+    the positions (each a sum of four terms below max(W, H) + |flow|: at most
+    two ulps of that magnitude) and of the division.
+
+    End to end (flows_ref given): against the oracle's output of its own
+    flows, with the bound propagated from the measured flow error e (every
+    position is a signed sum of three flows, so off by at most 3e).
+
+    Depth is NaN where disp_0 <= 0 and flow3d where either disparity is; the
+    NaN patterns must agree exactly wherever the disparity is farther than
+    the position error from zero.  Returns the number of pixels compared."""
+    depth = np.asarray(depth, np.float64).reshape(-1)
+    flow3d = np.asarray(flow3d, np.float64).reshape(3, -1)
+    cases = [(flows_gpu, 2 * float(np.spacing(np.float32(1.5 * max(W, H)))))]
+    if flows_ref is not None:
+        cases.append((flows_ref, 3 * flow_err + cases[0][1]))
+    n = 0
+    for flows, dP in cases:
+        d_ref, f_ref, _ = O.output_from_flows(flows, W, H, calib)
+        d_ref = d_ref.reshape(-1)
+        f_ref = f_ref.reshape(3, -1)
+        dZ, dF, disp = _output_bound(flows, W, H, calib, dP)
+        sure = np.abs(disp) > 2 * dP                 # NaN decision is certain
+        nan_g, nan_r = ~np.isfinite(depth), ~np.isfinite(d_ref)
+        assert np.array_equal(nan_g[sure[0]], nan_r[sure[0]]), "depth NaN pattern differs"
+        fnan_g = ~np.isfinite(flow3d).all(0)
+        fnan_r = ~np.isfinite(f_ref).all(0)
+        both = sure.all(0)
+        assert np.array_equal(fnan_g[both], fnan_r[both]), "flow3d NaN pattern differs"
+        v = (disp[0] > 2 * dP)
+        assert np.all(np.abs(depth[v] - d_ref[v]) <= dZ[v]), (
+            "depth", float(np.max(np.abs(depth[v] - d_ref[v]) - dZ[v])))
+        fin = (disp > 2 * dP).all(0)
+        assert np.all(np.abs(flow3d[:, fin] - f_ref[:, fin]) <= dF[:, fin]), (
+            "flow3d", float(np.max(np.abs(flow3d[:, fin] - f_ref[:, fin]) - dF[:, fin])))
+        n = max(n, int(fin.sum()))
+    return n

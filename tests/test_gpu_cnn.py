@@ -4,8 +4,12 @@ bfloat16-emulating mode (the same roundings of weights, input, hidden
 activations and gradients, exact sums).  The two then differ only where
 float32 accumulation puts a value on the other side of a bfloat16 rounding
 boundary (one unit in the last place, 2^-8 relative), and such flips
-propagate through later layers; the tolerances below allow that and
-nothing more."""
+propagate through later layers.  Measured on MI355X for the cases below:
+at least 99.8 % of every activation and pre-activation gradient within one
+bf16 ulp, the largest error 2.4e-3 of the tensor's scale, norm errors up to
+1.8e-4 (activations, pre-activation gradients) and 8.6e-5 (weight
+gradients); the bars (99.5 %, 5e-3, 5e-4) sit about three times above them
+and the tests print what each run achieves."""
 import numpy as np
 import pytest
 
@@ -20,12 +24,15 @@ pytestmark = pytest.mark.gpu
 ULP = 2.0 ** -7
 
 
-def _close_bf16(gpu, ref, what, frac=0.995, max_rel=0.05, norm_rel=5e-3):
+def _close_bf16(gpu, ref, what, frac=0.995, max_rel=5e-3, norm_rel=5e-4):
     gpu = np.asarray(gpu, np.float64)
     ref = np.asarray(ref, np.float64)
     err = np.abs(gpu - ref)
     scale = max(np.abs(ref).max(), 1e-30)
     ok = err <= ULP * np.abs(ref) + 1e-6 * scale
+    print(f"{what}: {100 * ok.mean():.3f} % within one bf16 ulp, max error "
+          f"{err.max() / scale:.2e} of scale, norm error "
+          f"{np.linalg.norm(err) / max(np.linalg.norm(ref), 1e-30):.2e}", flush=True)
     assert ok.mean() >= frac, (what, ok.mean())
     assert err.max() <= max_rel * scale, (what, err.max() / scale)
     assert np.linalg.norm(err) <= norm_rel * max(np.linalg.norm(ref), 1e-30), what
@@ -97,7 +104,7 @@ def test_backward_and_adam_match_oracle():
         hid = C.hidden_gradients(f64, acts, dout, bf16=True)
         for l in range(5):
             d = _nchw(sf.sf_trainer_read(t, sf.SF_TR_DPRE, l), B, H, W, 32)
-            _close_bf16(d, hid[l], f"dpre{l}", frac=0.99, max_rel=0.1, norm_rel=1e-2)
+            _close_bf16(d, hid[l], f"dpre{l}")
         g = sf.sf_trainer_read(t, sf.SF_TR_GRAD).astype(np.float64)
         g_ref = C.backward(f64, acts, dout, bf16=True)
         L = C.unpack(np.arange(C.N_PARAMS))
@@ -105,7 +112,9 @@ def test_backward_and_adam_match_oracle():
         for l, (Wl, bl) in enumerate(L):
             n = Wl.size + bl.size
             gl, rl = g[k:k + n], g_ref[k:k + n]
-            assert np.linalg.norm(gl - rl) <= 1e-2 * np.linalg.norm(rl), l
+            rel = np.linalg.norm(gl - rl) / np.linalg.norm(rl)
+            print(f"layer {l} gradient: norm error {rel:.2e}", flush=True)
+            assert rel <= 5e-4, l
             k += n
         # Adam: the lr = 0 step counted as step 1; step 2 with lr on the
         # same batch (same gradient, parameters unchanged by step 1)

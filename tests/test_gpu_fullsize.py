@@ -1,10 +1,22 @@
 """Parity at the benchmark workloads' full sizes (640x480 and 1280x720 at
 strides 2, 4, 8), in the launch configuration bench.py times (captured
-graph, autotuned PCG tiles), on outputs the oracle computes one by one:
+graph, autotuned PCG tiles).
+
+Whole solves (test_fullsize_solve_parity, the learned and batched ones):
+every (level, Gauss-Newton step) energy within 1e-4 relative of the FP64
+oracle's, final per-pixel flows within 0.02 px at >= 99.9 % of the pixels
+and everywhere within a cap that allows for the iteration's sensitivity at a
+few featureless nodes (see _check_against_golden), and depth and 3D flow
+against the
+oracle's output, with the oracle's results stored in tests/golden/ by
+tests/golden/make_fullsize.py (the oracle needs minutes per frame at these
+sizes).
+
+Stages (test_fullsize_stage_parity), on outputs the oracle computes one by
+one:
 masks and smoothness weights, the total energy, the linearisation records
 of sampled pixels and the gradient, diag(H) and H u of sampled nodes, at a
-level-0 state the test sets; plus properties of the full solve (energy never
-increases, finite outputs).
+level-0 state the test sets.
 
 Tolerances: those of test_gpu_parity.py (2e-4 relative for records, node
 rows and products) scaled by the float32 spacing of the largest sample
@@ -20,14 +32,18 @@ the reweighting c / Phi has curvature ~ 1 / eps and amplifies the float32
 rounding of the sample positions a thousandfold.  Those pixels still enter
 the total energy and the node sums compared above and below."""
 import functools
+import hashlib
+import json
+import os
 
 import numpy as np
 import pytest
 
+import oracle.cnn as C
 import oracle.halfway as O
 from synth import make_frame, vga_config, hd_config
 
-from gpu_util import GpuCase, oracle_params, mask_flip_ok, rel_err
+from gpu_util import check_output, GpuCase, oracle_params, mask_flip_ok, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -54,23 +70,201 @@ def _smooth_field(grid, amp, seed):
             + fv * ((1 - fu) * lat[:, j0 + 1, i0] + fu * lat[:, j0 + 1, i0 + 1]))
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.mark.parametrize("case", ["vga640x480_s4", "hd1280x720_s8", "hd1280x720_s4",
+                                  "hd1280x720_s2"])
+def test_fullsize_solve_parity(case):
+    z, meta = _golden(case)
+    imgs, calib = _frame(meta["generator"])
+    assert hashlib.sha256(imgs.tobytes()).hexdigest() == str(z["images_sha256"]), \
+        "the generator did not reproduce the stored frame"
+    prm = dict(levels=meta["levels"], grid_stride=meta["grid_stride"],
+               gn_iters=meta["gn_iters"], pcg_iters=meta["pcg_iters"], tile_mode=1)
+    g = GpuCase(imgs, calib, exec_mode=0, **prm)
+    try:
+        depth, flow3d, flows = g.solve()
+        log, code = g.log()
+    finally:
+        g.close()
+    assert code == 0
+    _check_against_golden(case, z, meta, log, depth, flow3d, flows, calib)
+
+
+def _golden(case):
+    z = np.load(os.path.join(GOLDEN, f"fullsize_{case}.npz"))
+    return z, json.loads(str(z["meta"]))
+
+
+def learned_energy_tol(e_pred_gpu, e_pred_oracle):
+    """Per-step energy tolerance of a solve started from the network's
+    prediction.  The GPU network differs from the oracle's bf16 emulation
+    where float32 accumulation crosses a bf16 rounding boundary, so the two
+    solves start the coarsest level from slightly different points; the
+    fallback energy of the prediction (E at that start) measures the
+    difference, r0.  r0 itself must stay within 1e-4, and the steps that
+    follow (two per level in the equal-EPE schedule, too few to contract the
+    difference away) are held to 1e-4 + 2 r0."""
+    r0 = abs(e_pred_gpu - e_pred_oracle) / abs(e_pred_oracle)
+    assert r0 <= 1e-4, r0
+    return 1e-4 + 2 * r0
+
+
+def _sensitivity(case):
+    with open(os.path.join(GOLDEN, f"sensitivity_{case}.json")) as f:
+        return json.load(f)
+
+
+def _check_against_golden(case, z, meta, log, depth, flow3d, flows, calib, e_tol=1e-4,
+                          learned=False):
+    """Per-step energies within e_tol relative; final flows within 0.02 px
+    at >= 99.9 % of the pixels, and everywhere within 0.05 px (plain solves)
+    or within 0.02 px plus twice the oracle's own sensitivity to a start
+    moved by the size of the networks' bf16 differences (learned solves,
+    tests/golden/sensitivity_<case>.json).  At these sizes the fixed
+    schedule (10 Gauss-Newton steps of 20 PCG iterations) leaves a few
+    weakly textured nodes far from converged, and there the iterate moves by
+    hundredths of a pixel for perturbations at the level of float32
+    rounding: the float64 oracle itself moves by up to 0.013 px at 640x480
+    when its input images change by one float32 rounding
+    (sensitivity_vga640x480_s4.json), while the median node moves by 3e-7 px.
+    The max-abs difference at those nodes measures that sensitivity, not the
+    arithmetic (the GPU's median difference is ~1e-6 px).  Depth and 3D flow
+    as check_output."""
+    W, H, stride = meta["width"], meta["height"], meta["grid_stride"]
+    assert len(log) == len(z["energy"])
+    rel = []
+    for k, lg in enumerate(log):
+        assert (lg["level"], lg["gn_iter"]) == (z["level"][k], z["gn_iter"][k])
+        rel.append(abs(lg["energy"] - z["energy"][k]) / abs(z["energy"][k]))
+        assert lg["energy_after"] <= lg["energy"]
+    tau_diff = sum(lg["tau"] != t for lg, t in zip(log, z["tau"]))
+    grid = O.Grid(W, H, stride)
+    ref = grid.to_pixels(z["total0"].astype(np.float64)).reshape(6, H, W)
+    diff = np.abs(flows - ref).max(axis=0)
+    err = float(diff.max())
+    frac = float((diff <= 0.02).mean())
+    cap = 0.02 + 2 * _sensitivity(case.split()[-1])["max_px"] if learned else 0.05
+    print(f"{case}: worst per-step energy rel diff {max(rel):.3g}; final flows: max diff "
+          f"{err:.3g} px (cap {cap:.3g}), median {float(np.median(diff)):.2g} px, "
+          f"{100 * frac:.3f} % within 0.02 px; step-length disagreements {tau_diff}",
+          flush=True)
+    assert max(rel) <= e_tol, [f"{r:.2e}" for r in rel]
+    assert frac >= 0.999
+    assert err <= cap, (err, cap)
+    check_output(depth, flow3d, flows, W, H, calib, ref, err)
+
+
+def network_difference(weights, imgs):
+    """Largest difference, in level-4 pixels, between the GPU network's
+    output and the oracle's bf16-emulating network on this frame's level-4
+    images (the oracle's pyramid fed to both): the bf16 rounding flips that
+    separate the two starts of a learned solve."""
+    import torch
+    from paper_1610_07159_amd import sf
+    lev4 = O.pyramid(imgs.astype(np.float64), C.INPUT_LEVEL + 1)[C.INPUT_LEVEL]
+    h, w = lev4.shape[1:]
+    t = sf.sf_trainer_create(1, h, w, torch.cuda.current_stream().cuda_stream)
+    try:
+        sf.sf_trainer_set_params(t, weights)
+        x = torch.from_numpy(lev4[None].astype(np.float32)).cuda()
+        out = torch.empty((1, 6, h, w), device="cuda")
+        sf.sf_trainer_forward(t, x.data_ptr(), 1, out.data_ptr())
+        torch.cuda.synchronize()
+        ref, _ = C.forward(np.asarray(weights, np.float64),
+                           lev4[None].astype(np.float32).astype(np.float64) - 0.5, bf16=True)
+        return float(np.abs(out.cpu().numpy() - ref).max())
+    finally:
+        sf.sf_trainer_destroy(t)
+
+
+@pytest.mark.parametrize("case", ["vga640x480_s4_learned", "vga640x480_s4_learned10"])
+def test_fullsize_learned_solve_parity(case):
+    """The learned initialisation with the shipped 640x480 network on a
+    frame outside its training and evaluation seeds, at the equal-EPE
+    schedule (2 Gauss-Newton steps per level) and at the full one (10),
+    against the oracle's solve from the oracle's bf16-emulating network:
+    the fallback decision and energies, every step's energy and the final
+    flows.  The two networks differ by bf16 rounding flips, d0 level-4 px
+    (measured here through the trainer); the starts at the coarsest nodes
+    differ by at most d0 (a convex combination of outputs, scaled by
+    2^(4 - l_c) = 1), which must stay within the 2e-4 px at which the
+    oracle's sensitivity of this case was measured."""
+    from paper_1610_07159_amd import sf
+    z, meta = _golden(case)
+    imgs, calib, _ = make_frame(vga_config(), meta["seed"])
+    assert hashlib.sha256(imgs.tobytes()).hexdigest() == str(z["images_sha256"])
+    root = os.path.dirname(os.path.dirname(GOLDEN))
+    weights = np.load(os.path.join(root, "paper_1610_07159_amd", "weights", meta["weights"]),
+                      allow_pickle=False)
+    prm = dict(levels=meta["levels"], grid_stride=meta["grid_stride"],
+               gn_iters=meta["gn_iters"], pcg_iters=meta["pcg_iters"], tile_mode=1)
+    g = GpuCase(imgs, calib, exec_mode=0, init_mode=1, **prm)
+    try:
+        sf.sf_set_initializer(g.ctx, weights)
+        depth, flow3d, flows = g.solve()
+        log, code = g.log()
+        used, ep, ez = sf.sf_get_init_result(g.ctx)
+    finally:
+        g.close()
+    assert code == 0
+    d0 = network_difference(weights, imgs)
+    print(f"{case}: fallback energies pred {ep:.7g} (oracle {meta['e_pred']:.7g}), "
+          f"zero {ez:.7g} (oracle {meta['e_zero']:.7g}); network output difference "
+          f"{d0:.3g} level-4 px", flush=True)
+    # the oracle's sensitivity at this case was measured for starts moved
+    # by 2e-4 px
+    assert d0 <= 2e-4
+    assert bool(used) == meta["prediction_kept"]
+    assert ez == pytest.approx(meta["e_zero"], rel=1e-5)
+    _check_against_golden(case, z, meta, log, depth, flow3d, flows, calib,
+                          learned_energy_tol(ep, meta["e_pred"]), learned=True)
+
+
+def test_fullsize_batch_parity():
+    """The 640x480 and 1280x720 (stride 4) frames above solved together in
+    one batch (5 and 6 levels by the batch's level rule), each against its
+    oracle solve: the batch's level-0 reductions run over the partial sums
+    of both frames' thousands of workgroups."""
+    import torch
+    from paper_1610_07159_amd import sf, SceneFlowSolver
+    cases = ["hd1280x720_s4", "vga640x480_s4"]
+    gold = [_golden(c) for c in cases]
+    frames = []
+    for z, meta in gold:
+        imgs, calib = _frame(meta["generator"])
+        assert hashlib.sha256(imgs.tobytes()).hexdigest() == str(z["images_sha256"])
+        frames.append((imgs, calib))
+    prm = dict(levels=6, grid_stride=4, gn_iters=10, pcg_iters=20, tile_mode=1)
+    solver = SceneFlowSolver(1280, 720, exec_mode=0, **prm)
+    try:
+        dev = [(torch.from_numpy(i).cuda().contiguous(), c) for i, c in frames]
+        outs = solver.solve_batch(dev, params=sf.sf_params_default(exec_mode=0, **prm))
+        torch.cuda.synchronize()
+        res = [tuple(t.cpu().numpy() for t in o) for o in outs]
+        logs = [solver.batch_log(f) for f in range(len(frames))]
+    finally:
+        solver.close()
+    for c, (z, meta), (imgs, calib), (depth, flow3d, flows), log in zip(
+            cases, gold, frames, res, logs):
+        assert sf.sf_batch_levels(meta["width"], meta["height"], 6) == meta["levels"]
+        _check_against_golden("batch " + c, z, meta, log, depth, flow3d, flows, calib)
+
+
 @pytest.mark.parametrize("name,W,H,stride,levels", [("vga", 640, 480, 4, 5),
                                                     ("hd", 1280, 720, 2, 6),
                                                     ("hd", 1280, 720, 4, 6),
                                                     ("hd", 1280, 720, 8, 6)])
-def test_fullsize_parity(name, W, H, stride, levels):
+def test_fullsize_stage_parity(name, W, H, stride, levels):
     imgs, calib = _frame(name)
     prm = dict(levels=levels, grid_stride=stride, gn_iters=10, pcg_iters=20, tile_mode=1)
     p = oracle_params(**prm)
     g = GpuCase(imgs, calib, exec_mode=0, **prm)
     try:
         # the full solve as benchmarked (also tunes the tiles)
-        depth, flow3d, flows = g.solve()
-        log, code = g.log()
-        assert code == 0 and len(log) == levels * 10
-        assert all(r["energy_after"] <= r["energy"] for r in log)
-        assert np.isfinite(flows).all() and np.isfinite(flow3d[:, np.isfinite(depth)]).all()
-        assert np.isfinite(depth).mean() > 0.95
+        g.solve()
+        assert g.log()[1] == 0
 
         # a level-0 state chosen here
         sf = g.sf

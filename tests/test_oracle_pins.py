@@ -396,6 +396,23 @@ def test_tiny_energy_monotone(tiny_solve):
     assert acc >= 0.8
 
 
+def test_split_schedule_counts_and_prefix():
+    """gn_fine (the split schedule of Sec. 6.2): the two finest levels take
+    gn_fine steps and the others gn_iters, and the coarse levels' steps are
+    exactly those of the uniform schedule (the split changes nothing
+    before level 1)."""
+    imgs, calib, _ = make_frame(tiny_plane_config(), 0)
+    p = O.Params(levels=3, grid_stride=8, gn_iters=3, gn_fine=1, pcg_iters=6)
+    rec, rec_u = [], []
+    O.solve(imgs, calib, p, record=rec)
+    O.solve(imgs, calib, O.Params(levels=3, grid_stride=8, gn_iters=3, pcg_iters=6),
+            record=rec_u)
+    assert [r["level"] for r in rec] == [2, 2, 2, 1, 0]
+    assert [p.gn_at(l) for l in range(3)] == [1, 1, 3]
+    for a, b in zip(rec[:4], rec_u[:4]):
+        assert a["energy"] == b["energy"] and a["tau"] == b["tau"]
+
+
 def _plane_closed_form(grid, f=60.0, B=0.1, Z0=2.0, T=(0.01, 0.0, 0.02),
                        cx=31.5, cy=23.5):
     """Halfway flows of the translating fronto-parallel plane, derived from
