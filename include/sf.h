@@ -325,6 +325,37 @@ void sf_destroy(sf_ctx *ctx);
  * context's stream.  Errors: SF_ERR_INVALID_ARG, SF_ERR_HIP. */
 sf_status sf_reset_sequence(sf_ctx *ctx);
 
+/* ---- solving without allocation ------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * sf_solve_noalloc is sf_create + sf_solve in one call without a context:
+ * the same inputs, parameters and outputs as sf_solve (p is required), run
+ * with direct launches (exec_mode is ignored) and the default tile shapes
+ * (tile_mode 1, autotuning, is treated as 0), giving bitwise the outputs of
+ * a context created with those parameters.  It allocates nothing: the
+ * whole workspace lives in the library's static device array of
+ * SF_NOALLOC_SCRATCH_BYTES, which every GPU the library runs on holds until
+ * the process ends; per-call constants travel as kernel arguments and the
+ * array is cleared by a kernel, so every step is a kernel launch on
+ * hip_stream (a hipStream_t, NULL for the null stream).  The first call on
+ * a device looks up the array's address there.
+ *
+ * Limits: the frame's workspace must fit the array (at stride 4 with 4
+ * levels, frames up to 320 x 240 pixels), else SF_ERR_SIZE with the needed
+ * size in sf_last_error; init_mode and temporal must be 0, else
+ * SF_ERR_INVALID_ARG.  Every call on a device uses that device's one
+ * array, and each call starts by clearing it: calls whose GPU work overlaps
+ * on one device (different streams, or host threads enqueueing at once)
+ * race on it and give undefined results.  Other errors as sf_create and
+ * sf_solve.  There is no log (sf_get_log needs a context). */
+#define SF_NOALLOC_SCRATCH_BYTES (32u << 20)
+sf_status sf_solve_noalloc(int width, int height, const float *I_left_t,
+                           const float *I_right_t, const float *I_left_t1,
+                           const float *I_right_t1, const sf_calib *calib,
+                           const sf_params *p, float *depth, float *flow3d,
+                           float *flows, void *hip_stream);
+
 /* ---- test support: per-stage access to intermediates --------------------
  * These entry points exist so that tests can compare each stage with an
  * independent implementation.  They synchronise the stream.  host_dst /

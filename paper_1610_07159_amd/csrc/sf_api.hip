@@ -100,6 +100,15 @@ struct Plan {
     std::vector<int> shape;  // W, H per frame (batch cache key)
     CnnRun cnn;              // learned initialiser
     const CnnNet *net = nullptr;
+    bool external = false;   // pool is caller-provided workspace (not freed)
+    size_t pool_bytes = 0;
+};
+
+// Caller-provided device workspace for a plan: the plan is carved from it
+// instead of an allocation, with no staging buffer and no host copies.
+struct ExtPool {
+    char *base = nullptr;
+    size_t cap = 0;
 };
 
 }  // namespace
@@ -246,7 +255,7 @@ void free_plan(Plan &P) {
     // best-effort release: errors here cannot be reported to anyone
     if (P.gexec) (void)hipGraphExecDestroy(P.gexec);
     if (P.graph) (void)hipGraphDestroy(P.graph);
-    if (P.pool) (void)hipFree(P.pool);
+    if (P.pool && !P.external) (void)hipFree(P.pool);
     if (P.cnn.pool) (void)hipFree(P.cnn.pool);
     if (P.stage) (void)hipHostFree(P.stage);
     if (P.stage_ev) (void)hipEventDestroy(P.stage_ev);
@@ -256,7 +265,8 @@ void free_plan(Plan &P) {
 // Allocates and initialises the workspace of frames of the given sizes and
 // level counts.
 sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shape,
-                     const std::vector<int> &levels, bool batched, const CnnNet *net) {
+                     const std::vector<int> &levels, bool batched, const CnnNet *net,
+                     const ExtPool *ext = nullptr) {
     P.prm = prm;
     P.net = net;
     P.batched = batched;
@@ -345,21 +355,33 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
         for (int f = 0; f < P.nf; ++f) ntab += P.fr[f].L > l ? 1 : 0;
     }
     off += align_up(sizeof(LevelArgs) * (size_t)ntab);
-    hipError_t e = hipMalloc(&P.pool, off);
-    if (e != hipSuccess) {
-        note_hip_error("hipMalloc(workspace)", e);
-        P.pool = nullptr;
-        return SF_ERR_OOM;
+    P.pool_bytes = off;
+    hipError_t e = hipSuccess;
+    if (ext) {
+        if (off > ext->cap) {
+            snprintf(g_err, sizeof(g_err),
+                     "workspace of %zu bytes exceeds the %zu bytes available", off, ext->cap);
+            return SF_ERR_SIZE;
+        }
+        P.pool = ext->base;
+        P.external = true;
+    } else {
+        e = hipMalloc(&P.pool, off);
+        if (e != hipSuccess) {
+            note_hip_error("hipMalloc(workspace)", e);
+            P.pool = nullptr;
+            return SF_ERR_OOM;
+        }
+        e = hipHostMalloc(&P.stage, stage_len, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            note_hip_error("hipHostMalloc(staging)", e);
+            P.stage = nullptr;
+            return SF_ERR_OOM;
+        }
+        memset(P.stage, 0, stage_len);
+        P.stage_bytes = stage_len;
+        HIP_TRY(hipEventCreateWithFlags(&P.stage_ev, hipEventDisableTiming));
     }
-    e = hipHostMalloc(&P.stage, stage_len, hipHostMallocDefault);
-    if (e != hipSuccess) {
-        note_hip_error("hipHostMalloc(staging)", e);
-        P.stage = nullptr;
-        return SF_ERR_OOM;
-    }
-    memset(P.stage, 0, stage_len);
-    P.stage_bytes = stage_len;
-    HIP_TRY(hipEventCreateWithFlags(&P.stage_ev, hipEventDisableTiming));
     P.dcst = (DevConst *)(P.pool + cst_off);
     P.dio = (FrameIO *)(P.pool + io_off);
     P.dtab = (LevelArgs *)(P.pool + tab_off);
@@ -386,11 +408,11 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
         F.cst = P.dcst + f;
         F.io = P.dio + f;
     }
-    // zeroed workspace
-    HIP_TRY(hipMemset(P.pool, 0, off));
+    // zeroed workspace (a caller-provided one is cleared by its caller)
+    if (!ext) HIP_TRY(hipMemset(P.pool, 0, off));
     // learned initialiser: frames with a level 4, grouped by its size
     std::vector<const float *> cnn_out(P.nf, nullptr);
-    if (prm.init_mode == 1) {
+    if (prm.init_mode == 1 && !ext) {
         CnnRun &R = P.cnn;
         for (int f = 0; f < P.nf; ++f) {
             const FrameBuf &F = P.fr[f];
@@ -503,6 +525,7 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
             flat.push_back(a);
         }
     }
+    if (ext) return SF_OK;  // single frames take their arguments by value
     if (!flat.empty())
         HIP_TRY(hipMemcpy(P.dtab, flat.data(), sizeof(LevelArgs) * flat.size(),
                           hipMemcpyHostToDevice));
@@ -1137,6 +1160,94 @@ sf_status sf_get_batch_init_result(sf_ctx *c, int frame, int *used, double *e_pr
     if (!P || !P->have_inputs || P->prm.init_mode != 1) return SF_ERR_STATE;
     if (frame < 0 || frame >= P->nf) return SF_ERR_INVALID_ARG;
     return init_result(c, *P, frame, used, e_pred, e_zero);
+}
+
+// ---- solves without allocation ------------------------------------------
+//
+// The workspace of sf_solve_noalloc lives in this library's static device
+// array, SF_NOALLOC_SCRATCH_BYTES per device for the life of the process.
+// In host code `scratch` only names the symbol: its device address is
+// looked up once per device (hipGetSymbolAddress, with that device current)
+// and only that address is handed to kernels.
+
+}  // extern "C"
+
+static __device__ __align__(256) char scratch[SF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SF_NOALLOC_DEVICES = 64;
+struct NoAllocState {
+    std::mutex mu;
+    char *ptr = nullptr;  // device address of this device's `scratch`
+    Plan plan;            // host-side layout of the last call's frame
+    bool have_plan = false;
+    int W = 0, H = 0;
+};
+NoAllocState g_noalloc[SF_NOALLOC_DEVICES];
+}  // namespace
+
+extern "C" {
+
+sf_status sf_solve_noalloc(int width, int height, const float *I_left_t, const float *I_right_t,
+                           const float *I_left_t1, const float *I_right_t1,
+                           const sf_calib *calib, const sf_params *p, float *depth,
+                           float *flow3d, float *flows, void *hip_stream) {
+    if (!depth || !flow3d) return SF_ERR_INVALID_ARG;
+    const float *img[4] = {I_left_t, I_right_t, I_left_t1, I_right_t1};
+    for (int k = 0; k < 4; ++k)
+        if (!img[k]) return SF_ERR_INVALID_ARG;
+    sf_status s = check_params(p);
+    if (s != SF_OK) return s;
+    // no network weights and no state between calls
+    if (p->init_mode != 0 || p->temporal != 0) return SF_ERR_INVALID_ARG;
+    s = check_calib(calib);
+    if (s != SF_OK) return s;
+    if (width < 8 || height < 8) return SF_ERR_SIZE;
+    if ((width >> (p->levels - 1)) < 8 || (height >> (p->levels - 1)) < 8) return SF_ERR_SIZE;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SF_NOALLOC_DEVICES) return SF_ERR_INVALID_ARG;
+    NoAllocState &S = g_noalloc[dev];
+    std::lock_guard<std::mutex> lock(S.mu);
+    if (!S.ptr) {
+        void *q = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)));
+        if (!q) return SF_ERR_HIP;
+        S.ptr = (char *)q;
+    }
+    // direct launches with the default (or a forced) tile shape: autotuning
+    // and graph capture would allocate
+    sf_params prm = *p;
+    prm.exec_mode = 1;
+    if (prm.tile_mode == 1) prm.tile_mode = 0;
+    if (!S.have_plan || S.W != width || S.H != height || !same_schedule(S.plan.prm, prm)) {
+        S.have_plan = false;
+        free_plan(S.plan);
+        ExtPool ext;
+        ext.base = S.ptr;
+        ext.cap = SF_NOALLOC_SCRATCH_BYTES;
+        s = build_plan(S.plan, prm, {width, height}, {prm.levels}, false, nullptr, &ext);
+        if (s != SF_OK) {
+            free_plan(S.plan);
+            return s;
+        }
+        S.have_plan = true;
+        S.W = width;
+        S.H = height;
+    }
+    Plan &P = S.plan;
+    P.prm = prm;
+    hipStream_t st = (hipStream_t)hip_stream;
+    // the previous call's contents: cleared, then this call's constants
+    launch_fill_zero(st, S.ptr, P.pool_bytes);
+    DevConst k;
+    fill_const(P.fr[0].L, prm, *calib, k);
+    launch_store_const(st, k, P.fr[0].cst);
+    enqueue_pyramid(P, st, img);
+    enqueue_body(P, st);
+    launch_output(st, slot(P, 0), depth, flow3d, flows);
+    HIP_TRY(hipGetLastError());
+    return SF_OK;
 }
 
 const char *sf_last_error(void) { return g_err; }

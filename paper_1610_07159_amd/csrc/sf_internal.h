@@ -243,6 +243,10 @@ void launch_illum_zero(hipStream_t st, const Launch &L);
 void launch_illum_next(hipStream_t st, const Launch &L);
 // occlusion map of the next finer level from this level's final flow
 void launch_occ_next(hipStream_t st, const Launch &L);
+// Clears bytes (a multiple of 16, 16-byte aligned) at p; stores the
+// per-call constants through a kernel argument.
+void launch_fill_zero(hipStream_t st, void *p, size_t bytes);
+void launch_store_const(hipStream_t st, const DevConst &k, DevConst *dst);
 void launch_output(hipStream_t st, const Launch &L, float *depth,
                    float *flow3d, float *flows);
 TileCfg pick_tile(int s);

@@ -3018,6 +3018,32 @@ void launch_finish_level(hipStream_t st, const Launch &L) {
     go(st, L, nd_blocks, k_finish_level<true>, k_finish_level<false>, SF_BLOCK, 0);
 }
 
+// Workspace clearing and per-call constants of solves that bring their own
+// workspace (no memset or host-to-device copy: both are plain kernels, so
+// the launches can also be captured).
+__global__ __launch_bounds__(SF_BLOCK) void k_fill_zero(uint4 *p, long n16) {
+    const uint4 z = {0u, 0u, 0u, 0u};
+    for (long i = (long)blockIdx.x * SF_BLOCK + threadIdx.x; i < n16;
+         i += (long)gridDim.x * SF_BLOCK)
+        p[i] = z;
+}
+
+__global__ __launch_bounds__(64) void k_store_const(DevConst k, DevConst *dst) {
+    if (threadIdx.x == 0) *dst = k;
+}
+
+void launch_fill_zero(hipStream_t st, void *p, size_t bytes) {
+    const long n16 = (long)(bytes / 16);
+    if (n16 <= 0) return;
+    const long want = (n16 + SF_BLOCK - 1) / SF_BLOCK;
+    const int nb = (int)(want < 4096 ? want : 4096);
+    hipLaunchKernelGGL(k_fill_zero, dim3(nb), dim3(SF_BLOCK), 0, st, (uint4 *)p, n16);
+}
+
+void launch_store_const(hipStream_t st, const DevConst &k, DevConst *dst) {
+    hipLaunchKernelGGL(k_store_const, dim3(1), dim3(64), 0, st, k, dst);
+}
+
 void launch_output(hipStream_t st, const Launch &L, float *depth, float *flow3d,
                    float *flows) {
     go(st, L, px_blocks, k_output<true>, k_output<false>, SF_BLOCK, 0, depth, flow3d, flows);

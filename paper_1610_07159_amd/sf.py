@@ -122,6 +122,9 @@ def _load():
                                    ctypes.POINTER(sf_params)]
     lib.sf_get_batch_log.argtypes = [P, I, ctypes.POINTER(sf_iter_log), I,
                                      ctypes.POINTER(I)]
+    lib.sf_solve_noalloc.argtypes = [I, I, P, P, P, P, ctypes.POINTER(sf_calib),
+                                     ctypes.POINTER(sf_params), P, P, P, P]
+    lib.sf_solve_noalloc.restype = I
     F = ctypes.c_float
     D = ctypes.c_double
     S = ctypes.c_size_t
@@ -218,6 +221,16 @@ def sf_get_log(ctx, cap: int = 4096):
     if code not in (SF_OK, -5):
         _check(code, "sf_get_log")
     return _log_records(buf, n), code
+
+
+def sf_solve_noalloc(width, height, imgs, calib: sf_calib, params: sf_params, depth, flow3d,
+                     flows=0, stream=0):
+    """imgs: four device addresses; depth, flow3d, flows: device addresses
+    (flows may be 0); stream: a hipStream_t as an integer."""
+    _check(lib.sf_solve_noalloc(int(width), int(height), *[int(a) for a in imgs],
+                                ctypes.byref(calib), ctypes.byref(params), int(depth),
+                                int(flow3d), int(flows) or None, int(stream) or None),
+           "sf_solve_noalloc")
 
 
 def sf_batch_levels(width: int, height: int, max_levels: int) -> int:
