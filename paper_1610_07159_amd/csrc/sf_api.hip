@@ -314,7 +314,8 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
             const int gb = (d.G + SF_BLOCK - 1) / SF_BLOCK;
             mb = mb > gb ? mb : gb;
         }
-        F.max_blocks = mb;
+        // a multiple of 4: every partial-sum plane starts on 16 bytes
+        F.max_blocks = (mb + 3) & ~3;
         F.nlog = 0;
         for (int l = 0; l < F.L; ++l) F.nlog += gn_at(prm, l);
         long g_all = 0;
@@ -327,7 +328,7 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
                                sizeof(float) * 16 * (size_t)F.G0,
                                sizeof(float) * NV_COUNT * 8 * (size_t)F.G0,
                                sizeof(float) * SF_GRAM_STRIDE * (size_t)F.N0,
-                               sizeof(float) * PS_COUNT * (size_t)mb,
+                               sizeof(float) * PS_COUNT * (size_t)F.max_blocks,
                                sizeof(DevScalars),
                                sizeof(DevLog) * (size_t)F.nlog,
                                sizeof(float) * SF_GRAD_STRIDE * (size_t)F.N0,

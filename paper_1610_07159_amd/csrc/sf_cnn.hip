@@ -6,10 +6,13 @@
 //
 // Tensors are NHWC bfloat16 with the channel count padded to a multiple of
 // 16 (input 4 -> 16, output 6 -> 16); accumulation is float32 on the matrix
-// cores (v_mfma_f32_16x16x16_bf16).  Every convolution is an implicit GEMM:
-// a wavefront owns 16 consecutive pixels of one image row (the M rows of
-// the tile) and all output channels (N), and runs K over the 9 taps times
-// the input channels.  The weight gradient is a GEMM over pixels split into
+// cores with gfx950's 16 x 16 x 32 bf16 product (v_mfma_f32_16x16x32_bf16,
+// eight K values per lane).  Every convolution is an implicit GEMM: a
+// wavefront owns 16 consecutive pixels of one image row (the M rows of the
+// tile) and all output channels (N), and runs K over the 9 taps times the
+// input channels (32 channels: one tap per product; 16 channels: two taps
+// per product), with the layer's weights staged in LDS once per workgroup.
+// The weight gradient is a GEMM over pixels (32 per product) split into
 // fixed chunks whose partial sums are reduced in a fixed order.
 #include <math.h>
 
@@ -17,7 +20,8 @@
 
 namespace {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ unsigned short f2bf(float f) {
@@ -29,16 +33,17 @@ __device__ __forceinline__ float bf2f(unsigned short h) {
     return __builtin_bit_cast(float, (unsigned)h << 16);
 }
 
-// MFMA 16x16x16 operand layouts (lane l, r = l % 16, q = l / 16):
-//   A (16 x 16, rows x k): row r, k = 4q .. 4q + 3
-//   B (16 x 16, k x cols): col r, k = 4q .. 4q + 3
+// MFMA 16x16x32 operand layouts (lane l, r = l % 16, q = l / 16):
+//   A (16 x 32, rows x k): row r, k = 8q .. 8q + 7
+//   B (32 x 16, k x cols): col r, k = 8q .. 8q + 7
 //   D (16 x 16):           col r, rows 4q .. 4q + 3
-__device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+__device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                   __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
 }
 
-__device__ __forceinline__ v4s load4(const unsigned short *p) {
-    return *reinterpret_cast<const v4s *>(p);
+__device__ __forceinline__ v8s load8(const unsigned short *p) {
+    return *reinterpret_cast<const v8s *>(p);
 }
 
 enum { CONV_RELU = 0, CONV_LINEAR = 1, CONV_DGRAD = 2 };
@@ -58,30 +63,40 @@ __global__ __launch_bounds__(256) void k_conv(const unsigned short *__restrict__
                                               unsigned short *__restrict__ out_bf,
                                               float *__restrict__ out_f, int n_out, int B,
                                               int H, int W) {
+    static_assert(CIN == 16 || CIN == 32, "input channels");
     constexpr int NB = COUT / 16;
+    constexpr int NW = COUT * 9 * CIN;  // weights of the layer
+    __shared__ __attribute__((aligned(16))) unsigned short wl[NW];
+    for (int e = threadIdx.x * 8; e < NW; e += 256 * 8)
+        *reinterpret_cast<v8s *>(wl + e) = load8(wt + e);
+    __syncthreads();
     const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
     const int xs = (W + 15) / 16;
     const int seg = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (seg >= B * H * xs) return;  // uniform per wavefront
+    if (seg >= B * H * xs) return;  // uniform per wavefront, after the barrier
     const int b = seg / (H * xs), rem = seg % (H * xs);
     const int y = rem / xs, x0 = (rem % xs) * 16;
     const int px = x0 + r;
     v4f acc[NB];
 #pragma unroll
     for (int n = 0; n < NB; ++n) acc[n] = v4f{0.f, 0.f, 0.f, 0.f};
+    // K step: 32 channels of one tap, or 16 channels of two taps (lanes
+    // q = 0, 1 the even tap, q = 2, 3 the odd one; the tenth tap is zero)
+    constexpr int STEPS = CIN == 32 ? 9 : 5;
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
+    for (int s = 0; s < STEPS; ++s) {
+        const int tap = CIN == 32 ? s : 2 * s + (q >> 1);
+        const int ch = CIN == 32 ? 8 * q : 8 * (q & 1);
         const int yy = y + tap / 3 - 1, xx = px + tap % 3 - 1;
-        const bool ok = px < W && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const bool ok = tap < 9 && px < W && yy >= 0 && yy < H && xx >= 0 && xx < W;
         const unsigned short *src = in + ((long)(b * H + (ok ? yy : 0)) * W + (ok ? xx : 0)) * CIN;
+        const v8s a = ok ? load8(src + ch) : v8s{0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-        for (int c0 = 0; c0 < CIN; c0 += 16) {
-            const v4s a = ok ? load4(src + c0 + 4 * q) : v4s{0, 0, 0, 0};
-#pragma unroll
-            for (int n = 0; n < NB; ++n) {
-                const v4s w = load4(wt + ((long)(n * 16 + r) * 9 + tap) * CIN + c0 + 4 * q);
-                acc[n] = mfma16(a, w, acc[n]);
-            }
+        for (int n = 0; n < NB; ++n) {
+            const v8s w = tap < 9 ? *reinterpret_cast<const v8s *>(
+                                        wl + ((n * 16 + r) * 9 + tap) * CIN + ch)
+                                  : v8s{0, 0, 0, 0, 0, 0, 0, 0};
+            acc[n] = mfma32(a, w, acc[n]);
         }
     }
 #pragma unroll
@@ -126,11 +141,11 @@ __global__ __launch_bounds__(256) void k_wgrad(const unsigned short *__restrict_
     const int co = mb * 16 + r, ci = nb * 16 + r;
     v4f acc = {0.f, 0.f, 0.f, 0.f};
     const long p_end = min(P, (long)(c + 1) * chunk);
-    for (long p0 = (long)c * chunk; p0 < p_end; p0 += 16) {
-        v4s a, bv;
+    for (long p0 = (long)c * chunk; p0 < p_end; p0 += 32) {
+        v8s a, bv;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const long p = p0 + 4 * q + i;
+        for (int i = 0; i < 8; ++i) {
+            const long p = p0 + 8 * q + i;
             short av = 0, xv = 0;
             if (p < p_end) {
                 av = (short)dpre[p * COUT + co];
@@ -143,7 +158,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const unsigned short *__restrict_
             a[i] = av;
             bv[i] = xv;
         }
-        acc = mfma16(a, bv, acc);
+        acc = mfma32(a, bv, acc);
     }
     // D rows = output channels mb*16 + 4q + i, column = input channel ci
 #pragma unroll

@@ -1356,12 +1356,45 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, Til
 // Per-lane strided sums of the previous iteration's three partial planes;
 // every wavefront of every workgroup loads and sums all of them in the same
 // order.
+// Up to 512 workgroups, eight scalar loads per plane and lane take one
+// memory round trip.  Beyond (the level-0 iteration at 640x480 has 600),
+// each lane reads four consecutive partials at a time (the planes start on
+// 16-byte boundaries: max_blocks is a multiple of 4): three 16-byte loads
+// per plane and lane cover 768 workgroups in one round trip instead of two.
 __device__ __forceinline__ void load_pcg_partials(const LevelArgs &a, int i, int nb_prev,
                                                   double (&acc)[3]) {
     const float *prev = a.partials + (long)(((i - 1) & 1) ? PS_PCG1 : PS_PCG0) * a.max_blocks;
+    constexpr int U = 3;
+    const int lane = threadIdx.x & 63;
     acc[0] = acc[1] = acc[2] = 0.0;
-    strided_sums<3, 8>(threadIdx.x & 63, 64, nb_prev,
-                       [&](int k, int b) { return prev[(long)k * a.max_blocks + b]; }, acc);
+    if (nb_prev <= 64 * 8) {
+        strided_sums<3, 8>(lane, 64, nb_prev,
+                           [&](int k, int b) { return prev[(long)k * a.max_blocks + b]; }, acc);
+        return;
+    }
+    const int nq = (nb_prev + 3) >> 2;  // float4 groups holding the nb_prev partials
+    for (int j0 = lane; j0 < nq; j0 += 64 * U) {
+        float4 v[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + 64 * u;
+            const int jj = j < nq ? j : 0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                v[u][k] = reinterpret_cast<const float4 *>(prev + (long)k * a.max_blocks)[jj];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = 4 * (j0 + 64 * u);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                acc[k] += b < nb_prev ? (double)v[u][k].x : 0.0;
+                acc[k] += b + 1 < nb_prev ? (double)v[u][k].y : 0.0;
+                acc[k] += b + 2 < nb_prev ? (double)v[u][k].z : 0.0;
+                acc[k] += b + 3 < nb_prev ? (double)v[u][k].w : 0.0;
+            }
+        }
+    }
 }
 
 // The scalars of iteration i-1 from the lane sums: every wavefront reduces

@@ -129,7 +129,7 @@ def stream_training_data(ex, W, H, seeds, sched, log=print, max_disp=None, blobs
             k = 1 << LEVEL_IN
             fl = out[2][:, :(H // k) * k, :(W // k) * k]
             ys.append((torch.nn.functional.avg_pool2d(fl[None], k)[0] / k).cpu().numpy())
-            if (k + 1) % 100 == 0:
+            if (k + 1) % 10 == 0:
                 log(f"  rendered and solved {k + 1}/{len(jobs)}")
     finally:
         solver.close()
@@ -325,6 +325,14 @@ def main():
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--out", default="init_weights.npy")
     ap.add_argument("--report", default="init_report.json")
+    ap.add_argument("--seed0", type=int, default=0, help="first training seed")
+    ap.add_argument("--save-data", default=None,
+                    help="write this run's training inputs and targets (float16) to this file")
+    ap.add_argument("--load-data", nargs="*", default=[],
+                    help="training inputs and targets written by earlier --save-data runs, "
+                         "used together with this run's frames")
+    ap.add_argument("--no-train", action="store_true",
+                    help="only render, solve and save the training data")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only time this many trainer steps on random level-4 inputs of "
                          "the frame size (batch --batch) and exit")
@@ -336,21 +344,43 @@ def main():
     W, H = args.width, args.height
     sched_full = dict(SCHEDULE, levels=args.levels)
     scene = dict(max_disp=args.max_disp, blobs=args.blobs)
+    import torch  # (the first import on a fresh machine takes a while)
+    log("torch imported")
     # host workers first: nothing has touched the GPU yet
     ex = start_pool(args.workers)
     t0 = time.time()
     eval_seeds = range(1_000_000, 1_000_000 + args.eval)
-    eval_frames = list(ex.map(_render, [(W, H, s, True, args.max_disp, args.blobs)
-                                        for s in eval_seeds], chunksize=1))
+    eval_frames = []
+    for k, f in enumerate(ex.map(_render, [(W, H, s, True, args.max_disp, args.blobs)
+                                           for s in eval_seeds], chunksize=1)):
+        eval_frames.append(f)
+        if (k + 1) % 10 == 0:
+            log(f"  rendered {k + 1}/{args.eval} evaluation frames")
     log(f"rendered {len(eval_frames)} evaluation frames with truth in {time.time() - t0:.0f} s")
 
-    import torch
     torch.cuda.set_device(0)
     t1 = time.time()
-    x, y = stream_training_data(ex, W, H, range(args.frames), sched_full, log, **scene)
+    x, y = stream_training_data(ex, W, H, range(args.seed0, args.seed0 + args.frames),
+                                sched_full, log, **scene)
     ex.shutdown()
     log(f"{len(x)} training frames rendered and solved in {time.time() - t1:.0f} s; "
         f"inputs {x.shape}, targets {y.shape}")
+    if args.save_data:
+        with open(args.save_data, "wb") as f:
+            np.savez(f, x=x.astype(np.float16), y=y.astype(np.float16),
+                     seeds=np.arange(args.seed0, args.seed0 + args.frames))
+        log(f"saved {args.save_data}")
+    n_loaded = 0
+    for path in args.load_data:
+        with open(path, "rb") as f:
+            z = np.load(f, allow_pickle=False)
+            x = np.concatenate([x, z["x"].astype(np.float32)])
+            y = np.concatenate([y, z["y"].astype(np.float32)])
+            n_loaded += len(z["x"])
+    if n_loaded:
+        log(f"training on {len(x)} frames ({n_loaded} from earlier runs)")
+    if args.no_train:
+        return
     t2 = time.time()
     params, curve = train_gpu(x, y, args.epochs, args.batch, args.lr, seed=1, log=log)
     log(f"trained in {time.time() - t2:.1f} s")
@@ -375,7 +405,7 @@ def main():
     speedup = (round(reach["plain"]["ms_per_frame"] / reach["learned"]["ms_per_frame"], 3)
                if reach["plain"] and reach["learned"] else None)
     report = dict(
-        frames=args.frames, eval_frames=args.eval, eval_seeds=[eval_seeds[0], eval_seeds[-1]],
+        frames=len(x), eval_frames=args.eval, eval_seeds=[eval_seeds[0], eval_seeds[-1]],
         size=f"{W}x{H}", schedule=sched_full, max_disp=args.max_disp, blobs=args.blobs,
         epochs=args.epochs, batch=args.batch, lr=args.lr,
         loss_curve=[round(c, 5) for c in curve], target_epe_px=round(target, 4),

@@ -119,10 +119,12 @@ def _sensitivity(case):
 def _check_against_golden(case, z, meta, log, depth, flow3d, flows, calib, e_tol=1e-4,
                           learned=False):
     """Per-step energies within e_tol relative; final flows within 0.02 px
-    at >= 99.9 % of the pixels, and everywhere within 0.05 px (plain solves)
-    or within 0.02 px plus twice the oracle's own sensitivity to a start
-    moved by the size of the networks' bf16 differences (learned solves,
-    tests/golden/sensitivity_<case>.json).  At these sizes the fixed
+    at >= 99.9 % of the pixels and everywhere within 0.05 px (plain
+    solves); learned solves, whose starts differ by the networks' bf16
+    rounding flips, are held to 0.02 px plus twice the oracle's own spread
+    for a start moved by that much (tests/golden/sensitivity_<case>.json):
+    its 99.9th percentile at >= 99.9 % of the pixels, its maximum
+    everywhere.  At these sizes the fixed
     schedule (10 Gauss-Newton steps of 20 PCG iterations) leaves a few
     weakly textured nodes far from converged, and there the iterate moves by
     hundredths of a pixel for perturbations at the level of float32
@@ -144,11 +146,17 @@ def _check_against_golden(case, z, meta, log, depth, flow3d, flows, calib, e_tol
     ref = grid.to_pixels(z["total0"].astype(np.float64)).reshape(6, H, W)
     diff = np.abs(flows - ref).max(axis=0)
     err = float(diff.max())
-    frac = float((diff <= 0.02).mean())
-    cap = 0.02 + 2 * _sensitivity(case.split()[-1])["max_px"] if learned else 0.05
+    if learned:
+        # the oracle's own spread for a start moved by the networks' bf16
+        # differences: its 99.9th percentile and its maximum
+        sens = _sensitivity(case.split()[-1])
+        bulk, cap = 0.02 + 2 * sens["p999_px"], 0.02 + 2 * sens["max_px"]
+    else:
+        bulk, cap = 0.02, 0.05
+    frac = float((diff <= bulk).mean())
     print(f"{case}: worst per-step energy rel diff {max(rel):.3g}; final flows: max diff "
           f"{err:.3g} px (cap {cap:.3g}), median {float(np.median(diff)):.2g} px, "
-          f"{100 * frac:.3f} % within 0.02 px; step-length disagreements {tau_diff}",
+          f"{100 * frac:.3f} % within {bulk:.3g} px; step-length disagreements {tau_diff}",
           flush=True)
     assert max(rel) <= e_tol, [f"{r:.2e}" for r in rel]
     assert frac >= 0.999
