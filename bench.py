@@ -623,10 +623,11 @@ def main():
                     help="skip the learned-init vs plain comparison")
     ap.add_argument("--exec-mode", type=int, default=0,
                     help="0 = captured HIP graph, 1 = direct launches")
-    ap.add_argument("--apply-mode", type=int, default=2, choices=(0, 1, 2),
+    ap.add_argument("--apply-mode", type=int, default=2, choices=(0, 1, 2, 3),
                     help="0: matrix-free products from the pixel records, "
                          "1: per-node blocks, 2: per-node blocks and one-workgroup "
-                         "PCG at levels of at most 336 nodes")
+                         "PCG at levels of at most 336 nodes, 3: 2 plus the co-resident "
+                         "PCG at mid-size levels (single frames)")
     ap.add_argument("--tile-mode", type=int, default=1,
                     help="PCG tile shapes: 0 = default, 1 = autotuned (timed on the "
                          "warm-up solve), 2 / 3 / 4 = the alternative shapes")

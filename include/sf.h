@@ -87,7 +87,15 @@ typedef struct {
  *                  Gauss-Newton step (the paper's precomputed per-node
  *                  blocks; 120 floats of extra workspace per node); 2 = as
  *                  1, and levels with at most 336 nodes run all PCG
- *                  iterations of a Gauss-Newton step in one workgroup
+ *                  iterations of a Gauss-Newton step in one workgroup;
+ *                  3 = as 2, and in single-frame solves levels of 337 to
+ *                  10752 nodes with rows of at most 128 nodes run all PCG
+ *                  iterations in ceil(G / 336) co-resident workgroups with
+ *                  a grid barrier per iteration (bounded waits: if a wait
+ *                  gives up, sf_get_log reports SF_ERR_STATE, the solve is
+ *                  undefined and the context falls back to per-iteration
+ *                  kernels); batches, and devices on which 32 such
+ *                  workgroups cannot be resident at once, run mode 3 as 2
  *  temporal        1 = video mode (Sec. 5.3): every sf_solve after the first
  *                  starts each level's delta from the previous sf_solve of
  *                  the context, transferred by its motion flow under

@@ -100,6 +100,7 @@ struct Plan {
     std::vector<int> shape;  // W, H per frame (batch cache key)
     CnnRun cnn;              // learned initialiser
     const CnnNet *net = nullptr;
+    bool no_mid = false;     // co-resident PCG switched off after a failed wait
     bool external = false;   // pool is caller-provided workspace (not freed)
     size_t pool_bytes = 0;
 };
@@ -153,7 +154,7 @@ sf_status check_params(const sf_params *p) {
     if (p->init_mode == 1 && p->levels <= SF_CNN_INPUT_LEVEL) return SF_ERR_INVALID_ARG;
     if (p->exec_mode != 0 && p->exec_mode != 1) return SF_ERR_INVALID_ARG;
     if (p->tile_mode < 0 || p->tile_mode > 4) return SF_ERR_INVALID_ARG;
-    if (p->apply_mode < 0 || p->apply_mode > 2) return SF_ERR_INVALID_ARG;
+    if (p->apply_mode < 0 || p->apply_mode > 3) return SF_ERR_INVALID_ARG;
     if (p->temporal != 0 && p->temporal != 1) return SF_ERR_INVALID_ARG;
     if (p->temporal == 1 && p->init_mode != 0) return SF_ERR_INVALID_ARG;
     if (p->illum != 0 && p->illum != 1) return SF_ERR_INVALID_ARG;
@@ -270,6 +271,8 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
     P.prm = prm;
     P.net = net;
     P.batched = batched;
+    // co-residency of the mid-level PCG's workgroups, checked once per plan
+    P.no_mid = prm.apply_mode == 3 && !batched && !mid_fits_device();
     P.nf = (int)levels.size();
     P.shape = shape;
     const int st = prm.grid_stride;
@@ -591,11 +594,17 @@ void enqueue_linearize(const Plan &P, hipStream_t st, int l) {
 
 // With apply_mode 2 the frames of a slot with at most SF_SMALL_G nodes run
 // their PCG in one workgroup each and the others in the multi-kernel form,
-// so a frame takes the same path alone or in any batch.
+// so a frame takes the same path alone or in any batch.  apply_mode 3
+// (single frames; batches run it as 2) also gives mid-size levels their
+// PCG in a few co-resident workgroups.
 void enqueue_pcg(const Plan &P, hipStream_t st, int l, int gn) {
     const Launch L = slot(P, l);
     const int n = P.prm.pcg_iters;
-    const bool sm = P.prm.apply_mode == 2;
+    if (P.prm.apply_mode == 3 && !P.batched && !P.no_mid && mid_level(L.host[0].d)) {
+        launch_pcg_mid(st, L, n, gn);
+        return;
+    }
+    const bool sm = P.prm.apply_mode >= 2;
     if (sm) launch_pcg_small(st, L, n, gn);
     const TileCfg &t = P.ptile[l];
     launch_pcg_first(st, L, t, sm);
@@ -1093,7 +1102,29 @@ sf_status sf_solve_batch(sf_ctx *c, int n, const sf_frame *frames, const sf_para
 
 sf_status sf_get_log(sf_ctx *c, sf_iter_log *out, int cap, int *n_written) {
     if (!c || !n_written || (cap > 0 && !out) || cap < 0) return SF_ERR_INVALID_ARG;
-    return copy_log(c->stream, c->single.fr[0], out, cap, n_written);
+    sf_status s = copy_log(c->stream, c->single.fr[0], out, cap, n_written);
+    if (s != SF_OK && s != SF_ERR_NUMERIC) return s;
+    // a co-resident PCG that gave up waiting leaves the solve undefined:
+    // report it, clear the flag and use the per-iteration kernels from now on
+    Plan &P = c->single;
+    if (P.prm.apply_mode == 3) {
+        int fail = 0;
+        HIP_TRY(hipMemcpy(&fail, &P.fr[0].sc->mid_fail, sizeof(int), hipMemcpyDeviceToHost));
+        if (fail) {
+            const int zero = 0;
+            HIP_TRY(hipMemcpy(&P.fr[0].sc->mid_fail, &zero, sizeof(int), hipMemcpyHostToDevice));
+            P.no_mid = true;
+            if (P.gexec) (void)hipGraphExecDestroy(P.gexec);
+            if (P.graph) (void)hipGraphDestroy(P.graph);
+            P.gexec = nullptr;
+            P.graph = nullptr;
+            snprintf(g_err, sizeof(g_err),
+                     "co-resident PCG workgroups gave up waiting for each other: the last "
+                     "solve is undefined; later solves use the per-iteration kernels");
+            return SF_ERR_STATE;
+        }
+    }
+    return s;
 }
 
 sf_status sf_get_batch_log(sf_ctx *c, int frame, sf_iter_log *out, int cap, int *n_written) {

@@ -114,6 +114,8 @@ struct DevScalars {
     int init_used;     // the learned initialisation was kept
     int n_valid;
     int have_prev;     // the temporal state holds a finished solve
+    unsigned mid_count;  // arrivals at the co-resident PCG's grid barriers
+    int mid_fail;        // a co-resident PCG gave up waiting (sticky)
 };
 
 // Device log record (mirrors sf_iter_log).
@@ -234,6 +236,16 @@ void launch_pcg_last(hipStream_t st, const Launch &L, const TileCfg &t,
 // iter / last for them)
 #define SF_SMALL_G 336
 void launch_pcg_small(hipStream_t st, const Launch &L, int n_it, int gn);
+// all pcg_iters iterations of a single frame's level in a few co-resident
+// workgroups of SF_SMALL_G nodes each, with grid barriers between the
+// iterations (apply_mode 3, levels with more than SF_SMALL_G and at most
+// SF_MID_G nodes and rows of at most SF_MID_GX nodes)
+#define SF_MID_WG 32
+#define SF_MID_G (SF_SMALL_G * SF_MID_WG)
+#define SF_MID_GX 128
+bool mid_level(const LevelDims &d);
+bool mid_fits_device();
+void launch_pcg_mid(hipStream_t st, const Launch &L, int n_it, int gn);
 void launch_accept(hipStream_t st, const Launch &L, int n_trials, int gn,
                    int pcg_iters);
 void launch_finish_level(hipStream_t st, const Launch &L);

@@ -15,6 +15,7 @@
 // that consume the sum add all partials in a fixed order in double
 // precision (every consuming workgroup obtaining the same value).
 #include <math.h>
+#include <stdlib.h>
 
 #include "sf_cnn.h"
 #include "sf_internal.h"
@@ -1179,6 +1180,8 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(KArg<B> ka, TileCfg t
     RhsNode nd;
     if (mine) nd.load(a, i, j, n);
     if (bid == 0) rhs_level_scalars(a);
+    // a fresh count for the co-resident PCG that may follow
+    if (bid == 0 && threadIdx.x == 0) a.sc->mid_count = 0u;
     tile_brackets(a, g, L);
     pixels_to_lds<12>(g, L, [&](int x, int y, int, int, float (&v)[12]) {
         const long pix = (long)y * d.W + x;
@@ -1255,6 +1258,8 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, Til
     RhsNode nd;
     if (mine) nd.load(a, i, j, n);
     if (bid == 0) rhs_level_scalars(a);
+    // a fresh count for the co-resident PCG that may follow
+    if (bid == 0 && threadIdx.x == 0) a.sc->mid_count = 0u;
     tile_brackets(a, g, L);
     pixels_to_lds<27>(g, L, [&](int x, int y, int, int, float (&v)[27]) {
         const long pix = (long)y * d.W + x;
@@ -2100,6 +2105,319 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_small(KArg<B> ka, int n_it, in
         a.partials[(long)(((n_it & 1) ? PS_PCG1 : PS_PCG0) + 2) * a.max_blocks + threadIdx.x] =
             threadIdx.x == 0 ? (float)rsum : 0.f;
     }
+}
+
+// ---- PCG of a mid-size level in a few co-resident workgroups ----------------
+//
+// apply_mode 3, single frames: a level with more than SF_SMALL_G nodes (and
+// at most SF_MID_G, rows of at most SF_MID_GX nodes) runs all PCG
+// iterations of a Gauss-Newton step in ceil(G / SF_SMALL_G) workgroups of
+// the one-workgroup layout (three lanes per node, blocks in registers and
+// LDS).  Workgroup w owns the nodes [w M, (w + 1) M) in row-major order,
+// M = SF_SMALL_G; the block products need u one node row (plus one) beyond
+// that range, which the workgroup forms itself from the r, w, s and diag
+// records its neighbours publish, as the multi-kernel form does for a
+// tile's halo.  One grid barrier per iteration replaces the kernel
+// boundary: after publishing its boundary records and its three partial
+// sums, a workgroup arrives on a counter (device-scope fence, atomic add)
+// and waits until all have arrived; every wait is bounded, and a
+// workgroup that gives up raises a sticky flag, which ends the waits of the
+// others at once and which the host reports.  The iterates are those of the
+// single-reduction PCG (the partial sums are reduced in another order than
+// in the multi-kernel form).
+
+// Waits at the grid barrier until `target` arrivals; false if it gave up.
+__device__ bool mid_barrier(DevScalars *sc, unsigned target, int spin_limit, int &s_stop) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(&sc->mid_count, 1u);
+        int spins = 0, ok = 1;
+        while (__hip_atomic_load(&sc->mid_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+               target) {
+            if (++spins > spin_limit ||
+                __hip_atomic_load(&sc->mid_fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                atomicExch(&sc->mid_fail, 1);
+                ok = 0;
+                break;
+            }
+        }
+        __threadfence();
+        s_stop = !ok;
+    }
+    __syncthreads();
+    return !s_stop;
+}
+
+#define MID_SU (SF_SMALL_G + 2 * (SF_MID_GX + 1))
+
+__global__ __launch_bounds__(SMALL_NT) void k_pcg_mid(LevelArgs a, int n_it, int gn,
+                                                      int spin_limit) {
+    __shared__ __attribute__((aligned(16))) float su[MID_SU * 8];
+    __shared__ __attribute__((aligned(16))) float sb[SMALL_NT * SF_GRAM_STRIDE];
+    __shared__ __attribute__((aligned(16))) float sx[(SMALL_NT + 2) * 8];
+    __shared__ float red[SMALL_NT / 64][3];
+    __shared__ int s_stop;
+    const LevelDims &d = a.d;
+    const int Pw = gridDim.x, wg = blockIdx.x;
+    const int n_begin = wg * SF_SMALL_G, n_end = min(n_begin + SF_SMALL_G, d.G);
+    // nodes whose u this workgroup holds in LDS: its own and one row + 1 beyond
+    const int h_begin = max(n_begin - d.Gx - 1, 0), h_end = min(n_end + d.Gx + 1, d.G);
+    const int log_index = gn >= 0 ? a.log_base + gn : -1;
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sub = lane % 3;
+    const int n = n_begin + wv * SMALL_NPW + lane / 3;
+    const bool valid = lane < 3 * SMALL_NPW && n < n_end;
+    const int i_n = valid ? n % d.Gx : 0, j_n = valid ? n / d.Gx : 0;
+    const int c0 = 2 * sub;
+    const int n_loc = valid ? n - h_begin : 0;
+    // blocks as in the one-workgroup kernel; partners by global index, their
+    // u at su[partner - h_begin]
+    float Bk[2][21];
+    int pn[3];
+    float *myb = sb + threadIdx.x * SF_GRAM_STRIDE;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        int k, di, dj;
+        bool own;
+        small_task(sub, q, k, own);
+        blk_offset(k, di, dj);
+        const int pi = own ? i_n + di : i_n - di, pj = own ? j_n + dj : j_n - dj;
+        const bool has = valid && pi >= 0 && pi < d.Gx && pj >= 0 && pj < d.Gy;
+        pn[q] = has ? pj * d.Gx + pi - h_begin : n_loc;
+        float t[21];
+#pragma unroll
+        for (int e = 0; e < 21; ++e) t[e] = 0.f;
+        if (has) {
+            const long owner = own ? (long)n : (long)(pj * d.Gx + pi);
+            rec_load<21>(a.blk + owner * SF_BLK_STRIDE + k * SF_GRAM_STRIDE, t);
+        }
+        if (q < 2) {
+#pragma unroll
+            for (int e = 0; e < 21; ++e) Bk[q][e] = t[e];
+        } else {
+            rec_store<21>(myb, t);
+        }
+    }
+    float cnb[4] = {0.f, 0.f, 0.f, 0.f}, J0o[2] = {0.f, 0.f}, J1o[2] = {0.f, 0.f};
+    int nbr[4];
+    float r2[2] = {0.f, 0.f}, u2[2] = {0.f, 0.f}, D2[2] = {1.f, 1.f};
+    float x2[2] = {0.f, 0.f}, p2[2] = {0.f, 0.f}, s2[2] = {0.f, 0.f}, w2[2] = {0.f, 0.f};
+    float wf2[2], cm2[2];
+    {
+        const DevConst *C = a.cst;
+        const float c = 2.f * C->w_reg * C->w_mag;
+        wf2[0] = C->wf[c0]; wf2[1] = C->wf[c0 + 1];
+        cm2[0] = c * C->mf[c0]; cm2[1] = c * C->mf[c0 + 1];
+    }
+    if (valid) {
+        const float2 rv = *reinterpret_cast<const float2 *>(nvec(a, NV_R0) + (long)n * 8 + c0);
+        const float2 uv = *reinterpret_cast<const float2 *>(nvec(a, NV_U) + (long)n * 8 + c0);
+        const float2 dv = *reinterpret_cast<const float2 *>(nvec(a, NV_DIAG) + (long)n * 8 + c0);
+        r2[0] = rv.x; r2[1] = rv.y; u2[0] = uv.x; u2[1] = uv.y; D2[0] = dv.x; D2[1] = dv.y;
+        float rg[REG_PLANES];
+        rec_load<REG_PLANES>(a.reg + (long)n * REG_PLANES, rg);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cnb[k] = rg[k];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            J0o[j] = sub == 0 ? rg[4 + j] : (sub == 1 ? rg[6 + j] : rg[8 + j]);
+            J1o[j] = sub == 0 ? rg[10 + j] : (sub == 1 ? rg[12 + j] : rg[14 + j]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int di, dj;
+        nb_offset(k, di, dj);
+        nbr[k] = valid && cnb[k] != 0.f ? (j_n + dj) * d.Gx + i_n + di - h_begin : n_loc;
+    }
+    // this workgroup's nodes that neighbouring workgroups hold as halo
+    const bool publish = valid && (n < n_begin + d.Gx + 1 || n >= n_end - d.Gx - 1);
+
+    double hg = 0.0;           // gamma of the previous decision
+    float ha = 0.f;            // alpha of the previous decision
+    float al = 0.f, be = 0.f;  // scalars of iteration i-1
+    int act = 1;
+    int nbar = 0;              // barriers passed
+    for (int i = 0; i <= n_it; ++i) {
+        if (i > 0) {
+            // the sums of pass i-1 from every workgroup (each wavefront reduces
+            // them in the same order) decide iteration i-1
+            const float *pp = a.partials + (long)(((i - 1) & 1) ? PS_PCG1 : PS_PCG0) * a.max_blocks;
+            const int rw = lane & 31;
+            const double g0 = rw < Pw ? (double)pp[rw] : 0.0;
+            const double g1 = rw < Pw ? (double)pp[a.max_blocks + rw] : 0.0;
+            const double g2 = rw < Pw ? (double)pp[2 * a.max_blocks + rw] : 0.0;
+            const double gam = uniform_d(group_sum<double>(g0, 32));
+            const double del = uniform_d(group_sum<double>(g1, 32));
+            const double rsum = uniform_d(group_sum<double>(g2, 32));
+            double b = 0.0, pq = del;
+            if (i - 1 > 0) {
+                b = gam / hg;
+                pq = del - b * gam / (double)ha;
+            }
+            const int ok = act && gam > 1e-30 && pq > 0.0 && isfinite(pq);
+            al = ok ? (float)(gam / pq) : 0.f;
+            be = ok ? (float)b : 0.f;
+            if (wg == 0 && threadIdx.x == 0) {
+                // an inactive iteration leaves every later one inactive with
+                // the same sums
+                for (int m = i; m <= (ok ? i : n_it); ++m) {
+                    PcgHist o;
+                    o.gamma = gam; o.alpha = al; o.beta = be; o.active = ok; o.pad = 0;
+                    a.sc->hist[m] = o;
+                    if (log_index >= 0 && m >= 2) a.log[log_index].pcg_res[m - 2] = (float)sqrt(rsum);
+                }
+            }
+            hg = gam;
+            ha = al;
+            act = ok;
+            if (!act) break;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                s2[j] = i > 1 ? w2[j] + be * s2[j] : w2[j];
+                p2[j] = i > 1 ? u2[j] + be * p2[j] : u2[j];
+                x2[j] = x2[j] + al * p2[j];
+                r2[j] = r2[j] - al * s2[j];
+                u2[j] = r2[j] / D2[j];
+            }
+            if (i == n_it) break;
+            // halo u_i from the neighbours' records of pass i-1
+            const float *Rp = nvec(a, ((i - 1) & 1) ? NV_R1 : NV_R0);
+            const float *Wp = nvec(a, ((i - 1) & 1) ? NV_W1 : NV_W0);
+            const float *Sp = nvec(a, ((i - 2) & 1) ? NV_S1 : NV_S0);
+            const float *Dg = nvec(a, NV_DIAG);
+            for (int m = h_begin + threadIdx.x; m < h_end; m += blockDim.x) {
+                if (m >= n_begin && m < n_end) continue;
+                float rv[6], wv6[6], sv[6], dv[6], uh[6];
+                ld6(Rp, m, rv);
+                ld6(Wp, m, wv6);
+                ld6(Dg, m, dv);
+                if (i > 1) {
+                    ld6(Sp, m, sv);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) sv[q] = 0.f;
+                }
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    const float sn = i > 1 ? wv6[q] + be * sv[q] : wv6[q];
+                    const float rn = rv[q] - al * sn;
+                    uh[q] = rn / dv[q];
+                }
+                rec_store<6>(su + (size_t)(m - h_begin) * 8, uh);
+            }
+        } else {
+            // u_0 of the halo as the right-hand-side kernel stored it
+            const float *Ug = nvec(a, NV_U);
+            for (int m = h_begin + threadIdx.x; m < h_end; m += blockDim.x) {
+                if (m >= n_begin && m < n_end) continue;
+                float uh[6];
+                ld6(Ug, m, uh);
+                rec_store<6>(su + (size_t)(m - h_begin) * 8, uh);
+            }
+        }
+        // u_i of the own nodes; w_i = H u_i
+        if (valid) *reinterpret_cast<float2 *>(su + n_loc * 8 + c0) = make_float2(u2[0], u2[1]);
+        __syncthreads();
+        float y[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        {
+            float un[3][6];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) rec_load<6>(su + pn[q] * 8, un[q]);
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int r = 0; r < 6; ++r)
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) y[r] += Bk[q][gram_index(r, c)] * un[q][c];
+            float b2[21];
+            rec_load<21>(myb, b2);
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) y[r] += b2[gram_index(r, c)] * un[2][c];
+        }
+        {
+            const float e0 = J0o[0] * u2[0] + J0o[1] * u2[1];
+            const float e1 = J1o[0] * u2[0] + J1o[1] * u2[1];
+            float4 *mx = reinterpret_cast<float4 *>(sx + threadIdx.x * 8);
+            mx[0] = make_float4(y[0], y[1], y[2], y[3]);
+            mx[1] = make_float4(y[4], y[5], e0, e1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        float w2s[2] = {0.f, 0.f}, jp0 = 0.f, jp1 = 0.f;
+        const float *gx = sx + (threadIdx.x - sub) * 8;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const float2 yc = *reinterpret_cast<const float2 *>(gx + t * 8 + c0);
+            const float2 ee = *reinterpret_cast<const float2 *>(gx + t * 8 + 6);
+            w2s[0] += yc.x;
+            w2s[1] += yc.y;
+            jp0 += ee.x;
+            jp1 += ee.y;
+        }
+        float ru = 0.f, wu = 0.f, rr = 0.f;
+        if (valid) {
+            float sm[2] = {0.f, 0.f};
+            float2 un[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) un[k] = *reinterpret_cast<const float2 *>(su + nbr[k] * 8 + c0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                sm[0] += cnb[k] * (u2[0] - un[k].x);
+                sm[1] += cnb[k] * (u2[1] - un[k].y);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                w2[j] = w2s[j] + wf2[j] * sm[j] + J0o[j] * jp0 + J1o[j] * jp1 + cm2[j] * u2[j];
+                ru += r2[j] * u2[j];
+                wu += w2[j] * u2[j];
+                rr += r2[j] * r2[j];
+            }
+        }
+        // this workgroup's sums (wavefront sums in float, the wavefronts'
+        // in double, fixed order) and its boundary records of pass i
+        const float t0 = wave_sum(ru), t1 = wave_sum(wu), t2 = wave_sum(rr);
+        if (lane == 0) { red[wv][0] = t0; red[wv][1] = t1; red[wv][2] = t2; }
+        if (publish) {
+            *reinterpret_cast<float2 *>(nvec(a, (i & 1) ? NV_R1 : NV_R0) + (long)n * 8 + c0) =
+                make_float2(r2[0], r2[1]);
+            *reinterpret_cast<float2 *>(nvec(a, (i & 1) ? NV_W1 : NV_W0) + (long)n * 8 + c0) =
+                make_float2(w2[0], w2[1]);
+            if (i > 0)
+                *reinterpret_cast<float2 *>(nvec(a, ((i - 1) & 1) ? NV_S1 : NV_S0) + (long)n * 8 + c0) =
+                    make_float2(s2[0], s2[1]);
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            double t = 0.0;
+            for (int w = 0; w < nw; ++w) t += (double)red[w][threadIdx.x];
+            a.partials[(long)(((i & 1) ? PS_PCG1 : PS_PCG0) + threadIdx.x) * a.max_blocks + wg] =
+                (float)t;
+        }
+        ++nbar;
+        if (!mid_barrier(a.sc, (unsigned)nbar * Pw, spin_limit, s_stop)) return;
+    }
+    // the solution, and ||r||^2 of the final residual for the step control's
+    // log (one partial per workgroup, zeros up to the node-block count the
+    // step control sums)
+    if (valid) *reinterpret_cast<float2 *>(nvec(a, NV_X) + (long)n * 8 + c0) = make_float2(x2[0], x2[1]);
+    const float rrf = valid ? r2[0] * r2[0] + r2[1] * r2[1] : 0.f;
+    const float t2 = wave_sum(rrf);
+    __syncthreads();
+    if (lane == 0) red[wv][2] = t2;
+    __syncthreads();
+    float *rrp = a.partials + (long)(((n_it & 1) ? PS_PCG1 : PS_PCG0) + 2) * a.max_blocks;
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += (double)red[w][2];
+        rrp[wg] = (float)t;
+    }
+    if (wg == 0)
+        for (int b = Pw + threadIdx.x; b < node_blocks(d); b += blockDim.x) rrp[b] = 0.f;
 }
 
 // ---- step control: accept the first tau with E_trial <= E ------------------
@@ -3001,6 +3319,34 @@ void launch_pcg_small(hipStream_t st, const Launch &L, int n_it, int gn) {
     if (gmax == 0) return;
     const int threads = 64 * ((gmax + SMALL_NPW - 1) / SMALL_NPW);
     go(st, L, one, k_pcg_small<true>, k_pcg_small<false>, threads, 0, n_it, gn);
+}
+
+bool mid_level(const LevelDims &d) {
+    return d.G > SF_SMALL_G && d.G <= SF_MID_G && d.Gx <= SF_MID_GX;
+}
+
+// Whether SF_MID_WG workgroups of k_pcg_mid fit on the current device at
+// once (occupancy per compute unit times the unit count); the co-resident
+// form is used only then.
+bool mid_fits_device() {
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pcg_mid, SMALL_NT, 0) !=
+        hipSuccess)
+        return false;
+    return (long)per_cu * prop.multiProcessorCount >= SF_MID_WG;
+}
+
+void launch_pcg_mid(hipStream_t st, const Launch &L, int n_it, int gn) {
+    const LevelArgs &a = L.host[0];
+    const int P = (a.d.G + SF_SMALL_G - 1) / SF_SMALL_G;
+    // about a second of polling before a wait gives up; SF_MID_SPIN_LIMIT
+    // overrides it (tests force the give-up path with a tiny limit)
+    int spin_limit = 1 << 21;
+    if (const char *e = getenv("SF_MID_SPIN_LIMIT")) spin_limit = atoi(e);
+    hipLaunchKernelGGL(k_pcg_mid, dim3(P), dim3(SMALL_NT), 0, st, a, n_it, gn, spin_limit);
 }
 
 void launch_pcg_last(hipStream_t st, const Launch &L, const TileCfg &t, int iter, int gn,

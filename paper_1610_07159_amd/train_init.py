@@ -108,10 +108,13 @@ def level4_intensities(solver, H, W):
     return tex.reshape(4, H >> LEVEL_IN, W >> LEVEL_IN, 4)[..., 0].copy()
 
 
-def stream_training_data(ex, W, H, seeds, sched, log=print, max_disp=None, blobs=0):
+def stream_training_data(ex, W, H, seeds, sched, log=print, max_disp=None, blobs=0,
+                         deadline=None):
     """Renders the training frames in the pool and solves each on the GPU
     as it arrives (plain solver, zero initialisation); returns the level-4
-    inputs x (N, 4, h, w) and targets y (N, 6, h, w), float32."""
+    inputs x (N, 4, h, w) and targets y (N, 6, h, w), float32, of the
+    first N seeds (all of them, or those done when time.time() passes
+    deadline)."""
     import torch
     from paper_1610_07159_amd import SceneFlowSolver
     jobs = [(W, H, s, False, max_disp, blobs) for s in seeds]
@@ -126,11 +129,14 @@ def stream_training_data(ex, W, H, seeds, sched, log=print, max_disp=None, blobs
             xs.append(level4_intensities(solver, H, W))
             # restriction to level 4 (16 x 16 box average, floor sizes) on
             # the device: only the small target crosses to the host
-            k = 1 << LEVEL_IN
-            fl = out[2][:, :(H // k) * k, :(W // k) * k]
-            ys.append((torch.nn.functional.avg_pool2d(fl[None], k)[0] / k).cpu().numpy())
+            c = 1 << LEVEL_IN
+            fl = out[2][:, :(H // c) * c, :(W // c) * c]
+            ys.append((torch.nn.functional.avg_pool2d(fl[None], c)[0] / c).cpu().numpy())
             if (k + 1) % 10 == 0:
                 log(f"  rendered and solved {k + 1}/{len(jobs)}")
+            if deadline is not None and time.time() > deadline:
+                log(f"  time limit: stopping after {k + 1} frames")
+                break
     finally:
         solver.close()
     return np.stack(xs), np.stack(ys)
@@ -333,6 +339,9 @@ def main():
                          "used together with this run's frames")
     ap.add_argument("--no-train", action="store_true",
                     help="only render, solve and save the training data")
+    ap.add_argument("--time-limit", type=float, default=None,
+                    help="stop rendering training frames after this many seconds "
+                         "(counted from the start) and keep those done")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only time this many trainer steps on random level-4 inputs of "
                          "the frame size (batch --batch) and exit")
@@ -341,6 +350,7 @@ def main():
     if args.profile_steps:
         return profile_trainer(args.width >> LEVEL_IN, args.height >> LEVEL_IN, args.batch,
                                args.profile_steps, log)
+    t_start = time.time()
     W, H = args.width, args.height
     sched_full = dict(SCHEDULE, levels=args.levels)
     scene = dict(max_disp=args.max_disp, blobs=args.blobs)
@@ -361,14 +371,15 @@ def main():
     torch.cuda.set_device(0)
     t1 = time.time()
     x, y = stream_training_data(ex, W, H, range(args.seed0, args.seed0 + args.frames),
-                                sched_full, log, **scene)
-    ex.shutdown()
+                                sched_full, log, **scene,
+                                deadline=(t_start + args.time_limit if args.time_limit else None))
+    ex.shutdown(cancel_futures=True)
     log(f"{len(x)} training frames rendered and solved in {time.time() - t1:.0f} s; "
         f"inputs {x.shape}, targets {y.shape}")
     if args.save_data:
         with open(args.save_data, "wb") as f:
             np.savez(f, x=x.astype(np.float16), y=y.astype(np.float16),
-                     seeds=np.arange(args.seed0, args.seed0 + args.frames))
+                     seeds=np.arange(args.seed0, args.seed0 + len(x)))
         log(f"saved {args.save_data}")
     n_loaded = 0
     for path in args.load_data:

@@ -50,7 +50,7 @@ def test_host_validation_without_gpu():
     for field, bad in (("levels", 0), ("levels", 99), ("pcg_iters", 65),
                        ("grid_stride", 0), ("m_m", 0.0), ("w_photo", -1.0),
                        ("max_backtracks", 9), ("exec_mode", 3), ("tile_mode", 5),
-                       ("init_mode", 2), ("apply_mode", 3), ("apply_mode", -1), ("temporal", 2), ("illum", 2),
+                       ("init_mode", 2), ("apply_mode", 4), ("apply_mode", -1), ("temporal", 2), ("illum", 2),
                        ("occlusion", 2), ("occlusion", -1),
                        ("eps", float("nan"))):
         q = sf.sf_params_default(**{field: bad})

@@ -73,15 +73,20 @@ def _smooth_field(grid, amp, seed):
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-@pytest.mark.parametrize("case", ["vga640x480_s4", "hd1280x720_s8", "hd1280x720_s4",
-                                  "hd1280x720_s2"])
-def test_fullsize_solve_parity(case):
+@pytest.mark.parametrize("case,apply", [("vga640x480_s4", 2), ("vga640x480_s4", 3),
+                                        ("hd1280x720_s8", 2), ("hd1280x720_s8", 3),
+                                        ("hd1280x720_s4", 2), ("hd1280x720_s2", 2)])
+def test_fullsize_solve_parity(case, apply):
+    """Full-size solves against the stored oracle solves, with the default
+    node-block PCG (apply_mode 2) and with the co-resident PCG of the
+    mid-size levels (apply_mode 3)."""
     z, meta = _golden(case)
     imgs, calib = _frame(meta["generator"])
     assert hashlib.sha256(imgs.tobytes()).hexdigest() == str(z["images_sha256"]), \
         "the generator did not reproduce the stored frame"
     prm = dict(levels=meta["levels"], grid_stride=meta["grid_stride"],
-               gn_iters=meta["gn_iters"], pcg_iters=meta["pcg_iters"], tile_mode=1)
+               gn_iters=meta["gn_iters"], pcg_iters=meta["pcg_iters"], tile_mode=1,
+               apply_mode=apply)
     g = GpuCase(imgs, calib, exec_mode=0, **prm)
     try:
         depth, flow3d, flows = g.solve()

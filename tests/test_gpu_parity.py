@@ -246,7 +246,9 @@ def test_solve_tiny_parity():
                                               (160, 120, 4, 1), (96, 72, 2, 1),
                                               (144, 104, 8, 1), (90, 70, 3, 1),
                                               (100, 76, 4, 2), (160, 120, 4, 2),
-                                              (96, 72, 2, 2), (144, 104, 8, 2)])
+                                              (96, 72, 2, 2), (144, 104, 8, 2),
+                                              (160, 120, 4, 3), (96, 72, 2, 3),
+                                              (144, 104, 4, 3), (200, 150, 2, 3)])
 def test_solve_medium_parity(W, H, stride, apply):
     imgs, calib = _frame(W, H, seed=7)
     prm = dict(levels=3, grid_stride=stride, gn_iters=4, pcg_iters=10, apply_mode=apply)
@@ -260,7 +262,7 @@ def test_solve_tiny_parity_node_blocks(apply):
     _solve_parity(imgs, calib, prm)
 
 
-@pytest.mark.parametrize("apply", [0, 1, 2])
+@pytest.mark.parametrize("apply", [0, 1, 2, 3])
 def test_graph_replay_matches_eager_and_repeats(apply):
     imgs, calib = _frame(128, 96, seed=9)
     prm = dict(levels=3, grid_stride=4, gn_iters=3, pcg_iters=8, apply_mode=apply)
@@ -389,3 +391,36 @@ def test_stereo_only_call(apply):
     fin = np.isfinite(flow3d).all(0)
     assert fin.mean() > 0.9
     assert np.abs(flow3d[:, fin]).max() <= 1e-3 * np.nanmax(depth)
+
+
+def test_mid_pcg_gives_up_without_hanging(monkeypatch):
+    """apply_mode 3 with the co-resident PCG's waits forced to give up at
+    once (a spin limit of zero set from the host): every workgroup still
+    exits, sf_get_log reports SF_ERR_STATE for that solve, and the next
+    solve of the context runs the per-iteration kernels and matches the
+    oracle."""
+    from paper_1610_07159_amd import sf
+    imgs, calib = _frame(160, 120, seed=7)
+    prm = dict(levels=3, grid_stride=4, gn_iters=4, pcg_iters=10, apply_mode=3)
+    monkeypatch.setenv("SF_MID_SPIN_LIMIT", "0")
+    g = GpuCase(imgs, calib, exec_mode=0, **prm)
+    try:
+        g.solve()
+        with pytest.raises(sf.SfError) as e:
+            g.log()
+        assert e.value.code == -6
+        assert "gave up" in sf.lib.sf_last_error().decode()
+        monkeypatch.delenv("SF_MID_SPIN_LIMIT")
+        depth, flow3d, flows = g.solve()
+        log, code = g.log()
+    finally:
+        g.close()
+    assert code == 0
+    p = oracle_params(**prm)
+    rec = []
+    res = O.solve(imgs.astype(np.float64), calib, p, record=rec)
+    for lg, ro in zip(log, rec):
+        assert abs(lg["energy"] - ro["energy"]) <= 1e-4 * abs(ro["energy"])
+    grid = res["grid"]
+    ref = grid.to_pixels(res["total"]).reshape(6, grid.H, grid.W)
+    assert np.abs(flows - ref).max() <= 0.02
