@@ -419,7 +419,15 @@ sf_status sf_debug_set_images(sf_ctx *ctx, const float *I_left_t,
  *                        energy does not exceed E at the last
  *                        SF_STAGE_LINEARIZE (delta unchanged if none)
  *  SF_STAGE_OCC          the occlusion map of level - 1 from this level's
- *                        base + delta (level >= 1, occlusion = 1)        */
+ *                        base + delta (level >= 1, occlusion = 1)
+ *  SF_STAGE_SPEC_STEP    the same step control in the solve's speculative
+ *                        form (apply_mode >= 1; every Gauss-Newton step of
+ *                        a level but its last): the linearisation at
+ *                        delta + dx, the shorter trials, then the next
+ *                        step's right-hand side and PCG.  Afterwards delta
+ *                        is moved as by SF_STAGE_STEP, the energy
+ *                        (SF_DBG_ENERGY) and diag(H) are those at the new
+ *                        delta, and dx is the new PCG solution         */
 enum {
     SF_STAGE_LEVEL_INIT = 0,
     SF_STAGE_LINEARIZE = 1,
@@ -429,7 +437,8 @@ enum {
     SF_STAGE_FINISH = 5,
     SF_STAGE_MASKS = 6,
     SF_STAGE_STEP = 7,
-    SF_STAGE_OCC = 8
+    SF_STAGE_OCC = 8,
+    SF_STAGE_SPEC_STEP = 9
 };
 sf_status sf_debug_run(sf_ctx *ctx, int stage, int level);
 

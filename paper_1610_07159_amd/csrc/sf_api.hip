@@ -310,6 +310,10 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
                 mb = mb > nt ? mb : nt;
             }
             mb = mb > node_tile_blocks(d, P.tile) ? mb : node_tile_blocks(d, P.tile);
+            // the block-assembly tiles (their energy partials, when they
+            // re-linearise after a rejected speculative step)
+            const int bt = node_tile_blocks(d, pick_blk_tile(st));
+            mb = mb > bt ? mb : bt;
             for (int v = 0; v < SF_NB_VARIANTS; ++v) {
                 const int nbt = node_tile_blocks(d, pick_nb_tile(v));
                 mb = mb > nbt ? mb : nbt;
@@ -597,17 +601,17 @@ void enqueue_linearize(const Plan &P, hipStream_t st, int l) {
 // so a frame takes the same path alone or in any batch.  apply_mode 3
 // (single frames; batches run it as 2) also gives mid-size levels their
 // PCG in a few co-resident workgroups.
-void enqueue_pcg(const Plan &P, hipStream_t st, int l, int gn) {
+void enqueue_pcg(const Plan &P, hipStream_t st, int l, int gn, bool pend = false) {
     const Launch L = slot(P, l);
     const int n = P.prm.pcg_iters;
     if (P.prm.apply_mode == 3 && !P.batched && !P.no_mid && mid_level(L.host[0].d)) {
-        launch_pcg_mid(st, L, n, gn);
+        launch_pcg_mid(st, L, n, gn, pend);
         return;
     }
     const bool sm = P.prm.apply_mode >= 2;
-    if (sm) launch_pcg_small(st, L, n, gn);
+    if (sm) launch_pcg_small(st, L, n, gn, pend);
     const TileCfg &t = P.ptile[l];
-    launch_pcg_first(st, L, t, sm);
+    launch_pcg_first(st, L, t, sm, pend);
     for (int i = 1; i < n; ++i) launch_pcg_iter(st, L, t, i, gn, 0, sm);
     launch_pcg_last(st, L, t, n, gn, 0, sm);
 }
@@ -626,6 +630,36 @@ void enqueue_gn(const Plan &P, hipStream_t st, int l, int g, bool log) {
     enqueue_linearize(P, st, l);
     enqueue_pcg(P, st, l, log ? g : -1);
     enqueue_step(P, st, l, log ? g : -1);
+}
+
+// The Gauss-Newton steps of level l.  In the node-block modes every step
+// but the level's last ends speculatively: the linearisation at delta + dx
+// (its energy is the tau = 1 trial), then the shorter-trial kernel, which
+// on acceptance moves delta, so that the next step starts at its
+// right-hand side.  A rejected tau = 1 is finished by the next step's
+// right-hand-side and first PCG kernels (step length, records at the
+// chosen point, delta).  Either way every iterate is that of the plain
+// sequence (linearise, PCG, trials, accept), with three launches per step
+// instead of five.
+void enqueue_gn_steps(const Plan &P, hipStream_t st, int l) {
+    const int n = gn_at(P.prm, l);
+    const bool spec = P.prm.apply_mode >= 1;
+    const int T = P.prm.max_backtracks + 1;
+    const Launch L = slot(P, l);
+    for (int g = 0; g < n; ++g) {
+        const bool pend = spec && g > 0;
+        if (pend)
+            launch_rhs_blocks(st, L, T, g - 1, P.prm.pcg_iters);
+        else
+            enqueue_linearize(P, st, l);
+        enqueue_pcg(P, st, l, g, pend);
+        if (spec && g + 1 < n) {
+            launch_spec_linearize(st, L);
+            launch_trials_rest(st, L, T - 1, true, g, P.prm.pcg_iters);
+        } else {
+            enqueue_step(P, st, l, g);
+        }
+    }
 }
 
 // The network on the level-4 images of every frame that uses it: each
@@ -651,7 +685,7 @@ void enqueue_levels(const Plan &P, hipStream_t st) {
         // level this is
         if (P.cnn.on && P.cnn.slot_has[l]) launch_cnn_candidate(st, slot(P, l));
         launch_level_init(st, slot(P, l));
-        for (int g = 0; g < gn_at(P.prm, l); ++g) enqueue_gn(P, st, l, g, true);
+        enqueue_gn_steps(P, st, l);
         launch_finish_level(st, slot(P, l));
         if (P.prm.illum) launch_illum_next(st, slot(P, l));
         if (P.prm.occlusion) launch_occ_next(st, slot(P, l));
@@ -1464,6 +1498,15 @@ sf_status sf_debug_run(sf_ctx *c, int stage, int level) {
             if (level == 0 || !P.fr[0].occ) return SF_ERR_INVALID_ARG;
             launch_occ_next(st, L);
             break;
+        case SF_STAGE_SPEC_STEP: {
+            if (P.prm.apply_mode < 1) return SF_ERR_INVALID_ARG;
+            const int T = P.prm.max_backtracks + 1;
+            launch_spec_linearize(st, L);
+            launch_trials_rest(st, L, T - 1, true, -1, P.prm.pcg_iters);
+            launch_rhs_blocks(st, L, T, -1, P.prm.pcg_iters);
+            enqueue_pcg(P, st, level, -1, true);
+            break;
+        }
         default: return SF_ERR_INVALID_ARG;
     }
     HIP_TRY(hipGetLastError());

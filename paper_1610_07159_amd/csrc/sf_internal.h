@@ -116,6 +116,12 @@ struct DevScalars {
     int have_prev;     // the temporal state holds a finished solve
     unsigned mid_count;  // arrivals at the co-resident PCG's grid barriers
     int mid_fail;        // a co-resident PCG gave up waiting (sticky)
+    // speculative steps: tau = 1 was accepted (the shorter-trial kernel's
+    // verdict); otherwise the step length the right-hand-side kernel chose
+    // and the number of energy partials it left
+    int spec_acc;
+    float spec_tau;
+    int lin_n;
 };
 
 // Device log record (mirrors sf_iter_log).
@@ -215,18 +221,33 @@ void launch_level_masks(hipStream_t st, const Launch &L);
 // (before launch_level_init)
 void launch_cnn_candidate(hipStream_t st, const Launch &L);
 void launch_linearize(hipStream_t st, const Launch &L);
+// speculative step (node-block modes, every Gauss-Newton step of a level
+// but its last): the linearisation at delta + dx, whose energy is also the
+// step control's tau = 1 trial
+void launch_spec_linearize(hipStream_t st, const Launch &L);
 // step control: the energy at tau = 1, then (each workgroup returning at
-// once if tau = 1 was accepted) the n_rest shorter steps 2^-1 .. 2^-n_rest
+// once if tau = 1 was accepted) the n_rest shorter steps 2^-1 .. 2^-n_rest.
+// spec: the tau = 1 energy came from launch_spec_linearize; the kernel then
+// records its verdict, and on acceptance applies delta += dx and writes the
+// step's log (gn, pcg_iters as for launch_accept)
 void launch_trial0(hipStream_t st, const Launch &L);
-void launch_trials_rest(hipStream_t st, const Launch &L, int n_rest);
+void launch_trials_rest(hipStream_t st, const Launch &L, int n_rest, bool spec = false,
+                        int gn = -1, int pcg_iters = 0);
 void launch_rhs(hipStream_t st, const Launch &L, const TileCfg &t);
 // right-hand side, diag(H) and the per-node blocks from the pixel records
-// (node-block apply mode; replaces launch_rhs after launch_linearize)
-void launch_rhs_blocks(hipStream_t st, const Launch &L);
+// (node-block apply mode; replaces launch_rhs after launch_linearize).
+// n_pend > 0 (= the step control's trial count): a speculative step
+// precedes; where tau = 1 was rejected the kernel chooses the step length,
+// forms the pixel records at delta + tau dx itself and writes the previous
+// step's log (gn_prev, pcg_iters); delta itself moves in the PCG's first
+// kernel
+void launch_rhs_blocks(hipStream_t st, const Launch &L, int n_pend = 0, int gn_prev = -1,
+                       int pcg_iters = 0);
 // skip_small: frames with at most SF_SMALL_G nodes are left out (their PCG
-// runs in launch_pcg_small)
+// runs in launch_pcg_small); pend: a speculative step precedes (the
+// deferred delta update of a rejected tau = 1 happens here)
 void launch_pcg_first(hipStream_t st, const Launch &L, const TileCfg &t,
-                      bool skip_small = false);
+                      bool skip_small = false, bool pend = false);
 void launch_pcg_iter(hipStream_t st, const Launch &L, const TileCfg &t,
                      int iter, int gn, int force, bool skip_small = false);
 void launch_pcg_last(hipStream_t st, const Launch &L, const TileCfg &t,
@@ -235,7 +256,7 @@ void launch_pcg_last(hipStream_t st, const Launch &L, const TileCfg &t,
 // frames with at most SF_SMALL_G nodes (node-block mode; replaces first /
 // iter / last for them)
 #define SF_SMALL_G 336
-void launch_pcg_small(hipStream_t st, const Launch &L, int n_it, int gn);
+void launch_pcg_small(hipStream_t st, const Launch &L, int n_it, int gn, bool pend = false);
 // all pcg_iters iterations of a single frame's level in a few co-resident
 // workgroups of SF_SMALL_G nodes each, with grid barriers between the
 // iterations (apply_mode 3, levels with more than SF_SMALL_G and at most
@@ -245,7 +266,7 @@ void launch_pcg_small(hipStream_t st, const Launch &L, int n_it, int gn);
 #define SF_MID_GX 128
 bool mid_level(const LevelDims &d);
 bool mid_fits_device();
-void launch_pcg_mid(hipStream_t st, const Launch &L, int n_it, int gn);
+void launch_pcg_mid(hipStream_t st, const Launch &L, int n_it, int gn, bool pend = false);
 void launch_accept(hipStream_t st, const Launch &L, int n_trials, int gn,
                    int pcg_iters);
 void launch_finish_level(hipStream_t st, const Launch &L);

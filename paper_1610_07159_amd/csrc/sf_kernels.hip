@@ -736,9 +736,11 @@ __device__ void node_energy(const LevelArgs &a, int n, float tau, float (&part)[
 }
 
 // Energy grid: blocks [0, n_pix) are 16x16 pixel tiles, blocks
-// [n_pix, grid) 256 nodes each for the regulariser energies.  With LIN the
-// per-pixel records and the energy at delta (summed by the right-hand-side
-// kernel); otherwise a trial energy at delta + tau dx (summed by the step
+// [n_pix, grid) 256 nodes each for the regulariser energies, at
+// delta + tau dx.  With LIN also the per-pixel records (tau = 0: the
+// linearisation at delta; tau = 1: the speculative one at delta + dx, whose
+// energy is also the step control's tau = 1 trial); the right-hand-side
+// kernel sums the energy.  Otherwise a trial energy (summed by the step
 // control).
 
 // Energy terms of one energy-grid workgroup's share at step length tau:
@@ -804,7 +806,7 @@ __global__ __launch_bounds__(SF_BLOCK) void k_energy(KArg<B> ka, float tau) {
     (void)nblk;
     __shared__ NodeStage S;
     float part[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    energy_tile<LIN>(a, bid, LIN ? 0.f : tau, S, part);
+    energy_tile<LIN>(a, bid, tau, S, part);
     float tot5[5];
     block_sum<5, false>(part, tot5);
     if (threadIdx.x == 0) {
@@ -837,22 +839,101 @@ __host__ __device__ inline int rest_blocks_of(const LevelDims &d) {
     return n < 128 ? n : 128;
 }
 
+// The first shorter step tau = 2^-t (t = 1 .. n_trials - 1) whose energy
+// does not exceed E(delta), from the shorter trials' partials, once tau = 1
+// was rejected; -1 if none (delta stays).  e: that trial's terms.  One
+// wavefront; every caller obtains the same result.
+__device__ int rest_decision(const LevelArgs &a, int n_trials, double (&e)[6]) {
+    const double e0 = a.sc->e_lin[5];
+    int kacc = -1;
+    for (int t = 1; t < n_trials && kacc < 0; ++t) {
+        trial_energy_wave(a, PS_TRIAL + 5 * (t - 1), rest_blocks_of(a.d), e);
+        if (e[5] <= e0) kacc = t;
+    }
+    return kacc;
+}
+
+// The log entry of a Gauss-Newton step (gn_iter >= 0) and the accepted
+// trial's terms e (kacc >= 0), by one wavefront of one workgroup, before
+// the next linearisation energy replaces e_lin.
+__device__ void step_record(const LevelArgs &a, int gn_iter, int pcg_iters, int kacc,
+                            const double (&e)[6]) {
+    const int lane = threadIdx.x & 63;
+    const int log_index = gn_iter >= 0 ? a.log_base + gn_iter : -1;
+    const DevScalars *sc = a.sc;
+    double rr = 0.0;
+    if (log_index >= 0) {
+        // ||r||^2 of the final PCG residual (node_blocks partials)
+        const float *rrp = a.partials +
+                           (long)(((pcg_iters & 1) ? PS_PCG1 : PS_PCG0) + 2) * a.max_blocks;
+        double acc[1] = {0.0};
+        strided_sums<1, 8>(lane, 64, node_blocks(a.d), [&](int, int b) { return rrp[b]; }, acc);
+        rr = wave_sum_d(acc[0]);
+    }
+    if (lane != 0) return;
+    const double e0 = sc->e_lin[5];
+    if (kacc >= 0)
+        for (int k = 0; k < 6; ++k) a.sc->e_trial[kacc][k] = e[k];
+    if (log_index < 0) return;
+    DevLog &Lg = a.log[log_index];
+    Lg.level = a.level;
+    Lg.gn_iter = gn_iter;
+    Lg.energy = e0;
+    Lg.e_photo = sc->e_lin[0];
+    Lg.e_grad = sc->e_lin[1];
+    Lg.e_smooth = sc->e_lin[2];
+    Lg.e_epi = sc->e_lin[3];
+    Lg.e_mag = sc->e_lin[4];
+    Lg.energy_after = kacc >= 0 ? e[5] : e0;
+    Lg.tau = kacc >= 0 ? ldexpf(1.f, -kacc) : 0.f;
+    Lg.pcg_iters = pcg_iters;
+    // an inactive last iteration left r unchanged
+    const bool same = !sc->hist[pcg_iters].active && pcg_iters >= 2;
+    Lg.pcg_res[pcg_iters - 1] = same ? Lg.pcg_res[pcg_iters - 2] : (float)sqrt(rr);
+    Lg.n_valid = sc->n_valid;
+}
+
 // Trials tau = 1/2, 1/4, ... (n_rest of them), evaluated only if tau = 1
 // was rejected: every workgroup first sums the tau = 1 partials itself and
 // returns at once on acceptance.  Partials of trial t go to plane
-// PS_TRIAL + 5 (t - 1).
+// PS_TRIAL + 5 (t - 1).  spec (the tau = 1 energy came with the
+// speculative linearisation at delta + dx): workgroup 0 records the
+// verdict, and on acceptance the workgroups apply delta += dx (striding
+// over the nodes) and workgroup 0 writes the step's log, which leaves the
+// speculative records as the next step's linearisation.
 template <bool B>
-__global__ __launch_bounds__(SF_BLOCK) void k_trials_rest(KArg<B> ka, int n_rest) {
+__global__ __launch_bounds__(SF_BLOCK) void k_trials_rest(KArg<B> ka, int n_rest, int spec,
+                                                          int gn_iter, int pcg_iters) {
     SF_BIND(ka);
     __shared__ NodeStage S;
     __shared__ int s_go;
     if (threadIdx.x < 64) {
         double e[6];
         trial_energy_wave(a, PS_E, energy_blocks_of(a.d), e);
-        if (threadIdx.x == 0) s_go = !(e[5] <= a.sc->e_lin[5]);
+        const int acc = e[5] <= a.sc->e_lin[5];
+        if (threadIdx.x == 0) s_go = !acc;
+        if (spec && bid == 0) {
+            if (threadIdx.x == 0) a.sc->spec_acc = acc;
+            if (acc) step_record(a, gn_iter, pcg_iters, 0, e);
+        }
     }
     __syncthreads();
-    if (!s_go) return;
+    if (!s_go) {
+        if (spec) {
+            float *delta = nvec(a, NV_DELTA);
+            const float *dx = nvec(a, NV_X);
+            for (long n = (long)bid * SF_BLOCK + threadIdx.x; n < a.d.G;
+                 n += (long)nblk * SF_BLOCK) {
+                float dl[6], x[6];
+                ld6(delta, n, dl);
+                ld6(dx, n, x);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) dl[q] = dl[q] + x[q];
+                st6(delta, n, dl);
+            }
+        }
+        return;
+    }
     const int n_tiles = energy_blocks_of(a.d);
     for (int t = 1; t <= n_rest; ++t) {
         const float tau = ldexpf(1.f, -t);
@@ -1079,14 +1160,22 @@ struct RhsNode {
     float dl[6], tot[6], dn[4][6], wn[4], wi = 0.f;
     int has[4];
 
-    __device__ void load(const LevelArgs &a, int i, int j, long n) {
+    // delta + tau dx (tau != 0: a step the PCG's first kernel applies later)
+    __device__ void load(const LevelArgs &a, int i, int j, long n, float tau = 0.f) {
         const LevelDims &d = a.d;
         const float *base = nvec(a, NV_BASE);
         const float *delta = nvec(a, NV_DELTA);
+        const float *dx = nvec(a, NV_X);
         wi = a.wnode[n];
         float b[6];
         ld6(delta, n, dl);
         ld6(base, n, b);
+        if (tau != 0.f) {
+            float x[6];
+            ld6(dx, n, x);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) dl[q] = dl[q] + tau * x[q];
+        }
 #pragma unroll
         for (int q = 0; q < 6; ++q) tot[q] = b[q] + dl[q];
 #pragma unroll
@@ -1097,12 +1186,20 @@ struct RhsNode {
             const long m = has[k] ? (long)(j + dj) * d.Gx + i + di : n;
             wn[k] = has[k] ? a.wnode[m] : 0.f;
             ld6(delta, m, dn[k]);
+            if (tau != 0.f) {
+                float x[6];
+                ld6(dx, m, x);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) dn[k][q] = dn[k][q] + tau * x[q];
+            }
         }
     }
 
+    // keep_x: the PCG solution still holds a deferred step (the PCG's first
+    // kernel clears it)
     template <int S>
     __device__ void finish(const LevelArgs &a, int i, int j, long n, const float (&gdata)[6],
-                           const float (&ddata)[6]) const {
+                           const float (&ddata)[6], bool keep_x = false) const {
         const DevConst &C = *a.cst;
         float grad[6], dg[6];
 #pragma unroll
@@ -1133,7 +1230,7 @@ struct RhsNode {
             rv[q] = -grad[q];
             uv[q] = rv[q] / dg[q];
         }
-        st6(nvec(a, NV_X), n, zero);
+        if (!keep_x) st6(nvec(a, NV_X), n, zero);
         st6(nvec(a, NV_R0), n, rv);
         st6(nvec(a, NV_U), n, uv);
         st6(nvec(a, NV_DIAG), n, dg);
@@ -1145,19 +1242,27 @@ struct RhsNode {
     }
 };
 
-// Workgroup 0 of a right-hand-side kernel: the energy at the linearisation
-// point (the linearise kernel's partials) and the PCG start state.
-__device__ void rhs_level_scalars(const LevelArgs &a) {
+// The energy at the linearisation point from n partials of plane PS_E
+// (whole workgroup; valid after the call).
+__device__ void lin_energy_scalars(const LevelArgs &a, int n) {
     const DevConst &C = *a.cst;
-    const int n_lin_blocks = energy_blocks_of(a.d);
     double es[5];
     const float *p0 = a.partials + (long)PS_E * a.max_blocks;
-    block_sum_planes<5>([&](int k) { return p0 + (long)k * a.max_blocks; }, n_lin_blocks, es);
+    block_sum_planes<5>([&](int k) { return p0 + (long)k * a.max_blocks; }, n, es);
     if (threadIdx.x == 0) {
         for (int k = 0; k < 5; ++k) a.sc->e_lin[k] = es[k];
         a.sc->e_lin[5] = (double)C.w_photo * es[0] + (double)C.w_grad * es[1] +
                          (double)C.w_reg * ((double)C.w_smooth * es[2] + (double)C.w_epi * es[3] +
                                             (double)C.w_mag * es[4]);
+    }
+}
+
+// Workgroup 0 of a right-hand-side kernel: the energy at the linearisation
+// point (the linearise kernel's partials; with_energy false: formed later,
+// by the PCG's first kernel) and the PCG start state.
+__device__ void rhs_level_scalars(const LevelArgs &a, bool with_energy = true) {
+    if (with_energy) lin_energy_scalars(a, energy_blocks_of(a.d));
+    if (threadIdx.x == 0) {
         PcgHist h0;
         h0.gamma = 0.0; h0.alpha = 0.f; h0.beta = 0.f; h0.active = 1; h0.pad = 0;
         a.sc->hist[0] = h0;
@@ -1242,8 +1347,75 @@ __host__ __device__ inline void blk_offset(int k, int &di, int &dj) {
     dj = k >= 2 ? 1 : 0;
 }
 
+// Pixel records of a node tile's region at delta + tau dx, formed in place
+// of the linearisation kernel's (a rejected speculative step), and the
+// energies of the pixels this tile owns: each pixel belongs to the tile of
+// the node with the larger bilinear weight in each direction (the first on
+// a tie), so every pixel is counted once.
+template <int S>
+__device__ void relin_pixels(const LevelArgs &a, const TileGeom &g, const TileLds &L, float tau,
+                             float (&part)[5]) {
+    const LevelDims &d = a.d;
+    const float *base = nvec(a, NV_BASE);
+    const float *delta = nvec(a, NV_DELTA);
+    const float *dx = nvec(a, NV_X);
+    const int n_px = g.RX * g.RY;
+    for (int u = threadIdx.x; u < n_px; u += blockDim.x) {
+        const int rx = u % g.RX, ry = u / g.RX;
+        const int x = g.X0 + rx, y = g.Y0 + ry;
+        const Bracket bx = bracket(x, S, d.Gx), by = bracket(y, S, d.Gy);
+        float t[2][2][6];
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+                const long m = (long)(cy ? by.i1 : by.i0) * d.Gx + (cx ? bx.i1 : bx.i0);
+                float b[6], dl[6], xv[6];
+                ld6(base, m, b);
+                ld6(delta, m, dl);
+                if (tau != 0.f) ld6(dx, m, xv);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    float v = dl[q];
+                    if (tau != 0.f) v = v + tau * xv[q];
+                    t[cy][cx][q] = b[q] + v;
+                }
+            }
+        float f[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            f[q] = by.w0 * (bx.w0 * t[0][0][q] + bx.w1 * t[0][1][q]) +
+                   by.w1 * (bx.w0 * t[1][0][q] + bx.w1 * t[1][1][q]);
+        const long pix = (long)y * d.W + x;
+        PixelOut o;
+        pixel_terms<true>(a, x, y, f, a.cmask[pix] ? 1.f : 0.f, o);
+        const int ox = bx.w1 > bx.w0 ? bx.i1 : bx.i0, oy = by.w1 > by.w0 ? by.i1 : by.i0;
+        if (ox >= g.i0 && ox < g.i0 + g.txa && oy >= g.j0 && oy < g.j0 + g.tya) {
+            part[0] += o.e_photo;
+            part[1] += o.e_grad;
+        }
+        float v[27];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v[q] = o.grad[q];
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int c = r; c < 6; ++c) v[6 + gram_index(r, c)] = o.gram[tri(r, c)];
+        rec_store<27>(L.vals + (size_t)ry * L.pitch + rx * rec_pad(27), v);
+    }
+}
+
+// n_pend > 0: a speculative step precedes (the linearisation at
+// delta + dx).  If its tau = 1 was accepted, delta has moved and the
+// records are the ones to use.  Otherwise every workgroup chooses the step
+// length from the shorter trials (as k_accept does), workgroup 0 writes
+// that step's log (gn_prev), and the tile forms its records, the right-hand
+// side and the energy partials at delta + tau dx itself; delta and the
+// energy sum follow in the PCG's first kernel, which also clears dx.
 template <bool B, int S>
-__global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, TileCfg t) {
+__global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, TileCfg t,
+                                                                 int n_pend, int gn_prev,
+                                                                 int pcg_iters) {
     extern __shared__ __attribute__((aligned(16))) float lds[];
     SF_BIND(ka);
     const LevelDims &d = a.d;
@@ -1255,12 +1427,46 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, Til
     const bool mine = valid && sub == 0;
     const int i = g.i0 + nl % max(g.txa, 1), j = g.j0 + nl / max(g.txa, 1);
     const long n = (long)j * d.Gx + i;
+    __shared__ int s_k;
+    const bool redo = n_pend > 0 && !a.sc->spec_acc;
+    float tau = 0.f;
+    if (redo) {
+        if (threadIdx.x < 64) {
+            double e[6];
+            const int kacc = rest_decision(a, n_pend, e);
+            if (threadIdx.x == 0) s_k = kacc;
+            if (bid == 0) step_record(a, gn_prev, pcg_iters, kacc, e);
+        }
+        __syncthreads();
+        tau = s_k >= 0 ? ldexpf(1.f, -s_k) : 0.f;
+        if (bid == 0 && threadIdx.x == 0) {
+            a.sc->spec_tau = tau;
+            a.sc->lin_n = nblk;
+        }
+    }
     RhsNode nd;
-    if (mine) nd.load(a, i, j, n);
-    if (bid == 0) rhs_level_scalars(a);
+    if (mine && !redo) nd.load(a, i, j, n);
+    if (bid == 0) rhs_level_scalars(a, !redo);
     // a fresh count for the co-resident PCG that may follow
     if (bid == 0 && threadIdx.x == 0) a.sc->mid_count = 0u;
     tile_brackets(a, g, L);
+    if (redo) {
+        float part[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        relin_pixels<S>(a, g, L, tau, part);
+        if (mine) {
+            float pn[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+            node_energy(a, (int)n, tau, pn);
+#pragma unroll
+            for (int k = 2; k < 5; ++k) part[k] += pn[k];
+        }
+        float tot5[5];
+        block_sum<5>(part, tot5);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) a.partials[(long)(PS_E + k) * a.max_blocks + bid] = tot5[k];
+        }
+        if (mine) nd.load(a, i, j, n, tau);
+    } else
     pixels_to_lds<27>(g, L, [&](int x, int y, int, int, float (&v)[27]) {
         const long pix = (long)y * d.W + x;
         const float4 *rp = reinterpret_cast<const float4 *>(a.grad + pix * SF_GRAD_STRIDE);
@@ -1337,7 +1543,7 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, Til
         }
         if (valid && sub == kb % TPN) rec_store<21>(dst + kb * SF_GRAM_STRIDE, o);
     }
-    if (mine) nd.finish<S>(a, i, j, n, gs, sd);
+    if (mine) nd.finish<S>(a, i, j, n, gs, sd, redo);
 }
 
 // ---- preconditioned CG in single-reduction form --------------------------
@@ -1459,6 +1665,23 @@ __device__ __forceinline__ void nb_task(int sub, int q, int &k, bool &own) {
 // Every load of an iteration that does not depend on its scalars is issued
 // before the partial sums are reduced, and constants are read once, so the
 // workgroup waits for memory about once.
+// Deferred step of a rejected speculative tau = 1 (see k_rhs_blocks), for
+// the PCG's first kernel: delta += tau dx on node n with the step length
+// the right-hand-side kernel chose.
+__device__ __forceinline__ void deferred_step(const LevelArgs &a, long n, float tau) {
+    if (tau == 0.f) return;
+    float *delta = nvec(a, NV_DELTA);
+    float dl[6], x[6];
+    ld6(delta, n, dl);
+    ld6(nvec(a, NV_X), n, x);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) dl[q] = dl[q] + tau * x[q];
+    st6(delta, n, dl);
+}
+
+// force: later iterations are applied even if inactive (kernel timing);
+// in the first kernel (node-block form) it means that a speculative step
+// precedes, whose deferred part (if tau = 1 was rejected) happens here.
 template <bool B, bool FIRST, int S, int V>
 __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, TileCfg t, int i,
                                                               int gn, int force) {
@@ -1507,6 +1730,14 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     const int ti = nl % max(g.txa, 1), tj = nl / max(g.txa, 1);
     const int i_n = g.i0 + ti, j_n = g.j0 + tj;
     const long n_own = (long)j_n * d.Gx + i_n;
+    if (FIRST && S == 0 && force && !a.sc->spec_acc) {
+        if (mine) {
+            deferred_step(a, n_own, a.sc->spec_tau);
+            const float zero[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            st6(X, n_own, zero);
+        }
+        if (bid == 0) lin_energy_scalars(a, a.sc->lin_n);
+    }
     // S > 0: Gram blocks of this thread's region pixels; S = 0: the node
     // blocks of this thread's share of its node's nine block products, and
     // the halo records of the u they multiply (-1: no such neighbour)
@@ -1869,7 +2100,7 @@ __device__ __forceinline__ void small_task(int sub, int q, int &k, bool &own) {
 }
 
 template <bool B>
-__global__ __launch_bounds__(SMALL_NT) void k_pcg_small(KArg<B> ka, int n_it, int gn) {
+__global__ __launch_bounds__(SMALL_NT) void k_pcg_small(KArg<B> ka, int n_it, int gn, int pend) {
     __shared__ __attribute__((aligned(16))) float su[SF_SMALL_G * 8];
     // each lane's third block (registers hold the first two)
     __shared__ __attribute__((aligned(16))) float sb[SMALL_NT * SF_GRAM_STRIDE];
@@ -1884,6 +2115,12 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_small(KArg<B> ka, int n_it, in
     (void)nblk;
     const LevelDims &d = a.d;
     if (d.G > SF_SMALL_G) return;  // the host never launches such a level
+    if (pend && !a.sc->spec_acc) {
+        // the deferred step of a rejected speculative tau = 1 (k_rhs_blocks)
+        const float tau = a.sc->spec_tau;
+        for (int m = threadIdx.x; m < d.G; m += blockDim.x) deferred_step(a, m, tau);
+        lin_energy_scalars(a, a.sc->lin_n);
+    }
     const int log_index = gn >= 0 ? a.log_base + gn : -1;
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
@@ -2152,7 +2389,7 @@ __device__ bool mid_barrier(DevScalars *sc, unsigned target, int spin_limit, int
 #define MID_SU (SF_SMALL_G + 2 * (SF_MID_GX + 1))
 
 __global__ __launch_bounds__(SMALL_NT) void k_pcg_mid(LevelArgs a, int n_it, int gn,
-                                                      int spin_limit) {
+                                                      int spin_limit, int pend) {
     __shared__ __attribute__((aligned(16))) float su[MID_SU * 8];
     __shared__ __attribute__((aligned(16))) float sb[SMALL_NT * SF_GRAM_STRIDE];
     __shared__ __attribute__((aligned(16))) float sx[(SMALL_NT + 2) * 8];
@@ -2163,6 +2400,12 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_mid(LevelArgs a, int n_it, int
     const int n_begin = wg * SF_SMALL_G, n_end = min(n_begin + SF_SMALL_G, d.G);
     // nodes whose u this workgroup holds in LDS: its own and one row + 1 beyond
     const int h_begin = max(n_begin - d.Gx - 1, 0), h_end = min(n_end + d.Gx + 1, d.G);
+    if (pend && !a.sc->spec_acc) {
+        // the deferred step of a rejected speculative tau = 1 (k_rhs_blocks)
+        const float tau = a.sc->spec_tau;
+        for (int m = n_begin + threadIdx.x; m < n_end; m += blockDim.x) deferred_step(a, m, tau);
+        if (wg == 0) lin_energy_scalars(a, a.sc->lin_n);
+    }
     const int log_index = gn >= 0 ? a.log_base + gn : -1;
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -2427,24 +2670,15 @@ __global__ __launch_bounds__(SF_BLOCK) void k_accept(KArg<B> ka, int n_trials, i
                                                      int pcg_iters) {
     SF_BIND(ka);
     __shared__ int s_k;
-    __shared__ double s_e[6];
-    const int log_index = gn_iter >= 0 ? a.log_base + gn_iter : -1;
-    const int nb_last = node_blocks(a.d);
-    const DevScalars *sc = a.sc;
-    const double e0 = sc->e_lin[5];
+    const double e0 = a.sc->e_lin[5];
     if (threadIdx.x < 64) {
         // the first trial with E_trial <= E, from the trial kernels' partials
         double e[6];
         trial_energy_wave(a, PS_E, energy_blocks_of(a.d), e);
         int kacc = e[5] <= e0 ? 0 : -1;
-        for (int t = 1; t < n_trials && kacc < 0; ++t) {
-            trial_energy_wave(a, PS_TRIAL + 5 * (t - 1), rest_blocks_of(a.d), e);
-            if (e[5] <= e0) kacc = t;
-        }
-        if (threadIdx.x == 0) {
-            s_k = kacc;
-            for (int k = 0; k < 6; ++k) s_e[k] = e[k];
-        }
+        if (kacc < 0) kacc = rest_decision(a, n_trials, e);
+        if (threadIdx.x == 0) s_k = kacc;
+        if (bid == 0) step_record(a, gn_iter, pcg_iters, kacc, e);
     }
     __syncthreads();
     const int kacc = s_k;
@@ -2458,36 +2692,6 @@ __global__ __launch_bounds__(SF_BLOCK) void k_accept(KArg<B> ka, int n_trials, i
 #pragma unroll
         for (int q = 0; q < 6; ++q) dl[q] = dl[q] + tau * x[q];
         st6(delta, n, dl);
-    }
-    if (bid == 0) {
-        double rr = 0.0;
-        if (log_index >= 0) {
-            const float *rrp = a.partials +
-                               (long)(((pcg_iters & 1) ? PS_PCG1 : PS_PCG0) + 2) * a.max_blocks;
-            rr = block_sum_partials(rrp, nb_last);
-        }
-        if (threadIdx.x == 0) {
-            if (kacc >= 0)
-                for (int k = 0; k < 6; ++k) a.sc->e_trial[kacc][k] = s_e[k];
-            if (log_index >= 0) {
-                DevLog &Lg = a.log[log_index];
-                Lg.level = a.level;
-                Lg.gn_iter = gn_iter;
-                Lg.energy = e0;
-                Lg.e_photo = sc->e_lin[0];
-                Lg.e_grad = sc->e_lin[1];
-                Lg.e_smooth = sc->e_lin[2];
-                Lg.e_epi = sc->e_lin[3];
-                Lg.e_mag = sc->e_lin[4];
-                Lg.energy_after = kacc >= 0 ? s_e[5] : e0;
-                Lg.tau = tau;
-                Lg.pcg_iters = pcg_iters;
-                // an inactive last iteration left r unchanged
-                const bool same = !sc->hist[pcg_iters].active && pcg_iters >= 2;
-                Lg.pcg_res[pcg_iters - 1] = same ? Lg.pcg_res[pcg_iters - 2] : (float)sqrt(rr);
-                Lg.n_valid = sc->n_valid;
-            }
-        }
     }
 }
 
@@ -3225,13 +3429,19 @@ void launch_linearize(hipStream_t st, const Launch &L) {
     go(st, L, en_blocks, k_energy<true, true>, k_energy<false, true>, SF_BLOCK, 0, 0.f);
 }
 
+void launch_spec_linearize(hipStream_t st, const Launch &L) {
+    go(st, L, en_blocks, k_energy<true, true>, k_energy<false, true>, SF_BLOCK, 0, 1.f);
+}
+
 void launch_trial0(hipStream_t st, const Launch &L) {
     go(st, L, en_blocks, k_energy<true, false>, k_energy<false, false>, SF_BLOCK, 0, 1.f);
 }
 
-void launch_trials_rest(hipStream_t st, const Launch &L, int n_rest) {
+void launch_trials_rest(hipStream_t st, const Launch &L, int n_rest, bool spec, int gn,
+                        int pcg_iters) {
     auto nb = [](const LevelArgs &a) { return rest_blocks_of(a.d); };
-    go(st, L, nb, k_trials_rest<true>, k_trials_rest<false>, SF_BLOCK, 0, n_rest);
+    go(st, L, nb, k_trials_rest<true>, k_trials_rest<false>, SF_BLOCK, 0, n_rest, spec ? 1 : 0,
+       gn, pcg_iters);
 }
 
 void launch_rhs(hipStream_t st, const Launch &L, const TileCfg &t) {
@@ -3273,14 +3483,15 @@ void launch_rhs(hipStream_t st, const Launch &L, const TileCfg &t) {
 // when `skip_small` (their PCG runs in launch_pcg_small).
 static bool small_frame(const LevelArgs &a) { return a.d.G <= SF_SMALL_G; }
 
-void launch_pcg_first(hipStream_t st, const Launch &L, const TileCfg &t, bool skip_small) {
+void launch_pcg_first(hipStream_t st, const Launch &L, const TileCfg &t, bool skip_small,
+                      bool pend) {
     auto nb = [t, skip_small](const LevelArgs &a) {
         return skip_small && small_frame(a) ? 0 : node_tiles_of(a.d, t);
     };
     const int s = L.host[0].s;
 #define PCG0(S, V)                                                                            \
     go(st, L, nb, k_pcg<true, true, S, V>, k_pcg<false, true, S, V>, TileTraits<S, V>::NT,    \
-       node_tile_lds_bytes(t, S, 6), t, 0, -1, 0)
+       node_tile_lds_bytes(t, S, 6), t, 0, -1, pend ? 1 : 0)
     SF_PCG_SWITCH(s, t.v, PCG0)
 #undef PCG0
 }
@@ -3298,27 +3509,27 @@ void launch_pcg_iter(hipStream_t st, const Launch &L, const TileCfg &t, int iter
 #undef PCGI
 }
 
-void launch_rhs_blocks(hipStream_t st, const Launch &L) {
+void launch_rhs_blocks(hipStream_t st, const Launch &L, int n_pend, int gn_prev, int pcg_iters) {
     const int s = L.host[0].s;
     const TileCfg t = pick_blk_tile(s);
     auto nb = [t](const LevelArgs &a) { return node_tiles_of(a.d, t); };
 #define BLK(S)                                                                            \
     go(st, L, nb, k_rhs_blocks<true, S>, k_rhs_blocks<false, S>, BlkTraits<S>::NT,        \
-       node_tile_lds_bytes(t, S, 27), t)
+       node_tile_lds_bytes(t, S, 27), t, n_pend, gn_prev, pcg_iters)
     SF_STRIDE_SWITCH(s, BLK)
 #undef BLK
 }
 
 // One workgroup per small frame with a wavefront per 21 of its nodes (the
 // largest small frame of the launch sets the count).
-void launch_pcg_small(hipStream_t st, const Launch &L, int n_it, int gn) {
+void launch_pcg_small(hipStream_t st, const Launch &L, int n_it, int gn, bool pend) {
     auto one = [](const LevelArgs &a) { return small_frame(a) ? 1 : 0; };
     int gmax = 0;
     for (int f = 0; f < L.nf; ++f)
         if (small_frame(L.host[f])) gmax = gmax > L.host[f].d.G ? gmax : L.host[f].d.G;
     if (gmax == 0) return;
     const int threads = 64 * ((gmax + SMALL_NPW - 1) / SMALL_NPW);
-    go(st, L, one, k_pcg_small<true>, k_pcg_small<false>, threads, 0, n_it, gn);
+    go(st, L, one, k_pcg_small<true>, k_pcg_small<false>, threads, 0, n_it, gn, pend ? 1 : 0);
 }
 
 bool mid_level(const LevelDims &d) {
@@ -3339,14 +3550,15 @@ bool mid_fits_device() {
     return (long)per_cu * prop.multiProcessorCount >= SF_MID_WG;
 }
 
-void launch_pcg_mid(hipStream_t st, const Launch &L, int n_it, int gn) {
+void launch_pcg_mid(hipStream_t st, const Launch &L, int n_it, int gn, bool pend) {
     const LevelArgs &a = L.host[0];
     const int P = (a.d.G + SF_SMALL_G - 1) / SF_SMALL_G;
     // about a second of polling before a wait gives up; SF_MID_SPIN_LIMIT
     // overrides it (tests force the give-up path with a tiny limit)
     int spin_limit = 1 << 21;
     if (const char *e = getenv("SF_MID_SPIN_LIMIT")) spin_limit = atoi(e);
-    hipLaunchKernelGGL(k_pcg_mid, dim3(P), dim3(SMALL_NT), 0, st, a, n_it, gn, spin_limit);
+    hipLaunchKernelGGL(k_pcg_mid, dim3(P), dim3(SMALL_NT), 0, st, a, n_it, gn, spin_limit,
+                       pend ? 1 : 0);
 }
 
 void launch_pcg_last(hipStream_t st, const Launch &L, const TileCfg &t, int iter, int gn,

@@ -207,6 +207,63 @@ def test_step_control_parity(apply):
         g.close()
 
 
+@pytest.mark.parametrize("level,apply", [(1, 1), (1, 2), (0, 2), (0, 3)])
+def test_speculative_step_parity(level, apply):
+    """The solve's speculative step control (SF_STAGE_SPEC_STEP: the
+    linearisation at delta + dx, the shorter trials, then the next step's
+    right-hand side and PCG) against the oracle's rule: delta moves by
+    tau dx for the first acceptable tau (1, a shorter step, or none), and
+    the energy, diag(H) and PCG solution that follow are the oracle's at
+    the new delta.  A shorter step or none is the path where the
+    right-hand-side kernel forms the pixel records itself and the PCG's
+    first kernel moves delta.  Level 1 of 104 x 78 at stride 4 takes the
+    one-workgroup PCG in apply_mode 2, level 0 the multi-kernel (2) or the
+    co-resident (3) one."""
+    g, imgs, calib, p = _stage_case(W=104, H=78, grid_stride=4, apply_mode=apply,
+                                    max_backtracks=4)
+    sf = g.sf
+    try:
+        g.run(sf.SF_STAGE_LEVEL_INIT, level)
+        ls, _ = _oracle_level(imgs, calib, p, level)
+        delta = np.random.default_rng(4).normal(scale=0.3, size=(6, ls.grid.G))
+        g.write(sf.SF_DBG_DELTA, level, delta.astype(np.float32))
+        delta = g.read(sf.SF_DBG_DELTA, level).reshape(6, -1).astype(np.float64)
+        grad, Hm = O.linearize(ls, delta, p)
+        step = O.pcg(Hm, -grad, 40).reshape(6, -1)
+        e0 = O.energy(ls, delta, p)["total"]
+        taus = [2.0 ** -k for k in range(5)]
+        seen = set()
+        for scale in (1.0, 12.0, 40.0, -1.0):
+            dx = (scale * step).astype(np.float32)
+            g.write(sf.SF_DBG_DELTA, level, delta.astype(np.float32))
+            g.run(sf.SF_STAGE_LINEARIZE, level)
+            g.write(sf.SF_DBG_DX, level, dx)
+            g.run(sf.SF_STAGE_SPEC_STEP, level)
+            got = g.read(sf.SF_DBG_DELTA, level).reshape(6, -1).astype(np.float64)
+            et = [O.energy(ls, delta + t * dx.astype(np.float64), p)["total"] for t in taus]
+            if min(abs(e - e0) for e in et) < 1e-4 * abs(e0):
+                continue
+            tau = next((t for t, e in zip(taus, et) if e <= e0), 0.0)
+            want = delta + tau * dx.astype(np.float64)
+            np.testing.assert_allclose(got, want, rtol=0, atol=1e-5 * (1 + np.abs(want).max()))
+            # the next step, at the new delta as the GPU holds it
+            e = O.energy(ls, got, p)
+            eg = g.read(sf.SF_DBG_ENERGY, level)
+            for k, name in enumerate(("photo", "grad", "smooth", "epi", "mag", "total")):
+                assert eg[k] == pytest.approx(e[name], rel=2e-5, abs=1e-6), (scale, name)
+            grad2, H2 = O.linearize(ls, got, p)
+            _, kink_nodes = _kink_pixels(ls, got)
+            nodes6 = np.tile(~kink_nodes, 6)
+            D = g.read(sf.SF_DBG_DIAG, level)
+            np.testing.assert_allclose(D[nodes6], H2.diagonal()[nodes6], rtol=2e-4)
+            dxn = g.read(sf.SF_DBG_DX, level)
+            assert rel_err(dxn, O.pcg(H2, -grad2, p.pcg_iters)) < 5e-3, scale
+            seen.add("full" if tau == 1.0 else ("none" if tau == 0.0 else "short"))
+        assert seen == {"full", "short", "none"}, seen
+    finally:
+        g.close()
+
+
 def _solve_parity(imgs, calib, prm, e_tol=1e-4, f_tol=0.02):
     p = oracle_params(**prm)
     rec = []
