@@ -627,7 +627,7 @@ def main():
                     help="0: matrix-free products from the pixel records, "
                          "1: per-node blocks, 2: per-node blocks and one-workgroup "
                          "PCG at levels of at most 336 nodes, 3: 2 plus the co-resident "
-                         "PCG at mid-size levels (single frames)")
+                         "tiled PCG at the larger levels (single frames)")
     ap.add_argument("--tile-mode", type=int, default=1,
                     help="PCG tile shapes: 0 = default, 1 = autotuned (timed on the "
                          "warm-up solve), 2 / 3 / 4 = the alternative shapes")

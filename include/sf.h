@@ -88,14 +88,16 @@ typedef struct {
  *                  blocks; 120 floats of extra workspace per node); 2 = as
  *                  1, and levels with at most 336 nodes run all PCG
  *                  iterations of a Gauss-Newton step in one workgroup;
- *                  3 = as 2, and in single-frame solves levels of 337 to
- *                  10752 nodes with rows of at most 128 nodes run all PCG
- *                  iterations in ceil(G / 336) co-resident workgroups with
- *                  a grid barrier per iteration (bounded waits: if a wait
- *                  gives up, sf_get_log reports SF_ERR_STATE, the solve is
- *                  undefined and the context falls back to per-iteration
- *                  kernels); batches, and devices on which 32 such
- *                  workgroups cannot be resident at once, run mode 3 as 2
+ *                  3 = as 2, and in single-frame solves every level with
+ *                  more than 336 nodes whose 12 x 7-node tiles (at most
+ *                  256) the device holds at once runs all PCG iterations
+ *                  of a Gauss-Newton step in one launch, one workgroup
+ *                  per tile, its blocks in registers, the tiles
+ *                  exchanging tagged partial sums and border records
+ *                  (bounded waits: if a wait gives up, sf_get_log reports
+ *                  SF_ERR_STATE, the solve is undefined and the context
+ *                  falls back to per-iteration kernels); other levels and
+ *                  batches run as in mode 2
  *  temporal        1 = video mode (Sec. 5.3): every sf_solve after the first
  *                  starts each level's delta from the previous sf_solve of
  *                  the context, transferred by its motion flow under
@@ -456,14 +458,19 @@ sf_status sf_debug_run(sf_ctx *ctx, int stage, int level);
  *                       apply_mode >= 1 together with the per-node blocks)
  *  SF_KERNEL_BLOCKS     right-hand side and per-node blocks (apply_mode >= 1
  *                       only; the same kernel as SF_KERNEL_RHS there)
- * The PCG kernels run forced active with fixed step lengths. 
+ *  SF_KERNEL_PCG_TILE   all pcg_iters iterations of the level in the
+ *                       co-resident tiled PCG (apply_mode 3, levels it
+ *                       takes; as in the solve, not forced active)
+ * The per-iteration PCG kernels run forced active with fixed step
+ * lengths. 
  * Errors: SF_ERR_STATE before the first solve, SF_ERR_INVALID_ARG. */
 enum {
     SF_KERNEL_APPLY = 0,
     SF_KERNEL_LINEARIZE = 1,
     SF_KERNEL_UPDATE = 2,
     SF_KERNEL_RHS = 3,
-    SF_KERNEL_BLOCKS = 4
+    SF_KERNEL_BLOCKS = 4,
+    SF_KERNEL_PCG_TILE = 5
 };
 sf_status sf_time_kernel(sf_ctx *ctx, int kernel, int level, int reps,
                          float *avg_ms);

@@ -19,7 +19,7 @@
 namespace {
 
 // Device buffers of one frame (SF_FRAME_BUFS sub-allocations of the pool).
-#define SF_FRAME_BUFS 16
+#define SF_FRAME_BUFS 17
 struct FrameBuf {
     int W = 0, H = 0, L = 0;
     LevelDims lv[SF_MAX_LEVELS]{};
@@ -36,6 +36,7 @@ struct FrameBuf {
     unsigned char *occ = nullptr;  // occlusion map of the level being solved (N0)
     float *occ_pos = nullptr;      // its scratch: 10 planes of N_1 ...
     unsigned *occ_zb = nullptr;    // ... and 4 z-buffers of N_1
+    unsigned long long *xtag = nullptr;  // co-resident tiled PCG exchange
     float *partials = nullptr;
     DevConst *cst = nullptr;
     DevScalars *sc = nullptr;
@@ -101,6 +102,7 @@ struct Plan {
     CnnRun cnn;              // learned initialiser
     const CnnNet *net = nullptr;
     bool no_mid = false;     // co-resident PCG switched off after a failed wait
+    int pt_cap = 0;          // co-resident tiles the device holds (0: not used)
     bool external = false;   // pool is caller-provided workspace (not freed)
     size_t pool_bytes = 0;
 };
@@ -271,8 +273,9 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
     P.prm = prm;
     P.net = net;
     P.batched = batched;
-    // co-residency of the mid-level PCG's workgroups, checked once per plan
-    P.no_mid = prm.apply_mode == 3 && !batched && !mid_fits_device();
+    // tiles of the co-resident PCG the device holds at once (apply_mode 3,
+    // single frames), checked once per plan
+    P.pt_cap = prm.apply_mode == 3 && !batched ? pt_capacity() : 0;
     P.nf = (int)levels.size();
     P.shape = shape;
     const int st = prm.grid_stride;
@@ -344,7 +347,8 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
                                prm.illum ? sizeof(float) * 3 * (size_t)F.N0 : 0,
                                occ ? (size_t)F.N0 : 0,
                                occ ? sizeof(float) * 10 * n1 : 0,
-                               occ ? sizeof(unsigned) * 4 * n1 : 0};
+                               occ ? sizeof(unsigned) * 4 * n1 : 0,
+                               P.pt_cap > 0 ? 8 * pt_xtag_words(F.G0) : 0};
         for (int k = 0; k < SF_FRAME_BUFS; ++k) {
             o[f * SF_FRAME_BUFS + k] = off;
             off += align_up(sz[k]);
@@ -411,6 +415,8 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
             F.occ_zb = (unsigned *)(P.pool + o[f * SF_FRAME_BUFS + 15]);
         }
         F.partials = (float *)(P.pool + o[f * SF_FRAME_BUFS + 6]);
+        F.xtag = P.pt_cap > 0 ? (unsigned long long *)(P.pool + o[f * SF_FRAME_BUFS + 16])
+                              : nullptr;
         F.sc = (DevScalars *)(P.pool + o[f * SF_FRAME_BUFS + 7]);
         F.log = (DevLog *)(P.pool + o[f * SF_FRAME_BUFS + 8]);
         F.cst = P.dcst + f;
@@ -520,6 +526,7 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
             }
             a.partials = F.partials;
             a.max_blocks = F.max_blocks;
+            a.xtag = F.xtag;
             a.cst = F.cst;
             a.sc = F.sc;
             a.log = F.log;
@@ -596,6 +603,16 @@ void enqueue_linearize(const Plan &P, hipStream_t st, int l) {
         launch_rhs(st, L, P.tile);
 }
 
+// Levels of a single frame that the co-resident tiled PCG takes (apply_mode
+// 3): more nodes than the one-workgroup kernel, and tiles the device holds
+// at once.
+bool pt_level(const Plan &P, int l) {
+    if (P.prm.apply_mode != 3 || P.pt_cap <= 0 || P.no_mid || P.batched) return false;
+    const LevelDims &d = P.fr[0].lv[l];
+    const int cap = P.pt_cap < SF_PT_MAXWG ? P.pt_cap : SF_PT_MAXWG;
+    return d.G > SF_SMALL_G && pt_tiles(d) <= cap;
+}
+
 // With apply_mode 2 the frames of a slot with at most SF_SMALL_G nodes run
 // their PCG in one workgroup each and the others in the multi-kernel form,
 // so a frame takes the same path alone or in any batch.  apply_mode 3
@@ -604,8 +621,8 @@ void enqueue_linearize(const Plan &P, hipStream_t st, int l) {
 void enqueue_pcg(const Plan &P, hipStream_t st, int l, int gn, bool pend = false) {
     const Launch L = slot(P, l);
     const int n = P.prm.pcg_iters;
-    if (P.prm.apply_mode == 3 && !P.batched && !P.no_mid && mid_level(L.host[0].d)) {
-        launch_pcg_mid(st, L, n, gn, pend);
+    if (pt_level(P, l)) {
+        launch_pcg_tile(st, L, n, gn, pend);
         return;
     }
     const bool sm = P.prm.apply_mode >= 2;
@@ -928,10 +945,12 @@ sf_status time_kernel(hipStream_t st, const Plan &P, int kernel, int level, int 
                     launch_rhs(st, L, P.tile);
                 break;
             case SF_KERNEL_BLOCKS: launch_rhs_blocks(st, L); break;
+            case SF_KERNEL_PCG_TILE: launch_pcg_tile(st, L, P.prm.pcg_iters, -1); break;
         }
     };
-    if (kernel < SF_KERNEL_APPLY || kernel > SF_KERNEL_BLOCKS ||
-        (kernel == SF_KERNEL_BLOCKS && P.prm.apply_mode < 1)) {
+    if (kernel < SF_KERNEL_APPLY || kernel > SF_KERNEL_PCG_TILE ||
+        (kernel == SF_KERNEL_BLOCKS && P.prm.apply_mode < 1) ||
+        (kernel == SF_KERNEL_PCG_TILE && !pt_level(P, level))) {
         s = SF_ERR_INVALID_ARG;
     } else {
         // the PCG kernels are forced active with fixed step lengths so that

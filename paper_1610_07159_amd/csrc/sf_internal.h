@@ -114,7 +114,7 @@ struct DevScalars {
     int init_used;     // the learned initialisation was kept
     int n_valid;
     int have_prev;     // the temporal state holds a finished solve
-    unsigned mid_count;  // arrivals at the co-resident PCG's grid barriers
+    unsigned pt_epoch;   // launches of the co-resident tiled PCG (its tags)
     int mid_fail;        // a co-resident PCG gave up waiting (sticky)
     // speculative steps: tau = 1 was accepted (the shorter-trial kernel's
     // verdict); otherwise the step length the right-hand-side kernel chose
@@ -188,6 +188,8 @@ struct LevelArgs {
     float *blk;            // per-node blocks (SF_BLK_STRIDE), node-block mode
     float *partials;       // per-workgroup partial sums
     int max_blocks;        // stride of the partial-sum planes
+    unsigned long long *xtag;  // tagged exchange of the co-resident tiled PCG
+                               // (nullptr: not used)
     const DevConst *cst;
     DevScalars *sc;
     DevLog *log;
@@ -257,16 +259,20 @@ void launch_pcg_last(hipStream_t st, const Launch &L, const TileCfg &t,
 // iter / last for them)
 #define SF_SMALL_G 336
 void launch_pcg_small(hipStream_t st, const Launch &L, int n_it, int gn, bool pend = false);
-// all pcg_iters iterations of a single frame's level in a few co-resident
-// workgroups of SF_SMALL_G nodes each, with grid barriers between the
-// iterations (apply_mode 3, levels with more than SF_SMALL_G and at most
-// SF_MID_G nodes and rows of at most SF_MID_GX nodes)
-#define SF_MID_WG 32
-#define SF_MID_G (SF_SMALL_G * SF_MID_WG)
-#define SF_MID_GX 128
-bool mid_level(const LevelDims &d);
-bool mid_fits_device();
-void launch_pcg_mid(hipStream_t st, const Launch &L, int n_it, int gn, bool pend = false);
+// all pcg_iters iterations of a single frame's level in one launch of
+// co-resident tiles of SF_PT_TW x SF_PT_TH nodes that exchange tagged
+// partial sums and border records (apply_mode 3; levels with more than
+// SF_SMALL_G nodes and at most min(SF_PT_MAXWG, the device's co-resident
+// capacity) tiles)
+#define SF_PT_TW 12
+#define SF_PT_TH 7
+#define SF_PT_MAXWG 256
+int pt_tiles(const LevelDims &d);
+// tiles of k_pcg_tile the current device holds at once
+int pt_capacity();
+// 64-bit words of a frame's exchange buffer (G0 nodes at level 0)
+size_t pt_xtag_words(long G0);
+void launch_pcg_tile(hipStream_t st, const Launch &L, int n_it, int gn, bool pend = false);
 void launch_accept(hipStream_t st, const Launch &L, int n_trials, int gn,
                    int pcg_iters);
 void launch_finish_level(hipStream_t st, const Launch &L);

@@ -1285,8 +1285,6 @@ __global__ __launch_bounds__(TileTraits<S>::NT) void k_rhs(KArg<B> ka, TileCfg t
     RhsNode nd;
     if (mine) nd.load(a, i, j, n);
     if (bid == 0) rhs_level_scalars(a);
-    // a fresh count for the co-resident PCG that may follow
-    if (bid == 0 && threadIdx.x == 0) a.sc->mid_count = 0u;
     tile_brackets(a, g, L);
     pixels_to_lds<12>(g, L, [&](int x, int y, int, int, float (&v)[12]) {
         const long pix = (long)y * d.W + x;
@@ -1447,8 +1445,6 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, Til
     RhsNode nd;
     if (mine && !redo) nd.load(a, i, j, n);
     if (bid == 0) rhs_level_scalars(a, !redo);
-    // a fresh count for the co-resident PCG that may follow
-    if (bid == 0 && threadIdx.x == 0) a.sc->mid_count = 0u;
     tile_brackets(a, g, L);
     if (redo) {
         float part[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
@@ -2344,82 +2340,173 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_small(KArg<B> ka, int n_it, in
     }
 }
 
-// ---- PCG of a mid-size level in a few co-resident workgroups ----------------
+// ---- PCG of a level in co-resident tiles, tagged exchange --------------------
 //
-// apply_mode 3, single frames: a level with more than SF_SMALL_G nodes (and
-// at most SF_MID_G, rows of at most SF_MID_GX nodes) runs all PCG
-// iterations of a Gauss-Newton step in ceil(G / SF_SMALL_G) workgroups of
-// the one-workgroup layout (three lanes per node, blocks in registers and
-// LDS).  Workgroup w owns the nodes [w M, (w + 1) M) in row-major order,
-// M = SF_SMALL_G; the block products need u one node row (plus one) beyond
-// that range, which the workgroup forms itself from the r, w, s and diag
-// records its neighbours publish, as the multi-kernel form does for a
-// tile's halo.  One grid barrier per iteration replaces the kernel
-// boundary: after publishing its boundary records and its three partial
-// sums, a workgroup arrives on a counter (device-scope fence, atomic add)
-// and waits until all have arrived; every wait is bounded, and a
-// workgroup that gives up raises a sticky flag, which ends the waits of the
-// others at once and which the host reports.  The iterates are those of the
-// single-reduction PCG (the partial sums are reduced in another order than
-// in the multi-kernel form).
+// apply_mode 3, single frames: a level with more than SF_SMALL_G nodes whose
+// tiles all fit on the device at once runs all PCG iterations of a
+// Gauss-Newton step in one launch, one workgroup per tile of SF_PT_TW x
+// SF_PT_TH nodes (four wavefronts, three lanes per node as in the
+// one-workgroup kernel).  Each lane keeps its three block products'
+// blocks in registers for all iterations.  Between passes the tiles
+// exchange only what the next pass needs: their three partial sums and,
+// for the nodes on the tile border, r, w and s of the pass, from which a
+// neighbour rebuilds the u of its halo (as the multi-kernel form does).
+// Every value travels as one 64-bit word, the float and a tag (the
+// launch's epoch and the pass), stored and loaded with relaxed agent-scope
+// atomics: a reader polls until the tag it expects is there, so no fence,
+// counter or barrier is needed.  Two parity slots per pass suffice: a tile
+// that writes pass p + 2 has read every tile's pass p + 1 sums, so each
+// reader of pass p has finished.  The epoch advances by one per launch
+// (tile 0 moves it once every tile has published its last word, so every
+// tile has read it); a word a launch waits for was last written by an
+// earlier launch of the same level, whose tags differ unless 2^24 launches
+// lie between them.  Every wait is bounded, and a tile that
+// gives up raises the sticky flag the host reports.  The iterates are those
+// of the single-reduction PCG (the partial sums are reduced per tile).
 
-// Waits at the grid barrier until `target` arrivals; false if it gave up.
-__device__ bool mid_barrier(DevScalars *sc, unsigned target, int spin_limit, int &s_stop) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        atomicAdd(&sc->mid_count, 1u);
-        int spins = 0, ok = 1;
-        while (__hip_atomic_load(&sc->mid_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-               target) {
-            if (++spins > spin_limit ||
-                __hip_atomic_load(&sc->mid_fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                atomicExch(&sc->mid_fail, 1);
-                ok = 0;
-                break;
-            }
-        }
-        __threadfence();
-        s_stop = !ok;
+#define PT_N (SF_PT_TW * SF_PT_TH)
+#define PT_NT (64 * (PT_N / SMALL_NPW))
+#define PT_HX (SF_PT_TW + 2)
+#define PT_HY (SF_PT_TH + 2)
+#define PT_PER_LANE (SF_PT_MAXWG / 64)
+static_assert(PT_N % SMALL_NPW == 0, "whole wavefronts of three-lane nodes");
+static_assert(SF_PT_MAXWG % 64 == 0, "lane-strided partial slots");
+static_assert(2 * (SF_PT_TW + 2) + 2 * SF_PT_TH <= 64, "halo nodes in wavefront 0");
+
+// Tagged words: the float in the high half, the tag in the low half.
+__device__ __forceinline__ void tag_store(unsigned long long *p, float v, unsigned tag) {
+    const unsigned long long w = ((unsigned long long)__float_as_uint(v) << 32) | tag;
+    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long tag_load(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float tag_value(unsigned long long w) {
+    return __uint_as_float((unsigned)(w >> 32));
+}
+__device__ __forceinline__ bool wave_any(bool p) {
+    return __builtin_amdgcn_readfirstlane((unsigned)(__ballot(p) != 0ull)) != 0u;
+}
+// A give-up: raise the flag; true if this wait (or another tile) gave up.
+__device__ __forceinline__ bool wait_over(DevScalars *sc, int &spins, int spin_limit) {
+    if (++spins > spin_limit ||
+        __hip_atomic_load(&sc->mid_fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        atomicExch(&sc->mid_fail, 1);
+        return true;
     }
-    __syncthreads();
-    return !s_stop;
+    return false;
 }
 
-#define MID_SU (SF_SMALL_G + 2 * (SF_MID_GX + 1))
+// Exchange-buffer layout (64-bit words): the partial sums of each parity
+// (3 planes) and the final ||r||^2 partials, each in PT_REP replicas (a
+// tile reads replica wg % PT_REP, so that the tiles' polls spread over
+// several lines instead of all meeting on one), then per parity and node
+// the 18 words r, w, s of its border record.
+#define PT_REP 8
+__device__ __forceinline__ unsigned long long *pt_part(const LevelArgs &a, int par, int k,
+                                                      int rep) {
+    return a.xtag + (((size_t)par * 3 + k) * PT_REP + rep) * SF_PT_MAXWG;
+}
+__device__ __forceinline__ unsigned long long *pt_final(const LevelArgs &a, int rep) {
+    return a.xtag + ((size_t)6 * PT_REP + rep) * SF_PT_MAXWG;
+}
+__device__ __forceinline__ unsigned long long *pt_rec(const LevelArgs &a, int par, long n) {
+    return a.xtag + (size_t)7 * PT_REP * SF_PT_MAXWG + ((size_t)par * a.G0 + n) * 18;
+}
 
-__global__ __launch_bounds__(SMALL_NT) void k_pcg_mid(LevelArgs a, int n_it, int gn,
-                                                      int spin_limit, int pend) {
-    __shared__ __attribute__((aligned(16))) float su[MID_SU * 8];
-    __shared__ __attribute__((aligned(16))) float sb[SMALL_NT * SF_GRAM_STRIDE];
-    __shared__ __attribute__((aligned(16))) float sx[(SMALL_NT + 2) * 8];
-    __shared__ float red[SMALL_NT / 64][3];
-    __shared__ int s_stop;
-    const LevelDims &d = a.d;
-    const int Pw = gridDim.x, wg = blockIdx.x;
-    const int n_begin = wg * SF_SMALL_G, n_end = min(n_begin + SF_SMALL_G, d.G);
-    // nodes whose u this workgroup holds in LDS: its own and one row + 1 beyond
-    const int h_begin = max(n_begin - d.Gx - 1, 0), h_end = min(n_end + d.Gx + 1, d.G);
-    if (pend && !a.sc->spec_acc) {
-        // the deferred step of a rejected speculative tau = 1 (k_rhs_blocks)
-        const float tau = a.sc->spec_tau;
-        for (int m = n_begin + threadIdx.x; m < n_end; m += blockDim.x) deferred_step(a, m, tau);
-        if (wg == 0) lin_energy_scalars(a, a.sc->lin_n);
+// One wavefront's poll: the K planes' sums over the P tiles (lane-strided
+// loads, polled until every tag matches, summed in double in a fixed
+// order: the same in every tile) and, in lanes with a halo node (rec not
+// null), the record words `need_h` of that node, all issued together in
+// each round; false if a wait gave up (alike in every lane).
+template <int K>
+__device__ bool pt_poll(const LevelArgs &a, unsigned long long *const (&src)[K], int P,
+                        unsigned tag, const unsigned long long *rec, unsigned need_h,
+                        float (&hv)[18], int spin_limit, double (&out)[K]) {
+    const int lane = threadIdx.x & 63;
+    float v[PT_PER_LANE][K];
+    unsigned need = 0;
+#pragma unroll
+    for (int u = 0; u < PT_PER_LANE; ++u)
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            v[u][q] = 0.f;
+            if (lane + 64 * u < P) need |= 1u << (u * K + q);
+        }
+    if (!rec) need_h = 0;
+    int spins = 0;
+    while (true) {
+#pragma unroll
+        for (int u = 0; u < PT_PER_LANE; ++u)
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                if (need & (1u << (u * K + q))) {
+                    const unsigned long long w = tag_load(src[q] + lane + 64 * u);
+                    if ((unsigned)w == tag) {
+                        v[u][q] = tag_value(w);
+                        need &= ~(1u << (u * K + q));
+                    }
+                }
+            }
+#pragma unroll
+        for (int q = 0; q < 18; ++q) {
+            if (need_h & (1u << q)) {
+                const unsigned long long w = tag_load(rec + q);
+                if ((unsigned)w == tag) {
+                    hv[q] = tag_value(w);
+                    need_h &= ~(1u << q);
+                }
+            }
+        }
+        if (!wave_any(need != 0 || need_h != 0)) break;
+        if (__builtin_amdgcn_readfirstlane(wait_over(a.sc, spins, spin_limit) ? 1u : 0u))
+            return false;
     }
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < PT_PER_LANE; ++u) acc += (double)v[u][q];
+        out[q] = uniform_d(group_sum<double>(acc, 64));
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(PT_NT) void k_pcg_tile(LevelArgs a, int n_it, int gn,
+                                                    int spin_limit, int pend) {
+    __shared__ __attribute__((aligned(16))) float su[PT_HX * PT_HY * 8];
+    __shared__ __attribute__((aligned(16))) float sx[(PT_NT + 2) * 8];
+    __shared__ float red[PT_NT / 64][3];
+    __shared__ double s_sum[3];
+    const LevelDims &d = a.d;
+    const int tiles_x = (d.Gx + SF_PT_TW - 1) / SF_PT_TW;
+    const int P = gridDim.x, wg = blockIdx.x;
+    const int i0 = (wg % tiles_x) * SF_PT_TW, j0 = (wg / tiles_x) * SF_PT_TH;
+    const int tw = min(SF_PT_TW, d.Gx - i0), th = min(SF_PT_TH, d.Gy - j0);
+    const unsigned epoch = a.sc->pt_epoch;
+    // tags: pass p of this launch (p = 200: the final ||r||^2); never 0, the
+    // word of a cleared buffer
+    auto tag = [epoch](int p) { return (epoch << 8) | (unsigned)(p + 1); };
     const int log_index = gn >= 0 ? a.log_base + gn : -1;
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int sub = lane % 3;
-    const int n = n_begin + wv * SMALL_NPW + lane / 3;
-    const bool valid = lane < 3 * SMALL_NPW && n < n_end;
-    const int i_n = valid ? n % d.Gx : 0, j_n = valid ? n / d.Gx : 0;
+    const int t = wv * SMALL_NPW + lane / 3;
+    const bool valid = lane < 3 * SMALL_NPW && t < tw * th;
+    const int i_n = i0 + (valid ? t % tw : 0), j_n = j0 + (valid ? t / tw : 0);
+    const long n = (long)j_n * d.Gx + i_n;
     const int c0 = 2 * sub;
-    const int n_loc = valid ? n - h_begin : 0;
-    // blocks as in the one-workgroup kernel; partners by global index, their
-    // u at su[partner - h_begin]
-    float Bk[2][21];
+    // LDS record of node (i, j) of the tile or its halo ring
+    auto loc = [i0, j0](int i, int j) { return (j - j0 + 1) * PT_HX + (i - i0 + 1); };
+    const int n_loc = loc(i_n, j_n);
+    if (pend && !a.sc->spec_acc) {
+        // the deferred step of a rejected speculative tau = 1 (k_rhs_blocks)
+        if (valid && sub == 0) deferred_step(a, n, a.sc->spec_tau);
+        if (wg == 0) lin_energy_scalars(a, a.sc->lin_n);
+    }
+    // this lane's three blocks, partners at their LDS records
+    float Bk[3][21];
     int pn[3];
-    float *myb = sb + threadIdx.x * SF_GRAM_STRIDE;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         int k, di, dj;
@@ -2428,19 +2515,12 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_mid(LevelArgs a, int n_it, int
         blk_offset(k, di, dj);
         const int pi = own ? i_n + di : i_n - di, pj = own ? j_n + dj : j_n - dj;
         const bool has = valid && pi >= 0 && pi < d.Gx && pj >= 0 && pj < d.Gy;
-        pn[q] = has ? pj * d.Gx + pi - h_begin : n_loc;
-        float t[21];
+        pn[q] = has ? loc(pi, pj) : n_loc;
 #pragma unroll
-        for (int e = 0; e < 21; ++e) t[e] = 0.f;
+        for (int e = 0; e < 21; ++e) Bk[q][e] = 0.f;
         if (has) {
-            const long owner = own ? (long)n : (long)(pj * d.Gx + pi);
-            rec_load<21>(a.blk + owner * SF_BLK_STRIDE + k * SF_GRAM_STRIDE, t);
-        }
-        if (q < 2) {
-#pragma unroll
-            for (int e = 0; e < 21; ++e) Bk[q][e] = t[e];
-        } else {
-            rec_store<21>(myb, t);
+            const long owner = own ? n : (long)pj * d.Gx + pi;
+            rec_load<21>(a.blk + owner * SF_BLK_STRIDE + k * SF_GRAM_STRIDE, Bk[q]);
         }
     }
     float cnb[4] = {0.f, 0.f, 0.f, 0.f}, J0o[2] = {0.f, 0.f}, J1o[2] = {0.f, 0.f};
@@ -2455,12 +2535,12 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_mid(LevelArgs a, int n_it, int
         cm2[0] = c * C->mf[c0]; cm2[1] = c * C->mf[c0 + 1];
     }
     if (valid) {
-        const float2 rv = *reinterpret_cast<const float2 *>(nvec(a, NV_R0) + (long)n * 8 + c0);
-        const float2 uv = *reinterpret_cast<const float2 *>(nvec(a, NV_U) + (long)n * 8 + c0);
-        const float2 dv = *reinterpret_cast<const float2 *>(nvec(a, NV_DIAG) + (long)n * 8 + c0);
+        const float2 rv = *reinterpret_cast<const float2 *>(nvec(a, NV_R0) + n * 8 + c0);
+        const float2 uv = *reinterpret_cast<const float2 *>(nvec(a, NV_U) + n * 8 + c0);
+        const float2 dv = *reinterpret_cast<const float2 *>(nvec(a, NV_DIAG) + n * 8 + c0);
         r2[0] = rv.x; r2[1] = rv.y; u2[0] = uv.x; u2[1] = uv.y; D2[0] = dv.x; D2[1] = dv.y;
         float rg[REG_PLANES];
-        rec_load<REG_PLANES>(a.reg + (long)n * REG_PLANES, rg);
+        rec_load<REG_PLANES>(a.reg + n * REG_PLANES, rg);
 #pragma unroll
         for (int k = 0; k < 4; ++k) cnb[k] = rg[k];
 #pragma unroll
@@ -2473,28 +2553,53 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_mid(LevelArgs a, int n_it, int
     for (int k = 0; k < 4; ++k) {
         int di, dj;
         nb_offset(k, di, dj);
-        nbr[k] = valid && cnb[k] != 0.f ? (j_n + dj) * d.Gx + i_n + di - h_begin : n_loc;
+        nbr[k] = valid && cnb[k] != 0.f ? loc(i_n + di, j_n + dj) : n_loc;
     }
-    // this workgroup's nodes that neighbouring workgroups hold as halo
-    const bool publish = valid && (n < n_begin + d.Gx + 1 || n >= n_end - d.Gx - 1);
+    // the border nodes publish their records; the halo ring's nodes (one
+    // thread each) are rebuilt from their owners' records
+    const bool border = valid && (i_n == i0 || i_n == i0 + tw - 1 || j_n == j0 || j_n == j0 + th - 1);
+    const int hw = tw + 2, hh = th + 2, n_ring = 2 * hw + 2 * (hh - 2);
+    int hi = -1, hj = -1;
+    if ((int)threadIdx.x < n_ring) {
+        const int r = threadIdx.x;
+        if (r < hw) { hi = i0 - 1 + r; hj = j0 - 1; }
+        else if (r < 2 * hw) { hi = i0 - 1 + (r - hw); hj = j0 + th; }
+        else { const int q = r - 2 * hw; hi = (q & 1) ? i0 + tw : i0 - 1; hj = j0 + (q >> 1); }
+    }
+    const bool halo = hi >= 0 && hi < d.Gx && hj >= 0 && hj < d.Gy;
+    const long hn = halo ? (long)hj * d.Gx + hi : 0;
+    float hdg[6] = {1.f, 1.f, 1.f, 1.f, 1.f, 1.f};
+    if (halo) ld6(nvec(a, NV_DIAG), hn, hdg);
 
     double hg = 0.0;           // gamma of the previous decision
     float ha = 0.f;            // alpha of the previous decision
     float al = 0.f, be = 0.f;  // scalars of iteration i-1
     int act = 1;
-    int nbar = 0;              // barriers passed
     for (int i = 0; i <= n_it; ++i) {
         if (i > 0) {
-            // the sums of pass i-1 from every workgroup (each wavefront reduces
-            // them in the same order) decide iteration i-1
-            const float *pp = a.partials + (long)(((i - 1) & 1) ? PS_PCG1 : PS_PCG0) * a.max_blocks;
-            const int rw = lane & 31;
-            const double g0 = rw < Pw ? (double)pp[rw] : 0.0;
-            const double g1 = rw < Pw ? (double)pp[a.max_blocks + rw] : 0.0;
-            const double g2 = rw < Pw ? (double)pp[2 * a.max_blocks + rw] : 0.0;
-            const double gam = uniform_d(group_sum<double>(g0, 32));
-            const double del = uniform_d(group_sum<double>(g1, 32));
-            const double rsum = uniform_d(group_sum<double>(g2, 32));
+            // wavefront 0 polls every tile's sums of pass i-1 and, in the
+            // lanes of halo nodes, their owners' records of pass i-1, all
+            // in the same rounds; the workgroup goes on only if every wait
+            // succeeded
+            float hv[18];
+            bool ok_w = true;
+            if (wv == 0) {
+                const int par = (i - 1) & 1, rep = wg % PT_REP;
+                unsigned long long *const src[3] = {pt_part(a, par, 0, rep),
+                                                    pt_part(a, par, 1, rep),
+                                                    pt_part(a, par, 2, rep)};
+                const bool hpoll = halo && i < n_it;
+#pragma unroll
+                for (int q = 0; q < 18; ++q) hv[q] = 0.f;
+                double s3w[3];
+                ok_w = pt_poll<3>(a, src, P, tag(i - 1), hpoll ? pt_rec(a, par, hn) : nullptr,
+                                  i > 1 ? 0x3FFFFu : 0xFFFu, hv, spin_limit, s3w);
+                if (lane == 0) { s_sum[0] = s3w[0]; s_sum[1] = s3w[1]; s_sum[2] = s3w[2]; }
+            }
+            if (!__syncthreads_and(ok_w)) return;
+            const double s3[3] = {s_sum[0], s_sum[1], s_sum[2]};
+            // iteration i-1 from those sums (alike in every wavefront)
+            const double gam = s3[0], del = s3[1], rsum = s3[2];
             double b = 0.0, pq = del;
             if (i - 1 > 0) {
                 b = gam / hg;
@@ -2526,39 +2631,23 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_mid(LevelArgs a, int n_it, int
                 u2[j] = r2[j] / D2[j];
             }
             if (i == n_it) break;
-            // halo u_i from the neighbours' records of pass i-1
-            const float *Rp = nvec(a, ((i - 1) & 1) ? NV_R1 : NV_R0);
-            const float *Wp = nvec(a, ((i - 1) & 1) ? NV_W1 : NV_W0);
-            const float *Sp = nvec(a, ((i - 2) & 1) ? NV_S1 : NV_S0);
-            const float *Dg = nvec(a, NV_DIAG);
-            for (int m = h_begin + threadIdx.x; m < h_end; m += blockDim.x) {
-                if (m >= n_begin && m < n_end) continue;
-                float rv[6], wv6[6], sv[6], dv[6], uh[6];
-                ld6(Rp, m, rv);
-                ld6(Wp, m, wv6);
-                ld6(Dg, m, dv);
-                if (i > 1) {
-                    ld6(Sp, m, sv);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 6; ++q) sv[q] = 0.f;
-                }
+            // halo u_i
+            if (halo) {
+                float uh[6];
 #pragma unroll
                 for (int q = 0; q < 6; ++q) {
-                    const float sn = i > 1 ? wv6[q] + be * sv[q] : wv6[q];
-                    const float rn = rv[q] - al * sn;
-                    uh[q] = rn / dv[q];
+                    const float sv = i > 1 ? hv[6 + q] + be * hv[12 + q] : hv[6 + q];
+                    const float rn = hv[q] - al * sv;
+                    uh[q] = rn / hdg[q];
                 }
-                rec_store<6>(su + (size_t)(m - h_begin) * 8, uh);
+                rec_store<6>(su + (size_t)loc(hi, hj) * 8, uh);
             }
         } else {
             // u_0 of the halo as the right-hand-side kernel stored it
-            const float *Ug = nvec(a, NV_U);
-            for (int m = h_begin + threadIdx.x; m < h_end; m += blockDim.x) {
-                if (m >= n_begin && m < n_end) continue;
+            if (halo) {
                 float uh[6];
-                ld6(Ug, m, uh);
-                rec_store<6>(su + (size_t)(m - h_begin) * 8, uh);
+                ld6(nvec(a, NV_U), hn, uh);
+                rec_store<6>(su + (size_t)loc(hi, hj) * 8, uh);
             }
         }
         // u_i of the own nodes; w_i = H u_i
@@ -2570,17 +2659,11 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_mid(LevelArgs a, int n_it, int
 #pragma unroll
             for (int q = 0; q < 3; ++q) rec_load<6>(su + pn[q] * 8, un[q]);
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
+            for (int q = 0; q < 3; ++q)
 #pragma unroll
                 for (int r = 0; r < 6; ++r)
 #pragma unroll
                     for (int c = 0; c < 6; ++c) y[r] += Bk[q][gram_index(r, c)] * un[q][c];
-            float b2[21];
-            rec_load<21>(myb, b2);
-#pragma unroll
-            for (int r = 0; r < 6; ++r)
-#pragma unroll
-                for (int c = 0; c < 6; ++c) y[r] += b2[gram_index(r, c)] * un[2][c];
         }
         {
             const float e0 = J0o[0] * u2[0] + J0o[1] * u2[1];
@@ -2594,9 +2677,9 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_mid(LevelArgs a, int n_it, int
         float w2s[2] = {0.f, 0.f}, jp0 = 0.f, jp1 = 0.f;
         const float *gx = sx + (threadIdx.x - sub) * 8;
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const float2 yc = *reinterpret_cast<const float2 *>(gx + t * 8 + c0);
-            const float2 ee = *reinterpret_cast<const float2 *>(gx + t * 8 + 6);
+        for (int tt = 0; tt < 3; ++tt) {
+            const float2 yc = *reinterpret_cast<const float2 *>(gx + tt * 8 + c0);
+            const float2 ee = *reinterpret_cast<const float2 *>(gx + tt * 8 + 6);
             w2s[0] += yc.x;
             w2s[1] += yc.y;
             jp0 += ee.x;
@@ -2621,46 +2704,52 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_mid(LevelArgs a, int n_it, int
                 rr += r2[j] * r2[j];
             }
         }
-        // this workgroup's sums (wavefront sums in float, the wavefronts'
-        // in double, fixed order) and its boundary records of pass i
+        // the border records of pass i (s of pass i-1, as the halo rebuild
+        // of pass i+1 needs it), then this tile's sums
+        if (border) {
+            unsigned long long *rec = pt_rec(a, i & 1, n);
+            const unsigned tg = tag(i);
+            tag_store(rec + c0, r2[0], tg);
+            tag_store(rec + c0 + 1, r2[1], tg);
+            tag_store(rec + 6 + c0, w2[0], tg);
+            tag_store(rec + 6 + c0 + 1, w2[1], tg);
+            tag_store(rec + 12 + c0, s2[0], tg);
+            tag_store(rec + 12 + c0 + 1, s2[1], tg);
+        }
         const float t0 = wave_sum(ru), t1 = wave_sum(wu), t2 = wave_sum(rr);
         if (lane == 0) { red[wv][0] = t0; red[wv][1] = t1; red[wv][2] = t2; }
-        if (publish) {
-            *reinterpret_cast<float2 *>(nvec(a, (i & 1) ? NV_R1 : NV_R0) + (long)n * 8 + c0) =
-                make_float2(r2[0], r2[1]);
-            *reinterpret_cast<float2 *>(nvec(a, (i & 1) ? NV_W1 : NV_W0) + (long)n * 8 + c0) =
-                make_float2(w2[0], w2[1]);
-            if (i > 0)
-                *reinterpret_cast<float2 *>(nvec(a, ((i - 1) & 1) ? NV_S1 : NV_S0) + (long)n * 8 + c0) =
-                    make_float2(s2[0], s2[1]);
-        }
         __syncthreads();
-        if (threadIdx.x < 3) {
-            double t = 0.0;
-            for (int w = 0; w < nw; ++w) t += (double)red[w][threadIdx.x];
-            a.partials[(long)(((i & 1) ? PS_PCG1 : PS_PCG0) + threadIdx.x) * a.max_blocks + wg] =
-                (float)t;
+        if (threadIdx.x < 3 * PT_REP) {
+            const int k = threadIdx.x % 3;
+            double tsum = 0.0;
+            for (int w = 0; w < nw; ++w) tsum += (double)red[w][k];
+            tag_store(pt_part(a, i & 1, k, threadIdx.x / 3) + wg, (float)tsum, tag(i));
         }
-        ++nbar;
-        if (!mid_barrier(a.sc, (unsigned)nbar * Pw, spin_limit, s_stop)) return;
     }
-    // the solution, and ||r||^2 of the final residual for the step control's
-    // log (one partial per workgroup, zeros up to the node-block count the
-    // step control sums)
-    if (valid) *reinterpret_cast<float2 *>(nvec(a, NV_X) + (long)n * 8 + c0) = make_float2(x2[0], x2[1]);
+    // the solution, and ||r_n||^2 for the step control's log: tile 0 sums
+    // every tile's final partial and leaves it as the one nonzero partial
+    if (valid) *reinterpret_cast<float2 *>(nvec(a, NV_X) + n * 8 + c0) = make_float2(x2[0], x2[1]);
     const float rrf = valid ? r2[0] * r2[0] + r2[1] * r2[1] : 0.f;
-    const float t2 = wave_sum(rrf);
+    const float tr = wave_sum(rrf);
     __syncthreads();
-    if (lane == 0) red[wv][2] = t2;
+    if (lane == 0) red[wv][2] = tr;
     __syncthreads();
-    float *rrp = a.partials + (long)(((n_it & 1) ? PS_PCG1 : PS_PCG0) + 2) * a.max_blocks;
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < nw; ++w) t += (double)red[w][2];
-        rrp[wg] = (float)t;
+    if (threadIdx.x < PT_REP) {
+        double tsum = 0.0;
+        for (int w = 0; w < nw; ++w) tsum += (double)red[w][2];
+        tag_store(pt_final(a, threadIdx.x) + wg, (float)tsum, tag(200));
     }
-    if (wg == 0)
-        for (int b = Pw + threadIdx.x; b < node_blocks(d); b += blockDim.x) rrp[b] = 0.f;
+    if (wg == 0 && wv == 0) {
+        unsigned long long *const src[1] = {pt_final(a, 0)};
+        double fr[1];
+        float unused[18];
+        if (!pt_poll<1>(a, src, P, tag(200), nullptr, 0u, unused, spin_limit, fr)) return;
+        float *rrp = a.partials + (long)(((n_it & 1) ? PS_PCG1 : PS_PCG0) + 2) * a.max_blocks;
+        for (int b = lane; b < node_blocks(d); b += 64) rrp[b] = b == 0 ? (float)fr[0] : 0.f;
+        // every tile has read the epoch (each published its final partial):
+        // the next launch takes a fresh one
+        if (lane == 0) a.sc->pt_epoch = epoch + 1u;
+    }
 }
 
 // ---- step control: accept the first tau with E_trial <= E ------------------
@@ -3532,33 +3621,30 @@ void launch_pcg_small(hipStream_t st, const Launch &L, int n_it, int gn, bool pe
     go(st, L, one, k_pcg_small<true>, k_pcg_small<false>, threads, 0, n_it, gn, pend ? 1 : 0);
 }
 
-bool mid_level(const LevelDims &d) {
-    return d.G > SF_SMALL_G && d.G <= SF_MID_G && d.Gx <= SF_MID_GX;
+int pt_tiles(const LevelDims &d) {
+    return ((d.Gx + SF_PT_TW - 1) / SF_PT_TW) * ((d.Gy + SF_PT_TH - 1) / SF_PT_TH);
 }
 
-// Whether SF_MID_WG workgroups of k_pcg_mid fit on the current device at
-// once (occupancy per compute unit times the unit count); the co-resident
-// form is used only then.
-bool mid_fits_device() {
+int pt_capacity() {
     int dev = 0, per_cu = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-        return false;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pcg_mid, SMALL_NT, 0) !=
-        hipSuccess)
-        return false;
-    return (long)per_cu * prop.multiProcessorCount >= SF_MID_WG;
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pcg_tile, PT_NT, 0) != hipSuccess)
+        return 0;
+    return per_cu * prop.multiProcessorCount;
 }
 
-void launch_pcg_mid(hipStream_t st, const Launch &L, int n_it, int gn, bool pend) {
+size_t pt_xtag_words(long G0) { return (size_t)7 * PT_REP * SF_PT_MAXWG + (size_t)2 * 18 * G0; }
+
+void launch_pcg_tile(hipStream_t st, const Launch &L, int n_it, int gn, bool pend) {
     const LevelArgs &a = L.host[0];
-    const int P = (a.d.G + SF_SMALL_G - 1) / SF_SMALL_G;
     // about a second of polling before a wait gives up; SF_MID_SPIN_LIMIT
     // overrides it (tests force the give-up path with a tiny limit)
-    int spin_limit = 1 << 21;
+    int spin_limit = 1 << 20;
     if (const char *e = getenv("SF_MID_SPIN_LIMIT")) spin_limit = atoi(e);
-    hipLaunchKernelGGL(k_pcg_mid, dim3(P), dim3(SMALL_NT), 0, st, a, n_it, gn, spin_limit,
-                       pend ? 1 : 0);
+    hipLaunchKernelGGL(k_pcg_tile, dim3(pt_tiles(a.d)), dim3(PT_NT), 0, st, a, n_it, gn,
+                       spin_limit, pend ? 1 : 0);
 }
 
 void launch_pcg_last(hipStream_t st, const Launch &L, const TileCfg &t, int iter, int gn,

@@ -28,6 +28,7 @@ SF_STAGE_LEVEL_INIT, SF_STAGE_LINEARIZE, SF_STAGE_APPLY = 0, 1, 2
 SF_STAGE_PCG, SF_STAGE_GN, SF_STAGE_FINISH, SF_STAGE_MASKS, SF_STAGE_STEP = 3, 4, 5, 6, 7
 SF_STAGE_OCC, SF_STAGE_SPEC_STEP = 8, 9
 SF_KERNEL_APPLY, SF_KERNEL_LINEARIZE, SF_KERNEL_UPDATE, SF_KERNEL_RHS, SF_KERNEL_BLOCKS = 0, 1, 2, 3, 4
+SF_KERNEL_PCG_TILE = 5
 SF_CNN_PARAMS = 39910
 SF_TR_INPUT, SF_TR_ACT, SF_TR_OUT, SF_TR_DOUT, SF_TR_DPRE, SF_TR_GRAD = 0, 1, 2, 3, 4, 5
 

@@ -450,9 +450,9 @@ def test_stereo_only_call(apply):
     assert np.abs(flow3d[:, fin]).max() <= 1e-3 * np.nanmax(depth)
 
 
-def test_mid_pcg_gives_up_without_hanging(monkeypatch):
-    """apply_mode 3 with the co-resident PCG's waits forced to give up at
-    once (a spin limit of zero set from the host): every workgroup still
+def test_tiled_pcg_gives_up_without_hanging(monkeypatch):
+    """apply_mode 3 with the co-resident tiled PCG's waits forced to give up
+    at once (a spin limit of zero set from the host): every workgroup still
     exits, sf_get_log reports SF_ERR_STATE for that solve, and the next
     solve of the context runs the per-iteration kernels and matches the
     oracle."""
