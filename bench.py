@@ -49,14 +49,14 @@ WORKLOADS = {
                          "stride 4, 5 levels",
                     width=640, height=480, n_eval=16, weights="init_640x480.npy",
                     params=dict(levels=5, grid_stride=4, gn_iters=10, pcg_iters=20)),
-    "learned_hd": dict(desc="learned-init vs plain at equal EPE: 16 held-out 1280x720 "
-                            "generator frames (seeds 1000000..1000015, 80 px displacement, "
+    "learned_hd": dict(desc="learned-init vs plain at equal EPE: 100 held-out 1280x720 "
+                            "generator frames (seeds 1000000..1000099, 80 px displacement, "
                             "two moving blobs); target = mean EPE of the plain solver (zero "
                             "initialisation) at 10 GN x 20 PCG per level; plain and learned "
-                            "(the stored 1280x720 initialiser, trained on 256 frames, seeds "
-                            "0..255, with the energy fallback) each at the fewest GN steps "
+                            "(the stored 1280x720 initialiser, trained on 2000 frames, seeds "
+                            "0..1999, with the energy fallback) each at the fewest GN steps "
                             "per level reaching it; stride 4, 6 levels",
-                       width=1280, height=720, n_eval=16, weights="init_1280x720.npy",
+                       width=1280, height=720, n_eval=100, weights="init_1280x720.npy",
                        max_disp=80.0, blobs=2,
                        params=dict(levels=6, grid_stride=4, gn_iters=10, pcg_iters=20)),
     "batch": dict(desc="batches of 64 frames, resolutions drawn by seed 3 from "

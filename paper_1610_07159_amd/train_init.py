@@ -348,7 +348,7 @@ def main():
     args = ap.parse_args()
     log = lambda m: print(m, flush=True)  # noqa: E731
     if args.profile_steps:
-        return profile_trainer(args.width >> LEVEL_IN, args.height >> LEVEL_IN, args.batch,
+        return profile_trainer(args.height >> LEVEL_IN, args.width >> LEVEL_IN, args.batch,
                                args.profile_steps, log)
     t_start = time.time()
     W, H = args.width, args.height
