@@ -211,4 +211,10 @@ def test_stored_networks_load_safely(name):
     assert np.isfinite(w).all()
     with open(os.path.join(root, name + "_report.json")) as f:
         rep = json.load(f)
-    assert rep["equal_epe"]["gn_iters"] < rep["plain"]["gn_iters"]
+    if "learned_at_target" in rep:
+        # each method at the fewest steps per level reaching the plain
+        # solver's full-schedule EPE
+        assert rep["learned_at_target"]["epe_px"] <= rep["target_epe_px"]
+        assert rep["learned_at_target"]["gn_iters"] < rep["plain_at_target"]["gn_iters"]
+    else:
+        assert rep["equal_epe"]["gn_iters"] < rep["plain"]["gn_iters"]
