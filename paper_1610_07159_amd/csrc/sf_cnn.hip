@@ -120,94 +120,192 @@ __global__ __launch_bounds__(256) void k_conv(const unsigned short *__restrict__
     }
 }
 
-// Weight-gradient partials of one layer: for pixel chunk c, output-channel
-// block m, tap and input-channel block n, the 16 x 16 tile
-//   sum over the chunk's pixels p of dpre[p][co] x[p + off(tap)][ci].
-// part: [chunks][COUT][9][CIN] float.
+// Weight-gradient partials of one layer, one workgroup per chunk of `chunk`
+// pixels (flattened over the batch):
+//   part[c][co][tap][ci] = sum over the chunk's pixels p of
+//                          dpre[p][co] x[p + off(tap)][ci]
+// (x zero where the tap leaves the image).  The contraction runs over
+// pixels, which NHWC stores apart, so each slice of WG_SLICE pixels is
+// staged transposed in LDS: the output gradient once (dT[co][p]), then per
+// tap the shifted inputs (xT[ci][p]).  An MFMA operand is then eight
+// consecutive pixels of one channel, one 16-byte LDS read (rows padded by
+// 16 bytes so that the 16 channels of a read fall on different banks).
+// Wavefront w takes tile w mod T of the (co block, ci block) grid and every
+// (4 / T)-th 32-pixel step of each slice; the partial tiles of a K split are
+// added in wavefront order at the end.  The bias-gradient partial
+// bpart[c][co] = sum over the chunk of dpre[p][co] comes from the same
+// staged rows: thread t sums its share (co = t mod COUT) of each slice, and
+// the shares are added in thread order.
+#define WG_SLICE 256
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_wgrad(const unsigned short *__restrict__ dpre,
                                                const unsigned short *__restrict__ x,
-                                               float *__restrict__ part, int B, int H, int W,
+                                               float *__restrict__ part,
+                                               float *__restrict__ bpart, int B, int H, int W,
                                                int chunk) {
-    constexpr int MB = COUT / 16, NBK = CIN / 16, TILES = MB * 9 * NBK;
+    constexpr int MB = COUT / 16, NB = CIN / 16, T = MB * NB, KP = 4 / T;
+    static_assert(T == 1 || T == 2 || T == 4, "tiles per tap");
+    constexpr int ROW = WG_SLICE + 8;  // shorts per LDS row
+    __shared__ __attribute__((aligned(16))) unsigned short dT[COUT * ROW];
+    __shared__ __attribute__((aligned(16))) unsigned short xT[CIN * ROW];
+    __shared__ __attribute__((aligned(16))) float comb[KP > 1 ? (KP - 1) * T : 1][9][64][4];
+    __shared__ float bred[256];
+    constexpr int BPARTS = 256 / COUT, BSEG = WG_SLICE / BPARTS;
+    static_assert(BSEG % 8 == 0, "16-byte bias reads");
+    float bacc = 0.f;
     const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
-    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wv = threadIdx.x >> 6, t = wv % T, kp = wv / T;
+    const int mb = t / NB, nb = t % NB;
     const long P = (long)B * H * W;
-    const int nchunks = (int)((P + chunk - 1) / chunk);
-    if (w >= nchunks * TILES) return;  // uniform per wavefront
-    const int c = w / TILES, t = w % TILES;
-    const int mb = t / (9 * NBK), tap = (t / NBK) % 9, nb = t % NBK;
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    const int co = mb * 16 + r, ci = nb * 16 + r;
-    v4f acc = {0.f, 0.f, 0.f, 0.f};
-    const long p_end = min(P, (long)(c + 1) * chunk);
-    for (long p0 = (long)c * chunk; p0 < p_end; p0 += 32) {
-        v8s a, bv;
+    const long HW = (long)H * W;
+    const int c = blockIdx.x;
+    const long p_begin = (long)c * chunk, p_end = min(P, p_begin + chunk);
+    v4f acc[9];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const long p = p0 + 8 * q + i;
-            short av = 0, xv = 0;
-            if (p < p_end) {
-                av = (short)dpre[p * COUT + co];
-                const int b = (int)(p / ((long)H * W));
-                const int rem = (int)(p % ((long)H * W));
-                const int yy = rem / W + dy, xx = rem % W + dx;
-                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                    xv = (short)x[((long)(b * H + yy) * W + xx) * CIN + ci];
+    for (int k = 0; k < 9; ++k) acc[k] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (long p0 = p_begin; p0 < p_end; p0 += WG_SLICE) {
+        // this thread's pixel of the slice, its image and position
+        const long p = p0 + threadIdx.x;
+        const bool in = p < p_end;
+        const int b = in ? (int)(p / HW) : 0;
+        const int rem = in ? (int)(p % HW) : 0;
+        const int py = rem / W, px = rem % W;
+        {
+            unsigned short v[COUT];
+            if (in) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(dpre + p * COUT);
+#pragma unroll
+                for (int k = 0; k < COUT / 8; ++k) {
+                    const uint4 u = src[k];
+                    const unsigned w4[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        v[8 * k + 2 * j] = (unsigned short)(w4[j] & 0xFFFFu);
+                        v[8 * k + 2 * j + 1] = (unsigned short)(w4[j] >> 16);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < COUT; ++k) v[k] = 0;
             }
-            a[i] = av;
-            bv[i] = xv;
+#pragma unroll
+            for (int k = 0; k < COUT; ++k) dT[k * ROW + threadIdx.x] = v[k];
         }
-        acc = mfma32(a, bv, acc);
+#pragma unroll 1
+        for (int tap = 0; tap < 9; ++tap) {
+            const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
+            const bool ok = in && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            unsigned short v[CIN];
+            if (ok) {
+                const uint4 *src =
+                    reinterpret_cast<const uint4 *>(x + ((long)(b * H + yy) * W + xx) * CIN);
+#pragma unroll
+                for (int k = 0; k < CIN / 8; ++k) {
+                    const uint4 u = src[k];
+                    const unsigned w4[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        v[8 * k + 2 * j] = (unsigned short)(w4[j] & 0xFFFFu);
+                        v[8 * k + 2 * j + 1] = (unsigned short)(w4[j] >> 16);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < CIN; ++k) v[k] = 0;
+            }
+            __syncthreads();  // the previous tap's products are done with xT
+#pragma unroll
+            for (int k = 0; k < CIN; ++k) xT[k * ROW + threadIdx.x] = v[k];
+            __syncthreads();
+            if (tap == 0) {
+                // this thread's share of the slice's bias gradient
+                const unsigned short *row =
+                    dT + (threadIdx.x % COUT) * ROW + (threadIdx.x / COUT) * BSEG;
+#pragma unroll
+                for (int k = 0; k < BSEG; k += 8) {
+                    const v8s v = load8(row + k);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) bacc += bf2f((unsigned short)v[j]);
+                }
+            }
+#pragma unroll
+            for (int kk = kp; kk < WG_SLICE / 32; kk += KP) {
+                const v8s av = load8(dT + (mb * 16 + r) * ROW + 32 * kk + 8 * q);
+                const v8s bv = load8(xT + (nb * 16 + r) * ROW + 32 * kk + 8 * q);
+                acc[tap] = mfma32(av, bv, acc[tap]);
+            }
+        }
+        __syncthreads();  // dT and xT are rewritten by the next slice
+    }
+    // the bias partial: the threads' shares in thread order
+    bred[threadIdx.x] = bacc;
+    __syncthreads();
+    if (threadIdx.x < COUT) {
+        float t = 0.f;
+        for (int k = 0; k < BPARTS; ++k) t += bred[k * COUT + threadIdx.x];
+        bpart[(long)c * COUT + threadIdx.x] = t;
+    }
+    // the K split's partial tiles, added in wavefront order
+    if (KP > 1) {
+        if (kp > 0)
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) comb[(kp - 1) * T + t][tap][lane][i] = acc[tap][i];
+        __syncthreads();
+        if (kp > 0) return;
+#pragma unroll
+        for (int k = 1; k < KP; ++k)
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[tap][i] += comb[(k - 1) * T + t][tap][lane][i];
     }
     // D rows = output channels mb*16 + 4q + i, column = input channel ci
+    const int ci = nb * 16 + r;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int o = mb * 16 + 4 * q + i;
-        part[(((long)c * COUT + o) * 9 + tap) * CIN + ci] = acc[i];
-    }
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = mb * 16 + 4 * q + i;
+            part[(((long)c * COUT + o) * 9 + tap) * CIN + ci] = acc[tap][i];
+        }
 }
 
-// Bias-gradient partials: part[c][co] = sum over chunk c of dpre[p][co].
-template <int COUT>
-__global__ __launch_bounds__(256) void k_bgrad(const unsigned short *__restrict__ dpre,
-                                               float *__restrict__ part, long P, int chunk) {
-    const int c = blockIdx.x;
-    const int co = threadIdx.x % COUT, sub = threadIdx.x / COUT;
-    constexpr int SUBS = 256 / COUT;
-    __shared__ float red[256];
-    float acc = 0.f;
-    const long p_end = min(P, (long)(c + 1) * chunk);
-    for (long p = (long)c * chunk + sub; p < p_end; p += SUBS) acc += bf2f(dpre[p * COUT + co]);
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    if (sub == 0) {
-        float s = 0.f;
-        for (int k = 0; k < SUBS; ++k) s += red[k * COUT + co];
-        part[(long)c * COUT + co] = s;
-    }
-}
-
-// Sums the chunk partials in chunk order into the flat gradient vector
-// (layout of sf_cnn.h: per layer the weights (c_out, c_in, ky, kx) of the
-// real channels, then the biases).
+// Sums the chunk partials into the flat gradient vector (layout of
+// sf_cnn.h: per layer the weights (c_out, c_in, ky, kx) of the real
+// channels, then the biases).  A workgroup takes 64 consecutive partial
+// entries (coalesced loads) in 4 chunk groups: group g sums chunks g, g + 4,
+// ... in order, and the group sums are added in group order, so the result
+// does not depend on scheduling.
 __global__ __launch_bounds__(256) void k_grad_reduce(const float *__restrict__ wpart,
                                                      const float *__restrict__ bpart,
                                                      float *__restrict__ grad, int nchunks,
                                                      int cin, int cout, int cinp, int coutp) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nw = cout * cin * 9;
-    if (k >= nw + cout) return;
+    __shared__ double red[4][64];
+    const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + l;
+    const int nwp = coutp * 9 * cinp, ne = nwp + coutp;
     double s = 0.0;
-    if (k < nw) {
-        const int co = k / (cin * 9), ci = (k / 9) % cin, tap = k % 9;
-        for (int c = 0; c < nchunks; ++c)
-            s += (double)wpart[(((long)c * coutp + co) * 9 + tap) * cinp + ci];
-    } else {
-        const int co = k - nw;
-        for (int c = 0; c < nchunks; ++c) s += (double)bpart[(long)c * coutp + co];
+    if (e < ne) {
+        if (e < nwp) {
+#pragma unroll 8
+            for (int c = g; c < nchunks; c += 4) s += (double)wpart[(long)c * nwp + e];
+        } else {
+            for (int c = g; c < nchunks; c += 4) s += (double)bpart[(long)c * coutp + (e - nwp)];
+        }
     }
-    grad[k] = (float)s;
+    red[g][l] = s;
+    __syncthreads();
+    if (g != 0 || e >= ne) return;
+    const double tot = ((red[0][l] + red[1][l]) + red[2][l]) + red[3][l];
+    if (e < nwp) {
+        const int co = e / (9 * cinp), tap = (e / cinp) % 9, ci = e % cinp;
+        if (co < cout && ci < cin) grad[(co * cin + ci) * 9 + tap] = (float)tot;
+    } else {
+        const int co = e - nwp;
+        if (co < cout) grad[cout * cin * 9 + co] = (float)tot;
+    }
 }
 
 // Network input: bf16(I - 0.5) in channels 0..3, zero in 4..15.
@@ -415,20 +513,18 @@ void launch_cnn_backward(hipStream_t st, const CnnLayout &L, const CnnWeights &w
         const unsigned short *d = l == SF_CNN_LAYERS - 1 ? dout : dpre[l];
         const unsigned short *xin = l == 0 ? x : acts[l - 1];
         const int cinp = L.cinp[l], coutp = L.coutp[l];
-        const int tiles = (coutp / 16) * 9 * (cinp / 16);
-        const dim3 gw((unsigned)(((long)nch * tiles + 3) / 4));
+        const dim3 gw((unsigned)nch);
         if (l == 0)
-            hipLaunchKernelGGL((k_wgrad<16, 32>), gw, blk, 0, st, d, xin, wpart, B, H, W, SF_CNN_CHUNK);
+            hipLaunchKernelGGL((k_wgrad<16, 32>), gw, blk, 0, st, d, xin, wpart, bpart, B, H, W,
+                               SF_CNN_CHUNK);
         else if (l < SF_CNN_LAYERS - 1)
-            hipLaunchKernelGGL((k_wgrad<32, 32>), gw, blk, 0, st, d, xin, wpart, B, H, W, SF_CNN_CHUNK);
+            hipLaunchKernelGGL((k_wgrad<32, 32>), gw, blk, 0, st, d, xin, wpart, bpart, B, H, W,
+                               SF_CNN_CHUNK);
         else
-            hipLaunchKernelGGL((k_wgrad<32, 16>), gw, blk, 0, st, d, xin, wpart, B, H, W, SF_CNN_CHUNK);
-        if (coutp == 32)
-            hipLaunchKernelGGL(k_bgrad<32>, dim3(nch), blk, 0, st, d, bpart, P, SF_CNN_CHUNK);
-        else
-            hipLaunchKernelGGL(k_bgrad<16>, dim3(nch), blk, 0, st, d, bpart, P, SF_CNN_CHUNK);
-        const int ng = L.cout[l] * L.cin[l] * 9 + L.cout[l];
-        hipLaunchKernelGGL(k_grad_reduce, dim3((ng + 255) / 256), blk, 0, st, wpart, bpart,
+            hipLaunchKernelGGL((k_wgrad<32, 16>), gw, blk, 0, st, d, xin, wpart, bpart, B, H, W,
+                               SF_CNN_CHUNK);
+        const int nge = coutp * 9 * cinp + coutp;
+        hipLaunchKernelGGL(k_grad_reduce, dim3((nge + 63) / 64), blk, 0, st, wpart, bpart,
                            grad + L.flat_off[l], nch, L.cin[l], L.cout[l], cinp, coutp);
         if (l == 0) break;
         // gradient w.r.t. this layer's input, through the ReLU below
