@@ -99,7 +99,7 @@ WORKLOADS = {
 
 # Bytes one PCG iteration kernel (H u plus the vector updates) must move per
 # node at level 0, counting every value it loads or stores once.  Node
-# vectors are 6 floats (stored as 8-float records; 24 B accessed): it reads
+# vectors are packed 6-float records (24 B): it reads
 # r, w, s, diag (for u and the halo) and u, x, p (the owned node), and writes
 # s, r, w, p, x, u; plus the 16-float regulariser record.
 VEC_BYTES = 6 * 4

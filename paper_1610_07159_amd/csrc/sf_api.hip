@@ -336,7 +336,7 @@ sf_status build_plan(Plan &P, const sf_params &prm, const std::vector<int> &shap
                                (size_t)F.N0,
                                sizeof(float) * (size_t)F.G0,
                                sizeof(float) * 16 * (size_t)F.G0,
-                               sizeof(float) * NV_COUNT * 8 * (size_t)F.G0,
+                               sizeof(float) * NV_COUNT * SF_NREC * (size_t)F.G0,
                                sizeof(float) * SF_GRAM_STRIDE * (size_t)F.N0,
                                sizeof(float) * PS_COUNT * (size_t)F.max_blocks,
                                sizeof(DevScalars),
@@ -1459,19 +1459,19 @@ static sf_status debug_copy(sf_ctx *c, int what, int level, void *host, size_t b
             // node records on the device, six planes at the interface
             const int v = node_vec_of(what);
             if (v < 0) return SF_ERR_INVALID_ARG;
-            float *base = F.nodes + (size_t)v * 8 * F.G0;
-            std::vector<float> rec((size_t)8 * d.G, 0.f);
+            float *base = F.nodes + (size_t)v * SF_NREC * F.G0;
+            std::vector<float> rec((size_t)SF_NREC * d.G, 0.f);
             float *hp = (float *)host;
             if (to_device) {
                 ok = hipMemcpy(rec.data(), base, rec.size() * sizeof(float),
                                hipMemcpyDeviceToHost) == hipSuccess;
                 for (long n = 0; ok && n < d.G; ++n)
-                    for (int q = 0; q < 6; ++q) rec[n * 8 + q] = hp[(size_t)q * d.G + n];
+                    for (int q = 0; q < 6; ++q) rec[n * SF_NREC + q] = hp[(size_t)q * d.G + n];
                 ok = ok && hipMemcpy(base, rec.data(), rec.size() * sizeof(float), kind) == hipSuccess;
             } else {
                 ok = hipMemcpy(rec.data(), base, rec.size() * sizeof(float), kind) == hipSuccess;
                 for (long n = 0; ok && n < d.G; ++n)
-                    for (int q = 0; q < 6; ++q) hp[(size_t)q * d.G + n] = rec[n * 8 + q];
+                    for (int q = 0; q < 6; ++q) hp[(size_t)q * d.G + n] = rec[n * SF_NREC + q];
             }
         }
     }

@@ -45,10 +45,12 @@ __host__ __device__ inline int gram_index(int i, int j) {
     return i == j ? i : 6 + i * 5 - (i * (i - 1)) / 2 + (j - i - 1);
 }
 
-// Node vectors (each G_0 records of 8 floats: s_x, s_y, m_x, m_y, d_x, d_y
-// and 2 padding).  The PCG runs in the
+// Node vectors (each G_0 records of SF_NREC = 6 floats: s_x, s_y, m_x, m_y,
+// d_x, d_y, packed, so that a run of nodes moves no padding).  The PCG runs
+// in the
 // single-reduction form: r, w = H u and s = H p alternate between two
 // buffers by iteration parity because neighbouring tiles read them.
+#define SF_NREC 6
 enum {
     NV_BASE = 0,
     NV_DELTA,

@@ -318,20 +318,23 @@ __device__ __forceinline__ void bind(const FrameMap &m, LevelArgs &a, int &bid, 
 }
 // ---- node vectors ------------------------------------------------------------
 //
-// A node vector holds one 8-float record per node (s_x, s_y, m_x, m_y, d_x,
-// d_y, 2 pad) so that a node's components move with one 16-byte and one
-// 8-byte access; vector v of the level starts at nodes + v * 8 G_0.
+// A node vector holds one packed 6-float record per node (s_x, s_y, m_x,
+// m_y, d_x, d_y; 24 bytes, so a run of nodes moves no padding), moved as
+// three 8-byte accesses; vector v of the level starts at
+// nodes + v * SF_NREC * G_0.
 __device__ __forceinline__ float *nvec(const LevelArgs &a, int v) {
-    return a.nodes + (size_t)v * 8 * a.G0;
+    return a.nodes + (size_t)v * SF_NREC * a.G0;
 }
 __device__ __forceinline__ void ld6(const float *vec, long n, float (&x)[6]) {
-    const float4 p = *reinterpret_cast<const float4 *>(vec + n * 8);
-    const float2 q = *reinterpret_cast<const float2 *>(vec + n * 8 + 4);
-    x[0] = p.x; x[1] = p.y; x[2] = p.z; x[3] = p.w; x[4] = q.x; x[5] = q.y;
+    const float2 *p = reinterpret_cast<const float2 *>(vec + n * SF_NREC);
+    const float2 a = p[0], b = p[1], c = p[2];
+    x[0] = a.x; x[1] = a.y; x[2] = b.x; x[3] = b.y; x[4] = c.x; x[5] = c.y;
 }
 __device__ __forceinline__ void st6(float *vec, long n, const float (&x)[6]) {
-    *reinterpret_cast<float4 *>(vec + n * 8) = make_float4(x[0], x[1], x[2], x[3]);
-    *reinterpret_cast<float2 *>(vec + n * 8 + 4) = make_float2(x[4], x[5]);
+    float2 *p = reinterpret_cast<float2 *>(vec + n * SF_NREC);
+    p[0] = make_float2(x[0], x[1]);
+    p[1] = make_float2(x[2], x[3]);
+    p[2] = make_float2(x[4], x[5]);
 }
 
 #define SF_BIND(ka)              \
@@ -2166,9 +2169,9 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_small(KArg<B> ka, int n_it, in
         cm2[0] = c * C->mf[c0]; cm2[1] = c * C->mf[c0 + 1];
     }
     if (valid) {
-        const float2 rv = *reinterpret_cast<const float2 *>(nvec(a, NV_R0) + (long)n * 8 + c0);
-        const float2 uv = *reinterpret_cast<const float2 *>(nvec(a, NV_U) + (long)n * 8 + c0);
-        const float2 dv = *reinterpret_cast<const float2 *>(nvec(a, NV_DIAG) + (long)n * 8 + c0);
+        const float2 rv = *reinterpret_cast<const float2 *>(nvec(a, NV_R0) + (long)n * SF_NREC + c0);
+        const float2 uv = *reinterpret_cast<const float2 *>(nvec(a, NV_U) + (long)n * SF_NREC + c0);
+        const float2 dv = *reinterpret_cast<const float2 *>(nvec(a, NV_DIAG) + (long)n * SF_NREC + c0);
         r2[0] = rv.x; r2[1] = rv.y; u2[0] = uv.x; u2[1] = uv.y; D2[0] = dv.x; D2[1] = dv.y;
         float rg[REG_PLANES];
         rec_load<REG_PLANES>(a.reg + (long)n * REG_PLANES, rg);
@@ -2328,7 +2331,7 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_small(KArg<B> ka, int n_it, in
         const int rw = lane & 15;
         rsum = group_sum<double>(rw < nw ? (double)red[rw][2] : 0.0, 16);
     }
-    if (valid) *reinterpret_cast<float2 *>(nvec(a, NV_X) + (long)n * 8 + c0) = make_float2(x2[0], x2[1]);
+    if (valid) *reinterpret_cast<float2 *>(nvec(a, NV_X) + (long)n * SF_NREC + c0) = make_float2(x2[0], x2[1]);
     __syncthreads();
     for (int m = threadIdx.x + 1; m <= n_it; m += blockDim.x) {
         a.sc->hist[m] = shist[m];
@@ -2535,9 +2538,9 @@ __global__ __launch_bounds__(PT_NT) void k_pcg_tile(LevelArgs a, int n_it, int g
         cm2[0] = c * C->mf[c0]; cm2[1] = c * C->mf[c0 + 1];
     }
     if (valid) {
-        const float2 rv = *reinterpret_cast<const float2 *>(nvec(a, NV_R0) + n * 8 + c0);
-        const float2 uv = *reinterpret_cast<const float2 *>(nvec(a, NV_U) + n * 8 + c0);
-        const float2 dv = *reinterpret_cast<const float2 *>(nvec(a, NV_DIAG) + n * 8 + c0);
+        const float2 rv = *reinterpret_cast<const float2 *>(nvec(a, NV_R0) + n * SF_NREC + c0);
+        const float2 uv = *reinterpret_cast<const float2 *>(nvec(a, NV_U) + n * SF_NREC + c0);
+        const float2 dv = *reinterpret_cast<const float2 *>(nvec(a, NV_DIAG) + n * SF_NREC + c0);
         r2[0] = rv.x; r2[1] = rv.y; u2[0] = uv.x; u2[1] = uv.y; D2[0] = dv.x; D2[1] = dv.y;
         float rg[REG_PLANES];
         rec_load<REG_PLANES>(a.reg + n * REG_PLANES, rg);
@@ -2728,7 +2731,7 @@ __global__ __launch_bounds__(PT_NT) void k_pcg_tile(LevelArgs a, int n_it, int g
     }
     // the solution, and ||r_n||^2 for the step control's log: tile 0 sums
     // every tile's final partial and leaves it as the one nonzero partial
-    if (valid) *reinterpret_cast<float2 *>(nvec(a, NV_X) + n * 8 + c0) = make_float2(x2[0], x2[1]);
+    if (valid) *reinterpret_cast<float2 *>(nvec(a, NV_X) + n * SF_NREC + c0) = make_float2(x2[0], x2[1]);
     const float rrf = valid ? r2[0] * r2[0] + r2[1] * r2[1] : 0.f;
     const float tr = wave_sum(rrf);
     __syncthreads();
