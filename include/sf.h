@@ -380,7 +380,9 @@ enum {
     SF_DBG_DELTA = 4,   /* 6 x G_l float: delta unknowns                     */
     SF_DBG_DX = 5,      /* 6 x G_l float: PCG solution (GN step)             */
     SF_DBG_R = 6,       /* 6 x G_l float: PCG residual (initially -grad E)   */
-    SF_DBG_Z = 7,       /* 6 x G_l float: preconditioned residual u          */
+    SF_DBG_Z = 7,       /* 6 x G_l float: preconditioned residual u =
+                           diag(H)^-1 r at the PCG's start (the vector
+                           SF_STAGE_APPLY multiplies)                       */
     SF_DBG_Q = 8,       /* 6 x G_l float: H u of the first PCG product        */
     SF_DBG_DIAG = 9,    /* 6 x G_l float: diag(H)                            */
     SF_DBG_REC = 10,    /* 27 x N_l float: per-pixel gradient (6) and

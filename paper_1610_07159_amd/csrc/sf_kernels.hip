@@ -996,7 +996,8 @@ struct TileLds {
     int pitch;        // floats per row of records
     float *vals;      // RY rows of RX records of KP floats
     float *halo;      // (ty + 2) x (tx + 2) records of 8 floats
-    float *ownd;      // 2 x tx x ty scratch per owned node
+    float *ownd;      // 8 x tx x ty scratch per owned node (two partial
+                      // products, then u of the previous iteration)
 };
 
 __host__ __device__ constexpr int rec_pad(int K) { return (K + 3) / 4 * 4; }
@@ -1011,7 +1012,7 @@ __host__ __device__ inline int tile_pitch(const TileCfg &t, int s, int K) {
 __host__ __device__ inline size_t tile_lds_floats(const TileCfg &t, int s, int K) {
     const size_t RXs = tile_rxs(t, s), RYs = tile_rys(t, s);
     return 4 * RXs + 4 * RYs + (size_t)tile_pitch(t, s, K) * RYs +
-           (size_t)8 * (t.tx + 2) * (t.ty + 2) + (size_t)2 * t.tx * t.ty;
+           (size_t)8 * (t.tx + 2) * (t.ty + 2) + (size_t)8 * t.tx * t.ty;
 }
 
 __device__ TileLds tile_lds(float *lds, const TileCfg &t, int s, int K) {
@@ -1818,10 +1819,14 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     // fewer dependent memory round trip, same occupancy); batched launches,
     // which stream from HBM, read them after the LDS phases to keep the
     // register count (and occupancy) lower
+    // (u of iteration i-1: read here in single-frame launches; batched
+    // launches, which stream from HBM, rebuild it as r / diag from the halo
+    // records they read anyway, bitwise the same value, and neither read
+    // nor write the u vector)
     float uo[6], po[6], xo[6];
     auto load_own = [&]() {
         if (mine && !FIRST) {
-            ld6(U, n_own, uo);
+            if (!B) ld6(U, n_own, uo);
             ld6(X, n_own, xo);
             if (i > 1) {
                 ld6(P, n_own, po);
@@ -1872,6 +1877,13 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
             const int o = (hnj - g.j0) * t.tx + (hni - g.i0);
             L.ownd[o] = ru;
             L.ownd[t.tx * t.ty + o] = rr;
+            if (B && !FIRST) {
+                // u of iteration i-1 of this owned node, r / diag as the
+                // previous kernel formed it (bitwise), for its p update
+#pragma unroll
+                for (int q = 0; q < 6; ++q)
+                    L.ownd[(2 + q) * t.tx * t.ty + o] = hv0[q] / hv3[q];
+            }
         }
     }
     __syncthreads();
@@ -1913,6 +1925,11 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
 
     // ---- phase 4: sums onto nodes, regularisers ----------------------------
     if (B) load_own();
+    if (B && mine && !FIRST) {
+        const int o = tj * t.tx + ti;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) uo[q] = L.ownd[(2 + q) * t.tx * t.ty + o];
+    }
     float acc[6];
     if constexpr (S > 0) {
         lds_to_nodes<6, S, TileTraits<S, V>::TPN>(a, t, g, L, 0u, acc);
@@ -1985,7 +2002,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
             }
             st6(P, n_own, pn);
             st6(X, n_own, xn);
-            st6(U, n_own, uv);
+            if (!B) st6(U, n_own, uv);
         }
     }
     if (tid == 0) {
@@ -2007,7 +2024,7 @@ __global__ __launch_bounds__(SF_BLOCK) void k_pcg_last(KArg<B> ka, TileCfg t, in
     float *Rc = nvec(a, (i & 1) ? NV_R1 : NV_R0);
     const float *Wp = nvec(a, ((i - 1) & 1) ? NV_W1 : NV_W0);
     const float *Sp = nvec(a, ((i - 2) & 1) ? NV_S1 : NV_S0);
-    const float *U = nvec(a, NV_U);
+    const float *D = nvec(a, NV_DIAG);
     float *P = nvec(a, NV_P);
     float *X = nvec(a, NV_X);
     const long n = (long)bid * SF_BLOCK + threadIdx.x;
@@ -2019,7 +2036,16 @@ __global__ __launch_bounds__(SF_BLOCK) void k_pcg_last(KArg<B> ka, TileCfg t, in
     if (in) {
         ld6(Rp, n, rp);
         ld6(Wp, n, wp);
-        ld6(U, n, up);
+        // u of iteration n-1 (batched: r / diag, bitwise as the iteration
+        // kernel formed it, which does not store u there)
+        if (B) {
+            float dg[6];
+            ld6(D, n, dg);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) up[q] = rp[q] / dg[q];
+        } else {
+            ld6(nvec(a, NV_U), n, up);
+        }
         ld6(X, n, xp);
         if (i > 1) {
             ld6(Sp, n, sp);
