@@ -172,10 +172,11 @@ def source_hash():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(workload, apply_mode=0):
-    """HBM bytes per launch of the level-0 H-product from the committed
-    counter summary (profiles/pcg_apply_<workload>[_nb]_traffic.txt), or
-    None if it is missing or was taken on a different kernel source."""
+def measured_traffic(workload, apply_mode, kernel):
+    """HBM bytes per launch of `kernel` (the level-0 PCG iteration kernel the
+    run timed) from the committed counter summary
+    (profiles/pcg_apply_<workload>[_nb]_traffic.txt), or None if it is
+    missing, lacks that kernel or was taken on a different kernel source."""
     tag = "_nb" if apply_mode >= 1 else ""
     path = os.path.join(ROOT, "profiles", f"pcg_apply_{workload}{tag}_traffic.txt")
     if not os.path.exists(path):
@@ -187,7 +188,15 @@ def measured_traffic(workload, apply_mode=0):
             vals[k.strip()] = v.strip()
     if vals.get("source_sha256") != source_hash():
         return None
-    return int(vals["traffic_bytes_per_launch"])
+    v = vals.get(f"traffic_bytes_per_launch[{kernel}]")
+    return int(v) if v is not None else None
+
+
+def pcg_kernel_name(batched, apply_mode, stride, variant):
+    """The name of the PCG iteration kernel (k_pcg<B, FIRST, S, V>) as the
+    traces and counter summaries print it."""
+    S = 0 if apply_mode >= 1 else stride
+    return f"k_pcg<{'true' if batched else 'false'}, false, {S}, {variant}>"
 
 
 def equal_epe_sweeps(run, full):
@@ -574,12 +583,13 @@ def trace_summary(path, focus=("k_",)):
         print(f"  {k:44s} grid {g:9d}: calls {c:6d}, avg {t / c:8.2f} us")
 
 
-def traffic_report(fetch_csv, write_csv, kernel, copy_mib):
-    """HBM bytes per launch of `kernel` (its largest launch grid) from two
-    rocprofv3 counter CSVs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each
-    counter scaled by what it reads for the copy probe of copy_mib MiB
-    (which reads and writes exactly that much).  Prints the summary that
-    bench.py reads back as roofline.traffic."""
+def traffic_report(fetch_csv, write_csv, kernels, copy_mib):
+    """HBM bytes per launch of each kernel in `kernels` (its largest launch
+    grid; every k_pcg iteration kernel in the files if `kernels` is empty)
+    from two rocprofv3 counter CSVs (FETCH_SIZE, WRITE_SIZE; KiB per
+    dispatch), each counter scaled by what it reads for the copy probe of
+    copy_mib MiB (which reads and writes exactly that much).  Prints the
+    summary that bench.py reads back as roofline.traffic."""
     import collections
     import csv
 
@@ -597,17 +607,19 @@ def traffic_report(fetch_csv, write_csv, kernel, copy_mib):
                  key=lambda v: abs(v - expect))
     copy_f = max(v for (k, g), vs in f.items() if "copyBuffer" in k for v in vs)
     ff, fw = expect / copy_f, expect / copy_w
-    key = max((kg for kg in f if kg[0] == kernel), key=lambda kg: kg[1])
-    mf = float(np.mean(f[key]))
-    mw = float(np.mean(w[key]))
-    traffic = int(round((mf * ff + mw * fw) * 1024))
+    if not kernels:
+        kernels = sorted({k for k, g in f if k.startswith("k_pcg<") and ", false, " in k})
     print(f"# copy probe {copy_mib} MiB: FETCH_SIZE reads {copy_f:.1f} KiB (factor {ff:.4f}), "
           f"WRITE_SIZE reads {copy_w:.1f} KiB (factor {fw:.4f})")
-    print(f"# {kernel}, launch grid {key[1]} threads: FETCH_SIZE {mf:.1f} KiB, WRITE_SIZE "
-          f"{mw:.1f} KiB per dispatch (means over {len(f[key])} / {len(w[key])} dispatches)")
-    print(f"kernel = {kernel}")
     print(f"source_sha256 = {source_hash()}")
-    print(f"traffic_bytes_per_launch = {traffic}")
+    for kernel in kernels:
+        key = max((kg for kg in f if kg[0] == kernel), key=lambda kg: kg[1])
+        mf = float(np.mean(f[key]))
+        mw = float(np.mean(w[key]))
+        traffic = int(round((mf * ff + mw * fw) * 1024))
+        print(f"# {kernel}, launch grid {key[1]} threads: FETCH_SIZE {mf:.1f} KiB, WRITE_SIZE "
+              f"{mw:.1f} KiB per dispatch (means over {len(f[key])} / {len(w[key])} dispatches)")
+        print(f"traffic_bytes_per_launch[{kernel}] = {traffic}")
 
 
 def main():
@@ -654,15 +666,19 @@ def main():
                          "calibration under rocprofv3 --pmc)")
     ap.add_argument("--trace-summary", metavar="CSV",
                     help="summarise a rocprofv3 kernel-trace or counter CSV and exit")
-    ap.add_argument("--traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL"),
-                    help="HBM traffic per launch of KERNEL from two counter CSVs "
-                         "(calibrated by the copy probe) and exit")
+    ap.add_argument("--traffic", nargs="+", metavar="CSV_OR_KERNEL",
+                    help="FETCH_CSV WRITE_CSV [KERNEL ...]: HBM traffic per launch of each "
+                         "KERNEL (default: every PCG iteration kernel in the files) from two "
+                         "counter CSVs (calibrated by the copy probe) and exit")
     args = ap.parse_args()
     if args.trace_summary:
         trace_summary(args.trace_summary)
         return
     if args.traffic:
-        traffic_report(*args.traffic, copy_mib=args.copy_probe_mib or 512)
+        if len(args.traffic) < 2:
+            ap.error("--traffic needs FETCH_CSV WRITE_CSV [KERNEL ...]")
+        traffic_report(args.traffic[0], args.traffic[1], args.traffic[2:],
+                       copy_mib=args.copy_probe_mib or 512)
         return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU "
@@ -777,6 +793,8 @@ def main():
     achieved = bytes_apply / (avg_ms * 1e-3) / 1e9
     per_level = [round(sf.sf_time_kernel(solver.ctx, sf.SF_KERNEL_APPLY, l, reps) * 1e3, 2)
                  for l in range(params["levels"])]
+    kernel0 = pcg_kernel_name(False, args.apply_mode, params["grid_stride"],
+                              sf.sf_tile_variant(solver.ctx, False, 0))
 
     result = {
         "metric": METRIC,
@@ -797,11 +815,11 @@ def main():
         "frames_per_s": round(1e3 / ms, 2),
         "wall_ms_per_frame": round(wall * 1e3 / args.steps, 4),
         "roofline": {"bound": "hbm",
-                     "kernel": ("k_pcg node-block H p" if args.apply_mode >= 1
-                                else "k_pcg matrix-free H p") + " at level 0",
+                     "kernel": kernel0 + (" (node-block" if args.apply_mode >= 1
+                                          else " (matrix-free") + " H p at level 0)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": (measured_traffic(args.workload, args.apply_mode)
+                     "traffic": (measured_traffic(args.workload, args.apply_mode, kernel0)
                                  if args.exec_mode == 0 and params == dict(
                                      w["params"], apply_mode=args.apply_mode) else None),
                      "bytes_per_launch": bytes_apply,
@@ -984,6 +1002,8 @@ def run_batch(args, workload):
         N0, G0 = level_sizes(W, H, L, params["grid_stride"])[0][2:]
         bytes_apply += apply_bytes(N0, G0, args.apply_mode, batched=True)
     achieved = bytes_apply / (avg_ms * 1e-3) / 1e9
+    kernel0 = pcg_kernel_name(True, args.apply_mode, params["grid_stride"],
+                              sf.sf_tile_variant(solver.ctx, True, 0))
     ms_frame = total_ms / (args.steps * n)
     sizes = {f"{W}x{H}": res.count((W, H)) for W, H in sorted(set(res))}
     result = {
@@ -1007,11 +1027,11 @@ def run_batch(args, workload):
         "batch_ms_p99": round(float(np.percentile(per_batch, 99)), 3),
         "wall_ms_per_batch": round(wall * 1e3 / args.steps, 3),
         "roofline": {"bound": "hbm",
-                     "kernel": ("k_pcg node-block H p" if args.apply_mode >= 1
-                                else "k_pcg matrix-free H p") + " at level 0, all frames",
+                     "kernel": kernel0 + (" (node-block" if args.apply_mode >= 1
+                                          else " (matrix-free") + " H p at level 0, all frames)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("batch", args.apply_mode),
+                     "traffic": measured_traffic("batch", args.apply_mode, kernel0),
                      "bytes_per_launch": bytes_apply,
                      "avg_us_per_launch": round(avg_ms * 1e3, 2)},
     }

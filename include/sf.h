@@ -482,6 +482,14 @@ sf_status sf_time_kernel(sf_ctx *ctx, int kernel, int level, int reps,
 sf_status sf_time_batch_kernel(sf_ctx *ctx, int kernel, int level, int reps,
                                float *avg_ms);
 
+/* The tile shape of the PCG iteration kernel at `level` that the last solve
+ * (batched = 0) or batch (batched = 1) used, as chosen by tile_mode and the
+ * autotuner: *variant = V of k_pcg<B, FIRST, S, V> (node-block modes: 8 x 8,
+ * 16 x 8, 8 x 4, 4 x 4 nodes for 0..3).  Lets measurements name the kernel
+ * they report.  Errors: SF_ERR_STATE before the first solve / batch,
+ * SF_ERR_INVALID_ARG. */
+sf_status sf_tile_variant(sf_ctx *ctx, int batched, int level, int *variant);
+
 #ifdef __cplusplus
 }
 #endif

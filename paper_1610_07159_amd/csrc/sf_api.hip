@@ -1547,4 +1547,15 @@ sf_status sf_time_batch_kernel(sf_ctx *c, int kernel, int level, int reps, float
     return time_kernel(c->stream, *c->batch, kernel, level, reps, avg_ms);
 }
 
+sf_status sf_tile_variant(sf_ctx *c, int batched, int level, int *variant) {
+    if (!c || !variant) return SF_ERR_INVALID_ARG;
+    const Plan *P = batched ? c->batch : &c->single;
+    if (!P || !P->have_inputs) return SF_ERR_STATE;
+    if (level < 0 || level >= P->Lmax) return SF_ERR_INVALID_ARG;
+    // node-block tiles carry SF_TILE_NB + their shape index
+    const int v = P->ptile[level].v;
+    *variant = v >= SF_TILE_NB ? v - SF_TILE_NB : v;
+    return SF_OK;
+}
+
 }  // extern "C"

@@ -118,6 +118,7 @@ def _load():
     lib.sf_debug_run.argtypes = [P, I, I]
     lib.sf_time_kernel.argtypes = [P, I, I, I, ctypes.POINTER(ctypes.c_float)]
     lib.sf_time_batch_kernel.argtypes = [P, I, I, I, ctypes.POINTER(ctypes.c_float)]
+    lib.sf_tile_variant.argtypes = [P, I, I, ctypes.POINTER(I)]
     lib.sf_batch_levels.argtypes = [I, I, I]
     lib.sf_solve_batch.argtypes = [P, I, ctypes.POINTER(sf_frame),
                                    ctypes.POINTER(sf_params)]
@@ -151,7 +152,7 @@ def _load():
         getattr(lib, f).restype = I
     for f in ("sf_params_default", "sf_create", "sf_solve", "sf_get_log",
               "sf_debug_read", "sf_debug_write", "sf_debug_set_images",
-              "sf_debug_run", "sf_time_kernel", "sf_time_batch_kernel",
+              "sf_debug_run", "sf_time_kernel", "sf_time_batch_kernel", "sf_tile_variant",
               "sf_batch_levels", "sf_solve_batch", "sf_get_batch_log"):
         getattr(lib, f).restype = I
     return lib
@@ -320,6 +321,15 @@ def sf_time_kernel(ctx, kernel, level, reps) -> float:
     _check(lib.sf_time_kernel(ctx, kernel, level, reps, ctypes.byref(ms)),
            "sf_time_kernel")
     return ms.value
+
+
+def sf_tile_variant(ctx, batched, level) -> int:
+    """The PCG iteration kernel's tile variant V at `level` of the last
+    solve (batched False) or batch (True)."""
+    v = ctypes.c_int(-1)
+    _check(lib.sf_tile_variant(ctx, 1 if batched else 0, level, ctypes.byref(v)),
+           "sf_tile_variant")
+    return v.value
 
 
 def sf_time_batch_kernel(ctx, kernel, level, reps) -> float:

@@ -89,3 +89,5 @@ def test_batch_levels_rule_and_validation_without_gpu():
     assert lib.sf_get_batch_log(None, 0, None, 0, ctypes.byref(n)) == -1
     ms = ctypes.c_float()
     assert lib.sf_time_batch_kernel(None, 0, 0, 1, ctypes.byref(ms)) == -1
+    v = ctypes.c_int(-1)
+    assert lib.sf_tile_variant(None, 0, 0, ctypes.byref(v)) == -1
