@@ -28,9 +28,11 @@
 // Per-node system-matrix blocks (the node-block apply mode): for each node
 // n = (i, j) the symmetric 6x6 blocks H_nm = sum_x a_n(x) a_m(x) G(x) of its
 // pairs with m = n, (i+1, j), (i, j+1), (i+1, j+1), (i-1, j+1), in that
-// order, each in the gram record layout (24 floats).
+// order, each as the 21 entries of a gram record: the first 20 of block k
+// at floats 20 k .. 20 k + 19 of the node's record (five aligned float4),
+// its last at float 100 + k, then 3 floats of padding (432 bytes a node).
 #define SF_BLK_TYPES 5
-#define SF_BLK_STRIDE (SF_BLK_TYPES * SF_GRAM_STRIDE)
+#define SF_BLK_STRIDE (SF_BLK_TYPES * 20 + 8)
 // the test interface's plane layout: 6 gradient planes, then the 21
 // upper-triangular entries of the block row by row
 #define SF_REC_PLANES 27

@@ -1027,6 +1027,30 @@ __device__ TileLds tile_lds(float *lds, const TileCfg &t, int s, int K) {
     return L;
 }
 
+// LDS of the block-assembly kernel: the bracket tables and the pixel
+// records of a tile's largest region, (n + 1) s pixels wide and high (one
+// more for odd s), and nothing else, so that more of its workgroups fit on
+// a compute unit.
+__host__ __device__ inline int blk_rxm(const TileCfg &t, int s) { return (t.tx + 1) * s + (s & 1); }
+__host__ __device__ inline int blk_rym(const TileCfg &t, int s) { return (t.ty + 1) * s + (s & 1); }
+__host__ __device__ inline int blk_pitch(const TileCfg &t, int s) {
+    return (blk_rxm(t, s) * rec_pad(27) + 31) / 32 * 32 + 4;
+}
+__host__ __device__ inline size_t blk_lds_floats(const TileCfg &t, int s) {
+    return 4 * (size_t)blk_rxm(t, s) + 4 * (size_t)blk_rym(t, s) +
+           (size_t)blk_pitch(t, s) * blk_rym(t, s);
+}
+__device__ TileLds blk_lds(float *lds, const TileCfg &t, int s) {
+    TileLds L;
+    L.bx = reinterpret_cast<float4 *>(lds);
+    L.by = L.bx + blk_rxm(t, s);
+    L.pitch = blk_pitch(t, s);
+    L.vals = reinterpret_cast<float *>(L.by + blk_rym(t, s));
+    L.halo = nullptr;
+    L.ownd = nullptr;
+    return L;
+}
+
 __device__ void tile_brackets(const LevelArgs &a, const TileGeom &g, const TileLds &L) {
     for (int u = threadIdx.x; u < g.RX; u += blockDim.x) {
         const Bracket b = bracket(g.X0 + u, a.s, a.d.Gx);
@@ -1058,6 +1082,29 @@ __device__ __forceinline__ void rec_store(float *p, const float (&v)[K]) {
     for (int m = 0; m < rec_pad(K) / 4; ++m)
         p4[m] = make_float4(v[4 * m], 4 * m + 1 < K ? v[4 * m + 1] : 0.f,
                             4 * m + 2 < K ? v[4 * m + 2] : 0.f, 4 * m + 3 < K ? v[4 * m + 3] : 0.f);
+}
+
+// Block k of node n's record in the node-block layout (SF_BLK_STRIDE).
+__device__ __forceinline__ void blk_load(const float *blk, long n, int k, float (&v)[21]) {
+    const float *p = blk + n * SF_BLK_STRIDE;
+    const float4 *p4 = reinterpret_cast<const float4 *>(p + 20 * k);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+        const float4 t4 = p4[m];
+        v[4 * m] = t4.x;
+        v[4 * m + 1] = t4.y;
+        v[4 * m + 2] = t4.z;
+        v[4 * m + 3] = t4.w;
+    }
+    v[20] = p[100 + k];
+}
+__device__ __forceinline__ void blk_store(float *blk, long n, int k, const float (&v)[21]) {
+    float *p = blk + n * SF_BLK_STRIDE;
+    float4 *p4 = reinterpret_cast<float4 *>(p + 20 * k);
+#pragma unroll
+    for (int m = 0; m < 5; ++m)
+        p4[m] = make_float4(v[4 * m], v[4 * m + 1], v[4 * m + 2], v[4 * m + 3]);
+    p[100 + k] = v[20];
 }
 
 // (unrolled so that the loads of several pixels are in flight together:
@@ -1422,7 +1469,7 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, Til
     SF_BIND(ka);
     const LevelDims &d = a.d;
     const TileGeom g = tile_geom(a, t, bid);
-    const TileLds L = tile_lds(lds, t, S, 27);
+    const TileLds L = blk_lds(lds, t, S);
     constexpr int TPN = BlkShape<S>::TPN;
     const int nl = threadIdx.x / TPN, sub = threadIdx.x % TPN;
     const bool valid = nl < g.txa * g.tya;
@@ -1526,7 +1573,6 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, Til
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k) gs[k] = group_sum<float>(gs[k], TPN);
-    float *dst = a.blk + n * SF_BLK_STRIDE;
     float sd[6];
 #pragma unroll
     for (int kb = 0; kb < SF_BLK_TYPES; ++kb) {
@@ -1541,7 +1587,7 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, Til
 #pragma unroll
             for (int q = 0; q < 6; ++q) sd[q] = o[gram_index(q, q)];
         }
-        if (valid && sub == kb % TPN) rec_store<21>(dst + kb * SF_GRAM_STRIDE, o);
+        if (valid && sub == kb % TPN) blk_store(a.blk, n, kb, o);
     }
     if (mine) nd.finish<S>(a, i, j, n, gs, sd, redo);
 }
@@ -1774,7 +1820,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
             if (valid && k >= 0 && pi >= 0 && pi < d.Gx && pj >= 0 && pj < d.Gy) {
                 bu[q] = (tj + 1 + pj - j_n) * HX + (ti + 1 + pi - i_n);
                 const long owner = own ? n_own : (long)pj * d.Gx + pi;
-                rec_load<21>(a.blk + owner * SF_BLK_STRIDE + k * SF_GRAM_STRIDE, Bk[q]);
+                blk_load(a.blk, owner, k, Bk[q]);
             }
         }
     }
@@ -2174,7 +2220,7 @@ __global__ __launch_bounds__(SMALL_NT) void k_pcg_small(KArg<B> ka, int n_it, in
         for (int e = 0; e < 21; ++e) t[e] = 0.f;
         if (has) {
             const long owner = own ? (long)n : (long)pn[q];
-            rec_load<21>(a.blk + owner * SF_BLK_STRIDE + k * SF_GRAM_STRIDE, t);
+            blk_load(a.blk, owner, k, t);
         }
         if (q < 2) {
 #pragma unroll
@@ -2549,7 +2595,7 @@ __global__ __launch_bounds__(PT_NT) void k_pcg_tile(LevelArgs a, int n_it, int g
         for (int e = 0; e < 21; ++e) Bk[q][e] = 0.f;
         if (has) {
             const long owner = own ? n : (long)pj * d.Gx + pi;
-            rec_load<21>(a.blk + owner * SF_BLK_STRIDE + k * SF_GRAM_STRIDE, Bk[q]);
+            blk_load(a.blk, owner, k, Bk[q]);
         }
     }
     float cnb[4] = {0.f, 0.f, 0.f, 0.f}, J0o[2] = {0.f, 0.f}, J1o[2] = {0.f, 0.f};
@@ -3474,7 +3520,7 @@ TileCfg pick_blk_tile(int s) {
     return blk_tile_of<8>();
 }
 
-size_t blk_tile_lds_bytes(int s) { return node_tile_lds_bytes(pick_blk_tile(s), s, 27); }
+size_t blk_tile_lds_bytes(int s) { return blk_lds_floats(pick_blk_tile(s), s) * sizeof(float); }
 
 int tile_threads(const TileCfg &t) { return t.tx * t.ty * t.tpn; }
 
@@ -3633,7 +3679,7 @@ void launch_rhs_blocks(hipStream_t st, const Launch &L, int n_pend, int gn_prev,
     auto nb = [t](const LevelArgs &a) { return node_tiles_of(a.d, t); };
 #define BLK(S)                                                                            \
     go(st, L, nb, k_rhs_blocks<true, S>, k_rhs_blocks<false, S>, BlkTraits<S>::NT,        \
-       node_tile_lds_bytes(t, S, 27), t, n_pend, gn_prev, pcg_iters)
+       blk_tile_lds_bytes(S), t, n_pend, gn_prev, pcg_iters)
     SF_STRIDE_SWITCH(s, BLK)
 #undef BLK
 }
