@@ -1764,8 +1764,14 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     double pacc[3] = {0.0, 0.0, 0.0};
     PcgHist h;
     h.gamma = 0.0; h.alpha = 0.f; h.beta = 0.f; h.active = 1; h.pad = 0;
+    // Many partial sums (batched launches; the level-0 tiles of a single
+    // frame): wavefront 0 reduces them and decides, the others read the
+    // scalars from LDS after a barrier, instead of every wavefront loading
+    // every partial.  Few partials: each wavefront decides itself, which
+    // spares the barrier.  Either way every thread gets the same scalars.
+    const bool w0_decides = B || nb_prev > 256;
     if (!FIRST) {
-        load_pcg_partials(a, i, nb_prev, pacc);
+        if (!w0_decides || tid < 64) load_pcg_partials(a, i, nb_prev, pacc);
         h = a.sc->hist[i - 1];
     }
     // owned node of this thread's node group
@@ -1891,7 +1897,24 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     PcgHist rec;
     double rr_prev = 0.0;
     if (!FIRST) {
-        pcg_decide(i, pacc, h, force, alpha, beta, act, rec, rr_prev);
+        if (w0_decides) {
+            __shared__ float s_ab[2];
+            __shared__ int s_act;
+            if (tid < 64) {
+                pcg_decide(i, pacc, h, force, alpha, beta, act, rec, rr_prev);
+                if (tid == 0) {
+                    s_ab[0] = alpha;
+                    s_ab[1] = beta;
+                    s_act = act;
+                }
+            }
+            __syncthreads();
+            alpha = s_ab[0];
+            beta = s_ab[1];
+            act = s_act;
+        } else {
+            pcg_decide(i, pacc, h, force, alpha, beta, act, rec, rr_prev);
+        }
         if (!act) {
             carry_partials(a, bid, i);
             if (bid == 0 && tid == 0) record_decision(a, i, log_index, rec, rr_prev);
