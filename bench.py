@@ -14,6 +14,7 @@ same workload on the host.
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -172,31 +173,41 @@ def source_hash():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(workload, apply_mode, kernel):
-    """HBM bytes per launch of `kernel` (the level-0 PCG iteration kernel the
-    run timed) from the committed counter summary
-    (profiles/pcg_apply_<workload>[_nb]_traffic.txt), or None if it is
-    missing, lacks that kernel or was taken on a different kernel source."""
+def measured_traffic(workload, apply_mode, prefix):
+    """(name, HBM bytes per launch) of the level-0 PCG iteration kernel the
+    run timed, from the committed counter summary
+    (profiles/pcg_apply_<workload>[_nb]_traffic.txt): of the kernels whose
+    name starts with `prefix` (k_pcg<B, false, S, V, the last template
+    argument, WD, follows from the launch's size), the one of the largest
+    launch grid, which is level 0.  (None, None) if the summary is missing,
+    lacks such a kernel or was taken on a different kernel source."""
     tag = "_nb" if apply_mode >= 1 else ""
     path = os.path.join(ROOT, "profiles", f"pcg_apply_{workload}{tag}_traffic.txt")
     if not os.path.exists(path):
-        return None
-    vals = {}
+        return None, None
+    vals, grids = {}, {}
     for line in open(path):
-        if "=" in line and not line.startswith("#"):
+        m = re.match(r"# (k_pcg<[^>]*>), launch grid (\d+) threads", line)
+        if m:
+            grids[m.group(1)] = int(m.group(2))
+        elif "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
     if vals.get("source_sha256") != source_hash():
-        return None
-    v = vals.get(f"traffic_bytes_per_launch[{kernel}]")
-    return int(v) if v is not None else None
+        return None, None
+    names = [k for k in grids if k.startswith(prefix + ",")
+             and f"traffic_bytes_per_launch[{k}]" in vals]
+    if not names:
+        return None, None
+    name = max(names, key=lambda k: grids[k])
+    return name, int(vals[f"traffic_bytes_per_launch[{name}]"])
 
 
-def pcg_kernel_name(batched, apply_mode, stride, variant):
-    """The name of the PCG iteration kernel (k_pcg<B, FIRST, S, V>) as the
-    traces and counter summaries print it."""
+def pcg_kernel_prefix(batched, apply_mode, stride, variant):
+    """The PCG iteration kernel k_pcg<B, FIRST, S, V, WD> as the traces and
+    counter summaries print it, up to its last template argument."""
     S = 0 if apply_mode >= 1 else stride
-    return f"k_pcg<{'true' if batched else 'false'}, false, {S}, {variant}>"
+    return f"k_pcg<{'true' if batched else 'false'}, false, {S}, {variant}"
 
 
 def equal_epe_sweeps(run, full):
@@ -793,8 +804,11 @@ def main():
     achieved = bytes_apply / (avg_ms * 1e-3) / 1e9
     per_level = [round(sf.sf_time_kernel(solver.ctx, sf.SF_KERNEL_APPLY, l, reps) * 1e3, 2)
                  for l in range(params["levels"])]
-    kernel0 = pcg_kernel_name(False, args.apply_mode, params["grid_stride"],
-                              sf.sf_tile_variant(solver.ctx, False, 0))
+    prefix0 = pcg_kernel_prefix(False, args.apply_mode, params["grid_stride"],
+                                sf.sf_tile_variant(solver.ctx, False, 0))
+    kernel0, traffic0 = measured_traffic(args.workload, args.apply_mode, prefix0)
+    if not (args.exec_mode == 0 and params == dict(w["params"], apply_mode=args.apply_mode)):
+        kernel0, traffic0 = None, None  # the counters cover the default configuration only
 
     result = {
         "metric": METRIC,
@@ -815,13 +829,12 @@ def main():
         "frames_per_s": round(1e3 / ms, 2),
         "wall_ms_per_frame": round(wall * 1e3 / args.steps, 4),
         "roofline": {"bound": "hbm",
-                     "kernel": kernel0 + (" (node-block" if args.apply_mode >= 1
-                                          else " (matrix-free") + " H p at level 0)",
+                     "kernel": (kernel0 or prefix0 + ", ...>") + (
+                         " (node-block" if args.apply_mode >= 1 else " (matrix-free")
+                     + " H p at level 0)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": (measured_traffic(args.workload, args.apply_mode, kernel0)
-                                 if args.exec_mode == 0 and params == dict(
-                                     w["params"], apply_mode=args.apply_mode) else None),
+                     "traffic": traffic0,
                      "bytes_per_launch": bytes_apply,
                      "avg_us_per_launch": round(bytes_apply / achieved / 1e3, 2),
                      "apply_us_per_level": per_level},
@@ -1002,8 +1015,9 @@ def run_batch(args, workload):
         N0, G0 = level_sizes(W, H, L, params["grid_stride"])[0][2:]
         bytes_apply += apply_bytes(N0, G0, args.apply_mode, batched=True)
     achieved = bytes_apply / (avg_ms * 1e-3) / 1e9
-    kernel0 = pcg_kernel_name(True, args.apply_mode, params["grid_stride"],
-                              sf.sf_tile_variant(solver.ctx, True, 0))
+    prefix0 = pcg_kernel_prefix(True, args.apply_mode, params["grid_stride"],
+                                sf.sf_tile_variant(solver.ctx, True, 0))
+    kernel0, traffic0 = measured_traffic("batch", args.apply_mode, prefix0)
     ms_frame = total_ms / (args.steps * n)
     sizes = {f"{W}x{H}": res.count((W, H)) for W, H in sorted(set(res))}
     result = {
@@ -1027,11 +1041,12 @@ def run_batch(args, workload):
         "batch_ms_p99": round(float(np.percentile(per_batch, 99)), 3),
         "wall_ms_per_batch": round(wall * 1e3 / args.steps, 3),
         "roofline": {"bound": "hbm",
-                     "kernel": kernel0 + (" (node-block" if args.apply_mode >= 1
-                                          else " (matrix-free") + " H p at level 0, all frames)",
+                     "kernel": (kernel0 or prefix0 + ", ...>") + (
+                         " (node-block" if args.apply_mode >= 1 else " (matrix-free")
+                     + " H p at level 0, all frames)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("batch", args.apply_mode, kernel0),
+                     "traffic": traffic0,
                      "bytes_per_launch": bytes_apply,
                      "avg_us_per_launch": round(avg_ms * 1e3, 2)},
     }

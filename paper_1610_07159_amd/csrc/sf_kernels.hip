@@ -1728,7 +1728,12 @@ __device__ __forceinline__ void deferred_step(const LevelArgs &a, long n, float 
 // force: later iterations are applied even if inactive (kernel timing);
 // in the first kernel (node-block form) it means that a speculative step
 // precedes, whose deferred part (if tau = 1 was rejected) happens here.
-template <bool B, bool FIRST, int S, int V>
+// Single-frame iteration launches of more tiles than this reduce the
+// previous iteration's partial sums in wavefront 0 (WD; batched launches
+// always do).
+#define SF_WD_TILES 256
+
+template <bool B, bool FIRST, int S, int V, bool WD>
 __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, TileCfg t, int i,
                                                               int gn, int force) {
     constexpr int NT_TILE = TileTraits<S, V>::NT;
@@ -1764,12 +1769,13 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     double pacc[3] = {0.0, 0.0, 0.0};
     PcgHist h;
     h.gamma = 0.0; h.alpha = 0.f; h.beta = 0.f; h.active = 1; h.pad = 0;
-    // Many partial sums (batched launches; the level-0 tiles of a single
-    // frame): wavefront 0 reduces them and decides, the others read the
-    // scalars from LDS after a barrier, instead of every wavefront loading
-    // every partial.  Few partials: each wavefront decides itself, which
-    // spares the barrier.  Either way every thread gets the same scalars.
-    const bool w0_decides = B || nb_prev > 256;
+    // WD (many partial sums: batched launches, single-frame launches of more
+    // than SF_WD_TILES tiles): wavefront 0 reduces them and decides, the
+    // others read the scalars from LDS after a barrier, instead of every
+    // wavefront loading every partial.  Few partials: each wavefront
+    // decides itself, which spares the barrier.  Either way every thread
+    // gets the same scalars.
+    constexpr bool w0_decides = WD;
     if (!FIRST) {
         if (!w0_decides || tid < 64) load_pcg_partials(a, i, nb_prev, pacc);
         h = a.sc->hist[i - 1];
@@ -3676,9 +3682,9 @@ void launch_pcg_first(hipStream_t st, const Launch &L, const TileCfg &t, bool sk
         return skip_small && small_frame(a) ? 0 : node_tiles_of(a.d, t);
     };
     const int s = L.host[0].s;
-#define PCG0(S, V)                                                                            \
-    go(st, L, nb, k_pcg<true, true, S, V>, k_pcg<false, true, S, V>, TileTraits<S, V>::NT,    \
-       node_tile_lds_bytes(t, S, 6), t, 0, -1, pend ? 1 : 0)
+#define PCG0(S, V)                                                                         \
+    go(st, L, nb, k_pcg<true, true, S, V, true>, k_pcg<false, true, S, V, false>,          \
+       TileTraits<S, V>::NT, node_tile_lds_bytes(t, S, 6), t, 0, -1, pend ? 1 : 0)
     SF_PCG_SWITCH(s, t.v, PCG0)
 #undef PCG0
 }
@@ -3689,9 +3695,16 @@ void launch_pcg_iter(hipStream_t st, const Launch &L, const TileCfg &t, int iter
         return skip_small && small_frame(a) ? 0 : node_tiles_of(a.d, t);
     };
     const int s = L.host[0].s;
-#define PCGI(S, V)                                                                            \
-    go(st, L, nb, k_pcg<true, false, S, V>, k_pcg<false, false, S, V>, TileTraits<S, V>::NT,  \
-       node_tile_lds_bytes(t, S, 6), t, iter, gn, force)
+    // the single-frame variant by the number of partial sums it reduces
+    // (the previous iteration ran on the same tiles)
+    const bool wd = !L.batched && nb(L.host[0]) > SF_WD_TILES;
+#define PCGI(S, V)                                                                         \
+    if (wd)                                                                                \
+        go(st, L, nb, k_pcg<true, false, S, V, true>, k_pcg<false, false, S, V, true>,     \
+           TileTraits<S, V>::NT, node_tile_lds_bytes(t, S, 6), t, iter, gn, force);        \
+    else                                                                                   \
+        go(st, L, nb, k_pcg<true, false, S, V, true>, k_pcg<false, false, S, V, false>,    \
+           TileTraits<S, V>::NT, node_tile_lds_bytes(t, S, 6), t, iter, gn, force)
     SF_PCG_SWITCH(s, t.v, PCGI)
 #undef PCGI
 }
