@@ -1802,8 +1802,10 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     // Single-frame launches load the blocks here, with the other loads that
     // do not depend on the scalars (one memory round trip).  Batched
     // launches, whose speed follows how many workgroups fit on a CU, load
-    // each block just before its product: 118 instead of 154 registers
-    // (93 instead of 120 for the first kernel), one more wavefront per SIMD.
+    // each block just before its product (and the regulariser record and
+    // the owned node's vectors where they are used): 96 instead of 154
+    // registers (93 instead of 120 for the first kernel), five wavefronts
+    // per SIMD instead of three.
     const int npx = S > 0 ? g.RX * g.RY : 0;
     float Gm[PPT][SF_GRAM_STRIDE];
     float Bk[3][21];
@@ -1873,9 +1875,10 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
             ld6(D, hn, hv3);
         }
     }
-    // the owned node's regulariser record
+    // the owned node's regulariser record (batched launches: where it is
+    // used, as their blocks)
     float rg[REG_PLANES];
-    if (mine) {
+    auto load_rg = [&]() {
 #pragma unroll
         for (int k = 0; k < REG_PLANES / 4; ++k) {
             const float4 t4 = reinterpret_cast<const float4 *>(a.reg + n_own * REG_PLANES)[k];
@@ -1884,11 +1887,12 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
             rg[4 * k + 2] = t4.z;
             rg[4 * k + 3] = t4.w;
         }
-    }
+    };
+    if (mine && !B) load_rg();
     // the owned node's u, p and x: read here in single-frame launches (one
     // fewer dependent memory round trip, same occupancy); batched launches,
-    // which stream from HBM, read them after the LDS phases to keep the
-    // register count (and occupancy) lower
+    // which stream from HBM, read them just before the final reduction to
+    // keep the register count (and occupancy) lower
     // (u of iteration i-1: read here in single-frame launches; batched
     // launches, which stream from HBM, rebuild it as r / diag from the halo
     // records they read anyway, bitwise the same value, and neither read
@@ -2011,12 +2015,6 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     }
 
     // ---- phase 4: sums onto nodes, regularisers ----------------------------
-    if (B) load_own();
-    if (B && mine && !FIRST) {
-        const int o = tj * t.tx + ti;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) uo[q] = L.ownd[(2 + q) * t.tx * t.ty + o];
-    }
     float acc[6];
     if constexpr (S > 0) {
         lds_to_nodes<6, S, TileTraits<S, V>::TPN>(a, t, g, L, 0u, acc);
@@ -2042,6 +2040,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     float prt[3] = {0.f, 0.f, 0.f};
     float w6[6], uv[6];
     if (mine) {
+        if (B) load_rg();
         rec_load<6>(L.halo + (size_t)((tj + 1) * HX + ti + 1) * 8, uv);
         float jp0 = 0.f, jp1 = 0.f;
 #pragma unroll
@@ -2072,6 +2071,12 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
         prt[2] = L.ownd[t.tx * t.ty + o];
     }
     float tot3[3];
+    if (B) load_own();
+    if (B && mine && !FIRST) {
+        const int o = tj * t.tx + ti;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) uo[q] = L.ownd[(2 + q) * t.tx * t.ty + o];
+    }
     block_sum<3, false>(prt, tot3);
 
     // ---- stores ---------------------------------------------------------------
