@@ -1027,18 +1027,37 @@ __device__ TileLds tile_lds(float *lds, const TileCfg &t, int s, int K) {
     return L;
 }
 
-// LDS of the block-assembly kernel: the bracket tables and the pixel
-// records of a tile's largest region, (n + 1) s pixels wide and high (one
-// more for odd s), and nothing else, so that more of its workgroups fit on
-// a compute unit.
+// LDS of the block-assembly kernel: the bracket tables and, for each pixel
+// of a tile's largest region ((n + 1) s pixels wide and high, one more for
+// odd s), the 21 entries of its Gauss-Newton block (gram order) in a
+// 22-float record of 8-byte pairs; the pixel's gradient stays in global
+// memory.  Nothing else, so that more of its workgroups fit on a compute
+// unit (four at stride 4).
+#define BLK_REC 22
 __host__ __device__ inline int blk_rxm(const TileCfg &t, int s) { return (t.tx + 1) * s + (s & 1); }
 __host__ __device__ inline int blk_rym(const TileCfg &t, int s) { return (t.ty + 1) * s + (s & 1); }
 __host__ __device__ inline int blk_pitch(const TileCfg &t, int s) {
-    return (blk_rxm(t, s) * rec_pad(27) + 31) / 32 * 32 + 4;
+    return (blk_rxm(t, s) * BLK_REC + 31) / 32 * 32 + 4;
 }
 __host__ __device__ inline size_t blk_lds_floats(const TileCfg &t, int s) {
     return 4 * (size_t)blk_rxm(t, s) + 4 * (size_t)blk_rym(t, s) +
            (size_t)blk_pitch(t, s) * blk_rym(t, s);
+}
+__device__ __forceinline__ void blk_rec_store(float *p, const float (&v)[21]) {
+    float2 *p2 = reinterpret_cast<float2 *>(p);
+#pragma unroll
+    for (int m = 0; m < 10; ++m) p2[m] = make_float2(v[2 * m], v[2 * m + 1]);
+    p[20] = v[20];
+}
+__device__ __forceinline__ void blk_rec_load(const float *p, float (&v)[21]) {
+    const float2 *p2 = reinterpret_cast<const float2 *>(p);
+#pragma unroll
+    for (int m = 0; m < 10; ++m) {
+        const float2 t2 = p2[m];
+        v[2 * m] = t2.x;
+        v[2 * m + 1] = t2.y;
+    }
+    v[20] = p[20];
 }
 __device__ TileLds blk_lds(float *lds, const TileCfg &t, int s) {
     TileLds L;
@@ -1397,10 +1416,12 @@ __host__ __device__ inline void blk_offset(int k, int &di, int &dj) {
 }
 
 // Pixel records of a node tile's region at delta + tau dx, formed in place
-// of the linearisation kernel's (a rejected speculative step), and the
-// energies of the pixels this tile owns: each pixel belongs to the tile of
-// the node with the larger bilinear weight in each direction (the first on
-// a tie), so every pixel is counted once.
+// of the linearisation kernel's (a rejected speculative step): the blocks
+// into the tile's LDS, the gradients over the per-pixel gradient records
+// in global memory (a pixel shared with a neighbouring tile gets the same
+// value from both); and the energies of the pixels this tile owns: each
+// pixel belongs to the tile of the node with the larger bilinear weight in
+// each direction (the first on a tie), so every pixel is counted once.
 template <int S>
 __device__ void relin_pixels(const LevelArgs &a, const TileGeom &g, const TileLds &L, float tau,
                              float (&part)[5]) {
@@ -1443,14 +1464,15 @@ __device__ void relin_pixels(const LevelArgs &a, const TileGeom &g, const TileLd
             part[0] += o.e_photo;
             part[1] += o.e_grad;
         }
-        float v[27];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) v[q] = o.grad[q];
+        float v[21];
 #pragma unroll
         for (int r = 0; r < 6; ++r)
 #pragma unroll
-            for (int c = r; c < 6; ++c) v[6 + gram_index(r, c)] = o.gram[tri(r, c)];
-        rec_store<27>(L.vals + (size_t)ry * L.pitch + rx * rec_pad(27), v);
+            for (int c = r; c < 6; ++c) v[gram_index(r, c)] = o.gram[tri(r, c)];
+        blk_rec_store(L.vals + (size_t)ry * L.pitch + rx * BLK_REC, v);
+        float4 *rp = reinterpret_cast<float4 *>(a.grad + pix * SF_GRAD_STRIDE);
+        rp[0] = make_float4(o.grad[0], o.grad[1], o.grad[2], o.grad[3]);
+        rp[1] = make_float4(o.grad[4], o.grad[5], 0.f, 0.f);
     }
 }
 
@@ -1513,21 +1535,38 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, Til
             for (int k = 0; k < 5; ++k) a.partials[(long)(PS_E + k) * a.max_blocks + bid] = tot5[k];
         }
         if (mine) nd.load(a, i, j, n, tau);
-    } else
-    pixels_to_lds<27>(g, L, [&](int x, int y, int, int, float (&v)[27]) {
-        const long pix = (long)y * d.W + x;
-        const float4 *rp = reinterpret_cast<const float4 *>(a.grad + pix * SF_GRAD_STRIDE);
-        const float4 *gp = reinterpret_cast<const float4 *>(a.gram + pix * SF_GRAM_STRIDE);
-        const float4 r0 = rp[0], r1 = rp[1];
-        v[0] = r0.x; v[1] = r0.y; v[2] = r0.z; v[3] = r0.w; v[4] = r1.x; v[5] = r1.y;
+    } else {
+        // the region's blocks into LDS, two pixels in flight per thread
+        const int n_px = g.RX * g.RY;
+        for (int u0 = threadIdx.x; u0 < n_px; u0 += 2 * blockDim.x) {
+            float v[2][21];
 #pragma unroll
-        for (int m = 0; m < 5; ++m) {
-            const float4 t4 = gp[m];
-            v[6 + 4 * m] = t4.x; v[7 + 4 * m] = t4.y; v[8 + 4 * m] = t4.z; v[9 + 4 * m] = t4.w;
+            for (int q = 0; q < 2; ++q) {
+                // past the region: reload its first pixel, not stored
+                const int u = u0 + q * blockDim.x < n_px ? u0 + q * blockDim.x : 0;
+                const long pix = (long)(g.Y0 + u / g.RX) * d.W + g.X0 + u % g.RX;
+                const float4 *gp = reinterpret_cast<const float4 *>(a.gram + pix * SF_GRAM_STRIDE);
+#pragma unroll
+                for (int m = 0; m < 5; ++m) {
+                    const float4 t4 = gp[m];
+                    v[q][4 * m] = t4.x; v[q][4 * m + 1] = t4.y;
+                    v[q][4 * m + 2] = t4.z; v[q][4 * m + 3] = t4.w;
+                }
+                v[q][20] = gp[5].x;
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int u = u0 + q * blockDim.x;
+                if (u < n_px)
+                    blk_rec_store(L.vals + (size_t)(u / g.RX) * L.pitch + (u % g.RX) * BLK_REC, v[q]);
+            }
         }
-        v[26] = gp[5].x;
-    });
+    }
+    // the redo's gradient stores are read back below by other wavefronts
+    // of this workgroup
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     float gs[6], c0[21], cp[21], cm[21];
 #pragma unroll
     for (int k = 0; k < 6; ++k) gs[k] = 0.f;
@@ -1547,6 +1586,8 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, Til
             r_same = vj * vj;
             r_next = vj * vn;
             const float *row = L.vals + (size_t)ry * L.pitch;
+            const float4 *grow = reinterpret_cast<const float4 *>(
+                a.grad + ((long)(g.Y0 + ry) * d.W + g.X0) * SF_GRAD_STRIDE);
 #pragma unroll
             for (int c = 0; c < 2 * S; ++c) {
                 const int rx = xa + c;
@@ -1557,15 +1598,17 @@ __global__ __launch_bounds__(BlkTraits<S>::NT) void k_rhs_blocks(KArg<B> ka, Til
                     const float wm = i >= 1 ? bweight(b, i - 1, d.Gx) : 0.f;
                     const float w1 = wi * vj;
                     const float a0 = wi * wi, ap = wi * wp, am = wi * wm;
-                    float v[27];
-                    rec_load<27>(row + (size_t)rx * rec_pad(27), v);
+                    const float4 g0 = grow[2 * rx], g1 = grow[2 * rx + 1];
+                    const float gv[6] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y};
+                    float v[21];
+                    blk_rec_load(row + (size_t)rx * BLK_REC, v);
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) gs[k] += w1 * v[k];
+                    for (int k = 0; k < 6; ++k) gs[k] += w1 * gv[k];
 #pragma unroll
                     for (int k = 0; k < 21; ++k) {
-                        c0[k] += a0 * v[6 + k];
-                        cp[k] += ap * v[6 + k];
-                        cm[k] += am * v[6 + k];
+                        c0[k] += a0 * v[k];
+                        cp[k] += ap * v[k];
+                        cm[k] += am * v[k];
                     }
                 }
             }
