@@ -185,15 +185,24 @@ def measured_traffic(workload, apply_mode, prefix):
     path = os.path.join(ROOT, "profiles", f"pcg_apply_{workload}{tag}_traffic.txt")
     if not os.path.exists(path):
         return None, None
+    with open(path) as f:
+        return traffic_lookup(f.read().splitlines(), prefix, source_hash())
+
+
+def traffic_lookup(lines, prefix, sha):
+    """The (name, bytes per launch) entry of a counter summary (the lines
+    `bench.py --traffic` prints) for the kernel starting with `prefix` of
+    the largest launch grid; (None, None) unless the summary was taken on
+    kernel source `sha` and holds such a kernel."""
     vals, grids = {}, {}
-    for line in open(path):
+    for line in lines:
         m = re.match(r"# (k_pcg<[^>]*>), launch grid (\d+) threads", line)
         if m:
             grids[m.group(1)] = int(m.group(2))
         elif "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("source_sha256") != source_hash():
+    if vals.get("source_sha256") != sha:
         return None, None
     names = [k for k in grids if k.startswith(prefix + ",")
              and f"traffic_bytes_per_launch[{k}]" in vals]
