@@ -72,6 +72,38 @@ def test_batch_matches_single_frames_bitwise(stride, apply):
                                                 for _ in range(prm["gn_iters"])]
 
 
+def test_batch_rejected_speculative_step_matches_single_frame():
+    """A frame whose solve rejects tau = 1 in a speculative step (level 2,
+    Gauss-Newton step 8 of 10, tau = 1/2: the right-hand-side kernel forms
+    the pixel records at delta + tau dx itself, over eight tiles that share
+    region pixels, and writes the gradients it recomputes over the
+    per-pixel records) solves bitwise alike alone and inside a batch of
+    other frames, in every log entry and output."""
+    from paper_1610_07159_amd import sf
+    W, H = 160, 120
+    imgs, calib, _ = make_frame(sized_config(W, H, max_disp=0.12 * W), 134)
+    prm = dict(levels=4, grid_stride=4, gn_iters=10, pcg_iters=20)
+    L = sf.sf_batch_levels(W, H, prm["levels"])
+    frames = [(imgs, calib)] + _frames([(200, 150), (160, 120), (128, 96)], seed0=60)
+    (res, res2), logs = _batch(frames, exec_mode=0, repeat=2, **prm)
+    g = GpuCase(imgs, calib, exec_mode=1, **dict(prm, levels=L))
+    try:
+        single = g.solve()
+        slog, code = g.log()
+    finally:
+        g.close()
+    assert code == 0
+    rejected = [(r["level"], r["gn_iter"], r["tau"]) for r in slog
+                if r["tau"] < 1.0 and r["gn_iter"] < prm["gn_iters"] - 1]
+    assert rejected, "the frame no longer rejects a speculative step"
+    assert [r["energy"] for r in slog] == [r["energy"] for r in logs[0]]
+    assert [r["energy_after"] for r in slog] == [r["energy_after"] for r in logs[0]]
+    assert [r["tau"] for r in slog] == [r["tau"] for r in logs[0]]
+    for a, b, c in zip(single, res[0], res2[0]):
+        np.testing.assert_array_equal(a, b)
+        np.testing.assert_array_equal(b, c)
+
+
 def test_batch_direct_launches_match_graph_and_reshape():
     frames = _frames([(128, 96), (160, 120), (112, 80)], seed0=40)
     g_res, g_logs = _batch(frames, exec_mode=0, **PRM)
