@@ -605,7 +605,8 @@ def trace_summary(path, focus=("k_",)):
 
 def traffic_report(fetch_csv, write_csv, kernels, copy_mib):
     """HBM bytes per launch of each kernel in `kernels` (its largest launch
-    grid; every k_pcg iteration kernel in the files if `kernels` is empty)
+    grid found in both files; every k_pcg iteration kernel, FIRST = false,
+    in the files if `kernels` is empty)
     from two rocprofv3 counter CSVs (FETCH_SIZE, WRITE_SIZE; KiB per
     dispatch), each counter scaled by what it reads for the copy probe of
     copy_mib MiB (which reads and writes exactly that much).  Prints the
@@ -627,13 +628,19 @@ def traffic_report(fetch_csv, write_csv, kernels, copy_mib):
                  key=lambda v: abs(v - expect))
     copy_f = max(v for (k, g), vs in f.items() if "copyBuffer" in k for v in vs)
     ff, fw = expect / copy_f, expect / copy_w
+    # the counter runs autotune separately, so a kernel may run at a launch
+    # grid in one run only: use the grids both runs saw
     if not kernels:
-        kernels = sorted({k for k, g in f if k.startswith("k_pcg<") and ", false, " in k})
+        kernels = sorted({k for k, g in f if re.match(r"k_pcg<(true|false), false, ", k)
+                          and (k, g) in w})
     print(f"# copy probe {copy_mib} MiB: FETCH_SIZE reads {copy_f:.1f} KiB (factor {ff:.4f}), "
           f"WRITE_SIZE reads {copy_w:.1f} KiB (factor {fw:.4f})")
     print(f"source_sha256 = {source_hash()}")
     for kernel in kernels:
-        key = max((kg for kg in f if kg[0] == kernel), key=lambda kg: kg[1])
+        common = [kg for kg in f if kg[0] == kernel and kg in w]
+        if not common:
+            continue
+        key = max(common, key=lambda kg: kg[1])
         mf = float(np.mean(f[key]))
         mw = float(np.mean(w[key]))
         traffic = int(round((mf * ff + mw * fw) * 1024))

@@ -1775,8 +1775,12 @@ __device__ __forceinline__ void deferred_step(const LevelArgs &a, long n, float 
 // previous iteration's partial sums in wavefront 0 (WD; batched launches
 // always do).
 #define SF_WD_TILES 256
+// Single-frame node-block iteration launches of more threads than this
+// (two wavefronts per SIMD of the device) load their operands where they
+// are used (LATE; batched launches always do).
+#define SF_LATE_THREADS (2 * 64 * 1024)
 
-template <bool B, bool FIRST, int S, int V, bool WD>
+template <bool B, bool FIRST, int S, int V, bool WD, bool LATE>
 __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, TileCfg t, int i,
                                                               int gn, int force) {
     constexpr int NT_TILE = TileTraits<S, V>::NT;
@@ -1842,13 +1846,16 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     // S > 0: Gram blocks of this thread's region pixels; S = 0: the node
     // blocks of this thread's share of its node's nine block products, and
     // the halo records of the u they multiply (-1: no such neighbour).
-    // Single-frame launches load the blocks here, with the other loads that
-    // do not depend on the scalars (one memory round trip).  Batched
+    // Small single-frame launches load the blocks here, with the other loads
+    // that do not depend on the scalars (one memory round trip).  Batched
     // launches, whose speed follows how many workgroups fit on a CU, load
     // each block just before its product (and the regulariser record and
     // the owned node's vectors where they are used): 96 instead of 154
     // registers (93 instead of 120 for the first kernel), five wavefronts
-    // per SIMD instead of three.
+    // per SIMD instead of three.  Large single-frame launches (LATE) load
+    // the blocks and the regulariser record late: 106 instead of 158
+    // registers, four wavefronts instead of three.
+    constexpr bool late = B || LATE;
     const int npx = S > 0 ? g.RX * g.RY : 0;
     float Gm[PPT][SF_GRAM_STRIDE];
     float Bk[3][21];
@@ -1884,7 +1891,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
             if (valid && k >= 0 && pi >= 0 && pi < d.Gx && pj >= 0 && pj < d.Gy) {
                 bu[q] = (tj + 1 + pj - j_n) * HX + (ti + 1 + pi - i_n);
                 const long owner = own ? n_own : (long)pj * d.Gx + pi;
-                if (B) {
+                if (late) {
                     bo[q] = owner;
                     bt[q] = k;
                 } else {
@@ -1931,7 +1938,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
             rg[4 * k + 3] = t4.w;
         }
     };
-    if (mine && !B) load_rg();
+    if (mine && !late) load_rg();
     // the owned node's u, p and x: read here in single-frame launches (one
     // fewer dependent memory round trip, same occupancy); batched launches,
     // which stream from HBM, read them just before the final reduction to
@@ -2069,7 +2076,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
         for (int q = 0; q < 3; ++q) {
             if (bu[q] >= 0) {
                 float un[6];
-                if (B) blk_load(a.blk, bo[q], bt[q], Bk[q]);
+                if (late) blk_load(a.blk, bo[q], bt[q], Bk[q]);
                 rec_load<6>(L.halo + (size_t)bu[q] * 8, un);
 #pragma unroll
                 for (int r = 0; r < 6; ++r)
@@ -2083,7 +2090,7 @@ __global__ __launch_bounds__((TileTraits<S, V>::NT)) void k_pcg(KArg<B> ka, Tile
     float prt[3] = {0.f, 0.f, 0.f};
     float w6[6], uv[6];
     if (mine) {
-        if (B) load_rg();
+        if (late) load_rg();
         rec_load<6>(L.halo + (size_t)((tj + 1) * HX + ti + 1) * 8, uv);
         float jp0 = 0.f, jp1 = 0.f;
 #pragma unroll
@@ -3744,7 +3751,7 @@ void launch_pcg_first(hipStream_t st, const Launch &L, const TileCfg &t, bool sk
     };
     const int s = L.host[0].s;
 #define PCG0(S, V)                                                                         \
-    go(st, L, nb, k_pcg<true, true, S, V, true>, k_pcg<false, true, S, V, false>,          \
+    go(st, L, nb, k_pcg<true, true, S, V, true, false>, k_pcg<false, true, S, V, false, false>, \
        TileTraits<S, V>::NT, node_tile_lds_bytes(t, S, 6), t, 0, -1, pend ? 1 : 0)
     SF_PCG_SWITCH(s, t.v, PCG0)
 #undef PCG0
@@ -3757,15 +3764,29 @@ void launch_pcg_iter(hipStream_t st, const Launch &L, const TileCfg &t, int iter
     };
     const int s = L.host[0].s;
     // the single-frame variant by the number of partial sums it reduces
-    // (the previous iteration ran on the same tiles)
-    const bool wd = !L.batched && nb(L.host[0]) > SF_WD_TILES;
-#define PCGI(S, V)                                                                         \
-    if (wd)                                                                                \
-        go(st, L, nb, k_pcg<true, false, S, V, true>, k_pcg<false, false, S, V, true>,     \
-           TileTraits<S, V>::NT, node_tile_lds_bytes(t, S, 6), t, iter, gn, force);        \
-    else                                                                                   \
-        go(st, L, nb, k_pcg<true, false, S, V, true>, k_pcg<false, false, S, V, false>,    \
-           TileTraits<S, V>::NT, node_tile_lds_bytes(t, S, 6), t, iter, gn, force)
+    // (the previous iteration ran on the same tiles) and, node-block
+    // products only, by its size
+    const int nt1 = L.batched ? 0 : nb(L.host[0]);
+    const bool wd = nt1 > SF_WD_TILES;
+#define PCGI(S, V)                                                                            \
+    {                                                                                         \
+        auto kb = k_pcg<true, false, S, V, true, false>;                                      \
+        const int nth = TileTraits<S, V>::NT;                                                 \
+        const size_t lb = node_tile_lds_bytes(t, S, 6);                                       \
+        if constexpr (S == 0) {                                                               \
+            if ((long)nt1 * nth > SF_LATE_THREADS)                                            \
+                go(st, L, nb, kb, k_pcg<false, false, S, V, true, true>, nth, lb, t, iter, gn, force); \
+            else if (wd)                                                                      \
+                go(st, L, nb, kb, k_pcg<false, false, S, V, true, false>, nth, lb, t, iter, gn, force); \
+            else                                                                              \
+                go(st, L, nb, kb, k_pcg<false, false, S, V, false, false>, nth, lb, t, iter, gn, force); \
+        } else {                                                                              \
+            if (wd)                                                                           \
+                go(st, L, nb, kb, k_pcg<false, false, S, V, true, false>, nth, lb, t, iter, gn, force); \
+            else                                                                              \
+                go(st, L, nb, kb, k_pcg<false, false, S, V, false, false>, nth, lb, t, iter, gn, force); \
+        }                                                                                     \
+    }
     SF_PCG_SWITCH(s, t.v, PCGI)
 #undef PCGI
 }

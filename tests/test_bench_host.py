@@ -68,10 +68,14 @@ def _csv(path, counter, rows):
 def test_traffic_report_scales_by_the_copy_probe(tmp_path, capsys):
     name = "void (anonymous namespace)::k_pcg<true, false, 0, 0, true>(FrameMap, TileCfg, int, int, int)"
     # the copy of 1 MiB reads 512 KiB by FETCH_SIZE and 1024 KiB by WRITE_SIZE
+    # a grid only the fetch run saw (the runs autotune separately) is
+    # skipped, and so is the first-iteration kernel (FIRST = true)
+    first = "void (anonymous namespace)::k_pcg<true, true, 0, 0, true, false>(FrameMap, TileCfg, int, int, int)"
     fetch = [("__amd_rocclr_copyBuffer", 256, 512.0),
-             (name, 1000, 100.0), (name, 1000, 102.0), (name, 500, 7.0)]
+             (name, 1000, 100.0), (name, 1000, 102.0), (name, 500, 7.0), (name, 4000, 9.0),
+             (first, 1000, 5.0)]
     write = [("__amd_rocclr_copyBuffer", 256, 1024.0),
-             (name, 1000, 50.0), (name, 1000, 52.0), (name, 500, 3.0)]
+             (name, 1000, 50.0), (name, 1000, 52.0), (name, 500, 3.0), (first, 1000, 5.0)]
     fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
     _csv(fp, "FETCH_SIZE", fetch)
     _csv(wp, "WRITE_SIZE", write)
